@@ -1,0 +1,212 @@
+"""CPU oracle for tree-GP fitness evaluation -- test infrastructure only.
+
+Loads the plain C oracle (oracle.c) through ctypes.  Only the tests, the smoke
+check and the benchmark's CPU-baseline leg use this package; the GPU library
+never imports it, and it imports nothing from the GPU library.  See oracle.c
+for the paper passages each routine follows and the readings it takes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (scalar SSE float, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+L = C.c_int64
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        h = C.CDLL(_LIB)
+        h.orc_validate.argtypes = [u8p, L, C.c_int]
+        h.orc_subtree_end.argtypes = [u8p, L, L]
+        h.orc_subtree_end.restype = L
+        h.orc_eval_f32.argtypes = [u8p, L, C.c_int, f32p, L, f32p]
+        h.orc_eval_f32_nodes.argtypes = [u8p, L, C.c_int, f32p, L, f32p]
+        h.orc_fitness_f32.argtypes = [f32p, f32p, L]
+        h.orc_fitness_f32.restype = C.c_double
+        h.orc_eval_bool.argtypes = [u8p, L, C.c_int, u64p, L, u64p]
+        h.orc_eval_bool_bit.argtypes = [u8p, L, C.c_int, np.ctypeslib.ndpointer(np.int32)]
+        h.orc_fitness_bool.argtypes = [u64p, u64p, L, L]
+        h.orc_fitness_bool.restype = L
+        h.orc_splice.argtypes = [u8p, L, L, u8p, L, u8p, L]
+        h.orc_splice.restype = L
+        h.orc_incremental_f32.argtypes = [u8p, L, L, u8p, L, C.c_int, f32p, f32p, L, f32p,
+                                          i32p, i64p, f64p]
+        h.orc_incremental_bool.argtypes = [u8p, L, L, u8p, L, C.c_int, u64p, u64p, L, L, u64p,
+                                           i32p, i64p, i64p]
+        _lib = h
+    return _lib
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def validate(tree, n_inputs: int = 1) -> bool:
+    t = _u8(tree)
+    return lib().orc_validate(t, len(t), n_inputs) == 0
+
+
+def subtree_end(tree, i: int) -> int:
+    t = _u8(tree)
+    return int(lib().orc_subtree_end(t, len(t), i))
+
+
+def eval_f32(tree, x) -> np.ndarray:
+    """x: [n_inputs][T] float32 -> out[T]."""
+    t = _u8(tree)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float32)
+    out = np.empty(x.shape[1], np.float32)
+    rc = lib().orc_eval_f32(t, len(t), x.shape[0], x, x.shape[1], out)
+    if rc != 0:
+        raise ValueError(f"oracle eval_f32 failed ({rc})")
+    return out
+
+
+def eval_f32_nodes(tree, x) -> np.ndarray:
+    t = _u8(tree)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float32)
+    out = np.empty((len(t), x.shape[1]), np.float32)
+    rc = lib().orc_eval_f32_nodes(t, len(t), x.shape[0], x, x.shape[1], out)
+    if rc != 0:
+        raise ValueError(f"oracle eval_f32_nodes failed ({rc})")
+    return out
+
+
+def fitness_f32(out, y) -> float:
+    out = np.ascontiguousarray(out, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    return float(lib().orc_fitness_f32(out, y, len(y)))
+
+
+def eval_bool(tree, inputs) -> np.ndarray:
+    """inputs: [n_inputs][W] uint64 -> out[W]."""
+    t = _u8(tree)
+    inp = np.ascontiguousarray(inputs, dtype=np.uint64)
+    out = np.empty(inp.shape[1], np.uint64)
+    rc = lib().orc_eval_bool(t, len(t), inp.shape[0], inp, inp.shape[1], out)
+    if rc != 0:
+        raise ValueError(f"oracle eval_bool failed ({rc})")
+    return out
+
+
+def eval_bool_bit(tree, bits, n_inputs: int) -> int:
+    t = _u8(tree)
+    b = np.ascontiguousarray(bits, dtype=np.int32)
+    return int(lib().orc_eval_bool_bit(t, len(t), n_inputs, b))
+
+
+def fitness_bool(out, target, T: int) -> int:
+    out = np.ascontiguousarray(out, np.uint64)
+    target = np.ascontiguousarray(target, np.uint64)
+    return int(lib().orc_fitness_bool(out, target, len(target), T))
+
+
+def splice(parent, c: int, donor) -> np.ndarray:
+    p, d = _u8(parent), _u8(donor)
+    cap = len(p) + len(d)
+    child = np.empty(cap, np.uint8)
+    n = lib().orc_splice(p, len(p), c, d, len(d), child, cap)
+    if n < 0:
+        raise ValueError("oracle splice failed")
+    return child[:n].copy()
+
+
+def incremental_f32(parent, c: int, donor, x, y):
+    """-> (root_out[T], stop_level, interpreted_nodes, fitness)."""
+    p, d = _u8(parent), _u8(donor)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    T = x.shape[1]
+    out = np.empty(T, np.float32)
+    lvl = np.zeros(1, np.int32)
+    interp = np.zeros(1, np.int64)
+    fit = np.zeros(1, np.float64)
+    rc = lib().orc_incremental_f32(p, len(p), c, d, len(d), x.shape[0], x, y, T, out, lvl, interp, fit)
+    if rc != 0:
+        raise ValueError(f"oracle incremental_f32 failed ({rc})")
+    return out, int(lvl[0]), int(interp[0]), float(fit[0])
+
+
+def incremental_bool(parent, c: int, donor, inputs, target, T: int):
+    p, d = _u8(parent), _u8(donor)
+    inp = np.ascontiguousarray(inputs, dtype=np.uint64)
+    tg = np.ascontiguousarray(target, dtype=np.uint64)
+    W = inp.shape[1]
+    out = np.empty(W, np.uint64)
+    lvl = np.zeros(1, np.int32)
+    interp = np.zeros(1, np.int64)
+    fit = np.zeros(1, np.int64)
+    rc = lib().orc_incremental_bool(p, len(p), c, d, len(d), inp.shape[0], inp, tg, W, T, out, lvl,
+                                    interp, fit)
+    if rc != 0:
+        raise ValueError(f"oracle incremental_bool failed ({rc})")
+    return out, int(lvl[0]), int(interp[0]), int(fit[0])
+
+
+# ----------------------------------------------------------- population helpers
+def eval_population_f32(pop, x, y, threads: int = 1):
+    """Evaluate every tree; several independent single-threaded oracle
+    instances when threads > 1 (ctypes releases the GIL during each call)."""
+    T = np.atleast_2d(x).shape[1]
+    outs = np.empty((pop.n_trees, T), np.float32)
+    fits = np.empty(pop.n_trees, np.float64)
+
+    def one(i):
+        outs[i] = eval_f32(pop.tree(i), x)
+        fits[i] = fitness_f32(outs[i], y)
+
+    if threads <= 1:
+        for i in range(pop.n_trees):
+            one(i)
+    else:
+        order = np.argsort(-pop.sizes(), kind="stable")
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, order))
+    return outs, fits
+
+
+def eval_population_bool(pop, inputs, target, T: int, threads: int = 1):
+    W = np.asarray(inputs).shape[1]
+    outs = np.empty((pop.n_trees, W), np.uint64)
+    fits = np.empty(pop.n_trees, np.int64)
+
+    def one(i):
+        outs[i] = eval_bool(pop.tree(i), inputs)
+        fits[i] = fitness_bool(outs[i], target, T)
+
+    if threads <= 1:
+        for i in range(pop.n_trees):
+            one(i)
+    else:
+        order = np.argsort(-pop.sizes(), kind="stable")
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, order))
+    return outs, fits
