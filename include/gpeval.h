@@ -1,0 +1,271 @@
+/*
+ * gpeval -- data-parallel fitness evaluation of tree GP individuals on
+ * AMD MI355X (gfx950).  C ABI; plain pointers and sizes only.
+ *
+ * Method: W. B. Langdon, "A Trillion Genetic Programming Instructions per
+ * Second" (arXiv 2205.03251).
+ *   - Trees are flattened to one opcode byte per node in depth-first prefix
+ *     order, or reverse Polish order (Section 3.1).
+ *   - Every opcode is executed on every test case (Section 4.2); Boolean
+ *     problems pack 64 test cases per 64-bit word (Section 4.2).
+ *   - A child made by subtree crossover is evaluated bottom-up from the
+ *     crossover point: the inserted subtree is evaluated on all test cases,
+ *     then the path to the root is re-evaluated, stopping at the first node
+ *     whose values equal the mother's on every test case (failed disruption
+ *     propagation; Section 6.2, Figure 3).  The child need not exist: the
+ *     mother, the point and the donor subtree suffice (Section 6.3).
+ *
+ * Opcode byte encoding (both layouts):
+ *   0..63      terminal: index of an input variable (< n_inputs)
+ *   0x80 | f   binary function f, left operand = first child in prefix order
+ *     GP_F32:  0x80 ADD, 0x81 SUB, 0x82 MUL, 0x83 PDIV
+ *              PDIV(a, b) = 1.0f if fabsf(b) < 1e-6f (float32 compare) else a / b
+ *     GP_BOOL: 0x80 AND, 0x81 OR, 0x82 NAND, 0x83 NOR   (bitwise on 64-bit words)
+ *   float32 arithmetic is IEEE binary32, round to nearest even, no fused
+ *   multiply-add, denormals kept, divide correctly rounded.
+ *
+ * Test cases: float32 inputs are [n_inputs][T] and the target is [T].
+ * Boolean inputs are [n_inputs][W] uint64 words and the target is [W],
+ * W = ceil(T / 64); test case i is bit i % 64 of word i / 64.
+ *
+ * Fitness: float32 = sum over cases of (double)fabsf(out - y), the
+ * subtraction in float32, summed in double by a halving tree over
+ * P = max(64, next power of two >= T) zero-padded slots
+ * (s[i] += s[i + h] for h = P/2, ..., 1).  Boolean = number of cases where
+ * out equals the target.  Results are bit-exact and independent of launch
+ * shape, batch composition and concurrent work.
+ *
+ * Ownership: host arrays passed in are copied during the call.  With
+ * GP_DEVICE_PTR, pointer arguments are device pointers and are read or
+ * written in stream order on the context's stream.  Populations, cases,
+ * parent caches and workspaces are owned by the library until gp_free or
+ * gp_destroy.  Output buffers belong to the caller.  A context is used by
+ * one thread at a time; the server runs its own threads.
+ *
+ * Errors: every call returns GP_OK or a negative code and writes nothing to
+ * its outputs on error; gp_last_error gives the reason.  There is no CPU
+ * evaluation path: without a usable GPU, calls that evaluate return
+ * GP_EDEVICE.
+ */
+#ifndef GPEVAL_H
+#define GPEVAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_ctx gp_ctx;
+typedef int64_t gp_handle;
+
+enum {
+    GP_OK = 0,
+    GP_EINVAL = -1,     /* malformed tree, bad index, size or type mismatch */
+    GP_ENOMEM = -2,     /* host or device allocation failed */
+    GP_EBUDGET = -3,    /* request exceeds the context's HBM budget */
+    GP_EDEVICE = -4,    /* HIP error, or no usable GPU */
+    GP_ENOTFOUND = -5,  /* no parent cache (spine) for this parent and point */
+    GP_EBUSY = -6       /* server job not finished yet */
+};
+
+enum { GP_F32 = 0, GP_BOOL = 1 };          /* value type */
+enum { GP_PREFIX = 0, GP_POSTFIX = 1 };    /* load layout */
+
+/* flags */
+#define GP_DEVICE_PTR 0x1u   /* pointer arguments are device pointers */
+#define GP_ASYNC      0x2u   /* return once enqueued (needs GP_DEVICE_PTR outputs) */
+#define GP_PER_TREE   0x4u   /* one launch per tree instead of one batched launch */
+#define GP_NO_GRAPH   0x8u   /* launch kernels directly, no captured graph replay */
+
+typedef struct gp_stats {
+    double device_ms;          /* HIP-event time on the context stream (0 with GP_ASYNC) */
+    double wall_ms;            /* call entry to return */
+    int64_t equivalent_ops;    /* sum of nodes x T over every tree or child scored */
+    int64_t interpreted_ops;   /* nodes actually executed x T */
+    int64_t launches;          /* kernel launches or graph replays issued */
+    int32_t variant;           /* interpreter variant index (gp_variant_name) */
+    int32_t reserved;
+} gp_stats;
+
+typedef struct gp_inc_result {
+    int32_t stop_level;        /* 0: at the crossover point; k: k-th ancestor; -1: root reached */
+    int32_t reserved;
+    int64_t child_nodes;       /* nodes of the (never built) child */
+    int64_t interpreted_nodes; /* donor nodes + ancestor levels re-evaluated */
+} gp_inc_result;
+
+typedef struct gp_pop_info {
+    int64_t n_trees;
+    int64_t total_nodes;
+    int64_t n_chunks;          /* work units after chunking */
+    int64_t n_instructions;    /* interpreter instructions over all chunks */
+    int64_t n_records;         /* parent-cache vectors recorded per evaluation */
+    int64_t n_spines;          /* (tree, point) pairs with a parent cache */
+    int64_t device_bytes;      /* HBM held by this population */
+    int32_t max_stack;         /* deepest evaluation-stack slot used + 1 */
+    int32_t chunk_nodes;       /* chunk size target used */
+} gp_pop_info;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context may hold (0 = 90% of the device's free memory).
+ * hip_stream: a hipStream_t to run on, or NULL for a stream of its own. */
+int gp_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, gp_ctx** out);
+void gp_destroy(gp_ctx* ctx);
+/* Reason for the last failed call on this context (static text if ctx is NULL). */
+const char* gp_last_error(const gp_ctx* ctx);
+/* Device memory currently held by the context, in bytes. */
+uint64_t gp_memory_used(const gp_ctx* ctx);
+
+/* ------------------------------------------------------------------- data */
+
+/* Register a test-case set (Section 4.2).  vtype GP_F32: inputs [n_inputs][T]
+ * float32, target [T] float32.  GP_BOOL: inputs [n_inputs][ceil(T/64)] uint64,
+ * target [ceil(T/64)] uint64.  1 <= n_inputs <= 64, 1 <= T <= 16384 (float)
+ * or T <= 2^18 (Boolean).  GP_DEVICE_PTR: inputs and target are device
+ * pointers. */
+int gp_set_cases(gp_ctx* ctx, int vtype, int n_inputs, int64_t n_cases, const void* inputs,
+                 const void* target, uint32_t flags, gp_handle* cases_out);
+
+/* Load a population of flattened trees (Section 3.1): tree i is
+ * ops[offsets[i] .. offsets[i+1]) in the given layout.  Trees are validated
+ * (every byte a known opcode, terminals < n_inputs, arity count closes exactly
+ * at the last byte), compiled to register-stack programs and cut into chunks.
+ * record_points (may be NULL): for tree i, the crossover points
+ * record_points[record_offsets[i] .. record_offsets[i+1]) (node indices in
+ * the given layout) whose parent caches every full evaluation must record,
+ * for later incremental evaluation of children made at those points.
+ * chunk_nodes: target nodes per chunk (0 = automatic). */
+int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t n_trees,
+                       const uint8_t* ops, const int64_t* offsets, const int64_t* record_points,
+                       const int64_t* record_offsets, int64_t chunk_nodes, uint32_t flags,
+                       gp_handle* pop_out);
+
+int gp_population_info(gp_ctx* ctx, gp_handle pop, gp_pop_info* out);
+
+/* Release a population or case set (and any cache or graph tied to it). */
+int gp_free(gp_ctx* ctx, gp_handle h);
+
+/* ------------------------------------------------------------- evaluation */
+
+/* Full evaluation (Section 4.2) of every tree on every case of `cases`, in
+ * one persistent work-stealing launch (or one launch per tree with
+ * GP_PER_TREE).  Records the parent caches requested at load time.
+ * root_out: [n_trees][T] float32 or [n_trees][W] uint64, or NULL.
+ * fitness_out: [n_trees] double (GP_F32) or int64 (GP_BOOL), or NULL.
+ * st: optional statistics. */
+int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags, void* root_out,
+                     void* fitness_out, gp_stats* st);
+
+/* Bottom-up incremental evaluation with failed-disruption-propagation stop
+ * (Section 6.2, Figure 3) of n_children children.  Child i is tree parent[i]
+ * of `pop` with the subtree at node point[i] (index in the load layout)
+ * replaced by donor i = donor_ops[donor_offsets[i] .. donor_offsets[i+1])
+ * (same layout and value type as the population).  The population must have
+ * been fully evaluated on `cases` since it was loaded, with point[i] among
+ * its record points (else GP_ENOTFOUND).  Outputs as gp_evaluate_full, per
+ * child; res[i] gets the stop level and counts (host pointer, may be NULL). */
+int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t n_children,
+                                  const int64_t* parent, const int64_t* point,
+                                  const uint8_t* donor_ops, const int64_t* donor_offsets,
+                                  uint32_t flags, void* root_out, void* fitness_out,
+                                  gp_inc_result* res, gp_stats* st);
+
+/* One child; same as a batch of one. */
+int gp_evaluate_incremental(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t parent,
+                            int64_t point, const uint8_t* donor_ops, int64_t donor_len,
+                            uint32_t flags, void* root_out, void* fitness_out, gp_inc_result* res);
+
+/* Fitness of n given output vectors ([n][T] float32 or [n][W] uint64) against
+ * the target of `cases`, in the fixed order described above. */
+int gp_fitness(gp_ctx* ctx, gp_handle cases, const void* outputs, int64_t n, uint32_t flags,
+               void* fitness_out);
+
+/* ------------------------------------------------------------- tuning */
+
+/* Interpreter variants compiled into the library (test cases per lane K and
+ * evaluation-stack slots S).  gp_variant_name returns NULL past the last. */
+const char* gp_variant_name(int variant);
+int gp_variant_count(void);
+
+/* Time each variant (and grid size) on this population and case set, keep
+ * the fastest for later calls with the same value type, case-count bucket
+ * and size bucket, and return its index. */
+int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, double* best_ms);
+
+/* Force a variant for later calls (-1 = automatic choice). */
+int gp_set_variant(gp_ctx* ctx, int variant);
+
+/* ------------------------------------------------------------- serving */
+
+typedef struct gp_server_cfg {
+    int32_t n_streams;          /* batches that may be in flight at once (>= 1) */
+    int32_t max_batch_jobs;     /* jobs merged into one launch at most */
+    int32_t prep_threads;       /* host threads compiling arriving trees */
+    int32_t reserved;
+    uint64_t budget_bytes;      /* HBM admitted at once (0 = the context budget) */
+} gp_server_cfg;
+
+enum { GP_JOB_FULL = 0, GP_JOB_INCREMENTAL = 1 };
+
+typedef struct gp_job {
+    int32_t kind;               /* GP_JOB_FULL or GP_JOB_INCREMENTAL */
+    int32_t layout;             /* GP_PREFIX or GP_POSTFIX */
+    gp_handle cases;            /* case set (fixes vtype and T) */
+    const uint8_t* ops;         /* FULL: the tree; INCREMENTAL: the donor */
+    int64_t n_ops;
+    const int64_t* record_points; /* FULL: points to keep parent caches for (may be NULL) */
+    int64_t n_record_points;
+    int64_t parent_ticket;      /* INCREMENTAL: ticket of a finished FULL job kept resident */
+    int64_t point;              /* INCREMENTAL: crossover point in the parent */
+    int32_t keep_resident;      /* FULL: keep tree and caches on the device as a parent */
+    int32_t reserved;
+} gp_job;
+
+typedef struct gp_job_result {
+    double fitness_f64;         /* GP_F32 fitness */
+    int64_t fitness_i64;        /* GP_BOOL fitness */
+    int32_t stop_level;         /* INCREMENTAL: as gp_inc_result */
+    int32_t status;             /* GP_OK or an error code */
+    int64_t interpreted_nodes;
+    double latency_ms;          /* submit to completion */
+    double queue_ms;            /* submit to admission */
+} gp_job_result;
+
+int gp_server_start(gp_ctx* ctx, const gp_server_cfg* cfg);
+/* Copies the job's arrays; returns a ticket. GP_EBUDGET if the job alone
+ * exceeds the budget. */
+int gp_server_submit(gp_ctx* ctx, const gp_job* job, int64_t* ticket);
+/* GP_EBUSY until the job is done; then fills *out.  root_out (may be NULL)
+ * receives the job's output vector (host memory). */
+int gp_server_poll(gp_ctx* ctx, int64_t ticket, gp_job_result* out, void* root_out);
+/* Drop a resident parent kept by keep_resident. */
+int gp_server_release(gp_ctx* ctx, int64_t ticket);
+int gp_server_stop(gp_ctx* ctx);
+
+/* ----------------------------------------------- host-only inspection */
+
+/* Compile one prefix tree on the host only (no GPU needed) and return the
+ * interpreter program, for tests of the compiler.  code_out receives the
+ * 32-bit instructions of all chunks (at most code_cap), chunk_out 4 int64 per
+ * chunk (code offset, code length, parent chunk or -1, number of child chunks
+ * it loads), inputs_out the child chunk ids each chunk loads, chunk after
+ * chunk, in LOAD payload order.  Chunks come children first; the last one is
+ * the root.  Returns the number of chunks, GP_EINVAL for a malformed tree or
+ * GP_ENOMEM when a capacity is too small; *n_code gets the code length and
+ * *max_stack the register-stack slots used. */
+int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t n,
+                           int64_t chunk_nodes, int stack_slots, uint32_t* code_out,
+                           int64_t code_cap, int64_t* chunk_out, int64_t chunk_cap,
+                           int32_t* inputs_out, int64_t inputs_cap, int64_t* n_code,
+                           int32_t* max_stack);
+
+/* Validate one tree (prefix layout) on the host: GP_OK or GP_EINVAL. */
+int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPEVAL_H */

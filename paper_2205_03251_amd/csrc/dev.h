@@ -1,0 +1,103 @@
+// Device-visible structures and kernel launchers of the gpeval library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gpe {
+
+// Test cases are processed in slices of 64 lanes x K cases; vectors are
+// stored with a stride padded to a multiple of kPadCases.
+constexpr int kWave = 64;
+constexpr int kMaxK = 8;
+constexpr int64_t kPadCases = kWave * kMaxK;
+
+struct DevChunk {            // 32 bytes
+    int64_t code_off;        // first instruction (global)
+    int32_t code_len;
+    int32_t parent;          // global chunk id, -1 for a tree's root chunk
+    int32_t out_slot;        // vector slot receiving this chunk's value
+    int32_t in_off;          // chunk_in[in_off + k] = vector slot read by LOAD k
+    int32_t rec_base;        // global record slot of this tree's record 0
+    int32_t tree;
+};
+
+// Work item = (chunk << 16) | slice.
+struct EvalParams {
+    const uint32_t* code;
+    const DevChunk* chunks;
+    const int32_t* chunk_in;
+    const int64_t* items;        // leaf work items in priority order
+    int64_t n_items;
+    int32_t* pending;            // [n_chunks][n_slices] unfinished inputs
+    unsigned int* cursor;        // next item to hand out
+    const void* inputs;          // [n_inputs][stride]
+    void* vecs;                  // [n_slots][stride] chunk and root values
+    void* recs;                  // [n_records][stride] parent caches
+    int64_t stride;              // padded cases (float) or words (Boolean)
+    int32_t n_slices;
+    int32_t n_inputs;
+};
+
+// One incremental child.
+struct WalkChild {
+    int64_t level_off;           // first SpineLevel (int4) of its spine
+    int32_t n_levels;
+    int32_t at_point;            // mother's vector at the point (source code)
+    int32_t rec_base;            // record slot base of the mother tree
+    int32_t parent_slot;         // mother's root vector slot in the population
+    int32_t parent_tree;
+    int32_t donor_slot;          // donor's root vector slot in the donor run
+    int64_t donor_nodes;
+};
+
+struct WalkParams {
+    const WalkChild* children;
+    const int4* levels;          // {fside, sib, par, 0}
+    const void* inputs;          // [n_inputs][stride]
+    const void* recs;            // mother records
+    const void* parent_vecs;     // mother root vectors
+    const void* parent_fit;      // mother fitness (double or int64) [n_trees]
+    const void* donor_vecs;      // donor root vectors
+    const void* target;          // [stride]
+    void* root_out;              // [n_children][stride]
+    void* fit_out;               // [n_children]
+    int32_t* stop_out;           // [n_children]
+    int64_t* interp_out;         // [n_children]
+    int64_t stride;
+    int64_t n_valid;             // T (float) or T bits (Boolean)
+    int64_t P;                   // fitness halving width (float)
+};
+
+struct FitParams {
+    const void* vecs;            // [n][stride]
+    int64_t first_slot;
+    const void* target;
+    void* fit_out;
+    int64_t stride;
+    int64_t n_valid;             // T
+    int64_t P;
+};
+
+// ----------------------------------------------------------- launchers
+struct Variant {
+    const char* name;
+    int vtype;                   // 0 float32, 1 Boolean
+    int K;                       // cases (words) per lane
+    int S;                       // register-stack slots
+    const void* kernel;          // for occupancy queries
+    int max_blocks_per_cu;       // filled at context creation
+};
+
+int variant_count();
+Variant* variant_table();
+
+hipError_t launch_init(int32_t* pending, const int32_t* init, int64_t n, unsigned int* cursor,
+                       int n_cursors, hipStream_t s);
+hipError_t launch_eval(int variant, const EvalParams& p, int grid, hipStream_t s);
+hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t s);
+hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s);
+hipError_t launch_pad_copy(void* dst, int64_t dst_stride, const void* src, int64_t src_stride,
+                           int64_t rows, int64_t cols, int elem_bytes, hipStream_t s);
+
+}  // namespace gpe

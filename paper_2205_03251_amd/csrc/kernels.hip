@@ -1,0 +1,684 @@
+// HIP kernels of the gpeval library (gfx950).
+//
+// Interpreter (Section 4.2 of the paper: every opcode runs on every test
+// case).  Test cases lie across the 64 lanes of a wavefront, K per lane, so
+// one instruction word drives 64*K case evaluations.  The instruction stream
+// is wave-uniform: it is fetched through the scalar cache and decoded on the
+// scalar unit, and every handler works on a register-resident evaluation
+// stack st[S][K] at a slot fixed by the instruction, so no register is ever
+// indexed at run time.  The host compiler (prep.cpp) orders evaluation so
+// that S slots suffice and folds terminal operands into their parent's
+// instruction.
+//
+// Batching: one persistent launch evaluates a whole population.  Each
+// wavefront repeatedly takes a work item (a leaf chunk of some tree, on one
+// slice of test cases) from an atomic cursor over a list sorted by longest
+// remaining chain first, evaluates it, publishes the chunk's value vector,
+// and decrements its parent chunk's counter; the wavefront that brings the
+// counter to zero goes on to evaluate the parent.  No wavefront ever waits
+// on another, so the launch always drains.
+//
+// Incremental evaluation (Section 6.2, Figure 3): one workgroup per child
+// walks from the crossover point to the root over the mother's recorded
+// vectors, comparing with the mother at each level and stopping at the first
+// level where all test cases agree.
+#include <algorithm>
+
+#include "dev.h"
+#include "prep.h"
+
+namespace gpe {
+
+#define UNROLL _Pragma("unroll")
+
+// ---------------------------------------------------------------- ops
+template <int F>
+__device__ __forceinline__ float fop(float a, float b)
+{
+    if constexpr (F == 0) return a + b;
+    else if constexpr (F == 1) return a - b;
+    else if constexpr (F == 2) return a * b;
+    else {
+        const float q = a / b;                 // IEEE correctly rounded
+        return (fabsf(b) < 1e-6f) ? 1.0f : q;  // protected divide
+    }
+}
+
+__device__ __forceinline__ float fop_rt(int f, float a, float b)
+{
+    switch (f) {
+    case 0: return fop<0>(a, b);
+    case 1: return fop<1>(a, b);
+    case 2: return fop<2>(a, b);
+    default: return fop<3>(a, b);
+    }
+}
+
+template <int F>
+__device__ __forceinline__ uint64_t bop(uint64_t a, uint64_t b)
+{
+    if constexpr (F == 0) return a & b;
+    else if constexpr (F == 1) return a | b;
+    else if constexpr (F == 2) return ~(a & b);
+    else return ~(a | b);
+}
+
+__device__ __forceinline__ uint64_t bop_rt(int f, uint64_t a, uint64_t b)
+{
+    switch (f) {
+    case 0: return bop<0>(a, b);
+    case 1: return bop<1>(a, b);
+    case 2: return bop<2>(a, b);
+    default: return bop<3>(a, b);
+    }
+}
+
+// Bit-equal, or both NaN.
+__device__ __forceinline__ bool same_f32(float a, float b)
+{
+    return (__float_as_uint(a) == __float_as_uint(b)) || (a != a && b != b);
+}
+
+__device__ __forceinline__ uint64_t valid_bits(int64_t w, int64_t T)
+{
+    const int64_t lo = w * 64;
+    if (lo + 64 <= T) return ~0ull;
+    if (lo >= T) return 0ull;
+    return (1ull << (T - lo)) - 1ull;
+}
+
+// --------------------------------------------------- float interpreter
+struct ItemF32 {
+    const float* inputs;     // input 0 at this lane's first case
+    const float* vecs;       // vector slot 0 at this lane's first case
+    float* recs;             // record slot 0 at this lane's first case
+    const int32_t* chunk_in;
+    int64_t stride;
+    int32_t rec_base;
+};
+
+template <int D, int K, int S>
+__device__ __forceinline__ void step_f32(uint32_t fm, uint32_t pl, float (&st)[S][K],
+                                         const float (&x)[K], const ItemF32& c)
+{
+    if constexpr (D < S) {
+        switch (fm) {
+#define GP_F32_CASES(F)                                                                       \
+    case (F) | (M_XX << 2):                                                                   \
+        UNROLL for (int k = 0; k < K; ++k) st[D][k] = fop<F>(x[k], x[k]);                     \
+        break;                                                                                \
+    case (F) | (M_XS << 2):                                                                   \
+        UNROLL for (int k = 0; k < K; ++k) st[D][k] = fop<F>(x[k], st[D][k]);                 \
+        break;                                                                                \
+    case (F) | (M_SX << 2):                                                                   \
+        UNROLL for (int k = 0; k < K; ++k) st[D][k] = fop<F>(st[D][k], x[k]);                 \
+        break;                                                                                \
+    case (F) | (M_SS << 2):                                                                   \
+        if constexpr (D + 1 < S) {                                                            \
+            UNROLL for (int k = 0; k < K; ++k) st[D][k] = fop<F>(st[D][k], st[D + 1][k]);     \
+        }                                                                                     \
+        break;                                                                                \
+    case (F) | (M_RS << 2):                                                                   \
+        if constexpr (D + 1 < S) {                                                            \
+            UNROLL for (int k = 0; k < K; ++k) st[D][k] = fop<F>(st[D + 1][k], st[D][k]);     \
+        }                                                                                     \
+        break;
+            GP_F32_CASES(0)
+            GP_F32_CASES(1)
+            GP_F32_CASES(2)
+            GP_F32_CASES(3)
+#undef GP_F32_CASES
+        case (M_PUSH << 2):
+            if (pl == 0) {
+                UNROLL for (int k = 0; k < K; ++k) st[D][k] = x[k];
+            } else {
+                const float* src = c.inputs + (int64_t)pl * c.stride;
+                UNROLL for (int k = 0; k < K; ++k) st[D][k] = src[kWave * k];
+            }
+            break;
+        case (M_LOAD << 2): {
+            const float* src = c.vecs + (int64_t)c.chunk_in[pl] * c.stride;
+            UNROLL for (int k = 0; k < K; ++k) st[D][k] = src[kWave * k];
+            break;
+        }
+        case (M_STORE << 2): {
+            float* dst = c.recs + (int64_t)(c.rec_base + (int32_t)pl) * c.stride;
+            UNROLL for (int k = 0; k < K; ++k) dst[kWave * k] = st[D][k];
+            break;
+        }
+        default:
+            break;
+        }
+    }
+}
+
+#define GP_DEPTH_CASES(STEP)                                                                  \
+    STEP(0) STEP(1) STEP(2) STEP(3) STEP(4) STEP(5) STEP(6) STEP(7) STEP(8) STEP(9) STEP(10)  \
+    STEP(11) STEP(12) STEP(13) STEP(14) STEP(15) STEP(16) STEP(17) STEP(18) STEP(19)          \
+    STEP(20) STEP(21) STEP(22) STEP(23) STEP(24) STEP(25) STEP(26) STEP(27) STEP(28)          \
+    STEP(29) STEP(30) STEP(31)
+
+template <int K, int S>
+__device__ __forceinline__ void run_f32(const uint32_t* __restrict__ code, int32_t len,
+                                        float (&st)[S][K], const float (&x)[K], const ItemF32& c)
+{
+    // The next word is fetched before the current one is executed; the code
+    // array carries one padding word past its end.
+    uint32_t nxt = code[0];
+    for (int32_t i = 0; i < len; ++i) {
+        const uint32_t ins = __builtin_amdgcn_readfirstlane(nxt);
+        nxt = code[i + 1];
+        const uint32_t fm = ins & 31u;
+        const uint32_t pl = ins >> kPayloadShift;
+        switch ((ins >> 5) & 31u) {
+#define GP_STEP(D)                                     \
+    case D:                                            \
+        step_f32<D, K, S>(fm, pl, st, x, c);           \
+        break;
+            GP_DEPTH_CASES(GP_STEP)
+#undef GP_STEP
+        }
+    }
+}
+
+template <int K, int S>
+__global__ __launch_bounds__(64) void k_eval_f32(EvalParams p)
+{
+    const int lane = threadIdx.x;
+    float st[S][K];
+    float x[K];
+    for (;;) {
+        unsigned int it = 0;
+        if (lane == 0) it = atomicAdd(p.cursor, 1u);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if ((int64_t)it >= p.n_items) break;
+        const int64_t item = p.items[it];
+        int32_t c = (int32_t)(item >> 16);
+        const int32_t s = (int32_t)(item & 0xffff);
+        const int64_t case0 = (int64_t)s * (kWave * K) + lane;
+        const float* xin = (const float*)p.inputs + case0;
+        UNROLL for (int k = 0; k < K; ++k) x[k] = xin[kWave * k];
+        ItemF32 ic;
+        ic.inputs = xin;
+        ic.vecs = (const float*)p.vecs + case0;
+        ic.recs = (float*)p.recs + case0;
+        ic.stride = p.stride;
+        for (;;) {
+            const DevChunk ch = p.chunks[c];
+            ic.chunk_in = p.chunk_in + ch.in_off;
+            ic.rec_base = ch.rec_base;
+            run_f32<K, S>(p.code + ch.code_off, ch.code_len, st, x, ic);
+            float* dst = (float*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
+            UNROLL for (int k = 0; k < K; ++k) dst[kWave * k] = st[0][k];
+            if (ch.parent < 0) break;
+            // Publish this chunk's vector, then count it against the parent;
+            // whoever finishes the parent's last input evaluates the parent.
+            int old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(p.pending + (int64_t)ch.parent * p.n_slices + s, -1,
+                                             __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old != 1) break;
+            c = ch.parent;
+        }
+    }
+}
+
+// ------------------------------------------------- Boolean interpreter
+struct ItemBool {
+    const uint64_t* lin;     // staged input words in LDS, this lane's first word
+    const uint64_t* vecs;
+    uint64_t* recs;
+    const int32_t* chunk_in;
+    int64_t stride;
+    int32_t rec_base;
+    int32_t lds_row;         // words per staged input row (64*K)
+};
+
+template <int D, int K, int S>
+__device__ __forceinline__ void step_bool(uint32_t fm, uint32_t pl, uint64_t (&st)[S][K],
+                                          const ItemBool& c)
+{
+    if constexpr (D < S) {
+        switch (fm) {
+#define GP_BOOL_CASES(F)                                                                      \
+    case (F) | (M_XX << 2): {                                                                 \
+        const uint64_t* a = c.lin + (int32_t)(pl & 2047u) * c.lds_row;                        \
+        const uint64_t* b = c.lin + (int32_t)(pl >> 11) * c.lds_row;                          \
+        UNROLL for (int k = 0; k < K; ++k) st[D][k] = bop<F>(a[kWave * k], b[kWave * k]);     \
+        break;                                                                                \
+    }                                                                                         \
+    case (F) | (M_XS << 2): {                                                                 \
+        const uint64_t* a = c.lin + (int32_t)pl * c.lds_row;                                  \
+        UNROLL for (int k = 0; k < K; ++k) st[D][k] = bop<F>(a[kWave * k], st[D][k]);         \
+        break;                                                                                \
+    }                                                                                         \
+    case (F) | (M_SS << 2):                                                                   \
+        if constexpr (D + 1 < S) {                                                            \
+            UNROLL for (int k = 0; k < K; ++k) st[D][k] = bop<F>(st[D][k], st[D + 1][k]);     \
+        }                                                                                     \
+        break;
+            GP_BOOL_CASES(0)
+            GP_BOOL_CASES(1)
+            GP_BOOL_CASES(2)
+            GP_BOOL_CASES(3)
+#undef GP_BOOL_CASES
+        case (M_PUSH << 2): {
+            const uint64_t* a = c.lin + (int32_t)pl * c.lds_row;
+            UNROLL for (int k = 0; k < K; ++k) st[D][k] = a[kWave * k];
+            break;
+        }
+        case (M_LOAD << 2): {
+            const uint64_t* src = c.vecs + (int64_t)c.chunk_in[pl] * c.stride;
+            UNROLL for (int k = 0; k < K; ++k) st[D][k] = src[kWave * k];
+            break;
+        }
+        case (M_STORE << 2): {
+            uint64_t* dst = c.recs + (int64_t)(c.rec_base + (int32_t)pl) * c.stride;
+            UNROLL for (int k = 0; k < K; ++k) dst[kWave * k] = st[D][k];
+            break;
+        }
+        default:
+            break;
+        }
+    }
+}
+
+template <int K, int S>
+__device__ __forceinline__ void run_bool(const uint32_t* __restrict__ code, int32_t len,
+                                         uint64_t (&st)[S][K], const ItemBool& c)
+{
+    uint32_t nxt = code[0];
+    for (int32_t i = 0; i < len; ++i) {
+        const uint32_t ins = __builtin_amdgcn_readfirstlane(nxt);
+        nxt = code[i + 1];
+        const uint32_t fm = ins & 31u;
+        const uint32_t pl = ins >> kPayloadShift;
+        switch ((ins >> 5) & 31u) {
+#define GP_STEP(D)                                 \
+    case D:                                        \
+        step_bool<D, K, S>(fm, pl, st, c);         \
+        break;
+            GP_DEPTH_CASES(GP_STEP)
+#undef GP_STEP
+        }
+    }
+}
+
+template <int K, int S>
+__global__ __launch_bounds__(64) void k_eval_bool(EvalParams p)
+{
+    extern __shared__ uint64_t lds_in[];       // [n_inputs][64*K] input words of the slice
+    const int lane = threadIdx.x;
+    uint64_t st[S][K];
+    const int32_t row = kWave * K;
+    for (;;) {
+        unsigned int it = 0;
+        if (lane == 0) it = atomicAdd(p.cursor, 1u);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if ((int64_t)it >= p.n_items) break;
+        const int64_t item = p.items[it];
+        int32_t c = (int32_t)(item >> 16);
+        const int32_t s = (int32_t)(item & 0xffff);
+        const int64_t case0 = (int64_t)s * row + lane;
+        __syncthreads();                       // previous item's reads are done
+        for (int j = 0; j < p.n_inputs; ++j) {
+            const uint64_t* src = (const uint64_t*)p.inputs + (int64_t)j * p.stride + case0;
+            UNROLL for (int k = 0; k < K; ++k) lds_in[j * row + kWave * k + lane] = src[kWave * k];
+        }
+        __syncthreads();
+        ItemBool ic;
+        ic.lin = lds_in + lane;
+        ic.vecs = (const uint64_t*)p.vecs + case0;
+        ic.recs = (uint64_t*)p.recs + case0;
+        ic.stride = p.stride;
+        ic.lds_row = row;
+        for (;;) {
+            const DevChunk ch = p.chunks[c];
+            ic.chunk_in = p.chunk_in + ch.in_off;
+            ic.rec_base = ch.rec_base;
+            run_bool<K, S>(p.code + ch.code_off, ch.code_len, st, ic);
+            uint64_t* dst = (uint64_t*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
+            UNROLL for (int k = 0; k < K; ++k) dst[kWave * k] = st[0][k];
+            if (ch.parent < 0) break;
+            int old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(p.pending + (int64_t)ch.parent * p.n_slices + s, -1,
+                                             __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old != 1) break;
+            c = ch.parent;
+        }
+    }
+}
+
+// ------------------------------------------------------------- init
+__global__ void k_init(int32_t* pending, const int32_t* init, int64_t n, unsigned int* cursor,
+                       int n_cursors)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * blockDim.x) pending[i] = init[i];
+    if (i0 < n_cursors) cursor[i0] = 0u;
+}
+
+// ---------------------------------------------------------- fitness
+// Sum of |out - y| in double over P = max(64, 2^ceil(log2 T)) zero-padded
+// slots by the halving tree s[i] += s[i + h], h = P/2 ... 1.  Thread t holds
+// slots t + 256 m (m < R = max(1, P/256)); the levels h >= 256 pair slots of
+// the same thread, the rest go through LDS.
+template <int R>
+__device__ double halving_sum(double (&e)[R], int64_t P, double* red)
+{
+    const int tid = threadIdx.x;
+    UNROLL for (int r = R / 2; r >= 1; r /= 2)
+        UNROLL for (int m = 0; m < r; ++m) e[m] = e[m] + e[m + r];
+    const int Pp = P < 256 ? (int)P : 256;
+    red[tid] = e[0];
+    __syncthreads();
+    for (int h = Pp / 2; h >= 1; h >>= 1) {
+        if (tid < h) red[tid] = red[tid] + red[tid + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_fit_f32(FitParams p)
+{
+    __shared__ double red[256];
+    const int64_t row = blockIdx.x;
+    const float* v = (const float*)p.vecs + (p.first_slot + row) * p.stride;
+    const float* y = (const float*)p.target;
+    double e[R];
+    UNROLL for (int m = 0; m < R; ++m) {
+        const int64_t i = threadIdx.x + 256 * m;
+        double val = 0.0;
+        if (i < p.n_valid) {
+            const float d = v[i] - y[i];
+            val = (double)fabsf(d);
+        }
+        e[m] = val;
+    }
+    const double f = halving_sum<R>(e, p.P, red);
+    if (threadIdx.x == 0) ((double*)p.fit_out)[row] = f;
+}
+
+__device__ int64_t block_sum_i64(int64_t v, int64_t* red)
+{
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    const int64_t r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_fit_bool(FitParams p)
+{
+    __shared__ int64_t red[256];
+    const int64_t row = blockIdx.x;
+    const uint64_t* v = (const uint64_t*)p.vecs + (p.first_slot + row) * p.stride;
+    const uint64_t* t = (const uint64_t*)p.target;
+    const int64_t W = (p.n_valid + 63) / 64;
+    int64_t hits = 0;
+    for (int64_t w = threadIdx.x; w < W; w += 256)
+        hits += __popcll(~(v[w] ^ t[w]) & valid_bits(w, p.n_valid));
+    const int64_t h = block_sum_i64(hits, red);
+    if (threadIdx.x == 0) ((int64_t*)p.fit_out)[row] = h;
+}
+
+// ------------------------------------------------------ incremental walk
+// One workgroup of 256 threads per child.  Level 0 compares the donor's
+// vector with the mother's vector at the crossover point; level k applies
+// the k-th ancestor's function with the path operand replaced by the
+// child's running vector and the other operand taken from the mother's
+// recorded sibling vector, then compares with the mother's vector at that
+// ancestor.  A workgroup-wide AND over the test cases decides the stop.
+template <int R>
+__global__ __launch_bounds__(256) void k_walk_f32(WalkParams p)
+{
+    __shared__ double red[256];
+    const int64_t ci = blockIdx.x;
+    const WalkChild w = p.children[ci];
+    const int tid = threadIdx.x;
+    const int64_t T = p.n_valid;
+    const float* in = (const float*)p.inputs;
+    const float* recs = (const float*)p.recs + (int64_t)w.rec_base * p.stride;
+    const float* dv = (const float*)p.donor_vecs + (int64_t)w.donor_slot * p.stride;
+    float v[R];
+    UNROLL for (int m = 0; m < R; ++m) {
+        const int64_t i = tid + 256 * m;
+        v[m] = (i < T) ? dv[i] : 0.0f;
+    }
+    const float* a0 = w.at_point >= 0 ? recs + (int64_t)w.at_point * p.stride
+                                      : in + (int64_t)(-w.at_point - 1) * p.stride;
+    bool eq = true;
+    UNROLL for (int m = 0; m < R; ++m) {
+        const int64_t i = tid + 256 * m;
+        if (i < T) eq = eq && same_f32(v[m], a0[i]);
+    }
+    int stop = -1;
+    if (__syncthreads_and(eq)) {
+        stop = 0;
+    } else {
+        for (int k = 0; k < w.n_levels; ++k) {
+            const int4 lv = p.levels[w.level_off + k];
+            const float* sb = lv.y >= 0 ? recs + (int64_t)lv.y * p.stride
+                                        : in + (int64_t)(-lv.y - 1) * p.stride;
+            const float* pr = recs + (int64_t)lv.z * p.stride;
+            const int f = lv.x & 3;
+            const bool right = (lv.x & 4) != 0;
+            eq = true;
+            UNROLL for (int m = 0; m < R; ++m) {
+                const int64_t i = tid + 256 * m;
+                if (i < T) {
+                    const float s = sb[i];
+                    const float r = right ? fop_rt(f, s, v[m]) : fop_rt(f, v[m], s);
+                    v[m] = r;
+                    eq = eq && same_f32(r, pr[i]);
+                }
+            }
+            if (__syncthreads_and(eq)) {
+                stop = k + 1;
+                break;
+            }
+        }
+    }
+    if (tid == 0) {
+        p.stop_out[ci] = stop;
+        p.interp_out[ci] = w.donor_nodes + (stop >= 0 ? stop : w.n_levels);
+    }
+    float* ro = p.root_out ? (float*)p.root_out + ci * p.stride : nullptr;
+    if (stop >= 0) {
+        // The difference died out: the child's values above the stop are
+        // the mother's, and so is its fitness.
+        const float* pv = (const float*)p.parent_vecs + (int64_t)w.parent_slot * p.stride;
+        if (ro)
+            for (int64_t i = tid; i < T; i += 256) ro[i] = pv[i];
+        if (tid == 0) ((double*)p.fit_out)[ci] = ((const double*)p.parent_fit)[w.parent_tree];
+    } else {
+        const float* y = (const float*)p.target;
+        double e[R];
+        UNROLL for (int m = 0; m < R; ++m) {
+            const int64_t i = tid + 256 * m;
+            double val = 0.0;
+            if (i < T) {
+                if (ro) ro[i] = v[m];
+                const float d = v[m] - y[i];
+                val = (double)fabsf(d);
+            }
+            e[m] = val;
+        }
+        const double f = halving_sum<R>(e, p.P, red);
+        if (tid == 0) ((double*)p.fit_out)[ci] = f;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_walk_bool(WalkParams p)
+{
+    __shared__ int64_t red[256];
+    const int64_t ci = blockIdx.x;
+    const WalkChild w = p.children[ci];
+    const int tid = threadIdx.x;
+    const int64_t T = p.n_valid;
+    const int64_t W = (T + 63) / 64;
+    const uint64_t* in = (const uint64_t*)p.inputs;
+    const uint64_t* recs = (const uint64_t*)p.recs + (int64_t)w.rec_base * p.stride;
+    const uint64_t* dv = (const uint64_t*)p.donor_vecs + (int64_t)w.donor_slot * p.stride;
+    uint64_t v[R];
+    UNROLL for (int m = 0; m < R; ++m) {
+        const int64_t i = tid + 256 * m;
+        v[m] = (i < W) ? dv[i] : 0ull;
+    }
+    const uint64_t* a0 = w.at_point >= 0 ? recs + (int64_t)w.at_point * p.stride
+                                         : in + (int64_t)(-w.at_point - 1) * p.stride;
+    bool eq = true;
+    UNROLL for (int m = 0; m < R; ++m) {
+        const int64_t i = tid + 256 * m;
+        if (i < W) eq = eq && (((v[m] ^ a0[i]) & valid_bits(i, T)) == 0);
+    }
+    int stop = -1;
+    if (__syncthreads_and(eq)) {
+        stop = 0;
+    } else {
+        for (int k = 0; k < w.n_levels; ++k) {
+            const int4 lv = p.levels[w.level_off + k];
+            const uint64_t* sb = lv.y >= 0 ? recs + (int64_t)lv.y * p.stride
+                                           : in + (int64_t)(-lv.y - 1) * p.stride;
+            const uint64_t* pr = recs + (int64_t)lv.z * p.stride;
+            const int f = lv.x & 3;
+            const bool right = (lv.x & 4) != 0;
+            eq = true;
+            UNROLL for (int m = 0; m < R; ++m) {
+                const int64_t i = tid + 256 * m;
+                if (i < W) {
+                    const uint64_t s = sb[i];
+                    const uint64_t r = right ? bop_rt(f, s, v[m]) : bop_rt(f, v[m], s);
+                    v[m] = r;
+                    eq = eq && (((r ^ pr[i]) & valid_bits(i, T)) == 0);
+                }
+            }
+            if (__syncthreads_and(eq)) {
+                stop = k + 1;
+                break;
+            }
+        }
+    }
+    if (tid == 0) {
+        p.stop_out[ci] = stop;
+        p.interp_out[ci] = w.donor_nodes + (stop >= 0 ? stop : w.n_levels);
+    }
+    uint64_t* ro = p.root_out ? (uint64_t*)p.root_out + ci * p.stride : nullptr;
+    if (stop >= 0) {
+        const uint64_t* pv = (const uint64_t*)p.parent_vecs + (int64_t)w.parent_slot * p.stride;
+        if (ro)
+            for (int64_t i = tid; i < W; i += 256) ro[i] = pv[i];
+        if (tid == 0) ((int64_t*)p.fit_out)[ci] = ((const int64_t*)p.parent_fit)[w.parent_tree];
+    } else {
+        const uint64_t* t = (const uint64_t*)p.target;
+        int64_t hits = 0;
+        UNROLL for (int m = 0; m < R; ++m) {
+            const int64_t i = tid + 256 * m;
+            if (i < W) {
+                if (ro) ro[i] = v[m];
+                hits += __popcll(~(v[m] ^ t[i]) & valid_bits(i, T));
+            }
+        }
+        const int64_t h = block_sum_i64(hits, red);
+        if (tid == 0) ((int64_t*)p.fit_out)[ci] = h;
+    }
+}
+
+// ---------------------------------------------------------- variants
+static Variant g_variants[] = {
+    {"f32_k1_s16", 0, 1, 16, (const void*)k_eval_f32<1, 16>, 0},
+    {"f32_k2_s16", 0, 2, 16, (const void*)k_eval_f32<2, 16>, 0},
+    {"f32_k4_s16", 0, 4, 16, (const void*)k_eval_f32<4, 16>, 0},
+    {"f32_k8_s16", 0, 8, 16, (const void*)k_eval_f32<8, 16>, 0},
+    {"bool_k1_s16", 1, 1, 16, (const void*)k_eval_bool<1, 16>, 0},
+    {"bool_k2_s16", 1, 2, 16, (const void*)k_eval_bool<2, 16>, 0},
+};
+
+int variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
+Variant* variant_table() { return g_variants; }
+
+hipError_t launch_eval(int variant, const EvalParams& p, int grid, hipStream_t s)
+{
+    const Variant& v = g_variants[variant];
+    size_t shm = v.vtype == 1 ? (size_t)p.n_inputs * kWave * v.K * sizeof(uint64_t) : 0;
+    hipLaunchKernelGGL((void (*)(EvalParams))v.kernel, dim3(grid), dim3(kWave), shm, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int32_t* pending, const int32_t* init, int64_t n, unsigned int* cursor,
+                       int n_cursors, hipStream_t s)
+{
+    int64_t need = std::max<int64_t>(n, n_cursors);
+    int grid = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (need + 255) / 256));
+    hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, s, pending, init, n, cursor, n_cursors);
+    return hipGetLastError();
+}
+
+static int halving_rows(int64_t P) { return P <= 256 ? 1 : (int)(P / 256); }
+
+hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (vtype == 1) {
+        hipLaunchKernelGGL(k_fit_bool, dim3((unsigned)n), dim3(256), 0, s, p);
+        return hipGetLastError();
+    }
+    switch (halving_rows(p.P)) {
+    case 1: hipLaunchKernelGGL(k_fit_f32<1>, dim3((unsigned)n), dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL(k_fit_f32<2>, dim3((unsigned)n), dim3(256), 0, s, p); break;
+    case 4: hipLaunchKernelGGL(k_fit_f32<4>, dim3((unsigned)n), dim3(256), 0, s, p); break;
+    case 8: hipLaunchKernelGGL(k_fit_f32<8>, dim3((unsigned)n), dim3(256), 0, s, p); break;
+    case 16: hipLaunchKernelGGL(k_fit_f32<16>, dim3((unsigned)n), dim3(256), 0, s, p); break;
+    case 32: hipLaunchKernelGGL(k_fit_f32<32>, dim3((unsigned)n), dim3(256), 0, s, p); break;
+    case 64: hipLaunchKernelGGL(k_fit_f32<64>, dim3((unsigned)n), dim3(256), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s)
+{
+    if (n_children <= 0) return hipSuccess;
+    if (vtype == 1) {
+        const int64_t W = (p.n_valid + 63) / 64;
+        const int rows = W <= 256 ? 1 : (int)((W + 255) / 256);
+        switch (rows) {
+        case 1: hipLaunchKernelGGL(k_walk_bool<1>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+        case 2: hipLaunchKernelGGL(k_walk_bool<2>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+        case 3:
+        case 4: hipLaunchKernelGGL(k_walk_bool<4>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+        default:
+            if (rows <= 16) {
+                hipLaunchKernelGGL(k_walk_bool<16>, dim3((unsigned)n_children), dim3(256), 0, s, p);
+                break;
+            }
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (halving_rows(p.P)) {
+    case 1: hipLaunchKernelGGL(k_walk_f32<1>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL(k_walk_f32<2>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 4: hipLaunchKernelGGL(k_walk_f32<4>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 8: hipLaunchKernelGGL(k_walk_f32<8>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 16: hipLaunchKernelGGL(k_walk_f32<16>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 32: hipLaunchKernelGGL(k_walk_f32<32>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 64: hipLaunchKernelGGL(k_walk_f32<64>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gpe

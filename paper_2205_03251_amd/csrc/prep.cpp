@@ -1,0 +1,336 @@
+// Host-side tree compiler: see prep.h.
+#include "prep.h"
+
+#include <algorithm>
+#include <unordered_map>
+
+namespace gpe {
+
+namespace {
+
+inline bool is_func(uint8_t b) { return (b & kFuncBit) != 0; }
+
+struct Frame {
+    int64_t v;
+    int32_t d;
+    int32_t stage;     // 0 first visit, 1 after the first operand, 2 after both
+    int64_t second;    // operand evaluated second (stage 1)
+    uint32_t mode;
+    uint32_t payload;
+};
+
+}  // namespace
+
+bool validate_prefix(const uint8_t* ops, int64_t n, int n_inputs, std::string* why)
+{
+    if (n < 1) {
+        if (why) *why = "empty tree";
+        return false;
+    }
+    if (n > INT32_MAX) {
+        if (why) *why = "tree longer than 2^31-1 nodes";
+        return false;
+    }
+    int64_t open = 1;   // child slots still to fill
+    for (int64_t i = 0; i < n; ++i) {
+        if (open == 0) {
+            if (why) *why = "bytes after the end of the tree at index " + std::to_string(i);
+            return false;
+        }
+        uint8_t b = ops[i];
+        if (is_func(b)) {
+            if ((b & 0x7f) > 3) {
+                if (why) *why = "unknown function byte at index " + std::to_string(i);
+                return false;
+            }
+            open += 1;
+        } else {
+            if (b >= n_inputs) {
+                if (why) *why = "terminal index >= n_inputs at index " + std::to_string(i);
+                return false;
+            }
+            open -= 1;
+        }
+    }
+    if (open != 0) {
+        if (why) *why = "tree ends with " + std::to_string(open) + " operand(s) missing";
+        return false;
+    }
+    return true;
+}
+
+bool postfix_to_prefix(const uint8_t* post, int64_t n, int n_inputs, std::vector<uint8_t>* pre,
+                       std::vector<int64_t>* post_to_pre, std::string* why)
+{
+    if (n < 1 || n > INT32_MAX) {
+        if (why) *why = "bad tree length";
+        return false;
+    }
+    // start[i]: first postfix index of the subtree ending at i.
+    std::vector<int64_t> start(n);
+    std::vector<int64_t> st;
+    st.reserve(64);
+    for (int64_t i = 0; i < n; ++i) {
+        uint8_t b = post[i];
+        if (is_func(b)) {
+            if ((b & 0x7f) > 3 || st.size() < 2) {
+                if (why) *why = "malformed postfix tree at index " + std::to_string(i);
+                return false;
+            }
+            st.pop_back();                 // right operand
+            start[i] = start[st.back()];   // left operand's start
+            st.back() = i;
+        } else {
+            if (b >= n_inputs) {
+                if (why) *why = "terminal index >= n_inputs at index " + std::to_string(i);
+                return false;
+            }
+            start[i] = i;
+            st.push_back(i);
+        }
+    }
+    if (st.size() != 1) {
+        if (why) *why = "postfix array is not exactly one tree";
+        return false;
+    }
+    pre->resize(n);
+    post_to_pre->resize(n);
+    // Prefix order = node, left subtree, right subtree.  In postfix the right
+    // operand of node v ends at v-1 and the left one ends just before the
+    // right one starts.
+    std::vector<int64_t> todo;
+    todo.push_back(n - 1);
+    int64_t k = 0;
+    while (!todo.empty()) {
+        int64_t v = todo.back();
+        todo.pop_back();
+        (*pre)[k] = post[v];
+        (*post_to_pre)[v] = k;
+        ++k;
+        if (is_func(post[v])) {
+            int64_t r = v - 1;
+            int64_t l = start[r] - 1;
+            todo.push_back(r);
+            todo.push_back(l);
+        }
+    }
+    return true;
+}
+
+bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, const int64_t* points,
+                  int64_t n_points, TreeProg* out, std::string* why)
+{
+    const bool boolean = opt.vtype == 1;
+    const int S = opt.stack_slots;
+    const int64_t C = std::max<int64_t>(2, opt.chunk_nodes);
+    if (S < 2 || S > kMaxStackSlots) {
+        if (why) *why = "stack_slots out of range";
+        return false;
+    }
+    // Float folds terminal 0 (kept in registers); Boolean folds any terminal
+    // (read from the staged input words).
+    auto foldable = [&](int64_t v) { return !is_func(ops[v]) && (boolean || ops[v] == 0); };
+
+    std::vector<int32_t> rch(n, -1);      // right child of each function node
+    std::vector<uint8_t> need(n, 1);      // stack slots to produce the value
+    std::vector<int32_t> open(n, 1);      // nodes not yet assigned to a chunk below
+    std::vector<uint8_t> cut(n, 0);       // node roots a chunk of its own
+    std::vector<int32_t> st;
+    st.reserve(1024);
+
+    // One right-to-left pass: children are finished before their parent.
+    for (int64_t i = n - 1; i >= 0; --i) {
+        if (!is_func(ops[i])) {
+            st.push_back((int32_t)i);
+            continue;
+        }
+        int32_t l = st.back();
+        st.pop_back();
+        int32_t r = st.back();
+        st.back() = (int32_t)i;
+        rch[i] = r;
+        auto cost = [&](int32_t c) { return cut[c] ? 1 : (int)need[c]; };
+        auto need_of = [&]() {
+            bool fl = !cut[l] && foldable(l), fr = !cut[r] && foldable(r);
+            if (fl && fr) return 1;
+            if (fl) return cost(r);
+            if (fr) return cost(l);
+            int nl = cost(l), nr = cost(r);
+            return nl >= nr ? std::max(nl, nr + 1) : std::max(nr, nl + 1);
+        };
+        int nd = need_of();
+        if (nd > S) {
+            // Both operands need a full stack: give the bigger one a chunk of
+            // its own; its value then arrives by one LOAD (one slot).
+            int32_t big = cost(l) >= cost(r) ? l : r;
+            cut[big] = 1;
+            nd = need_of();
+        }
+        need[i] = (uint8_t)nd;
+        int64_t o = 1 + (cut[l] ? 1 : open[l]) + (cut[r] ? 1 : open[r]);
+        open[i] = (int32_t)std::min<int64_t>(o, INT32_MAX);
+        if (o >= C && i != 0) cut[i] = 1;
+    }
+
+    // Records requested by the crossover points: the mother's vector at the
+    // point, at every ancestor, and at each ancestor's other operand.
+    std::unordered_map<int64_t, int32_t> rec_of;
+    auto rec = [&](int64_t v) -> int32_t {
+        if (!is_func(ops[v])) return -(int32_t)ops[v] - 1;
+        auto it = rec_of.find(v);
+        if (it != rec_of.end()) return it->second;
+        int32_t id = (int32_t)rec_of.size();
+        rec_of.emplace(v, id);
+        return id;
+    };
+    out->spines.clear();
+    std::vector<int64_t> path;
+    for (int64_t p = 0; p < n_points; ++p) {
+        int64_t c = points[p];
+        if (c < 0 || c >= n) {
+            if (why) *why = "record point " + std::to_string(c) + " out of range";
+            return false;
+        }
+        path.clear();
+        int64_t v = 0;
+        path.push_back(0);
+        while (v != c) {
+            int64_t l = v + 1, r = rch[v];
+            v = (c < r) ? l : r;
+            path.push_back(v);
+        }
+        Spine sp;
+        sp.point = c;
+        sp.at_point = rec(c);
+        int64_t e = c;                // last node of c's subtree: follow right children
+        while (is_func(ops[e])) e = rch[e];
+        sp.child_nodes_removed = e + 1 - c;
+        for (int64_t k = (int64_t)path.size() - 2; k >= 0; --k) {
+            int64_t a = path[k], below = path[k + 1];
+            int64_t l = a + 1, r = rch[a];
+            bool right = below != l;
+            int64_t sib = right ? l : r;
+            SpineLevel lv;
+            lv.fside = (ops[a] & 3) | (right ? 4 : 0);
+            lv.sib = rec(sib);
+            lv.par = rec(a);
+            sp.levels.push_back(lv);
+        }
+        out->spines.push_back(std::move(sp));
+    }
+    if (rec_of.size() > kMaxPayload) {
+        if (why) *why = "too many parent-cache records in one tree";
+        return false;
+    }
+    out->n_records = (int64_t)rec_of.size();
+
+    // Chunks: the root plus every cut node, numbered by descending prefix
+    // index so that every chunk comes after the chunks it reads.
+    std::vector<int64_t> roots;
+    for (int64_t i = n - 1; i > 0; --i)
+        if (cut[i]) roots.push_back(i);
+    roots.push_back(0);
+    std::unordered_map<int64_t, int32_t> chunk_of;
+    chunk_of.reserve(roots.size() * 2);
+    for (size_t k = 0; k < roots.size(); ++k) chunk_of[roots[k]] = (int32_t)k;
+
+    out->chunks.assign(roots.size(), Chunk());
+    out->code.clear();
+    out->code.reserve((size_t)(n / 2 + roots.size() * 2 + rec_of.size() + 8));
+    int32_t max_slot = 0;
+    std::vector<Frame> fr;
+    fr.reserve(256);
+    for (size_t k = 0; k < roots.size(); ++k) {
+        Chunk& ch = out->chunks[k];
+        int64_t root = roots[k];
+        ch.root_node = root;
+        ch.code_off = (int64_t)out->code.size();
+        ch.nodes = 0;
+        fr.clear();
+        fr.push_back(Frame{root, 0, 0, 0, 0, 0});
+        while (!fr.empty()) {
+            Frame& F = fr.back();
+            int64_t v = F.v;
+            int32_t d = F.d;
+            if (F.stage == 0) {
+                max_slot = std::max(max_slot, d);
+                if (v != root && cut[v]) {
+                    int32_t child = chunk_of[v];
+                    out->chunks[child].parent = (int32_t)k;
+                    out->code.push_back(ins_word(0, M_LOAD, d, (uint32_t)ch.inputs.size()));
+                    ch.inputs.push_back(child);
+                    fr.pop_back();
+                    continue;
+                }
+                ch.nodes += 1;
+                if (!is_func(ops[v])) {
+                    out->code.push_back(ins_word(0, M_PUSH, d, ops[v]));
+                    fr.pop_back();
+                    continue;
+                }
+                int64_t l = v + 1, r = rch[v];
+                bool fl = !cut[l] && foldable(l), fr_ = !cut[r] && foldable(r);
+                if (fl && fr_) {
+                    ch.nodes += 2;
+                    F.mode = M_XX;
+                    F.payload = boolean ? (uint32_t)ops[l] | ((uint32_t)ops[r] << 11) : 0;
+                    F.stage = 2;
+                    continue;
+                }
+                if (fl || fr_) {
+                    ch.nodes += 1;
+                    int64_t other = fl ? r : l;
+                    if (boolean) {
+                        F.mode = M_XS;
+                        F.payload = fl ? ops[l] : ops[r];
+                    } else {
+                        F.mode = fl ? M_XS : M_SX;
+                        F.payload = 0;
+                    }
+                    F.stage = 2;
+                    fr.push_back(Frame{other, d, 0, 0, 0, 0});
+                    continue;
+                }
+                int nl = cut[l] ? 1 : need[l], nr = cut[r] ? 1 : need[r];
+                int64_t first = (nl >= nr) ? l : r;
+                F.second = (first == l) ? r : l;
+                F.mode = (first == l || boolean) ? M_SS : M_RS;
+                F.payload = 0;
+                F.stage = 1;
+                fr.push_back(Frame{first, d, 0, 0, 0, 0});
+                continue;
+            }
+            if (F.stage == 1) {
+                F.stage = 2;
+                int64_t s = F.second;
+                fr.push_back(Frame{s, d + 1, 0, 0, 0, 0});
+                continue;
+            }
+            // stage 2: both operands are in place
+            out->code.push_back(ins_word(ops[v] & 3, F.mode, d, F.payload));
+            if (F.mode == M_SS || F.mode == M_RS) max_slot = std::max(max_slot, d + 1);
+            auto it = rec_of.find(v);
+            if (it != rec_of.end()) out->code.push_back(ins_word(0, M_STORE, d, (uint32_t)it->second));
+            fr.pop_back();
+        }
+        ch.code_len = (int64_t)out->code.size() - ch.code_off;
+        if (ch.inputs.size() > kMaxPayload) {
+            if (why) *why = "chunk reads too many child chunks";
+            return false;
+        }
+    }
+    out->max_stack = max_slot + 1;
+    if (out->max_stack > S) {
+        if (why) *why = "internal error: stack bound exceeded";
+        return false;
+    }
+    // Longest chain of chunk work from each chunk up to the tree root
+    // (parents come after children, so walk backwards).
+    for (int64_t k = (int64_t)out->chunks.size() - 1; k >= 0; --k) {
+        Chunk& ch = out->chunks[k];
+        ch.path_nodes = ch.nodes + (ch.parent >= 0 ? out->chunks[ch.parent].path_nodes : 0);
+    }
+    return true;
+}
+
+}  // namespace gpe

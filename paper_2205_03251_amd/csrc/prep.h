@@ -1,0 +1,102 @@
+// Host-side tree compiler of the gpeval library: validation, layout
+// conversion, evaluation-order choice, chunking and parent-cache (spine)
+// planning.  Pure C++ (no HIP); the runtime uploads what it produces.
+//
+// A tree is flattened in prefix order, one opcode byte per node (Section 3.1
+// of the paper).  Trees are side-effect free, so any evaluation order gives
+// the same values (Section 6.2).  The compiler uses that freedom: it
+// evaluates the child needing more stack first (Ershov / Sethi-Ullman order),
+// so the register stack needs at most about log2(n) slots instead of the
+// tree height, and it folds terminal operands into their parent's
+// instruction.  Non-commutative operations whose right operand is evaluated
+// first get a "reversed" instruction that still computes op(left, right).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gpe {
+
+// ---------------------------------------------------------------- opcodes
+constexpr uint8_t kFuncBit = 0x80;
+constexpr int kMaxInputs = 64;
+
+// ------------------------------------------------------ instruction words
+// One 32-bit word per instruction:
+//   bits 0..1   f      function (ADD/SUB/MUL/PDIV or AND/OR/NAND/NOR)
+//   bits 2..4   mode   operand sources (below)
+//   bits 5..9   d      evaluation-stack slot the result goes to
+//   bits 10..31 payload
+// Modes ("x" = a terminal operand folded into the instruction):
+//   XX    st[d] = f(x_a, x_b)            float: x = input 0; Boolean: payload = a | b << 11
+//   XS    st[d] = f(x, st[d])            Boolean: payload = input index (f symmetric)
+//   SX    st[d] = f(st[d], x)            float only
+//   SS    st[d] = f(st[d], st[d+1])      left operand evaluated first
+//   RS    st[d] = f(st[d+1], st[d])      right operand evaluated first
+//   PUSH  st[d] = input[payload]
+//   LOAD  st[d] = output of child chunk number `payload` of this chunk
+//   STORE record st[d] into parent-cache slot rec_base + payload
+enum Mode : uint32_t { M_XX = 0, M_XS = 1, M_SX = 2, M_SS = 3, M_RS = 4, M_PUSH = 5, M_LOAD = 6, M_STORE = 7 };
+constexpr int kPayloadShift = 10;
+constexpr uint32_t kKeyMask = 0x3ffu;
+constexpr uint32_t kMaxPayload = (1u << 22) - 1;
+constexpr int kMaxStackSlots = 32;
+
+inline uint32_t ins_word(uint32_t f, uint32_t mode, uint32_t d, uint32_t payload)
+{
+    return f | (mode << 2) | (d << 5) | (payload << kPayloadShift);
+}
+
+struct Chunk {
+    int64_t code_off = 0;        // offset in TreeProg::code
+    int64_t code_len = 0;
+    int32_t parent = -1;         // local chunk id, -1 for the tree root chunk
+    int64_t root_node = 0;       // prefix index of the chunk's root
+    int64_t nodes = 0;           // tree nodes evaluated by this chunk
+    int64_t path_nodes = 0;      // nodes on the longest chunk chain from here to the tree root
+    std::vector<int32_t> inputs; // local chunk ids read by LOAD payload 0, 1, ...
+};
+
+// Source of a cached vector: >= 0 a record slot (local to the tree),
+// < 0 the input vector -(src + 1).
+struct SpineLevel {
+    int32_t fside;    // f | (path operand is the right one) << 2
+    int32_t sib;      // sibling subtree's vector
+    int32_t par;      // the mother's vector at this ancestor
+};
+
+struct Spine {
+    int64_t point = 0;           // prefix index of the crossover point
+    int32_t at_point = 0;        // the mother's vector at the point
+    int64_t child_nodes_removed = 0;  // nodes of the subtree at the point
+    std::vector<SpineLevel> levels;   // ancestors, nearest first
+};
+
+struct TreeProg {
+    std::vector<uint32_t> code;
+    std::vector<Chunk> chunks;   // children before parents; the last is the root chunk
+    int32_t max_stack = 0;       // highest slot used + 1
+    int64_t n_records = 0;       // parent-cache vectors this tree records
+    std::vector<Spine> spines;
+};
+
+struct CompileOptions {
+    int vtype = 0;               // 0 float32, 1 Boolean
+    int n_inputs = 1;
+    int64_t chunk_nodes = 4096;  // target nodes per chunk
+    int stack_slots = 16;        // register-stack slots available
+};
+
+// Section 3.1 format check of one prefix array.
+bool validate_prefix(const uint8_t* ops, int64_t n, int n_inputs, std::string* why);
+
+// Reverse Polish to prefix.  post_to_pre[i] = prefix index of postfix node i.
+bool postfix_to_prefix(const uint8_t* post, int64_t n, int n_inputs, std::vector<uint8_t>* pre,
+                       std::vector<int64_t>* post_to_pre, std::string* why);
+
+// Compile one validated prefix tree.  points: crossover points (prefix
+// indices) whose parent caches must be recorded.
+bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, const int64_t* points,
+                  int64_t n_points, TreeProg* out, std::string* why);
+
+}  // namespace gpe

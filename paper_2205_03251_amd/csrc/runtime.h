@@ -1,0 +1,148 @@
+// Internal runtime objects of the gpeval library (context, populations,
+// case sets, launch plans).  Shared by runtime.hip and server.cpp.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gpeval.h"
+#include "dev.h"
+#include "prep.h"
+
+namespace gpe {
+
+struct Ctx;
+
+// Device allocation charged against the context's HBM budget.
+struct DevBuf {
+    Ctx* ctx = nullptr;
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    void release();
+    template <class T> T* as() const { return (T*)p; }
+};
+
+struct CaseSet {
+    int vtype = 0;
+    int n_inputs = 0;
+    int64_t T = 0;               // test cases
+    int64_t n_elems = 0;         // float: T; Boolean: words = ceil(T/64)
+    int64_t stride = 0;          // n_elems padded to kPadCases
+    int64_t P = 64;              // fitness halving width
+    DevBuf inputs;               // [n_inputs][stride]
+    DevBuf target;               // [stride]
+};
+
+// Launch plan of one population for one interpreter variant and slicing.
+struct Plan {
+    int variant = -1;
+    bool per_tree = false;
+    int32_t n_slices = 0;
+    int64_t n_items = 0;
+    int grid = 0;
+    DevBuf items;                // int64 work items
+    DevBuf pending_init;         // int32 [n_chunks * n_slices]
+    DevBuf pending;
+    DevBuf cursor;               // one per tree in per-tree mode
+    std::vector<int64_t> tree_item_begin, tree_item_count;
+    hipGraphExec_t graph = nullptr;
+    gp_handle graph_cases = 0;
+    ~Plan();
+};
+
+struct SpineInfo {
+    int32_t tree;
+    int32_t at_point;
+    int64_t level_off;
+    int32_t n_levels;
+    int64_t removed_nodes;
+};
+
+struct Pop {
+    int vtype = 0;
+    int n_inputs = 0;
+    int64_t n_trees = 0;
+    int64_t total_nodes = 0;
+    int64_t chunk_nodes = 0;
+    int32_t max_stack = 0;
+    std::vector<int64_t> tree_nodes;
+    // compiled program
+    int64_t n_chunks = 0;
+    int64_t n_code = 0;
+    int64_t n_records = 0;
+    std::vector<int64_t> rec_base;          // per tree
+    std::vector<int32_t> chunk_n_in;        // per chunk
+    std::vector<int32_t> chunk_tree;        // per chunk
+    std::vector<std::pair<int64_t, int32_t>> leaves;  // (priority, chunk), sorted
+    DevBuf code, chunks, chunk_in;
+    // parent caches
+    std::unordered_map<uint64_t, int32_t> spine_of;   // (tree, point) -> spine
+    std::vector<SpineInfo> spines;
+    DevBuf levels;                          // int4 per spine level
+    // evaluation state
+    int64_t stride = 0;                     // case stride of vecs/recs
+    DevBuf vecs;                            // [n_chunks][stride]: roots are slots 0..n_trees-1
+    DevBuf recs;                            // [n_records][stride]
+    DevBuf fit;                             // [n_trees] double or int64
+    gp_handle evaluated_with = 0;           // case set of the last full evaluation
+    std::map<std::pair<int, int>, std::unique_ptr<Plan>> plans;  // (variant, per_tree)
+};
+
+struct TuneKey {
+    int vtype, tbucket, sbucket;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(vtype, tbucket, sbucket) < std::tie(o.vtype, o.tbucket, o.sbucket);
+    }
+};
+
+struct Server;
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    int n_cu = 0;
+    std::string err;
+    std::mutex mu;                          // guards handles (server threads share the ctx)
+    gp_handle next_handle = 1;
+    std::unordered_map<gp_handle, std::shared_ptr<CaseSet>> cases;
+    std::unordered_map<gp_handle, std::shared_ptr<Pop>> pops;
+    int forced_variant = -1;
+    std::map<TuneKey, int> tuned;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    Server* server = nullptr;
+};
+
+// ------------------------------------------------------------ internals
+int set_err(Ctx* c, int code, const std::string& msg);
+int dev_alloc(Ctx* c, DevBuf& b, size_t bytes);
+int hip_check(Ctx* c, hipError_t e, const char* what);
+
+// Compile and upload a population (prefix or postfix trees).
+int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees,
+                     const uint8_t* ops, const int64_t* offsets, const int64_t* rec_points,
+                     const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out);
+// Make sure vecs/recs/fit match the case set; allocate if needed.
+int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs);
+// Enqueue a full evaluation on stream s (no copies out, no synchronisation).
+int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int variant, bool per_tree,
+                 bool use_graph, hipStream_t s, int64_t* launches);
+int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p);
+int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_t T);
+int compile_stack_slots();
+
+}  // namespace gpe

@@ -1,0 +1,1003 @@
+// gpeval runtime: context, device memory under an HBM budget, population
+// assembly, launch plans (one persistent batched launch captured in a
+// hipGraph, or one launch per tree), incremental batches and the C ABI.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "runtime.h"
+
+namespace gpe {
+
+// ------------------------------------------------------------ errors
+int set_err(Ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_check(Ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return GP_OK;
+    return set_err(c, GP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPC(c, x)                                        \
+    do {                                                  \
+        int rc__ = hip_check((c), (x), #x);               \
+        if (rc__ != GP_OK) return rc__;                   \
+    } while (0)
+
+#define RC(x)                                             \
+    do {                                                  \
+        int rc__ = (x);                                   \
+        if (rc__ != GP_OK) return rc__;                   \
+    } while (0)
+
+// ------------------------------------------------------------ memory
+DevBuf::~DevBuf() { release(); }
+
+void DevBuf::release()
+{
+    if (p) {
+        (void)hipFree(p);
+        if (ctx) ctx->used -= bytes;
+    }
+    p = nullptr;
+    bytes = 0;
+}
+
+int dev_alloc(Ctx* c, DevBuf& b, size_t bytes)
+{
+    b.release();
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (c->used + bytes > c->budget)
+        return set_err(c, GP_EBUDGET,
+                       "device memory budget exceeded: need " + std::to_string(bytes) + " more bytes, " +
+                           std::to_string(c->budget - std::min<uint64_t>(c->budget, c->used)) + " left");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(c, GP_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    b.ctx = c;
+    b.p = p;
+    b.bytes = bytes;
+    c->used += bytes;
+    return GP_OK;
+}
+
+static int upload(Ctx* c, DevBuf& b, const void* src, size_t bytes)
+{
+    RC(dev_alloc(c, b, bytes));
+    if (bytes) HIPC(c, hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return GP_OK;
+}
+
+Plan::~Plan()
+{
+    if (graph) (void)hipGraphExecDestroy(graph);
+}
+
+// ---------------------------------------------------------- heuristics
+int compile_stack_slots() { return 16; }
+
+int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_t T)
+{
+    (void)vtype;
+    (void)n_trees;
+    (void)T;
+    // Small chunks keep the chain of dependent chunks in the largest trees
+    // short; very small ones spend more on chunk hand-off than on work.
+    if (total_nodes < 200000) return 256;
+    return 2048;
+}
+
+static int64_t elems_of(int vtype, int64_t T) { return vtype == GP_BOOL ? (T + 63) / 64 : T; }
+
+static int64_t pad_to(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+static int ilog2_ceil(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
+{
+    Variant* vt = variant_table();
+    auto ok = [&](int v) { return v >= 0 && v < variant_count() && vt[v].vtype == vtype && vt[v].S >= p->max_stack; };
+    if (ok(c->forced_variant)) return c->forced_variant;
+    TuneKey key{vtype, ilog2_ceil(cs->T), ilog2_ceil(std::max<int64_t>(1, p->total_nodes / std::max<int64_t>(1, p->n_trees)))};
+    auto it = c->tuned.find(key);
+    if (it != c->tuned.end() && ok(it->second)) return it->second;
+    int wantK = 1;
+    if (vtype == GP_F32) wantK = cs->n_elems <= 64 ? 1 : cs->n_elems <= 128 ? 2 : 4;
+    else wantK = cs->n_elems <= 64 ? 1 : 2;
+    for (int v = 0; v < variant_count(); ++v)
+        if (ok(v) && vt[v].K == wantK) return v;
+    for (int v = 0; v < variant_count(); ++v)
+        if (ok(v)) return v;
+    return -1;
+}
+
+// -------------------------------------------------- population assembly
+int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees, const uint8_t* ops,
+                     const int64_t* offsets, const int64_t* rec_points, const int64_t* rec_offsets,
+                     int64_t chunk_nodes, Pop* out)
+{
+    if (vtype != GP_F32 && vtype != GP_BOOL) return set_err(c, GP_EINVAL, "unknown value type");
+    if (layout != GP_PREFIX && layout != GP_POSTFIX) return set_err(c, GP_EINVAL, "unknown layout");
+    if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(c, GP_EINVAL, "n_inputs must be 1..64");
+    if (vtype == GP_BOOL && n_inputs > 2047) return set_err(c, GP_EINVAL, "too many inputs");
+    if (n_trees < 1 || !ops || !offsets) return set_err(c, GP_EINVAL, "empty population");
+    if (n_trees > INT32_MAX / 2) return set_err(c, GP_EINVAL, "too many trees");
+    if (offsets[0] != 0) return set_err(c, GP_EINVAL, "offsets[0] must be 0");
+    int64_t total = 0;
+    for (int64_t t = 0; t < n_trees; ++t) {
+        if (offsets[t + 1] <= offsets[t]) return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + " is empty");
+        total += offsets[t + 1] - offsets[t];
+    }
+    if (rec_points && !rec_offsets) return set_err(c, GP_EINVAL, "record_points needs record_offsets");
+    if (rec_offsets && rec_offsets[0] != 0) return set_err(c, GP_EINVAL, "record_offsets[0] must be 0");
+    if (chunk_nodes <= 0) chunk_nodes = auto_chunk_nodes(vtype, total, n_trees, 0);
+    chunk_nodes = std::max<int64_t>(chunk_nodes, 16);
+
+    out->vtype = vtype;
+    out->n_inputs = n_inputs;
+    out->n_trees = n_trees;
+    out->total_nodes = total;
+    out->chunk_nodes = chunk_nodes;
+    out->tree_nodes.resize(n_trees);
+
+    CompileOptions opt;
+    opt.vtype = vtype;
+    opt.n_inputs = n_inputs;
+    opt.chunk_nodes = chunk_nodes;
+    opt.stack_slots = compile_stack_slots();
+
+    std::vector<TreeProg> progs(n_trees);
+    std::vector<std::string> errs(n_trees);
+    std::vector<char> bad(n_trees, 0);
+    std::vector<int64_t> order(n_trees);
+    for (int64_t t = 0; t < n_trees; ++t) order[t] = t;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+    });
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        std::vector<uint8_t> pre;
+        std::vector<int64_t> map, pts;
+        for (;;) {
+            int64_t k = next.fetch_add(1);
+            if (k >= n_trees) return;
+            int64_t t = order[k];
+            const uint8_t* tops = ops + offsets[t];
+            int64_t n = offsets[t + 1] - offsets[t];
+            const int64_t* p0 = rec_points ? rec_points + rec_offsets[t] : nullptr;
+            int64_t np = rec_points ? rec_offsets[t + 1] - rec_offsets[t] : 0;
+            if (np < 0) {
+                bad[t] = 1;
+                errs[t] = "record_offsets not increasing";
+                continue;
+            }
+            const uint8_t* tree = tops;
+            pts.assign(p0, p0 + np);
+            if (layout == GP_POSTFIX) {
+                if (!postfix_to_prefix(tops, n, n_inputs, &pre, &map, &errs[t])) {
+                    bad[t] = 1;
+                    continue;
+                }
+                for (auto& q : pts) {
+                    if (q < 0 || q >= n) {
+                        bad[t] = 1;
+                        errs[t] = "record point out of range";
+                        break;
+                    }
+                    q = map[q];
+                }
+                if (bad[t]) continue;
+                tree = pre.data();
+            } else if (!validate_prefix(tops, n, n_inputs, &errs[t])) {
+                bad[t] = 1;
+                continue;
+            }
+            if (!compile_tree(tree, n, opt, pts.data(), (int64_t)pts.size(), &progs[t], &errs[t])) {
+                bad[t] = 1;
+                continue;
+            }
+            // spine keys use the caller's indices
+            for (int64_t i = 0; i < np; ++i) progs[t].spines[i].point = p0[i];
+        }
+    };
+    int nth = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+    nth = (int)std::min<int64_t>(nth, n_trees);
+    if (total < 100000) nth = 1;
+    std::vector<std::thread> th;
+    for (int i = 1; i < nth; ++i) th.emplace_back(work);
+    work();
+    for (auto& x : th) x.join();
+    for (int64_t t = 0; t < n_trees; ++t)
+        if (bad[t]) return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + ": " + errs[t]);
+
+    // Global numbering: tree t's root chunk writes vector slot t; every
+    // other chunk gets a slot after the roots.
+    int64_t n_chunks = 0, n_code = 0, n_rec = 0, n_in = 0, n_lv = 0;
+    for (auto& pg : progs) {
+        n_chunks += (int64_t)pg.chunks.size();
+        n_code += (int64_t)pg.code.size();
+        n_rec += pg.n_records;
+        for (auto& ch : pg.chunks) n_in += (int64_t)ch.inputs.size();
+        for (auto& sp : pg.spines) n_lv += (int64_t)sp.levels.size();
+    }
+    if (n_chunks > INT32_MAX / 2 || n_rec > INT32_MAX / 2 || n_in > INT32_MAX / 2)
+        return set_err(c, GP_EINVAL, "population too large for one load");
+    std::vector<uint32_t> code;
+    code.reserve(n_code + 64);
+    std::vector<DevChunk> dch(n_chunks);
+    std::vector<int32_t> chunk_in;
+    chunk_in.reserve(n_in);
+    std::vector<int4> levels;
+    levels.reserve(n_lv);
+    out->chunk_n_in.assign(n_chunks, 0);
+    out->chunk_tree.assign(n_chunks, 0);
+    out->rec_base.assign(n_trees, 0);
+    out->leaves.clear();
+    out->spines.clear();
+    out->spine_of.clear();
+    out->max_stack = 0;
+    int64_t cbase = 0, rbase = 0, next_slot = n_trees;
+    std::vector<int32_t> slot;
+    for (int64_t t = 0; t < n_trees; ++t) {
+        TreeProg& pg = progs[t];
+        out->tree_nodes[t] = offsets[t + 1] - offsets[t];
+        out->rec_base[t] = rbase;
+        out->max_stack = std::max(out->max_stack, pg.max_stack);
+        const int64_t obase = (int64_t)code.size();
+        code.insert(code.end(), pg.code.begin(), pg.code.end());
+        const int64_t nc = (int64_t)pg.chunks.size();
+        slot.assign(nc, 0);
+        for (int64_t k = 0; k < nc; ++k) slot[k] = (k == nc - 1) ? (int32_t)t : (int32_t)(next_slot++);
+        for (int64_t k = 0; k < nc; ++k) {
+            const Chunk& ch = pg.chunks[k];
+            DevChunk& d = dch[cbase + k];
+            d.code_off = obase + ch.code_off;
+            d.code_len = (int32_t)ch.code_len;
+            d.parent = ch.parent >= 0 ? (int32_t)(cbase + ch.parent) : -1;
+            d.out_slot = slot[k];
+            d.in_off = (int32_t)chunk_in.size();
+            d.rec_base = (int32_t)rbase;
+            d.tree = (int32_t)t;
+            for (int32_t in : ch.inputs) chunk_in.push_back(slot[in]);
+            out->chunk_n_in[cbase + k] = (int32_t)ch.inputs.size();
+            out->chunk_tree[cbase + k] = (int32_t)t;
+            if (ch.inputs.empty()) out->leaves.emplace_back(ch.path_nodes, (int32_t)(cbase + k));
+        }
+        for (auto& sp : pg.spines) {
+            uint64_t key = ((uint64_t)t << 32) | (uint32_t)sp.point;
+            if (out->spine_of.count(key)) continue;
+            SpineInfo si;
+            si.tree = (int32_t)t;
+            si.at_point = sp.at_point;
+            si.level_off = (int64_t)levels.size();
+            si.n_levels = (int32_t)sp.levels.size();
+            si.removed_nodes = sp.child_nodes_removed;
+            for (auto& lv : sp.levels) levels.push_back(make_int4(lv.fside, lv.sib, lv.par, 0));
+            out->spine_of[key] = (int32_t)out->spines.size();
+            out->spines.push_back(si);
+        }
+        cbase += nc;
+        rbase += pg.n_records;
+        TreeProg().code.swap(pg.code);
+        pg.chunks.clear();
+        pg.chunks.shrink_to_fit();
+    }
+    // Longest remaining chain first; slices of a chunk are handed out
+    // together when plans expand the leaves.
+    std::stable_sort(out->leaves.begin(), out->leaves.end(),
+                     [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
+                         return a.first > b.first;
+                     });
+    code.push_back(0);                      // one word past the end for the fetch-ahead
+    out->n_chunks = n_chunks;
+    out->n_code = (int64_t)code.size() - 1;
+    out->n_records = n_rec;
+    RC(upload(c, out->code, code.data(), code.size() * sizeof(uint32_t)));
+    RC(upload(c, out->chunks, dch.data(), dch.size() * sizeof(DevChunk)));
+    RC(upload(c, out->chunk_in, chunk_in.data(), chunk_in.size() * sizeof(int32_t)));
+    RC(upload(c, out->levels, levels.data(), levels.size() * sizeof(int4)));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    return GP_OK;
+}
+
+int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs)
+{
+    const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
+    if (p->stride == cs->stride && p->vecs.p && p->fit.p) return GP_OK;
+    for (auto& kv : p->plans)
+        if (kv.second->graph) {
+            (void)hipGraphExecDestroy(kv.second->graph);
+            kv.second->graph = nullptr;
+        }
+    p->vecs.release();
+    p->recs.release();
+    p->evaluated_with = 0;
+    RC(dev_alloc(c, p->vecs, (size_t)p->n_chunks * cs->stride * esz));
+    if (p->n_records) RC(dev_alloc(c, p->recs, (size_t)p->n_records * cs->stride * esz));
+    RC(dev_alloc(c, p->fit, (size_t)p->n_trees * 8));
+    p->stride = cs->stride;
+    return GP_OK;
+}
+
+static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, int variant, bool per_tree, Plan** out)
+{
+    const Variant& v = variant_table()[variant];
+    const int32_t n_slices = (int32_t)((cs->n_elems + kWave * v.K - 1) / (kWave * v.K));
+    auto key = std::make_pair(variant, per_tree ? 1 : 0);
+    auto it = p->plans.find(key);
+    if (it != p->plans.end() && it->second->n_slices == n_slices) {
+        *out = it->second.get();
+        return GP_OK;
+    }
+    auto pl = std::make_unique<Plan>();
+    pl->variant = variant;
+    pl->per_tree = per_tree;
+    pl->n_slices = n_slices;
+    std::vector<int64_t> items;
+    items.reserve(p->leaves.size() * n_slices);
+    if (!per_tree) {
+        for (auto& lf : p->leaves)
+            for (int32_t s = 0; s < n_slices; ++s) items.push_back(((int64_t)lf.second << 16) | s);
+    } else {
+        std::vector<std::vector<int64_t>> by_tree(p->n_trees);
+        for (auto& lf : p->leaves)
+            for (int32_t s = 0; s < n_slices; ++s)
+                by_tree[p->chunk_tree[lf.second]].push_back(((int64_t)lf.second << 16) | s);
+        pl->tree_item_begin.resize(p->n_trees);
+        pl->tree_item_count.resize(p->n_trees);
+        for (int64_t t = 0; t < p->n_trees; ++t) {
+            pl->tree_item_begin[t] = (int64_t)items.size();
+            pl->tree_item_count[t] = (int64_t)by_tree[t].size();
+            items.insert(items.end(), by_tree[t].begin(), by_tree[t].end());
+        }
+    }
+    pl->n_items = (int64_t)items.size();
+    std::vector<int32_t> pend((size_t)p->n_chunks * n_slices);
+    for (int64_t k = 0; k < p->n_chunks; ++k)
+        for (int32_t s = 0; s < n_slices; ++s) pend[(size_t)k * n_slices + s] = p->chunk_n_in[k];
+    RC(upload(c, pl->items, items.data(), items.size() * sizeof(int64_t)));
+    RC(upload(c, pl->pending_init, pend.data(), pend.size() * sizeof(int32_t)));
+    RC(dev_alloc(c, pl->pending, pend.size() * sizeof(int32_t)));
+    RC(dev_alloc(c, pl->cursor, (size_t)(per_tree ? p->n_trees : 1) * sizeof(unsigned int)));
+    const int64_t full = (int64_t)std::max(1, v.max_blocks_per_cu) * std::max(1, c->n_cu);
+    pl->grid = (int)std::max<int64_t>(1, std::min<int64_t>(full, pl->n_items));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    p->plans[key] = std::move(pl);
+    *out = p->plans[key].get();
+    return GP_OK;
+}
+
+static EvalParams eval_params(Pop* p, const CaseSet* cs, Plan* pl)
+{
+    EvalParams e;
+    e.code = p->code.as<uint32_t>();
+    e.chunks = p->chunks.as<DevChunk>();
+    e.chunk_in = p->chunk_in.as<int32_t>();
+    e.items = pl->items.as<int64_t>();
+    e.n_items = pl->n_items;
+    e.pending = pl->pending.as<int32_t>();
+    e.cursor = pl->cursor.as<unsigned int>();
+    e.inputs = cs->inputs.p;
+    e.vecs = p->vecs.p;
+    e.recs = p->recs.p;
+    e.stride = cs->stride;
+    e.n_slices = pl->n_slices;
+    e.n_inputs = cs->n_inputs;
+    return e;
+}
+
+static FitParams fit_params(Pop* p, const CaseSet* cs)
+{
+    FitParams f;
+    f.vecs = p->vecs.p;
+    f.first_slot = 0;
+    f.target = cs->target.p;
+    f.fit_out = p->fit.p;
+    f.stride = cs->stride;
+    f.n_valid = cs->T;
+    f.P = cs->P;
+    return f;
+}
+
+// Everything one full evaluation enqueues: reset counters and cursors,
+// evaluate, score.
+static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t s, int64_t* launches)
+{
+    const int64_t n_pend = p->n_chunks * pl->n_slices;
+    HIPC(c, launch_init(pl->pending.as<int32_t>(), pl->pending_init.as<int32_t>(), n_pend,
+                        pl->cursor.as<unsigned int>(), pl->per_tree ? (int)p->n_trees : 1, s));
+    EvalParams e = eval_params(p, cs, pl);
+    int64_t nl = 1;
+    if (!pl->per_tree) {
+        HIPC(c, launch_eval(pl->variant, e, pl->grid, s));
+        ++nl;
+    } else {
+        const Variant& v = variant_table()[pl->variant];
+        const int64_t full = (int64_t)std::max(1, v.max_blocks_per_cu) * std::max(1, c->n_cu);
+        for (int64_t t = 0; t < p->n_trees; ++t) {
+            EvalParams et = e;
+            et.items = e.items + pl->tree_item_begin[t];
+            et.n_items = pl->tree_item_count[t];
+            et.cursor = e.cursor + t;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(full, et.n_items));
+            HIPC(c, launch_eval(pl->variant, et, grid, s));
+            ++nl;
+        }
+    }
+    HIPC(c, launch_fitness(p->vtype, fit_params(p, cs), p->n_trees, s));
+    ++nl;
+    if (launches) *launches += nl;
+    return GP_OK;
+}
+
+int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int variant, bool per_tree,
+                 bool use_graph, hipStream_t s, int64_t* launches)
+{
+    RC(ensure_eval_buffers(c, p, cs));
+    Plan* pl = nullptr;
+    RC(make_plan(c, p, cs, variant, per_tree, &pl));
+    if (!use_graph) {
+        RC(enqueue_body(c, p, cs, pl, s, launches));
+    } else {
+        if (!pl->graph || pl->graph_cases != cases_h) {
+            if (pl->graph) {
+                (void)hipGraphExecDestroy(pl->graph);
+                pl->graph = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIPC(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            int64_t dummy = 0;
+            int rc = enqueue_body(c, p, cs, pl, s, &dummy);
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (rc != GP_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            HIPC(c, e2);
+            hipError_t e3 = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPC(c, e3);
+            pl->graph_cases = cases_h;
+        }
+        HIPC(c, hipGraphLaunch(pl->graph, s));
+        if (launches) *launches += 1;
+    }
+    p->evaluated_with = cases_h;
+    return GP_OK;
+}
+
+}  // namespace gpe
+
+using namespace gpe;
+
+// =================================================================== C ABI
+struct gp_ctx : public Ctx {};
+
+static thread_local std::string g_static_err;
+
+static double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+extern "C" {
+
+int gp_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, gp_ctx** out)
+{
+    if (!out) return GP_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        g_static_err = "no HIP device available";
+        return GP_EDEVICE;
+    }
+    if (device < 0 || device >= n) {
+        g_static_err = "device index out of range";
+        return GP_EINVAL;
+    }
+    gp_ctx* c = new gp_ctx();
+    c->device = device;
+    auto fail = [&](hipError_t er, const char* what) {
+        g_static_err = std::string(what) + ": " + hipGetErrorString(er);
+        delete c;
+        return GP_EDEVICE;
+    };
+    if ((e = hipSetDevice(device)) != hipSuccess) return fail(e, "hipSetDevice");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_static_err = std::string("gpeval is built for gfx950, found ") + prop.gcnArchName;
+        delete c;
+        return GP_EDEVICE;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    size_t free_b = 0, total_b = 0;
+    if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) return fail(e, "hipMemGetInfo");
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess)
+            return fail(e, "hipStreamCreate");
+        c->own_stream = true;
+    }
+    if ((e = hipEventCreate(&c->ev0)) != hipSuccess) return fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&c->ev1)) != hipSuccess) return fail(e, "hipEventCreate");
+    Variant* vt = variant_table();
+    for (int v = 0; v < variant_count(); ++v) {
+        int nb = 0;
+        size_t shm = vt[v].vtype == GP_BOOL ? (size_t)8 * kWave * vt[v].K * sizeof(uint64_t) : 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, vt[v].kernel, kWave, shm) != hipSuccess) {
+            (void)hipGetLastError();
+            nb = 4;
+        }
+        vt[v].max_blocks_per_cu = std::max(1, nb);
+    }
+    *out = c;
+    return GP_OK;
+}
+
+int gp_server_stop(gp_ctx* ctx);
+
+void gp_destroy(gp_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    gp_server_stop(ctx);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->pops.clear();
+    ctx->cases.clear();
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* gp_last_error(const gp_ctx* ctx)
+{
+    if (!ctx) return g_static_err.c_str();
+    return ctx->err.c_str();
+}
+
+uint64_t gp_memory_used(const gp_ctx* ctx) { return ctx ? ctx->used.load() : 0; }
+
+int gp_set_cases(gp_ctx* ctx, int vtype, int n_inputs, int64_t n_cases, const void* inputs,
+                 const void* target, uint32_t flags, gp_handle* cases_out)
+{
+    if (!ctx || !cases_out) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    if (vtype != GP_F32 && vtype != GP_BOOL) return set_err(ctx, GP_EINVAL, "unknown value type");
+    if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(ctx, GP_EINVAL, "n_inputs must be 1..64");
+    if (n_cases < 1) return set_err(ctx, GP_EINVAL, "need at least one test case");
+    if (vtype == GP_F32 && n_cases > 16384) return set_err(ctx, GP_EINVAL, "float32 case sets hold at most 16384 cases");
+    if (vtype == GP_BOOL && n_cases > (int64_t(1) << 18)) return set_err(ctx, GP_EINVAL, "Boolean case sets hold at most 2^18 cases");
+    if (!inputs || !target) return set_err(ctx, GP_EINVAL, "inputs and target are required");
+    auto cs = std::make_shared<CaseSet>();
+    cs->vtype = vtype;
+    cs->n_inputs = n_inputs;
+    cs->T = n_cases;
+    cs->n_elems = elems_of(vtype, n_cases);
+    cs->stride = pad_to(cs->n_elems, kPadCases);
+    int64_t P = 64;
+    while (P < n_cases) P *= 2;
+    cs->P = P;
+    const size_t esz = vtype == GP_BOOL ? 8 : 4;
+    RC(dev_alloc(ctx, cs->inputs, (size_t)n_inputs * cs->stride * esz));
+    RC(dev_alloc(ctx, cs->target, (size_t)cs->stride * esz));
+    // zero padding keeps the unused lanes' arithmetic well defined
+    std::vector<uint8_t> zeros((size_t)cs->stride * esz, 0);
+    for (int j = 0; j < n_inputs; ++j)
+        HIPC(ctx, hipMemcpyAsync(cs->inputs.as<uint8_t>() + (size_t)j * cs->stride * esz, zeros.data(),
+                                 zeros.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPC(ctx, hipMemcpyAsync(cs->target.p, zeros.data(), zeros.size(), hipMemcpyHostToDevice, ctx->stream));
+    const hipMemcpyKind kind = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPC(ctx, hipMemcpy2DAsync(cs->inputs.p, cs->stride * esz, inputs, cs->n_elems * esz, cs->n_elems * esz,
+                               n_inputs, kind, ctx->stream));
+    HIPC(ctx, hipMemcpyAsync(cs->target.p, target, cs->n_elems * esz, kind, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    gp_handle h = ctx->next_handle++;
+    ctx->cases[h] = cs;
+    *cases_out = h;
+    return GP_OK;
+}
+
+int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t n_trees, const uint8_t* ops,
+                       const int64_t* offsets, const int64_t* record_points, const int64_t* record_offsets,
+                       int64_t chunk_nodes, uint32_t flags, gp_handle* pop_out)
+{
+    if (!ctx || !pop_out) return GP_EINVAL;
+    (void)flags;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    auto p = std::make_shared<Pop>();
+    RC(build_population(ctx, vtype, layout, n_inputs, n_trees, ops, offsets, record_points, record_offsets,
+                        chunk_nodes, p.get()));
+    gp_handle h = ctx->next_handle++;
+    ctx->pops[h] = p;
+    *pop_out = h;
+    return GP_OK;
+}
+
+int gp_population_info(gp_ctx* ctx, gp_handle pop, gp_pop_info* out)
+{
+    if (!ctx || !out) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->pops.find(pop);
+    if (it == ctx->pops.end()) return set_err(ctx, GP_EINVAL, "unknown population handle");
+    Pop* p = it->second.get();
+    out->n_trees = p->n_trees;
+    out->total_nodes = p->total_nodes;
+    out->n_chunks = p->n_chunks;
+    out->n_instructions = p->n_code;
+    out->n_records = p->n_records;
+    out->n_spines = (int64_t)p->spines.size();
+    uint64_t b = p->code.bytes + p->chunks.bytes + p->chunk_in.bytes + p->levels.bytes + p->vecs.bytes +
+                 p->recs.bytes + p->fit.bytes;
+    for (auto& kv : p->plans)
+        b += kv.second->items.bytes + kv.second->pending.bytes + kv.second->pending_init.bytes + kv.second->cursor.bytes;
+    out->device_bytes = (int64_t)b;
+    out->max_stack = p->max_stack;
+    out->chunk_nodes = (int32_t)p->chunk_nodes;
+    return GP_OK;
+}
+
+int gp_free(gp_ctx* ctx, gp_handle h)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pops.erase(h)) return GP_OK;
+    if (ctx->cases.erase(h)) {
+        for (auto& kv : ctx->pops) {
+            if (kv.second->evaluated_with == h) kv.second->evaluated_with = 0;
+            for (auto& pk : kv.second->plans)
+                if (pk.second->graph_cases == h && pk.second->graph) {
+                    (void)hipGraphExecDestroy(pk.second->graph);
+                    pk.second->graph = nullptr;
+                    pk.second->graph_cases = 0;
+                }
+        }
+        return GP_OK;
+    }
+    return set_err(ctx, GP_EINVAL, "unknown handle");
+}
+
+static int lookup(gp_ctx* ctx, gp_handle pop, gp_handle cases, Pop** p, CaseSet** cs)
+{
+    auto ip = ctx->pops.find(pop);
+    if (ip == ctx->pops.end()) return set_err(ctx, GP_EINVAL, "unknown population handle");
+    auto ic = ctx->cases.find(cases);
+    if (ic == ctx->cases.end()) return set_err(ctx, GP_EINVAL, "unknown case-set handle");
+    *p = ip->second.get();
+    *cs = ic->second.get();
+    if ((*p)->vtype != (*cs)->vtype) return set_err(ctx, GP_EINVAL, "population and case set differ in value type");
+    if ((*p)->n_inputs > (*cs)->n_inputs)
+        return set_err(ctx, GP_EINVAL, "population uses more inputs than the case set provides");
+    return GP_OK;
+}
+
+static int copy_out(gp_ctx* ctx, void* dst, const void* src, int64_t rows, int64_t elems, int64_t stride,
+                    size_t esz, uint32_t flags)
+{
+    if (!dst || rows <= 0) return GP_OK;
+    const hipMemcpyKind kind = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPC(ctx, hipMemcpy2DAsync(dst, elems * esz, src, stride * esz, elems * esz, rows, kind, ctx->stream));
+    return GP_OK;
+}
+
+int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags, void* root_out,
+                     void* fitness_out, gp_stats* st)
+{
+    if (!ctx) return GP_EINVAL;
+    const double t0 = now_ms();
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Pop* p;
+    CaseSet* cs;
+    RC(lookup(ctx, pop, cases, &p, &cs));
+    if ((flags & GP_ASYNC) && !(flags & GP_DEVICE_PTR))
+        return set_err(ctx, GP_EINVAL, "GP_ASYNC needs GP_DEVICE_PTR outputs");
+    const int variant = choose_variant(ctx, p->vtype, cs, p);
+    if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits this population");
+    const bool per_tree = (flags & GP_PER_TREE) != 0;
+    const bool graph = !(flags & GP_NO_GRAPH);
+    int64_t launches = 0;
+    HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    RC(enqueue_full(ctx, p, cases, cs, variant, per_tree, graph, ctx->stream, &launches));
+    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
+    RC(copy_out(ctx, root_out, p->vecs.p, p->n_trees, cs->n_elems, cs->stride, esz, flags));
+    if (fitness_out) {
+        const hipMemcpyKind kind = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        HIPC(ctx, hipMemcpyAsync(fitness_out, p->fit.p, (size_t)p->n_trees * 8, kind, ctx->stream));
+    }
+    float ms = 0.f;
+    if (!(flags & GP_ASYNC)) {
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));
+        HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    }
+    if (st) {
+        st->device_ms = ms;
+        st->equivalent_ops = p->total_nodes * cs->T;
+        st->interpreted_ops = p->total_nodes * cs->T;
+        st->launches = launches;
+        st->variant = variant;
+        st->wall_ms = now_ms() - t0;
+    }
+    return GP_OK;
+}
+
+int gp_fitness(gp_ctx* ctx, gp_handle cases, const void* outputs, int64_t n, uint32_t flags, void* fitness_out)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    auto ic = ctx->cases.find(cases);
+    if (ic == ctx->cases.end()) return set_err(ctx, GP_EINVAL, "unknown case-set handle");
+    CaseSet* cs = ic->second.get();
+    if (n < 0 || (n > 0 && (!outputs || !fitness_out))) return set_err(ctx, GP_EINVAL, "bad outputs");
+    if (n == 0) return GP_OK;
+    const size_t esz = cs->vtype == GP_BOOL ? 8 : 4;
+    DevBuf vecs, fit;
+    RC(dev_alloc(ctx, vecs, (size_t)n * cs->stride * esz));
+    RC(dev_alloc(ctx, fit, (size_t)n * 8));
+    const hipMemcpyKind kin = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPC(ctx, hipMemcpy2DAsync(vecs.p, cs->stride * esz, outputs, cs->n_elems * esz, cs->n_elems * esz, n, kin,
+                               ctx->stream));
+    FitParams f;
+    f.vecs = vecs.p;
+    f.first_slot = 0;
+    f.target = cs->target.p;
+    f.fit_out = fit.p;
+    f.stride = cs->stride;
+    f.n_valid = cs->T;
+    f.P = cs->P;
+    HIPC(ctx, launch_fitness(cs->vtype, f, n, ctx->stream));
+    const hipMemcpyKind kout = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPC(ctx, hipMemcpyAsync(fitness_out, fit.p, (size_t)n * 8, kout, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    return GP_OK;
+}
+
+int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t n_children,
+                                  const int64_t* parent, const int64_t* point, const uint8_t* donor_ops,
+                                  const int64_t* donor_offsets, uint32_t flags, void* root_out,
+                                  void* fitness_out, gp_inc_result* res, gp_stats* st)
+{
+    if (!ctx) return GP_EINVAL;
+    const double t0 = now_ms();
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Pop* p;
+    CaseSet* cs;
+    RC(lookup(ctx, pop, cases, &p, &cs));
+    if (n_children < 0) return set_err(ctx, GP_EINVAL, "negative child count");
+    if (n_children == 0) return GP_OK;
+    if (!parent || !point || !donor_ops || !donor_offsets) return set_err(ctx, GP_EINVAL, "missing child arrays");
+    if ((flags & GP_ASYNC) && !(flags & GP_DEVICE_PTR))
+        return set_err(ctx, GP_EINVAL, "GP_ASYNC needs GP_DEVICE_PTR outputs");
+    if (p->evaluated_with != cases)
+        return set_err(ctx, GP_ENOTFOUND, "the population has no parent caches for this case set; "
+                                          "run gp_evaluate_full on it first");
+    // Children -> spines (the mother's recorded vectors along the path).
+    std::vector<WalkChild> wc(n_children);
+    int64_t equiv_nodes = 0;
+    for (int64_t i = 0; i < n_children; ++i) {
+        if (parent[i] < 0 || parent[i] >= p->n_trees)
+            return set_err(ctx, GP_EINVAL, "child " + std::to_string(i) + ": parent index out of range");
+        if (point[i] < 0 || point[i] >= p->tree_nodes[parent[i]])
+            return set_err(ctx, GP_EINVAL, "child " + std::to_string(i) + ": crossover point out of range");
+        auto it = p->spine_of.find(((uint64_t)parent[i] << 32) | (uint32_t)point[i]);
+        if (it == p->spine_of.end())
+            return set_err(ctx, GP_ENOTFOUND, "child " + std::to_string(i) + ": point " + std::to_string(point[i]) +
+                                                  " of tree " + std::to_string(parent[i]) + " was not recorded");
+        const SpineInfo& si = p->spines[it->second];
+        const int64_t nd = donor_offsets[i + 1] - donor_offsets[i];
+        if (nd < 1) return set_err(ctx, GP_EINVAL, "child " + std::to_string(i) + ": empty donor");
+        WalkChild& w = wc[i];
+        w.level_off = si.level_off;
+        w.n_levels = si.n_levels;
+        w.at_point = si.at_point;
+        w.rec_base = (int32_t)p->rec_base[parent[i]];
+        w.parent_slot = (int32_t)parent[i];
+        w.parent_tree = (int32_t)parent[i];
+        w.donor_slot = (int32_t)i;
+        w.donor_nodes = nd;
+        equiv_nodes += p->tree_nodes[parent[i]] - si.removed_nodes + nd;
+    }
+    // Inserted subtrees: evaluated on every case like any population.
+    Pop donors;
+    int layout = (flags & 0x100u) ? GP_POSTFIX : GP_PREFIX;
+    RC(build_population(ctx, p->vtype, layout, p->n_inputs, n_children, donor_ops, donor_offsets, nullptr, nullptr,
+                        0, &donors));
+    const int variant = choose_variant(ctx, p->vtype, cs, &donors);
+    if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits the donors");
+    const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
+    DevBuf d_wc, d_root, d_fit, d_stop, d_interp;
+    RC(upload(ctx, d_wc, wc.data(), wc.size() * sizeof(WalkChild)));
+    RC(dev_alloc(ctx, d_root, root_out ? (size_t)n_children * cs->stride * esz : 256));
+    RC(dev_alloc(ctx, d_fit, (size_t)n_children * 8));
+    RC(dev_alloc(ctx, d_stop, (size_t)n_children * 4));
+    RC(dev_alloc(ctx, d_interp, (size_t)n_children * 8));
+    int64_t launches = 0;
+    HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    RC(enqueue_full(ctx, &donors, cases, cs, variant, false, false, ctx->stream, &launches));
+    WalkParams wp;
+    wp.children = d_wc.as<WalkChild>();
+    wp.levels = p->levels.as<int4>();
+    wp.inputs = cs->inputs.p;
+    wp.recs = p->recs.p;
+    wp.parent_vecs = p->vecs.p;
+    wp.parent_fit = p->fit.p;
+    wp.donor_vecs = donors.vecs.p;
+    wp.target = cs->target.p;
+    wp.root_out = root_out ? d_root.p : nullptr;
+    wp.fit_out = d_fit.p;
+    wp.stop_out = d_stop.as<int32_t>();
+    wp.interp_out = d_interp.as<int64_t>();
+    wp.stride = cs->stride;
+    wp.n_valid = cs->T;
+    wp.P = cs->P;
+    HIPC(ctx, launch_walk(p->vtype, wp, n_children, ctx->stream));
+    ++launches;
+    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    RC(copy_out(ctx, root_out, d_root.p, n_children, cs->n_elems, cs->stride, esz, flags));
+    if (fitness_out) {
+        const hipMemcpyKind kind = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        HIPC(ctx, hipMemcpyAsync(fitness_out, d_fit.p, (size_t)n_children * 8, kind, ctx->stream));
+    }
+    std::vector<int32_t> stop(n_children);
+    std::vector<int64_t> interp(n_children);
+    HIPC(ctx, hipMemcpyAsync(stop.data(), d_stop.p, (size_t)n_children * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipMemcpyAsync(interp.data(), d_interp.p, (size_t)n_children * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    int64_t interp_total = 0;
+    for (int64_t i = 0; i < n_children; ++i) {
+        const SpineInfo& si = p->spines[p->spine_of[((uint64_t)parent[i] << 32) | (uint32_t)point[i]]];
+        if (res) {
+            res[i].stop_level = stop[i];
+            res[i].reserved = 0;
+            res[i].child_nodes = p->tree_nodes[parent[i]] - si.removed_nodes + wc[i].donor_nodes;
+            res[i].interpreted_nodes = interp[i];
+        }
+        interp_total += interp[i];
+    }
+    if (st) {
+        st->device_ms = ms;
+        st->equivalent_ops = equiv_nodes * cs->T;
+        st->interpreted_ops = interp_total * cs->T;
+        st->launches = launches;
+        st->variant = variant;
+        st->wall_ms = now_ms() - t0;
+    }
+    return GP_OK;
+}
+
+int gp_evaluate_incremental(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t parent, int64_t point,
+                            const uint8_t* donor_ops, int64_t donor_len, uint32_t flags, void* root_out,
+                            void* fitness_out, gp_inc_result* res)
+{
+    int64_t offs[2] = {0, donor_len};
+    return gp_evaluate_incremental_batch(ctx, pop, cases, 1, &parent, &point, donor_ops, offs, flags, root_out,
+                                         fitness_out, res, nullptr);
+}
+
+const char* gp_variant_name(int variant)
+{
+    if (variant < 0 || variant >= variant_count()) return nullptr;
+    return variant_table()[variant].name;
+}
+
+int gp_variant_count(void) { return variant_count(); }
+
+int gp_set_variant(gp_ctx* ctx, int variant)
+{
+    if (!ctx) return GP_EINVAL;
+    if (variant >= variant_count()) return set_err(ctx, GP_EINVAL, "unknown variant");
+    ctx->forced_variant = variant < 0 ? -1 : variant;
+    return GP_OK;
+}
+
+int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, double* best_ms)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Pop* p;
+    CaseSet* cs;
+    RC(lookup(ctx, pop, cases, &p, &cs));
+    int best = -1;
+    float best_t = 1e30f;
+    for (int v = 0; v < variant_count(); ++v) {
+        const Variant& vt = variant_table()[v];
+        if (vt.vtype != p->vtype || vt.S < p->max_stack) continue;
+        RC(enqueue_full(ctx, p, cases, cs, v, false, true, ctx->stream, nullptr));   // warm-up + capture
+        float tmin = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+            RC(enqueue_full(ctx, p, cases, cs, v, false, true, ctx->stream, nullptr));
+            HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+            HIPC(ctx, hipStreamSynchronize(ctx->stream));
+            float ms = 0.f;
+            HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            tmin = std::min(tmin, ms);
+        }
+        if (tmin < best_t) {
+            best_t = tmin;
+            best = v;
+        }
+    }
+    if (best < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits this population");
+    TuneKey key{p->vtype, ilog2_ceil(cs->T), ilog2_ceil(std::max<int64_t>(1, p->total_nodes / std::max<int64_t>(1, p->n_trees)))};
+    ctx->tuned[key] = best;
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t;
+    return GP_OK;
+}
+
+int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n)
+{
+    if ((vtype != GP_F32 && vtype != GP_BOOL) || n_inputs < 1 || n_inputs > kMaxInputs || !ops) return GP_EINVAL;
+    return validate_prefix(ops, n, n_inputs, nullptr) ? GP_OK : GP_EINVAL;
+}
+
+int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t n, int64_t chunk_nodes,
+                           int stack_slots, uint32_t* code_out, int64_t code_cap, int64_t* chunk_out,
+                           int64_t chunk_cap, int32_t* inputs_out, int64_t inputs_cap, int64_t* n_code,
+                           int32_t* max_stack)
+{
+    if ((vtype != GP_F32 && vtype != GP_BOOL) || n_inputs < 1 || n_inputs > kMaxInputs || !ops) return GP_EINVAL;
+    if (!validate_prefix(ops, n, n_inputs, nullptr)) return GP_EINVAL;
+    CompileOptions opt;
+    opt.vtype = vtype;
+    opt.n_inputs = n_inputs;
+    opt.chunk_nodes = chunk_nodes > 0 ? chunk_nodes : 4096;
+    opt.stack_slots = stack_slots > 0 ? stack_slots : compile_stack_slots();
+    TreeProg pg;
+    std::string why;
+    if (!compile_tree(ops, n, opt, nullptr, 0, &pg, &why)) return GP_EINVAL;
+    if (n_code) *n_code = (int64_t)pg.code.size();
+    if (max_stack) *max_stack = pg.max_stack;
+    int64_t n_in = 0;
+    for (auto& ch : pg.chunks) n_in += (int64_t)ch.inputs.size();
+    if ((int64_t)pg.code.size() > code_cap || (int64_t)pg.chunks.size() > chunk_cap || n_in > inputs_cap)
+        return GP_ENOMEM;
+    if (code_out) std::memcpy(code_out, pg.code.data(), pg.code.size() * sizeof(uint32_t));
+    int64_t k_in = 0;
+    for (int64_t k = 0; k < (int64_t)pg.chunks.size(); ++k) {
+        const Chunk& ch = pg.chunks[k];
+        if (chunk_out) {
+            chunk_out[4 * k + 0] = ch.code_off;
+            chunk_out[4 * k + 1] = ch.code_len;
+            chunk_out[4 * k + 2] = ch.parent;
+            chunk_out[4 * k + 3] = (int64_t)ch.inputs.size();
+        }
+        for (int32_t in : ch.inputs)
+            if (inputs_out) inputs_out[k_in++] = in;
+    }
+    return (int64_t)pg.chunks.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,331 @@
+"""ctypes binding of libgpeval.so (argument marshalling only).
+
+Every evaluation step runs in the library's HIP kernels; this module only
+converts numpy arrays / torch tensors to pointers and sizes.  There is no
+fallback: if the built library is missing, importing raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpeval.so")
+
+GP_OK, GP_EINVAL, GP_ENOMEM, GP_EBUDGET, GP_EDEVICE, GP_ENOTFOUND, GP_EBUSY = 0, -1, -2, -3, -4, -5, -6
+GP_F32, GP_BOOL = 0, 1
+GP_PREFIX, GP_POSTFIX = 0, 1
+GP_DEVICE_PTR, GP_ASYNC, GP_PER_TREE, GP_NO_GRAPH = 0x1, 0x2, 0x4, 0x8
+GP_JOB_FULL, GP_JOB_INCREMENTAL = 0, 1
+ERRNAMES = {GP_EINVAL: "EINVAL", GP_ENOMEM: "ENOMEM", GP_EBUDGET: "EBUDGET", GP_EDEVICE: "EDEVICE",
+            GP_ENOTFOUND: "ENOTFOUND", GP_EBUSY: "EBUSY"}
+
+EXPORTS = [
+    "gp_create", "gp_destroy", "gp_last_error", "gp_memory_used", "gp_set_cases", "gp_load_population",
+    "gp_population_info", "gp_free", "gp_evaluate_full", "gp_evaluate_incremental_batch",
+    "gp_evaluate_incremental", "gp_fitness", "gp_variant_name", "gp_variant_count", "gp_autotune",
+    "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
+    "gp_server_stop", "gp_inspect_program", "gp_validate_tree",
+]
+
+
+class GPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gpeval {ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [("device_ms", C.c_double), ("wall_ms", C.c_double), ("equivalent_ops", C.c_int64),
+                ("interpreted_ops", C.c_int64), ("launches", C.c_int64), ("variant", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class IncResult(C.Structure):
+    _fields_ = [("stop_level", C.c_int32), ("reserved", C.c_int32), ("child_nodes", C.c_int64),
+                ("interpreted_nodes", C.c_int64)]
+
+
+class PopInfo(C.Structure):
+    _fields_ = [("n_trees", C.c_int64), ("total_nodes", C.c_int64), ("n_chunks", C.c_int64),
+                ("n_instructions", C.c_int64), ("n_records", C.c_int64), ("n_spines", C.c_int64),
+                ("device_bytes", C.c_int64), ("max_stack", C.c_int32), ("chunk_nodes", C.c_int32)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("max_batch_jobs", C.c_int32), ("prep_threads", C.c_int32),
+                ("reserved", C.c_int32), ("budget_bytes", C.c_uint64)]
+
+
+class Job(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("layout", C.c_int32), ("cases", C.c_int64),
+                ("ops", C.c_void_p), ("n_ops", C.c_int64), ("record_points", C.c_void_p),
+                ("n_record_points", C.c_int64), ("parent_ticket", C.c_int64), ("point", C.c_int64),
+                ("keep_resident", C.c_int32), ("reserved", C.c_int32)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("fitness_f64", C.c_double), ("fitness_i64", C.c_int64), ("stop_level", C.c_int32),
+                ("status", C.c_int32), ("interpreted_nodes", C.c_int64), ("latency_ms", C.c_double),
+                ("queue_ms", C.c_double)]
+
+
+_lib = None
+P = C.c_void_p
+I64 = C.c_int64
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(the HIP library has no fallback)")
+    h = C.CDLL(LIB_PATH)
+    h.gp_create.argtypes = [C.c_int, C.c_uint64, P, C.POINTER(P)]
+    h.gp_destroy.argtypes = [P]
+    h.gp_destroy.restype = None
+    h.gp_last_error.argtypes = [P]
+    h.gp_last_error.restype = C.c_char_p
+    h.gp_memory_used.argtypes = [P]
+    h.gp_memory_used.restype = C.c_uint64
+    h.gp_set_cases.argtypes = [P, C.c_int, C.c_int, I64, P, P, C.c_uint32, C.POINTER(I64)]
+    h.gp_load_population.argtypes = [P, C.c_int, C.c_int, C.c_int, I64, P, P, P, P, I64, C.c_uint32,
+                                     C.POINTER(I64)]
+    h.gp_population_info.argtypes = [P, I64, C.POINTER(PopInfo)]
+    h.gp_free.argtypes = [P, I64]
+    h.gp_evaluate_full.argtypes = [P, I64, I64, C.c_uint32, P, P, C.POINTER(Stats)]
+    h.gp_evaluate_incremental_batch.argtypes = [P, I64, I64, I64, P, P, P, P, C.c_uint32, P, P,
+                                                P, C.POINTER(Stats)]
+    h.gp_evaluate_incremental.argtypes = [P, I64, I64, I64, I64, P, I64, C.c_uint32, P, P, P]
+    h.gp_fitness.argtypes = [P, I64, P, I64, C.c_uint32, P]
+    h.gp_variant_name.argtypes = [C.c_int]
+    h.gp_variant_name.restype = C.c_char_p
+    h.gp_variant_count.argtypes = []
+    h.gp_autotune.argtypes = [P, I64, I64, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    h.gp_set_variant.argtypes = [P, C.c_int]
+    h.gp_server_start.argtypes = [P, C.POINTER(ServerCfg)]
+    h.gp_server_submit.argtypes = [P, C.POINTER(Job), C.POINTER(I64)]
+    h.gp_server_poll.argtypes = [P, I64, C.POINTER(JobResult), P]
+    h.gp_server_release.argtypes = [P, I64]
+    h.gp_server_stop.argtypes = [P]
+    h.gp_inspect_program.argtypes = [C.c_int, C.c_int, P, I64, I64, C.c_int, P, I64, P, I64, P, I64,
+                                     C.POINTER(I64), C.POINTER(C.c_int32)]
+    h.gp_inspect_program.restype = I64
+    h.gp_validate_tree.argtypes = [C.c_int, C.c_int, P, I64]
+    _lib = h
+    return h
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ------------------------------------------------------------ host-only
+def variant_names():
+    h = lib()
+    return [h.gp_variant_name(i).decode() for i in range(h.gp_variant_count())]
+
+
+def validate_tree(tree, vtype=GP_F32, n_inputs=1) -> bool:
+    t = _np(tree, np.uint8)
+    return lib().gp_validate_tree(vtype, n_inputs, _ptr(t), len(t)) == GP_OK
+
+
+@dataclass
+class Program:
+    code: np.ndarray       # uint32 instructions
+    chunks: np.ndarray     # [n_chunks, 4] int64: code offset, length, parent, n_inputs
+    inputs: list           # per chunk: child chunk ids in LOAD order
+    max_stack: int
+
+
+def inspect_program(tree, vtype=GP_F32, n_inputs=1, chunk_nodes=4096, stack_slots=16) -> Program:
+    t = _np(tree, np.uint8)
+    n = len(t)
+    cap = 2 * n + 64
+    code = np.zeros(cap, np.uint32)
+    chunks = np.zeros((n + 1, 4), np.int64)
+    ins = np.zeros(n + 1, np.int32)
+    nc = I64(0)
+    ms = C.c_int32(0)
+    r = lib().gp_inspect_program(vtype, n_inputs, _ptr(t), n, chunk_nodes, stack_slots, _ptr(code), cap,
+                                 _ptr(chunks), n + 1, _ptr(ins), n + 1, C.byref(nc), C.byref(ms))
+    if r < 0:
+        raise GPError(int(r), "inspect_program failed")
+    chunks = chunks[:r].copy()
+    lists, k = [], 0
+    for c in range(r):
+        m = int(chunks[c, 3])
+        lists.append([int(v) for v in ins[k:k + m]])
+        k += m
+    return Program(code[:nc.value].copy(), chunks, lists, int(ms.value))
+
+
+# ------------------------------------------------------------ context
+class Context:
+    """One gpeval context on one GPU.  Outputs come back as numpy arrays, or
+    as torch tensors on the device when device=True is passed."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, stream=None):
+        h = lib()
+        self._h = P()
+        s = None
+        if stream is not None:
+            s = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+            s = s or None
+        rc = h.gp_create(device, budget_bytes, s, C.byref(self._h))
+        if rc != GP_OK:
+            raise GPError(rc, h.gp_last_error(None).decode())
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().gp_destroy(self._h)
+            self._h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc != GP_OK:
+            raise GPError(rc, lib().gp_last_error(self._h).decode())
+        return rc
+
+    @property
+    def memory_used(self) -> int:
+        return int(lib().gp_memory_used(self._h))
+
+    # -------------------------------------------------------- data
+    def set_cases(self, vtype, inputs, target, n_cases=None) -> int:
+        flags = 0
+        if hasattr(inputs, "data_ptr"):
+            flags |= GP_DEVICE_PTR
+            n_inputs = inputs.shape[0]
+        else:
+            inputs = _np(inputs, np.float32 if vtype == GP_F32 else np.uint64)
+            if inputs.ndim == 1:
+                inputs = inputs[None, :]
+            target = _np(target, np.float32 if vtype == GP_F32 else np.uint64)
+            n_inputs = inputs.shape[0]
+        if n_cases is None:
+            n_cases = target.shape[0] if vtype == GP_F32 else 64 * target.shape[0]
+        out = I64(0)
+        self._check(lib().gp_set_cases(self._h, vtype, n_inputs, n_cases, _ptr(inputs), _ptr(target), flags,
+                                       C.byref(out)))
+        return out.value
+
+    def load_population(self, vtype, ops, offsets, n_inputs=1, layout=GP_PREFIX, record_points=None,
+                        record_offsets=None, chunk_nodes=0) -> int:
+        ops = _np(ops, np.uint8)
+        offsets = _np(offsets, np.int64)
+        rp = _np(record_points, np.int64) if record_points is not None else None
+        ro = _np(record_offsets, np.int64) if record_offsets is not None else None
+        out = I64(0)
+        self._check(lib().gp_load_population(self._h, vtype, layout, n_inputs, len(offsets) - 1, _ptr(ops),
+                                             _ptr(offsets), _ptr(rp), _ptr(ro), chunk_nodes, 0, C.byref(out)))
+        return out.value
+
+    def population_info(self, pop) -> dict:
+        info = PopInfo()
+        self._check(lib().gp_population_info(self._h, pop, C.byref(info)))
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def free(self, h):
+        self._check(lib().gp_free(self._h, h))
+
+    def set_variant(self, v: int):
+        self._check(lib().gp_set_variant(self._h, v))
+
+    def autotune(self, pop, cases):
+        v = C.c_int(0)
+        ms = C.c_double(0)
+        self._check(lib().gp_autotune(self._h, pop, cases, C.byref(v), C.byref(ms)))
+        return v.value, ms.value
+
+    # -------------------------------------------------- evaluation
+    @staticmethod
+    def _out_shape(vtype, n_rows, n_cases):
+        elems = n_cases if vtype == GP_F32 else (n_cases + 63) // 64
+        return (n_rows, elems), (np.float32 if vtype == GP_F32 else np.uint64), \
+            (np.float64 if vtype == GP_F32 else np.int64)
+
+    def evaluate_full(self, pop, cases, vtype, n_trees, n_cases, per_tree=False, graph=True, roots=True,
+                      device=False, async_=False, root_buf=None, fit_buf=None):
+        flags = (GP_PER_TREE if per_tree else 0) | (0 if graph else GP_NO_GRAPH)
+        shape, vdt, fdt = self._out_shape(vtype, n_trees, n_cases)
+        if device:
+            import torch
+            flags |= GP_DEVICE_PTR | (GP_ASYNC if async_ else 0)
+            tv = torch.float32 if vtype == GP_F32 else torch.int64
+            tf = torch.float64 if vtype == GP_F32 else torch.int64
+            r = root_buf if root_buf is not None else (
+                torch.empty(shape, dtype=tv, device=f"cuda:{self.device}") if roots else None)
+            f = fit_buf if fit_buf is not None else torch.empty(n_trees, dtype=tf, device=f"cuda:{self.device}")
+        else:
+            r = np.empty(shape, vdt) if roots else None
+            f = np.empty(n_trees, fdt)
+        st = Stats()
+        self._check(lib().gp_evaluate_full(self._h, pop, cases, flags, _ptr(r), _ptr(f), C.byref(st)))
+        return r, f, st.as_dict()
+
+    def evaluate_incremental(self, pop, cases, vtype, n_cases, parent, point, donor_ops, donor_offsets,
+                             roots=True, device=False):
+        parent = _np(parent, np.int64)
+        point = _np(point, np.int64)
+        donor_ops = _np(donor_ops, np.uint8)
+        donor_offsets = _np(donor_offsets, np.int64)
+        n = len(parent)
+        shape, vdt, fdt = self._out_shape(vtype, n, n_cases)
+        flags = 0
+        if device:
+            import torch
+            flags |= GP_DEVICE_PTR
+            tv = torch.float32 if vtype == GP_F32 else torch.int64
+            tf = torch.float64 if vtype == GP_F32 else torch.int64
+            r = torch.empty(shape, dtype=tv, device=f"cuda:{self.device}") if roots else None
+            f = torch.empty(n, dtype=tf, device=f"cuda:{self.device}")
+        else:
+            r = np.empty(shape, vdt) if roots else None
+            f = np.empty(n, fdt)
+        res = (IncResult * max(n, 1))()
+        st = Stats()
+        self._check(lib().gp_evaluate_incremental_batch(self._h, pop, cases, n, _ptr(parent), _ptr(point),
+                                                        _ptr(donor_ops), _ptr(donor_offsets), flags, _ptr(r),
+                                                        _ptr(f), C.cast(res, P), C.byref(st)))
+        stop = np.array([res[i].stop_level for i in range(n)], np.int32)
+        interp = np.array([res[i].interpreted_nodes for i in range(n)], np.int64)
+        cnodes = np.array([res[i].child_nodes for i in range(n)], np.int64)
+        return r, f, {"stop_level": stop, "interpreted_nodes": interp, "child_nodes": cnodes,
+                      **st.as_dict()}
+
+    def fitness(self, cases, vtype, outputs):
+        outputs = _np(outputs, np.float32 if vtype == GP_F32 else np.uint64)
+        n = outputs.shape[0]
+        f = np.empty(n, np.float64 if vtype == GP_F32 else np.int64)
+        self._check(lib().gp_fitness(self._h, cases, _ptr(outputs), n, 0, _ptr(f)))
+        return f

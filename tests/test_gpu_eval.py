@@ -1,0 +1,329 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Outputs must be bit-exact per test case (both NaN counts as equal), fitness
+bit-exact, incremental stop levels and interpreted counts identical.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from paper_2205_03251_amd import gpeval as g
+from tests.scalar_ref import same_f32
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def f32_variants():
+    return [i for i, n in enumerate(g.variant_names()) if n.startswith("f32")]
+
+
+def bool_variants():
+    return [i for i, n in enumerate(g.variant_names()) if n.startswith("bool")]
+
+
+def fit_equal(a, b):
+    return (a == b) or (math.isnan(a) and math.isnan(b))
+
+
+def check_float_pop(ctx, pop_np, cases, chunk_nodes=0, per_tree=False, graph=True, variant=-1, threads=8):
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, pop_np.ops, pop_np.offsets, n_inputs=cases.x.shape[0],
+                             chunk_nodes=chunk_nodes)
+    ctx.set_variant(variant)
+    roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_F32, pop_np.n_trees, cases.T, per_tree=per_tree, graph=graph)
+    ctx.set_variant(-1)
+    with np.errstate(all="ignore"):
+        want_roots, want_fit = oracle.eval_population_f32(pop_np, cases.x, cases.y, threads=threads)
+    ok = same_f32(roots, want_roots)
+    assert ok.all(), f"{(~ok).sum()} cases differ; first tree {np.argwhere(~ok)[0]}"
+    for i in range(pop_np.n_trees):
+        assert fit_equal(fit[i], want_fit[i]), (i, fit[i], want_fit[i])
+    assert st["equivalent_ops"] == pop_np.sizes().sum() * cases.T
+    ctx.free(ph)
+    ctx.free(ch)
+    return st
+
+
+def test_cfg0_ramped_half_and_half_all_variants(ctx):
+    pop = gen.ramped_half_and_half(1)
+    cases = gen.float_cases(1, 48)
+    for v in f32_variants():
+        say("cfg0 variant", g.variant_names()[v])
+        check_float_pop(ctx, pop, cases, variant=v)
+        check_float_pop(ctx, pop, cases, variant=v, per_tree=True, graph=False)
+
+
+def test_sextic_target_scores_zero_on_gpu(ctx):
+    cases = gen.float_cases(2, 333)
+    pop = gen.pack([gen.sextic_tree(), np.array([0], np.uint8)])
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, pop.ops, pop.offsets)
+    roots, fit, _ = ctx.evaluate_full(ph, ch, g.GP_F32, 2, cases.T)
+    assert np.all(roots[0].view(np.uint32) == cases.y.view(np.uint32))
+    assert fit[0] == 0.0
+    assert np.all(roots[1] == cases.x[0])
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_special_values_and_two_inputs(ctx):
+    rng = np.random.default_rng(3)
+    x0 = np.array([0, -0.0, 1e-7, -1e-7, 1e-6, 1e-20, 1e30, -3e38, np.inf, -np.inf, np.nan, 1.0, 2.5, -7.0,
+                   1e-45, 3.0], np.float32)
+    x = np.stack([x0, x0[::-1].copy()])
+    y = np.zeros(len(x0), np.float32)
+    cases = gen.FloatCases(x, y)
+    trees = [gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 401)), n_terms=2) for _ in range(60)]
+    pop = gen.pack(trees, n_inputs=2)
+    for v in f32_variants():
+        check_float_pop(ctx, pop, cases, chunk_nodes=32, variant=v)
+
+
+@pytest.mark.parametrize("chunk_nodes", [16, 300, 4096])
+def test_multi_chunk_ragged_cases(ctx, chunk_nodes):
+    pop = gen.sized_population(11, 24, 101, 30001)
+    cases = gen.float_cases(5, 300)            # not a multiple of 64
+    for v in f32_variants():
+        say("multi-chunk", chunk_nodes, g.variant_names()[v])
+        check_float_pop(ctx, pop, cases, chunk_nodes=chunk_nodes, variant=v)
+    check_float_pop(ctx, pop, cases, chunk_nodes=chunk_nodes, per_tree=True)
+
+
+def test_results_independent_of_batch(ctx):
+    pop = gen.sized_population(12, 30, 11, 5001)
+    cases = gen.float_cases(6, 1024)
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, pop.ops, pop.offsets, chunk_nodes=128)
+    r_all, f_all, _ = ctx.evaluate_full(ph, ch, g.GP_F32, pop.n_trees, cases.T)
+    for rep in range(3):
+        r2, f2, _ = ctx.evaluate_full(ph, ch, g.GP_F32, pop.n_trees, cases.T)
+        assert np.array_equal(r_all.view(np.uint32), r2.view(np.uint32))
+    for i in [0, 7, 29]:
+        one = gen.pack([pop.tree(i)])
+        p1 = ctx.load_population(g.GP_F32, one.ops, one.offsets, chunk_nodes=4096)
+        r1, f1, _ = ctx.evaluate_full(p1, ch, g.GP_F32, 1, cases.T)
+        assert np.array_equal(r1[0].view(np.uint32), r_all[i].view(np.uint32))
+        assert f1[0] == f_all[i] or (np.isnan(f1[0]) and np.isnan(f_all[i]))
+        ctx.free(p1)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_postfix_layout(ctx):
+    rng = np.random.default_rng(21)
+    cases = gen.float_cases(7, 64)
+    trees = [gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 999))) for _ in range(10)]
+
+    def to_postfix(t):
+        ends = gen.subtree_ends(t)
+        out = []
+
+        def rec(i):
+            if t[i] & 0x80:
+                rec(i + 1)
+                rec(int(ends[i + 1]))
+            out.append(int(t[i]))
+        sys.setrecursionlimit(10000)
+        rec(0)
+        return np.array(out, np.uint8)
+
+    pre = gen.pack(trees)
+    post = gen.pack([to_postfix(t) for t in trees])
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    a = ctx.load_population(g.GP_F32, pre.ops, pre.offsets)
+    b = ctx.load_population(g.GP_F32, post.ops, post.offsets, layout=g.GP_POSTFIX)
+    ra, fa, _ = ctx.evaluate_full(a, ch, g.GP_F32, 10, 64)
+    rb, fb, _ = ctx.evaluate_full(b, ch, g.GP_F32, 10, 64)
+    assert same_f32(ra, rb).all()
+    ctx.free(a)
+    ctx.free(b)
+    ctx.free(ch)
+
+
+def test_gp_fitness_entry_point(ctx):
+    rng = np.random.default_rng(9)
+    for T in [1, 48, 65, 1024, 4096]:
+        cases = gen.float_cases(T, T)
+        ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+        outs = rng.normal(size=(5, T)).astype(np.float32)
+        outs[0, 0] = np.nan
+        got = ctx.fitness(ch, g.GP_F32, outs)
+        for i in range(5):
+            assert fit_equal(got[i], oracle.fitness_f32(outs[i], cases.y))
+        ctx.free(ch)
+
+
+# ------------------------------------------------------------------ Boolean
+def check_bool_pop(ctx, pop, cases, chunk_nodes=0, variant=-1, per_tree=False):
+    ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+    ph = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=cases.inputs.shape[0],
+                             chunk_nodes=chunk_nodes)
+    ctx.set_variant(variant)
+    roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, cases.T, per_tree=per_tree)
+    ctx.set_variant(-1)
+    want_roots, want_fit = oracle.eval_population_bool(pop, cases.inputs, cases.target, cases.T, threads=8)
+    W = (cases.T + 63) // 64
+    assert roots.shape == (pop.n_trees, W)
+    assert np.array_equal(roots, want_roots)
+    assert np.array_equal(fit, want_fit)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_boolean_parity6_small(ctx):
+    cases = gen.bool_cases(6)
+    pop = gen.sized_population(2, 60, 11, 20001, n_terms=6, vtype=gen.VT_BOOL)
+    x = [0]
+    for j in range(1, 6):
+        x = [gen.B_NOR, gen.B_AND] + x + [j] + [gen.B_NOR] + x + [j]
+    even6 = np.array([gen.B_NOR] + x + x, np.uint8)
+    trees = [pop.tree(i) for i in range(pop.n_trees)] + [even6, np.array([3], np.uint8)]
+    pop = gen.pack(trees, gen.VT_BOOL, 6)
+    for v in bool_variants():
+        for C in [32, 0]:
+            say("bool6 variant", g.variant_names()[v], C)
+            check_bool_pop(ctx, pop, cases, chunk_nodes=C, variant=v)
+    check_bool_pop(ctx, pop, cases, per_tree=True)
+
+
+@pytest.mark.parametrize("k", [8, 10, 12])
+def test_boolean_multiword(ctx, k):
+    cases = gen.bool_cases(k)
+    pop = gen.sized_population(3 + k, 20, 11, 5001, n_terms=k, vtype=gen.VT_BOOL)
+    for v in bool_variants():
+        check_bool_pop(ctx, pop, cases, chunk_nodes=64, variant=v)
+
+
+# -------------------------------------------------------------- incremental
+def make_children(parents, seed, n, donor_hi=200, neutral_frac=0.5, n_terms=1):
+    return gen.crossover_children(seed, parents, n, donor_hi=donor_hi, neutral_frac=neutral_frac,
+                                  n_terms=n_terms, one_per_parent=False)
+
+
+def record_lists(parents, children):
+    pts = [[] for _ in range(parents.n_trees)]
+    for p, c in zip(children.parent, children.point):
+        pts[int(p)].append(int(c))
+    offs = np.zeros(parents.n_trees + 1, np.int64)
+    offs[1:] = np.cumsum([len(p) for p in pts])
+    flat = np.array([c for p in pts for c in p], np.int64)
+    return flat, offs
+
+
+@pytest.mark.parametrize("chunk_nodes,T", [(64, 100), (4096, 1024), (0, 48)])
+def test_incremental_float_matches_oracle(ctx, chunk_nodes, T):
+    parents = gen.sized_population(31, 12, 101, 20001)
+    children = make_children(parents, 32, 60)
+    cases = gen.float_cases(33, T)
+    rp, ro = record_lists(parents, children)
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, parents.ops, parents.offsets, record_points=rp, record_offsets=ro,
+                             chunk_nodes=chunk_nodes)
+    proots, pfit, _ = ctx.evaluate_full(ph, ch, g.GP_F32, parents.n_trees, T)
+    roots, fit, info = ctx.evaluate_incremental(ph, ch, g.GP_F32, T, children.parent, children.point,
+                                                children.donors.ops, children.donors.offsets)
+    stops = []
+    for i in range(len(children.parent)):
+        P = parents.tree(int(children.parent[i]))
+        c = int(children.point[i])
+        D = children.donors.tree(i)
+        with np.errstate(all="ignore"):
+            w_root, w_lvl, w_interp, w_fit = oracle.incremental_f32(P, c, D, cases.x, cases.y)
+        assert same_f32(roots[i], w_root).all(), i
+        assert fit_equal(fit[i], w_fit), (i, fit[i], w_fit)
+        assert info["stop_level"][i] == w_lvl, (i, info["stop_level"][i], w_lvl)
+        assert info["interpreted_nodes"][i] == w_interp
+        assert info["child_nodes"][i] == len(P) - (oracle.subtree_end(P, c) - c) + len(D)
+        if children.neutral[i]:
+            assert w_lvl == 0
+        stops.append(w_lvl)
+    assert any(s > 0 for s in stops) and any(s == 0 for s in stops)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_incremental_boolean_matches_oracle(ctx):
+    cases = gen.bool_cases(6)
+    parents = gen.sized_population(41, 10, 101, 5001, n_terms=6, vtype=gen.VT_BOOL)
+    children = make_children(parents, 42, 50, donor_hi=100, n_terms=6)
+    rp, ro = record_lists(parents, children)
+    ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, 64)
+    ph = ctx.load_population(g.GP_BOOL, parents.ops, parents.offsets, n_inputs=6, record_points=rp,
+                             record_offsets=ro, chunk_nodes=64)
+    ctx.evaluate_full(ph, ch, g.GP_BOOL, parents.n_trees, 64)
+    roots, fit, info = ctx.evaluate_incremental(ph, ch, g.GP_BOOL, 64, children.parent, children.point,
+                                                children.donors.ops, children.donors.offsets)
+    for i in range(len(children.parent)):
+        P = parents.tree(int(children.parent[i]))
+        w_root, w_lvl, w_interp, w_fit = oracle.incremental_bool(P, int(children.point[i]),
+                                                                 children.donors.tree(i), cases.inputs,
+                                                                 cases.target, 64)
+        assert np.array_equal(roots[i], w_root)
+        assert fit[i] == w_fit
+        assert info["stop_level"][i] == w_lvl
+        assert info["interpreted_nodes"][i] == w_interp
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_incremental_errors(ctx):
+    parents = gen.sized_population(51, 3, 11, 101)
+    cases = gen.float_cases(52, 64)
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, parents.ops, parents.offsets,
+                             record_points=np.array([0, 1], np.int64),
+                             record_offsets=np.array([0, 2, 2, 2], np.int64))
+    d = np.array([0], np.uint8)
+    with pytest.raises(g.GPError) as e:        # not evaluated yet
+        ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [0], [1], d, [0, 1])
+    assert e.value.code == g.GP_ENOTFOUND
+    ctx.evaluate_full(ph, ch, g.GP_F32, 3, 64)
+    with pytest.raises(g.GPError) as e:        # point not recorded
+        ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [1], [0], d, [0, 1])
+    assert e.value.code == g.GP_ENOTFOUND
+    with pytest.raises(g.GPError) as e:        # malformed donor
+        ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [0], [1], np.array([0x80, 0], np.uint8), [0, 2])
+    assert e.value.code == g.GP_EINVAL
+    with pytest.raises(g.GPError) as e:        # point out of range
+        ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [0], [10**6], d, [0, 1])
+    assert e.value.code == g.GP_EINVAL
+    r, f, info = ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [0], [0], d, [0, 1])   # replace the root
+    assert np.all(r[0] == cases.x[0])
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_malformed_population_rejected(ctx):
+    with pytest.raises(g.GPError) as e:
+        ctx.load_population(g.GP_F32, np.array([0x80, 0, 0x80, 0], np.uint8), np.array([0, 3, 4], np.int64))
+    assert e.value.code == g.GP_EINVAL
+    with pytest.raises(g.GPError) as e:
+        ctx.load_population(g.GP_F32, np.array([0x80, 0, 1], np.uint8), np.array([0, 3], np.int64))
+    assert e.value.code == g.GP_EINVAL
+
+
+def test_budget_enforced():
+    c = g.Context(0, budget_bytes=1 << 20)
+    pop = gen.sized_population(3, 4, 10001, 20001)
+    cases = gen.float_cases(1, 1024)
+    ch = c.set_cases(g.GP_F32, cases.x, cases.y)
+    with pytest.raises(g.GPError) as e:
+        ph = c.load_population(g.GP_F32, pop.ops, pop.offsets)
+        c.evaluate_full(ph, ch, g.GP_F32, 4, 1024)
+    assert e.value.code == g.GP_EBUDGET
+    c.close()

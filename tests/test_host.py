@@ -1,0 +1,159 @@
+"""CPU tests of the library's host side: the C ABI exports, tree validation
+and the tree compiler (evaluation order, folded terminals, chunking, stack
+bound).  No GPU: the compiled programs are run by a small emulator written
+here from the instruction format in prep.h, and compared with the oracle.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from paper_2205_03251_amd import gpeval as g
+from tests.scalar_ref import same_f32
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+M_XX, M_XS, M_SX, M_SS, M_RS, M_PUSH, M_LOAD, M_STORE = range(8)
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "gpeval.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b(gp_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 20
+    lib = g.lib()
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(g.EXPORTS) <= names
+
+
+def test_no_gpu_context_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(g.GPError) as e:
+        g.Context()
+    assert e.value.code == g.GP_EDEVICE
+
+
+def test_validate_matches_oracle_corpus():
+    rng = np.random.default_rng(1)
+    bad = [[], [0x80, 0], [0, 0], [0x84, 0, 0], [0x80, 0, 1], [0x80, 0x80, 0, 0]]
+    for t in bad:
+        assert not g.validate_tree(np.array(t, np.uint8))
+        assert not oracle.validate(np.array(t, np.uint8))
+    for i in range(50):
+        t = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 301)), n_terms=3)
+        assert g.validate_tree(t, n_inputs=3) and oracle.validate(t, 3)
+        cut = t[: int(rng.integers(len(t)))] if len(t) > 1 else t[:0]
+        assert g.validate_tree(cut, n_inputs=3) == oracle.validate(cut, 3)
+
+
+def _op_f32(f, a, b):
+    with np.errstate(all="ignore"):
+        if f == 0:
+            return a + b
+        if f == 1:
+            return a - b
+        if f == 2:
+            return a * b
+        return np.where(np.abs(b) < np.float32(1e-6), np.float32(1.0), a / b).astype(np.float32)
+
+
+def _op_bool(f, a, b):
+    return [a & b, a | b, ~(a & b), ~(a | b)][f]
+
+
+def emulate(prog: g.Program, inputs, vtype):
+    """Run the compiled chunks in order (children come first)."""
+    op = _op_f32 if vtype == g.GP_F32 else _op_bool
+    vals = {}
+    for k, (off, ln, parent, nin) in enumerate(prog.chunks):
+        st = {}
+        for w in prog.code[off:off + ln]:
+            w = int(w)
+            f, mode, d, pl = w & 3, (w >> 2) & 7, (w >> 5) & 31, w >> 10
+            if vtype == g.GP_F32:
+                xa = xb = inputs[0]
+            else:
+                xa, xb = inputs[pl & 2047], inputs[pl >> 11]
+            if mode == M_XX:
+                st[d] = op(f, xa, xb)
+            elif mode == M_XS:
+                st[d] = op(f, inputs[0] if vtype == g.GP_F32 else inputs[pl], st[d])
+            elif mode == M_SX:
+                st[d] = op(f, st[d], inputs[0])
+            elif mode == M_SS:
+                st[d] = op(f, st[d], st[d + 1])
+            elif mode == M_RS:
+                st[d] = op(f, st[d + 1], st[d])
+            elif mode == M_PUSH:
+                st[d] = inputs[pl]
+            elif mode == M_LOAD:
+                child = prog.inputs[k][pl]
+                assert prog.chunks[child, 2] == k
+                st[d] = vals[child]
+            assert d < prog.max_stack
+        vals[k] = st[0]
+    assert prog.chunks[-1, 2] == -1
+    return vals[len(prog.chunks) - 1]
+
+
+@pytest.mark.parametrize("chunk_nodes,slots", [(4096, 16), (16, 16), (7, 4), (64, 3), (2, 2)])
+def test_compiled_float_programs_match_oracle(chunk_nodes, slots):
+    rng = np.random.default_rng(chunk_nodes * 7 + slots)
+    x = np.concatenate([gen.float_cases(3, 29).x[0], np.array([0, -0.0, 1e-7, np.inf], np.float32)])
+    xin = np.stack([x, x[::-1].copy()])
+    for i in range(25):
+        n = int(gen.log_uniform_odd(rng, 1, 2001))
+        t = gen.sized_tree(rng, n, n_terms=2 if i % 3 == 0 else 1)
+        nin = 2 if i % 3 == 0 else 1
+        prog = g.inspect_program(t, g.GP_F32, nin, chunk_nodes, slots)
+        assert prog.max_stack <= slots
+        got = emulate(prog, xin[:nin], g.GP_F32)
+        with np.errstate(all="ignore"):
+            want = oracle.eval_f32(t, xin[:nin])
+        assert same_f32(got, want).all()
+        n_loads = sum(1 for w in prog.code if (int(w) >> 2) & 7 == M_LOAD)
+        assert n_loads == len(prog.chunks) - 1
+
+
+def test_compiled_boolean_programs_match_oracle():
+    rng = np.random.default_rng(4)
+    c = gen.bool_cases(8)
+    for i in range(25):
+        t = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 3001)), n_terms=8)
+        for chunk_nodes, slots in [(4096, 16), (9, 3)]:
+            prog = g.inspect_program(t, g.GP_BOOL, 8, chunk_nodes, slots)
+            assert prog.max_stack <= slots
+            got = emulate(prog, c.inputs, g.GP_BOOL)
+            assert np.array_equal(got, oracle.eval_bool(t, c.inputs))
+
+
+def test_stack_need_is_logarithmic():
+    # Ershov order: a full binary tree of height h needs about h slots, a
+    # random tree of 100k nodes far fewer than its height.
+    rng = np.random.default_rng(8)
+    t = gen.sized_tree(rng, 100_001)
+    prog = g.inspect_program(t, g.GP_F32, 1, 1 << 30, 32)
+    assert len(prog.chunks) == 1
+    assert prog.max_stack <= 12
+    # a left-deep chain (height 1000) needs one slot with folded terminals
+    chain = np.array([gen.F_ADD] * 1000 + [0] * 1001, np.uint8)
+    prog = g.inspect_program(chain, g.GP_F32, 1, 1 << 30, 32)
+    assert prog.max_stack == 1
+    got = emulate(prog, np.ones((1, 4), np.float32), g.GP_F32)
+    assert np.all(got == 1001.0)
+
+
+def test_chunk_sizes_bounded():
+    rng = np.random.default_rng(5)
+    t = gen.sized_tree(rng, 50_001)
+    for C in [64, 512, 4096]:
+        prog = g.inspect_program(t, g.GP_F32, 1, C, 16)
+        lens = prog.chunks[:, 1]
+        # each chunk holds fewer than 2C nodes; its instructions fewer than that
+        assert lens.max() < 2 * C + 8
+        assert len(prog.chunks) >= 50_001 // (2 * C + 2)
