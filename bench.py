@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Benchmark: equivalent and interpreted GP operations per second on one MI355X.
+
+Default workload (incremental evaluation in a converged population): 500
+parent trees of 1e6..1e7 nodes (log-uniform, uniform random shapes, float32
+functions + - * /protected over terminal x), 1024 test cases x ~ U[-1, 1),
+sextic target; one crossover child per parent (point uniform over nodes,
+donor 1..1e4 nodes, half of the donors semantically neutral).
+
+One step = one pass over the whole evaluation path on device-resident data:
+  full batched evaluation of the parent population in one persistent launch
+  (recording the parent caches along each child's path), then bottom-up
+  incremental evaluation of the 500 children with the failed-disruption stop.
+Host-side loading (validation, compilation, chunking, upload) happens once
+before the timed region and is reported separately.
+
+Prints ONE JSON line.  `value` = equivalent GPop/s of the step (tree nodes x
+test cases per second, every tree and child counted in full).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import gen  # noqa: E402
+
+PEAK_FP32_LANE_OPS = 256 * 4 * 16 * 2.4e9      # non-packed FP32 VALU lane-ops/s (39.3e12)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload_inputs(name: str, scale: float, threads: int):
+    if name == "incremental":
+        n = max(2, int(round(500 * scale)))
+        parents = gen.sized_population(4, n, 10**6, 10**7, threads=threads)
+        cases = gen.float_cases(4, 1024)
+        kids = gen.crossover_children(40, parents, n, donor_lo=1, donor_hi=10**4, neutral_frac=0.5)
+        desc = {"workload": "incremental_converged", "parents": n, "parent_nodes": "log-uniform 1e6..1e7",
+                "children": n, "donor_nodes": "log-uniform 1..1e4", "neutral_frac": 0.5, "test_cases": 1024,
+                "value_type": "float32"}
+        return parents, cases, kids, desc
+    if name == "full_large":
+        n = max(2, int(round(1000 * scale)))
+        pop = gen.sized_population(3, n, 10**4, 10**6, threads=threads)
+        return pop, gen.float_cases(3, 1024), None, {
+            "workload": "full_large", "trees": n, "tree_nodes": "log-uniform 1e4..1e6", "test_cases": 1024,
+            "value_type": "float32"}
+    if name == "boolean":
+        n = max(2, int(round(1000 * scale)))
+        pop = gen.sized_population(2, n, 10**3, 10**5, n_terms=6, vtype=gen.VT_BOOL, threads=threads)
+        return pop, gen.bool_cases(6), None, {
+            "workload": "boolean_parity6", "trees": n, "tree_nodes": "log-uniform 1e3..1e5", "test_cases": 64,
+            "value_type": "bool"}
+    if name == "small":
+        return gen.ramped_half_and_half(1), gen.float_cases(1, 48), None, {
+            "workload": "small_ramped", "trees": 100, "test_cases": 48, "value_type": "float32"}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def record_lists(n_trees, kids):
+    pts = [[] for _ in range(n_trees)]
+    for p, c in zip(kids.parent, kids.point):
+        pts[int(p)].append(int(c))
+    offs = np.zeros(n_trees + 1, np.int64)
+    offs[1:] = np.cumsum([len(p) for p in pts])
+    return np.array([c for p in pts for c in p], np.int64), offs
+
+
+def cpu_baseline(pop, cases, kids, vtype, threads, budget_s=12.0):
+    """The oracle as it stands, P independent single-threaded instances."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    T = cases.T
+    sizes = pop.sizes()
+    # bounded sample: trees in index order until ~budget_s of work at ~2.5 ns per op
+    per_thread_ops = budget_s / 2.5e-9
+    target = per_thread_ops * threads
+    chosen, tot = [], 0
+    for i in range(pop.n_trees):
+        if tot >= target:
+            break
+        chosen.append(i)
+        tot += int(sizes[i]) * T
+    ops_done = 0
+
+    def one(i):
+        if vtype == gen.VT_BOOL:
+            oracle.fitness_bool(oracle.eval_bool(pop.tree(i), cases.inputs), cases.target, T)
+        else:
+            with np.errstate(all="ignore"):
+                oracle.fitness_f32(oracle.eval_f32(pop.tree(i), cases.x), cases.y)
+        return int(sizes[i]) * T
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        ops_done = sum(ex.map(one, sorted(chosen, key=lambda i: -sizes[i])))
+    dt = time.perf_counter() - t0
+    return {"value": ops_done / dt / 1e9, "unit": "GPop/s", "cores": threads, "kind": "oracle",
+            "sample": f"full evaluation of {len(chosen)} of the {pop.n_trees} trees "
+                      f"({int(sizes[chosen].sum())} nodes) on all {T} cases, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="incremental",
+                    choices=["incremental", "full_large", "boolean", "small"])
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the population size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time per-tree launches and full re-evaluation of the children")
+    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the evaluation path is not "
+                                   "sharded across GPUs (see DESIGN.md for how it would shard)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2205_03251_amd import gpeval as g
+
+    t0 = time.perf_counter()
+    pop, cases, kids, desc = workload_inputs(args.workload, args.scale, args.threads)
+    vtype = g.GP_BOOL if desc["value_type"] == "bool" else g.GP_F32
+    T = cases.T
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] generated {desc['workload']}: {pop.n_trees} trees, {int(pop.sizes().sum())} nodes "
+        f"in {gen_s:.1f} s")
+
+    torch.cuda.init()
+    ctx = g.Context(0)
+    if vtype == g.GP_BOOL:
+        ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, T)
+    else:
+        ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    t1 = time.perf_counter()
+    if kids is not None:
+        rp, ro = record_lists(pop.n_trees, kids)
+        ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, record_points=rp,
+                                 record_offsets=ro)
+    else:
+        ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs)
+    load_s = time.perf_counter() - t1
+    info = ctx.population_info(ph)
+    log(f"[bench] loaded in {load_s:.1f} s: {info}")
+
+    tuned = None
+    if not args.no_autotune:
+        v, ms = ctx.autotune(ph, ch)
+        tuned = g.variant_names()[v]
+        log(f"[bench] autotune picked {tuned} ({ms:.2f} ms per full evaluation)")
+
+    n_trees = pop.n_trees
+    fdt = torch.float64 if vtype == g.GP_F32 else torch.int64
+    fit_buf = torch.empty(n_trees, dtype=fdt, device="cuda:0")
+    total_nodes = int(pop.sizes().sum())
+
+    def step():
+        _, _, st_full = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, device=True, async_=True,
+                                          fit_buf=fit_buf)
+        if kids is None:
+            return st_full, None
+        _, _, st_inc = ctx.evaluate_incremental(ph, ch, vtype, T, kids.parent, kids.point, kids.donors.ops,
+                                                kids.donors.offsets, roots=False, device=True)
+        return st_full, st_inc
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    inc_stats = None
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        _, inc_stats = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed / args.steps * 1e3
+
+    equiv_nodes = total_nodes
+    interp_nodes = total_nodes
+    extra = {}
+    if kids is not None:
+        child_nodes = int(inc_stats["child_nodes"].sum())
+        equiv_nodes += child_nodes
+        interp_nodes += int(inc_stats["interpreted_nodes"].sum())
+        stops = inc_stats["stop_level"]
+        extra["incremental"] = {
+            "children": int(len(stops)), "child_nodes": child_nodes,
+            "interpreted_nodes": int(inc_stats["interpreted_nodes"].sum()),
+            "stop_at_point": int((stops == 0).sum()), "reached_root": int((stops < 0).sum()),
+            "median_stop_level": float(np.median(stops[stops >= 0])) if (stops >= 0).any() else None,
+            "device_ms": inc_stats["device_ms"],
+            "equivalent_gpops": child_nodes * T / (inc_stats["device_ms"] * 1e-3) / 1e9,
+            "interpreted_gpops": int(inc_stats["interpreted_nodes"].sum()) * T / (inc_stats["device_ms"] * 1e-3) / 1e9,
+        }
+
+    # dominant kernel: the interpreter launch, timed with HIP events on the library stream
+    kms = []
+    for _ in range(3):
+        _, _, st = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, graph=False)
+        kms.append(st["kernel_ms"])
+    kernel_ms = float(np.median(kms))
+    func_nodes = (total_nodes - n_trees) // 2
+    achieved = func_nodes * T / (kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_FP32_LANE_OPS / 1e12, 2),
+                "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_LANE_OPS, 4), "traffic": None,
+                "kernel": "k_eval_" + ("bool" if vtype == g.GP_BOOL else "f32"), "kernel_ms": round(kernel_ms, 3),
+                "gp_ops_per_s": round(total_nodes * T / (kernel_ms * 1e-3) / 1e12, 4)}
+    if vtype == g.GP_BOOL:
+        roofline["note"] = "Boolean: one 64-bit word op per function node per 64 cases"
+
+    if args.compare:
+        _, _, st_pt = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, per_tree=True)
+        extra["per_tree_launch_ms"] = st_pt["device_ms"]
+        _, _, st_b = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False)
+        extra["batched_launch_ms"] = st_b["device_ms"]
+        if kids is not None:
+            childpop = gen.pack([gen.splice(pop.tree(int(p)), int(c), kids.donors.tree(i))
+                                 for i, (p, c) in enumerate(zip(kids.parent, kids.point))])
+            cph = ctx.load_population(vtype, childpop.ops, childpop.offsets)
+            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, childpop.n_trees, T, roots=False)
+            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, childpop.n_trees, T, roots=False)
+            extra["children_full_reeval_ms"] = st_c["device_ms"]
+            extra["children_full_reeval_gpops"] = int(childpop.sizes().sum()) * T / (st_c["device_ms"] * 1e-3) / 1e9
+            ctx.free(cph)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(pop, cases, kids, pop.vtype, args.threads)
+
+    value = equiv_nodes * T / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": "equivalent GPop/s (tree nodes x test cases per second)",
+        "value": round(value, 3),
+        "unit": "GPop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bool" if vtype == g.GP_BOOL else "f32",
+        "data": "synthetic",
+        "config": {**desc, "chunk_nodes": info["chunk_nodes"], "variant": tuned, "parallelism": "single_gpu"},
+        "interpreted_gpops": round(interp_nodes * T / (ms_per_step * 1e-3) / 1e9, 3),
+        "host_load_s": round(load_s, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -60,17 +60,25 @@ def pack(trees, vtype=VT_F32, n_inputs=1) -> Population:
     return Population(ops, offsets, vtype, n_inputs)
 
 
-def subtree_end(tree: np.ndarray, i: int) -> int:
-    """First index past the subtree rooted at i (arity scan of a prefix array)."""
-    need = 1
-    j = i
+def subtree_end(tree: np.ndarray, i: int, max_len: int | None = None) -> int:
+    """First index past the subtree rooted at i (arity scan of a prefix array).
+    With max_len, returns -1 when the subtree is longer than max_len."""
     n = len(tree)
-    while need > 0:
-        if j >= n:
-            raise ValueError("truncated prefix array")
-        need += 1 if tree[j] & 0x80 else -1
-        j += 1
-    return j
+    j, open_ = i, 1
+    stop = n if max_len is None else min(n, i + max_len)
+    step = 4096
+    while j < stop:
+        blk = tree[j:min(stop, j + step)]
+        run = open_ + np.cumsum(np.where(blk & 0x80, 1, -1), dtype=np.int64)
+        hit = np.flatnonzero(run == 0)
+        if len(hit):
+            return j + int(hit[0]) + 1
+        open_ = int(run[-1])
+        j += len(blk)
+        step = min(step * 4, 1 << 24)
+    if max_len is not None and j < n:
+        return -1
+    raise ValueError("truncated prefix array")
 
 
 def subtree_ends(tree: np.ndarray) -> np.ndarray:
@@ -160,10 +168,24 @@ def log_uniform_odd(rng: np.random.Generator, lo: int, hi: int, size=None):
 
 
 def sized_population(seed: int, n_trees: int, lo: int, hi: int, n_terms: int = 1,
-                     vtype: int = VT_F32) -> Population:
+                     vtype: int = VT_F32, threads: int = 1) -> Population:
+    """n_trees uniformly shaped trees with log-uniform odd sizes in [lo, hi].
+    Tree i draws from its own seed stream, so the result does not depend on
+    how many threads build it."""
     rng = rng_for(seed)
     sizes = log_uniform_odd(rng, lo, hi, n_trees)
-    return pack([sized_tree(rng, int(s), n_terms) for s in sizes], vtype, n_terms)
+    seqs = np.random.SeedSequence(seed).spawn(n_trees)
+
+    def one(i):
+        return sized_tree(np.random.default_rng(seqs[i]), int(sizes[i]), n_terms)
+
+    if threads > 1 and n_trees > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            trees = list(ex.map(one, range(n_trees)))
+    else:
+        trees = [one(i) for i in range(n_trees)]
+    return pack(trees, vtype, n_terms)
 
 
 # ------------------------------------------------------------ test cases
@@ -279,8 +301,8 @@ def crossover_children(seed: int, parents: Population, n_children: int, donor_lo
             m = max(m, 5)
             while True:
                 c = int(rng.integers(n))
-                e = subtree_end(tree, c)
-                if (e - c) + 4 <= m:
+                e = subtree_end(tree, c, max_len=m - 4)
+                if e > 0:
                     break
             donors.append(neutral_donor(rng, tree[c:e].copy(), m))
             neutral[ci] = True

@@ -80,6 +80,8 @@ enum { GP_PREFIX = 0, GP_POSTFIX = 1 };    /* load layout */
 
 typedef struct gp_stats {
     double device_ms;          /* HIP-event time on the context stream (0 with GP_ASYNC) */
+    double kernel_ms;          /* HIP-event time of the interpreter launch alone (GP_NO_GRAPH
+                                  full evaluations; 0 otherwise) */
     double wall_ms;            /* call entry to return */
     int64_t equivalent_ops;    /* sum of nodes x T over every tree or child scored */
     int64_t interpreted_ops;   /* nodes actually executed x T */

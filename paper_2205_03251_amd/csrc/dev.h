@@ -41,7 +41,7 @@ struct EvalParams {
 
 // One incremental child.
 struct WalkChild {
-    int64_t level_off;           // first SpineLevel (int4) of its spine
+    int64_t level_off;           // first SpineLvl of its spine
     int32_t n_levels;
     int32_t at_point;            // mother's vector at the point (source code)
     int32_t rec_base;            // record slot base of the mother tree
@@ -51,9 +51,14 @@ struct WalkChild {
     int64_t donor_nodes;
 };
 
+// One ancestor level of a spine (see SpineLevel in prep.h).
+struct SpineLvl {
+    int32_t fside, sib, par, pad;
+};
+
 struct WalkParams {
     const WalkChild* children;
-    const int4* levels;          // {fside, sib, par, 0}
+    const SpineLvl* levels;
     const void* inputs;          // [n_inputs][stride]
     const void* recs;            // mother records
     const void* parent_vecs;     // mother root vectors
@@ -97,7 +102,5 @@ hipError_t launch_init(int32_t* pending, const int32_t* init, int64_t n, unsigne
 hipError_t launch_eval(int variant, const EvalParams& p, int grid, hipStream_t s);
 hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t s);
 hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s);
-hipError_t launch_pad_copy(void* dst, int64_t dst_stride, const void* src, int64_t src_stride,
-                           int64_t rows, int64_t cols, int elem_bytes, hipStream_t s);
 
 }  // namespace gpe

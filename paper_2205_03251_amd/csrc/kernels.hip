@@ -31,6 +31,16 @@ namespace gpe {
 
 #define UNROLL _Pragma("unroll")
 
+// Read-only tables (instruction words, chunk descriptors, work items, input
+// lists, spine levels) are read through the constant address space: uniform
+// reads then go through the scalar data cache into SGPRs.
+#define GP_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const GP_CONST T* cst(const T* p)
+{
+    return (const GP_CONST T*)p;
+}
+
 // ---------------------------------------------------------------- ops
 template <int F>
 __device__ __forceinline__ float fop(float a, float b)
@@ -87,12 +97,29 @@ __device__ __forceinline__ uint64_t valid_bits(int64_t w, int64_t T)
     return (1ull << (T - lo)) - 1ull;
 }
 
+struct ChunkHdr {
+    int64_t code_off;
+    int32_t code_len, parent, out_slot, in_off, rec_base;
+};
+
+__device__ __forceinline__ ChunkHdr load_chunk(const GP_CONST DevChunk* c)
+{
+    ChunkHdr h;
+    h.code_off = c->code_off;
+    h.code_len = c->code_len;
+    h.parent = c->parent;
+    h.out_slot = c->out_slot;
+    h.in_off = c->in_off;
+    h.rec_base = c->rec_base;
+    return h;
+}
+
 // --------------------------------------------------- float interpreter
 struct ItemF32 {
     const float* inputs;     // input 0 at this lane's first case
     const float* vecs;       // vector slot 0 at this lane's first case
     float* recs;             // record slot 0 at this lane's first case
-    const int32_t* chunk_in;
+    const GP_CONST int32_t* chunk_in;
     int64_t stride;
     int32_t rec_base;
 };
@@ -159,12 +186,16 @@ __device__ __forceinline__ void step_f32(uint32_t fm, uint32_t pl, float (&st)[S
     STEP(29) STEP(30) STEP(31)
 
 template <int K, int S>
-__device__ __forceinline__ void run_f32(const uint32_t* __restrict__ code, int32_t len,
+__device__ __forceinline__ void run_f32(const GP_CONST uint32_t* code, int32_t len,
                                         float (&st)[S][K], const float (&x)[K], const ItemF32& c)
 {
     // The next word is fetched before the current one is executed; the code
     // array carries one padding word past its end.
     uint32_t nxt = code[0];
+    // Settle the first fetch before the loop (0xffffffff is no valid word),
+    // so that inside it only the loop latch waits, for the word fetched
+    // while the current handler ran.
+    if (nxt == 0xffffffffu) len = 0;
     for (int32_t i = 0; i < len; ++i) {
         const uint32_t ins = __builtin_amdgcn_readfirstlane(nxt);
         nxt = code[i + 1];
@@ -192,7 +223,7 @@ __global__ __launch_bounds__(64) void k_eval_f32(EvalParams p)
         if (lane == 0) it = atomicAdd(p.cursor, 1u);
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= p.n_items) break;
-        const int64_t item = p.items[it];
+        const int64_t item = cst(p.items)[it];
         int32_t c = (int32_t)(item >> 16);
         const int32_t s = (int32_t)(item & 0xffff);
         const int64_t case0 = (int64_t)s * (kWave * K) + lane;
@@ -204,10 +235,11 @@ __global__ __launch_bounds__(64) void k_eval_f32(EvalParams p)
         ic.recs = (float*)p.recs + case0;
         ic.stride = p.stride;
         for (;;) {
-            const DevChunk ch = p.chunks[c];
-            ic.chunk_in = p.chunk_in + ch.in_off;
+            const GP_CONST DevChunk* chp = cst(p.chunks) + c;
+            const ChunkHdr ch = load_chunk(chp);
+            ic.chunk_in = cst(p.chunk_in) + ch.in_off;
             ic.rec_base = ch.rec_base;
-            run_f32<K, S>(p.code + ch.code_off, ch.code_len, st, x, ic);
+            run_f32<K, S>(cst(p.code) + ch.code_off, ch.code_len, st, x, ic);
             float* dst = (float*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
             UNROLL for (int k = 0; k < K; ++k) dst[kWave * k] = st[0][k];
             if (ch.parent < 0) break;
@@ -229,7 +261,7 @@ struct ItemBool {
     const uint64_t* lin;     // staged input words in LDS, this lane's first word
     const uint64_t* vecs;
     uint64_t* recs;
-    const int32_t* chunk_in;
+    const GP_CONST int32_t* chunk_in;
     int64_t stride;
     int32_t rec_base;
     int32_t lds_row;         // words per staged input row (64*K)
@@ -285,10 +317,11 @@ __device__ __forceinline__ void step_bool(uint32_t fm, uint32_t pl, uint64_t (&s
 }
 
 template <int K, int S>
-__device__ __forceinline__ void run_bool(const uint32_t* __restrict__ code, int32_t len,
+__device__ __forceinline__ void run_bool(const GP_CONST uint32_t* code, int32_t len,
                                          uint64_t (&st)[S][K], const ItemBool& c)
 {
     uint32_t nxt = code[0];
+    if (nxt == 0xffffffffu) len = 0;      // settle the first fetch, as in run_f32
     for (int32_t i = 0; i < len; ++i) {
         const uint32_t ins = __builtin_amdgcn_readfirstlane(nxt);
         nxt = code[i + 1];
@@ -317,7 +350,7 @@ __global__ __launch_bounds__(64) void k_eval_bool(EvalParams p)
         if (lane == 0) it = atomicAdd(p.cursor, 1u);
         it = __builtin_amdgcn_readfirstlane(it);
         if ((int64_t)it >= p.n_items) break;
-        const int64_t item = p.items[it];
+        const int64_t item = cst(p.items)[it];
         int32_t c = (int32_t)(item >> 16);
         const int32_t s = (int32_t)(item & 0xffff);
         const int64_t case0 = (int64_t)s * row + lane;
@@ -334,10 +367,11 @@ __global__ __launch_bounds__(64) void k_eval_bool(EvalParams p)
         ic.stride = p.stride;
         ic.lds_row = row;
         for (;;) {
-            const DevChunk ch = p.chunks[c];
-            ic.chunk_in = p.chunk_in + ch.in_off;
+            const GP_CONST DevChunk* chp = cst(p.chunks) + c;
+            const ChunkHdr ch = load_chunk(chp);
+            ic.chunk_in = cst(p.chunk_in) + ch.in_off;
             ic.rec_base = ch.rec_base;
-            run_bool<K, S>(p.code + ch.code_off, ch.code_len, st, ic);
+            run_bool<K, S>(cst(p.code) + ch.code_off, ch.code_len, st, ic);
             uint64_t* dst = (uint64_t*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
             UNROLL for (int k = 0; k < K; ++k) dst[kWave * k] = st[0][k];
             if (ch.parent < 0) break;
@@ -445,7 +479,16 @@ __global__ __launch_bounds__(256) void k_walk_f32(WalkParams p)
 {
     __shared__ double red[256];
     const int64_t ci = blockIdx.x;
-    const WalkChild w = p.children[ci];
+    const GP_CONST WalkChild* wcp = cst(p.children) + ci;
+    WalkChild w;
+    w.level_off = wcp->level_off;
+    w.n_levels = wcp->n_levels;
+    w.at_point = wcp->at_point;
+    w.rec_base = wcp->rec_base;
+    w.parent_slot = wcp->parent_slot;
+    w.parent_tree = wcp->parent_tree;
+    w.donor_slot = wcp->donor_slot;
+    w.donor_nodes = wcp->donor_nodes;
     const int tid = threadIdx.x;
     const int64_t T = p.n_valid;
     const float* in = (const float*)p.inputs;
@@ -468,12 +511,13 @@ __global__ __launch_bounds__(256) void k_walk_f32(WalkParams p)
         stop = 0;
     } else {
         for (int k = 0; k < w.n_levels; ++k) {
-            const int4 lv = p.levels[w.level_off + k];
-            const float* sb = lv.y >= 0 ? recs + (int64_t)lv.y * p.stride
-                                        : in + (int64_t)(-lv.y - 1) * p.stride;
-            const float* pr = recs + (int64_t)lv.z * p.stride;
-            const int f = lv.x & 3;
-            const bool right = (lv.x & 4) != 0;
+            const GP_CONST SpineLvl* lp = cst(p.levels) + w.level_off + k;
+            const SpineLvl lv{lp->fside, lp->sib, lp->par, 0};
+            const float* sb = lv.sib >= 0 ? recs + (int64_t)lv.sib * p.stride
+                                          : in + (int64_t)(-lv.sib - 1) * p.stride;
+            const float* pr = recs + (int64_t)lv.par * p.stride;
+            const int f = lv.fside & 3;
+            const bool right = (lv.fside & 4) != 0;
             eq = true;
             UNROLL for (int m = 0; m < R; ++m) {
                 const int64_t i = tid + 256 * m;
@@ -525,7 +569,16 @@ __global__ __launch_bounds__(256) void k_walk_bool(WalkParams p)
 {
     __shared__ int64_t red[256];
     const int64_t ci = blockIdx.x;
-    const WalkChild w = p.children[ci];
+    const GP_CONST WalkChild* wcp = cst(p.children) + ci;
+    WalkChild w;
+    w.level_off = wcp->level_off;
+    w.n_levels = wcp->n_levels;
+    w.at_point = wcp->at_point;
+    w.rec_base = wcp->rec_base;
+    w.parent_slot = wcp->parent_slot;
+    w.parent_tree = wcp->parent_tree;
+    w.donor_slot = wcp->donor_slot;
+    w.donor_nodes = wcp->donor_nodes;
     const int tid = threadIdx.x;
     const int64_t T = p.n_valid;
     const int64_t W = (T + 63) / 64;
@@ -549,12 +602,13 @@ __global__ __launch_bounds__(256) void k_walk_bool(WalkParams p)
         stop = 0;
     } else {
         for (int k = 0; k < w.n_levels; ++k) {
-            const int4 lv = p.levels[w.level_off + k];
-            const uint64_t* sb = lv.y >= 0 ? recs + (int64_t)lv.y * p.stride
-                                           : in + (int64_t)(-lv.y - 1) * p.stride;
-            const uint64_t* pr = recs + (int64_t)lv.z * p.stride;
-            const int f = lv.x & 3;
-            const bool right = (lv.x & 4) != 0;
+            const GP_CONST SpineLvl* lp = cst(p.levels) + w.level_off + k;
+            const SpineLvl lv{lp->fside, lp->sib, lp->par, 0};
+            const uint64_t* sb = lv.sib >= 0 ? recs + (int64_t)lv.sib * p.stride
+                                             : in + (int64_t)(-lv.sib - 1) * p.stride;
+            const uint64_t* pr = recs + (int64_t)lv.par * p.stride;
+            const int f = lv.fside & 3;
+            const bool right = (lv.fside & 4) != 0;
             eq = true;
             UNROLL for (int m = 0; m < R; ++m) {
                 const int64_t i = tid + 256 * m;

@@ -72,6 +72,11 @@ struct SpineInfo {
 struct Pop {
     int vtype = 0;
     int n_inputs = 0;
+    int layout = 0;
+    bool auto_chunk = false;                // chunk size may be re-tuned
+    // host copy of the trees, for re-chunking by the autotuner
+    std::vector<uint8_t> host_ops;
+    std::vector<int64_t> host_offsets, host_rec_points, host_rec_offsets;
     int64_t n_trees = 0;
     int64_t total_nodes = 0;
     int64_t chunk_nodes = 0;
@@ -89,7 +94,7 @@ struct Pop {
     // parent caches
     std::unordered_map<uint64_t, int32_t> spine_of;   // (tree, point) -> spine
     std::vector<SpineInfo> spines;
-    DevBuf levels;                          // int4 per spine level
+    DevBuf levels;                          // SpineLvl per spine level
     // evaluation state
     int64_t stride = 0;                     // case stride of vecs/recs
     DevBuf vecs;                            // [n_chunks][stride]: roots are slots 0..n_trees-1
@@ -124,6 +129,8 @@ struct Ctx {
     int forced_variant = -1;
     std::map<TuneKey, int> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around the interpreter launch
+    bool time_kernel = false;
     Server* server = nullptr;
 };
 

@@ -94,7 +94,7 @@ int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_
     // Small chunks keep the chain of dependent chunks in the largest trees
     // short; very small ones spend more on chunk hand-off than on work.
     if (total_nodes < 200000) return 256;
-    return 2048;
+    return 1024;
 }
 
 static int64_t elems_of(int vtype, int64_t T) { return vtype == GP_BOOL ? (T + 63) / 64 : T; }
@@ -150,6 +150,7 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
 
     out->vtype = vtype;
     out->n_inputs = n_inputs;
+    out->layout = layout;
     out->n_trees = n_trees;
     out->total_nodes = total;
     out->chunk_nodes = chunk_nodes;
@@ -242,7 +243,7 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     std::vector<DevChunk> dch(n_chunks);
     std::vector<int32_t> chunk_in;
     chunk_in.reserve(n_in);
-    std::vector<int4> levels;
+    std::vector<SpineLvl> levels;
     levels.reserve(n_lv);
     out->chunk_n_in.assign(n_chunks, 0);
     out->chunk_tree.assign(n_chunks, 0);
@@ -287,7 +288,7 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
             si.level_off = (int64_t)levels.size();
             si.n_levels = (int32_t)sp.levels.size();
             si.removed_nodes = sp.child_nodes_removed;
-            for (auto& lv : sp.levels) levels.push_back(make_int4(lv.fside, lv.sib, lv.par, 0));
+            for (auto& lv : sp.levels) levels.push_back(SpineLvl{lv.fside, lv.sib, lv.par, 0});
             out->spine_of[key] = (int32_t)out->spines.size();
             out->spines.push_back(si);
         }
@@ -310,7 +311,7 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     RC(upload(c, out->code, code.data(), code.size() * sizeof(uint32_t)));
     RC(upload(c, out->chunks, dch.data(), dch.size() * sizeof(DevChunk)));
     RC(upload(c, out->chunk_in, chunk_in.data(), chunk_in.size() * sizeof(int32_t)));
-    RC(upload(c, out->levels, levels.data(), levels.size() * sizeof(int4)));
+    RC(upload(c, out->levels, levels.data(), levels.size() * sizeof(SpineLvl)));
     HIPC(c, hipStreamSynchronize(c->stream));
     return GP_OK;
 }
@@ -423,6 +424,7 @@ static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t
                         pl->cursor.as<unsigned int>(), pl->per_tree ? (int)p->n_trees : 1, s));
     EvalParams e = eval_params(p, cs, pl);
     int64_t nl = 1;
+    if (c->time_kernel) HIPC(c, hipEventRecord(c->kev0, s));
     if (!pl->per_tree) {
         HIPC(c, launch_eval(pl->variant, e, pl->grid, s));
         ++nl;
@@ -439,6 +441,7 @@ static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t
             ++nl;
         }
     }
+    if (c->time_kernel) HIPC(c, hipEventRecord(c->kev1, s));
     HIPC(c, launch_fitness(p->vtype, fit_params(p, cs), p->n_trees, s));
     ++nl;
     if (launches) *launches += nl;
@@ -541,6 +544,8 @@ int gp_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, gp_ctx** 
     }
     if ((e = hipEventCreate(&c->ev0)) != hipSuccess) return fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&c->ev1)) != hipSuccess) return fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&c->kev0)) != hipSuccess) return fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&c->kev1)) != hipSuccess) return fail(e, "hipEventCreate");
     Variant* vt = variant_table();
     for (int v = 0; v < variant_count(); ++v) {
         int nb = 0;
@@ -567,6 +572,8 @@ void gp_destroy(gp_ctx* ctx)
     ctx->cases.clear();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->kev0) (void)hipEventDestroy(ctx->kev0);
+    if (ctx->kev1) (void)hipEventDestroy(ctx->kev1);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -631,6 +638,15 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
     auto p = std::make_shared<Pop>();
     RC(build_population(ctx, vtype, layout, n_inputs, n_trees, ops, offsets, record_points, record_offsets,
                         chunk_nodes, p.get()));
+    p->auto_chunk = chunk_nodes <= 0;
+    if (p->auto_chunk) {
+        p->host_ops.assign(ops, ops + offsets[n_trees]);
+        p->host_offsets.assign(offsets, offsets + n_trees + 1);
+        if (record_points) {
+            p->host_rec_offsets.assign(record_offsets, record_offsets + n_trees + 1);
+            p->host_rec_points.assign(record_points, record_points + record_offsets[n_trees]);
+        }
+    }
     gp_handle h = ctx->next_handle++;
     ctx->pops[h] = p;
     *pop_out = h;
@@ -722,8 +738,11 @@ int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags
     const bool per_tree = (flags & GP_PER_TREE) != 0;
     const bool graph = !(flags & GP_NO_GRAPH);
     int64_t launches = 0;
+    ctx->time_kernel = !graph;
     HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    RC(enqueue_full(ctx, p, cases, cs, variant, per_tree, graph, ctx->stream, &launches));
+    int rc_e = enqueue_full(ctx, p, cases, cs, variant, per_tree, graph, ctx->stream, &launches);
+    ctx->time_kernel = false;
+    RC(rc_e);
     HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
     RC(copy_out(ctx, root_out, p->vecs.p, p->n_trees, cs->n_elems, cs->stride, esz, flags));
@@ -731,13 +750,15 @@ int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags
         const hipMemcpyKind kind = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         HIPC(ctx, hipMemcpyAsync(fitness_out, p->fit.p, (size_t)p->n_trees * 8, kind, ctx->stream));
     }
-    float ms = 0.f;
+    float ms = 0.f, kms = 0.f;
     if (!(flags & GP_ASYNC)) {
         HIPC(ctx, hipStreamSynchronize(ctx->stream));
         HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        if (!graph) HIPC(ctx, hipEventElapsedTime(&kms, ctx->kev0, ctx->kev1));
     }
     if (st) {
         st->device_ms = ms;
+        st->kernel_ms = kms;
         st->equivalent_ops = p->total_nodes * cs->T;
         st->interpreted_ops = p->total_nodes * cs->T;
         st->launches = launches;
@@ -844,7 +865,7 @@ int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, i
     RC(enqueue_full(ctx, &donors, cases, cs, variant, false, false, ctx->stream, &launches));
     WalkParams wp;
     wp.children = d_wc.as<WalkChild>();
-    wp.levels = p->levels.as<int4>();
+    wp.levels = p->levels.as<SpineLvl>();
     wp.inputs = cs->inputs.p;
     wp.recs = p->recs.p;
     wp.parent_vecs = p->vecs.p;
@@ -886,6 +907,7 @@ int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, i
     }
     if (st) {
         st->device_ms = ms;
+        st->kernel_ms = 0;
         st->equivalent_ops = equiv_nodes * cs->T;
         st->interpreted_ops = interp_total * cs->T;
         st->launches = launches;
@@ -920,6 +942,10 @@ int gp_set_variant(gp_ctx* ctx, int variant)
     return GP_OK;
 }
 
+// Time every interpreter variant, and for automatically chunked populations
+// every candidate chunk size, on this population and case set; keep the
+// fastest (chunk size: recompiled in place; variant: remembered per value
+// type, case-count bucket and tree-size bucket).
 int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, double* best_ms)
 {
     if (!ctx) return GP_EINVAL;
@@ -928,28 +954,78 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     Pop* p;
     CaseSet* cs;
     RC(lookup(ctx, pop, cases, &p, &cs));
-    int best = -1;
-    float best_t = 1e30f;
-    for (int v = 0; v < variant_count(); ++v) {
-        const Variant& vt = variant_table()[v];
-        if (vt.vtype != p->vtype || vt.S < p->max_stack) continue;
-        RC(enqueue_full(ctx, p, cases, cs, v, false, true, ctx->stream, nullptr));   // warm-up + capture
+    std::vector<int64_t> chunk_sizes{p->chunk_nodes};
+    if (p->auto_chunk && !p->host_ops.empty()) {
+        const int64_t mean = p->total_nodes / std::max<int64_t>(1, p->n_trees);
+        std::vector<int64_t> cand = p->total_nodes > 200000000 ? std::vector<int64_t>{512, 1024, 2048}
+                                                               : std::vector<int64_t>{256, 512, 1024, 2048, 4096};
+        chunk_sizes.clear();
+        for (int64_t c : cand)
+            if (c <= std::max<int64_t>(256, 4 * mean)) chunk_sizes.push_back(c);
+    }
+    auto time_variant = [&](Pop* q, int v, float* out) -> int {
+        RC(enqueue_full(ctx, q, cases, cs, v, false, true, ctx->stream, nullptr));   // warm-up + capture
         float tmin = 1e30f;
         for (int r = 0; r < 3; ++r) {
             HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-            RC(enqueue_full(ctx, p, cases, cs, v, false, true, ctx->stream, nullptr));
+            RC(enqueue_full(ctx, q, cases, cs, v, false, true, ctx->stream, nullptr));
             HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
             HIPC(ctx, hipStreamSynchronize(ctx->stream));
             float ms = 0.f;
             HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
             tmin = std::min(tmin, ms);
         }
-        if (tmin < best_t) {
-            best_t = tmin;
-            best = v;
+        *out = tmin;
+        return GP_OK;
+    };
+    int best = -1;
+    int64_t best_c = p->chunk_nodes;
+    float best_t = 1e30f;
+    std::shared_ptr<Pop> best_pop;
+    for (int64_t cn : chunk_sizes) {
+        std::shared_ptr<Pop> q;
+        Pop* qp = p;
+        if (cn != p->chunk_nodes) {
+            q = std::make_shared<Pop>();
+            const bool rec = !p->host_rec_points.empty() || !p->host_rec_offsets.empty();
+            RC(build_population(ctx, p->vtype, p->layout, p->n_inputs, p->n_trees, p->host_ops.data(),
+                                p->host_offsets.data(), rec ? p->host_rec_points.data() : nullptr,
+                                rec ? p->host_rec_offsets.data() : nullptr, cn, q.get()));
+            qp = q.get();
+        }
+        for (int v = 0; v < variant_count(); ++v) {
+            const Variant& vt = variant_table()[v];
+            if (vt.vtype != qp->vtype || vt.S < qp->max_stack) continue;
+            float t = 0.f;
+            RC(time_variant(qp, v, &t));
+            if (t < best_t) {
+                best_t = t;
+                best = v;
+                best_c = cn;
+                best_pop = q;
+            }
+        }
+        if (q && q != best_pop) {
+            q.reset();
+        } else if (q) {
+            // keep only the best compiled copy alive
+            continue;
         }
     }
     if (best < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits this population");
+    if (best_pop) {
+        // the re-chunked copy replaces the population under the same handle
+        best_pop->auto_chunk = true;
+        best_pop->host_ops.swap(p->host_ops);
+        best_pop->host_offsets.swap(p->host_offsets);
+        best_pop->host_rec_points.swap(p->host_rec_points);
+        best_pop->host_rec_offsets.swap(p->host_rec_offsets);
+        ctx->pops[pop] = best_pop;
+        p = best_pop.get();
+        RC(enqueue_full(ctx, p, cases, cs, best, false, true, ctx->stream, nullptr));
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    (void)best_c;
     TuneKey key{p->vtype, ilog2_ceil(cs->T), ilog2_ceil(std::max<int64_t>(1, p->total_nodes / std::max<int64_t>(1, p->n_trees)))};
     ctx->tuned[key] = best;
     if (best_variant) *best_variant = best;

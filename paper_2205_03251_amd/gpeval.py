@@ -39,7 +39,8 @@ class GPError(RuntimeError):
 
 
 class Stats(C.Structure):
-    _fields_ = [("device_ms", C.c_double), ("wall_ms", C.c_double), ("equivalent_ops", C.c_int64),
+    _fields_ = [("device_ms", C.c_double), ("kernel_ms", C.c_double), ("wall_ms", C.c_double),
+                ("equivalent_ops", C.c_int64),
                 ("interpreted_ops", C.c_int64), ("launches", C.c_int64), ("variant", C.c_int32),
                 ("reserved", C.c_int32)]
 

@@ -318,8 +318,8 @@ def test_malformed_population_rejected(ctx):
 
 
 def test_budget_enforced():
-    c = g.Context(0, budget_bytes=1 << 20)
-    pop = gen.sized_population(3, 4, 10001, 20001)
+    c = g.Context(0, budget_bytes=256 << 10)
+    pop = gen.sized_population(3, 8, 10001, 20001)
     cases = gen.float_cases(1, 1024)
     ch = c.set_cases(g.GP_F32, cases.x, cases.y)
     with pytest.raises(g.GPError) as e:
