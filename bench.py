@@ -82,8 +82,9 @@ def cpu_baseline(pop, cases, kids, vtype, threads, budget_s=12.0):
     from concurrent.futures import ThreadPoolExecutor
     T = cases.T
     sizes = pop.sizes()
-    # bounded sample: trees in index order until ~budget_s of work at ~2.5 ns per op
-    per_thread_ops = budget_s / 2.5e-9
+    # bounded sample: trees in index order until ~budget_s of work at the
+    # oracle's ~10 ns per node and case
+    per_thread_ops = budget_s / 10e-9
     target = per_thread_ops * threads
     chosen, tot = [], 0
     for i in range(pop.n_trees):

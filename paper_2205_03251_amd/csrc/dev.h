@@ -39,33 +39,30 @@ struct EvalParams {
     int32_t n_inputs;
 };
 
-// One incremental child.
-struct WalkChild {
-    int64_t level_off;           // first SpineLvl of its spine
-    int32_t n_levels;
-    int32_t at_point;            // mother's vector at the point (source code)
-    int32_t rec_base;            // record slot base of the mother tree
-    int32_t parent_slot;         // mother's root vector slot in the population
-    int32_t parent_tree;
-    int32_t donor_slot;          // donor's root vector slot in the donor run
-    int64_t donor_nodes;
+// One incremental child.  Pointers refer to the mother's population, so one
+// launch may walk children of different populations.
+struct SpineLvl {
+    int32_t fside, sib, par, pad;   // see SpineLevel in prep.h
 };
 
-// One ancestor level of a spine (see SpineLevel in prep.h).
-struct SpineLvl {
-    int32_t fside, sib, par, pad;
+struct WalkChild {
+    const SpineLvl* levels;      // the spine's ancestor levels, nearest first
+    const void* recs;            // the mother's record slot 0
+    const void* parent_vec;      // the mother's root vector
+    const void* parent_fit;      // the mother's fitness (double or int64)
+    int32_t n_levels;
+    int32_t at_point;            // mother's vector at the point (source code)
+    int32_t donor_slot;          // donor's root vector slot in the donor run
+    int32_t pad;
+    int64_t donor_nodes;
 };
 
 struct WalkParams {
     const WalkChild* children;
-    const SpineLvl* levels;
     const void* inputs;          // [n_inputs][stride]
-    const void* recs;            // mother records
-    const void* parent_vecs;     // mother root vectors
-    const void* parent_fit;      // mother fitness (double or int64) [n_trees]
     const void* donor_vecs;      // donor root vectors
     const void* target;          // [stride]
-    void* root_out;              // [n_children][stride]
+    void* root_out;              // [n_children][stride] or null
     void* fit_out;               // [n_children]
     int32_t* stop_out;           // [n_children]
     int64_t* interp_out;         // [n_children]

@@ -480,27 +480,26 @@ __global__ __launch_bounds__(256) void k_walk_f32(WalkParams p)
     __shared__ double red[256];
     const int64_t ci = blockIdx.x;
     const GP_CONST WalkChild* wcp = cst(p.children) + ci;
-    WalkChild w;
-    w.level_off = wcp->level_off;
-    w.n_levels = wcp->n_levels;
-    w.at_point = wcp->at_point;
-    w.rec_base = wcp->rec_base;
-    w.parent_slot = wcp->parent_slot;
-    w.parent_tree = wcp->parent_tree;
-    w.donor_slot = wcp->donor_slot;
-    w.donor_nodes = wcp->donor_nodes;
+    const SpineLvl* levels = wcp->levels;
+    const void* w_recs = wcp->recs;
+    const void* w_pvec = wcp->parent_vec;
+    const void* w_pfit = wcp->parent_fit;
+    const int32_t n_levels = wcp->n_levels;
+    const int32_t at_point = wcp->at_point;
+    const int32_t donor_slot = wcp->donor_slot;
+    const int64_t donor_nodes = wcp->donor_nodes;
     const int tid = threadIdx.x;
     const int64_t T = p.n_valid;
     const float* in = (const float*)p.inputs;
-    const float* recs = (const float*)p.recs + (int64_t)w.rec_base * p.stride;
-    const float* dv = (const float*)p.donor_vecs + (int64_t)w.donor_slot * p.stride;
+    const float* recs = (const float*)w_recs;
+    const float* dv = (const float*)p.donor_vecs + (int64_t)donor_slot * p.stride;
     float v[R];
     UNROLL for (int m = 0; m < R; ++m) {
         const int64_t i = tid + 256 * m;
         v[m] = (i < T) ? dv[i] : 0.0f;
     }
-    const float* a0 = w.at_point >= 0 ? recs + (int64_t)w.at_point * p.stride
-                                      : in + (int64_t)(-w.at_point - 1) * p.stride;
+    const float* a0 = at_point >= 0 ? recs + (int64_t)at_point * p.stride
+                                    : in + (int64_t)(-at_point - 1) * p.stride;
     bool eq = true;
     UNROLL for (int m = 0; m < R; ++m) {
         const int64_t i = tid + 256 * m;
@@ -510,8 +509,8 @@ __global__ __launch_bounds__(256) void k_walk_f32(WalkParams p)
     if (__syncthreads_and(eq)) {
         stop = 0;
     } else {
-        for (int k = 0; k < w.n_levels; ++k) {
-            const GP_CONST SpineLvl* lp = cst(p.levels) + w.level_off + k;
+        for (int k = 0; k < n_levels; ++k) {
+            const GP_CONST SpineLvl* lp = cst(levels) + k;
             const SpineLvl lv{lp->fside, lp->sib, lp->par, 0};
             const float* sb = lv.sib >= 0 ? recs + (int64_t)lv.sib * p.stride
                                           : in + (int64_t)(-lv.sib - 1) * p.stride;
@@ -536,16 +535,16 @@ __global__ __launch_bounds__(256) void k_walk_f32(WalkParams p)
     }
     if (tid == 0) {
         p.stop_out[ci] = stop;
-        p.interp_out[ci] = w.donor_nodes + (stop >= 0 ? stop : w.n_levels);
+        p.interp_out[ci] = donor_nodes + (stop >= 0 ? stop : n_levels);
     }
     float* ro = p.root_out ? (float*)p.root_out + ci * p.stride : nullptr;
     if (stop >= 0) {
         // The difference died out: the child's values above the stop are
         // the mother's, and so is its fitness.
-        const float* pv = (const float*)p.parent_vecs + (int64_t)w.parent_slot * p.stride;
+        const float* pv = (const float*)w_pvec;
         if (ro)
             for (int64_t i = tid; i < T; i += 256) ro[i] = pv[i];
-        if (tid == 0) ((double*)p.fit_out)[ci] = ((const double*)p.parent_fit)[w.parent_tree];
+        if (tid == 0) ((double*)p.fit_out)[ci] = *(const double*)w_pfit;
     } else {
         const float* y = (const float*)p.target;
         double e[R];
@@ -570,28 +569,27 @@ __global__ __launch_bounds__(256) void k_walk_bool(WalkParams p)
     __shared__ int64_t red[256];
     const int64_t ci = blockIdx.x;
     const GP_CONST WalkChild* wcp = cst(p.children) + ci;
-    WalkChild w;
-    w.level_off = wcp->level_off;
-    w.n_levels = wcp->n_levels;
-    w.at_point = wcp->at_point;
-    w.rec_base = wcp->rec_base;
-    w.parent_slot = wcp->parent_slot;
-    w.parent_tree = wcp->parent_tree;
-    w.donor_slot = wcp->donor_slot;
-    w.donor_nodes = wcp->donor_nodes;
+    const SpineLvl* levels = wcp->levels;
+    const void* w_recs = wcp->recs;
+    const void* w_pvec = wcp->parent_vec;
+    const void* w_pfit = wcp->parent_fit;
+    const int32_t n_levels = wcp->n_levels;
+    const int32_t at_point = wcp->at_point;
+    const int32_t donor_slot = wcp->donor_slot;
+    const int64_t donor_nodes = wcp->donor_nodes;
     const int tid = threadIdx.x;
     const int64_t T = p.n_valid;
     const int64_t W = (T + 63) / 64;
     const uint64_t* in = (const uint64_t*)p.inputs;
-    const uint64_t* recs = (const uint64_t*)p.recs + (int64_t)w.rec_base * p.stride;
-    const uint64_t* dv = (const uint64_t*)p.donor_vecs + (int64_t)w.donor_slot * p.stride;
+    const uint64_t* recs = (const uint64_t*)w_recs;
+    const uint64_t* dv = (const uint64_t*)p.donor_vecs + (int64_t)donor_slot * p.stride;
     uint64_t v[R];
     UNROLL for (int m = 0; m < R; ++m) {
         const int64_t i = tid + 256 * m;
         v[m] = (i < W) ? dv[i] : 0ull;
     }
-    const uint64_t* a0 = w.at_point >= 0 ? recs + (int64_t)w.at_point * p.stride
-                                         : in + (int64_t)(-w.at_point - 1) * p.stride;
+    const uint64_t* a0 = at_point >= 0 ? recs + (int64_t)at_point * p.stride
+                                       : in + (int64_t)(-at_point - 1) * p.stride;
     bool eq = true;
     UNROLL for (int m = 0; m < R; ++m) {
         const int64_t i = tid + 256 * m;
@@ -601,8 +599,8 @@ __global__ __launch_bounds__(256) void k_walk_bool(WalkParams p)
     if (__syncthreads_and(eq)) {
         stop = 0;
     } else {
-        for (int k = 0; k < w.n_levels; ++k) {
-            const GP_CONST SpineLvl* lp = cst(p.levels) + w.level_off + k;
+        for (int k = 0; k < n_levels; ++k) {
+            const GP_CONST SpineLvl* lp = cst(levels) + k;
             const SpineLvl lv{lp->fside, lp->sib, lp->par, 0};
             const uint64_t* sb = lv.sib >= 0 ? recs + (int64_t)lv.sib * p.stride
                                              : in + (int64_t)(-lv.sib - 1) * p.stride;
@@ -627,14 +625,14 @@ __global__ __launch_bounds__(256) void k_walk_bool(WalkParams p)
     }
     if (tid == 0) {
         p.stop_out[ci] = stop;
-        p.interp_out[ci] = w.donor_nodes + (stop >= 0 ? stop : w.n_levels);
+        p.interp_out[ci] = donor_nodes + (stop >= 0 ? stop : n_levels);
     }
     uint64_t* ro = p.root_out ? (uint64_t*)p.root_out + ci * p.stride : nullptr;
     if (stop >= 0) {
-        const uint64_t* pv = (const uint64_t*)p.parent_vecs + (int64_t)w.parent_slot * p.stride;
+        const uint64_t* pv = (const uint64_t*)w_pvec;
         if (ro)
             for (int64_t i = tid; i < W; i += 256) ro[i] = pv[i];
-        if (tid == 0) ((int64_t*)p.fit_out)[ci] = ((const int64_t*)p.parent_fit)[w.parent_tree];
+        if (tid == 0) ((int64_t*)p.fit_out)[ci] = *(const int64_t*)w_pfit;
     } else {
         const uint64_t* t = (const uint64_t*)p.target;
         int64_t hits = 0;

@@ -122,6 +122,7 @@ struct Ctx {
     std::atomic<uint64_t> used{0};
     int n_cu = 0;
     std::string err;
+    std::mutex err_mu;                      // server threads may report errors too
     std::mutex mu;                          // guards handles (server threads share the ctx)
     gp_handle next_handle = 1;
     std::unordered_map<gp_handle, std::shared_ptr<CaseSet>> cases;
@@ -130,7 +131,6 @@ struct Ctx {
     std::map<TuneKey, int> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around the interpreter launch
-    bool time_kernel = false;
     Server* server = nullptr;
 };
 
@@ -139,15 +139,38 @@ int set_err(Ctx* c, int code, const std::string& msg);
 int dev_alloc(Ctx* c, DevBuf& b, size_t bytes);
 int hip_check(Ctx* c, hipError_t e, const char* what);
 
-// Compile and upload a population (prefix or postfix trees).
+// Compile and upload a population (prefix or postfix trees) on stream s
+// (s synchronised before return).
 int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees,
                      const uint8_t* ops, const int64_t* offsets, const int64_t* rec_points,
-                     const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out);
+                     const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, hipStream_t s);
+// Assemble already compiled trees into a population and upload it on s.
+int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& progs,
+                        const std::vector<int64_t>& tree_nodes, int64_t chunk_nodes, Pop* out,
+                        hipStream_t s);
 // Make sure vecs/recs/fit match the case set; allocate if needed.
 int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs);
 // Enqueue a full evaluation on stream s (no copies out, no synchronisation).
+// time_kernel: record c->kev0/kev1 around the interpreter launch.
 int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int variant, bool per_tree,
-                 bool use_graph, hipStream_t s, int64_t* launches);
+                 bool use_graph, hipStream_t s, int64_t* launches, bool time_kernel = false);
+// Build the walk descriptors of an incremental batch and enqueue donor
+// evaluation + walk on s.  Outputs are device buffers owned by the caller.
+struct IncJob {
+    Pop* parent;                 // population holding the mother
+    int64_t tree;                // mother's tree index in it
+    int64_t point;               // crossover point (caller's layout)
+    const uint8_t* donor;        // donor bytes (prefix)
+    int64_t donor_len;
+};
+struct IncOut {
+    DevBuf wc, root, fit, stop, interp;
+    Pop donors;
+    int64_t equiv_nodes = 0;
+    std::vector<int64_t> child_nodes;
+};
+int enqueue_incremental(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, const CaseSet* cs,
+                        bool want_roots, hipStream_t s, IncOut* out, int64_t* launches);
 int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p);
 int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_t T);
 int compile_stack_slots();

@@ -14,7 +14,10 @@ namespace gpe {
 // ------------------------------------------------------------ errors
 int set_err(Ctx* c, int code, const std::string& msg)
 {
-    if (c) c->err = msg;
+    if (c) {
+        std::lock_guard<std::mutex> lk(c->err_mu);
+        c->err = msg;
+    }
     return code;
 }
 
@@ -71,10 +74,10 @@ int dev_alloc(Ctx* c, DevBuf& b, size_t bytes)
     return GP_OK;
 }
 
-static int upload(Ctx* c, DevBuf& b, const void* src, size_t bytes)
+static int upload(Ctx* c, DevBuf& b, const void* src, size_t bytes, hipStream_t s)
 {
     RC(dev_alloc(c, b, bytes));
-    if (bytes) HIPC(c, hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream));
+    if (bytes) HIPC(c, hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
     return GP_OK;
 }
 
@@ -129,12 +132,11 @@ int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
 // -------------------------------------------------- population assembly
 int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees, const uint8_t* ops,
                      const int64_t* offsets, const int64_t* rec_points, const int64_t* rec_offsets,
-                     int64_t chunk_nodes, Pop* out)
+                     int64_t chunk_nodes, Pop* out, hipStream_t stream)
 {
     if (vtype != GP_F32 && vtype != GP_BOOL) return set_err(c, GP_EINVAL, "unknown value type");
     if (layout != GP_PREFIX && layout != GP_POSTFIX) return set_err(c, GP_EINVAL, "unknown layout");
     if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(c, GP_EINVAL, "n_inputs must be 1..64");
-    if (vtype == GP_BOOL && n_inputs > 2047) return set_err(c, GP_EINVAL, "too many inputs");
     if (n_trees < 1 || !ops || !offsets) return set_err(c, GP_EINVAL, "empty population");
     if (n_trees > INT32_MAX / 2) return set_err(c, GP_EINVAL, "too many trees");
     if (offsets[0] != 0) return set_err(c, GP_EINVAL, "offsets[0] must be 0");
@@ -148,14 +150,6 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     if (chunk_nodes <= 0) chunk_nodes = auto_chunk_nodes(vtype, total, n_trees, 0);
     chunk_nodes = std::max<int64_t>(chunk_nodes, 16);
 
-    out->vtype = vtype;
-    out->n_inputs = n_inputs;
-    out->layout = layout;
-    out->n_trees = n_trees;
-    out->total_nodes = total;
-    out->chunk_nodes = chunk_nodes;
-    out->tree_nodes.resize(n_trees);
-
     CompileOptions opt;
     opt.vtype = vtype;
     opt.n_inputs = n_inputs;
@@ -165,11 +159,12 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     std::vector<TreeProg> progs(n_trees);
     std::vector<std::string> errs(n_trees);
     std::vector<char> bad(n_trees, 0);
-    std::vector<int64_t> order(n_trees);
-    for (int64_t t = 0; t < n_trees; ++t) order[t] = t;
-    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-        return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
-    });
+    std::vector<int64_t> order(n_trees), tree_nodes(n_trees);
+    for (int64_t t = 0; t < n_trees; ++t) {
+        order[t] = t;
+        tree_nodes[t] = offsets[t + 1] - offsets[t];
+    }
+    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return tree_nodes[x] > tree_nodes[y]; });
     std::atomic<int64_t> next{0};
     auto work = [&]() {
         std::vector<uint8_t> pre;
@@ -179,7 +174,7 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
             if (k >= n_trees) return;
             int64_t t = order[k];
             const uint8_t* tops = ops + offsets[t];
-            int64_t n = offsets[t + 1] - offsets[t];
+            int64_t n = tree_nodes[t];
             const int64_t* p0 = rec_points ? rec_points + rec_offsets[t] : nullptr;
             int64_t np = rec_points ? rec_offsets[t + 1] - rec_offsets[t] : 0;
             if (np < 0) {
@@ -225,6 +220,22 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     for (auto& x : th) x.join();
     for (int64_t t = 0; t < n_trees; ++t)
         if (bad[t]) return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + ": " + errs[t]);
+    out->layout = layout;
+    return assemble_population(c, vtype, n_inputs, progs, tree_nodes, chunk_nodes, out, stream);
+}
+
+int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& progs,
+                        const std::vector<int64_t>& tree_nodes, int64_t chunk_nodes, Pop* out,
+                        hipStream_t stream)
+{
+    const int64_t n_trees = (int64_t)progs.size();
+    out->vtype = vtype;
+    out->n_inputs = n_inputs;
+    out->n_trees = n_trees;
+    out->chunk_nodes = chunk_nodes;
+    out->tree_nodes = tree_nodes;
+    out->total_nodes = 0;
+    for (int64_t v : tree_nodes) out->total_nodes += v;
 
     // Global numbering: tree t's root chunk writes vector slot t; every
     // other chunk gets a slot after the roots.
@@ -256,7 +267,6 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     std::vector<int32_t> slot;
     for (int64_t t = 0; t < n_trees; ++t) {
         TreeProg& pg = progs[t];
-        out->tree_nodes[t] = offsets[t + 1] - offsets[t];
         out->rec_base[t] = rbase;
         out->max_stack = std::max(out->max_stack, pg.max_stack);
         const int64_t obase = (int64_t)code.size();
@@ -294,25 +304,23 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
         }
         cbase += nc;
         rbase += pg.n_records;
-        TreeProg().code.swap(pg.code);
-        pg.chunks.clear();
-        pg.chunks.shrink_to_fit();
+        std::vector<uint32_t>().swap(pg.code);
+        std::vector<Chunk>().swap(pg.chunks);
     }
-    // Longest remaining chain first; slices of a chunk are handed out
-    // together when plans expand the leaves.
+    // Longest remaining chain first.
     std::stable_sort(out->leaves.begin(), out->leaves.end(),
-                     [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
-                         return a.first > b.first;
+                     [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                         return x.first > y.first;
                      });
     code.push_back(0);                      // one word past the end for the fetch-ahead
     out->n_chunks = n_chunks;
     out->n_code = (int64_t)code.size() - 1;
     out->n_records = n_rec;
-    RC(upload(c, out->code, code.data(), code.size() * sizeof(uint32_t)));
-    RC(upload(c, out->chunks, dch.data(), dch.size() * sizeof(DevChunk)));
-    RC(upload(c, out->chunk_in, chunk_in.data(), chunk_in.size() * sizeof(int32_t)));
-    RC(upload(c, out->levels, levels.data(), levels.size() * sizeof(SpineLvl)));
-    HIPC(c, hipStreamSynchronize(c->stream));
+    RC(upload(c, out->code, code.data(), code.size() * sizeof(uint32_t), stream));
+    RC(upload(c, out->chunks, dch.data(), dch.size() * sizeof(DevChunk), stream));
+    RC(upload(c, out->chunk_in, chunk_in.data(), chunk_in.size() * sizeof(int32_t), stream));
+    RC(upload(c, out->levels, levels.data(), levels.size() * sizeof(SpineLvl), stream));
+    HIPC(c, hipStreamSynchronize(stream));
     return GP_OK;
 }
 
@@ -335,7 +343,8 @@ int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs)
     return GP_OK;
 }
 
-static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, int variant, bool per_tree, Plan** out)
+static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, int variant, bool per_tree, Plan** out,
+                     hipStream_t stream)
 {
     const Variant& v = variant_table()[variant];
     const int32_t n_slices = (int32_t)((cs->n_elems + kWave * v.K - 1) / (kWave * v.K));
@@ -371,13 +380,13 @@ static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, int variant, bool per_tr
     std::vector<int32_t> pend((size_t)p->n_chunks * n_slices);
     for (int64_t k = 0; k < p->n_chunks; ++k)
         for (int32_t s = 0; s < n_slices; ++s) pend[(size_t)k * n_slices + s] = p->chunk_n_in[k];
-    RC(upload(c, pl->items, items.data(), items.size() * sizeof(int64_t)));
-    RC(upload(c, pl->pending_init, pend.data(), pend.size() * sizeof(int32_t)));
+    RC(upload(c, pl->items, items.data(), items.size() * sizeof(int64_t), stream));
+    RC(upload(c, pl->pending_init, pend.data(), pend.size() * sizeof(int32_t), stream));
     RC(dev_alloc(c, pl->pending, pend.size() * sizeof(int32_t)));
     RC(dev_alloc(c, pl->cursor, (size_t)(per_tree ? p->n_trees : 1) * sizeof(unsigned int)));
     const int64_t full = (int64_t)std::max(1, v.max_blocks_per_cu) * std::max(1, c->n_cu);
     pl->grid = (int)std::max<int64_t>(1, std::min<int64_t>(full, pl->n_items));
-    HIPC(c, hipStreamSynchronize(c->stream));
+    HIPC(c, hipStreamSynchronize(stream));
     p->plans[key] = std::move(pl);
     *out = p->plans[key].get();
     return GP_OK;
@@ -417,14 +426,15 @@ static FitParams fit_params(Pop* p, const CaseSet* cs)
 
 // Everything one full evaluation enqueues: reset counters and cursors,
 // evaluate, score.
-static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t s, int64_t* launches)
+static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t s, int64_t* launches,
+                        bool time_kernel)
 {
     const int64_t n_pend = p->n_chunks * pl->n_slices;
     HIPC(c, launch_init(pl->pending.as<int32_t>(), pl->pending_init.as<int32_t>(), n_pend,
                         pl->cursor.as<unsigned int>(), pl->per_tree ? (int)p->n_trees : 1, s));
     EvalParams e = eval_params(p, cs, pl);
     int64_t nl = 1;
-    if (c->time_kernel) HIPC(c, hipEventRecord(c->kev0, s));
+    if (time_kernel) HIPC(c, hipEventRecord(c->kev0, s));
     if (!pl->per_tree) {
         HIPC(c, launch_eval(pl->variant, e, pl->grid, s));
         ++nl;
@@ -441,7 +451,7 @@ static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t
             ++nl;
         }
     }
-    if (c->time_kernel) HIPC(c, hipEventRecord(c->kev1, s));
+    if (time_kernel) HIPC(c, hipEventRecord(c->kev1, s));
     HIPC(c, launch_fitness(p->vtype, fit_params(p, cs), p->n_trees, s));
     ++nl;
     if (launches) *launches += nl;
@@ -449,13 +459,13 @@ static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t
 }
 
 int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int variant, bool per_tree,
-                 bool use_graph, hipStream_t s, int64_t* launches)
+                 bool use_graph, hipStream_t s, int64_t* launches, bool time_kernel)
 {
     RC(ensure_eval_buffers(c, p, cs));
     Plan* pl = nullptr;
-    RC(make_plan(c, p, cs, variant, per_tree, &pl));
+    RC(make_plan(c, p, cs, variant, per_tree, &pl, s));
     if (!use_graph) {
-        RC(enqueue_body(c, p, cs, pl, s, launches));
+        RC(enqueue_body(c, p, cs, pl, s, launches, time_kernel));
     } else {
         if (!pl->graph || pl->graph_cases != cases_h) {
             if (pl->graph) {
@@ -465,7 +475,7 @@ int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int varia
             hipGraph_t g = nullptr;
             HIPC(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             int64_t dummy = 0;
-            int rc = enqueue_body(c, p, cs, pl, s, &dummy);
+            int rc = enqueue_body(c, p, cs, pl, s, &dummy, false);
             hipError_t e2 = hipStreamEndCapture(s, &g);
             if (rc != GP_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -481,6 +491,78 @@ int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int varia
         if (launches) *launches += 1;
     }
     p->evaluated_with = cases_h;
+    return GP_OK;
+}
+
+int enqueue_incremental(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, const CaseSet* cs,
+                        bool want_roots, hipStream_t s, IncOut* out, int64_t* launches)
+{
+    const int64_t n = (int64_t)jobs.size();
+    if (n == 0) return GP_OK;
+    const int vtype = cs->vtype;
+    std::vector<WalkChild> wc(n);
+    std::vector<int64_t> doffs(n + 1, 0);
+    std::vector<uint8_t> dops;
+    out->equiv_nodes = 0;
+    out->child_nodes.assign(n, 0);
+    const size_t esz = vtype == GP_BOOL ? 8 : 4;
+    for (int64_t i = 0; i < n; ++i) {
+        const IncJob& j = jobs[i];
+        Pop* p = j.parent;
+        if (p->vtype != vtype) return set_err(c, GP_EINVAL, "child " + std::to_string(i) + ": value type mismatch");
+        if (j.tree < 0 || j.tree >= p->n_trees)
+            return set_err(c, GP_EINVAL, "child " + std::to_string(i) + ": parent index out of range");
+        if (j.point < 0 || j.point >= p->tree_nodes[j.tree])
+            return set_err(c, GP_EINVAL, "child " + std::to_string(i) + ": crossover point out of range");
+        if (p->evaluated_with != cases_h)
+            return set_err(c, GP_ENOTFOUND, "child " + std::to_string(i) + ": the parent population has no parent "
+                                            "caches for this case set; run gp_evaluate_full on it first");
+        auto it = p->spine_of.find(((uint64_t)j.tree << 32) | (uint32_t)j.point);
+        if (it == p->spine_of.end())
+            return set_err(c, GP_ENOTFOUND, "child " + std::to_string(i) + ": point " + std::to_string(j.point) +
+                                                " of tree " + std::to_string(j.tree) + " was not recorded");
+        const SpineInfo& si = p->spines[it->second];
+        if (j.donor_len < 1 || !j.donor) return set_err(c, GP_EINVAL, "child " + std::to_string(i) + ": empty donor");
+        WalkChild& w = wc[i];
+        w.levels = p->levels.as<SpineLvl>() + si.level_off;
+        w.recs = (const uint8_t*)p->recs.p + (size_t)p->rec_base[j.tree] * cs->stride * esz;
+        w.parent_vec = (const uint8_t*)p->vecs.p + (size_t)j.tree * cs->stride * esz;
+        w.parent_fit = (const uint8_t*)p->fit.p + (size_t)j.tree * 8;
+        w.n_levels = si.n_levels;
+        w.at_point = si.at_point;
+        w.donor_slot = (int32_t)i;
+        w.pad = 0;
+        w.donor_nodes = j.donor_len;
+        out->child_nodes[i] = p->tree_nodes[j.tree] - si.removed_nodes + j.donor_len;
+        out->equiv_nodes += out->child_nodes[i];
+        dops.insert(dops.end(), j.donor, j.donor + j.donor_len);
+        doffs[i + 1] = (int64_t)dops.size();
+    }
+    // Inserted subtrees: evaluated on every case like any population.
+    RC(build_population(c, vtype, GP_PREFIX, jobs[0].parent->n_inputs, n, dops.data(), doffs.data(), nullptr,
+                        nullptr, 0, &out->donors, s));
+    const int variant = choose_variant(c, vtype, cs, &out->donors);
+    if (variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the donors");
+    RC(upload(c, out->wc, wc.data(), wc.size() * sizeof(WalkChild), s));
+    RC(dev_alloc(c, out->root, want_roots ? (size_t)n * cs->stride * esz : 256));
+    RC(dev_alloc(c, out->fit, (size_t)n * 8));
+    RC(dev_alloc(c, out->stop, (size_t)n * 4));
+    RC(dev_alloc(c, out->interp, (size_t)n * 8));
+    RC(enqueue_full(c, &out->donors, cases_h, cs, variant, false, false, s, launches));
+    WalkParams wp;
+    wp.children = out->wc.as<WalkChild>();
+    wp.inputs = cs->inputs.p;
+    wp.donor_vecs = out->donors.vecs.p;
+    wp.target = cs->target.p;
+    wp.root_out = want_roots ? out->root.p : nullptr;
+    wp.fit_out = out->fit.p;
+    wp.stop_out = out->stop.as<int32_t>();
+    wp.interp_out = out->interp.as<int64_t>();
+    wp.stride = cs->stride;
+    wp.n_valid = cs->T;
+    wp.P = cs->P;
+    HIPC(c, launch_walk(vtype, wp, n, s));
+    if (launches) ++*launches;
     return GP_OK;
 }
 
@@ -637,7 +719,7 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
     HIPC(ctx, hipSetDevice(ctx->device));
     auto p = std::make_shared<Pop>();
     RC(build_population(ctx, vtype, layout, n_inputs, n_trees, ops, offsets, record_points, record_offsets,
-                        chunk_nodes, p.get()));
+                        chunk_nodes, p.get(), ctx->stream));
     p->auto_chunk = chunk_nodes <= 0;
     if (p->auto_chunk) {
         p->host_ops.assign(ops, ops + offsets[n_trees]);
@@ -738,11 +820,8 @@ int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags
     const bool per_tree = (flags & GP_PER_TREE) != 0;
     const bool graph = !(flags & GP_NO_GRAPH);
     int64_t launches = 0;
-    ctx->time_kernel = !graph;
     HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    int rc_e = enqueue_full(ctx, p, cases, cs, variant, per_tree, graph, ctx->stream, &launches);
-    ctx->time_kernel = false;
-    RC(rc_e);
+    RC(enqueue_full(ctx, p, cases, cs, variant, per_tree, graph, ctx->stream, &launches, !graph));
     HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
     RC(copy_out(ctx, root_out, p->vecs.p, p->n_trees, cs->n_elems, cs->stride, esz, flags));
@@ -817,90 +896,47 @@ int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, i
     if (!parent || !point || !donor_ops || !donor_offsets) return set_err(ctx, GP_EINVAL, "missing child arrays");
     if ((flags & GP_ASYNC) && !(flags & GP_DEVICE_PTR))
         return set_err(ctx, GP_EINVAL, "GP_ASYNC needs GP_DEVICE_PTR outputs");
-    if (p->evaluated_with != cases)
-        return set_err(ctx, GP_ENOTFOUND, "the population has no parent caches for this case set; "
-                                          "run gp_evaluate_full on it first");
-    // Children -> spines (the mother's recorded vectors along the path).
-    std::vector<WalkChild> wc(n_children);
-    int64_t equiv_nodes = 0;
+    if (donor_offsets[0] != 0) return set_err(ctx, GP_EINVAL, "donor_offsets[0] must be 0");
+    std::vector<IncJob> jobs(n_children);
+    std::vector<std::vector<uint8_t>> converted;   // donors given in postfix order
+    if (p->layout == GP_POSTFIX) converted.resize(n_children);
     for (int64_t i = 0; i < n_children; ++i) {
-        if (parent[i] < 0 || parent[i] >= p->n_trees)
-            return set_err(ctx, GP_EINVAL, "child " + std::to_string(i) + ": parent index out of range");
-        if (point[i] < 0 || point[i] >= p->tree_nodes[parent[i]])
-            return set_err(ctx, GP_EINVAL, "child " + std::to_string(i) + ": crossover point out of range");
-        auto it = p->spine_of.find(((uint64_t)parent[i] << 32) | (uint32_t)point[i]);
-        if (it == p->spine_of.end())
-            return set_err(ctx, GP_ENOTFOUND, "child " + std::to_string(i) + ": point " + std::to_string(point[i]) +
-                                                  " of tree " + std::to_string(parent[i]) + " was not recorded");
-        const SpineInfo& si = p->spines[it->second];
+        if (donor_offsets[i + 1] < donor_offsets[i]) return set_err(ctx, GP_EINVAL, "donor_offsets not increasing");
+        const uint8_t* d = donor_ops + donor_offsets[i];
         const int64_t nd = donor_offsets[i + 1] - donor_offsets[i];
-        if (nd < 1) return set_err(ctx, GP_EINVAL, "child " + std::to_string(i) + ": empty donor");
-        WalkChild& w = wc[i];
-        w.level_off = si.level_off;
-        w.n_levels = si.n_levels;
-        w.at_point = si.at_point;
-        w.rec_base = (int32_t)p->rec_base[parent[i]];
-        w.parent_slot = (int32_t)parent[i];
-        w.parent_tree = (int32_t)parent[i];
-        w.donor_slot = (int32_t)i;
-        w.donor_nodes = nd;
-        equiv_nodes += p->tree_nodes[parent[i]] - si.removed_nodes + nd;
+        if (p->layout == GP_POSTFIX) {
+            std::vector<int64_t> map;
+            std::string why;
+            if (!postfix_to_prefix(d, nd, p->n_inputs, &converted[i], &map, &why))
+                return set_err(ctx, GP_EINVAL, "donor " + std::to_string(i) + ": " + why);
+            d = converted[i].data();
+        }
+        jobs[i] = IncJob{p, parent[i], point[i], d, nd};
     }
-    // Inserted subtrees: evaluated on every case like any population.
-    Pop donors;
-    int layout = (flags & 0x100u) ? GP_POSTFIX : GP_PREFIX;
-    RC(build_population(ctx, p->vtype, layout, p->n_inputs, n_children, donor_ops, donor_offsets, nullptr, nullptr,
-                        0, &donors));
-    const int variant = choose_variant(ctx, p->vtype, cs, &donors);
-    if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits the donors");
-    const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
-    DevBuf d_wc, d_root, d_fit, d_stop, d_interp;
-    RC(upload(ctx, d_wc, wc.data(), wc.size() * sizeof(WalkChild)));
-    RC(dev_alloc(ctx, d_root, root_out ? (size_t)n_children * cs->stride * esz : 256));
-    RC(dev_alloc(ctx, d_fit, (size_t)n_children * 8));
-    RC(dev_alloc(ctx, d_stop, (size_t)n_children * 4));
-    RC(dev_alloc(ctx, d_interp, (size_t)n_children * 8));
+    IncOut io;
     int64_t launches = 0;
     HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    RC(enqueue_full(ctx, &donors, cases, cs, variant, false, false, ctx->stream, &launches));
-    WalkParams wp;
-    wp.children = d_wc.as<WalkChild>();
-    wp.levels = p->levels.as<SpineLvl>();
-    wp.inputs = cs->inputs.p;
-    wp.recs = p->recs.p;
-    wp.parent_vecs = p->vecs.p;
-    wp.parent_fit = p->fit.p;
-    wp.donor_vecs = donors.vecs.p;
-    wp.target = cs->target.p;
-    wp.root_out = root_out ? d_root.p : nullptr;
-    wp.fit_out = d_fit.p;
-    wp.stop_out = d_stop.as<int32_t>();
-    wp.interp_out = d_interp.as<int64_t>();
-    wp.stride = cs->stride;
-    wp.n_valid = cs->T;
-    wp.P = cs->P;
-    HIPC(ctx, launch_walk(p->vtype, wp, n_children, ctx->stream));
-    ++launches;
+    RC(enqueue_incremental(ctx, jobs, cases, cs, root_out != nullptr, ctx->stream, &io, &launches));
     HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-    RC(copy_out(ctx, root_out, d_root.p, n_children, cs->n_elems, cs->stride, esz, flags));
+    const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
+    RC(copy_out(ctx, root_out, io.root.p, n_children, cs->n_elems, cs->stride, esz, flags));
     if (fitness_out) {
         const hipMemcpyKind kind = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        HIPC(ctx, hipMemcpyAsync(fitness_out, d_fit.p, (size_t)n_children * 8, kind, ctx->stream));
+        HIPC(ctx, hipMemcpyAsync(fitness_out, io.fit.p, (size_t)n_children * 8, kind, ctx->stream));
     }
     std::vector<int32_t> stop(n_children);
     std::vector<int64_t> interp(n_children);
-    HIPC(ctx, hipMemcpyAsync(stop.data(), d_stop.p, (size_t)n_children * 4, hipMemcpyDeviceToHost, ctx->stream));
-    HIPC(ctx, hipMemcpyAsync(interp.data(), d_interp.p, (size_t)n_children * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipMemcpyAsync(stop.data(), io.stop.p, (size_t)n_children * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipMemcpyAsync(interp.data(), io.interp.p, (size_t)n_children * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.f;
     HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     int64_t interp_total = 0;
     for (int64_t i = 0; i < n_children; ++i) {
-        const SpineInfo& si = p->spines[p->spine_of[((uint64_t)parent[i] << 32) | (uint32_t)point[i]]];
         if (res) {
             res[i].stop_level = stop[i];
             res[i].reserved = 0;
-            res[i].child_nodes = p->tree_nodes[parent[i]] - si.removed_nodes + wc[i].donor_nodes;
+            res[i].child_nodes = io.child_nodes[i];
             res[i].interpreted_nodes = interp[i];
         }
         interp_total += interp[i];
@@ -908,10 +944,10 @@ int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, i
     if (st) {
         st->device_ms = ms;
         st->kernel_ms = 0;
-        st->equivalent_ops = equiv_nodes * cs->T;
+        st->equivalent_ops = io.equiv_nodes * cs->T;
         st->interpreted_ops = interp_total * cs->T;
         st->launches = launches;
-        st->variant = variant;
+        st->variant = -1;
         st->wall_ms = now_ms() - t0;
     }
     return GP_OK;
@@ -957,7 +993,7 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     std::vector<int64_t> chunk_sizes{p->chunk_nodes};
     if (p->auto_chunk && !p->host_ops.empty()) {
         const int64_t mean = p->total_nodes / std::max<int64_t>(1, p->n_trees);
-        std::vector<int64_t> cand = p->total_nodes > 200000000 ? std::vector<int64_t>{512, 1024, 2048}
+        std::vector<int64_t> cand = p->total_nodes > 200000000 ? std::vector<int64_t>{1024, 2048, 4096, 8192}
                                                                : std::vector<int64_t>{256, 512, 1024, 2048, 4096};
         chunk_sizes.clear();
         for (int64_t c : cand)
@@ -990,7 +1026,7 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
             const bool rec = !p->host_rec_points.empty() || !p->host_rec_offsets.empty();
             RC(build_population(ctx, p->vtype, p->layout, p->n_inputs, p->n_trees, p->host_ops.data(),
                                 p->host_offsets.data(), rec ? p->host_rec_points.data() : nullptr,
-                                rec ? p->host_rec_offsets.data() : nullptr, cn, q.get()));
+                                rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), ctx->stream));
             qp = q.get();
         }
         for (int v = 0; v < variant_count(); ++v) {

@@ -330,3 +330,39 @@ class Context:
         f = np.empty(n, np.float64 if vtype == GP_F32 else np.int64)
         self._check(lib().gp_fitness(self._h, cases, _ptr(outputs), n, 0, _ptr(f)))
         return f
+
+    # ------------------------------------------------------------ serving
+    def server_start(self, n_streams=4, max_batch_jobs=64, prep_threads=8, budget_bytes=0):
+        cfg = ServerCfg(n_streams, max_batch_jobs, prep_threads, 0, budget_bytes)
+        self._check(lib().gp_server_start(self._h, C.byref(cfg)))
+
+    def server_submit(self, kind, cases, ops, layout=GP_PREFIX, record_points=None, parent_ticket=0, point=0,
+                      keep_resident=False) -> int:
+        ops = _np(ops, np.uint8)
+        rp = _np(record_points, np.int64) if record_points is not None else None
+        job = Job(kind, layout, cases, ops.ctypes.data, len(ops), rp.ctypes.data if rp is not None else None,
+                  len(rp) if rp is not None else 0, parent_ticket, point, 1 if keep_resident else 0, 0)
+        t = I64(0)
+        self._check(lib().gp_server_submit(self._h, C.byref(job), C.byref(t)))
+        return t.value
+
+    def server_poll(self, ticket, vtype=GP_F32, n_cases=0, want_root=True):
+        """None while the job runs; then a dict with its result (and output vector)."""
+        r = JobResult()
+        root = None
+        if want_root and n_cases:
+            root = np.empty(n_cases if vtype == GP_F32 else (n_cases + 63) // 64,
+                            np.float32 if vtype == GP_F32 else np.uint64)
+        rc = lib().gp_server_poll(self._h, ticket, C.byref(r), _ptr(root))
+        if rc == GP_EBUSY:
+            return None
+        self._check(rc)
+        out = {k: getattr(r, k) for k, _ in r._fields_}
+        out["root"] = root
+        return out
+
+    def server_release(self, ticket):
+        self._check(lib().gp_server_release(self._h, ticket))
+
+    def server_stop(self):
+        self._check(lib().gp_server_stop(self._h))
