@@ -82,16 +82,17 @@ def cpu_baseline(pop, cases, kids, vtype, threads, budget_s=12.0):
     from concurrent.futures import ThreadPoolExecutor
     T = cases.T
     sizes = pop.sizes()
-    # bounded sample: trees in index order until ~budget_s of work at the
-    # oracle's ~10 ns per node and case
+    # bounded sample: the smallest trees, at least one per thread, until about
+    # budget_s of work per thread at the oracle's ~10 ns per node and case
     per_thread_ops = budget_s / 10e-9
     target = per_thread_ops * threads
     chosen, tot = [], 0
-    for i in range(pop.n_trees):
-        if tot >= target:
+    for i in np.argsort(sizes, kind="stable"):
+        if tot >= target and len(chosen) >= threads:
             break
-        chosen.append(i)
+        chosen.append(int(i))
         tot += int(sizes[i]) * T
+    chosen = np.array(chosen, np.int64)
     ops_done = 0
 
     def one(i):
@@ -106,9 +107,105 @@ def cpu_baseline(pop, cases, kids, vtype, threads, budget_s=12.0):
     with ThreadPoolExecutor(threads) as ex:
         ops_done = sum(ex.map(one, sorted(chosen, key=lambda i: -sizes[i])))
     dt = time.perf_counter() - t0
-    return {"value": ops_done / dt / 1e9, "unit": "GPop/s", "cores": threads, "kind": "oracle",
-            "sample": f"full evaluation of {len(chosen)} of the {pop.n_trees} trees "
+    return {"value": ops_done / dt / 1e9, "unit": "GPop/s", "cores": int(min(threads, len(chosen))),
+            "kind": "oracle",
+            "sample": f"full evaluation of the {len(chosen)} smallest of the {pop.n_trees} trees "
                       f"({int(sizes[chosen].sum())} nodes) on all {T} cases, {dt:.1f} s"}
+
+
+def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, load=0.8):
+    """Served mixed stream: full jobs (kept resident as parents) and
+    incremental children arriving over time; continuous batching in the
+    library's server.  Returns throughput and latency percentiles."""
+    t0 = time.perf_counter()
+    jobs = gen.served_stream(5, n_jobs)
+    log(f"[serve] generated {n_jobs} jobs in {time.perf_counter() - t0:.1f} s")
+    handles = {}
+    for j in jobs:
+        key = (j.vtype, j.T)
+        if key not in handles:
+            if j.vtype == gen.VT_BOOL:
+                bc = gen.bool_cases(j.T.bit_length() - 1)
+                handles[key] = ctx.set_cases(g.GP_BOOL, bc.inputs, bc.target, j.T)
+            else:
+                fc = gen.float_cases(j.T, j.T)
+                handles[key] = ctx.set_cases(g.GP_F32, fc.x, fc.y)
+    equiv = np.zeros(len(jobs), np.int64)
+    for i, j in enumerate(jobs):
+        if j.kind == 0:
+            equiv[i] = len(j.ops) * j.T
+        else:
+            p = jobs[j.parent].ops
+            equiv[i] = (len(p) - (gen.subtree_end(p, j.point) - j.point) + len(j.ops)) * j.T
+
+    def run(rate):
+        ctx.server_start(n_streams=4, max_batch_jobs=64, prep_threads=threads, budget_bytes=int(budget_gb * 2**30))
+        tickets = [0] * len(jobs)
+        done = {}
+        pending = []
+        t_start = time.perf_counter()
+        for i, j in enumerate(jobs):
+            if rate:
+                wait_s = j.arrival / rate - (time.perf_counter() - t_start)
+                while wait_s > 0:
+                    # collect finished jobs while waiting for the next arrival
+                    pending = [k for k in pending if not collect(k, done, tickets)]
+                    wait_s = j.arrival / rate - (time.perf_counter() - t_start)
+                    if wait_s > 0.0005:
+                        time.sleep(min(wait_s, 0.0005))
+            vt = g.GP_BOOL if j.vtype == gen.VT_BOOL else g.GP_F32
+            if j.kind == 0:
+                tickets[i] = ctx.server_submit(g.GP_JOB_FULL, handles[(j.vtype, j.T)], j.ops,
+                                               record_points=j.points, keep_resident=True)
+            else:
+                tickets[i] = ctx.server_submit(g.GP_JOB_INCREMENTAL, handles[(j.vtype, j.T)], j.ops,
+                                               parent_ticket=tickets[j.parent], point=j.point)
+            pending.append(i)
+        while pending:
+            pending = [k for k in pending if not collect(k, done, tickets)]
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t_start
+        for i, j in enumerate(jobs):
+            if j.kind == 0:
+                ctx.server_release(tickets[i])
+        ctx.server_stop()
+        return done, wall
+
+    def collect(i, done, tickets):
+        j = jobs[i]
+        r = ctx.server_poll(tickets[i], g.GP_BOOL if j.vtype == gen.VT_BOOL else g.GP_F32, j.T, want_root=False)
+        if r is None:
+            return False
+        done[i] = r
+        return True
+
+    def summary(done, wall):
+        lat_full = np.array([done[i]["latency_ms"] for i, j in enumerate(jobs) if j.kind == 0])
+        lat_inc = np.array([done[i]["latency_ms"] for i, j in enumerate(jobs) if j.kind == 1])
+        lat = np.array([done[i]["latency_ms"] for i in range(len(jobs))])
+        bad = sum(1 for r in done.values() if r["status"] != 0)
+        return {"jobs": len(jobs), "failed": bad, "wall_s": round(wall, 3),
+                "jobs_per_s": round(len(jobs) / wall, 1),
+                "equivalent_gpops": round(float(equiv.sum()) / wall / 1e9, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "full_p50_ms": round(float(np.percentile(lat_full, 50)), 3),
+                "full_p99_ms": round(float(np.percentile(lat_full, 99)), 3),
+                "incremental_p50_ms": round(float(np.percentile(lat_inc, 50)), 3),
+                "incremental_p99_ms": round(float(np.percentile(lat_inc, 99)), 3)}
+
+    done, wall = run(None)
+    sat = summary(done, wall)
+    log(f"[serve] saturation: {sat}")
+    rate = load * len(jobs) / wall / max(1e-9, jobs[-1].arrival / len(jobs))
+    done, wall = run(rate)
+    at_load = summary(done, wall)
+    log(f"[serve] at {load:.2f} x saturation: {at_load}")
+    for h in handles.values():
+        ctx.free(h)
+    return {"stream": f"{n_jobs} jobs, 30% full (resident parents, 3 recorded points) / 70% incremental; "
+                      "10..1e7 nodes log-uniform; float32 or Boolean 50/50; 256..4096 cases; donors 1..1e4 nodes, "
+                      "half neutral; budget 200 GB",
+            "saturation": sat, f"poisson_{load:.2f}x": at_load}
 
 
 def main():
@@ -124,7 +221,21 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="also time per-tree launches and full re-evaluation of the children")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="served-stream jobs (0 = skip serving)")
+    ap.add_argument("--chunk-nodes", type=int, default=0, help="fix the chunk size (0 = automatic / tuned)")
+    ap.add_argument("--variant", default="", help="fix the interpreter variant, e.g. f32_k4_s16")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 3}))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the evaluation path is not "
@@ -153,19 +264,23 @@ def main():
     if kids is not None:
         rp, ro = record_lists(pop.n_trees, kids)
         ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, record_points=rp,
-                                 record_offsets=ro)
+                                 record_offsets=ro, chunk_nodes=args.chunk_nodes)
     else:
-        ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs)
+        ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, chunk_nodes=args.chunk_nodes)
     load_s = time.perf_counter() - t1
     info = ctx.population_info(ph)
     log(f"[bench] loaded in {load_s:.1f} s: {info}")
 
     tuned = None
-    if not args.no_autotune:
+    if args.variant:
+        ctx.set_variant(g.variant_names().index(args.variant))
+        tuned = args.variant
+    elif not args.no_autotune:
         v, ms = ctx.autotune(ph, ch)
         tuned = g.variant_names()[v]
         log(f"[bench] autotune picked {tuned} ({ms:.2f} ms per full evaluation)")
 
+    final_info = ctx.population_info(ph)
     n_trees = pop.n_trees
     fdt = torch.float64 if vtype == g.GP_F32 else torch.int64
     fit_buf = torch.empty(n_trees, dtype=fdt, device="cuda:0")
@@ -239,6 +354,11 @@ def main():
             extra["children_full_reeval_gpops"] = int(childpop.sizes().sum()) * T / (st_c["device_ms"] * 1e-3) / 1e9
             ctx.free(cph)
 
+    serving = None
+    if args.serve_jobs > 0:
+        ctx.free(ph)
+        serving = serve_bench(ctx, g, args.serve_jobs, args.threads)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
@@ -258,12 +378,13 @@ def main():
         "vs_baseline": None,
         "dtype": "bool" if vtype == g.GP_BOOL else "f32",
         "data": "synthetic",
-        "config": {**desc, "chunk_nodes": info["chunk_nodes"], "variant": tuned, "parallelism": "single_gpu"},
+        "config": {**desc, "chunk_nodes": final_info["chunk_nodes"], "variant": tuned, "parallelism": "single_gpu"},
         "interpreted_gpops": round(interp_nodes * T / (ms_per_step * 1e-3) / 1e9, 3),
         "host_load_s": round(load_s, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
         **extra,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -317,3 +317,69 @@ def splice(parent: np.ndarray, c: int, donor: np.ndarray) -> np.ndarray:
     """child = parent[0:c] ++ donor ++ parent[end(c):]  (structural copy)."""
     e = subtree_end(parent, c)
     return np.concatenate([parent[:c], donor, parent[e:]]).astype(np.uint8)
+
+
+# ----------------------------------------------------------- served stream
+def bool_neutral_donor(rng: np.random.Generator, removed: np.ndarray, size: int, n_terms: int) -> np.ndarray:
+    """AND(S, OR(R, NAND(R, R))) = AND(S, true) = S for every input."""
+    r = max(1, (size - 4 - len(removed)) // 3) | 1
+    R = sized_tree(rng, r, n_terms)
+    return np.concatenate([[B_AND], removed, [B_OR], R, [B_NAND], R, R]).astype(np.uint8)
+
+
+@dataclass
+class ServedJob:
+    kind: int                 # 0 full, 1 incremental
+    vtype: int
+    T: int
+    ops: np.ndarray
+    arrival: float            # seconds at unit arrival rate
+    points: np.ndarray | None = None   # full: crossover points to keep caches for
+    parent: int = -1          # incremental: index of the parent job in the stream
+    point: int = 0
+    neutral: bool = False
+
+
+def served_stream(seed: int, n_jobs: int, full_frac: float = 0.3, node_lo: int = 10, node_hi: int = 10**7,
+                  t_choices=(256, 512, 1024, 2048, 4096), bool_frac: float = 0.5, donor_hi: int = 10**4,
+                  points_per_parent: int = 3) -> list:
+    """Jobs with exponential inter-arrival gaps (mean 1); a share full_frac of
+    full jobs (kept resident as parents, each with crossover points drawn
+    ahead), the rest incremental children of earlier parents with the same
+    value type and case count; half of the children's donors neutral.
+    Boolean jobs with T cases use k = log2(T) inputs."""
+    rng = rng_for(seed)
+    jobs: list = []
+    parents: dict = {}
+    t = 0.0
+    for i in range(n_jobs):
+        t += float(rng.exponential(1.0))
+        vtype = VT_BOOL if rng.random() < bool_frac else VT_F32
+        T = int(t_choices[int(rng.integers(len(t_choices)))])
+        k = T.bit_length() - 1
+        n_terms = k if vtype == VT_BOOL else 1
+        key = (vtype, T)
+        if key not in parents or rng.random() < full_frac:
+            n = int(log_uniform_odd(rng, node_lo, node_hi))
+            tree = sized_tree(rng, n, n_terms)
+            pts = np.unique(rng.integers(n, size=points_per_parent)).astype(np.int64)
+            jobs.append(ServedJob(0, vtype, T, tree, t, points=pts))
+            parents.setdefault(key, []).append(len(jobs) - 1)
+        else:
+            pj = parents[key][int(rng.integers(len(parents[key])))]
+            ptree = jobs[pj].ops
+            c = int(jobs[pj].points[int(rng.integers(len(jobs[pj].points)))])
+            m = int(log_uniform_odd(rng, 1, donor_hi))
+            neutral = rng.random() < 0.5
+            donor = None
+            if neutral:
+                e = subtree_end(ptree, c, max_len=max(1, m - 4))
+                if e > 0:
+                    S = ptree[c:e].copy()
+                    donor = neutral_donor(rng, S, m) if vtype == VT_F32 else bool_neutral_donor(rng, S, m, n_terms)
+                else:
+                    neutral = False
+            if donor is None:
+                donor = sized_tree(rng, m, n_terms)
+            jobs.append(ServedJob(1, vtype, T, donor, t, parent=pj, point=c, neutral=neutral))
+    return jobs

@@ -649,13 +649,19 @@ __global__ __launch_bounds__(256) void k_walk_bool(WalkParams p)
 }
 
 // ---------------------------------------------------------- variants
+// Interpreter variants: K test cases (words) per lane and S stack slots.
+// Fewer slots free registers for more resident waves; a population can use
+// a variant when its programs need at most S slots.
 static Variant g_variants[] = {
     {"f32_k1_s16", 0, 1, 16, (const void*)k_eval_f32<1, 16>, 0},
     {"f32_k2_s16", 0, 2, 16, (const void*)k_eval_f32<2, 16>, 0},
     {"f32_k4_s16", 0, 4, 16, (const void*)k_eval_f32<4, 16>, 0},
     {"f32_k8_s16", 0, 8, 16, (const void*)k_eval_f32<8, 16>, 0},
+    {"f32_k4_s10", 0, 4, 10, (const void*)k_eval_f32<4, 10>, 0},
+    {"f32_k8_s10", 0, 8, 10, (const void*)k_eval_f32<8, 10>, 0},
     {"bool_k1_s16", 1, 1, 16, (const void*)k_eval_bool<1, 16>, 0},
     {"bool_k2_s16", 1, 2, 16, (const void*)k_eval_bool<2, 16>, 0},
+    {"bool_k1_s10", 1, 1, 10, (const void*)k_eval_bool<1, 10>, 0},
 };
 
 int variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
