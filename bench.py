@@ -338,6 +338,19 @@ def main():
                 "gp_ops_per_s": round(total_nodes * T / (kernel_ms * 1e-3) / 1e12, 4)}
     if vtype == g.GP_BOOL:
         roofline["note"] = "Boolean: one 64-bit word op per function node per 64 cases"
+    # HBM bytes from the committed counter runs, valid only for the kernel source they were taken with
+    try:
+        import hashlib
+        rec = json.load(open(os.path.join(ROOT, "profiles", "counters.json")))
+        src = open(os.path.join(ROOT, "paper_2205_03251_amd", "csrc", "kernels.hip"), "rb").read()
+        same = (hashlib.sha256(src).hexdigest() == rec["kernels_hip_sha256"] and
+                rec["workload"] == desc["workload"] and rec["chunk_nodes"] == final_info["chunk_nodes"] and
+                rec["variant"] == tuned)
+        if same:
+            roofline["traffic"] = int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
+            roofline["valu_lane_op_frac_counters"] = rec["valu_lane_op_frac"]
+    except (OSError, KeyError, ValueError):
+        pass
 
     if args.compare:
         _, _, st_pt = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, per_tree=True)

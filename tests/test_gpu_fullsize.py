@@ -1,0 +1,127 @@
+"""Full-size parity on the GPU, in the launch configuration bench.py uses.
+
+Where the oracle is fast enough (Boolean, 64 cases) every tree is compared;
+for the large float populations a sample of trees / children is compared with
+the oracle one by one (several independent oracle instances in threads) and
+properties that hold at any size are checked for all of them.
+"""
+import math
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from paper_2205_03251_amd import gpeval as g
+from tests.scalar_ref import same_f32
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def test_boolean_parity6_full_size_all_trees(ctx):
+    pop = gen.sized_population(2, 1000, 10**3, 10**5, n_terms=6, vtype=gen.VT_BOOL, threads=16)
+    cases = gen.bool_cases(6)
+    ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, 64)
+    ph = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=6)
+    roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, 64)
+    want_r, want_f = oracle.eval_population_bool(pop, cases.inputs, cases.target, 64, threads=16)
+    assert np.array_equal(roots, want_r)
+    assert np.array_equal(fit, want_f)
+    r2, f2, _ = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, 64, per_tree=True)
+    assert np.array_equal(r2, roots) and np.array_equal(f2, fit)
+    say("boolean full size:", st)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_large_float_full_size_sampled(ctx):
+    pop = gen.sized_population(3, 1000, 10**4, 10**6, threads=16)
+    cases = gen.float_cases(3, 1024)
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, pop.ops, pop.offsets)
+    v, ms = ctx.autotune(ph, ch)
+    roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_F32, pop.n_trees, 1024)
+    say("large float:", g.variant_names()[v], ctx.population_info(ph)["chunk_nodes"], st)
+    sizes = pop.sizes()
+    order = np.argsort(sizes)
+    rng = np.random.default_rng(0)
+    sample = list(order[:10]) + list(rng.choice(pop.n_trees, 5, replace=False)) + [int(order[-1])]
+
+    def check(i):
+        with np.errstate(all="ignore"):
+            want = oracle.eval_f32(pop.tree(int(i)), cases.x)
+        return bool(same_f32(roots[i], want).all()), (oracle.fitness_f32(want, cases.y), fit[i])
+
+    with ThreadPoolExecutor(16) as ex:
+        res = list(ex.map(check, sample))
+    for i, (ok, (wf, gf)) in zip(sample, res):
+        assert ok, f"tree {i} differs"
+        assert wf == gf or (math.isnan(wf) and math.isnan(gf)), (i, wf, gf)
+    # properties for every tree: fitness from the returned outputs, same order
+    f_again = ctx.fitness(ch, g.GP_F32, roots)
+    assert all(a == b or (math.isnan(a) and math.isnan(b)) for a, b in zip(f_again, fit))
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_incremental_full_size_sampled(ctx):
+    parents = gen.sized_population(4, 500, 10**6, 10**7, threads=16)
+    cases = gen.float_cases(4, 1024)
+    kids = gen.crossover_children(40, parents, 500, donor_lo=1, donor_hi=10**4, neutral_frac=0.5)
+    pts = [[] for _ in range(parents.n_trees)]
+    for p, c in zip(kids.parent, kids.point):
+        pts[int(p)].append(int(c))
+    ro = np.cumsum([0] + [len(p) for p in pts]).astype(np.int64)
+    rp = np.array([c for p in pts for c in p], np.int64)
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, parents.ops, parents.offsets, record_points=rp, record_offsets=ro,
+                             chunk_nodes=8192)
+    proots, pfit, _ = ctx.evaluate_full(ph, ch, g.GP_F32, parents.n_trees, 1024)
+    roots, fit, info = ctx.evaluate_incremental(ph, ch, g.GP_F32, 1024, kids.parent, kids.point,
+                                                kids.donors.ops, kids.donors.offsets)
+    stop = info["stop_level"]
+    say("incremental full size: stops at point", int((stop == 0).sum()), "reached root", int((stop < 0).sum()))
+    # properties for all 500 children
+    for i in range(500):
+        p = int(kids.parent[i])
+        nd = len(kids.donors.tree(i))
+        if kids.neutral[i]:
+            assert stop[i] == 0
+        if stop[i] >= 0:
+            assert info["interpreted_nodes"][i] == nd + stop[i]
+            assert fit[i] == pfit[p] or (math.isnan(fit[i]) and math.isnan(pfit[p]))
+            assert same_f32(roots[i], proots[p]).all()
+        else:
+            assert info["interpreted_nodes"][i] > nd
+    # the oracle, one by one, on the children of the smallest parents (both kinds)
+    sizes = parents.sizes()
+    by_size = sorted(range(500), key=lambda i: sizes[int(kids.parent[i])])
+    sample = [i for i in by_size if kids.neutral[i]][:3] + [i for i in by_size if not kids.neutral[i]][:5]
+
+    def check(i):
+        P = parents.tree(int(kids.parent[i]))
+        with np.errstate(all="ignore"):
+            return oracle.incremental_f32(P, int(kids.point[i]), kids.donors.tree(i), cases.x, cases.y)
+
+    with ThreadPoolExecutor(8) as ex:
+        res = list(ex.map(check, sample))
+    for i, (w_root, w_lvl, w_int, w_fit) in zip(sample, res):
+        assert stop[i] == w_lvl, (i, stop[i], w_lvl)
+        assert info["interpreted_nodes"][i] == w_int
+        assert same_f32(roots[i], w_root).all()
+        assert fit[i] == w_fit or (math.isnan(fit[i]) and math.isnan(w_fit))
+    ctx.free(ph)
+    ctx.free(ch)
