@@ -34,6 +34,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    # the table-dispatch interpreter loops are generated source
+    subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_dispatch.py"),
+                           os.path.join(CSRC, "dispatch_f32.inc")])
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

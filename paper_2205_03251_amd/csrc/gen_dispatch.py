@@ -1,0 +1,224 @@
+"""Generate the gfx950 dispatch loop of the float32 interpreter.
+
+Writes dispatch_f32.inc: for each (K, S) in VARIANTS a device function
+run_f32_dispatch_K_S() holding one inline-asm block that runs one chunk's
+program and stores the chunk's value.
+
+Why assembly: the interpreter spends most of its scalar instructions on
+choosing the handler.  The compiler lowers a switch to a tree of compares
+(about nine compare-and-branch pairs per instruction word); here the word's
+10-bit key indexes a table of branches, so choosing the handler costs five
+scalar instructions and one branch.  Each handler ends with the code that
+fetches the next-but-one word and jumps to the next word's handler.
+
+Register plan (per lane): st[d][k] = v[V_ST + d*K + k], x[k] = v[V_X + k],
+five temporaries from V_T; scalar temporaries from S_BASE.  All of them are
+declared clobbered, so the compiler keeps its own values elsewhere.
+
+Memory: every load issued here is waited for inside the block (no value is
+left in flight when the block ends); PUSH, LOAD and STORE address exactly the
+slots the C++ interpreter addresses.  The word kEndWord ends every chunk and
+every other key leads to a handler that moves to the next word, so the loop
+always reaches the end of the chunk's code.
+
+The protected divide is the instruction sequence the compiler emits for an
+IEEE float division with denormals enabled (div_scale, rcp, two Newton steps,
+div_fmas, div_fixup), in the same order, followed by the select of 1.0 where
+|b| < 1e-6; the wait states between dependent instructions are the
+compiler's (rcp result used two instructions later, VCC written six
+instructions before div_fmas reads it, the mask written twelve instructions
+before the select reads it).
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+VARIANTS = [(4, 10), (8, 10)]
+V_ST = 16
+S_BASE = 64
+M_XX, M_XS, M_SX, M_SS, M_RS, M_PUSH, M_LOAD, M_STORE = range(8)
+END_KEY = 1 | (M_STORE << 2)          # kEndWord & 0x3ff
+TINY = 0x358637BD                     # 1e-6f
+
+
+def gen_one(K: int, S: int) -> str:
+    V_X = V_ST + S * K
+    V_T = V_X + K
+    n_vgpr = V_T + 5
+    s = {n: S_BASE + i for i, n in enumerate(
+        ["INS", "NXT", "OFF", "KEY", "T0", "T1", "TB0", "TB1", "TG0", "TG1", "A0", "A1", "J0", "J1", "P0", "P1",
+         "TINY"])}
+    assert s["TB0"] % 2 == 0 and s["TG0"] % 2 == 0 and s["A0"] % 2 == 0 and s["J0"] % 2 == 0 and s["P0"] % 2 == 0
+    sr = lambda n: f"s{s[n]}"
+    sp = lambda n: f"s[{s[n]}:{s[n] + 1}]"
+    st = lambda d, k: f"v{V_ST + d * K + k}"
+    xv = lambda k: f"v{V_X + k}"
+    T = [f"v{V_T + i}" for i in range(5)]
+    L = []
+    a = L.append
+
+    def tail():
+        a("  s_waitcnt lgkmcnt(0)")
+        a(f"  s_mov_b32 {sr('INS')}, {sr('NXT')}")
+        a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
+        a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+        a(f"  s_and_b32 {sr('KEY')}, {sr('INS')}, 0x3ff")
+        a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('KEY')}, {sr('TB0')}")
+        a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
+        a(f"  s_setpc_b64 {sp('TG0')}")
+
+    def op(f, dst, A, B):
+        if f == 0:
+            a(f"  v_add_f32_e32 {dst}, {A}, {B}")
+        elif f == 1:
+            a(f"  v_sub_f32_e32 {dst}, {A}, {B}")
+        elif f == 2:
+            a(f"  v_mul_f32_e32 {dst}, {A}, {B}")
+        else:
+            a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{B}|, {sr('TINY')}")
+            a(f"  v_div_scale_f32 {T[0]}, {sp('J0')}, {B}, {B}, {A}")
+            a(f"  v_rcp_f32_e32 {T[1]}, {T[0]}")
+            a(f"  v_div_scale_f32 {T[2]}, vcc, {A}, {B}, {A}")
+            a(f"  v_fma_f32 {T[3]}, -{T[0]}, {T[1]}, 1.0")
+            a(f"  v_fmac_f32_e32 {T[1]}, {T[3]}, {T[1]}")
+            a(f"  v_mul_f32_e32 {T[3]}, {T[2]}, {T[1]}")
+            a(f"  v_fma_f32 {T[4]}, -{T[0]}, {T[3]}, {T[2]}")
+            a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {T[1]}")
+            a(f"  v_fma_f32 {T[0]}, -{T[0]}, {T[3]}, {T[2]}")
+            a(f"  v_div_fmas_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
+            a(f"  v_div_fixup_f32 {T[0]}, {T[0]}, {B}, {A}")
+            a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {sp('P0')}")
+
+    lab = lambda name: f".Lgp{K}_{S}_{name}_%="
+    # ---------------------------------------------------------- entry
+    a(f"  s_mov_b32 {sr('TINY')}, {TINY:#x}")
+    for k in range(K):
+        a(f"  global_load_dword {xv(k)}, %[voff], %[inb] offset:{256 * k}")
+    a(f"  s_getpc_b64 {sp('TB0')}")
+    a(f"{lab('pc')}:")
+    a(f"  s_add_u32 {sr('TB0')}, {sr('TB0')}, {lab('tbl')}-{lab('pc')}")
+    a(f"  s_addc_u32 {sr('TB1')}, {sr('TB1')}, 0")
+    a(f"  s_mov_b32 {sr('OFF')}, 0")
+    a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+    a("  s_waitcnt vmcnt(0)")
+    tail()
+    # ---------------------------------------------------------- table
+    handlers = {}
+    for key in range(1024):
+        f, mode, d = key & 3, (key >> 2) & 7, key >> 5
+        name = None
+        if key == END_KEY:
+            name = "end"
+        elif d < S and mode in (M_XX, M_XS, M_SX):
+            name = f"h{key}"
+        elif d + 1 < S and mode in (M_SS, M_RS):
+            name = f"h{key}"
+        elif d < S and f == 0 and mode in (M_PUSH, M_LOAD, M_STORE):
+            name = f"h{key}"
+        else:
+            name = "end"          # never emitted by the compiler; ends the chunk
+        handlers[key] = name
+    a(f"{lab('tbl')}:")
+    for key in range(1024):
+        a(f"  s_branch {lab(handlers[key])}")
+    # ---------------------------------------------------------- handlers
+    for key in range(1024):
+        if handlers[key] == "end" or handlers[key] != f"h{key}":
+            continue
+        f, mode, d = key & 3, (key >> 2) & 7, key >> 5
+        a(f"{lab(handlers[key])}:")
+        if mode == M_XX:
+            for k in range(K):
+                op(f, st(d, k), xv(k), xv(k))
+        elif mode == M_XS:
+            for k in range(K):
+                op(f, st(d, k), xv(k), st(d, k))
+        elif mode == M_SX:
+            for k in range(K):
+                op(f, st(d, k), st(d, k), xv(k))
+        elif mode == M_SS:
+            for k in range(K):
+                op(f, st(d, k), st(d, k), st(d + 1, k))
+        elif mode == M_RS:
+            for k in range(K):
+                op(f, st(d, k), st(d + 1, k), st(d, k))
+        elif mode == M_PUSH:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_cmp_eq_u32 {sr('T0')}, 0")
+            a(f"  s_cbranch_scc1 {lab(f'px{d}')}")
+            a(f"  s_mul_i32 {sr('T0')}, {sr('T0')}, %[strideb]")
+            a(f"  s_add_u32 {sr('A0')}, %[inb_lo], {sr('T0')}")
+            a(f"  s_addc_u32 {sr('A1')}, %[inb_hi], 0")
+            for k in range(K):
+                a(f"  global_load_dword {st(d, k)}, %[voff], {sp('A0')} offset:{256 * k}")
+            a("  s_waitcnt vmcnt(0)")
+            tail()
+            a(f"{lab(f'px{d}')}:")
+            for k in range(K):
+                a(f"  v_mov_b32_e32 {st(d, k)}, {xv(k)}")
+        elif mode == M_LOAD:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 2")
+            a(f"  s_load_dword {sr('T1')}, %[cin], {sr('T0')}")
+            a("  s_waitcnt lgkmcnt(0)")
+            a(f"  s_mul_i32 {sr('A0')}, {sr('T1')}, %[strideb]")
+            a(f"  s_mul_hi_u32 {sr('A1')}, {sr('T1')}, %[strideb]")
+            a(f"  s_add_u32 {sr('A0')}, {sr('A0')}, %[vb_lo]")
+            a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, %[vb_hi]")
+            for k in range(K):
+                a(f"  global_load_dword {st(d, k)}, %[voff], {sp('A0')} offset:{256 * k}")
+            a("  s_waitcnt vmcnt(0)")
+        elif mode == M_STORE:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_mul_i32 {sr('A0')}, {sr('T0')}, %[strideb]")
+            a(f"  s_mul_hi_u32 {sr('A1')}, {sr('T0')}, %[strideb]")
+            a(f"  s_add_u32 {sr('A0')}, {sr('A0')}, %[rb_lo]")
+            a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, %[rb_hi]")
+            for k in range(K):
+                a(f"  global_store_dword %[voff], {st(d, k)}, {sp('A0')} offset:{256 * k}")
+        tail()
+    # ---------------------------------------------------------- end
+    a(f"{lab('end')}:")
+    a("  s_waitcnt lgkmcnt(0)")
+    for k in range(K):
+        a(f"  global_store_dword %[voff], {st(0, k)}, %[outb] offset:{256 * k}")
+    a("  s_waitcnt vmcnt(0)")
+
+    body = "\n".join(f'        "{line}\\n"' for line in L)
+    vclob = ", ".join(f'"v{i}"' for i in range(V_ST, n_vgpr))
+    sclob = ", ".join(f'"s{s[n]}"' for n in s)
+    return f"""
+// K = {K} cases per lane, S = {S} stack slots: v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(s) - 1}.
+__device__ __forceinline__ void run_f32_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const float* inb,
+                                                     const float* vb, float* rb, const GP_CONST int32_t* cin,
+                                                     uint32_t strideb, float* outb, uint32_t voff)
+{{
+    const uint64_t inb64 = (uint64_t)inb, vb64 = (uint64_t)vb, rb64 = (uint64_t)rb;
+    asm volatile(
+{body}
+        :
+        : [code] "s"(code), [inb] "s"(inb), [inb_lo] "s"((uint32_t)inb64), [inb_hi] "s"((uint32_t)(inb64 >> 32)),
+          [vb_lo] "s"((uint32_t)vb64), [vb_hi] "s"((uint32_t)(vb64 >> 32)),
+          [rb_lo] "s"((uint32_t)rb64), [rb_hi] "s"((uint32_t)(rb64 >> 32)), [cin] "s"(cin),
+          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff)
+        : "memory", "vcc", "scc", {sclob},
+          {vclob});
+}}
+"""
+
+
+def main(out_path: str) -> None:
+    parts = ["// Generated by gen_dispatch.py; do not edit.\n#pragma once\n"]
+    for K, S in VARIANTS:
+        parts.append(gen_one(K, S))
+    text = "".join(parts)
+    old = open(out_path).read() if os.path.exists(out_path) else None
+    if old != text:
+        with open(out_path, "w") as fh:
+            fh.write(text)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                              "dispatch_f32.inc"))

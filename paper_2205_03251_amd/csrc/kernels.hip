@@ -256,6 +256,57 @@ __global__ __launch_bounds__(64) void k_eval_f32(EvalParams p)
     }
 }
 
+// -------------------------------- float interpreter, table dispatch
+// Same work items, chunk hand-off and memory layout as k_eval_f32; the
+// chunk's program runs in the generated dispatch loop (gen_dispatch.py),
+// which chooses each handler through a branch table.
+#include "dispatch_f32.inc"
+
+template <int K, int S>
+__device__ __forceinline__ void run_f32_dispatch(const GP_CONST uint32_t* code, const float* inb, const float* vb,
+                                                 float* rb, const GP_CONST int32_t* cin, uint32_t strideb,
+                                                 float* outb, uint32_t voff)
+{
+    if constexpr (K == 4 && S == 10) run_f32_dispatch_4_10(code, inb, vb, rb, cin, strideb, outb, voff);
+    else if constexpr (K == 8 && S == 10) run_f32_dispatch_8_10(code, inb, vb, rb, cin, strideb, outb, voff);
+    else static_assert(K == 4 && S == 10, "no generated dispatch loop for this K and S");
+}
+
+template <int K, int S>
+__global__ __launch_bounds__(64) void k_eval_f32_tbl(EvalParams p)
+{
+    const int lane = threadIdx.x;
+    const uint32_t voff = (uint32_t)lane * 4u;
+    const uint32_t strideb = (uint32_t)(p.stride * 4);
+    for (;;) {
+        unsigned int it = 0;
+        if (lane == 0) it = atomicAdd(p.cursor, 1u);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if ((int64_t)it >= p.n_items) break;
+        const int64_t item = cst(p.items)[it];
+        int32_t c = (int32_t)(item >> 16);
+        const int32_t s = (int32_t)(item & 0xffff);
+        const int64_t case0 = (int64_t)s * (kWave * K);
+        const float* inb = (const float*)p.inputs + case0;
+        const float* vb = (const float*)p.vecs + case0;
+        for (;;) {
+            const ChunkHdr ch = load_chunk(cst(p.chunks) + c);
+            float* rb = (float*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
+            float* outb = (float*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
+            run_f32_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
+                                   outb, voff);
+            if (ch.parent < 0) break;
+            int old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(p.pending + (int64_t)ch.parent * p.n_slices + s, -1,
+                                             __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old != 1) break;
+            c = ch.parent;
+        }
+    }
+}
+
 // ------------------------------------------------- Boolean interpreter
 struct ItemBool {
     const uint64_t* lin;     // staged input words in LDS, this lane's first word
@@ -659,6 +710,8 @@ static Variant g_variants[] = {
     {"f32_k8_s16", 0, 8, 16, (const void*)k_eval_f32<8, 16>, 0},
     {"f32_k4_s10", 0, 4, 10, (const void*)k_eval_f32<4, 10>, 0},
     {"f32_k8_s10", 0, 8, 10, (const void*)k_eval_f32<8, 10>, 0},
+    {"f32t_k4_s10", 0, 4, 10, (const void*)k_eval_f32_tbl<4, 10>, 0},
+    {"f32t_k8_s10", 0, 8, 10, (const void*)k_eval_f32_tbl<8, 10>, 0},
     {"bool_k1_s16", 1, 1, 16, (const void*)k_eval_bool<1, 16>, 0},
     {"bool_k2_s16", 1, 2, 16, (const void*)k_eval_bool<2, 16>, 0},
     {"bool_k1_s10", 1, 1, 10, (const void*)k_eval_bool<1, 10>, 0},

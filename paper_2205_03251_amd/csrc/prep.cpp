@@ -313,6 +313,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
             if (it != rec_of.end()) out->code.push_back(ins_word(0, M_STORE, d, (uint32_t)it->second));
             fr.pop_back();
         }
+        out->code.push_back(kEndWord);
         ch.code_len = (int64_t)out->code.size() - ch.code_off;
         if (ch.inputs.size() > kMaxPayload) {
             if (why) *why = "chunk reads too many child chunks";

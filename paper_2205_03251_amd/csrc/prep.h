@@ -36,6 +36,9 @@ constexpr int kMaxInputs = 64;
 //   PUSH  st[d] = input[payload]
 //   LOAD  st[d] = output of child chunk number `payload` of this chunk
 //   STORE record st[d] into parent-cache slot rec_base + payload
+// Every chunk's code ends with the word kEndWord (mode STORE, f = 1, d = 0),
+// which no other instruction uses: the register-indexed dispatch loop stops
+// there; the counted loop treats it as a no-op.
 enum Mode : uint32_t { M_XX = 0, M_XS = 1, M_SX = 2, M_SS = 3, M_RS = 4, M_PUSH = 5, M_LOAD = 6, M_STORE = 7 };
 constexpr int kPayloadShift = 10;
 constexpr uint32_t kKeyMask = 0x3ffu;
@@ -46,6 +49,7 @@ inline uint32_t ins_word(uint32_t f, uint32_t mode, uint32_t d, uint32_t payload
 {
     return f | (mode << 2) | (d << 5) | (payload << kPayloadShift);
 }
+constexpr uint32_t kEndWord = 1u | (7u << 2);
 
 struct Chunk {
     int64_t code_off = 0;        // offset in TreeProg::code

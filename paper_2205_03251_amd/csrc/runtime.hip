@@ -122,6 +122,9 @@ int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
     int wantK = 1;
     if (vtype == GP_F32) wantK = cs->n_elems <= 64 ? 1 : cs->n_elems <= 128 ? 2 : 4;
     else wantK = cs->n_elems <= 64 ? 1 : 2;
+    // prefer the table-dispatch interpreter (name "f32t_...") when the stack fits
+    for (int v = 0; v < variant_count(); ++v)
+        if (ok(v) && vt[v].K == wantK && vt[v].name[3] == 't') return v;
     for (int v = 0; v < variant_count(); ++v)
         if (ok(v) && vt[v].K == wantK) return v;
     for (int v = 0; v < variant_count(); ++v)

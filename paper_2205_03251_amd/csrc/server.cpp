@@ -120,6 +120,8 @@ int choose_for(Server* S, int vtype, const CaseSet* cs, const Pop* p)
     if (ok(S->forced_variant)) return S->forced_variant;
     int wantK = vtype == GP_F32 ? (cs->n_elems <= 64 ? 1 : cs->n_elems <= 128 ? 2 : 4) : (cs->n_elems <= 64 ? 1 : 2);
     for (int v = 0; v < variant_count(); ++v)
+        if (ok(v) && vt[v].K == wantK && vt[v].name[3] == 't') return v;
+    for (int v = 0; v < variant_count(); ++v)
         if (ok(v) && vt[v].K == wantK) return v;
     for (int v = 0; v < variant_count(); ++v)
         if (ok(v)) return v;

@@ -225,8 +225,9 @@ def record_lists(parents, children):
     return flat, offs
 
 
-@pytest.mark.parametrize("chunk_nodes,T", [(64, 100), (4096, 1024), (0, 48)])
-def test_incremental_float_matches_oracle(ctx, chunk_nodes, T):
+@pytest.mark.parametrize("chunk_nodes,T,variant", [(64, 100, ""), (4096, 1024, ""), (0, 48, ""),
+                                                   (64, 300, "f32t_k4_s10"), (2048, 1024, "f32t_k8_s10")])
+def test_incremental_float_matches_oracle(ctx, chunk_nodes, T, variant):
     parents = gen.sized_population(31, 12, 101, 20001)
     children = make_children(parents, 32, 60)
     cases = gen.float_cases(33, T)
@@ -234,9 +235,15 @@ def test_incremental_float_matches_oracle(ctx, chunk_nodes, T):
     ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
     ph = ctx.load_population(g.GP_F32, parents.ops, parents.offsets, record_points=rp, record_offsets=ro,
                              chunk_nodes=chunk_nodes)
-    proots, pfit, _ = ctx.evaluate_full(ph, ch, g.GP_F32, parents.n_trees, T)
+    if variant:
+        assert ctx.population_info(ph)["max_stack"] <= 10
+        ctx.set_variant(g.variant_names().index(variant))
+    proots, pfit, st = ctx.evaluate_full(ph, ch, g.GP_F32, parents.n_trees, T)
+    if variant:
+        assert g.variant_names()[st["variant"]] == variant
     roots, fit, info = ctx.evaluate_incremental(ph, ch, g.GP_F32, T, children.parent, children.point,
                                                 children.donors.ops, children.donors.offsets)
+    ctx.set_variant(-1)
     stops = []
     for i in range(len(children.parent)):
         P = parents.tree(int(children.parent[i]))

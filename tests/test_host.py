@@ -16,6 +16,7 @@ from tests.scalar_ref import same_f32
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 M_XX, M_XS, M_SX, M_SS, M_RS, M_PUSH, M_LOAD, M_STORE = range(8)
+END_WORD = 1 | (7 << 2)
 
 
 def test_library_exports_every_declared_symbol():
@@ -95,7 +96,12 @@ def emulate(prog: g.Program, inputs, vtype):
                 child = prog.inputs[k][pl]
                 assert prog.chunks[child, 2] == k
                 st[d] = vals[child]
+            elif mode == M_STORE and f == 1:
+                assert w == END_WORD and d == 0
+                continue
             assert d < prog.max_stack
+        assert int(prog.code[off + ln - 1]) == END_WORD          # every chunk ends with END
+        assert sum(1 for w in prog.code[off:off + ln] if int(w) == END_WORD) == 1
         vals[k] = st[0]
     assert prog.chunks[-1, 2] == -1
     return vals[len(prog.chunks) - 1]
