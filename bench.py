@@ -286,9 +286,12 @@ def main():
     fit_buf = torch.empty(n_trees, dtype=fdt, device="cuda:0")
     total_nodes = int(pop.sizes().sum())
 
+    used = {}
+
     def step():
         _, _, st_full = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, device=True, async_=True,
                                           fit_buf=fit_buf)
+        used["variant"] = g.variant_names()[st_full["variant"]]
         if kids is None:
             return st_full, None
         _, _, st_inc = ctx.evaluate_incremental(ph, ch, vtype, T, kids.parent, kids.point, kids.donors.ops,
@@ -342,10 +345,12 @@ def main():
     try:
         import hashlib
         rec = json.load(open(os.path.join(ROOT, "profiles", "counters.json")))
-        src = open(os.path.join(ROOT, "paper_2205_03251_amd", "csrc", "kernels.hip"), "rb").read()
-        same = (hashlib.sha256(src).hexdigest() == rec["kernels_hip_sha256"] and
+        h = hashlib.sha256()
+        for f in rec["kernel_source_files"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        same = (h.hexdigest() == rec["kernel_source_sha256"] and
                 rec["workload"] == desc["workload"] and rec["chunk_nodes"] == final_info["chunk_nodes"] and
-                rec["variant"] == tuned)
+                rec["variant"] == used.get("variant", tuned))
         if same:
             roofline["traffic"] = int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
             roofline["valu_lane_op_frac_counters"] = rec["valu_lane_op_frac"]
@@ -391,7 +396,8 @@ def main():
         "vs_baseline": None,
         "dtype": "bool" if vtype == g.GP_BOOL else "f32",
         "data": "synthetic",
-        "config": {**desc, "chunk_nodes": final_info["chunk_nodes"], "variant": tuned, "parallelism": "single_gpu"},
+        "config": {**desc, "chunk_nodes": final_info["chunk_nodes"], "variant": used.get("variant", tuned),
+                   "parallelism": "single_gpu"},
         "interpreted_gpops": round(interp_nodes * T / (ms_per_step * 1e-3) / 1e9, 3),
         "host_load_s": round(load_s, 2),
         "roofline": roofline,

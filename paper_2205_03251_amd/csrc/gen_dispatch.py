@@ -12,8 +12,14 @@ scalar instructions and one branch.  Each handler ends with the code that
 fetches the next-but-one word and jumps to the next word's handler.
 
 Register plan (per lane): st[d][k] = v[V_ST + d*K + k], x[k] = v[V_X + k],
-five temporaries from V_T; scalar temporaries from S_BASE.  All of them are
-declared clobbered, so the compiler keeps its own values elsewhere.
+q[k] = PDIV(x[k], x[k]) at v[V_Q + k], five temporaries from V_T; scalar
+temporaries from S_BASE, and per k the lane mask |x[k]| < 1e-6.  All of them
+are declared clobbered, so the compiler keeps its own values elsewhere.
+
+Work that depends on x alone does not change while a chunk runs, so it is
+done once per chunk: the protected quotient x/x (a handler whose operands
+are both x then only copies it) and the protection mask used when x is the
+divisor.
 
 Memory: every load issued here is waited for inside the block (no value is
 left in flight when the block ends); PUSH, LOAD and STORE address exactly the
@@ -44,11 +50,15 @@ TINY = 0x358637BD                     # 1e-6f
 
 def gen_one(K: int, S: int) -> str:
     V_X = V_ST + S * K
-    V_T = V_X + K
+    V_Q = V_X + K
+    V_T = V_Q + K
     n_vgpr = V_T + 5
-    s = {n: S_BASE + i for i, n in enumerate(
-        ["INS", "NXT", "OFF", "KEY", "T0", "T1", "TB0", "TB1", "TG0", "TG1", "A0", "A1", "J0", "J1", "P0", "P1",
-         "TINY"])}
+    names = ["INS", "NXT", "OFF", "KEY", "T0", "T1", "TB0", "TB1", "TG0", "TG1", "A0", "A1", "J0", "J1", "P0", "P1",
+             "TINY", "PAD"]
+    for k in range(K):
+        names += [f"XM{k}_0", f"XM{k}_1"]
+    s = {n: S_BASE + i for i, n in enumerate(names)}
+    assert all(s[f"XM{k}_0"] % 2 == 0 for k in range(K))
     assert s["TB0"] % 2 == 0 and s["TG0"] % 2 == 0 and s["A0"] % 2 == 0 and s["J0"] % 2 == 0 and s["P0"] % 2 == 0
     sr = lambda n: f"s{s[n]}"
     sp = lambda n: f"s[{s[n]}:{s[n] + 1}]"
@@ -68,7 +78,7 @@ def gen_one(K: int, S: int) -> str:
         a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
         a(f"  s_setpc_b64 {sp('TG0')}")
 
-    def op(f, dst, A, B):
+    def op(f, dst, A, B, mask=None):
         if f == 0:
             a(f"  v_add_f32_e32 {dst}, {A}, {B}")
         elif f == 1:
@@ -76,7 +86,9 @@ def gen_one(K: int, S: int) -> str:
         elif f == 2:
             a(f"  v_mul_f32_e32 {dst}, {A}, {B}")
         else:
-            a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{B}|, {sr('TINY')}")
+            if mask is None:
+                a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{B}|, {sr('TINY')}")
+                mask = sp('P0')
             a(f"  v_div_scale_f32 {T[0]}, {sp('J0')}, {B}, {B}, {A}")
             a(f"  v_rcp_f32_e32 {T[1]}, {T[0]}")
             a(f"  v_div_scale_f32 {T[2]}, vcc, {A}, {B}, {A}")
@@ -88,7 +100,7 @@ def gen_one(K: int, S: int) -> str:
             a(f"  v_fma_f32 {T[0]}, -{T[0]}, {T[3]}, {T[2]}")
             a(f"  v_div_fmas_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
             a(f"  v_div_fixup_f32 {T[0]}, {T[0]}, {B}, {A}")
-            a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {sp('P0')}")
+            a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {mask}")
 
     lab = lambda name: f".Lgp{K}_{S}_{name}_%="
     # ---------------------------------------------------------- entry
@@ -102,6 +114,11 @@ def gen_one(K: int, S: int) -> str:
     a(f"  s_mov_b32 {sr('OFF')}, 0")
     a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
     a("  s_waitcnt vmcnt(0)")
+    xm = lambda k: f"s[{s[f'XM{k}_0']}:{s[f'XM{k}_1']}]"
+    for k in range(K):
+        a(f"  v_cmp_lt_f32_e64 {xm(k)}, |{xv(k)}|, {sr('TINY')}")
+    for k in range(K):
+        op(3, f"v{V_Q + k}", xv(k), xv(k), mask=xm(k))
     tail()
     # ---------------------------------------------------------- table
     handlers = {}
@@ -128,7 +145,10 @@ def gen_one(K: int, S: int) -> str:
             continue
         f, mode, d = key & 3, (key >> 2) & 7, key >> 5
         a(f"{lab(handlers[key])}:")
-        if mode == M_XX:
+        if mode == M_XX and f == 3:
+            for k in range(K):
+                a(f"  v_mov_b32_e32 {st(d, k)}, v{V_Q + k}")
+        elif mode == M_XX:
             for k in range(K):
                 op(f, st(d, k), xv(k), xv(k))
         elif mode == M_XS:
@@ -136,7 +156,7 @@ def gen_one(K: int, S: int) -> str:
                 op(f, st(d, k), xv(k), st(d, k))
         elif mode == M_SX:
             for k in range(K):
-                op(f, st(d, k), st(d, k), xv(k))
+                op(f, st(d, k), st(d, k), xv(k), mask=xm(k))
         elif mode == M_SS:
             for k in range(K):
                 op(f, st(d, k), st(d, k), st(d + 1, k))

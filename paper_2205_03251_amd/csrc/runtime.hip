@@ -87,7 +87,10 @@ Plan::~Plan()
 }
 
 // ---------------------------------------------------------- heuristics
-int compile_stack_slots() { return 16; }
+// Programs are compiled for 10 stack slots, so every interpreter variant
+// (10 or 16 slots) can run them; the rare subtree needing more becomes a
+// chunk of its own.
+int compile_stack_slots() { return 10; }
 
 int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_t T)
 {
