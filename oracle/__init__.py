@@ -42,8 +42,11 @@ L = C.c_int64
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        h = C.CDLL(_LIB)
+        path = os.environ.get("GPE_ORACLE_LIB")     # a planted-mistake build, in tests only
+        if not path:
+            build(force=False)
+            path = _LIB
+        h = C.CDLL(path)
         h.orc_validate.argtypes = [u8p, L, C.c_int]
         h.orc_subtree_end.argtypes = [u8p, L, L]
         h.orc_subtree_end.restype = L

@@ -36,6 +36,7 @@ def test_validate_corpus():
     assert not oracle.validate(t(A, X))             # truncated
     assert not oracle.validate(t(X, X))             # trailing node
     assert not oracle.validate(t(A, X, X, X))       # trailing node after a full tree
+    assert not oracle.validate(t(X, A, X))          # final count is right, but the tree ends at node 0
     assert not oracle.validate(t(0x84, X, X))       # unknown function
     assert not oracle.validate(t(A, X, 1))          # terminal index >= n_inputs
     assert oracle.validate(t(A, X, 1), n_inputs=2)
