@@ -4,7 +4,8 @@ Each case below plants one mistake in a copy of oracle/oracle.c (a dropped
 term, a wrong sign, a transposed operand, a wrong threshold, a different
 reduction order, a wrong stop rule, ...), builds it on the CPU, points the
 `oracle` module at it and runs tests/test_oracle.py in a subprocess: at least
-one pin must fail.  The unmodified oracle passes the same run.
+one pin must fail.  The unmodified oracle passes the same run.  The
+hand-worked fixtures (tests/test_golden.py) run alongside the pins.
 """
 import os
 import subprocess
@@ -48,7 +49,7 @@ def run_pins(lib_path):
     env = dict(os.environ)
     env["GPE_ORACLE_LIB"] = lib_path
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")], cwd=ROOT, env=env,
+                        os.path.join(ROOT, "tests", "test_oracle.py"), os.path.join(ROOT, "tests", "test_golden.py")], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return r.returncode
 
