@@ -12,14 +12,16 @@ scalar instructions and one branch.  Each handler ends with the code that
 fetches the next-but-one word and jumps to the next word's handler.
 
 Register plan (per lane): st[d][k] = v[V_ST + d*K + k], x[k] = v[V_X + k],
-q[k] = PDIV(x[k], x[k]) at v[V_Q + k], five temporaries from V_T; scalar
-temporaries from S_BASE, and per k the lane mask |x[k]| < 1e-6.  All of them
-are declared clobbered, so the compiler keeps its own values elsewhere.
+q[k] = PDIV(x[k], x[k]) at v[V_Q + k], the refined reciprocal of x[k] at
+v[V_Y + k], five temporaries from V_T; scalar temporaries from S_BASE, per k
+the lane mask |x[k]| < 1e-6, the bounds of the short divides and a flag word
+saying which short divides this chunk's x allows.  All of them are declared
+clobbered, so the compiler keeps its own values elsewhere.
 
 Work that depends on x alone does not change while a chunk runs, so it is
 done once per chunk: the protected quotient x/x (a handler whose operands
-are both x then only copies it) and the protection mask used when x is the
-divisor.
+are both x then only copies it), the protection mask used when x is the
+divisor, the refined reciprocal of x and the range flags below.
 
 Memory: every load issued here is waited for inside the block (no value is
 left in flight when the block ends); PUSH, LOAD and STORE address exactly the
@@ -34,6 +36,25 @@ div_fmas, div_fixup), in the same order, followed by the select of 1.0 where
 compiler's (rcp result used two instructions later, VCC written six
 instructions before div_fmas reads it, the mask written twelve instructions
 before the select reads it).
+
+Short divides.  When neither operand nor any intermediate of that sequence
+can leave the normal range, div_scale returns its operand unchanged with VCC
+clear, div_fmas is a plain fma and div_fixup returns its first operand: the
+remaining steps (rcp, the two Newton steps, the final fma) give the same bits.
+Two handlers use this:
+  * stack / x: the refined reciprocal of x is hoisted with the other x-only
+    work.  Allowed when every lane's unprotected x lies in [1e-6, 2^20] (a
+    per-chunk flag) and every numerator lies in [2^-90, 2^70]: the quotient
+    stays in [2^-110, 2^90], each residual a - x*q is a multiple of 2^-137 and
+    so exact, and the exponent gap stays below the 96 at which div_scale
+    would rescale.
+  * x / stack: allowed when every lane's x lies in [2^-60, 2^60] (a per-chunk
+    flag) and every divisor satisfies |b| <= 2^64: an unprotected divisor is
+    then in [1e-6, 2^64], the quotient in [2^-124, 2^80] and the reciprocal
+    normal.
+Either check is made over all lanes and slots of the wave (a scalar branch);
+any value outside the ranges, NaN and infinities included, sends the whole
+wave through the full sequence, and protected lanes take 1.0 either way.
 """
 from __future__ import annotations
 
@@ -46,20 +67,23 @@ S_BASE = 64
 M_XX, M_XS, M_SX, M_SS, M_RS, M_PUSH, M_LOAD, M_STORE = range(8)
 END_KEY = 1 | (M_STORE << 2)          # kEndWord & 0x3ff
 TINY = 0x358637BD                     # 1e-6f
+P2 = lambda e: (127 + e) << 23        # bit pattern of 2^e (normal range)
 
 
 def gen_one(K: int, S: int) -> str:
     V_X = V_ST + S * K
     V_Q = V_X + K
-    V_T = V_Q + K
+    V_Y = V_Q + K
+    V_T = V_Y + K
     n_vgpr = V_T + 5
-    names = ["INS", "NXT", "OFF", "KEY", "T0", "T1", "TB0", "TB1", "TG0", "TG1", "A0", "A1", "J0", "J1", "P0", "P1",
-             "TINY", "PAD"]
-    for k in range(K):
-        names += [f"XM{k}_0", f"XM{k}_1"]
+    names = []
+    for p in ["TB", "TG", "A", "J", "P"] + [f"XM{k}" for k in range(K)]:
+        names += [f"{p}0", f"{p}1"]                   # pairs first: all even-aligned
+    names += ["INS", "NXT", "OFF", "T0", "T1", "TINY", "FLG", "LOSX", "HISX", "HIXS"]
     s = {n: S_BASE + i for i, n in enumerate(names)}
-    assert all(s[f"XM{k}_0"] % 2 == 0 for k in range(K))
-    assert s["TB0"] % 2 == 0 and s["TG0"] % 2 == 0 and s["A0"] % 2 == 0 and s["J0"] % 2 == 0 and s["P0"] % 2 == 0
+    assert S_BASE % 2 == 0 and S_BASE + len(names) <= 100
+    for k in range(K):
+        s[f"XM{k}"] = s[f"XM{k}0"]
     sr = lambda n: f"s{s[n]}"
     sp = lambda n: f"s[{s[n]}:{s[n] + 1}]"
     st = lambda d, k: f"v{V_ST + d * K + k}"
@@ -73,8 +97,8 @@ def gen_one(K: int, S: int) -> str:
         a(f"  s_mov_b32 {sr('INS')}, {sr('NXT')}")
         a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
         a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
-        a(f"  s_and_b32 {sr('KEY')}, {sr('INS')}, 0x3ff")
-        a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('KEY')}, {sr('TB0')}")
+        a(f"  s_and_b32 {sr('TG0')}, {sr('INS')}, 0x3ff")
+        a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
         a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
         a(f"  s_setpc_b64 {sp('TG0')}")
 
@@ -114,11 +138,41 @@ def gen_one(K: int, S: int) -> str:
     a(f"  s_mov_b32 {sr('OFF')}, 0")
     a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
     a("  s_waitcnt vmcnt(0)")
-    xm = lambda k: f"s[{s[f'XM{k}_0']}:{s[f'XM{k}_1']}]"
+    xm = lambda k: sp(f"XM{k}")
+    yv = lambda k: f"v{V_Y + k}"
     for k in range(K):
         a(f"  v_cmp_lt_f32_e64 {xm(k)}, |{xv(k)}|, {sr('TINY')}")
     for k in range(K):
         op(3, f"v{V_Q + k}", xv(k), xv(k), mask=xm(k))
+    # refined reciprocal of x (the division sequence's rcp and first Newton
+    # step, with div_scale's identity case): used by the short stack / x
+    for k in range(K):
+        a(f"  v_rcp_f32_e32 {yv(k)}, {xv(k)}")
+    for k in range(K):
+        a(f"  v_fma_f32 {T[0]}, -{xv(k)}, {yv(k)}, 1.0")
+        a(f"  v_fmac_f32_e32 {yv(k)}, {T[0]}, {yv(k)}")
+    a(f"  s_mov_b32 {sr('LOSX')}, {P2(-90):#x}")
+    a(f"  s_mov_b32 {sr('HISX')}, {P2(70):#x}")
+    a(f"  s_mov_b32 {sr('HIXS')}, {P2(64):#x}")
+    # FLG bit 0: every lane has |x| <= 2^20; bit 1: every lane has x in [2^-60, 2^60]
+    a(f"  s_mov_b32 {sr('T0')}, {P2(20):#x}")
+    a("  s_mov_b64 vcc, exec")
+    for k in range(K):
+        a(f"  v_cmp_le_f32_e64 {sp('P0')}, |{xv(k)}|, {sr('T0')}")
+        a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
+    a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
+    a(f"  s_cselect_b32 {sr('FLG')}, 0, 1")
+    a(f"  s_mov_b32 {sr('T0')}, {P2(-60):#x}")
+    a(f"  s_mov_b32 {sr('T1')}, {P2(60):#x}")
+    a("  s_mov_b64 vcc, exec")
+    for k in range(K):
+        a(f"  v_cmp_ge_f32_e64 {sp('P0')}, |{xv(k)}|, {sr('T0')}")
+        a(f"  v_cmp_le_f32_e64 {sp('J0')}, |{xv(k)}|, {sr('T1')}")
+        a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
+        a(f"  s_and_b64 vcc, vcc, {sp('J0')}")
+    a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
+    a(f"  s_cselect_b32 {sr('T0')}, 0, 2")
+    a(f"  s_or_b32 {sr('FLG')}, {sr('FLG')}, {sr('T0')}")
     tail()
     # ---------------------------------------------------------- table
     handlers = {}
@@ -151,9 +205,59 @@ def gen_one(K: int, S: int) -> str:
         elif mode == M_XX:
             for k in range(K):
                 op(f, st(d, k), xv(k), xv(k))
+        elif mode == M_XS and f == 3:
+            slow = lab(f"xs{d}")
+            a(f"  s_bitcmp0_b32 {sr('FLG')}, 1")
+            a(f"  s_cbranch_scc1 {slow}")
+            a("  s_mov_b64 vcc, exec")
+            for k in range(K):
+                a(f"  v_cmp_le_f32_e64 {sp('P0')}, |{st(d, k)}|, {sr('HIXS')}")
+                a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
+            a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
+            a(f"  s_cbranch_scc1 {slow}")
+            for k in range(K):
+                b, x = st(d, k), xv(k)
+                a(f"  v_rcp_f32_e32 {T[1]}, {b}")
+                a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{b}|, {sr('TINY')}")
+                a(f"  v_fma_f32 {T[3]}, -{b}, {T[1]}, 1.0")
+                a(f"  v_fmac_f32_e32 {T[1]}, {T[3]}, {T[1]}")
+                a(f"  v_mul_f32_e32 {T[3]}, {x}, {T[1]}")
+                a(f"  v_fma_f32 {T[4]}, -{b}, {T[3]}, {x}")
+                a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {T[1]}")
+                a(f"  v_fma_f32 {T[0]}, -{b}, {T[3]}, {x}")
+                a(f"  v_fma_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
+                a(f"  v_cndmask_b32_e64 {b}, {T[0]}, 1.0, {sp('P0')}")
+            tail()
+            a(f"{slow}:")
+            for k in range(K):
+                op(f, st(d, k), xv(k), st(d, k))
         elif mode == M_XS:
             for k in range(K):
                 op(f, st(d, k), xv(k), st(d, k))
+        elif mode == M_SX and f == 3:
+            slow = lab(f"sx{d}")
+            a(f"  s_bitcmp0_b32 {sr('FLG')}, 0")
+            a(f"  s_cbranch_scc1 {slow}")
+            a("  s_mov_b64 vcc, exec")
+            for k in range(K):
+                a(f"  v_cmp_ge_f32_e64 {sp('P0')}, |{st(d, k)}|, {sr('LOSX')}")
+                a(f"  v_cmp_le_f32_e64 {sp('J0')}, |{st(d, k)}|, {sr('HISX')}")
+                a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
+                a(f"  s_and_b64 vcc, vcc, {sp('J0')}")
+            a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
+            a(f"  s_cbranch_scc1 {slow}")
+            for k in range(K):
+                n, x, y = st(d, k), xv(k), yv(k)
+                a(f"  v_mul_f32_e32 {T[3]}, {n}, {y}")
+                a(f"  v_fma_f32 {T[4]}, -{x}, {T[3]}, {n}")
+                a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {y}")
+                a(f"  v_fma_f32 {T[0]}, -{x}, {T[3]}, {n}")
+                a(f"  v_fma_f32 {T[0]}, {T[0]}, {y}, {T[3]}")
+                a(f"  v_cndmask_b32_e64 {n}, {T[0]}, 1.0, {xm(k)}")
+            tail()
+            a(f"{slow}:")
+            for k in range(K):
+                op(f, st(d, k), st(d, k), xv(k), mask=xm(k))
         elif mode == M_SX:
             for k in range(K):
                 op(f, st(d, k), st(d, k), xv(k), mask=xm(k))
@@ -207,9 +311,9 @@ def gen_one(K: int, S: int) -> str:
 
     body = "\n".join(f'        "{line}\\n"' for line in L)
     vclob = ", ".join(f'"v{i}"' for i in range(V_ST, n_vgpr))
-    sclob = ", ".join(f'"s{s[n]}"' for n in s)
+    sclob = ", ".join(f'"s{s[n]}"' for n in names)
     return f"""
-// K = {K} cases per lane, S = {S} stack slots: v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(s) - 1}.
+// K = {K} cases per lane, S = {S} stack slots: v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(names) - 1}.
 __device__ __forceinline__ void run_f32_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const float* inb,
                                                      const float* vb, float* rb, const GP_CONST int32_t* cin,
                                                      uint32_t strideb, float* outb, uint32_t voff)
