@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 import gen  # noqa: E402
 
 PEAK_FP32_LANE_OPS = 256 * 4 * 16 * 2.4e9      # non-packed FP32 VALU lane-ops/s (39.3e12)
+PEAK_HBM_GBPS = 8000.0                        # MI355X HBM3E
 
 
 def log(*a):
@@ -239,7 +240,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the evaluation path is not "
-                                   "sharded across GPUs (see DESIGN.md for how it would shard)",
+                                   "sharded across GPUs",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -264,7 +265,7 @@ def main():
     if kids is not None:
         rp, ro = record_lists(pop.n_trees, kids)
         ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, record_points=rp,
-                                 record_offsets=ro, chunk_nodes=args.chunk_nodes)
+                                 record_offsets=ro, chunk_nodes=args.chunk_nodes, keep_trees=True)
     else:
         ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, chunk_nodes=args.chunk_nodes)
     load_s = time.perf_counter() - t1
@@ -357,20 +358,36 @@ def main():
     except (OSError, KeyError, ValueError):
         pass
 
+    # children built on the device (memory-bound copy kernel): 2 x bytes of HBM traffic
+    child_ops = None
+    if kids is not None:
+        sms = []
+        for _ in range(5):
+            child_ops, child_offs, sst = ctx.splice_children(ph, kids.parent, kids.point, kids.donors.ops,
+                                                             kids.donors.offsets, device=True, out=child_ops)
+            sms.append(sst["kernel_ms"])
+        sbytes = int(child_offs[-1])
+        skms = float(np.median(sms[1:]))
+        gbps = 2 * sbytes / (skms * 1e-3) / 1e9
+        extra["splice"] = {"children": int(len(kids.parent)), "bytes": sbytes, "kernel": "k_splice",
+                           "kernel_ms": round(skms, 4), "bound": "hbm", "achieved": round(gbps, 1),
+                           "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(gbps / PEAK_HBM_GBPS, 4),
+                           "algorithmic_bytes": 2 * sbytes}
+
     if args.compare:
         _, _, st_pt = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, per_tree=True)
         extra["per_tree_launch_ms"] = st_pt["device_ms"]
         _, _, st_b = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False)
         extra["batched_launch_ms"] = st_b["device_ms"]
         if kids is not None:
-            childpop = gen.pack([gen.splice(pop.tree(int(p)), int(c), kids.donors.tree(i))
-                                 for i, (p, c) in enumerate(zip(kids.parent, kids.point))])
-            cph = ctx.load_population(vtype, childpop.ops, childpop.offsets)
-            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, childpop.n_trees, T, roots=False)
-            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, childpop.n_trees, T, roots=False)
+            n_kids = len(child_offs) - 1
+            cph = ctx.load_population(vtype, child_ops.cpu().numpy(), child_offs, n_inputs=pop.n_inputs)
+            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, n_kids, T, roots=False)
+            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, n_kids, T, roots=False)
             extra["children_full_reeval_ms"] = st_c["device_ms"]
-            extra["children_full_reeval_gpops"] = int(childpop.sizes().sum()) * T / (st_c["device_ms"] * 1e-3) / 1e9
+            extra["children_full_reeval_gpops"] = int(child_offs[-1]) * T / (st_c["device_ms"] * 1e-3) / 1e9
             ctx.free(cph)
+    del child_ops
 
     serving = None
     if args.serve_jobs > 0:

@@ -77,13 +77,17 @@ enum { GP_PREFIX = 0, GP_POSTFIX = 1 };    /* load layout */
 #define GP_ASYNC      0x2u   /* return once enqueued (needs GP_DEVICE_PTR outputs) */
 #define GP_PER_TREE   0x4u   /* one launch per tree instead of one batched launch */
 #define GP_NO_GRAPH   0x8u   /* launch kernels directly, no captured graph replay */
+#define GP_KEEP_TREES 0x10u  /* gp_load_population: keep the trees' bytes in device
+                                memory (charged to the budget) for gp_splice_children */
 
 typedef struct gp_stats {
     double device_ms;          /* HIP-event time on the context stream (0 with GP_ASYNC) */
     double kernel_ms;          /* HIP-event time of the interpreter launch alone (GP_NO_GRAPH
-                                  full evaluations; 0 otherwise) */
+                                  full evaluations), of the copy kernel
+                                  (gp_splice_children); 0 otherwise */
     double wall_ms;            /* call entry to return */
-    int64_t equivalent_ops;    /* sum of nodes x T over every tree or child scored */
+    int64_t equivalent_ops;    /* sum of nodes x T over every tree or child scored
+                                  (gp_splice_children: bytes written) */
     int64_t interpreted_ops;   /* nodes actually executed x T */
     int64_t launches;          /* kernel launches or graph replays issued */
     int32_t variant;           /* interpreter variant index (gp_variant_name) */
@@ -139,7 +143,8 @@ int gp_set_cases(gp_ctx* ctx, int vtype, int n_inputs, int64_t n_cases, const vo
  * record_points[record_offsets[i] .. record_offsets[i+1]) (node indices in
  * the given layout) whose parent caches every full evaluation must record,
  * for later incremental evaluation of children made at those points.
- * chunk_nodes: target nodes per chunk (0 = automatic). */
+ * chunk_nodes: target nodes per chunk (0 = automatic).  flags: GP_KEEP_TREES
+ * keeps a device copy of ops for gp_splice_children; other bits are ignored. */
 int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t n_trees,
                        const uint8_t* ops, const int64_t* offsets, const int64_t* record_points,
                        const int64_t* record_offsets, int64_t chunk_nodes, uint32_t flags,
@@ -179,6 +184,27 @@ int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, i
 int gp_evaluate_incremental(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t parent,
                             int64_t point, const uint8_t* donor_ops, int64_t donor_len,
                             uint32_t flags, void* root_out, void* fitness_out, gp_inc_result* res);
+
+/* Build children on the device (Section 5, Figure 1).  Child i is tree
+ * parent[i] of `pop` with the subtree at node point[i] replaced by donor i =
+ * donor_ops[donor_offsets[i] .. donor_offsets[i+1]), all in the population's
+ * layout: the mother's nodes before that subtree, the donor, then her nodes
+ * after it (in reverse Polish order the subtree ends at point[i]).  The
+ * population must have been loaded with GP_KEEP_TREES, and point[i] must be
+ * one of tree parent[i]'s record points, whose parent cache gives the extent
+ * of the removed subtree (else GP_ENOTFOUND); no evaluation is needed.
+ * Donors are host arrays and are validated as trees.
+ * child_offsets: host int64[n_children + 1], filled on success: child i is
+ * child_ops[child_offsets[i] .. child_offsets[i+1]).  child_ops: NULL to
+ * obtain the offsets only; otherwise child_cap bytes of room (GP_EINVAL if
+ * the children need more), a device pointer on the context's GPU with
+ * GP_DEVICE_PTR, else host memory (staged through device memory charged to
+ * the budget).  The bytes are copied by one kernel at memory speed;
+ * st->kernel_ms is its duration and st->equivalent_ops the bytes written. */
+int gp_splice_children(gp_ctx* ctx, gp_handle pop, int64_t n_children, const int64_t* parent,
+                       const int64_t* point, const uint8_t* donor_ops, const int64_t* donor_offsets,
+                       uint32_t flags, uint8_t* child_ops, int64_t child_cap, int64_t* child_offsets,
+                       gp_stats* st);
 
 /* Fitness of n given output vectors ([n][T] float32 or [n][W] uint64) against
  * the target of `cases`, in the fixed order described above. */

@@ -82,6 +82,14 @@ struct FitParams {
 };
 
 // ----------------------------------------------------------- launchers
+// One piece of a child under construction: len bytes from src to
+// out + dst.  Pieces of one segment meet at 16-byte aligned output offsets.
+struct SpliceItem {
+    const uint8_t* src;
+    int64_t dst;
+    int64_t len;
+};
+
 struct Variant {
     const char* name;
     int vtype;                   // 0 float32, 1 Boolean
@@ -99,5 +107,6 @@ hipError_t launch_init(int32_t* pending, const int32_t* init, int64_t n, unsigne
 hipError_t launch_eval(int variant, const EvalParams& p, int grid, hipStream_t s);
 hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t s);
 hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s);
+hipError_t launch_splice(const SpliceItem* items, int64_t n_items, uint8_t* out, hipStream_t s);
 
 }  // namespace gpe

@@ -41,7 +41,7 @@ Short divides.  When neither operand nor any intermediate of that sequence
 can leave the normal range, div_scale returns its operand unchanged with VCC
 clear, div_fmas is a plain fma and div_fixup returns its first operand: the
 remaining steps (rcp, the two Newton steps, the final fma) give the same bits.
-Two handlers use this:
+Two kinds of handler use this:
   * stack / x: the refined reciprocal of x is hoisted with the other x-only
     work.  Allowed when every lane's unprotected x lies in [1e-6, 2^20] (a
     per-chunk flag) and every numerator lies in [2^-90, 2^70]: the quotient
@@ -52,7 +52,9 @@ Two handlers use this:
     flag) and every divisor satisfies |b| <= 2^64: an unprotected divisor is
     then in [1e-6, 2^64], the quotient in [2^-124, 2^80] and the reciprocal
     normal.
-Either check is made over all lanes and slots of the wave (a scalar branch);
+A stack / stack divide keeps the full sequence: checking both operands costs
+as many instructions as the short form saves, and measured slower.
+Each check is made over all lanes and slots of the wave (a scalar branch);
 any value outside the ranges, NaN and infinities included, sends the whole
 wave through the full sequence, and protected lanes take 1.0 either way.
 """
@@ -71,6 +73,7 @@ P2 = lambda e: (127 + e) << 23        # bit pattern of 2^e (normal range)
 
 
 def gen_one(K: int, S: int) -> str:
+    assert K % 2 == 0, "the range checks pair up slots"
     V_X = V_ST + S * K
     V_Q = V_X + K
     V_Y = V_Q + K
@@ -157,9 +160,11 @@ def gen_one(K: int, S: int) -> str:
     # FLG bit 0: every lane has |x| <= 2^20; bit 1: every lane has x in [2^-60, 2^60]
     a(f"  s_mov_b32 {sr('T0')}, {P2(20):#x}")
     a("  s_mov_b64 vcc, exec")
-    for k in range(K):
+    for k in range(0, K, 2):
         a(f"  v_cmp_le_f32_e64 {sp('P0')}, |{xv(k)}|, {sr('T0')}")
+        a(f"  v_cmp_le_f32_e64 {sp('J0')}, |{xv(k + 1)}|, {sr('T0')}")
         a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
+        a(f"  s_and_b64 vcc, vcc, {sp('J0')}")
     a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
     a(f"  s_cselect_b32 {sr('FLG')}, 0, 1")
     a(f"  s_mov_b32 {sr('T0')}, {P2(-60):#x}")
@@ -210,9 +215,11 @@ def gen_one(K: int, S: int) -> str:
             a(f"  s_bitcmp0_b32 {sr('FLG')}, 1")
             a(f"  s_cbranch_scc1 {slow}")
             a("  s_mov_b64 vcc, exec")
-            for k in range(K):
+            for k in range(0, K, 2):
                 a(f"  v_cmp_le_f32_e64 {sp('P0')}, |{st(d, k)}|, {sr('HIXS')}")
+                a(f"  v_cmp_le_f32_e64 {sp('J0')}, |{st(d, k + 1)}|, {sr('HIXS')}")
                 a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
+                a(f"  s_and_b64 vcc, vcc, {sp('J0')}")
             a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
             a(f"  s_cbranch_scc1 {slow}")
             for k in range(K):

@@ -759,6 +759,67 @@ hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------- splice
+// Children are built from three contiguous byte ranges each (the mother's
+// nodes before the replaced subtree, the donor, the mother's nodes after it;
+// Figure 1), copied here at memory speed.  One workgroup per piece: whole
+// 16-byte aligned output words are assembled from 4-byte aligned source words
+// with byte funnel shifts (the source offset within a word is the same for
+// the whole piece), and the unaligned head and tail bytes of the piece are
+// copied one by one.  Reads start at most 3 bytes before and end at most 4
+// bytes after a piece's source range (both inside 4-byte words that overlap
+// it); source buffers start 4-byte aligned and carry 32 bytes of padding.
+__global__ __launch_bounds__(256) void k_splice(const SpliceItem* items, uint8_t* out)
+{
+    typedef __attribute__((address_space(1))) uint8_t gu8;
+    typedef __attribute__((address_space(1))) uint32_t gu32;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) u32x4 gu128;
+    const GP_CONST SpliceItem* ip = cst(items) + blockIdx.x;
+    const gu8* src = (const gu8*)ip->src;
+    const int64_t len = ip->len;
+    gu8* dst = (gu8*)(out + ip->dst);
+    const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + (uintptr_t)len;
+    const uintptr_t a0 = (d0 + 15) & ~(uintptr_t)15, a1 = d1 & ~(uintptr_t)15;
+    const int tid = threadIdx.x;
+    if (a0 >= a1) {
+        for (int64_t i = tid; i < len; i += 256) dst[i] = src[i];
+        return;
+    }
+    const int64_t head = (int64_t)(a0 - d0), tail = (int64_t)(d1 - a1);
+    if (tid < head) dst[tid] = src[tid];
+    if (tid >= 64 && tid - 64 < tail) {
+        const int64_t i = (int64_t)(a1 - d0) + (tid - 64);
+        dst[i] = src[i];
+    }
+    const int64_t nw = (int64_t)((a1 - a0) >> 4);
+    const uintptr_t sa = (uintptr_t)(src + head);
+    const uint32_t sh = (uint32_t)(sa & 3);
+    const gu32* s4 = (const gu32*)(sa & ~(uintptr_t)3);
+    gu128* o = (gu128*)a0;
+    if (sh == 0) {
+        for (int64_t w = tid; w < nw; w += 256) {
+            const gu32* q = s4 + 4 * w;
+            o[w] = u32x4{q[0], q[1], q[2], q[3]};
+        }
+    } else {
+        for (int64_t w = tid; w < nw; w += 256) {
+            const gu32* q = s4 + 4 * w;
+            const uint32_t v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3], v4 = q[4];
+            o[w] = u32x4{__builtin_amdgcn_alignbyte(v1, v0, sh), __builtin_amdgcn_alignbyte(v2, v1, sh),
+                         __builtin_amdgcn_alignbyte(v3, v2, sh), __builtin_amdgcn_alignbyte(v4, v3, sh)};
+        }
+    }
+}
+
+hipError_t launch_splice(const SpliceItem* items, int64_t n_items, uint8_t* out, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (n_items > (int64_t(1) << 24)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_splice, dim3((unsigned)n_items), dim3(256), 0, s, items, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s)
 {
     if (n_children <= 0) return hipSuccess;

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "../../include/gpeval.h"
@@ -30,6 +31,12 @@ struct DevBuf {
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf();
     void release();
+    void swap(DevBuf& o)
+    {
+        std::swap(ctx, o.ctx);
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
     template <class T> T* as() const { return (T*)p; }
 };
 
@@ -95,6 +102,9 @@ struct Pop {
     std::unordered_map<uint64_t, int32_t> spine_of;   // (tree, point) -> spine
     std::vector<SpineInfo> spines;
     DevBuf levels;                          // SpineLvl per spine level
+    // the trees' bytes in device memory (GP_KEEP_TREES), for building children
+    DevBuf tree_ops;                        // load layout, 32 bytes of padding
+    std::vector<int64_t> tree_off;          // [n_trees + 1]
     // evaluation state
     int64_t stride = 0;                     // case stride of vecs/recs
     DevBuf vecs;                            // [n_chunks][stride]: roots are slots 0..n_trees-1

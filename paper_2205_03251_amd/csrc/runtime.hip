@@ -720,13 +720,19 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
                        int64_t chunk_nodes, uint32_t flags, gp_handle* pop_out)
 {
     if (!ctx || !pop_out) return GP_EINVAL;
-    (void)flags;
     std::lock_guard<std::mutex> lk(ctx->mu);
     HIPC(ctx, hipSetDevice(ctx->device));
     auto p = std::make_shared<Pop>();
     RC(build_population(ctx, vtype, layout, n_inputs, n_trees, ops, offsets, record_points, record_offsets,
                         chunk_nodes, p.get(), ctx->stream));
     p->auto_chunk = chunk_nodes <= 0;
+    if (flags & GP_KEEP_TREES) {
+        const size_t nb = (size_t)offsets[n_trees];
+        RC(dev_alloc(ctx, p->tree_ops, nb + 32));
+        HIPC(ctx, hipMemcpyAsync(p->tree_ops.p, ops, nb, hipMemcpyHostToDevice, ctx->stream));
+        p->tree_off.assign(offsets, offsets + n_trees + 1);
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    }
     if (p->auto_chunk) {
         p->host_ops.assign(ops, ops + offsets[n_trees]);
         p->host_offsets.assign(offsets, offsets + n_trees + 1);
@@ -959,6 +965,108 @@ int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, i
     return GP_OK;
 }
 
+int gp_splice_children(gp_ctx* ctx, gp_handle pop, int64_t n_children, const int64_t* parent,
+                       const int64_t* point, const uint8_t* donor_ops, const int64_t* donor_offsets,
+                       uint32_t flags, uint8_t* child_ops, int64_t child_cap, int64_t* child_offsets,
+                       gp_stats* st)
+{
+    if (!ctx) return GP_EINVAL;
+    const double t0 = now_ms();
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    auto ip = ctx->pops.find(pop);
+    if (ip == ctx->pops.end()) return set_err(ctx, GP_EINVAL, "unknown population handle");
+    Pop* p = ip->second.get();
+    if (n_children < 0) return set_err(ctx, GP_EINVAL, "negative child count");
+    if (!child_offsets) return set_err(ctx, GP_EINVAL, "child_offsets is required");
+    if (n_children > 0 && (!parent || !point || !donor_ops || !donor_offsets))
+        return set_err(ctx, GP_EINVAL, "missing child arrays");
+    if (!p->tree_ops.p) return set_err(ctx, GP_EINVAL, "the population was loaded without GP_KEEP_TREES");
+    if (n_children > 0 && donor_offsets[0] != 0) return set_err(ctx, GP_EINVAL, "donor_offsets[0] must be 0");
+    // Extents: child i = mother[0, a) + donor + mother[a + removed, n).
+    std::vector<int64_t> offs(n_children + 1, 0), cut(n_children), removed(n_children);
+    std::vector<uint8_t> pre;
+    std::vector<int64_t> map;
+    for (int64_t i = 0; i < n_children; ++i) {
+        const std::string who = "child " + std::to_string(i) + ": ";
+        const int64_t t = parent[i];
+        if (t < 0 || t >= p->n_trees) return set_err(ctx, GP_EINVAL, who + "parent index out of range");
+        if (point[i] < 0 || point[i] >= p->tree_nodes[t])
+            return set_err(ctx, GP_EINVAL, who + "crossover point out of range");
+        auto it = p->spine_of.find(((uint64_t)t << 32) | (uint32_t)point[i]);
+        if (it == p->spine_of.end())
+            return set_err(ctx, GP_ENOTFOUND, who + "point " + std::to_string(point[i]) + " of tree " +
+                                                  std::to_string(t) + " was not recorded");
+        const int64_t nd = donor_offsets[i + 1] - donor_offsets[i];
+        if (nd < 1) return set_err(ctx, GP_EINVAL, who + "empty donor");
+        const uint8_t* d = donor_ops + donor_offsets[i];
+        std::string why;
+        const bool ok = p->layout == GP_POSTFIX ? postfix_to_prefix(d, nd, p->n_inputs, &pre, &map, &why)
+                                                : validate_prefix(d, nd, p->n_inputs, &why);
+        if (!ok) return set_err(ctx, GP_EINVAL, who + "donor: " + why);
+        removed[i] = p->spines[it->second].removed_nodes;
+        cut[i] = p->layout == GP_POSTFIX ? point[i] - removed[i] + 1 : point[i];
+        offs[i + 1] = offs[i] + p->tree_nodes[t] - removed[i] + nd;
+    }
+    const int64_t total = offs[n_children];
+    float ms = 0.f;
+    if (child_ops && total > 0) {
+        if (child_cap < total)
+            return set_err(ctx, GP_EINVAL, "child_ops holds " + std::to_string(child_cap) + " bytes; the children need " +
+                                               std::to_string(total));
+        DevBuf dd, items_d, stage;
+        const int64_t nb = donor_offsets[n_children];
+        RC(dev_alloc(ctx, dd, (size_t)nb + 32));
+        HIPC(ctx, hipMemcpyAsync(dd.p, donor_ops, (size_t)nb, hipMemcpyHostToDevice, ctx->stream));
+        uint8_t* out = child_ops;
+        if (!(flags & GP_DEVICE_PTR)) {
+            RC(dev_alloc(ctx, stage, (size_t)total));
+            out = stage.as<uint8_t>();
+        }
+        // Pieces of at most 64 KiB that meet at 16-byte aligned output offsets.
+        std::vector<SpliceItem> items;
+        items.reserve((size_t)(total >> 16) + 3 * (size_t)n_children + 8);
+        auto add = [&](const uint8_t* src, int64_t dst, int64_t len) {
+            while (len > 0) {
+                int64_t take = std::min<int64_t>(len, ((dst + 65536) & ~int64_t(15)) - dst);
+                items.push_back(SpliceItem{src, dst, take});
+                src += take;
+                dst += take;
+                len -= take;
+            }
+        };
+        const uint8_t* base = p->tree_ops.as<uint8_t>();
+        for (int64_t i = 0; i < n_children; ++i) {
+            const int64_t t = parent[i], n = p->tree_nodes[t], nd = donor_offsets[i + 1] - donor_offsets[i];
+            const uint8_t* m = base + p->tree_off[t];
+            add(m, offs[i], cut[i]);
+            add(dd.as<uint8_t>() + donor_offsets[i], offs[i] + cut[i], nd);
+            add(m + cut[i] + removed[i], offs[i] + cut[i] + nd, n - cut[i] - removed[i]);
+        }
+        if ((int64_t)items.size() > (int64_t(1) << 24))
+            return set_err(ctx, GP_EINVAL, "too many bytes for one splice launch");
+        RC(upload(ctx, items_d, items.data(), items.size() * sizeof(SpliceItem), ctx->stream));
+        HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+        HIPC(ctx, launch_splice(items_d.as<SpliceItem>(), (int64_t)items.size(), out, ctx->stream));
+        HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+        if (!(flags & GP_DEVICE_PTR))
+            HIPC(ctx, hipMemcpyAsync(child_ops, out, (size_t)total, hipMemcpyDeviceToHost, ctx->stream));
+        HIPC(ctx, hipStreamSynchronize(ctx->stream));
+        HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    }
+    std::copy(offs.begin(), offs.end(), child_offsets);
+    if (st) {
+        st->device_ms = ms;
+        st->kernel_ms = ms;
+        st->equivalent_ops = child_ops ? total : 0;
+        st->interpreted_ops = 0;
+        st->launches = child_ops && total > 0 ? 1 : 0;
+        st->variant = -1;
+        st->wall_ms = now_ms() - t0;
+    }
+    return GP_OK;
+}
+
 int gp_evaluate_incremental(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t parent, int64_t point,
                             const uint8_t* donor_ops, int64_t donor_len, uint32_t flags, void* root_out,
                             void* fitness_out, gp_inc_result* res)
@@ -1062,6 +1170,8 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         best_pop->host_offsets.swap(p->host_offsets);
         best_pop->host_rec_points.swap(p->host_rec_points);
         best_pop->host_rec_offsets.swap(p->host_rec_offsets);
+        best_pop->tree_ops.swap(p->tree_ops);
+        best_pop->tree_off.swap(p->tree_off);
         ctx->pops[pop] = best_pop;
         p = best_pop.get();
         RC(enqueue_full(ctx, p, cases, cs, best, false, true, ctx->stream, nullptr));

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgpeval.so")
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EBUDGET, GP_EDEVICE, GP_ENOTFOUND, GP_EBUSY = 0, -1, -2, -3, -4, -5, -6
 GP_F32, GP_BOOL = 0, 1
 GP_PREFIX, GP_POSTFIX = 0, 1
-GP_DEVICE_PTR, GP_ASYNC, GP_PER_TREE, GP_NO_GRAPH = 0x1, 0x2, 0x4, 0x8
+GP_DEVICE_PTR, GP_ASYNC, GP_PER_TREE, GP_NO_GRAPH, GP_KEEP_TREES = 0x1, 0x2, 0x4, 0x8, 0x10
 GP_JOB_FULL, GP_JOB_INCREMENTAL = 0, 1
 ERRNAMES = {GP_EINVAL: "EINVAL", GP_ENOMEM: "ENOMEM", GP_EBUDGET: "EBUDGET", GP_EDEVICE: "EDEVICE",
             GP_ENOTFOUND: "ENOTFOUND", GP_EBUSY: "EBUSY"}
@@ -89,6 +89,13 @@ def lib() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(the HIP library has no fallback)")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library and torch's device tensors share that one
+    # runtime (loaded the other way round, torch finds no GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     h = C.CDLL(LIB_PATH)
     h.gp_create.argtypes = [C.c_int, C.c_uint64, P, C.POINTER(P)]
     h.gp_destroy.argtypes = [P]
@@ -107,6 +114,7 @@ def lib() -> C.CDLL:
                                                 P, C.POINTER(Stats)]
     h.gp_evaluate_incremental.argtypes = [P, I64, I64, I64, I64, P, I64, C.c_uint32, P, P, P]
     h.gp_fitness.argtypes = [P, I64, P, I64, C.c_uint32, P]
+    h.gp_splice_children.argtypes = [P, I64, I64, P, P, P, P, C.c_uint32, P, I64, P, C.POINTER(Stats)]
     h.gp_variant_name.argtypes = [C.c_int]
     h.gp_variant_name.restype = C.c_char_p
     h.gp_variant_count.argtypes = []
@@ -241,15 +249,46 @@ class Context:
         return out.value
 
     def load_population(self, vtype, ops, offsets, n_inputs=1, layout=GP_PREFIX, record_points=None,
-                        record_offsets=None, chunk_nodes=0) -> int:
+                        record_offsets=None, chunk_nodes=0, keep_trees=False) -> int:
         ops = _np(ops, np.uint8)
         offsets = _np(offsets, np.int64)
         rp = _np(record_points, np.int64) if record_points is not None else None
         ro = _np(record_offsets, np.int64) if record_offsets is not None else None
         out = I64(0)
+        flags = GP_KEEP_TREES if keep_trees else 0
         self._check(lib().gp_load_population(self._h, vtype, layout, n_inputs, len(offsets) - 1, _ptr(ops),
-                                             _ptr(offsets), _ptr(rp), _ptr(ro), chunk_nodes, 0, C.byref(out)))
+                                             _ptr(offsets), _ptr(rp), _ptr(ro), chunk_nodes, flags,
+                                             C.byref(out)))
         return out.value
+
+    def splice_children(self, pop, parent, point, donor_ops, donor_offsets, device=False, out=None):
+        """Children built on the device (gp_splice_children): returns (ops,
+        offsets, stats); ops is a numpy array, or a uint8 tensor on the device
+        when device=True (or the given `out` tensor)."""
+        parent = _np(parent, np.int64)
+        point = _np(point, np.int64)
+        donor_ops = _np(donor_ops, np.uint8)
+        donor_offsets = _np(donor_offsets, np.int64)
+        n = len(parent)
+        offs = np.zeros(n + 1, np.int64)
+        self._check(lib().gp_splice_children(self._h, pop, n, _ptr(parent), _ptr(point), _ptr(donor_ops),
+                                             _ptr(donor_offsets), 0, None, 0, _ptr(offs), None))
+        total = int(offs[-1])
+        flags = 0
+        if device or out is not None:
+            import torch
+            flags |= GP_DEVICE_PTR
+            ops = out if out is not None else torch.empty(max(total, 1), dtype=torch.uint8,
+                                                          device=f"cuda:{self.device}")
+            cap = ops.numel()
+        else:
+            ops = np.empty(max(total, 1), np.uint8)
+            cap = ops.size
+        st = Stats()
+        self._check(lib().gp_splice_children(self._h, pop, n, _ptr(parent), _ptr(point), _ptr(donor_ops),
+                                             _ptr(donor_offsets), flags, _ptr(ops), cap, _ptr(offs),
+                                             C.byref(st)))
+        return ops[:total], offs, st.as_dict()
 
     def population_info(self, pop) -> dict:
         info = PopInfo()

@@ -99,63 +99,70 @@ def _signed_pow2(rng, lo, hi, n):
 
 
 def _short_divide_cases():
-    """16384 cases in blocks of 512 (one wave slice for K = 8, two for K = 4).
-    Blocks that keep every value inside the short-divide ranges (exact bounds
-    included), blocks with one value just outside, blocks of extremes and
-    blocks like the benchmark's inputs."""
+    """16384 cases over three inputs in blocks of 512 (one wave slice for
+    K = 8, two for K = 4): blocks that keep every value inside the
+    short-divide ranges (exact bounds included), blocks with one value just
+    outside, blocks of extremes and blocks like the benchmark's inputs."""
     rng = np.random.default_rng(77)
     B = 512
     up = lambda v: np.nextafter(np.float32(v), np.float32(np.inf))
     down = lambda v: np.nextafter(np.float32(v), np.float32(0))
-    x0s, x1s = [], []
+    cols = [[], [], []]
     for blk in range(32):
         kind = blk % 8
-        if kind in (0, 1):          # stack / x short path: |x0| <= 2^20, |x1| in [2^-90, 2^70]
+        if kind in (0, 1):      # stack / x short path: |x0| <= 2^20, |x1| in [2^-90, 2^70]
             x0 = _signed_pow2(rng, -19.9, 20, B)
             x1 = _signed_pow2(rng, -90, 70, B)
+            x2 = _signed_pow2(rng, -25, 36, B)
             x0[:6] = [1e-6, -1e-6, 2.0 ** 20, -(2.0 ** 20), 0.0, 1e-7]          # protected lanes allowed
             x1[:4] = [2.0 ** -90, -(2.0 ** -90), 2.0 ** 70, -(2.0 ** 70)]
-        elif kind in (2, 3):        # x / stack short path: x0 in [2^-60, 2^60], |x1| <= 2^64
+            x2[:6] = [2.0 ** 36, -(2.0 ** 36), 1e-6, 0.0, -0.0, 1e-45]
+        elif kind in (2, 3):    # x / stack short path: x0 in [2^-60, 2^60], |x1| <= 2^64
             x0 = _signed_pow2(rng, -60, 60, B)
             x1 = _signed_pow2(rng, -25, 64, B)
+            x2 = _signed_pow2(rng, -25, 36, B)
             x0[:4] = [2.0 ** -60, -(2.0 ** -60), 2.0 ** 60, -(2.0 ** 60)]
             x1[:8] = [2.0 ** 64, -(2.0 ** 64), 1e-6, 9.99e-7, 0.0, -0.0, 1e-45, -1e-7]
-        elif kind == 4:             # one value just outside each range
+        elif kind == 4:         # one value just outside each range
             x0 = _signed_pow2(rng, -19.9, 20, B)
             x1 = _signed_pow2(rng, -60, 60, B)
+            x2 = _signed_pow2(rng, -20, 20, B)
             x0[rng.integers(B)] = up(2.0 ** 20)
             x1[rng.integers(B)] = up(2.0 ** 70)
             x1[rng.integers(B)] = down(2.0 ** -90)
             x1[rng.integers(B)] = up(2.0 ** 64)
-        elif kind == 5:             # x just outside [2^-60, 2^60]
+            x2[rng.integers(B)] = up(2.0 ** 36)
+        elif kind == 5:         # x just outside [2^-60, 2^60]
             x0 = _signed_pow2(rng, -60, 60, B)
             x1 = _signed_pow2(rng, -20, 20, B)
+            x2 = _signed_pow2(rng, -20, 20, B)
             x0[rng.integers(B)] = down(2.0 ** -60)
             x0[rng.integers(B)] = up(2.0 ** 60)
-        elif kind == 6:             # extremes
+        elif kind == 6:         # extremes
             pool = np.array([0.0, -0.0, 1e-45, -1e-40, 1.17549435e-38, 1e-30, 3.4e38, -3.4e38, np.inf, -np.inf,
                              np.nan, 1e-6, 2.0 ** 100, 2.0 ** -100, 1.0, -2.5], np.float32)
-            x0 = rng.choice(pool, B)
-            x1 = rng.choice(pool, B)
-        else:                       # like the benchmark: uniform in [-1, 1]
-            x0 = rng.uniform(-1, 1, B).astype(np.float32)
-            x1 = rng.uniform(-1, 1, B).astype(np.float32)
-        x0s.append(x0)
-        x1s.append(x1)
-    x = np.stack([np.concatenate(x0s), np.concatenate(x1s)]).astype(np.float32)
+            x0, x1, x2 = (rng.choice(pool, B) for _ in range(3))
+        else:                   # like the benchmark: uniform in [-1, 1]
+            x0, x1, x2 = (rng.uniform(-1, 1, B).astype(np.float32) for _ in range(3))
+        for c, v in zip(cols, (x0, x1, x2)):
+            c.append(v)
+    x = np.stack([np.concatenate(c) for c in cols]).astype(np.float32)
     return gen.FloatCases(x, np.zeros(x.shape[1], np.float32))
 
 
 def test_short_divides_bit_exact(ctx):
-    """Divisions by x and of x with operands at, inside and just outside the
-    ranges where the table-dispatch loop takes its short divide, against the
-    oracle's IEEE division."""
+    """Divisions by x and of x, with operands at, inside and just outside the
+    ranges where the table-dispatch loop takes its short divide, and of one
+    stack value by another, against the oracle's IEEE division."""
     from tests.golden_cases import parse_tree
     cases = _short_divide_cases()
     a1 = "(+ x1 (- x0 x0))"                  # x1 on the stack (x0 - x0 = +0 for finite x0)
+    a2 = "(+ x2 (- x0 x0))"
     trees = [f"(% {a1} x0)", f"(% x0 {a1})", f"(% (% {a1} x0) x0)", f"(% x0 (% x0 {a1}))",
-             f"(% (* {a1} x0) x0)", f"(% (% x0 {a1}) (% {a1} x0))", f"(- (% {a1} x0) (% x0 {a1}))"]
-    pop = gen.pack([parse_tree(t) for t in trees], n_inputs=2)
+             f"(% (* {a1} x0) x0)", f"(% (% x0 {a1}) (% {a1} x0))", f"(- (% {a1} x0) (% x0 {a1}))",
+             f"(% {a1} {a2})", f"(% (+ (- x0 x0) {a1}) {a2})", f"(% {a1} (+ (- x0 x0) {a2}))",
+             f"(% {a2} (% {a1} {a2}))", f"(% (% {a1} {a2}) (* {a2} {a2}))", f"(% {a1} (+ {a2} (- {a2} {a1})))"]
+    pop = gen.pack([parse_tree(t) for t in trees], n_inputs=3)
     for v in f32_variants():
         say("short divides", g.variant_names()[v])
         check_float_pop(ctx, pop, cases, variant=v)

@@ -88,7 +88,7 @@ def test_incremental_full_size_sampled(ctx):
     rp = np.array([c for p in pts for c in p], np.int64)
     ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
     ph = ctx.load_population(g.GP_F32, parents.ops, parents.offsets, record_points=rp, record_offsets=ro,
-                             chunk_nodes=8192)
+                             chunk_nodes=8192, keep_trees=True)
     proots, pfit, _ = ctx.evaluate_full(ph, ch, g.GP_F32, parents.n_trees, 1024)
     roots, fit, info = ctx.evaluate_incremental(ph, ch, g.GP_F32, 1024, kids.parent, kids.point,
                                                 kids.donors.ops, kids.donors.offsets)
@@ -123,5 +123,19 @@ def test_incremental_full_size_sampled(ctx):
         assert info["interpreted_nodes"][i] == w_int
         assert same_f32(roots[i], w_root).all()
         assert fit[i] == w_fit or (math.isnan(fit[i]) and math.isnan(w_fit))
+    # all 500 children built on the device, byte for byte against the oracle's splice
+    ops, offs, sst = ctx.splice_children(ph, kids.parent, kids.point, kids.donors.ops, kids.donors.offsets,
+                                         device=True)
+    say("splice full size:", int(offs[-1]), "bytes in", round(sst["kernel_ms"], 3), "ms")
+    assert np.array_equal(np.diff(offs), info["child_nodes"])
+    host = ops.cpu().numpy()
+    del ops
+
+    def same_child(i):
+        want = oracle.splice(parents.tree(int(kids.parent[i])), int(kids.point[i]), kids.donors.tree(i))
+        return np.array_equal(host[offs[i]:offs[i + 1]], want)
+
+    with ThreadPoolExecutor(8) as ex:
+        assert all(ex.map(same_child, range(500)))
     ctx.free(ph)
     ctx.free(ch)
