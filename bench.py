@@ -343,6 +343,7 @@ def main():
     if vtype == g.GP_BOOL:
         roofline["note"] = "Boolean: one 64-bit word op per function node per 64 cases"
     # HBM bytes from the committed counter runs, valid only for the kernel source they were taken with
+    counted = None
     try:
         import hashlib
         rec = json.load(open(os.path.join(ROOT, "profiles", "counters.json")))
@@ -355,6 +356,7 @@ def main():
         if same:
             roofline["traffic"] = int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
             roofline["valu_lane_op_frac_counters"] = rec["valu_lane_op_frac"]
+            counted = rec
     except (OSError, KeyError, ValueError):
         pass
 
@@ -385,7 +387,11 @@ def main():
         extra["splice"] = {"children": int(len(kids.parent)), "bytes": sbytes, "kernel": "k_splice",
                            "kernel_ms": round(skms, 4), "bound": "hbm", "achieved": round(gbps, 1),
                            "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(gbps / PEAK_HBM_GBPS, 4),
-                           "algorithmic_bytes": 2 * sbytes, "device_copy_same_bytes_GBps": round(copy_gbps, 1)}
+                           "algorithmic_bytes": 2 * sbytes, "device_copy_same_bytes_GBps": round(copy_gbps, 1),
+                           "traffic": None}
+        if counted is not None and "splice" in counted:
+            extra["splice"]["traffic"] = int(counted["splice"]["fetch_bytes_per_launch"] +
+                                             counted["splice"]["write_bytes_per_launch"])
 
     if args.compare:
         _, _, st_pt = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, per_tree=True)
