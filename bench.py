@@ -360,6 +360,23 @@ def main():
     except (OSError, KeyError, ValueError):
         pass
 
+    # the paper's own incremental form: the mother co-evaluated alongside each child (no parent caches)
+    if kids is not None:
+        co = []
+        for _ in range(2):
+            _, _, st_co = ctx.evaluate_incremental(ph, ch, vtype, T, kids.parent, kids.point, kids.donors.ops,
+                                                   kids.donors.offsets, roots=False, device=True, coeval=True)
+            co.append(st_co)
+        st_co = co[-1]
+        cn = int(st_co["child_nodes"].sum())
+        ci = int(st_co["interpreted_nodes"].sum())
+        extra["incremental_coeval"] = {
+            "children": int(len(kids.parent)), "wall_ms": round(st_co["wall_ms"], 3),
+            "device_ms": round(st_co["device_ms"], 3), "launches": int(st_co["launches"]),
+            "interpreted_nodes": ci, "equivalent_gpops": round(cn * T / (st_co["wall_ms"] * 1e-3) / 1e9, 1),
+            "interpreted_gpops": round(ci * T / (st_co["wall_ms"] * 1e-3) / 1e9, 1),
+            "same_stop_levels_as_cached": bool(np.array_equal(st_co["stop_level"], inc_stats["stop_level"]))}
+
     # children built on the device (memory-bound copy kernel): 2 x bytes of HBM traffic
     child_ops = None
     if kids is not None:

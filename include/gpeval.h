@@ -79,6 +79,8 @@ enum { GP_PREFIX = 0, GP_POSTFIX = 1 };    /* load layout */
 #define GP_NO_GRAPH   0x8u   /* launch kernels directly, no captured graph replay */
 #define GP_KEEP_TREES 0x10u  /* gp_load_population: keep the trees' bytes in device
                                 memory (charged to the budget) for gp_splice_children */
+#define GP_COEVAL     0x20u  /* gp_evaluate_incremental_batch: re-evaluate the mother
+                                alongside each child instead of reading parent caches */
 
 typedef struct gp_stats {
     double device_ms;          /* HIP-event time on the context stream (0 with GP_ASYNC) */
@@ -173,7 +175,15 @@ int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags
  * (same layout and value type as the population).  The population must have
  * been fully evaluated on `cases` since it was loaded, with point[i] among
  * its record points (else GP_ENOTFOUND).  Outputs as gp_evaluate_full, per
- * child; res[i] gets the stop level and counts (host pointer, may be NULL). */
+ * child; res[i] gets the stop level and counts (host pointer, may be NULL).
+ * GP_COEVAL: the paper's own form (Section 6.2): the mother is re-evaluated
+ * alongside each child from the point up, the sibling subtrees of the path
+ * evaluated on demand, so any node may be the point (no record points); the
+ * population must be in prefix layout and fully evaluated on `cases` (her root
+ * vector and fitness are the child's on a stop).  Results and stop levels are
+ * those of the cached form; res[i].interpreted_nodes then counts the nodes
+ * actually executed: donor + removed subtree + sibling subtrees evaluated +
+ * two per level walked (child and mother).  Runs synchronously (no GP_ASYNC). */
 int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t n_children,
                                   const int64_t* parent, const int64_t* point,
                                   const uint8_t* donor_ops, const int64_t* donor_offsets,
@@ -292,6 +302,18 @@ int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t 
 
 /* Validate one tree (prefix layout) on the host: GP_OK or GP_EINVAL. */
 int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n);
+
+/* The path that co-evaluation walks (Section 6.2), on the host, for tests:
+ * for node c of a prefix tree with terminals below 64, levels_out receives 4
+ * int64 per ancestor, nearest first: the ancestor's index, the sibling
+ * subtree's first index and end (exclusive), and f | 4 when the path operand
+ * is the right one.  *removed_end gets the end of c's subtree.  The search
+ * uses an index of the subtrees with at least index_min_size nodes (0: no
+ * index); the result does not depend on it.  Returns the number of ancestors,
+ * GP_EINVAL for a malformed tree or c out of range, or GP_ENOMEM when
+ * level_cap is too small. */
+int64_t gp_inspect_path(const uint8_t* ops, int64_t n, int64_t c, int64_t index_min_size, int64_t* levels_out,
+                        int64_t level_cap, int64_t* removed_end);
 
 #ifdef __cplusplus
 }

@@ -71,6 +71,42 @@ struct WalkParams {
     int64_t P;                   // fitness halving width (float)
 };
 
+// Co-evaluation of child and mother without parent caches (Section 6.2):
+// per level the ancestor's function, the side of the path operand and the
+// sibling subtree's vector, evaluated on demand.
+struct CoLevel {
+    const void* sib;
+    int32_t fside;               // f | 4 when the path operand is the right one
+    int32_t pad;
+};
+
+struct CoChild {
+    const void* v_in;            // child's running vector (first round: the donor's)
+    const void* m_in;            // mother's running vector (first round: the removed subtree's)
+    void* v_out;                 // running vectors kept for the next round
+    void* m_out;
+    const CoLevel* levels;       // this round's levels, nearest the point first
+    const void* parent_vec;      // the mother's root vector
+    const void* parent_fit;      // the mother's fitness (double or int64)
+    int32_t n_levels;
+    int32_t level_base;          // levels walked in earlier rounds
+    int32_t check0;              // compare v_in with m_in first (level 0)
+    int32_t last;                // this round's levels end at the root
+    int32_t out_slot;            // the child's index in the outputs
+    int32_t pad;
+};
+
+struct CoParams {
+    const CoChild* children;
+    const void* target;          // [stride]
+    void* root_out;              // [n_children][stride] or null
+    void* fit_out;               // [n_children]
+    int32_t* stop_out;           // [n_children]: stop level, -1 root reached, -2 walk goes on
+    int64_t stride;
+    int64_t n_valid;             // T (float) or T bits (Boolean)
+    int64_t P;                   // fitness halving width (float)
+};
+
 struct FitParams {
     const void* vecs;            // [n][stride]
     int64_t first_slot;
@@ -108,5 +144,6 @@ hipError_t launch_eval(int variant, const EvalParams& p, int grid, hipStream_t s
 hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t s);
 hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s);
 hipError_t launch_splice(const SpliceItem* items, int64_t n_items, uint8_t* out, hipStream_t s);
+hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipStream_t s);
 
 }  // namespace gpe

@@ -759,6 +759,201 @@ hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t 
     return hipGetLastError();
 }
 
+// ----------------------------------------------------- co-evaluation
+// One workgroup of 256 threads per child, over the levels of one round: the
+// child's running vector v and the mother's m both take the ancestor's
+// function with the same sibling vector as the other operand (the mother is
+// re-evaluated alongside her child), and the walk stops at the first level
+// where they agree on every case.  Level 0 compares the donor's vector with
+// the removed subtree's.  A walk that neither stops nor reaches the root in
+// this round leaves v and m for the next one.
+template <int R>
+__global__ __launch_bounds__(256) void k_coeval_f32(CoParams p)
+{
+    __shared__ double red[256];
+    const GP_CONST CoChild* cp = cst(p.children) + blockIdx.x;
+    const float* vin = (const float*)cp->v_in;
+    const float* min_ = (const float*)cp->m_in;
+    float* vout = (float*)cp->v_out;
+    float* mout = (float*)cp->m_out;
+    const CoLevel* levels = cp->levels;
+    const float* pvec = (const float*)cp->parent_vec;
+    const double* pfit = (const double*)cp->parent_fit;
+    const int32_t n_levels = cp->n_levels, level_base = cp->level_base, check0 = cp->check0, last = cp->last;
+    const int64_t slot = cp->out_slot;
+    const int tid = threadIdx.x;
+    const int64_t T = p.n_valid;
+    float v[R], m[R];
+    UNROLL for (int k = 0; k < R; ++k) {
+        const int64_t i = tid + 256 * k;
+        v[k] = (i < T) ? vin[i] : 0.0f;
+        m[k] = (i < T) ? min_[i] : 0.0f;
+    }
+    int stop = -2;
+    if (check0) {
+        bool eq = true;
+        UNROLL for (int k = 0; k < R; ++k)
+            if (tid + 256 * k < T) eq = eq && same_f32(v[k], m[k]);
+        if (__syncthreads_and(eq)) stop = 0;
+    }
+    for (int l = 0; stop == -2 && l < n_levels; ++l) {
+        const GP_CONST CoLevel* lp = cst(levels) + l;
+        const float* sb = (const float*)lp->sib;
+        const int fs = lp->fside;
+        const int f = fs & 3;
+        const bool right = (fs & 4) != 0;
+        bool eq = true;
+        UNROLL for (int k = 0; k < R; ++k) {
+            const int64_t i = tid + 256 * k;
+            if (i < T) {
+                const float s = sb[i];
+                v[k] = right ? fop_rt(f, s, v[k]) : fop_rt(f, v[k], s);
+                m[k] = right ? fop_rt(f, s, m[k]) : fop_rt(f, m[k], s);
+                eq = eq && same_f32(v[k], m[k]);
+            }
+        }
+        if (__syncthreads_and(eq)) stop = level_base + l + 1;
+    }
+    if (stop == -2 && last) stop = -1;
+    if (tid == 0) p.stop_out[slot] = stop;
+    float* ro = p.root_out ? (float*)p.root_out + slot * p.stride : nullptr;
+    if (stop >= 0) {
+        if (ro)
+            for (int64_t i = tid; i < T; i += 256) ro[i] = pvec[i];
+        if (tid == 0) ((double*)p.fit_out)[slot] = *pfit;
+    } else if (stop == -1) {
+        const float* y = (const float*)p.target;
+        double e[R];
+        UNROLL for (int k = 0; k < R; ++k) {
+            const int64_t i = tid + 256 * k;
+            double val = 0.0;
+            if (i < T) {
+                if (ro) ro[i] = v[k];
+                const float d = v[k] - y[i];
+                val = (double)fabsf(d);
+            }
+            e[k] = val;
+        }
+        const double f = halving_sum<R>(e, p.P, red);
+        if (tid == 0) ((double*)p.fit_out)[slot] = f;
+    } else {
+        UNROLL for (int k = 0; k < R; ++k) {
+            const int64_t i = tid + 256 * k;
+            if (i < T) {
+                vout[i] = v[k];
+                mout[i] = m[k];
+            }
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_coeval_bool(CoParams p)
+{
+    __shared__ int64_t red[256];
+    const GP_CONST CoChild* cp = cst(p.children) + blockIdx.x;
+    const uint64_t* vin = (const uint64_t*)cp->v_in;
+    const uint64_t* min_ = (const uint64_t*)cp->m_in;
+    uint64_t* vout = (uint64_t*)cp->v_out;
+    uint64_t* mout = (uint64_t*)cp->m_out;
+    const CoLevel* levels = cp->levels;
+    const uint64_t* pvec = (const uint64_t*)cp->parent_vec;
+    const int64_t* pfit = (const int64_t*)cp->parent_fit;
+    const int32_t n_levels = cp->n_levels, level_base = cp->level_base, check0 = cp->check0, last = cp->last;
+    const int64_t slot = cp->out_slot;
+    const int tid = threadIdx.x;
+    const int64_t T = p.n_valid;
+    const int64_t W = (T + 63) / 64;
+    uint64_t v[R], m[R];
+    UNROLL for (int k = 0; k < R; ++k) {
+        const int64_t i = tid + 256 * k;
+        v[k] = (i < W) ? vin[i] : 0ull;
+        m[k] = (i < W) ? min_[i] : 0ull;
+    }
+    int stop = -2;
+    if (check0) {
+        bool eq = true;
+        UNROLL for (int k = 0; k < R; ++k) {
+            const int64_t i = tid + 256 * k;
+            if (i < W) eq = eq && (((v[k] ^ m[k]) & valid_bits(i, T)) == 0);
+        }
+        if (__syncthreads_and(eq)) stop = 0;
+    }
+    for (int l = 0; stop == -2 && l < n_levels; ++l) {
+        const GP_CONST CoLevel* lp = cst(levels) + l;
+        const uint64_t* sb = (const uint64_t*)lp->sib;
+        const int fs = lp->fside;
+        const int f = fs & 3;
+        const bool right = (fs & 4) != 0;
+        bool eq = true;
+        UNROLL for (int k = 0; k < R; ++k) {
+            const int64_t i = tid + 256 * k;
+            if (i < W) {
+                const uint64_t s = sb[i];
+                v[k] = right ? bop_rt(f, s, v[k]) : bop_rt(f, v[k], s);
+                m[k] = right ? bop_rt(f, s, m[k]) : bop_rt(f, m[k], s);
+                eq = eq && (((v[k] ^ m[k]) & valid_bits(i, T)) == 0);
+            }
+        }
+        if (__syncthreads_and(eq)) stop = level_base + l + 1;
+    }
+    if (stop == -2 && last) stop = -1;
+    if (tid == 0) p.stop_out[slot] = stop;
+    uint64_t* ro = p.root_out ? (uint64_t*)p.root_out + slot * p.stride : nullptr;
+    if (stop >= 0) {
+        if (ro)
+            for (int64_t i = tid; i < W; i += 256) ro[i] = pvec[i];
+        if (tid == 0) ((int64_t*)p.fit_out)[slot] = *pfit;
+    } else if (stop == -1) {
+        const uint64_t* t = (const uint64_t*)p.target;
+        int64_t hits = 0;
+        UNROLL for (int k = 0; k < R; ++k) {
+            const int64_t i = tid + 256 * k;
+            if (i < W) {
+                if (ro) ro[i] = v[k];
+                hits += __popcll(~(v[k] ^ t[i]) & valid_bits(i, T));
+            }
+        }
+        const int64_t h = block_sum_i64(hits, red);
+        if (tid == 0) ((int64_t*)p.fit_out)[slot] = h;
+    } else {
+        UNROLL for (int k = 0; k < R; ++k) {
+            const int64_t i = tid + 256 * k;
+            if (i < W) {
+                vout[i] = v[k];
+                mout[i] = m[k];
+            }
+        }
+    }
+}
+
+hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipStream_t s)
+{
+    if (n_children <= 0) return hipSuccess;
+    if (n_children > 0x7fffffff) return hipErrorInvalidValue;
+    if (vtype == 1) {
+        const int64_t W = (p.n_valid + 63) / 64;
+        const int rows = W <= 256 ? 1 : (int)((W + 255) / 256);
+        if (rows == 1) hipLaunchKernelGGL(k_coeval_bool<1>, dim3((unsigned)n_children), dim3(256), 0, s, p);
+        else if (rows == 2) hipLaunchKernelGGL(k_coeval_bool<2>, dim3((unsigned)n_children), dim3(256), 0, s, p);
+        else if (rows <= 4) hipLaunchKernelGGL(k_coeval_bool<4>, dim3((unsigned)n_children), dim3(256), 0, s, p);
+        else if (rows <= 16) hipLaunchKernelGGL(k_coeval_bool<16>, dim3((unsigned)n_children), dim3(256), 0, s, p);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    switch (halving_rows(p.P)) {
+    case 1: hipLaunchKernelGGL(k_coeval_f32<1>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL(k_coeval_f32<2>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 4: hipLaunchKernelGGL(k_coeval_f32<4>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 8: hipLaunchKernelGGL(k_coeval_f32<8>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 16: hipLaunchKernelGGL(k_coeval_f32<16>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 32: hipLaunchKernelGGL(k_coeval_f32<32>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    case 64: hipLaunchKernelGGL(k_coeval_f32<64>, dim3((unsigned)n_children), dim3(256), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- splice
 // Children are built from three contiguous byte ranges each (the mother's
 // nodes before the replaced subtree, the donor, the mother's nodes after it;

@@ -137,17 +137,25 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     std::vector<uint8_t> cut(n, 0);       // node roots a chunk of its own
     std::vector<int32_t> st;
     st.reserve(1024);
+    const bool index = opt.index_min_size > 0;
+    std::vector<int32_t> end_at(index ? n : 0);   // subtree ends, for the index of large subtrees
+    out->big_ends.clear();
 
     // One right-to-left pass: children are finished before their parent.
     for (int64_t i = n - 1; i >= 0; --i) {
         if (!is_func(ops[i])) {
             st.push_back((int32_t)i);
+            if (index) end_at[i] = (int32_t)(i + 1);
             continue;
         }
         int32_t l = st.back();
         st.pop_back();
         int32_t r = st.back();
         st.back() = (int32_t)i;
+        if (index) {
+            end_at[i] = end_at[r];
+            if (end_at[i] - i >= opt.index_min_size) out->big_ends.push_back({(int32_t)i, end_at[i]});
+        }
         rch[i] = r;
         auto cost = [&](int32_t c) { return cut[c] ? 1 : (int)need[c]; };
         auto need_of = [&]() {
@@ -183,6 +191,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         rec_of.emplace(v, id);
         return id;
     };
+    std::reverse(out->big_ends.begin(), out->big_ends.end());   // found right to left
     out->spines.clear();
     std::vector<int64_t> path;
     for (int64_t p = 0; p < n_points; ++p) {
@@ -332,6 +341,72 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         ch.path_nodes = ch.nodes + (ch.parent >= 0 ? out->chunks[ch.parent].path_nodes : 0);
     }
     return true;
+}
+
+void big_subtree_ends(const uint8_t* ops, int64_t n, int64_t min_size,
+                      std::vector<SubtreeEnd>* out)
+{
+    out->clear();
+    std::vector<std::pair<int64_t, int32_t>> st;   // open function nodes: (node, operands started)
+    st.reserve(256);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!st.empty()) ++st.back().second;
+        if (is_func(ops[i])) {
+            st.push_back({i, 0});
+            continue;
+        }
+        while (!st.empty() && st.back().second == 2) {
+            const int64_t a = st.back().first;
+            if (i + 1 - a >= min_size) out->push_back({(int32_t)a, (int32_t)(i + 1)});
+            st.pop_back();
+        }
+    }
+    std::sort(out->begin(), out->end());
+}
+
+// From the root down: at each ancestor a of c the first operand starts at
+// a + 1 and ends at end(a + 1), taken from the index or found by scanning that
+// (small) subtree; c lies in whichever operand holds it, the other operand is
+// the sibling, and the end of the next ancestor is end(a + 1) or end(a).
+void path_to_root(const uint8_t* ops, int64_t n, int64_t c, const std::vector<SubtreeEnd>& big,
+                  std::vector<PathLevel>* levels, int64_t* removed_end)
+{
+    levels->clear();
+    *removed_end = -1;
+    if (c < 0 || c >= n) return;
+    auto end_of = [&](int64_t x) -> int64_t {
+        if (!is_func(ops[x])) return x + 1;
+        auto it = std::lower_bound(big.begin(), big.end(), SubtreeEnd{(int32_t)x, -1});
+        if (it != big.end() && it->first == x) return it->second;
+        int64_t o = 0;
+        for (int64_t k = x; k < n; ++k) {
+            o += is_func(ops[k]) ? 1 : -1;
+            if (o < 0) return k + 1;
+        }
+        return n;
+    };
+    int64_t a = 0, end_a = n;
+    while (a != c) {
+        const int64_t l = a + 1, end_l = end_of(l);
+        PathLevel lv;
+        lv.node = a;
+        lv.f = ops[a] & 3;
+        if (c < end_l) {
+            lv.right = 0;
+            lv.sib_begin = end_l;
+            lv.sib_end = end_a;
+            end_a = end_l;
+            a = l;
+        } else {
+            lv.right = 1;
+            lv.sib_begin = l;
+            lv.sib_end = end_l;
+            a = end_l;
+        }
+        levels->push_back(lv);
+    }
+    *removed_end = end_a;
+    std::reverse(levels->begin(), levels->end());   // nearest the point first
 }
 
 }  // namespace gpe

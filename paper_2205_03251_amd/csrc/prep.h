@@ -12,6 +12,7 @@
 // first get a "reversed" instruction that still computes op(left, right).
 #pragma once
 #include <cstdint>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -76,12 +77,16 @@ struct Spine {
     std::vector<SpineLevel> levels;   // ancestors, nearest first
 };
 
+// (node, end of its subtree) within one tree; trees hold fewer than 2^31 nodes.
+using SubtreeEnd = std::pair<int32_t, int32_t>;
+
 struct TreeProg {
     std::vector<uint32_t> code;
     std::vector<Chunk> chunks;   // children before parents; the last is the root chunk
     int32_t max_stack = 0;       // highest slot used + 1
     int64_t n_records = 0;       // parent-cache vectors this tree records
     std::vector<Spine> spines;
+    std::vector<SubtreeEnd> big_ends;   // see CompileOptions::index_min_size
 };
 
 struct CompileOptions {
@@ -89,6 +94,7 @@ struct CompileOptions {
     int n_inputs = 1;
     int64_t chunk_nodes = 4096;  // target nodes per chunk
     int stack_slots = 16;        // register-stack slots available
+    int64_t index_min_size = 0;  // > 0: list (node, end) of subtrees this large, sorted by node
 };
 
 // Section 3.1 format check of one prefix array.
@@ -97,6 +103,29 @@ bool validate_prefix(const uint8_t* ops, int64_t n, int n_inputs, std::string* w
 // Reverse Polish to prefix.  post_to_pre[i] = prefix index of postfix node i.
 bool postfix_to_prefix(const uint8_t* post, int64_t n, int n_inputs, std::vector<uint8_t>* pre,
                        std::vector<int64_t>* post_to_pre, std::string* why);
+
+// The path from node c of a validated prefix tree up to the root, for
+// co-evaluating a child with its mother (Section 6.2): the removed subtree is
+// [c, removed_end); level k (k = 1 for c's parent, the last level for the
+// root) applies function f of ancestor `node`, with the path operand on the
+// right when `right`, and the other operand is the sibling subtree
+// [sib_begin, sib_end), a contiguous slice of the tree.
+struct PathLevel {
+    int64_t node;
+    int64_t sib_begin, sib_end;
+    int32_t f;
+    int32_t right;
+};
+// Subtree ends of every node whose subtree has at least min_size nodes, as
+// (node, end) pairs sorted by node: an index that lets path_to_root skip
+// large subtrees.  One pass over the tree.
+void big_subtree_ends(const uint8_t* ops, int64_t n, int64_t min_size,
+                      std::vector<SubtreeEnd>* out);
+// `big` is that index for the same tree (any min_size; smaller subtrees are
+// scanned).  Cost: the first-operand subtrees along the path that the index
+// does not cover, instead of the whole tree.
+void path_to_root(const uint8_t* ops, int64_t n, int64_t c, const std::vector<SubtreeEnd>& big,
+                  std::vector<PathLevel>* levels, int64_t* removed_end);
 
 // Compile one validated prefix tree.  points: crossover points (prefix
 // indices) whose parent caches must be recorded.

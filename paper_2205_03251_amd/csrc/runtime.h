@@ -105,6 +105,9 @@ struct Pop {
     // the trees' bytes in device memory (GP_KEEP_TREES), for building children
     DevBuf tree_ops;                        // load layout, 32 bytes of padding
     std::vector<int64_t> tree_off;          // [n_trees + 1]
+    // per tree, the ends of its large subtrees (built on first co-evaluation)
+    std::vector<std::vector<SubtreeEnd>> big_ends;
+    std::vector<uint8_t> big_built;
     // evaluation state
     int64_t stride = 0;                     // case stride of vecs/recs
     DevBuf vecs;                            // [n_chunks][stride]: roots are slots 0..n_trees-1
@@ -151,9 +154,12 @@ int hip_check(Ctx* c, hipError_t e, const char* what);
 
 // Compile and upload a population (prefix or postfix trees) on stream s
 // (s synchronised before return).
+// index_subtrees: keep each tree's index of large subtrees (prefix layout),
+// for co-evaluation.
 int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees,
                      const uint8_t* ops, const int64_t* offsets, const int64_t* rec_points,
-                     const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, hipStream_t s);
+                     const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, hipStream_t s,
+                     bool index_subtrees = false);
 // Assemble already compiled trees into a population and upload it on s.
 int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& progs,
                         const std::vector<int64_t>& tree_nodes, int64_t chunk_nodes, Pop* out,
@@ -181,6 +187,11 @@ struct IncOut {
 };
 int enqueue_incremental(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, const CaseSet* cs,
                         bool want_roots, hipStream_t s, IncOut* out, int64_t* launches);
+// The same outputs by co-evaluating each child with its mother instead of
+// reading parent caches (any crossover point; prefix populations).  Runs its
+// rounds synchronously on s; interp receives the nodes actually executed.
+int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, const CaseSet* cs,
+                   bool want_roots, hipStream_t s, IncOut* out, int64_t* launches, int64_t* rounds);
 int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p);
 int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_t T);
 int compile_stack_slots();

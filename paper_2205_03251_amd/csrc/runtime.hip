@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <thread>
 
 #include "runtime.h"
@@ -135,10 +136,14 @@ int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
     return -1;
 }
 
+// Subtrees of at least this many nodes are indexed for co-evaluation's path
+// search (about 1.2 % of the nodes of a random tree, 8 bytes each).
+static constexpr int64_t kBigSubtree = 4096;
+
 // -------------------------------------------------- population assembly
 int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees, const uint8_t* ops,
                      const int64_t* offsets, const int64_t* rec_points, const int64_t* rec_offsets,
-                     int64_t chunk_nodes, Pop* out, hipStream_t stream)
+                     int64_t chunk_nodes, Pop* out, hipStream_t stream, bool index_subtrees)
 {
     if (vtype != GP_F32 && vtype != GP_BOOL) return set_err(c, GP_EINVAL, "unknown value type");
     if (layout != GP_PREFIX && layout != GP_POSTFIX) return set_err(c, GP_EINVAL, "unknown layout");
@@ -161,6 +166,7 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     opt.n_inputs = n_inputs;
     opt.chunk_nodes = chunk_nodes;
     opt.stack_slots = compile_stack_slots();
+    opt.index_min_size = index_subtrees && layout == GP_PREFIX ? kBigSubtree : 0;
 
     std::vector<TreeProg> progs(n_trees);
     std::vector<std::string> errs(n_trees);
@@ -227,6 +233,11 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     for (int64_t t = 0; t < n_trees; ++t)
         if (bad[t]) return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + ": " + errs[t]);
     out->layout = layout;
+    if (opt.index_min_size > 0) {
+        out->big_ends.resize(n_trees);
+        out->big_built.assign(n_trees, 1);
+        for (int64_t t = 0; t < n_trees; ++t) out->big_ends[t].swap(progs[t].big_ends);
+    }
     return assemble_population(c, vtype, n_inputs, progs, tree_nodes, chunk_nodes, out, stream);
 }
 
@@ -572,6 +583,196 @@ int enqueue_incremental(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases
     return GP_OK;
 }
 
+// Co-evaluation (Section 6.2): the mother is re-evaluated alongside her child
+// from the crossover point up.  Round 0 evaluates every donor and every removed
+// subtree; each round then evaluates, as one batched population, the sibling
+// subtrees of the next levels of every child still walking (a budget of
+// sibling nodes per child that grows eightfold per round, at least one level),
+// and one co-evaluation launch walks those levels.  Siblings evaluated past a
+// stop are the only wasted work, bounded by the budget growth.
+int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, const CaseSet* cs,
+                   bool want_roots, hipStream_t s, IncOut* out, int64_t* launches, int64_t* rounds)
+{
+    const int64_t n = (int64_t)jobs.size();
+    if (n == 0) return GP_OK;
+    Pop* p = jobs[0].parent;
+    const int vtype = cs->vtype;
+    const size_t esz = vtype == GP_BOOL ? 8 : 4;
+    if (p->vtype != vtype) return set_err(c, GP_EINVAL, "value type mismatch");
+    if (p->layout != GP_PREFIX) return set_err(c, GP_EINVAL, "co-evaluation needs a population loaded in prefix layout");
+    if (p->host_ops.empty()) return set_err(c, GP_EINVAL, "the population keeps no copy of its trees");
+    if (p->evaluated_with != cases_h)
+        return set_err(c, GP_ENOTFOUND, "the mother population has not been evaluated on this case set; run "
+                                        "gp_evaluate_full on it first");
+    for (int64_t i = 0; i < n; ++i) {
+        const IncJob& j = jobs[i];
+        if (j.tree < 0 || j.tree >= p->n_trees)
+            return set_err(c, GP_EINVAL, "child " + std::to_string(i) + ": parent index out of range");
+        if (j.point < 0 || j.point >= p->tree_nodes[j.tree])
+            return set_err(c, GP_EINVAL, "child " + std::to_string(i) + ": crossover point out of range");
+        if (j.donor_len < 1 || !j.donor) return set_err(c, GP_EINVAL, "child " + std::to_string(i) + ": empty donor");
+    }
+    auto tree_of = [&](int64_t i) { return p->host_ops.data() + p->host_offsets[jobs[i].tree]; };
+    const int nth_max = (int)std::min<int64_t>(16, std::max(1u, std::thread::hardware_concurrency()));
+    auto parallel = [&](int64_t count, const std::function<void(int64_t)>& fn) {
+        std::atomic<int64_t> next{0};
+        auto work = [&]() {
+            for (int64_t i; (i = next++) < count;) fn(i);
+        };
+        const int nth = (int)std::min<int64_t>(nth_max, count);
+        std::vector<std::thread> th;
+        for (int k = 1; k < nth; ++k) th.emplace_back(work);
+        work();
+        for (auto& t : th) t.join();
+    };
+    // the index of large subtrees, once per tree
+    if (p->big_built.size() != (size_t)p->n_trees) {
+        p->big_built.assign(p->n_trees, 0);
+        p->big_ends.assign(p->n_trees, {});
+    }
+    std::vector<int64_t> need;
+    for (int64_t i = 0; i < n; ++i)
+        if (!p->big_built[jobs[i].tree]) {
+            p->big_built[jobs[i].tree] = 1;
+            need.push_back(jobs[i].tree);
+        }
+    parallel((int64_t)need.size(), [&](int64_t k) {
+        const int64_t t = need[k];
+        big_subtree_ends(p->host_ops.data() + p->host_offsets[t], p->tree_nodes[t], kBigSubtree, &p->big_ends[t]);
+    });
+    std::vector<std::vector<PathLevel>> path(n);
+    std::vector<int64_t> rend(n);
+    parallel(n, [&](int64_t i) {
+        path_to_root(tree_of(i), p->tree_nodes[jobs[i].tree], jobs[i].point, p->big_ends[jobs[i].tree], &path[i],
+                     &rend[i]);
+    });
+    out->equiv_nodes = 0;
+    out->child_nodes.assign(n, 0);
+    std::vector<int64_t> interp(n), walked(n, 0), done(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t removed = rend[i] - jobs[i].point;
+        out->child_nodes[i] = p->tree_nodes[jobs[i].tree] - removed + jobs[i].donor_len;
+        out->equiv_nodes += out->child_nodes[i];
+        interp[i] = jobs[i].donor_len + removed;
+    }
+    RC(dev_alloc(c, out->root, want_roots ? (size_t)n * cs->stride * esz : 256));
+    RC(dev_alloc(c, out->fit, (size_t)n * 8));
+    RC(dev_alloc(c, out->stop, (size_t)n * 4));
+    RC(dev_alloc(c, out->interp, (size_t)n * 8));
+    DevBuf V, M;
+    RC(dev_alloc(c, V, (size_t)n * cs->stride * esz));
+    RC(dev_alloc(c, M, (size_t)n * cs->stride * esz));
+    std::vector<int32_t> stop(n, -2);
+    std::vector<int64_t> active(n);
+    for (int64_t i = 0; i < n; ++i) active[i] = i;
+    const size_t row = (size_t)cs->stride * esz;
+    int64_t budget = 16384;
+    int64_t r = 0;
+    for (; !active.empty(); ++r, budget = std::min<int64_t>(budget * 8, int64_t(1) << 40)) {
+        struct Pick {
+            int64_t child, first, count, slot0, slot_removed, slot_donor;
+        };
+        std::vector<Pick> picks;
+        std::vector<uint8_t> ops;
+        std::vector<int64_t> offs{0};
+        auto add = [&](const uint8_t* b, int64_t len) {
+            ops.insert(ops.end(), b, b + len);
+            offs.push_back((int64_t)ops.size());
+            return (int64_t)offs.size() - 2;
+        };
+        for (int64_t i : active) {
+            const uint8_t* t = tree_of(i);
+            Pick pk{i, done[i], 0, 0, -1, -1};
+            if (r == 0) {
+                pk.slot_removed = add(t + jobs[i].point, rend[i] - jobs[i].point);
+                pk.slot_donor = add(jobs[i].donor, jobs[i].donor_len);
+            }
+            pk.slot0 = (int64_t)offs.size() - 1;
+            int64_t k = done[i], sum = 0;
+            while (k < (int64_t)path[i].size()) {
+                const int64_t len = path[i][k].sib_end - path[i][k].sib_begin;
+                if (k > pk.first && sum + len > budget) break;
+                add(t + path[i][k].sib_begin, len);
+                sum += len;
+                ++k;
+            }
+            pk.count = k - pk.first;
+            interp[i] += sum;
+            done[i] = k;
+            picks.push_back(pk);
+        }
+        Pop rp;
+        RC(build_population(c, vtype, GP_PREFIX, p->n_inputs, (int64_t)offs.size() - 1, ops.data(), offs.data(),
+                            nullptr, nullptr, 0, &rp, s));
+        const int variant = choose_variant(c, vtype, cs, &rp);
+        if (variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the sibling subtrees");
+        RC(enqueue_full(c, &rp, cases_h, cs, variant, false, false, s, launches));
+        const uint8_t* rv = (const uint8_t*)rp.vecs.p;
+        std::vector<CoLevel> lv;
+        std::vector<int64_t> lv_at(picks.size());
+        for (size_t j = 0; j < picks.size(); ++j) {
+            const Pick& pk = picks[j];
+            lv_at[j] = (int64_t)lv.size();
+            for (int64_t q = 0; q < pk.count; ++q) {
+                const PathLevel& L = path[pk.child][pk.first + q];
+                lv.push_back(CoLevel{rv + (size_t)(pk.slot0 + q) * row, L.f | (L.right ? 4 : 0), 0});
+            }
+        }
+        DevBuf lvd, chd;
+        if (lv.empty()) lv.push_back(CoLevel{nullptr, 0, 0});      // never read: every n_levels is 0
+        RC(upload(c, lvd, lv.data(), lv.size() * sizeof(CoLevel), s));
+        std::vector<CoChild> ch(picks.size());
+        for (size_t j = 0; j < picks.size(); ++j) {
+            const Pick& pk = picks[j];
+            const int64_t i = pk.child, t = jobs[i].tree;
+            CoChild& cc = ch[j];
+            uint8_t* vi = V.as<uint8_t>() + (size_t)i * row;
+            uint8_t* mi = M.as<uint8_t>() + (size_t)i * row;
+            cc.v_in = r == 0 ? (const void*)(rv + (size_t)pk.slot_donor * row) : vi;
+            cc.m_in = r == 0 ? (const void*)(rv + (size_t)pk.slot_removed * row) : mi;
+            cc.v_out = vi;
+            cc.m_out = mi;
+            cc.levels = lvd.as<CoLevel>() + lv_at[j];
+            cc.parent_vec = (const uint8_t*)p->vecs.p + (size_t)t * row;
+            cc.parent_fit = (const uint8_t*)p->fit.p + (size_t)t * 8;
+            cc.n_levels = (int32_t)pk.count;
+            cc.level_base = (int32_t)pk.first;
+            cc.check0 = r == 0 ? 1 : 0;
+            cc.last = pk.first + pk.count == (int64_t)path[i].size() ? 1 : 0;
+            cc.out_slot = (int32_t)i;
+            cc.pad = 0;
+        }
+        if (lv.size() > 0x7fffffff || n > 0x7fffffff) return set_err(c, GP_EINVAL, "too many children or levels");
+        RC(upload(c, chd, ch.data(), ch.size() * sizeof(CoChild), s));
+        CoParams cp;
+        cp.children = chd.as<CoChild>();
+        cp.target = cs->target.p;
+        cp.root_out = want_roots ? out->root.p : nullptr;
+        cp.fit_out = out->fit.p;
+        cp.stop_out = out->stop.as<int32_t>();
+        cp.stride = cs->stride;
+        cp.n_valid = cs->T;
+        cp.P = cs->P;
+        HIPC(c, launch_coeval(vtype, cp, (int64_t)picks.size(), s));
+        if (launches) ++*launches;
+        HIPC(c, hipMemcpyAsync(stop.data(), out->stop.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        std::vector<int64_t> still;
+        for (const Pick& pk : picks) {
+            const int64_t i = pk.child;
+            const int32_t st = stop[i];
+            walked[i] = st >= 0 ? st : pk.first + pk.count;
+            if (st == -2) still.push_back(i);
+        }
+        active.swap(still);
+    }
+    for (int64_t i = 0; i < n; ++i) interp[i] += 2 * walked[i];
+    RC(upload(c, out->interp, interp.data(), (size_t)n * 8, s));
+    HIPC(c, hipStreamSynchronize(s));
+    if (rounds) *rounds = r;
+    return GP_OK;
+}
+
 }  // namespace gpe
 
 using namespace gpe;
@@ -724,8 +925,12 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
     HIPC(ctx, hipSetDevice(ctx->device));
     auto p = std::make_shared<Pop>();
     RC(build_population(ctx, vtype, layout, n_inputs, n_trees, ops, offsets, record_points, record_offsets,
-                        chunk_nodes, p.get(), ctx->stream));
+                        chunk_nodes, p.get(), ctx->stream, true));
     p->auto_chunk = chunk_nodes <= 0;
+    // host copy of the trees: re-chunking by the autotuner, sibling subtrees
+    // for co-evaluation
+    p->host_ops.assign(ops, ops + offsets[n_trees]);
+    p->host_offsets.assign(offsets, offsets + n_trees + 1);
     if (flags & GP_KEEP_TREES) {
         const size_t nb = (size_t)offsets[n_trees];
         RC(dev_alloc(ctx, p->tree_ops, nb + 32));
@@ -734,8 +939,6 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
         HIPC(ctx, hipStreamSynchronize(ctx->stream));
     }
     if (p->auto_chunk) {
-        p->host_ops.assign(ops, ops + offsets[n_trees]);
-        p->host_offsets.assign(offsets, offsets + n_trees + 1);
         if (record_points) {
             p->host_rec_offsets.assign(record_offsets, record_offsets + n_trees + 1);
             p->host_rec_points.assign(record_points, record_points + record_offsets[n_trees]);
@@ -927,8 +1130,13 @@ int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, i
     }
     IncOut io;
     int64_t launches = 0;
+    if ((flags & GP_COEVAL) && (flags & GP_ASYNC))
+        return set_err(ctx, GP_EINVAL, "GP_COEVAL runs synchronously; GP_ASYNC is not accepted with it");
     HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    RC(enqueue_incremental(ctx, jobs, cases, cs, root_out != nullptr, ctx->stream, &io, &launches));
+    if (flags & GP_COEVAL)
+        RC(enqueue_coeval(ctx, jobs, cases, cs, root_out != nullptr, ctx->stream, &io, &launches, nullptr));
+    else
+        RC(enqueue_incremental(ctx, jobs, cases, cs, root_out != nullptr, ctx->stream, &io, &launches));
     HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
     RC(copy_out(ctx, root_out, io.root.p, n_children, cs->n_elems, cs->stride, esz, flags));
@@ -1172,6 +1380,8 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         best_pop->host_rec_offsets.swap(p->host_rec_offsets);
         best_pop->tree_ops.swap(p->tree_ops);
         best_pop->tree_off.swap(p->tree_off);
+        best_pop->big_ends.swap(p->big_ends);
+        best_pop->big_built.swap(p->big_built);
         ctx->pops[pop] = best_pop;
         p = best_pop.get();
         RC(enqueue_full(ctx, p, cases, cs, best, false, true, ctx->stream, nullptr));
@@ -1189,6 +1399,27 @@ int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n)
 {
     if ((vtype != GP_F32 && vtype != GP_BOOL) || n_inputs < 1 || n_inputs > kMaxInputs || !ops) return GP_EINVAL;
     return validate_prefix(ops, n, n_inputs, nullptr) ? GP_OK : GP_EINVAL;
+}
+
+int64_t gp_inspect_path(const uint8_t* ops, int64_t n, int64_t c, int64_t index_min_size, int64_t* levels_out,
+                        int64_t level_cap, int64_t* removed_end)
+{
+    if (!ops || !levels_out || !removed_end || c < 0 || c >= n) return GP_EINVAL;
+    if (!validate_prefix(ops, n, kMaxInputs, nullptr)) return GP_EINVAL;
+    std::vector<SubtreeEnd> big;
+    if (index_min_size > 0) big_subtree_ends(ops, n, index_min_size, &big);
+    std::vector<PathLevel> lv;
+    int64_t e = -1;
+    path_to_root(ops, n, c, big, &lv, &e);
+    if ((int64_t)lv.size() > level_cap) return GP_ENOMEM;
+    for (size_t k = 0; k < lv.size(); ++k) {
+        levels_out[4 * k + 0] = lv[k].node;
+        levels_out[4 * k + 1] = lv[k].sib_begin;
+        levels_out[4 * k + 2] = lv[k].sib_end;
+        levels_out[4 * k + 3] = lv[k].f | (lv[k].right ? 4 : 0);
+    }
+    *removed_end = e;
+    return (int64_t)lv.size();
 }
 
 int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t n, int64_t chunk_nodes,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgpeval.so")
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EBUDGET, GP_EDEVICE, GP_ENOTFOUND, GP_EBUSY = 0, -1, -2, -3, -4, -5, -6
 GP_F32, GP_BOOL = 0, 1
 GP_PREFIX, GP_POSTFIX = 0, 1
-GP_DEVICE_PTR, GP_ASYNC, GP_PER_TREE, GP_NO_GRAPH, GP_KEEP_TREES = 0x1, 0x2, 0x4, 0x8, 0x10
+GP_DEVICE_PTR, GP_ASYNC, GP_PER_TREE, GP_NO_GRAPH, GP_KEEP_TREES, GP_COEVAL = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 GP_JOB_FULL, GP_JOB_INCREMENTAL = 0, 1
 ERRNAMES = {GP_EINVAL: "EINVAL", GP_ENOMEM: "ENOMEM", GP_EBUDGET: "EBUDGET", GP_EDEVICE: "EDEVICE",
             GP_ENOTFOUND: "ENOTFOUND", GP_EBUSY: "EBUSY"}
@@ -129,6 +129,8 @@ def lib() -> C.CDLL:
                                      C.POINTER(I64), C.POINTER(C.c_int32)]
     h.gp_inspect_program.restype = I64
     h.gp_validate_tree.argtypes = [C.c_int, C.c_int, P, I64]
+    h.gp_inspect_path.argtypes = [P, I64, I64, I64, P, I64, C.POINTER(I64)]
+    h.gp_inspect_path.restype = I64
     _lib = h
     return h
 
@@ -162,6 +164,19 @@ class Program:
     chunks: np.ndarray     # [n_chunks, 4] int64: code offset, length, parent, n_inputs
     inputs: list           # per chunk: child chunk ids in LOAD order
     max_stack: int
+
+
+def inspect_path(tree, c, index_min_size=4096):
+    """(levels [k][4]: ancestor, sibling begin, sibling end, f | 4*right;
+    end of c's subtree) for node c of a prefix tree (gp_inspect_path)."""
+    t = _np(tree, np.uint8)
+    cap = len(t) + 1
+    out = np.zeros((cap, 4), np.int64)
+    e = I64(0)
+    r = lib().gp_inspect_path(_ptr(t), len(t), c, index_min_size, _ptr(out), cap, C.byref(e))
+    if r < 0:
+        raise GPError(int(r), "inspect_path failed")
+    return out[:r].copy(), e.value
 
 
 def inspect_program(tree, vtype=GP_F32, n_inputs=1, chunk_nodes=4096, stack_slots=16) -> Program:
@@ -334,14 +349,14 @@ class Context:
         return r, f, st.as_dict()
 
     def evaluate_incremental(self, pop, cases, vtype, n_cases, parent, point, donor_ops, donor_offsets,
-                             roots=True, device=False):
+                             roots=True, device=False, coeval=False):
         parent = _np(parent, np.int64)
         point = _np(point, np.int64)
         donor_ops = _np(donor_ops, np.uint8)
         donor_offsets = _np(donor_offsets, np.int64)
         n = len(parent)
         shape, vdt, fdt = self._out_shape(vtype, n, n_cases)
-        flags = 0
+        flags = GP_COEVAL if coeval else 0
         if device:
             import torch
             flags |= GP_DEVICE_PTR

@@ -362,6 +362,103 @@ def test_incremental_boolean_matches_oracle(ctx):
     ctx.free(ch)
 
 
+def _coeval_bounds(P, c, D, walked):
+    """Lower and upper bounds of the co-evaluation's executed-node count: the
+    siblings of the walked levels at least, every sibling at most."""
+    from paper_2205_03251_amd.gpeval import inspect_path
+    levels, e = inspect_path(P, c)
+    sib = [int(r[2] - r[1]) for r in levels]
+    base = len(D) + (e - c) + 2 * walked
+    return base + sum(sib[:walked]), base + sum(sib)
+
+
+@pytest.mark.parametrize("T,vtype", [(300, "f32"), (1024, "f32"), (64, "bool")])
+def test_coeval_matches_cached_walk_and_oracle(ctx, T, vtype):
+    """Co-evaluating the mother (no parent caches) gives the cached walk's
+    outputs, fitness and stop levels, and the oracle's, also for points that
+    were never recorded."""
+    boolean = vtype == "bool"
+    nt = 6 if boolean else 1
+    parents = gen.sized_population(35, 10, 101, 20001, n_terms=nt, vtype=gen.VT_BOOL if boolean else gen.VT_F32)
+    kids = gen.crossover_children(36, parents, 60, donor_hi=200, neutral_frac=0.5, n_terms=nt, one_per_parent=False)
+    extra = gen.crossover_children(37, parents, 20, donor_hi=50, neutral_frac=0.3, n_terms=nt, one_per_parent=False)
+    extra.point[:4] = 0                                   # the whole tree replaced
+    gt = g.GP_BOOL if boolean else g.GP_F32
+    if boolean:
+        cases = gen.bool_cases(6)
+        ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, 64)
+    else:
+        cases = gen.float_cases(39, T)
+        ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    rp, ro = record_lists(parents, kids)
+    ph = ctx.load_population(gt, parents.ops, parents.offsets, n_inputs=nt, record_points=rp, record_offsets=ro)
+    ctx.evaluate_full(ph, ch, gt, parents.n_trees, T)
+    r1, f1, i1 = ctx.evaluate_incremental(ph, ch, gt, T, kids.parent, kids.point, kids.donors.ops, kids.donors.offsets)
+    r2, f2, i2 = ctx.evaluate_incremental(ph, ch, gt, T, kids.parent, kids.point, kids.donors.ops, kids.donors.offsets,
+                                          coeval=True)
+    assert np.array_equal(i1["stop_level"], i2["stop_level"])
+    if boolean:
+        assert np.array_equal(r1, r2) and np.array_equal(f1, f2)
+    else:
+        assert same_f32(r1, r2).all()
+        assert all(fit_equal(a, b) for a, b in zip(f1, f2))
+    assert np.array_equal(i1["child_nodes"], i2["child_nodes"])
+    # points never recorded: only co-evaluation can take them
+    recorded = set(zip(kids.parent.tolist(), kids.point.tolist()))
+    j = next(i for i in range(len(extra.parent)) if (int(extra.parent[i]), int(extra.point[i])) not in recorded)
+    dj = gen.pack([extra.donors.tree(j)])
+    with pytest.raises(g.GPError) as e:
+        ctx.evaluate_incremental(ph, ch, gt, T, extra.parent[j:j + 1], extra.point[j:j + 1], dj.ops, dj.offsets)
+    assert e.value.code == g.GP_ENOTFOUND
+    r3, f3, i3 = ctx.evaluate_incremental(ph, ch, gt, T, extra.parent, extra.point, extra.donors.ops,
+                                          extra.donors.offsets, coeval=True)
+    for i in range(len(extra.parent)):
+        P = parents.tree(int(extra.parent[i]))
+        c = int(extra.point[i])
+        D = extra.donors.tree(i)
+        if boolean:
+            w_root, w_lvl, _, w_fit = oracle.incremental_bool(P, c, D, cases.inputs, cases.target, 64)
+            assert np.array_equal(r3[i], w_root) and f3[i] == w_fit
+        else:
+            with np.errstate(all="ignore"):
+                w_root, w_lvl, _, w_fit = oracle.incremental_f32(P, c, D, cases.x, cases.y)
+            assert same_f32(r3[i], w_root).all() and fit_equal(f3[i], w_fit)
+        assert i3["stop_level"][i] == w_lvl, (i, i3["stop_level"][i], w_lvl)
+        walked = w_lvl if w_lvl >= 0 else len(g.inspect_path(P, c)[0])
+        lo, hi = _coeval_bounds(P, c, D, walked)
+        assert lo <= i3["interpreted_nodes"][i] <= hi, (i, lo, i3["interpreted_nodes"][i], hi)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_coeval_errors(ctx):
+    cases = gen.float_cases(41, 64)
+    pop = gen.sized_population(42, 3, 11, 101)
+    d = gen.pack([np.array([0], np.uint8)])
+    ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    ph = ctx.load_population(g.GP_F32, pop.ops, pop.offsets)
+    with pytest.raises(g.GPError) as e:                       # mother not evaluated yet
+        ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [0], [1], d.ops, d.offsets, coeval=True)
+    assert e.value.code == g.GP_ENOTFOUND
+    ctx.evaluate_full(ph, ch, g.GP_F32, 3, 64)
+    with pytest.raises(g.GPError) as e:                       # point out of range
+        ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [0], [10 ** 6], d.ops, d.offsets, coeval=True)
+    assert e.value.code == g.GP_EINVAL
+    bad = gen.pack([np.array([gen.F_ADD, 0], np.uint8)])
+    with pytest.raises(g.GPError) as e:                       # malformed donor
+        ctx.evaluate_incremental(ph, ch, g.GP_F32, 64, [0], [1], bad.ops, bad.offsets, coeval=True)
+    assert e.value.code == g.GP_EINVAL
+    post = ctx.load_population(g.GP_F32, np.array([0, 0, gen.F_ADD], np.uint8), np.array([0, 3], np.int64),
+                               layout=g.GP_POSTFIX)
+    ctx.evaluate_full(post, ch, g.GP_F32, 1, 64)
+    with pytest.raises(g.GPError) as e:                       # reverse Polish population
+        ctx.evaluate_incremental(post, ch, g.GP_F32, 64, [0], [0], d.ops, d.offsets, coeval=True)
+    assert e.value.code == g.GP_EINVAL
+    ctx.free(post)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
 def test_incremental_errors(ctx):
     parents = gen.sized_population(51, 3, 11, 101)
     cases = gen.float_cases(52, 64)

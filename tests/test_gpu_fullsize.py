@@ -123,6 +123,14 @@ def test_incremental_full_size_sampled(ctx):
         assert info["interpreted_nodes"][i] == w_int
         assert same_f32(roots[i], w_root).all()
         assert fit[i] == w_fit or (math.isnan(fit[i]) and math.isnan(w_fit))
+    # the paper's form: the mother co-evaluated alongside, no parent caches
+    r2, f2, i2 = ctx.evaluate_incremental(ph, ch, g.GP_F32, 1024, kids.parent, kids.point, kids.donors.ops,
+                                          kids.donors.offsets, coeval=True)
+    say("co-evaluation full size:", round(i2["wall_ms"], 1), "ms,", int(i2["interpreted_nodes"].sum()),
+        "nodes executed,", i2["launches"], "launches")
+    assert np.array_equal(i2["stop_level"], stop)
+    assert same_f32(r2, roots).all()
+    assert all(a == b or (math.isnan(a) and math.isnan(b)) for a, b in zip(f2, fit))
     # all 500 children built on the device, byte for byte against the oracle's splice
     ops, offs, sst = ctx.splice_children(ph, kids.parent, kids.point, kids.donors.ops, kids.donors.offsets,
                                          device=True)

@@ -163,3 +163,27 @@ def test_chunk_sizes_bounded():
         # each chunk holds fewer than 2C nodes; its instructions fewer than that
         assert lens.max() < 2 * C + 8
         assert len(prog.chunks) >= 50_001 // (2 * C + 2)
+
+
+def test_inspect_path_matches_brute_force():
+    """The co-evaluation path (ancestors nearest first, which side the path
+    runs, the sibling subtree's slice) against a brute force from subtree
+    ends, for every node of random trees."""
+    rng = np.random.default_rng(17)
+    for size in [1, 3, 5, 41, 333, 2001]:
+        for _ in range(3):
+            t = gen.sized_tree(rng, size)
+            ends = gen.subtree_ends(t)
+            for c in range(len(t)):
+                levels, e = g.inspect_path(t, c, index_min_size=[0, 3, 64][c % 3])
+                assert e == ends[c]
+                anc = [a for a in range(c) if ends[a] > c]          # nodes whose subtree holds c
+                assert [int(r[0]) for r in levels] == anc[::-1]
+                for r, a in zip(levels, anc[::-1]):
+                    left_end = int(ends[a + 1])
+                    right = c >= left_end
+                    sib = (a + 1, left_end) if right else (left_end, int(ends[a]))
+                    assert (int(r[1]), int(r[2])) == sib
+                    assert int(r[3]) == (int(t[a]) & 3) | (4 if right else 0)
+    with pytest.raises(g.GPError):
+        g.inspect_path(np.array([gen.F_ADD, 0], np.uint8), 0)      # malformed
