@@ -182,8 +182,10 @@ int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags
  * population must be in prefix layout and fully evaluated on `cases` (her root
  * vector and fitness are the child's on a stop).  Results and stop levels are
  * those of the cached form; res[i].interpreted_nodes then counts the nodes
- * actually executed: donor + removed subtree + sibling subtrees evaluated +
- * two per level walked (child and mother).  Runs synchronously (no GP_ASYNC). */
+ * actually executed: donor + the parts of the removed and sibling subtrees
+ * that were evaluated (float32: parts that are whole chunks of the mother are
+ * read from her last full evaluation instead) + two per level walked (child
+ * and mother).  Runs synchronously (no GP_ASYNC). */
 int gp_evaluate_incremental_batch(gp_ctx* ctx, gp_handle pop, gp_handle cases, int64_t n_children,
                                   const int64_t* parent, const int64_t* point,
                                   const uint8_t* donor_ops, const int64_t* donor_offsets,

@@ -145,5 +145,7 @@ hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t 
 hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s);
 hipError_t launch_splice(const SpliceItem* items, int64_t n_items, uint8_t* out, hipStream_t s);
 hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipStream_t s);
+hipError_t launch_gather_rows(const void* src, const int64_t* src_rows, int64_t n_rows, int64_t row_bytes, void* dst,
+                              hipStream_t s);
 
 }  // namespace gpe

@@ -954,6 +954,26 @@ hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipSt
     return hipGetLastError();
 }
 
+// Row k of dst = row src_rows[k] of src (rows of row_bytes, a multiple of 16):
+// chunk values of a mother gathered into an input matrix for co-evaluation.
+__global__ __launch_bounds__(256) void k_gather_rows(const uint4* src, const int64_t* src_rows, uint4* dst,
+                                                     int64_t row_u4)
+{
+    const int64_t k = blockIdx.x;
+    const int64_t r = src_rows[k];
+    for (int64_t i = threadIdx.x; i < row_u4; i += 256) dst[k * row_u4 + i] = src[r * row_u4 + i];
+}
+
+hipError_t launch_gather_rows(const void* src, const int64_t* src_rows, int64_t n_rows, int64_t row_bytes, void* dst,
+                              hipStream_t s)
+{
+    if (n_rows <= 0) return hipSuccess;
+    if (n_rows > 0x7fffffff || row_bytes % 16 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)n_rows), dim3(256), 0, s, (const uint4*)src, src_rows,
+                       (uint4*)dst, row_bytes / 16);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- splice
 // Children are built from three contiguous byte ranges each (the mother's
 // nodes before the replaced subtree, the donor, the mother's nodes after it;

@@ -118,7 +118,7 @@ bool postfix_to_prefix(const uint8_t* post, int64_t n, int n_inputs, std::vector
 }
 
 bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, const int64_t* points,
-                  int64_t n_points, TreeProg* out, std::string* why)
+                  int64_t n_points, TreeProg* out, std::string* why, const int32_t* ext)
 {
     const bool boolean = opt.vtype == 1;
     const int S = opt.stack_slots;
@@ -129,7 +129,8 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     }
     // Float folds terminal 0 (kept in registers); Boolean folds any terminal
     // (read from the staged input words).
-    auto foldable = [&](int64_t v) { return !is_func(ops[v]) && (boolean || ops[v] == 0); };
+    auto external = [&](int64_t v) { return ext != nullptr && ext[v] >= 0; };
+    auto foldable = [&](int64_t v) { return !is_func(ops[v]) && !external(v) && (boolean || ops[v] == 0); };
 
     std::vector<int32_t> rch(n, -1);      // right child of each function node
     std::vector<uint8_t> need(n, 1);      // stack slots to produce the value
@@ -253,6 +254,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         Chunk& ch = out->chunks[k];
         int64_t root = roots[k];
         ch.root_node = root;
+        ch.end_node = index ? end_at[root] : -1;
         ch.code_off = (int64_t)out->code.size();
         ch.nodes = 0;
         fr.clear();
@@ -273,7 +275,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
                 }
                 ch.nodes += 1;
                 if (!is_func(ops[v])) {
-                    out->code.push_back(ins_word(0, M_PUSH, d, ops[v]));
+                    out->code.push_back(ins_word(0, M_PUSH, d, external(v) ? (uint32_t)ext[v] : ops[v]));
                     fr.pop_back();
                     continue;
                 }

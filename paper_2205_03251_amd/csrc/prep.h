@@ -59,6 +59,7 @@ struct Chunk {
     int64_t root_node = 0;       // prefix index of the chunk's root
     int64_t nodes = 0;           // tree nodes evaluated by this chunk
     int64_t path_nodes = 0;      // nodes on the longest chunk chain from here to the tree root
+    int64_t end_node = -1;       // end of the root's subtree (with CompileOptions::index_min_size)
     std::vector<int32_t> inputs; // local chunk ids read by LOAD payload 0, 1, ...
 };
 
@@ -128,8 +129,10 @@ void path_to_root(const uint8_t* ops, int64_t n, int64_t c, const std::vector<Su
                   std::vector<PathLevel>* levels, int64_t* removed_end);
 
 // Compile one validated prefix tree.  points: crossover points (prefix
-// indices) whose parent caches must be recorded.
+// indices) whose parent caches must be recorded.  ext (may be null): per
+// node, -1 or the row of the input matrix that a terminal node stands for; such
+// a node is pushed from that row instead of being read as its input.
 bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, const int64_t* points,
-                  int64_t n_points, TreeProg* out, std::string* why);
+                  int64_t n_points, TreeProg* out, std::string* why, const int32_t* ext = nullptr);
 
 }  // namespace gpe

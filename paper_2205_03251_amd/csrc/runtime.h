@@ -108,6 +108,12 @@ struct Pop {
     // per tree, the ends of its large subtrees (built on first co-evaluation)
     std::vector<std::vector<SubtreeEnd>> big_ends;
     std::vector<uint8_t> big_built;
+    // per tree, its chunk roots sorted by node: after a full evaluation their
+    // vectors sit in vecs[slot] (kept with the subtree index)
+    struct CutSlot {
+        int32_t node, end, slot;
+    };
+    std::vector<std::vector<CutSlot>> cuts;
     // evaluation state
     int64_t stride = 0;                     // case stride of vecs/recs
     DevBuf vecs;                            // [n_chunks][stride]: roots are slots 0..n_trees-1
@@ -156,10 +162,12 @@ int hip_check(Ctx* c, hipError_t e, const char* what);
 // (s synchronised before return).
 // index_subtrees: keep each tree's index of large subtrees (prefix layout),
 // for co-evaluation.
+// ext_rows (prefix layout, may be null): per byte of ops, -1 or the input row
+// a terminal stands for (see compile_tree).
 int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees,
                      const uint8_t* ops, const int64_t* offsets, const int64_t* rec_points,
                      const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, hipStream_t s,
-                     bool index_subtrees = false);
+                     bool index_subtrees = false, const int32_t* ext_rows = nullptr);
 // Assemble already compiled trees into a population and upload it on s.
 int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& progs,
                         const std::vector<int64_t>& tree_nodes, int64_t chunk_nodes, Pop* out,

@@ -143,7 +143,8 @@ static constexpr int64_t kBigSubtree = 4096;
 // -------------------------------------------------- population assembly
 int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_trees, const uint8_t* ops,
                      const int64_t* offsets, const int64_t* rec_points, const int64_t* rec_offsets,
-                     int64_t chunk_nodes, Pop* out, hipStream_t stream, bool index_subtrees)
+                     int64_t chunk_nodes, Pop* out, hipStream_t stream, bool index_subtrees,
+                     const int32_t* ext_rows)
 {
     if (vtype != GP_F32 && vtype != GP_BOOL) return set_err(c, GP_EINVAL, "unknown value type");
     if (layout != GP_PREFIX && layout != GP_POSTFIX) return set_err(c, GP_EINVAL, "unknown layout");
@@ -215,7 +216,8 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
                 bad[t] = 1;
                 continue;
             }
-            if (!compile_tree(tree, n, opt, pts.data(), (int64_t)pts.size(), &progs[t], &errs[t])) {
+            const int32_t* ext = (ext_rows && layout == GP_PREFIX) ? ext_rows + offsets[t] : nullptr;
+            if (!compile_tree(tree, n, opt, pts.data(), (int64_t)pts.size(), &progs[t], &errs[t], ext)) {
                 bad[t] = 1;
                 continue;
             }
@@ -279,6 +281,7 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
     out->leaves.clear();
     out->spines.clear();
     out->spine_of.clear();
+    out->cuts.clear();
     out->max_stack = 0;
     int64_t cbase = 0, rbase = 0, next_slot = n_trees;
     std::vector<int32_t> slot;
@@ -291,6 +294,15 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
         const int64_t nc = (int64_t)pg.chunks.size();
         slot.assign(nc, 0);
         for (int64_t k = 0; k < nc; ++k) slot[k] = (k == nc - 1) ? (int32_t)t : (int32_t)(next_slot++);
+        if (nc > 0 && progs[t].chunks[0].end_node >= 0) {
+            if (out->cuts.size() != (size_t)n_trees) out->cuts.assign(n_trees, {});
+            auto& cl = out->cuts[t];
+            cl.reserve(nc);
+            for (int64_t k = 0; k < nc; ++k)
+                cl.push_back(Pop::CutSlot{(int32_t)progs[t].chunks[k].root_node, (int32_t)progs[t].chunks[k].end_node,
+                                          slot[k]});
+            std::sort(cl.begin(), cl.end(), [](const Pop::CutSlot& a, const Pop::CutSlot& b) { return a.node < b.node; });
+        }
         for (int64_t k = 0; k < nc; ++k) {
             const Chunk& ch = pg.chunks[k];
             DevChunk& d = dch[cbase + k];
@@ -669,32 +681,86 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
     int64_t budget = 16384;
     int64_t r = 0;
     for (; !active.empty(); ++r, budget = std::min<int64_t>(budget * 8, int64_t(1) << 40)) {
+        // A subtree's vector comes from the round's population (slot) or, when
+        // the subtree is a chunk of the mother, from her last evaluation (row).
+        struct Ref {
+            int64_t slot, row;
+        };
         struct Pick {
-            int64_t child, first, count, slot0, slot_removed, slot_donor;
+            int64_t child, first, count;
+            Ref removed, donor;
+            size_t refs_at;
         };
         std::vector<Pick> picks;
+        std::vector<Ref> refs;                  // level siblings, pick after pick
         std::vector<uint8_t> ops;
+        std::vector<int32_t> ext;               // per byte of ops: -1 or the input row it stands for
+        std::vector<int64_t> ext_src;           // mother rows behind input rows n_inputs, n_inputs + 1, ...
         std::vector<int64_t> offs{0};
-        auto add = [&](const uint8_t* b, int64_t len) {
-            ops.insert(ops.end(), b, b + len);
+        const bool ckpt = vtype == GP_F32 && p->cuts.size() == (size_t)p->n_trees;
+        const int64_t row_cap = ((int64_t(1) << 31) / (int64_t)row) - p->n_inputs - 1;   // row offsets stay < 2^31
+        // Subtree [b, e) of child i's mother: chunks of the mother inside it are
+        // read from her vectors (a placeholder terminal pushed from a gathered
+        // input row); only the rest is compiled.  Returns the nodes executed.
+        auto add_sub = [&](int64_t i, int64_t b, int64_t e, Ref* ref) -> int64_t {
+            const uint8_t* t = tree_of(i);
+            int64_t nodes = 0;
+            if (ckpt) {
+                const auto& cl = p->cuts[jobs[i].tree];
+                auto lb = [&](int64_t x) {
+                    return std::lower_bound(cl.begin(), cl.end(), x,
+                                            [](const Pop::CutSlot& a, int64_t v) { return a.node < v; });
+                };
+                auto it = lb(b);
+                if (it != cl.end() && it->node == b && it->end == e) {
+                    *ref = Ref{-1, it->slot};
+                    return 0;
+                }
+                int64_t pos = b;
+                it = lb(b + 1);
+                for (;;) {
+                    const int64_t u = (it != cl.end() && it->node < e) ? it->node : e;
+                    ops.insert(ops.end(), t + pos, t + u);
+                    ext.insert(ext.end(), (size_t)(u - pos), -1);
+                    nodes += u - pos;
+                    if (u == e) break;
+                    if ((int64_t)ext_src.size() < row_cap) {
+                        ops.push_back(0);
+                        ext.push_back((int32_t)(p->n_inputs + (int64_t)ext_src.size()));
+                        ext_src.push_back(it->slot);
+                    } else {                    // no input row left: compile that chunk too
+                        ops.insert(ops.end(), t + u, t + it->end);
+                        ext.insert(ext.end(), (size_t)(it->end - u), -1);
+                        nodes += it->end - u;
+                    }
+                    pos = it->end;
+                    it = lb(pos);
+                }
+            } else {
+                ops.insert(ops.end(), t + b, t + e);
+                ext.insert(ext.end(), (size_t)(e - b), -1);
+                nodes = e - b;
+            }
             offs.push_back((int64_t)ops.size());
-            return (int64_t)offs.size() - 2;
+            *ref = Ref{(int64_t)offs.size() - 2, -1};
+            return nodes;
         };
         for (int64_t i : active) {
-            const uint8_t* t = tree_of(i);
-            Pick pk{i, done[i], 0, 0, -1, -1};
+            Pick pk{i, done[i], 0, Ref{-1, -1}, Ref{-1, -1}, refs.size()};
             if (r == 0) {
-                pk.slot_removed = add(t + jobs[i].point, rend[i] - jobs[i].point);
-                pk.slot_donor = add(jobs[i].donor, jobs[i].donor_len);
+                interp[i] += add_sub(i, jobs[i].point, rend[i], &pk.removed) - (rend[i] - jobs[i].point);
+                ops.insert(ops.end(), jobs[i].donor, jobs[i].donor + jobs[i].donor_len);
+                ext.insert(ext.end(), (size_t)jobs[i].donor_len, -1);
+                offs.push_back((int64_t)ops.size());
+                pk.donor = Ref{(int64_t)offs.size() - 2, -1};
             }
-            pk.slot0 = (int64_t)offs.size() - 1;
             int64_t k = done[i], sum = 0;
             while (k < (int64_t)path[i].size()) {
-                const int64_t len = path[i][k].sib_end - path[i][k].sib_begin;
-                if (k > pk.first && sum + len > budget) break;
-                add(t + path[i][k].sib_begin, len);
-                sum += len;
+                Ref rf;
+                sum += add_sub(i, path[i][k].sib_begin, path[i][k].sib_end, &rf);
+                refs.push_back(rf);
                 ++k;
+                if (sum > budget) break;
             }
             pk.count = k - pk.first;
             interp[i] += sum;
@@ -702,12 +768,37 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
             picks.push_back(pk);
         }
         Pop rp;
-        RC(build_population(c, vtype, GP_PREFIX, p->n_inputs, (int64_t)offs.size() - 1, ops.data(), offs.data(),
-                            nullptr, nullptr, 0, &rp, s));
-        const int variant = choose_variant(c, vtype, cs, &rp);
-        if (variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the sibling subtrees");
-        RC(enqueue_full(c, &rp, cases_h, cs, variant, false, false, s, launches));
+        CaseSet tcs;                            // the case set with the gathered mother rows appended
+        DevBuf rows_d;
+        const CaseSet* ecs = cs;
+        if (offs.size() > 1) {
+            if (!ext_src.empty()) {
+                tcs.vtype = cs->vtype;
+                tcs.n_inputs = cs->n_inputs + (int)ext_src.size();
+                tcs.T = cs->T;
+                tcs.n_elems = cs->n_elems;
+                tcs.stride = cs->stride;
+                tcs.P = cs->P;
+                RC(dev_alloc(c, tcs.inputs, (size_t)tcs.n_inputs * row));
+                HIPC(c, hipMemcpyAsync(tcs.inputs.p, cs->inputs.p, (size_t)cs->n_inputs * row, hipMemcpyDeviceToDevice, s));
+                RC(upload(c, rows_d, ext_src.data(), ext_src.size() * sizeof(int64_t), s));
+                HIPC(c, launch_gather_rows(p->vecs.p, rows_d.as<int64_t>(), (int64_t)ext_src.size(), (int64_t)row,
+                                           tcs.inputs.as<uint8_t>() + (size_t)cs->n_inputs * row, s));
+                RC(dev_alloc(c, tcs.target, row));
+                HIPC(c, hipMemcpyAsync(tcs.target.p, cs->target.p, row, hipMemcpyDeviceToDevice, s));
+                ecs = &tcs;
+            }
+            RC(build_population(c, vtype, GP_PREFIX, p->n_inputs, (int64_t)offs.size() - 1, ops.data(), offs.data(),
+                                nullptr, nullptr, 0, &rp, s, false, ext.data()));
+            const int variant = choose_variant(c, vtype, ecs, &rp);
+            if (variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the sibling subtrees");
+            RC(enqueue_full(c, &rp, cases_h, ecs, variant, false, false, s, launches));
+        }
         const uint8_t* rv = (const uint8_t*)rp.vecs.p;
+        const uint8_t* mv = (const uint8_t*)p->vecs.p;
+        auto ptr = [&](const Ref& rf) -> const void* {
+            return rf.row >= 0 ? (const void*)(mv + (size_t)rf.row * row) : (const void*)(rv + (size_t)rf.slot * row);
+        };
         std::vector<CoLevel> lv;
         std::vector<int64_t> lv_at(picks.size());
         for (size_t j = 0; j < picks.size(); ++j) {
@@ -715,7 +806,7 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
             lv_at[j] = (int64_t)lv.size();
             for (int64_t q = 0; q < pk.count; ++q) {
                 const PathLevel& L = path[pk.child][pk.first + q];
-                lv.push_back(CoLevel{rv + (size_t)(pk.slot0 + q) * row, L.f | (L.right ? 4 : 0), 0});
+                lv.push_back(CoLevel{ptr(refs[pk.refs_at + q]), L.f | (L.right ? 4 : 0), 0});
             }
         }
         DevBuf lvd, chd;
@@ -728,8 +819,8 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
             CoChild& cc = ch[j];
             uint8_t* vi = V.as<uint8_t>() + (size_t)i * row;
             uint8_t* mi = M.as<uint8_t>() + (size_t)i * row;
-            cc.v_in = r == 0 ? (const void*)(rv + (size_t)pk.slot_donor * row) : vi;
-            cc.m_in = r == 0 ? (const void*)(rv + (size_t)pk.slot_removed * row) : mi;
+            cc.v_in = r == 0 ? ptr(pk.donor) : vi;
+            cc.m_in = r == 0 ? ptr(pk.removed) : mi;
             cc.v_out = vi;
             cc.m_out = mi;
             cc.levels = lvd.as<CoLevel>() + lv_at[j];
@@ -1348,7 +1439,7 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
             const bool rec = !p->host_rec_points.empty() || !p->host_rec_offsets.empty();
             RC(build_population(ctx, p->vtype, p->layout, p->n_inputs, p->n_trees, p->host_ops.data(),
                                 p->host_offsets.data(), rec ? p->host_rec_points.data() : nullptr,
-                                rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), ctx->stream));
+                                rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), ctx->stream, true));
             qp = q.get();
         }
         for (int v = 0; v < variant_count(); ++v) {
@@ -1380,8 +1471,6 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         best_pop->host_rec_offsets.swap(p->host_rec_offsets);
         best_pop->tree_ops.swap(p->tree_ops);
         best_pop->tree_off.swap(p->tree_off);
-        best_pop->big_ends.swap(p->big_ends);
-        best_pop->big_built.swap(p->big_built);
         ctx->pops[pop] = best_pop;
         p = best_pop.get();
         RC(enqueue_full(ctx, p, cases, cs, best, false, true, ctx->stream, nullptr));

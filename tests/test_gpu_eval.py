@@ -363,20 +363,22 @@ def test_incremental_boolean_matches_oracle(ctx):
 
 
 def _coeval_bounds(P, c, D, walked):
-    """Lower and upper bounds of the co-evaluation's executed-node count: the
-    siblings of the walked levels at least, every sibling at most."""
+    """Bounds of the co-evaluation's executed-node count: the donor and two
+    nodes per walked level at least (subtrees may be read whole from the
+    mother's chunk values), the removed subtree and every sibling at most."""
     from paper_2205_03251_amd.gpeval import inspect_path
     levels, e = inspect_path(P, c)
     sib = [int(r[2] - r[1]) for r in levels]
-    base = len(D) + (e - c) + 2 * walked
-    return base + sum(sib[:walked]), base + sum(sib)
+    return len(D) + 2 * walked, len(D) + (e - c) + sum(sib) + 2 * walked
 
 
-@pytest.mark.parametrize("T,vtype", [(300, "f32"), (1024, "f32"), (64, "bool")])
-def test_coeval_matches_cached_walk_and_oracle(ctx, T, vtype):
+@pytest.mark.parametrize("T,vtype,chunk_nodes", [(300, "f32", 0), (300, "f32", 16), (1024, "f32", 0),
+                                                 (64, "bool", 0)])
+def test_coeval_matches_cached_walk_and_oracle(ctx, T, vtype, chunk_nodes):
     """Co-evaluating the mother (no parent caches) gives the cached walk's
     outputs, fitness and stop levels, and the oracle's, also for points that
-    were never recorded."""
+    were never recorded.  With 16-node chunks most float siblings and removed
+    subtrees are read from the mother's chunk values rather than evaluated."""
     boolean = vtype == "bool"
     nt = 6 if boolean else 1
     parents = gen.sized_population(35, 10, 101, 20001, n_terms=nt, vtype=gen.VT_BOOL if boolean else gen.VT_F32)
@@ -391,7 +393,8 @@ def test_coeval_matches_cached_walk_and_oracle(ctx, T, vtype):
         cases = gen.float_cases(39, T)
         ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
     rp, ro = record_lists(parents, kids)
-    ph = ctx.load_population(gt, parents.ops, parents.offsets, n_inputs=nt, record_points=rp, record_offsets=ro)
+    ph = ctx.load_population(gt, parents.ops, parents.offsets, n_inputs=nt, record_points=rp, record_offsets=ro,
+                             chunk_nodes=chunk_nodes)
     ctx.evaluate_full(ph, ch, gt, parents.n_trees, T)
     r1, f1, i1 = ctx.evaluate_incremental(ph, ch, gt, T, kids.parent, kids.point, kids.donors.ops, kids.donors.offsets)
     r2, f2, i2 = ctx.evaluate_incremental(ph, ch, gt, T, kids.parent, kids.point, kids.donors.ops, kids.donors.offsets,
