@@ -64,6 +64,16 @@ def lib():
                                           i32p, i64p, f64p]
         h.orc_incremental_bool.argtypes = [u8p, L, L, u8p, L, C.c_int, u64p, u64p, L, L, u64p,
                                            i32p, i64p, i64p]
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        h.orc_philox.argtypes = [u32p, u32p, u32p]
+        h.orc_uniform.argtypes = [C.c_uint32, C.c_uint64]
+        h.orc_uniform.restype = C.c_uint64
+        h.orc_draw.argtypes = [C.c_uint64, L, L, C.c_int, L]
+        h.orc_draw.restype = C.c_uint32
+        h.orc_tournament_f64.argtypes = [f64p, L, C.c_int, C.c_uint64, L, L, C.c_int]
+        h.orc_tournament_f64.restype = L
+        h.orc_tournament_i64.argtypes = [i64p, L, C.c_int, C.c_uint64, L, L, C.c_int]
+        h.orc_tournament_i64.restype = L
         _lib = h
     return _lib
 
@@ -213,3 +223,82 @@ def eval_population_bool(pop, inputs, target, T: int, threads: int = 1):
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(one, order))
     return outs, fits
+
+
+# ------------------------------------------------------------------ selection
+def philox(ctr, key):
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return [int(v) for v in out]
+
+
+def uniform(u: int, n: int) -> int:
+    return int(lib().orc_uniform(u, n))
+
+
+def draw(seed: int, i: int, g: int, s: int, j: int) -> int:
+    return int(lib().orc_draw(seed, i, g, s, j))
+
+
+def tournament(fit, k: int, seed: int, i: int, g: int, s: int) -> int:
+    """Winner of tournament i (stream s, generation g) over `fit`: float64
+    errors (lower wins, NaN worst) or int64 hits (higher wins)."""
+    fit = np.ascontiguousarray(fit)
+    if fit.dtype == np.float64:
+        return int(lib().orc_tournament_f64(fit, len(fit), k, seed, i, g, s))
+    return int(lib().orc_tournament_i64(np.ascontiguousarray(fit, np.int64), len(fit), k, seed, i, g, s))
+
+
+def evolve(trees, boolean: bool, cases, generations: int, k: int, seed: int):
+    """Generational GP with fitness first (Sections 5 and 6.3), as plainly as
+    possible.  Generation g creates N = len(trees) children; child i has the
+    winners of tournaments (i, g, stream 0) and (i, g, stream 1) over the
+    current fitness as mother and father, a crossover point uniform over the
+    mother's nodes (draw (i, g, 2, word 0)) and, as donor, the father's subtree
+    at a node uniform over his nodes (word 1).  Every child is scored by
+    incremental evaluation before any is built; unless g is the last
+    generation, the tournaments of generation g + 1 are drawn over the
+    children's fitness and only their winners are built.  Returns one record
+    per generation and the final trees (all built)."""
+    if boolean:
+        inputs, target, T = cases.inputs, cases.target, cases.T
+        fit = np.array([fitness_bool(eval_bool(t, inputs), target, T) for t in trees], np.int64)
+    else:
+        with np.errstate(all="ignore"):
+            fit = np.array([fitness_f32(eval_f32(t, cases.x), cases.y) for t in trees], np.float64)
+    trees = [np.asarray(t, np.uint8) for t in trees]
+    N = len(trees)
+    records = []
+    for g in range(generations):
+        mother = np.array([tournament(fit, k, seed, i, g, 0) for i in range(N)], np.int64)
+        father = np.array([tournament(fit, k, seed, i, g, 1) for i in range(N)], np.int64)
+        point = np.array([uniform(draw(seed, i, g, 2, 0), len(trees[mother[i]])) for i in range(N)], np.int64)
+        dnode = np.array([uniform(draw(seed, i, g, 2, 1), len(trees[father[i]])) for i in range(N)], np.int64)
+        cfit = np.zeros(N, np.int64 if boolean else np.float64)
+        stop = np.zeros(N, np.int32)
+        donors = []
+        for i in range(N):
+            P, F = trees[mother[i]], trees[father[i]]
+            assert P is not None and F is not None, "a tournament winner was not built"
+            D = F[dnode[i]:subtree_end(F, int(dnode[i]))].copy()
+            donors.append(D)
+            if boolean:
+                _, lvl, _, fv = incremental_bool(P, int(point[i]), D, inputs, target, T)
+            else:
+                with np.errstate(all="ignore"):
+                    _, lvl, _, fv = incremental_f32(P, int(point[i]), D, cases.x, cases.y)
+            cfit[i], stop[i] = fv, lvl
+        if g == generations - 1:
+            built = np.ones(N, bool)
+        else:
+            built = np.zeros(N, bool)
+            for j in range(N):
+                built[tournament(cfit, k, seed, j, g + 1, 0)] = True
+                built[tournament(cfit, k, seed, j, g + 1, 1)] = True
+        new = [splice(trees[mother[i]], int(point[i]), donors[i]) if built[i] else None for i in range(N)]
+        records.append({"mother": mother, "father": father, "point": point, "donor_node": dnode,
+                        "fitness": cfit, "stop_level": stop, "built": built,
+                        "nodes": np.array([len(trees[mother[i]]) - (subtree_end(trees[mother[i]], int(point[i])) -
+                                           int(point[i])) + len(donors[i]) for i in range(N)], np.int64)})
+        trees, fit = new, cfit
+    return records, trees

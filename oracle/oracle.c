@@ -436,3 +436,70 @@ int orc_incremental_bool(const uint8_t* P, int64_t n, int64_t c, const uint8_t* 
     free(end); free(path); free(child); free(mother); free(sib);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------ selection */
+
+/* Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers:
+ * as easy as 1, 2, 3", SC 2011), from its definition: ten rounds; each
+ * multiplies counter words 0 and 2 by the two round multipliers, mixes the
+ * high halves with words 1 and 3 and the round key, and the key is bumped by
+ * the two Weyl constants after each round.  The random draws of a generation
+ * are not part of the paper's method; this generator is one both sides
+ * implement from its published definition. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform integer in [0, n) from one 32-bit word: floor(u * n / 2^32), for
+ * n < 2^32. */
+uint64_t orc_uniform(uint32_t u, uint64_t n) { return ((uint64_t)u * n) >> 32; }
+
+/* Word j of stream s for index i at generation g: word j mod 4 of Philox with
+ * counter (i, g, s, j / 4) and key (seed low, seed high). */
+uint32_t orc_draw(uint64_t seed, int64_t i, int64_t g, int s, int64_t j)
+{
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)g, (uint32_t)s, (uint32_t)(j / 4)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox(ctr, key, out);
+    return out[j % 4];
+}
+
+/* Tournament of size k over n fitness values (Section 6.3): k draws uniform
+ * with replacement; a candidate replaces the current winner only if strictly
+ * better (so ties keep the earlier draw).  Float fitness is an error (lower is
+ * better, NaN worst); Boolean fitness counts hits (higher is better). */
+int64_t orc_tournament_f64(const double* fit, int64_t n, int k, uint64_t seed, int64_t i, int64_t g, int s)
+{
+    int64_t best = (int64_t)orc_uniform(orc_draw(seed, i, g, s, 0), (uint64_t)n);
+    for (int j = 1; j < k; ++j) {
+        int64_t c = (int64_t)orc_uniform(orc_draw(seed, i, g, s, j), (uint64_t)n);
+        double a = fit[c], b = fit[best];
+        if (!isnan(a) && (isnan(b) || a < b)) best = c;
+    }
+    return best;
+}
+
+int64_t orc_tournament_i64(const int64_t* fit, int64_t n, int k, uint64_t seed, int64_t i, int64_t g, int s)
+{
+    int64_t best = (int64_t)orc_uniform(orc_draw(seed, i, g, s, 0), (uint64_t)n);
+    for (int j = 1; j < k; ++j) {
+        int64_t c = (int64_t)orc_uniform(orc_draw(seed, i, g, s, j), (uint64_t)n);
+        if (fit[c] > fit[best]) best = c;
+    }
+    return best;
+}

@@ -352,3 +352,104 @@ def test_children_generator():
         if ch.neutral[i]:
             _, lvl, _, _ = oracle.incremental_f32(p, int(ch.point[i]), ch.donors.tree(i), x.x, x.y)
             assert lvl == 0
+
+
+# --------------------------------------------------- selection (Section 6.3)
+def test_philox_known_answers():
+    # Known-answer vectors of Philox-4x32-10 published with the generator
+    # (Random123): counter, key -> output.
+    assert oracle.philox((0, 0, 0, 0), (0, 0)) == [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]
+    assert oracle.philox((0xffffffff,) * 4, (0xffffffff,) * 2) == [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]
+    assert oracle.philox((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0)) == \
+        [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+
+
+def test_uniform_mapping_closed_forms():
+    for n in [1, 2, 3, 7, 1000, 2 ** 31 - 1, 2 ** 32 - 1]:
+        assert oracle.uniform(0, n) == 0
+        assert oracle.uniform(2 ** 32 - 1, n) == n - 1          # (2^32 - 1) n / 2^32 = n - n / 2^32
+        assert oracle.uniform(2 ** 31, n) == n // 2
+    # every residue of n = 3 gets floor or ceil of 2^32 / 3 words
+    edges = [0] + [-(-(2 ** 32) * r // 3) for r in (1, 2)]          # first u mapping to 1, to 2
+    assert [oracle.uniform(e, 3) for e in edges] == [0, 1, 2]
+    assert [oracle.uniform(e - 1, 3) for e in edges[1:]] == [0, 1]
+
+
+def test_draws_follow_the_counter_layout():
+    seed = 0x0123456789ABCDEF
+    words = oracle.philox((5, 9, 2, 1), (seed & 0xffffffff, seed >> 32))
+    assert [oracle.draw(seed, 5, 9, 2, j) for j in range(4, 8)] == words
+
+
+def test_tournament_properties():
+    rng = np.random.default_rng(4)
+    fit = rng.normal(size=50)
+    fit[[3, 7]] = np.nan
+    seed = 77
+    for i in range(200):
+        w1 = oracle.tournament(fit, 1, seed, i, 0, 0)
+        assert w1 == oracle.uniform(oracle.draw(seed, i, 0, 0, 0), 50)
+        for k in (2, 5):
+            w = oracle.tournament(fit, k, seed, i, 0, 0)
+            drawn = [oracle.uniform(oracle.draw(seed, i, 0, 0, j), 50) for j in range(k)]
+            assert w in drawn
+            ok = [c for c in drawn if not np.isnan(fit[c])]
+            if ok:
+                assert not np.isnan(fit[w]) and fit[w] == min(fit[c] for c in ok)
+                assert w == next(c for c in drawn if fit[c] == fit[w])       # ties keep the earlier draw
+            else:
+                assert w == drawn[0]
+    same = np.full(50, 0.25)
+    for i in range(50):                                           # all tied: the first draw wins
+        assert oracle.tournament(same, 5, seed, i, 2, 0) == oracle.uniform(oracle.draw(seed, i, 2, 0, 0), 50)
+        assert oracle.tournament(np.full(50, 7, np.int64), 5, seed, i, 2, 1) == \
+            oracle.uniform(oracle.draw(seed, i, 2, 1, 0), 50)
+    hits = rng.integers(0, 64, 50).astype(np.int64)
+    for i in range(100):
+        w = oracle.tournament(hits, 4, seed, i, 1, 1)
+        drawn = [oracle.uniform(oracle.draw(seed, i, 1, 1, j), 50) for j in range(4)]
+        assert hits[w] == max(hits[c] for c in drawn)
+
+
+def test_fitness_first_savings_closed_forms():
+    """Section 6.3: children drawn as nobody's parent need not be built.
+    Converged population, two parents per child: the chance a child is never
+    drawn in 2N tournaments is (1 - 1/N)^(2N) -> e^-2 = 13.5 % (the paper's
+    14 %).  Diverse fitness, one tournament of size k per child: a child whose
+    fitness beats a fraction 1 - x of the others wins k (1 - x)^(k - 1)
+    tournaments on average, so the share never drawn is the integral of
+    exp(-k (1 - x)^(k - 1)) over [0, 1]: 0.671 for k = 7."""
+    N = 4000
+    same = np.zeros(N, np.float64)
+    drawn = np.zeros(N, bool)
+    for j in range(N):
+        drawn[oracle.tournament(same, 7, 11, j, 1, 0)] = True
+        drawn[oracle.tournament(same, 7, 11, j, 1, 1)] = True
+    assert abs((~drawn).mean() - math.exp(-2)) < 0.03
+    distinct = np.random.default_rng(5).permutation(N).astype(np.float64)
+    drawn[:] = False
+    for j in range(N):
+        drawn[oracle.tournament(distinct, 7, 12, j, 1, 0)] = True
+    y = np.linspace(0, 1, 200001)
+    want = float(np.mean(np.exp(-7 * y ** 6)))
+    assert abs(want - 0.6707) < 1e-3
+    assert abs((~drawn).mean() - want) < 0.03
+
+
+def test_evolve_invariants_small():
+    rng = np.random.default_rng(6)
+    trees = [gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 5, 301))) for _ in range(24)]
+    cases = gen.float_cases(7, 48)
+    recs, final = oracle.evolve(trees, False, cases, 3, 3, 99)
+    assert len(recs) == 3 and all(t is not None for t in final)
+    for g, r in enumerate(recs):
+        if g < 2:
+            nxt = recs[g + 1]
+            assert r["built"][nxt["mother"]].all() and r["built"][nxt["father"]].all()
+            assert 0 < r["built"].sum() < 24
+    with np.errstate(all="ignore"):
+        for t, f in zip(final, recs[-1]["fitness"]):
+            assert oracle.validate(t)
+            out = oracle.eval_f32(t, cases.x)
+            got = oracle.fitness_f32(out, cases.y)
+            assert got == f or (math.isnan(got) and math.isnan(f))        # incremental = full evaluation

@@ -42,6 +42,12 @@ MUTANTS = {
     "splice keeps the removed subtree": ("memcpy(child + c + nd, P + e, (size_t)(n - e));",
                                          "memcpy(child + c + nd, P + c, (size_t)(n - e));"),
     "validation only checks the final count": ("if (i < n - 1 && s < 0) return ORC_EINVAL;", "(void)0;"),
+    "Philox with nine rounds": ("for (int r = 0; r < 10; ++r) {", "for (int r = 0; r < 9; ++r) {"),
+    "uniform by modulo": ("return ((uint64_t)u * n) >> 32;", "return u % n;"),
+    "draw counter without blocks": ("(uint32_t)s, (uint32_t)(j / 4)}", "(uint32_t)s, (uint32_t)j}"),
+    "tournament ties keep the later draw": ("if (!isnan(a) && (isnan(b) || a < b)) best = c;",
+                                            "if (!isnan(a) && (isnan(b) || a <= b)) best = c;"),
+    "Boolean tournament prefers fewer hits": ("if (fit[c] > fit[best]) best = c;", "if (fit[c] < fit[best]) best = c;"),
 }
 
 
