@@ -218,6 +218,64 @@ int gp_splice_children(gp_ctx* ctx, gp_handle pop, int64_t n_children, const int
                        uint32_t flags, uint8_t* child_ops, int64_t child_cap, int64_t* child_offsets,
                        gp_stats* st);
 
+/* ------------------------------------------------------------- generations */
+
+typedef struct gp_evolve_cfg {
+    int64_t generations;       /* >= 1 */
+    int32_t tournament;        /* tournament size k >= 1 */
+    int32_t reserved;
+    uint64_t seed;             /* key of the random draws (Philox-4x32-10) */
+    int64_t first_generation;  /* counter of the first generation's draws */
+} gp_evolve_cfg;
+
+typedef struct gp_gen_stats {
+    double best_f64;           /* GP_F32: lowest error among the children (NaN if all NaN) */
+    int64_t best_i64;          /* GP_BOOL: most hits among the children */
+    int64_t children;          /* N, the population size */
+    int64_t built;             /* children built: drawn as a parent by the next generation (all in the last) */
+    int64_t child_nodes;       /* nodes of all N children */
+    int64_t built_nodes;       /* nodes of the children built */
+    int64_t interpreted_nodes; /* nodes executed to score the children */
+    double ms;                 /* wall time of the generation */
+} gp_gen_stats;
+
+typedef struct gp_gen_child {
+    int64_t mother, father;    /* slots of the previous generation */
+    int64_t point;             /* crossover point in the mother (prefix index) */
+    int64_t donor_node;        /* the donor is the father's subtree at this node */
+    int64_t nodes;             /* child size */
+    double fitness_f64;        /* GP_F32 */
+    int64_t fitness_i64;       /* GP_BOOL */
+    int32_t stop_level;        /* of its incremental evaluation */
+    int32_t drawn;             /* times drawn as a parent by the next generation */
+} gp_gen_child;
+
+/* Generational GP with fitness first (Sections 5, 6.2 and 6.3).  Generation g
+ * (g = cfg->first_generation, ...) makes N = population size children: child
+ * i gets as mother and father the winners of two tournaments over the previous
+ * generation's fitness, a crossover point uniform over the mother's nodes and,
+ * as donor, the father's subtree at a node uniform over his nodes; the draws
+ * are word j of Philox-4x32-10 with counter (i, g, stream, j / 4) and key
+ * seed (streams 0 mother, 1 father, 2 point and donor node; uniform over n:
+ * floor(word * n / 2^32); k draws with replacement, the strictly better wins:
+ * lower error with NaN worst, or more hits).  Every child is scored by
+ * co-evaluation with its mother before any is built; then the tournaments of
+ * generation g + 1 are drawn over the children's fitness and only the
+ * children drawn there are built (all of them in the last generation), on the
+ * device, and evaluated as the next population.  `pop` must be a prefix
+ * population fully evaluated on `cases`; its trees and results are not changed
+ * (a device copy of its trees may be kept with it).  *out_pop receives
+ * the last generation (N trees, evaluated on `cases`).  stats: host array of
+ * cfg->generations entries, or NULL.  children: host array of
+ * cfg->generations * N records, or NULL. */
+int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* cfg, gp_gen_stats* stats,
+              gp_gen_child* children, gp_handle* out_pop);
+
+/* The trees of a population, as loaded (host memory): offsets_out gets
+ * n_trees + 1 entries; ops_out (may be NULL to get the offsets only) gets
+ * offsets_out[n_trees] bytes, at most ops_cap. */
+int gp_population_ops(gp_ctx* ctx, gp_handle pop, uint8_t* ops_out, int64_t ops_cap, int64_t* offsets_out);
+
 /* Fitness of n given output vectors ([n][T] float32 or [n][W] uint64) against
  * the target of `cases`, in the fixed order described above. */
 int gp_fitness(gp_ctx* ctx, gp_handle cases, const void* outputs, int64_t n, uint32_t flags,

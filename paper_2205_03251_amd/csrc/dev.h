@@ -145,6 +145,37 @@ hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t 
 hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s);
 hipError_t launch_splice(const SpliceItem* items, int64_t n_items, uint8_t* out, hipStream_t s);
 hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipStream_t s);
+// One generation's random choices (Section 6.3): per slot i, the winners of
+// tournaments (i, g, 0) and (i, g, 1) over fit, the crossover point in the
+// mother and the donor node in the father.
+struct SelectParams {
+    const void* fit;             // [n] double (lower wins, NaN worst) or int64 (higher wins)
+    const int64_t* sizes;        // [n] nodes of each slot's tree (0: not built)
+    int64_t n;
+    int32_t k;                   // tournament size
+    int32_t boolean;
+    uint64_t seed;
+    int64_t generation;
+    int64_t* mother;             // [n] outputs
+    int64_t* father;
+    int64_t* point;
+    int64_t* donor_node;
+};
+// Fitness first: the tournaments of generation g over the children's fitness,
+// counting how often each child is drawn as a parent.
+struct MarkParams {
+    const void* fit;
+    int64_t n;
+    int32_t k;
+    int32_t boolean;
+    uint64_t seed;
+    int64_t generation;
+    int32_t* drawn;              // [n], zeroed by the caller's fill kernel
+};
+
+hipError_t launch_select(const SelectParams& p, hipStream_t s);
+hipError_t launch_mark(const MarkParams& p, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gather_rows(const void* src, const int64_t* src_rows, int64_t n_rows, int64_t row_bytes, void* dst,
                               hipStream_t s);
 

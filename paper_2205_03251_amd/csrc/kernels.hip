@@ -954,6 +954,108 @@ hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipSt
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------- selection
+// Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds of two
+// 32x32 -> 64-bit products whose halves are mixed with the other counter words
+// and the round key; the key advances by the two Weyl constants per round.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+    UNROLL for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Word j of stream s for index i at generation g (counter (i, g, s, j / 4)).
+__device__ __forceinline__ uint32_t gen_draw(uint64_t seed, int64_t i, int64_t g, int s, int j)
+{
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)g, (uint32_t)s, (uint32_t)(j / 4)),
+                                  (uint32_t)seed, (uint32_t)(seed >> 32));
+    const int q = j & 3;
+    return q == 0 ? w.x : q == 1 ? w.y : q == 2 ? w.z : w.w;
+}
+
+// floor(u * n / 2^32) for n < 2^32.
+__device__ __forceinline__ int64_t gen_uniform(uint32_t u, int64_t n)
+{
+    return (int64_t)(((uint64_t)u * (uint64_t)n) >> 32);
+}
+
+// k draws with replacement; a candidate replaces the winner only if strictly
+// better, so ties keep the earlier draw.
+__device__ int64_t tournament(const void* fit, bool boolean, int64_t n, int k, uint64_t seed, int64_t i,
+                              int64_t g, int s)
+{
+    int64_t best = gen_uniform(gen_draw(seed, i, g, s, 0), n);
+    for (int j = 1; j < k; ++j) {
+        const int64_t c = gen_uniform(gen_draw(seed, i, g, s, j), n);
+        if (boolean) {
+            const int64_t* h = (const int64_t*)fit;
+            if (h[c] > h[best]) best = c;
+        } else {
+            const double* e = (const double*)fit;
+            const double a = e[c], b = e[best];
+            if (!isnan(a) && (isnan(b) || a < b)) best = c;
+        }
+    }
+    return best;
+}
+
+__global__ __launch_bounds__(256) void k_select(SelectParams p)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= p.n) return;
+    const bool b = p.boolean != 0;
+    const int64_t m = tournament(p.fit, b, p.n, p.k, p.seed, i, p.generation, 0);
+    const int64_t f = tournament(p.fit, b, p.n, p.k, p.seed, i, p.generation, 1);
+    p.mother[i] = m;
+    p.father[i] = f;
+    p.point[i] = gen_uniform(gen_draw(p.seed, i, p.generation, 2, 0), p.sizes[m]);
+    p.donor_node[i] = gen_uniform(gen_draw(p.seed, i, p.generation, 2, 1), p.sizes[f]);
+}
+
+__global__ __launch_bounds__(256) void k_mark(MarkParams p)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= p.n) return;
+    const bool b = p.boolean != 0;
+    atomicAdd(p.drawn + tournament(p.fit, b, p.n, p.k, p.seed, j, p.generation, 0), 1);
+    atomicAdd(p.drawn + tournament(p.fit, b, p.n, p.k, p.seed, j, p.generation, 1), 1);
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t* dst, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+hipError_t launch_select(const SelectParams& p, hipStream_t s)
+{
+    if (p.n <= 0) return hipSuccess;
+    if (p.n >= (int64_t(1) << 32) || p.k < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_select, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark(const MarkParams& p, hipStream_t s)
+{
+    if (p.n <= 0) return hipSuccess;
+    if (p.n >= (int64_t(1) << 32) || p.k < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mark, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, n, v);
+    return hipGetLastError();
+}
+
 // Row k of dst = row src_rows[k] of src (rows of row_bytes, a multiple of 16):
 // chunk values of a mother gathered into an input matrix for co-evaluation.
 __global__ __launch_bounds__(256) void k_gather_rows(const uint4* src, const int64_t* src_rows, uint4* dst,

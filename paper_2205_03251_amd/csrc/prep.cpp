@@ -366,6 +366,19 @@ void big_subtree_ends(const uint8_t* ops, int64_t n, int64_t min_size,
     std::sort(out->begin(), out->end());
 }
 
+int64_t subtree_end_indexed(const uint8_t* ops, int64_t n, int64_t x, const std::vector<SubtreeEnd>& big)
+{
+    if (!is_func(ops[x])) return x + 1;
+    auto it = std::lower_bound(big.begin(), big.end(), SubtreeEnd{(int32_t)x, -1});
+    if (it != big.end() && it->first == x) return it->second;
+    int64_t o = 0;
+    for (int64_t k = x; k < n; ++k) {
+        o += is_func(ops[k]) ? 1 : -1;
+        if (o < 0) return k + 1;
+    }
+    return n;
+}
+
 // From the root down: at each ancestor a of c the first operand starts at
 // a + 1 and ends at end(a + 1), taken from the index or found by scanning that
 // (small) subtree; c lies in whichever operand holds it, the other operand is
@@ -376,17 +389,7 @@ void path_to_root(const uint8_t* ops, int64_t n, int64_t c, const std::vector<Su
     levels->clear();
     *removed_end = -1;
     if (c < 0 || c >= n) return;
-    auto end_of = [&](int64_t x) -> int64_t {
-        if (!is_func(ops[x])) return x + 1;
-        auto it = std::lower_bound(big.begin(), big.end(), SubtreeEnd{(int32_t)x, -1});
-        if (it != big.end() && it->first == x) return it->second;
-        int64_t o = 0;
-        for (int64_t k = x; k < n; ++k) {
-            o += is_func(ops[k]) ? 1 : -1;
-            if (o < 0) return k + 1;
-        }
-        return n;
-    };
+    auto end_of = [&](int64_t x) { return subtree_end_indexed(ops, n, x, big); };
     int64_t a = 0, end_a = n;
     while (a != c) {
         const int64_t l = a + 1, end_l = end_of(l);

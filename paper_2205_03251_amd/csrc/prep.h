@@ -125,6 +125,8 @@ void big_subtree_ends(const uint8_t* ops, int64_t n, int64_t min_size,
 // `big` is that index for the same tree (any min_size; smaller subtrees are
 // scanned).  Cost: the first-operand subtrees along the path that the index
 // does not cover, instead of the whole tree.
+// End of node x's subtree, from the index when listed, else by scanning.
+int64_t subtree_end_indexed(const uint8_t* ops, int64_t n, int64_t x, const std::vector<SubtreeEnd>& big);
 void path_to_root(const uint8_t* ops, int64_t n, int64_t c, const std::vector<SubtreeEnd>& big,
                   std::vector<PathLevel>* levels, int64_t* removed_end);
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <thread>
 
 #include "runtime.h"
@@ -1363,6 +1364,230 @@ int gp_splice_children(gp_ctx* ctx, gp_handle pop, int64_t n_children, const int
         st->variant = -1;
         st->wall_ms = now_ms() - t0;
     }
+    return GP_OK;
+}
+
+int gp_population_ops(gp_ctx* ctx, gp_handle pop, uint8_t* ops_out, int64_t ops_cap, int64_t* offsets_out)
+{
+    if (!ctx || !offsets_out) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->pops.find(pop);
+    if (it == ctx->pops.end()) return set_err(ctx, GP_EINVAL, "unknown population handle");
+    const Pop* p = it->second.get();
+    if (p->host_offsets.size() != (size_t)p->n_trees + 1)
+        return set_err(ctx, GP_EINVAL, "the population keeps no copy of its trees");
+    const int64_t total = p->host_offsets[p->n_trees];
+    if (ops_out) {
+        if (ops_cap < total) return set_err(ctx, GP_EINVAL, "ops_out holds fewer bytes than the trees");
+        std::memcpy(ops_out, p->host_ops.data(), (size_t)total);
+    }
+    std::copy(p->host_offsets.begin(), p->host_offsets.end(), offsets_out);
+    return GP_OK;
+}
+
+int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* cfg, gp_gen_stats* stats,
+              gp_gen_child* children, gp_handle* out_pop)
+{
+    if (!ctx || !cfg || !out_pop) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Pop* p0;
+    CaseSet* cs;
+    RC(lookup(ctx, pop, cases, &p0, &cs));
+    const int64_t G = cfg->generations, N = p0->n_trees;
+    if (G < 1 || cfg->tournament < 1) return set_err(ctx, GP_EINVAL, "need generations >= 1 and tournament >= 1");
+    if (cfg->first_generation < 0 || cfg->first_generation + G >= (int64_t(1) << 32))
+        return set_err(ctx, GP_EINVAL, "generation counters must stay below 2^32");
+    if (N < 1 || N >= (int64_t(1) << 31)) return set_err(ctx, GP_EINVAL, "population size out of range");
+    if (p0->layout != GP_PREFIX) return set_err(ctx, GP_EINVAL, "evolution needs a population loaded in prefix layout");
+    if (p0->evaluated_with != cases)
+        return set_err(ctx, GP_ENOTFOUND, "the population has not been evaluated on this case set; run "
+                                          "gp_evaluate_full on it first");
+    const int vtype = p0->vtype;
+    const bool boolean = vtype == GP_BOOL;
+    hipStream_t s = ctx->stream;
+    std::shared_ptr<Pop> holder;                 // the current generation once it is not the caller's
+    Pop* cur = p0;
+    std::vector<int64_t> slot_tree(N), slot_size(N);
+    for (int64_t i = 0; i < N; ++i) {
+        slot_tree[i] = i;
+        slot_size[i] = p0->tree_nodes[i];
+    }
+    DevBuf fitv, fitn, sizes_d, sel, drawn_d;
+    RC(dev_alloc(ctx, fitv, (size_t)N * 8));
+    RC(dev_alloc(ctx, fitn, (size_t)N * 8));
+    RC(dev_alloc(ctx, sel, (size_t)N * 4 * 8));
+    RC(dev_alloc(ctx, drawn_d, (size_t)N * 4));
+    HIPC(ctx, hipMemcpyAsync(fitv.p, p0->fit.p, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+    std::vector<int64_t> pick((size_t)N * 4);
+    std::vector<int32_t> stop(N), drawn(N);
+    std::vector<int64_t> interp(N), removed(N), dend(N);
+    std::vector<uint8_t> fit_h((size_t)N * 8);
+    for (int64_t gi = 0; gi < G; ++gi) {
+        const double t0 = now_ms();
+        const int64_t g = cfg->first_generation + gi;
+        const int64_t* mother = pick.data();
+        const int64_t* father = mother + N;
+        const int64_t* point = father + N;
+        const int64_t* dnode = point + N;
+        // parents, points and donor nodes, drawn on the device
+        RC(upload(ctx, sizes_d, slot_size.data(), (size_t)N * 8, s));
+        SelectParams sp;
+        sp.fit = fitv.p;
+        sp.sizes = sizes_d.as<int64_t>();
+        sp.n = N;
+        sp.k = cfg->tournament;
+        sp.boolean = boolean ? 1 : 0;
+        sp.seed = cfg->seed;
+        sp.generation = g;
+        sp.mother = sel.as<int64_t>();
+        sp.father = sp.mother + N;
+        sp.point = sp.father + N;
+        sp.donor_node = sp.point + N;
+        HIPC(ctx, launch_select(sp, s));
+        HIPC(ctx, hipMemcpyAsync(pick.data(), sel.p, (size_t)N * 4 * 8, hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipStreamSynchronize(s));
+        // score every child by co-evaluation with its mother
+        std::vector<IncJob> jobs(N);
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t mt = slot_tree[mother[i]], ft = slot_tree[father[i]];
+            if (mt < 0 || ft < 0) return set_err(ctx, GP_EINVAL, "internal error: a tournament winner was not built");
+            const uint8_t* fb = cur->host_ops.data() + cur->host_offsets[ft];
+            static const std::vector<SubtreeEnd> none;
+            const auto& fbig = cur->big_ends.size() == (size_t)cur->n_trees ? cur->big_ends[ft] : none;
+            const auto& mbig = cur->big_ends.size() == (size_t)cur->n_trees ? cur->big_ends[mt] : none;
+            dend[i] = subtree_end_indexed(fb, cur->tree_nodes[ft], dnode[i], fbig);
+            removed[i] = subtree_end_indexed(cur->host_ops.data() + cur->host_offsets[mt], cur->tree_nodes[mt], point[i],
+                                             mbig) - point[i];
+            jobs[i] = IncJob{cur, mt, point[i], fb + dnode[i], dend[i] - dnode[i]};
+        }
+        IncOut io;
+        RC(enqueue_coeval(ctx, jobs, cases, cs, false, s, &io, nullptr, nullptr));
+        HIPC(ctx, hipMemcpyAsync(fitn.p, io.fit.p, (size_t)N * 8, hipMemcpyDeviceToDevice, s));
+        HIPC(ctx, hipMemcpyAsync(stop.data(), io.stop.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipMemcpyAsync(interp.data(), io.interp.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+        HIPC(ctx, hipMemcpyAsync(fit_h.data(), io.fit.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+        // fitness first: only children the next generation's tournaments draw are built
+        const bool last = gi == G - 1;
+        if (!last) {
+            HIPC(ctx, launch_fill_i32(drawn_d.as<int32_t>(), N, 0, s));
+            MarkParams mp;
+            mp.fit = fitn.p;
+            mp.n = N;
+            mp.k = cfg->tournament;
+            mp.boolean = sp.boolean;
+            mp.seed = cfg->seed;
+            mp.generation = g + 1;
+            mp.drawn = drawn_d.as<int32_t>();
+            HIPC(ctx, launch_mark(mp, s));
+            HIPC(ctx, hipMemcpyAsync(drawn.data(), drawn_d.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+        }
+        HIPC(ctx, hipStreamSynchronize(s));
+        if (last) std::fill(drawn.begin(), drawn.end(), 1);
+        // build them on the device: mother's prefix, father's subtree, mother's suffix
+        if (!cur->tree_ops.p) {
+            const size_t nb = (size_t)cur->host_offsets[cur->n_trees];
+            RC(dev_alloc(ctx, cur->tree_ops, nb + 32));
+            HIPC(ctx, hipMemcpyAsync(cur->tree_ops.p, cur->host_ops.data(), nb, hipMemcpyHostToDevice, s));
+            cur->tree_off = cur->host_offsets;
+        }
+        std::vector<int64_t> noffs{0}, child_nodes(N), new_slot(N, -1);
+        for (int64_t i = 0; i < N; ++i) {
+            child_nodes[i] = cur->tree_nodes[slot_tree[mother[i]]] - removed[i] + (dend[i] - dnode[i]);
+            if (drawn[i] > 0) {
+                new_slot[i] = (int64_t)noffs.size() - 1;
+                noffs.push_back(noffs.back() + child_nodes[i]);
+            }
+        }
+        const int64_t nb = (int64_t)noffs.size() - 1, total = noffs.back();
+        auto np = std::make_shared<Pop>();
+        {
+            DevBuf out;
+            RC(dev_alloc(ctx, out, (size_t)total + 32));
+            std::vector<SpliceItem> items;
+            auto add = [&](const uint8_t* src, int64_t dst, int64_t len) {
+                while (len > 0) {
+                    const int64_t take = std::min<int64_t>(len, ((dst + 65536) & ~int64_t(15)) - dst);
+                    items.push_back(SpliceItem{src, dst, take});
+                    src += take;
+                    dst += take;
+                    len -= take;
+                }
+            };
+            const uint8_t* base = cur->tree_ops.as<uint8_t>();
+            for (int64_t i = 0; i < N; ++i) {
+                if (new_slot[i] < 0) continue;
+                const int64_t mt = slot_tree[mother[i]], ft = slot_tree[father[i]], o = noffs[new_slot[i]];
+                const uint8_t* m = base + cur->tree_off[mt];
+                const int64_t nd = dend[i] - dnode[i];
+                add(m, o, point[i]);
+                add(base + cur->tree_off[ft] + dnode[i], o + point[i], nd);
+                add(m + point[i] + removed[i], o + point[i] + nd, cur->tree_nodes[mt] - point[i] - removed[i]);
+            }
+            if ((int64_t)items.size() > (int64_t(1) << 24))
+                return set_err(ctx, GP_EINVAL, "too many bytes to build in one generation");
+            DevBuf items_d;
+            RC(upload(ctx, items_d, items.data(), std::max<size_t>(1, items.size()) * sizeof(SpliceItem), s));
+            HIPC(ctx, launch_splice(items_d.as<SpliceItem>(), (int64_t)items.size(), out.as<uint8_t>(), s));
+            np->host_ops.resize((size_t)total);
+            HIPC(ctx, hipMemcpyAsync(np->host_ops.data(), out.p, (size_t)total, hipMemcpyDeviceToHost, s));
+            HIPC(ctx, hipStreamSynchronize(s));
+            RC(build_population(ctx, vtype, GP_PREFIX, cur->n_inputs, nb, np->host_ops.data(), noffs.data(), nullptr,
+                                nullptr, 0, np.get(), s, true));
+            np->tree_ops.swap(out);                 // the built bytes stay on the device for the next generation
+        }
+        np->auto_chunk = true;
+        np->host_offsets = noffs;
+        np->tree_off = noffs;
+        const int variant = choose_variant(ctx, vtype, cs, np.get());
+        if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits the children");
+        RC(enqueue_full(ctx, np.get(), cases, cs, variant, false, false, s, nullptr));
+        HIPC(ctx, hipStreamSynchronize(s));
+        // statistics and records
+        const double* ff = (const double*)fit_h.data();
+        const int64_t* fi = (const int64_t*)fit_h.data();
+        if (stats) {
+            gp_gen_stats& st = stats[gi];
+            st.best_f64 = std::numeric_limits<double>::quiet_NaN();
+            st.best_i64 = std::numeric_limits<int64_t>::min();
+            st.children = N;
+            st.built = nb;
+            st.child_nodes = 0;
+            st.built_nodes = total;
+            st.interpreted_nodes = 0;
+            for (int64_t i = 0; i < N; ++i) {
+                if (boolean) st.best_i64 = std::max(st.best_i64, fi[i]);
+                else if (!std::isnan(ff[i]) && (std::isnan(st.best_f64) || ff[i] < st.best_f64)) st.best_f64 = ff[i];
+                st.child_nodes += child_nodes[i];
+                st.interpreted_nodes += interp[i];
+            }
+            st.ms = now_ms() - t0;
+        }
+        if (children)
+            for (int64_t i = 0; i < N; ++i) {
+                gp_gen_child& r = children[gi * N + i];
+                r.mother = mother[i];
+                r.father = father[i];
+                r.point = point[i];
+                r.donor_node = dnode[i];
+                r.nodes = child_nodes[i];
+                r.fitness_f64 = boolean ? 0.0 : ff[i];
+                r.fitness_i64 = boolean ? fi[i] : 0;
+                r.stop_level = stop[i];
+                r.drawn = last ? 0 : drawn[i];
+            }
+        // the children become the slots of the next generation
+        for (int64_t i = 0; i < N; ++i) {
+            slot_tree[i] = new_slot[i];
+            slot_size[i] = new_slot[i] >= 0 ? child_nodes[i] : 0;
+        }
+        fitv.swap(fitn);
+        holder = np;
+        cur = np.get();
+    }
+    gp_handle h = ctx->next_handle++;
+    ctx->pops[h] = holder;
+    *out_pop = h;
     return GP_OK;
 }
 

@@ -48,6 +48,23 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class EvolveCfg(C.Structure):
+    _fields_ = [("generations", C.c_int64), ("tournament", C.c_int32), ("reserved", C.c_int32),
+                ("seed", C.c_uint64), ("first_generation", C.c_int64)]
+
+
+class GenStats(C.Structure):
+    _fields_ = [("best_f64", C.c_double), ("best_i64", C.c_int64), ("children", C.c_int64), ("built", C.c_int64),
+                ("child_nodes", C.c_int64), ("built_nodes", C.c_int64), ("interpreted_nodes", C.c_int64),
+                ("ms", C.c_double)]
+
+
+class GenChild(C.Structure):
+    _fields_ = [("mother", C.c_int64), ("father", C.c_int64), ("point", C.c_int64), ("donor_node", C.c_int64),
+                ("nodes", C.c_int64), ("fitness_f64", C.c_double), ("fitness_i64", C.c_int64),
+                ("stop_level", C.c_int32), ("drawn", C.c_int32)]
+
+
 class IncResult(C.Structure):
     _fields_ = [("stop_level", C.c_int32), ("reserved", C.c_int32), ("child_nodes", C.c_int64),
                 ("interpreted_nodes", C.c_int64)]
@@ -115,6 +132,8 @@ def lib() -> C.CDLL:
     h.gp_evaluate_incremental.argtypes = [P, I64, I64, I64, I64, P, I64, C.c_uint32, P, P, P]
     h.gp_fitness.argtypes = [P, I64, P, I64, C.c_uint32, P]
     h.gp_splice_children.argtypes = [P, I64, I64, P, P, P, P, C.c_uint32, P, I64, P, C.POINTER(Stats)]
+    h.gp_evolve.argtypes = [P, I64, I64, C.POINTER(EvolveCfg), P, P, C.POINTER(I64)]
+    h.gp_population_ops.argtypes = [P, I64, P, I64, P]
     h.gp_variant_name.argtypes = [C.c_int]
     h.gp_variant_name.restype = C.c_char_p
     h.gp_variant_count.argtypes = []
@@ -377,6 +396,30 @@ class Context:
         cnodes = np.array([res[i].child_nodes for i in range(n)], np.int64)
         return r, f, {"stop_level": stop, "interpreted_nodes": interp, "child_nodes": cnodes,
                       **st.as_dict()}
+
+    def evolve(self, pop, cases, generations, tournament, seed, first_generation=0):
+        """gp_evolve: returns (new population handle, per-generation stats,
+        per-child records as a dict of [generations][N] arrays)."""
+        n = self.population_info(pop)["n_trees"]
+        cfg = EvolveCfg(generations, tournament, 0, seed, first_generation)
+        stats = (GenStats * generations)()
+        recs = (GenChild * (generations * n))()
+        out = I64(0)
+        self._check(lib().gp_evolve(self._h, pop, cases, C.byref(cfg), C.cast(stats, P), C.cast(recs, P),
+                                    C.byref(out)))
+        st = [{k: getattr(stats[g], k) for k, _ in GenStats._fields_} for g in range(generations)]
+        arr = np.ctypeslib.as_array(recs)
+        rec = {k: np.array(arr[k]).reshape(generations, n) for k, _ in GenChild._fields_}
+        return out.value, st, rec
+
+    def population_ops(self, pop):
+        """(ops, offsets) of a population's trees, as loaded."""
+        n = self.population_info(pop)["n_trees"]
+        offs = np.zeros(n + 1, np.int64)
+        self._check(lib().gp_population_ops(self._h, pop, None, 0, _ptr(offs)))
+        ops = np.empty(max(int(offs[-1]), 1), np.uint8)
+        self._check(lib().gp_population_ops(self._h, pop, _ptr(ops), ops.size, _ptr(offs)))
+        return ops[:int(offs[-1])], offs
 
     def fitness(self, cases, vtype, outputs):
         outputs = _np(outputs, np.float32 if vtype == GP_F32 else np.uint64)
