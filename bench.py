@@ -223,6 +223,7 @@ def main():
                     help="also time per-tree launches and full re-evaluation of the children")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--serve-jobs", type=int, default=2000, help="served-stream jobs (0 = skip serving)")
+    ap.add_argument("--generations", type=int, default=2, help="generations of the evolution leg (0 = skip)")
     ap.add_argument("--chunk-nodes", type=int, default=0, help="fix the chunk size (0 = automatic / tuned)")
     ap.add_argument("--variant", default="", help="fix the interpreter variant, e.g. f32_k4_s16")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -424,6 +425,21 @@ def main():
             extra["children_full_reeval_gpops"] = int(child_offs[-1]) * T / (st_c["device_ms"] * 1e-3) / 1e9
             ctx.free(cph)
     del child_ops
+
+    # generations with fitness first (tournaments of 7, the paper's size): children scored by
+    # co-evaluation, only those drawn by the next generation's tournaments built and compiled
+    if kids is not None and args.generations > 0:
+        nh, gstats, _ = ctx.evolve(ph, ch, args.generations, 7, 2022)
+        extra["evolve"] = {
+            "generations": args.generations, "tournament": 7, "population": n_trees,
+            "ms_per_generation": [round(x["ms"], 1) for x in gstats],
+            "built_fraction": [round(x["built"] / x["children"], 4) for x in gstats],
+            "child_nodes": [int(x["child_nodes"]) for x in gstats],
+            "interpreted_nodes": [int(x["interpreted_nodes"]) for x in gstats],
+            "best_error": [x["best_f64"] if vtype == g.GP_F32 else int(x["best_i64"]) for x in gstats],
+            "note": "the last generation builds all children; a generation's time includes host compilation of "
+                    "the built children"}
+        ctx.free(nh)
 
     serving = None
     if args.serve_jobs > 0:
