@@ -351,11 +351,13 @@ int gp_server_stop(gp_ctx* ctx);
  * chunk (code offset, code length, parent chunk or -1, number of child chunks
  * it loads), inputs_out the child chunk ids each chunk loads, chunk after
  * chunk, in LOAD payload order.  Chunks come children first; the last one is
- * the root.  Returns the number of chunks, GP_EINVAL for a malformed tree or
+ * the root.  threads (1..64; values outside are clamped) host threads may
+ * emit the chunks of a tree of 200000 nodes or more; the program does not
+ * depend on it.  Returns the number of chunks, GP_EINVAL for a malformed tree or
  * GP_ENOMEM when a capacity is too small; *n_code gets the code length and
  * *max_stack the register-stack slots used. */
 int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t n,
-                           int64_t chunk_nodes, int stack_slots, uint32_t* code_out,
+                           int64_t chunk_nodes, int stack_slots, int threads, uint32_t* code_out,
                            int64_t code_cap, int64_t* chunk_out, int64_t chunk_cap,
                            int32_t* inputs_out, int64_t inputs_cap, int64_t* n_code,
                            int32_t* max_stack);

@@ -2,6 +2,8 @@
 #include "prep.h"
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <unordered_map>
 
 namespace gpe {
@@ -240,22 +242,24 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     for (int64_t i = n - 1; i > 0; --i)
         if (cut[i]) roots.push_back(i);
     roots.push_back(0);
-    std::unordered_map<int64_t, int32_t> chunk_of;
-    chunk_of.reserve(roots.size() * 2);
+    std::vector<int32_t> chunk_of(n, -1);
     for (size_t k = 0; k < roots.size(); ++k) chunk_of[roots[k]] = (int32_t)k;
 
-    out->chunks.assign(roots.size(), Chunk());
-    out->code.clear();
-    out->code.reserve((size_t)(n / 2 + roots.size() * 2 + rec_of.size() + 8));
-    int32_t max_slot = 0;
-    std::vector<Frame> fr;
-    fr.reserve(256);
-    for (size_t k = 0; k < roots.size(); ++k) {
+    // Chunks are independent once the cuts are known: each one's code is
+    // emitted on its own (in parallel for a large tree) and concatenated in
+    // chunk order.
+    const int64_t nch = (int64_t)roots.size();
+    out->chunks.assign(nch, Chunk());
+    std::vector<std::vector<uint32_t>> codes(nch);
+    std::vector<int32_t> slot_hi(nch, 0);
+    std::vector<uint8_t> too_many(nch, 0);
+    auto emit = [&](int64_t k, std::vector<Frame>& fr) {
         Chunk& ch = out->chunks[k];
+        std::vector<uint32_t>& code = codes[k];
+        int32_t max_slot = 0;
         int64_t root = roots[k];
         ch.root_node = root;
         ch.end_node = index ? end_at[root] : -1;
-        ch.code_off = (int64_t)out->code.size();
         ch.nodes = 0;
         fr.clear();
         fr.push_back(Frame{root, 0, 0, 0, 0, 0});
@@ -268,14 +272,14 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
                 if (v != root && cut[v]) {
                     int32_t child = chunk_of[v];
                     out->chunks[child].parent = (int32_t)k;
-                    out->code.push_back(ins_word(0, M_LOAD, d, (uint32_t)ch.inputs.size()));
+                    code.push_back(ins_word(0, M_LOAD, d, (uint32_t)ch.inputs.size()));
                     ch.inputs.push_back(child);
                     fr.pop_back();
                     continue;
                 }
                 ch.nodes += 1;
                 if (!is_func(ops[v])) {
-                    out->code.push_back(ins_word(0, M_PUSH, d, external(v) ? (uint32_t)ext[v] : ops[v]));
+                    code.push_back(ins_word(0, M_PUSH, d, external(v) ? (uint32_t)ext[v] : ops[v]));
                     fr.pop_back();
                     continue;
                 }
@@ -313,23 +317,56 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
             }
             if (F.stage == 1) {
                 F.stage = 2;
-                int64_t s = F.second;
-                fr.push_back(Frame{s, d + 1, 0, 0, 0, 0});
+                int64_t s2 = F.second;
+                fr.push_back(Frame{s2, d + 1, 0, 0, 0, 0});
                 continue;
             }
             // stage 2: both operands are in place
-            out->code.push_back(ins_word(ops[v] & 3, F.mode, d, F.payload));
+            code.push_back(ins_word(ops[v] & 3, F.mode, d, F.payload));
             if (F.mode == M_SS || F.mode == M_RS) max_slot = std::max(max_slot, d + 1);
-            auto it = rec_of.find(v);
-            if (it != rec_of.end()) out->code.push_back(ins_word(0, M_STORE, d, (uint32_t)it->second));
+            if (!rec_of.empty()) {
+                auto it = rec_of.find(v);
+                if (it != rec_of.end()) code.push_back(ins_word(0, M_STORE, d, (uint32_t)it->second));
+            }
             fr.pop_back();
         }
-        out->code.push_back(kEndWord);
-        ch.code_len = (int64_t)out->code.size() - ch.code_off;
-        if (ch.inputs.size() > kMaxPayload) {
+        code.push_back(kEndWord);
+        slot_hi[k] = max_slot;
+        if (ch.inputs.size() > kMaxPayload) too_many[k] = 1;
+    };
+    const int nth = (int)std::min<int64_t>(std::max(1, opt.threads), nch / 2);
+    if (nth > 1 && n >= 200000) {
+        std::atomic<int64_t> next{0};
+        auto work = [&]() {
+            std::vector<Frame> fr;
+            fr.reserve(256);
+            for (int64_t k; (k = next++) < nch;) emit(k, fr);
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nth; ++t) th.emplace_back(work);
+        work();
+        for (auto& t : th) t.join();
+    } else {
+        std::vector<Frame> fr;
+        fr.reserve(256);
+        for (int64_t k = 0; k < nch; ++k) emit(k, fr);
+    }
+    size_t total_code = 0;
+    for (const auto& c : codes) total_code += c.size();
+    out->code.clear();
+    out->code.reserve(total_code);
+    int32_t max_slot = 0;
+    for (int64_t k = 0; k < nch; ++k) {
+        if (too_many[k]) {
             if (why) *why = "chunk reads too many child chunks";
             return false;
         }
+        Chunk& ch = out->chunks[k];
+        ch.code_off = (int64_t)out->code.size();
+        ch.code_len = (int64_t)codes[k].size();
+        out->code.insert(out->code.end(), codes[k].begin(), codes[k].end());
+        std::vector<uint32_t>().swap(codes[k]);
+        max_slot = std::max(max_slot, slot_hi[k]);
     }
     out->max_stack = max_slot + 1;
     if (out->max_stack > S) {

@@ -226,9 +226,11 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
             for (int64_t i = 0; i < np; ++i) progs[t].spines[i].point = p0[i];
         }
     };
-    int nth = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
-    nth = (int)std::min<int64_t>(nth, n_trees);
+    const int hw = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+    int nth = (int)std::min<int64_t>(hw, n_trees);
     if (total < 100000) nth = 1;
+    // with fewer trees than threads, each tree emits its chunks on the rest
+    if (total >= 100000 && n_trees < hw) opt.threads = std::max<int>(1, hw / (int)n_trees);
     std::vector<std::thread> th;
     for (int i = 1; i < nth; ++i) th.emplace_back(work);
     work();
@@ -1737,7 +1739,7 @@ int64_t gp_inspect_path(const uint8_t* ops, int64_t n, int64_t c, int64_t index_
 }
 
 int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t n, int64_t chunk_nodes,
-                           int stack_slots, uint32_t* code_out, int64_t code_cap, int64_t* chunk_out,
+                           int stack_slots, int threads, uint32_t* code_out, int64_t code_cap, int64_t* chunk_out,
                            int64_t chunk_cap, int32_t* inputs_out, int64_t inputs_cap, int64_t* n_code,
                            int32_t* max_stack)
 {
@@ -1748,6 +1750,7 @@ int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t 
     opt.n_inputs = n_inputs;
     opt.chunk_nodes = chunk_nodes > 0 ? chunk_nodes : 4096;
     opt.stack_slots = stack_slots > 0 ? stack_slots : compile_stack_slots();
+    opt.threads = std::max(1, std::min(threads, 64));
     TreeProg pg;
     std::string why;
     if (!compile_tree(ops, n, opt, nullptr, 0, &pg, &why)) return GP_EINVAL;

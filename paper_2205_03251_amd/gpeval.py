@@ -144,7 +144,7 @@ def lib() -> C.CDLL:
     h.gp_server_poll.argtypes = [P, I64, C.POINTER(JobResult), P]
     h.gp_server_release.argtypes = [P, I64]
     h.gp_server_stop.argtypes = [P]
-    h.gp_inspect_program.argtypes = [C.c_int, C.c_int, P, I64, I64, C.c_int, P, I64, P, I64, P, I64,
+    h.gp_inspect_program.argtypes = [C.c_int, C.c_int, P, I64, I64, C.c_int, C.c_int, P, I64, P, I64, P, I64,
                                      C.POINTER(I64), C.POINTER(C.c_int32)]
     h.gp_inspect_program.restype = I64
     h.gp_validate_tree.argtypes = [C.c_int, C.c_int, P, I64]
@@ -198,7 +198,7 @@ def inspect_path(tree, c, index_min_size=4096):
     return out[:r].copy(), e.value
 
 
-def inspect_program(tree, vtype=GP_F32, n_inputs=1, chunk_nodes=4096, stack_slots=16) -> Program:
+def inspect_program(tree, vtype=GP_F32, n_inputs=1, chunk_nodes=4096, stack_slots=16, threads=1) -> Program:
     t = _np(tree, np.uint8)
     n = len(t)
     cap = 2 * n + 64
@@ -207,7 +207,7 @@ def inspect_program(tree, vtype=GP_F32, n_inputs=1, chunk_nodes=4096, stack_slot
     ins = np.zeros(n + 1, np.int32)
     nc = I64(0)
     ms = C.c_int32(0)
-    r = lib().gp_inspect_program(vtype, n_inputs, _ptr(t), n, chunk_nodes, stack_slots, _ptr(code), cap,
+    r = lib().gp_inspect_program(vtype, n_inputs, _ptr(t), n, chunk_nodes, stack_slots, threads, _ptr(code), cap,
                                  _ptr(chunks), n + 1, _ptr(ins), n + 1, C.byref(nc), C.byref(ms))
     if r < 0:
         raise GPError(int(r), "inspect_program failed")

@@ -165,6 +165,20 @@ def test_chunk_sizes_bounded():
         assert len(prog.chunks) >= 50_001 // (2 * C + 2)
 
 
+def test_parallel_emission_matches_serial():
+    """A large tree's chunks may be emitted on several host threads; the
+    program (code, chunk table, load lists, stack use) is the same."""
+    rng = np.random.default_rng(23)
+    t = gen.sized_tree(rng, 400_001)
+    for C in [64, 4096]:
+        a = g.inspect_program(t, g.GP_F32, 1, C, 10, threads=1)
+        for th in [3, 8]:
+            b = g.inspect_program(t, g.GP_F32, 1, C, 10, threads=th)
+            assert np.array_equal(a.code, b.code)
+            assert np.array_equal(a.chunks, b.chunks)
+            assert a.inputs == b.inputs and a.max_stack == b.max_stack
+
+
 def test_inspect_path_matches_brute_force():
     """The co-evaluation path (ancestors nearest first, which side the path
     runs, the sibling subtree's slice) against a brute force from subtree
