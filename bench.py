@@ -433,12 +433,14 @@ def main():
         extra["evolve"] = {
             "generations": args.generations, "tournament": 7, "population": n_trees,
             "ms_per_generation": [round(x["ms"], 1) for x in gstats],
+            "ms_score_build_eval": [[round(x["ms_score"], 1), round(x["ms_build"], 1), round(x["ms_eval"], 1)]
+                                    for x in gstats],
             "built_fraction": [round(x["built"] / x["children"], 4) for x in gstats],
             "child_nodes": [int(x["child_nodes"]) for x in gstats],
             "interpreted_nodes": [int(x["interpreted_nodes"]) for x in gstats],
             "best_error": [x["best_f64"] if vtype == g.GP_F32 else int(x["best_i64"]) for x in gstats],
-            "note": "the last generation builds all children; a generation's time includes host compilation of "
-                    "the built children"}
+            "note": "the last generation builds all children; building includes the children's programs, made "
+                    "from their parents' chunks"}
         ctx.free(nh)
 
     serving = None

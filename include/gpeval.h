@@ -236,7 +236,10 @@ typedef struct gp_gen_stats {
     int64_t child_nodes;       /* nodes of all N children */
     int64_t built_nodes;       /* nodes of the children built */
     int64_t interpreted_nodes; /* nodes executed to score the children */
-    double ms;                 /* wall time of the generation */
+    double ms;                 /* wall time of the generation, of which: */
+    double ms_score;           /*   drawing parents and points, scoring the children, drawing the next tournaments */
+    double ms_build;           /*   building the drawn children: bytes on the device and the host, programs */
+    double ms_eval;            /*   evaluating the built children in full (the next generation's caches) */
 } gp_gen_stats;
 
 typedef struct gp_gen_child {
@@ -361,6 +364,32 @@ int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t 
                            int64_t code_cap, int64_t* chunk_out, int64_t chunk_cap,
                            int32_t* inputs_out, int64_t inputs_cap, int64_t* n_code,
                            int32_t* max_stack);
+
+/* The program of a crossover child built from its parents' programs
+ * (Section 5: the mother's prefix up to `point`, the father's subtree at
+ * `donor_node`, the mother's suffix after the subtree at `point`), on the host
+ * only, for tests: both parents are compiled whole (chunk_nodes, stack_slots
+ * as for gp_inspect_program, index of subtrees of index_min_size >= 1 nodes;
+ * the mother records parent caches for the n_mother_records points listed,
+ * as gp_load_population's record_points do), then the child reuses every
+ * chunk of theirs off the crossover path that records nothing and
+ * recompiles the rest.  Outputs as for gp_inspect_program, except that
+ * chunk_out receives 6 int64 per chunk (code offset, code length, parent,
+ * number of child chunks, root node, end of the root's subtree, in the
+ * child's numbering), big_out 2 int64 per subtree of at least index_min_size
+ * nodes (node, end; sorted by node), *n_big their number and *n_reused the
+ * number of chunks whose code was taken from a parent.  Returns the number of
+ * chunks, GP_EINVAL for malformed trees or points, GP_ENOMEM when a capacity
+ * is too small. */
+int64_t gp_inspect_child_program(int vtype, int n_inputs, const uint8_t* mother, int64_t n_mother,
+                                 int64_t point, const int64_t* mother_records,
+                                 int64_t n_mother_records, const uint8_t* father, int64_t n_father,
+                                 int64_t donor_node, int64_t chunk_nodes, int stack_slots,
+                                 int64_t index_min_size, uint32_t* code_out, int64_t code_cap,
+                                 int64_t* chunk_out, int64_t chunk_cap, int32_t* inputs_out,
+                                 int64_t inputs_cap, int64_t* big_out, int64_t big_cap,
+                                 int64_t* n_code, int32_t* max_stack, int64_t* n_big,
+                                 int64_t* n_reused);
 
 /* Validate one tree (prefix layout) on the host: GP_OK or GP_EINVAL. */
 int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n);

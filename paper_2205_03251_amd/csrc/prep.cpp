@@ -2,6 +2,7 @@
 #include "prep.h"
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <thread>
 #include <unordered_map>
@@ -120,7 +121,7 @@ bool postfix_to_prefix(const uint8_t* post, int64_t n, int n_inputs, std::vector
 }
 
 bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, const int64_t* points,
-                  int64_t n_points, TreeProg* out, std::string* why, const int32_t* ext)
+                  int64_t n_points, TreeProg* out, std::string* why, const int32_t* ext, const Collapsed* col)
 {
     const bool boolean = opt.vtype == 1;
     const int S = opt.stack_slots;
@@ -132,7 +133,16 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     // Float folds terminal 0 (kept in registers); Boolean folds any terminal
     // (read from the staged input words).
     auto external = [&](int64_t v) { return ext != nullptr && ext[v] >= 0; };
-    auto foldable = [&](int64_t v) { return !is_func(ops[v]) && !external(v) && (boolean || ops[v] == 0); };
+    auto opaque = [&](int64_t v) { return col != nullptr && col->opaque[v] >= 0; };
+    auto foldable = [&](int64_t v) {
+        return !is_func(ops[v]) && !external(v) && !opaque(v) && (boolean || ops[v] == 0);
+    };
+    auto full = [&](int64_t v) { return col != nullptr ? col->node_map[v] : v; };
+    const int32_t id_base = col != nullptr ? col->id_base : 0;
+    if (col != nullptr && n_points > 0) {
+        if (why) *why = "record points in a collapsed tree";
+        return false;
+    }
 
     std::vector<int32_t> rch(n, -1);      // right child of each function node
     std::vector<uint8_t> need(n, 1);      // stack slots to produce the value
@@ -149,6 +159,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         if (!is_func(ops[i])) {
             st.push_back((int32_t)i);
             if (index) end_at[i] = (int32_t)(i + 1);
+            if (opaque(i)) cut[i] = 1;        // a compiled chunk: one LOAD
             continue;
         }
         int32_t l = st.back();
@@ -157,7 +168,8 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         st.back() = (int32_t)i;
         if (index) {
             end_at[i] = end_at[r];
-            if (end_at[i] - i >= opt.index_min_size) out->big_ends.push_back({(int32_t)i, end_at[i]});
+            if (full(end_at[i]) - full(i) >= opt.index_min_size)
+                out->big_ends.push_back({(int32_t)full(i), (int32_t)full(end_at[i])});
         }
         rch[i] = r;
         auto cost = [&](int32_t c) { return cut[c] ? 1 : (int)need[c]; };
@@ -240,7 +252,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     // index so that every chunk comes after the chunks it reads.
     std::vector<int64_t> roots;
     for (int64_t i = n - 1; i > 0; --i)
-        if (cut[i]) roots.push_back(i);
+        if (cut[i] && !opaque(i)) roots.push_back(i);
     roots.push_back(0);
     std::vector<int32_t> chunk_of(n, -1);
     for (size_t k = 0; k < roots.size(); ++k) chunk_of[roots[k]] = (int32_t)k;
@@ -258,8 +270,8 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         std::vector<uint32_t>& code = codes[k];
         int32_t max_slot = 0;
         int64_t root = roots[k];
-        ch.root_node = root;
-        ch.end_node = index ? end_at[root] : -1;
+        ch.root_node = full(root);
+        ch.end_node = index ? full(end_at[root]) : -1;
         ch.nodes = 0;
         fr.clear();
         fr.push_back(Frame{root, 0, 0, 0, 0, 0});
@@ -270,8 +282,14 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
             if (F.stage == 0) {
                 max_slot = std::max(max_slot, d);
                 if (v != root && cut[v]) {
-                    int32_t child = chunk_of[v];
-                    out->chunks[child].parent = (int32_t)k;
+                    int32_t child;
+                    if (opaque(v)) {
+                        child = col->opaque[v];
+                    } else {
+                        child = chunk_of[v];
+                        out->chunks[child].parent = id_base + (int32_t)k;
+                        child += id_base;
+                    }
                     code.push_back(ins_word(0, M_LOAD, d, (uint32_t)ch.inputs.size()));
                     ch.inputs.push_back(child);
                     fr.pop_back();
@@ -326,7 +344,10 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
             if (F.mode == M_SS || F.mode == M_RS) max_slot = std::max(max_slot, d + 1);
             if (!rec_of.empty()) {
                 auto it = rec_of.find(v);
-                if (it != rec_of.end()) code.push_back(ins_word(0, M_STORE, d, (uint32_t)it->second));
+                if (it != rec_of.end()) {
+                    code.push_back(ins_word(0, M_STORE, d, (uint32_t)it->second));
+                    ch.stores = true;
+                }
             }
             fr.pop_back();
         }
@@ -375,7 +396,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     }
     // Longest chain of chunk work from each chunk up to the tree root
     // (parents come after children, so walk backwards).
-    for (int64_t k = (int64_t)out->chunks.size() - 1; k >= 0; --k) {
+    for (int64_t k = col != nullptr ? -1 : (int64_t)out->chunks.size() - 1; k >= 0; --k) {
         Chunk& ch = out->chunks[k];
         ch.path_nodes = ch.nodes + (ch.parent >= 0 ? out->chunks[ch.parent].path_nodes : 0);
     }
@@ -449,6 +470,146 @@ void path_to_root(const uint8_t* ops, int64_t n, int64_t c, const std::vector<Su
     }
     *removed_end = end_a;
     std::reverse(levels->begin(), levels->end());   // nearest the point first
+}
+
+bool compose_child(const SrcTree& m, int64_t c, int64_t c_end, const SrcTree& f, int64_t d, int64_t d_end,
+                   const uint8_t* child, int64_t n_child, const CompileOptions& opt, TreeProg* out,
+                   std::string* why)
+{
+    const int64_t delta = (d_end - d) - (c_end - c);
+    if (opt.index_min_size <= 0 || c < 0 || c_end > m.n || c >= c_end || d < 0 || d_end > f.n || d >= d_end ||
+        n_child != m.n + delta) {
+        if (why) *why = "compose_child: bad crossover";
+        return false;
+    }
+    out->code.clear();
+    out->chunks.clear();
+    out->spines.clear();
+    out->n_records = 0;
+    out->big_ends.clear();
+    out->max_stack = 1;
+    // A reused chunk keeps its code, its node count and its inputs (renumbered);
+    // the ones whose parent chunk is recompiled ("tops") become collapsed leaves.
+    struct Top {
+        int64_t root, end;               // in the child
+        int64_t src_root, src_end;       // in the parent it comes from
+        int32_t id;
+        bool from_mother;
+    };
+    std::vector<Top> tops;
+    std::vector<int32_t> mid(m.n_chunks, -1), fid(f.n_chunks, -1);
+    auto take = [&](const SrcTree& t, int64_t k, std::vector<int32_t>& ids, int64_t root, int64_t end) {
+        const Chunk& s = t.chunks[k];
+        ids[k] = (int32_t)out->chunks.size();
+        Chunk ch;
+        ch.code_off = 0;
+        ch.code_len = s.code_len;
+        ch.dev_src = s.code_off;
+        ch.root_node = root;
+        ch.end_node = end;
+        ch.nodes = s.nodes;
+        ch.parent = -2;                  // set below
+        ch.inputs.reserve(s.inputs.size());
+        for (int32_t in : s.inputs) ch.inputs.push_back(ids[in]);   // children come first
+        out->chunks.push_back(std::move(ch));
+        out->max_stack = std::max(out->max_stack, t.max_stack);
+    };
+    // the mother's chunks off the path; ends at c stay (the removed subtree starts there)
+    for (int64_t k = 0; k < m.n_chunks; ++k) {
+        const int64_t r = m.chunks[k].root_node, e = m.chunks[k].end_node;
+        if (r >= c && r < c_end) continue;       // inside the removed subtree
+        if (r < c && c < e) continue;            // holds the point: recompiled
+        if (m.chunks[k].stores) continue;        // the child records nothing: recompiled
+        take(m, k, mid, r < c ? r : r + delta, e <= c ? e : e + delta);
+    }
+    // the father's chunks inside the donor subtree
+    for (int64_t k = 0; k < f.n_chunks; ++k) {
+        const int64_t r = f.chunks[k].root_node, e = f.chunks[k].end_node;
+        if (r < d || r >= d_end || f.chunks[k].stores) continue;
+        take(f, k, fid, r - d + c, e - d + c);
+    }
+    for (int side = 0; side < 2; ++side) {
+        const SrcTree& t = side == 0 ? m : f;
+        const std::vector<int32_t>& ids = side == 0 ? mid : fid;
+        for (int64_t k = 0; k < t.n_chunks; ++k) {
+            if (ids[k] < 0) continue;
+            const int32_t p = t.chunks[k].parent;
+            Chunk& ch = out->chunks[ids[k]];
+            if (p >= 0 && ids[p] >= 0) {
+                ch.parent = ids[p];
+            } else {
+                tops.push_back(Top{ch.root_node, ch.end_node, t.chunks[k].root_node, t.chunks[k].end_node, ids[k],
+                                   side == 0});
+            }
+        }
+    }
+    std::sort(tops.begin(), tops.end(), [](const Top& a, const Top& b) { return a.root < b.root; });
+    const int32_t n_reused = (int32_t)out->chunks.size();
+    if (tops.size() == 1 && tops[0].root == 0 && tops[0].end == n_child) {
+        // the donor's chunk is the whole child
+        out->chunks[tops[0].id].parent = -1;
+    } else {
+        // the rest of the child, with every top collapsed to one leaf
+        std::vector<uint8_t> gops;
+        std::vector<int32_t> opq;
+        std::vector<int64_t> nmap;
+        size_t j = 0;
+        for (int64_t p = 0; p < n_child;) {
+            nmap.push_back(p);
+            if (j < tops.size() && tops[j].root == p) {
+                gops.push_back(0);
+                opq.push_back(tops[j].id);
+                p = tops[j].end;
+                ++j;
+            } else {
+                gops.push_back(child[p]);
+                opq.push_back(-1);
+                ++p;
+            }
+        }
+        nmap.push_back(n_child);
+        if (j != tops.size()) {
+            if (why) *why = "compose_child: overlapping chunks";
+            return false;
+        }
+        Collapsed col{opq.data(), nmap.data(), n_reused};
+        TreeProg glue;
+        if (!compile_tree(gops.data(), (int64_t)gops.size(), opt, nullptr, 0, &glue, why, nullptr, &col))
+            return false;
+        out->max_stack = std::max(out->max_stack, glue.max_stack);
+        out->code.swap(glue.code);
+        for (Chunk& ch : glue.chunks) {
+            for (int32_t in : ch.inputs)
+                if (in < n_reused) out->chunks[in].parent = n_reused + (int32_t)(&ch - glue.chunks.data());
+            out->chunks.push_back(std::move(ch));
+        }
+        out->big_ends.swap(glue.big_ends);
+    }
+    // the chunk graph must be a tree listed children first, the root last
+    const int64_t nc = (int64_t)out->chunks.size();
+    for (int64_t k = 0; k < nc; ++k) {
+        const Chunk& ch = out->chunks[k];
+        bool ok = (k == nc - 1) ? ch.parent == -1 : (ch.parent > k && ch.parent < nc);
+        for (int32_t in : ch.inputs) ok = ok && in >= 0 && in < k && out->chunks[in].parent == k;
+        if (!ok) {
+            if (why) *why = "compose_child: inconsistent chunk graph";
+            return false;
+        }
+    }
+    // index entries inside the reused chunks, from the parents' indexes
+    for (const Top& tp : tops) {
+        const std::vector<SubtreeEnd>& big = tp.from_mother ? *m.big : *f.big;
+        auto it = std::lower_bound(big.begin(), big.end(), SubtreeEnd{(int32_t)tp.src_root, INT32_MIN});
+        const int64_t shift = tp.root - tp.src_root;
+        for (; it != big.end() && it->first < tp.src_end; ++it)
+            out->big_ends.push_back({(int32_t)(it->first + shift), (int32_t)(it->second + shift)});
+    }
+    std::sort(out->big_ends.begin(), out->big_ends.end());
+    for (int64_t k = (int64_t)out->chunks.size() - 1; k >= 0; --k) {
+        Chunk& ch = out->chunks[k];
+        ch.path_nodes = ch.nodes + (ch.parent >= 0 ? out->chunks[ch.parent].path_nodes : 0);
+    }
+    return true;
 }
 
 }  // namespace gpe

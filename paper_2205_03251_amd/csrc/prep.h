@@ -60,6 +60,9 @@ struct Chunk {
     int64_t nodes = 0;           // tree nodes evaluated by this chunk
     int64_t path_nodes = 0;      // nodes on the longest chunk chain from here to the tree root
     int64_t end_node = -1;       // end of the root's subtree (with CompileOptions::index_min_size)
+    int64_t dev_src = -1;        // >= 0: the code is not in TreeProg::code but at this word
+                                 // offset of an already uploaded program (see compose_child)
+    bool stores = false;         // records parent caches (STORE words)
     std::vector<int32_t> inputs; // local chunk ids read by LOAD payload 0, 1, ...
 };
 
@@ -131,11 +134,56 @@ int64_t subtree_end_indexed(const uint8_t* ops, int64_t n, int64_t x, const std:
 void path_to_root(const uint8_t* ops, int64_t n, int64_t c, const std::vector<SubtreeEnd>& big,
                   std::vector<PathLevel>* levels, int64_t* removed_end);
 
+// A tree in which some subtrees are chunks compiled already: each of them is
+// collapsed to one leaf that LOADs that chunk.  Chunk ids in the output
+// (inputs, parent) are then final ids: id_base + k for the k-th chunk compiled
+// here, opaque[v] for the collapsed leaf v.  Nodes are reported in the full
+// tree's numbering: node v of the collapsed tree is node_map[v] of the full
+// tree (node_map has n + 1 entries, the last the full tree's size), and the
+// index of large subtrees uses full sizes.  path_nodes is left to the caller.
+struct Collapsed {
+    const int32_t* opaque;       // per node: -1, or the chunk id of a collapsed leaf
+    const int64_t* node_map;
+    int32_t id_base;
+};
+
 // Compile one validated prefix tree.  points: crossover points (prefix
 // indices) whose parent caches must be recorded.  ext (may be null): per
 // node, -1 or the row of the input matrix that a terminal node stands for; such
 // a node is pushed from that row instead of being read as its input.
+// col (may be null; then no points): collapsed subtrees, as above.
 bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, const int64_t* points,
-                  int64_t n_points, TreeProg* out, std::string* why, const int32_t* ext = nullptr);
+                  int64_t n_points, TreeProg* out, std::string* why, const int32_t* ext = nullptr,
+                  const Collapsed* col = nullptr);
+
+// A compiled tree kept with its population, for building children from it:
+// its bytes, its chunks (children first, the root chunk last, each with its
+// subtree end; code_off is the word offset of the chunk's code in the
+// population's uploaded program), its index of large subtrees and stack use.
+struct SrcTree {
+    const uint8_t* ops;
+    int64_t n;
+    const Chunk* chunks;
+    int64_t n_chunks;
+    const std::vector<SubtreeEnd>* big;
+    int32_t max_stack;
+};
+
+// The program of a crossover child (Section 5: the mother's prefix, the
+// subtree [d, d_end) of the father, the mother's suffix after the removed
+// subtree [c, c_end)) built from its parents' programs instead of compiling
+// it whole.  A chunk whose subtree neither holds nor lies in the removed
+// subtree is the mother's chunk unchanged; a chunk inside the donor subtree is
+// the father's; both keep their code where it is (Chunk::dev_src = its word
+// offset there).  Only the chunks on the path from c to the root, the
+// father's chunk holding d and chunks that record parent caches are compiled
+// again, as a tree in which the reused chunks are collapsed leaves.  child: the child's bytes (n_child).
+// The index of large subtrees (opt.index_min_size > 0, required) comes from
+// the parents' indexes and the recompiled part.  Each chunk's code computes
+// the same values as a whole compilation would; the chunking differs only
+// on the path.
+bool compose_child(const SrcTree& m, int64_t c, int64_t c_end, const SrcTree& f, int64_t d, int64_t d_end,
+                   const uint8_t* child, int64_t n_child, const CompileOptions& opt, TreeProg* out,
+                   std::string* why);
 
 }  // namespace gpe

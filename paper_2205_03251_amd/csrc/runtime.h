@@ -76,13 +76,25 @@ struct SpineInfo {
     int64_t removed_nodes;
 };
 
+// Allocator whose resize leaves new elements uninitialised: large byte
+// buffers that are written at once need no zeroing pass first.
+template <class T> struct NoInitAlloc : std::allocator<T> {
+    template <class U> struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U> NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+    template <class U> void construct(U* p) noexcept { ::new ((void*)p) U; }
+    template <class U, class... A> void construct(U* p, A&&... a) { ::new ((void*)p) U(std::forward<A>(a)...); }
+};
+
 struct Pop {
     int vtype = 0;
     int n_inputs = 0;
     int layout = 0;
     bool auto_chunk = false;                // chunk size may be re-tuned
     // host copy of the trees, for re-chunking by the autotuner
-    std::vector<uint8_t> host_ops;
+    std::vector<uint8_t, NoInitAlloc<uint8_t>> host_ops;
     std::vector<int64_t> host_offsets, host_rec_points, host_rec_offsets;
     int64_t n_trees = 0;
     int64_t total_nodes = 0;
@@ -114,6 +126,10 @@ struct Pop {
         int32_t node, end, slot;
     };
     std::vector<std::vector<CutSlot>> cuts;
+    // per tree, its chunks with their code offsets in `code` (populations
+    // compiled with the subtree index), for building children from them
+    std::vector<std::vector<Chunk>> kept_chunks;
+    std::vector<int32_t> kept_max_stack;
     // evaluation state
     int64_t stride = 0;                     // case stride of vecs/recs
     DevBuf vecs;                            // [n_chunks][stride]: roots are slots 0..n_trees-1
@@ -169,9 +185,10 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
                      const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, hipStream_t s,
                      bool index_subtrees = false, const int32_t* ext_rows = nullptr);
 // Assemble already compiled trees into a population and upload it on s.
+// Chunks with dev_src >= 0 take their code from dev_code_src (device words).
 int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& progs,
                         const std::vector<int64_t>& tree_nodes, int64_t chunk_nodes, Pop* out,
-                        hipStream_t s);
+                        hipStream_t s, const uint32_t* dev_code_src = nullptr);
 // Make sure vecs/recs/fit match the case set; allocate if needed.
 int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs);
 // Enqueue a full evaluation on stream s (no copies out, no synchronisation).

@@ -246,9 +246,22 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     return assemble_population(c, vtype, n_inputs, progs, tree_nodes, chunk_nodes, out, stream);
 }
 
+// One copy for k_splice, cut into pieces that end on 64 KiB boundaries of
+// the destination (one workgroup each).
+static void add_splice_item(std::vector<SpliceItem>& items, const uint8_t* src, int64_t dst, int64_t len)
+{
+    while (len > 0) {
+        const int64_t take = std::min<int64_t>(len, ((dst + 65536) & ~int64_t(15)) - dst);
+        items.push_back(SpliceItem{src, dst, take});
+        src += take;
+        dst += take;
+        len -= take;
+    }
+}
+
 int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& progs,
                         const std::vector<int64_t>& tree_nodes, int64_t chunk_nodes, Pop* out,
-                        hipStream_t stream)
+                        hipStream_t stream, const uint32_t* dev_code_src)
 {
     const int64_t n_trees = (int64_t)progs.size();
     out->vtype = vtype;
@@ -261,16 +274,30 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
 
     // Global numbering: tree t's root chunk writes vector slot t; every
     // other chunk gets a slot after the roots.
-    int64_t n_chunks = 0, n_code = 0, n_rec = 0, n_in = 0, n_lv = 0;
+    // Chunks whose code is already on the device (dev_src, from
+    // dev_code_src) are gathered after all host code.
+    int64_t n_chunks = 0, n_code = 0, n_rec = 0, n_in = 0, n_lv = 0, n_dev = 0;
     for (auto& pg : progs) {
         n_chunks += (int64_t)pg.chunks.size();
         n_code += (int64_t)pg.code.size();
+        for (auto& ch : pg.chunks)
+            if (ch.dev_src >= 0) n_dev += ch.code_len;
         n_rec += pg.n_records;
         for (auto& ch : pg.chunks) n_in += (int64_t)ch.inputs.size();
         for (auto& sp : pg.spines) n_lv += (int64_t)sp.levels.size();
     }
     if (n_chunks > INT32_MAX / 2 || n_rec > INT32_MAX / 2 || n_in > INT32_MAX / 2)
         return set_err(c, GP_EINVAL, "population too large for one load");
+    if (n_dev > 0 && !dev_code_src) return set_err(c, GP_EINVAL, "internal error: no source for reused chunks");
+    std::vector<SpliceItem> gather;
+    int64_t dev_at = n_code;
+    const bool keep = n_trees > 0 && !progs[0].chunks.empty() && progs[0].chunks[0].end_node >= 0;
+    out->kept_chunks.clear();
+    out->kept_max_stack.clear();
+    if (keep) {
+        out->kept_chunks.resize(n_trees);
+        out->kept_max_stack.assign(n_trees, 0);
+    }
     std::vector<uint32_t> code;
     code.reserve(n_code + 64);
     std::vector<DevChunk> dch(n_chunks);
@@ -309,7 +336,13 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
         for (int64_t k = 0; k < nc; ++k) {
             const Chunk& ch = pg.chunks[k];
             DevChunk& d = dch[cbase + k];
-            d.code_off = obase + ch.code_off;
+            if (ch.dev_src >= 0) {
+                d.code_off = dev_at;
+                add_splice_item(gather, (const uint8_t*)(dev_code_src + ch.dev_src), dev_at * 4, ch.code_len * 4);
+                dev_at += ch.code_len;
+            } else {
+                d.code_off = obase + ch.code_off;
+            }
             d.code_len = (int32_t)ch.code_len;
             d.parent = ch.parent >= 0 ? (int32_t)(cbase + ch.parent) : -1;
             d.out_slot = slot[k];
@@ -334,6 +367,15 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
             out->spine_of[key] = (int32_t)out->spines.size();
             out->spines.push_back(si);
         }
+        if (keep) {
+            // kept for building children: code offsets become the uploaded ones
+            for (int64_t k = 0; k < nc; ++k) {
+                pg.chunks[k].code_off = dch[cbase + k].code_off;
+                pg.chunks[k].dev_src = -1;
+            }
+            out->kept_chunks[t].swap(pg.chunks);
+            out->kept_max_stack[t] = pg.max_stack;
+        }
         cbase += nc;
         rbase += pg.n_records;
         std::vector<uint32_t>().swap(pg.code);
@@ -344,11 +386,24 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
                      [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
                          return x.first > y.first;
                      });
-    code.push_back(0);                      // one word past the end for the fetch-ahead
     out->n_chunks = n_chunks;
-    out->n_code = (int64_t)code.size() - 1;
+    out->n_code = n_code + n_dev;
     out->n_records = n_rec;
-    RC(upload(c, out->code, code.data(), code.size() * sizeof(uint32_t), stream));
+    if (n_dev == 0) {
+        code.push_back(0);                  // one word past the end for the fetch-ahead
+        RC(upload(c, out->code, code.data(), code.size() * sizeof(uint32_t), stream));
+    } else {
+        static const uint32_t zero = 0;
+        RC(dev_alloc(c, out->code, (size_t)(n_code + n_dev + 1) * sizeof(uint32_t)));
+        uint32_t* dc = out->code.as<uint32_t>();
+        if (n_code) HIPC(c, hipMemcpyAsync(dc, code.data(), (size_t)n_code * 4, hipMemcpyHostToDevice, stream));
+        HIPC(c, hipMemcpyAsync(dc + n_code + n_dev, &zero, 4, hipMemcpyHostToDevice, stream));
+        if ((int64_t)gather.size() > (int64_t(1) << 24)) return set_err(c, GP_EINVAL, "too many chunks to gather");
+        DevBuf items;
+        RC(upload(c, items, gather.data(), gather.size() * sizeof(SpliceItem), stream));
+        HIPC(c, launch_splice(items.as<SpliceItem>(), (int64_t)gather.size(), (uint8_t*)dc, stream));
+        HIPC(c, hipStreamSynchronize(stream));
+    }
     RC(upload(c, out->chunks, dch.data(), dch.size() * sizeof(DevChunk), stream));
     RC(upload(c, out->chunk_in, chunk_in.data(), chunk_in.size() * sizeof(int32_t), stream));
     RC(upload(c, out->levels, levels.data(), levels.size() * sizeof(SpineLvl), stream));
@@ -1485,6 +1540,7 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
             HIPC(ctx, hipMemcpyAsync(drawn.data(), drawn_d.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
         }
         HIPC(ctx, hipStreamSynchronize(s));
+        const double t1 = now_ms();
         if (last) std::fill(drawn.begin(), drawn.end(), 1);
         // build them on the device: mother's prefix, father's subtree, mother's suffix
         if (!cur->tree_ops.p) {
@@ -1507,44 +1563,107 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
             DevBuf out;
             RC(dev_alloc(ctx, out, (size_t)total + 32));
             std::vector<SpliceItem> items;
-            auto add = [&](const uint8_t* src, int64_t dst, int64_t len) {
-                while (len > 0) {
-                    const int64_t take = std::min<int64_t>(len, ((dst + 65536) & ~int64_t(15)) - dst);
-                    items.push_back(SpliceItem{src, dst, take});
-                    src += take;
-                    dst += take;
-                    len -= take;
-                }
-            };
             const uint8_t* base = cur->tree_ops.as<uint8_t>();
             for (int64_t i = 0; i < N; ++i) {
                 if (new_slot[i] < 0) continue;
                 const int64_t mt = slot_tree[mother[i]], ft = slot_tree[father[i]], o = noffs[new_slot[i]];
                 const uint8_t* m = base + cur->tree_off[mt];
                 const int64_t nd = dend[i] - dnode[i];
-                add(m, o, point[i]);
-                add(base + cur->tree_off[ft] + dnode[i], o + point[i], nd);
-                add(m + point[i] + removed[i], o + point[i] + nd, cur->tree_nodes[mt] - point[i] - removed[i]);
+                add_splice_item(items, m, o, point[i]);
+                add_splice_item(items, base + cur->tree_off[ft] + dnode[i], o + point[i], nd);
+                add_splice_item(items, m + point[i] + removed[i], o + point[i] + nd,
+                                cur->tree_nodes[mt] - point[i] - removed[i]);
             }
             if ((int64_t)items.size() > (int64_t(1) << 24))
                 return set_err(ctx, GP_EINVAL, "too many bytes to build in one generation");
             DevBuf items_d;
             RC(upload(ctx, items_d, items.data(), std::max<size_t>(1, items.size()) * sizeof(SpliceItem), s));
             HIPC(ctx, launch_splice(items_d.as<SpliceItem>(), (int64_t)items.size(), out.as<uint8_t>(), s));
+            // the host copy of the same bytes, and the children's programs:
+            // built from the parents' chunks when both parents' are kept,
+            // else compiled whole
+            bool compose = cur->kept_chunks.size() == (size_t)cur->n_trees &&
+                           cur->big_ends.size() == (size_t)cur->n_trees;
+            std::vector<int64_t> built(nb);
+            for (int64_t i = 0; i < N; ++i)
+                if (new_slot[i] >= 0) {
+                    built[new_slot[i]] = i;
+                    const int64_t mt = slot_tree[mother[i]], ft = slot_tree[father[i]];
+                    compose = compose && !cur->kept_chunks[mt].empty() && !cur->kept_chunks[ft].empty();
+                }
             np->host_ops.resize((size_t)total);
-            HIPC(ctx, hipMemcpyAsync(np->host_ops.data(), out.p, (size_t)total, hipMemcpyDeviceToHost, s));
+            std::vector<TreeProg> progs(nb);
+            std::vector<std::string> errs(nb);
+            std::vector<char> bad(nb, 0);
+            CompileOptions opt;
+            opt.vtype = vtype;
+            opt.n_inputs = cur->n_inputs;
+            opt.chunk_nodes = cur->chunk_nodes;
+            opt.stack_slots = compile_stack_slots();
+            opt.index_min_size = kBigSubtree;
+            std::atomic<int64_t> next{0};
+            auto work = [&]() {
+                for (int64_t k; (k = next++) < nb;) {
+                    const int64_t i = built[k];
+                    const int64_t mt = slot_tree[mother[i]], ft = slot_tree[father[i]], nd = dend[i] - dnode[i];
+                    const uint8_t* m = cur->host_ops.data() + cur->host_offsets[mt];
+                    const uint8_t* f = cur->host_ops.data() + cur->host_offsets[ft];
+                    uint8_t* o = np->host_ops.data() + noffs[k];
+                    std::memcpy(o, m, (size_t)point[i]);
+                    std::memcpy(o + point[i], f + dnode[i], (size_t)nd);
+                    std::memcpy(o + point[i] + nd, m + point[i] + removed[i],
+                                (size_t)(cur->tree_nodes[mt] - point[i] - removed[i]));
+                    if (!compose) continue;
+                    const auto& mc = cur->kept_chunks[mt];
+                    const auto& fc = cur->kept_chunks[ft];
+                    SrcTree ms{m, cur->tree_nodes[mt], mc.data(), (int64_t)mc.size(), &cur->big_ends[mt],
+                               cur->kept_max_stack[mt]};
+                    SrcTree fs{f, cur->tree_nodes[ft], fc.data(), (int64_t)fc.size(), &cur->big_ends[ft],
+                               cur->kept_max_stack[ft]};
+                    if (!compose_child(ms, point[i], point[i] + removed[i], fs, dnode[i], dend[i], o,
+                                       noffs[k + 1] - noffs[k], opt, &progs[k], &errs[k]))
+                        bad[k] = 1;
+                }
+            };
+            const int nth = (int)std::min<int64_t>(std::min<int64_t>(16, std::max(1u, std::thread::hardware_concurrency())),
+                                                   nb);
+            std::vector<std::thread> th;
+            for (int t = 1; t < nth; ++t) th.emplace_back(work);
+            work();
+            for (auto& t : th) t.join();
+            for (int64_t k = 0; k < nb; ++k) {
+                if (bad[k]) return set_err(ctx, GP_EINVAL, "child " + std::to_string(built[k]) + ": " + errs[k]);
+                for (const Chunk& ch : progs[k].chunks)
+                    if (ch.dev_src >= 0 && (ch.code_len < 1 || ch.dev_src + ch.code_len > cur->n_code))
+                        return set_err(ctx, GP_EINVAL, "internal error: reused code out of range");
+            }
+            if (compose) {
+                std::vector<int64_t> tn(nb);
+                np->big_ends.resize(nb);
+                for (int64_t k = 0; k < nb; ++k) {
+                    tn[k] = noffs[k + 1] - noffs[k];
+                    np->big_ends[k].swap(progs[k].big_ends);
+                }
+                np->big_built.assign(nb, 1);
+                np->layout = GP_PREFIX;
+                RC(assemble_population(ctx, vtype, cur->n_inputs, progs, tn, cur->chunk_nodes, np.get(), s,
+                                       cur->code.as<uint32_t>()));
+            } else {
+                RC(build_population(ctx, vtype, GP_PREFIX, cur->n_inputs, nb, np->host_ops.data(), noffs.data(),
+                                    nullptr, nullptr, 0, np.get(), s, true));
+            }
             HIPC(ctx, hipStreamSynchronize(s));
-            RC(build_population(ctx, vtype, GP_PREFIX, cur->n_inputs, nb, np->host_ops.data(), noffs.data(), nullptr,
-                                nullptr, 0, np.get(), s, true));
             np->tree_ops.swap(out);                 // the built bytes stay on the device for the next generation
         }
         np->auto_chunk = true;
         np->host_offsets = noffs;
         np->tree_off = noffs;
+        const double t2 = now_ms();
         const int variant = choose_variant(ctx, vtype, cs, np.get());
         if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits the children");
         RC(enqueue_full(ctx, np.get(), cases, cs, variant, false, false, s, nullptr));
         HIPC(ctx, hipStreamSynchronize(s));
+        const double t3 = now_ms();
         // statistics and records
         const double* ff = (const double*)fit_h.data();
         const int64_t* fi = (const int64_t*)fit_h.data();
@@ -1564,6 +1683,9 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
                 st.interpreted_nodes += interp[i];
             }
             st.ms = now_ms() - t0;
+            st.ms_score = t1 - t0;
+            st.ms_build = t2 - t1;
+            st.ms_eval = t3 - t2;
         }
         if (children)
             for (int64_t i = 0; i < N; ++i) {
@@ -1736,6 +1858,84 @@ int64_t gp_inspect_path(const uint8_t* ops, int64_t n, int64_t c, int64_t index_
     }
     *removed_end = e;
     return (int64_t)lv.size();
+}
+
+int64_t gp_inspect_child_program(int vtype, int n_inputs, const uint8_t* mother, int64_t n_mother, int64_t point,
+                                 const int64_t* mother_records, int64_t n_mother_records,
+                                 const uint8_t* father, int64_t n_father, int64_t donor_node, int64_t chunk_nodes,
+                                 int stack_slots, int64_t index_min_size, uint32_t* code_out, int64_t code_cap,
+                                 int64_t* chunk_out, int64_t chunk_cap, int32_t* inputs_out, int64_t inputs_cap,
+                                 int64_t* big_out, int64_t big_cap, int64_t* n_code, int32_t* max_stack,
+                                 int64_t* n_big, int64_t* n_reused)
+{
+    if ((vtype != GP_F32 && vtype != GP_BOOL) || n_inputs < 1 || n_inputs > kMaxInputs || !mother || !father ||
+        index_min_size < 1)
+        return GP_EINVAL;
+    if (!validate_prefix(mother, n_mother, n_inputs, nullptr) || !validate_prefix(father, n_father, n_inputs, nullptr))
+        return GP_EINVAL;
+    if (point < 0 || point >= n_mother || donor_node < 0 || donor_node >= n_father) return GP_EINVAL;
+    CompileOptions opt;
+    opt.vtype = vtype;
+    opt.n_inputs = n_inputs;
+    opt.chunk_nodes = chunk_nodes > 0 ? chunk_nodes : 4096;
+    opt.stack_slots = stack_slots > 0 ? stack_slots : compile_stack_slots();
+    opt.index_min_size = index_min_size;
+    TreeProg pm, pf, pc;
+    std::string why;
+    if (n_mother_records < 0 || (n_mother_records > 0 && !mother_records)) return GP_EINVAL;
+    if (!compile_tree(mother, n_mother, opt, mother_records, n_mother_records, &pm, &why) ||
+        !compile_tree(father, n_father, opt, nullptr, 0, &pf, &why))
+        return GP_EINVAL;
+    // the parents' programs as one uploaded program: the mother's code, then the father's
+    std::vector<uint32_t> src(pm.code);
+    src.insert(src.end(), pf.code.begin(), pf.code.end());
+    for (Chunk& ch : pf.chunks) ch.code_off += (int64_t)pm.code.size();
+    const int64_t c_end = subtree_end_indexed(mother, n_mother, point, pm.big_ends);
+    const int64_t d_end = subtree_end_indexed(father, n_father, donor_node, pf.big_ends);
+    std::vector<uint8_t> child(mother, mother + point);
+    child.insert(child.end(), father + donor_node, father + d_end);
+    child.insert(child.end(), mother + c_end, mother + n_mother);
+    SrcTree m{mother, n_mother, pm.chunks.data(), (int64_t)pm.chunks.size(), &pm.big_ends, pm.max_stack};
+    SrcTree f{father, n_father, pf.chunks.data(), (int64_t)pf.chunks.size(), &pf.big_ends, pf.max_stack};
+    if (!compose_child(m, point, c_end, f, donor_node, d_end, child.data(), (int64_t)child.size(), opt, &pc, &why))
+        return GP_EINVAL;
+    int64_t total = 0, n_in = 0, reused = 0;
+    for (const Chunk& ch : pc.chunks) {
+        total += ch.code_len;
+        n_in += (int64_t)ch.inputs.size();
+        reused += ch.dev_src >= 0;
+    }
+    if (n_code) *n_code = total;
+    if (max_stack) *max_stack = pc.max_stack;
+    if (n_big) *n_big = (int64_t)pc.big_ends.size();
+    if (n_reused) *n_reused = reused;
+    if (total > code_cap || (int64_t)pc.chunks.size() > chunk_cap || n_in > inputs_cap ||
+        (int64_t)pc.big_ends.size() > big_cap)
+        return GP_ENOMEM;
+    int64_t at = 0, k_in = 0;
+    for (int64_t k = 0; k < (int64_t)pc.chunks.size(); ++k) {
+        const Chunk& ch = pc.chunks[k];
+        const uint32_t* from = ch.dev_src >= 0 ? src.data() + ch.dev_src : pc.code.data() + ch.code_off;
+        if (code_out) std::memcpy(code_out + at, from, (size_t)ch.code_len * sizeof(uint32_t));
+        if (chunk_out) {
+            int64_t* o = chunk_out + 6 * k;
+            o[0] = at;
+            o[1] = ch.code_len;
+            o[2] = ch.parent;
+            o[3] = (int64_t)ch.inputs.size();
+            o[4] = ch.root_node;
+            o[5] = ch.end_node;
+        }
+        at += ch.code_len;
+        for (int32_t in : ch.inputs)
+            if (inputs_out) inputs_out[k_in++] = in;
+    }
+    for (size_t i = 0; i < pc.big_ends.size(); ++i)
+        if (big_out) {
+            big_out[2 * i] = pc.big_ends[i].first;
+            big_out[2 * i + 1] = pc.big_ends[i].second;
+        }
+    return (int64_t)pc.chunks.size();
 }
 
 int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t n, int64_t chunk_nodes,

@@ -28,7 +28,7 @@ EXPORTS = [
     "gp_population_info", "gp_free", "gp_evaluate_full", "gp_evaluate_incremental_batch",
     "gp_evaluate_incremental", "gp_fitness", "gp_variant_name", "gp_variant_count", "gp_autotune",
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
-    "gp_server_stop", "gp_inspect_program", "gp_validate_tree",
+    "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree",
 ]
 
 
@@ -56,7 +56,7 @@ class EvolveCfg(C.Structure):
 class GenStats(C.Structure):
     _fields_ = [("best_f64", C.c_double), ("best_i64", C.c_int64), ("children", C.c_int64), ("built", C.c_int64),
                 ("child_nodes", C.c_int64), ("built_nodes", C.c_int64), ("interpreted_nodes", C.c_int64),
-                ("ms", C.c_double)]
+                ("ms", C.c_double), ("ms_score", C.c_double), ("ms_build", C.c_double), ("ms_eval", C.c_double)]
 
 
 class GenChild(C.Structure):
@@ -147,6 +147,11 @@ def lib() -> C.CDLL:
     h.gp_inspect_program.argtypes = [C.c_int, C.c_int, P, I64, I64, C.c_int, C.c_int, P, I64, P, I64, P, I64,
                                      C.POINTER(I64), C.POINTER(C.c_int32)]
     h.gp_inspect_program.restype = I64
+    h.gp_inspect_child_program.argtypes = [C.c_int, C.c_int, P, I64, I64, P, I64, P, I64, I64, I64, C.c_int, I64, P,
+                                           I64,
+                                           P, I64, P, I64, P, I64, C.POINTER(I64), C.POINTER(C.c_int32),
+                                           C.POINTER(I64), C.POINTER(I64)]
+    h.gp_inspect_child_program.restype = I64
     h.gp_validate_tree.argtypes = [C.c_int, C.c_int, P, I64]
     h.gp_inspect_path.argtypes = [P, I64, I64, I64, P, I64, C.POINTER(I64)]
     h.gp_inspect_path.restype = I64
@@ -183,6 +188,47 @@ class Program:
     chunks: np.ndarray     # [n_chunks, 4] int64: code offset, length, parent, n_inputs
     inputs: list           # per chunk: child chunk ids in LOAD order
     max_stack: int
+
+
+@dataclass
+class ChildProgram:
+    program: Program       # chunks: offset, length, parent, n_inputs (as inspect_program)
+    roots: np.ndarray      # per chunk: root node in the child
+    ends: np.ndarray       # per chunk: end of the root's subtree
+    big: np.ndarray        # [k, 2] (node, end) of the child's subtrees of index_min_size nodes or more
+    reused: int            # chunks whose code came from a parent
+
+
+def inspect_child_program(mother, point, father, donor_node, vtype=GP_F32, n_inputs=1, chunk_nodes=4096,
+                          stack_slots=16, index_min_size=4096, mother_records=()) -> ChildProgram:
+    """The program of the crossover child built from its parents' programs
+    (gp_inspect_child_program)."""
+    m = _np(mother, np.uint8)
+    f = _np(father, np.uint8)
+    recs = np.ascontiguousarray(np.asarray(mother_records, np.int64).reshape(-1))
+    n = len(m) + len(f)
+    cap = 2 * n + 64
+    code = np.zeros(cap, np.uint32)
+    chunks = np.zeros((n + 1, 6), np.int64)
+    ins = np.zeros(n + 1, np.int32)
+    big = np.zeros((n + 1, 2), np.int64)
+    nc, nb, nr = I64(0), I64(0), I64(0)
+    ms = C.c_int32(0)
+    r = lib().gp_inspect_child_program(vtype, n_inputs, _ptr(m), len(m), point, _ptr(recs) if len(recs) else None,
+                                       len(recs), _ptr(f), len(f), donor_node,
+                                       chunk_nodes, stack_slots, index_min_size, _ptr(code), cap, _ptr(chunks),
+                                       n + 1, _ptr(ins), n + 1, _ptr(big), n + 1, C.byref(nc), C.byref(ms),
+                                       C.byref(nb), C.byref(nr))
+    if r < 0:
+        raise GPError(int(r), "inspect_child_program failed")
+    chunks = chunks[:r].copy()
+    lists, k = [], 0
+    for c in range(r):
+        q = int(chunks[c, 3])
+        lists.append([int(v) for v in ins[k:k + q]])
+        k += q
+    prog = Program(code[:nc.value].copy(), chunks[:, :4].copy(), lists, int(ms.value))
+    return ChildProgram(prog, chunks[:, 4].copy(), chunks[:, 5].copy(), big[:nb.value].copy(), int(nr.value))
 
 
 def inspect_path(tree, c, index_min_size=4096):

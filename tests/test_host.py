@@ -179,6 +179,99 @@ def test_parallel_emission_matches_serial():
             assert a.inputs == b.inputs and a.max_stack == b.max_stack
 
 
+def _crossover_points(rng, t, i):
+    ends = gen.subtree_ends(t)
+    leaves = np.flatnonzero(t < 0x80)
+    funcs = np.flatnonzero(t >= 0x80)
+    kind = i % 4
+    if kind == 0 or len(funcs) == 0:
+        return 0 if kind == 0 else int(rng.choice(leaves)), ends
+    if kind == 1:
+        return int(rng.choice(leaves)), ends
+    return int(rng.choice(funcs)), ends
+
+
+@pytest.mark.parametrize("vtype,chunk_nodes,slots,min_size",
+                         [(0, 16, 16, 8), (0, 64, 3, 40), (0, 7, 4, 1), (0, 4096, 16, 4096), (1, 16, 16, 8),
+                          (1, 9, 3, 2)])
+def test_child_program_from_parents_matches_oracle(vtype, chunk_nodes, slots, min_size):
+    """A crossover child's program built from its parents' compiled chunks
+    (Section 5 crossover; only the chunks on the path are recompiled)
+    computes the child's values, and its chunk table and index of large
+    subtrees agree with the child tree."""
+    rng = np.random.default_rng(31 + chunk_nodes + 100 * vtype)
+    boolean = vtype == 1
+    if boolean:
+        cases = gen.bool_cases(8)
+    else:
+        x = np.concatenate([gen.float_cases(5, 29).x[0], np.array([0, -0.0, 1e-7, np.inf], np.float32)])
+    reused = chunks = 0
+    for i in range(24):
+        nt = 8 if boolean else 1
+        m = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 3001)), n_terms=nt)
+        f = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 3001)), n_terms=nt)
+        c, _ = _crossover_points(rng, m, i)
+        d, fends = _crossover_points(rng, f, i // 4)
+        cp = g.inspect_child_program(m, c, f, d, g.GP_BOOL if boolean else g.GP_F32, nt, chunk_nodes, slots,
+                                     min_size)
+        child = oracle.splice(m, c, f[d:fends[d]])
+        assert cp.program.max_stack <= slots
+        if boolean:
+            got = emulate(cp.program, cases.inputs, g.GP_BOOL)
+            assert np.array_equal(got, oracle.eval_bool(child, cases.inputs))
+        else:
+            got = emulate(cp.program, x[None, :], g.GP_F32)
+            with np.errstate(all="ignore"):
+                want = oracle.eval_f32(child, x[None, :])
+            assert same_f32(got, want).all()
+        ends = gen.subtree_ends(child)
+        assert cp.roots[-1] == 0 and len(set(cp.roots.tolist())) == len(cp.roots)
+        assert np.array_equal(cp.ends, ends[cp.roots])
+        want_big = [(v, ends[v]) for v in range(len(child)) if child[v] >= 0x80 and ends[v] - v >= min_size]
+        assert [tuple(r) for r in cp.big.tolist()] == want_big
+        n_loads = sum(1 for w in cp.program.code if (int(w) >> 2) & 7 == M_LOAD)
+        assert n_loads == len(cp.program.chunks) - 1
+        reused += cp.reused
+        chunks += len(cp.program.chunks)
+    if chunk_nodes < 100:
+        assert reused > chunks // 2
+
+
+def test_child_program_skips_chunks_that_record():
+    """Chunks of a mother that records parent caches for some points hold
+    STORE words; a child records nothing, so those chunks are recompiled and
+    the child's program has no STORE but the chunk ends."""
+    rng = np.random.default_rng(41)
+    x = gen.float_cases(6, 33).x
+    for i in range(12):
+        m = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 101, 3001)))
+        f = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 1001)))
+        recs = rng.integers(0, len(m), 3)
+        c, _ = _crossover_points(rng, m, i)
+        d, fends = _crossover_points(rng, f, i + 1)
+        whole = g.inspect_child_program(m, c, f, d, chunk_nodes=16, index_min_size=8)
+        cp = g.inspect_child_program(m, c, f, d, chunk_nodes=16, index_min_size=8, mother_records=recs)
+        assert all(int(w) == END_WORD for w in cp.program.code if (int(w) >> 2) & 7 == M_STORE)
+        assert cp.reused <= whole.reused
+        child = oracle.splice(m, c, f[d:fends[d]])
+        with np.errstate(all="ignore"):
+            assert same_f32(emulate(cp.program, x, g.GP_F32), oracle.eval_f32(child, x)).all()
+        ends = gen.subtree_ends(child)
+        assert np.array_equal(cp.ends, ends[cp.roots])
+
+
+def test_child_program_errors():
+    t = np.array([gen.F_ADD, 0, 0], np.uint8)
+    with pytest.raises(g.GPError):
+        g.inspect_child_program(t, 3, t, 0)
+    with pytest.raises(g.GPError):
+        g.inspect_child_program(t, 0, t, -1)
+    with pytest.raises(g.GPError):
+        g.inspect_child_program(t[:2], 0, t, 0)
+    with pytest.raises(g.GPError):
+        g.inspect_child_program(t, 0, t, 0, index_min_size=0)
+
+
 def test_inspect_path_matches_brute_force():
     """The co-evaluation path (ancestors nearest first, which side the path
     runs, the sibling subtree's slice) against a brute force from subtree
