@@ -145,5 +145,28 @@ def test_incremental_full_size_sampled(ctx):
 
     with ThreadPoolExecutor(8) as ex:
         assert all(ex.map(same_child, range(500)))
+    # two generations with fitness first from these parents: the children's
+    # programs are built from their parents' chunks; the final trees compiled
+    # whole, and the oracle on the smallest of them, score the same
+    nh, gst, rec = ctx.evolve(ph, ch, 2, 7, 2022)
+    say("evolve full size:", [(round(x["ms"], 1), x["built"]) for x in gst])
+    _, fit_c, _ = ctx.evaluate_full(nh, ch, g.GP_F32, 500, 1024)
+    last = rec["fitness_f64"][-1]
+    assert np.all((last == fit_c) | (np.isnan(last) & np.isnan(fit_c)))
+    ops2, offs2 = ctx.population_ops(nh)
+    wh = ctx.load_population(g.GP_F32, ops2, offs2, chunk_nodes=8192)
+    _, fit_w, _ = ctx.evaluate_full(wh, ch, g.GP_F32, 500, 1024)
+    assert np.all((fit_w == fit_c) | (np.isnan(fit_w) & np.isnan(fit_c)))
+    ctx.free(wh)
+    small = np.argsort(np.diff(offs2))[:4]
+
+    def final_fit(t):
+        with np.errstate(all="ignore"):
+            return oracle.fitness_f32(oracle.eval_f32(ops2[offs2[t]:offs2[t + 1]], cases.x), cases.y)
+
+    with ThreadPoolExecutor(4) as ex:
+        for t, w in zip(small, ex.map(final_fit, small)):
+            assert fit_c[t] == w or (math.isnan(fit_c[t]) and math.isnan(w)), t
+    ctx.free(nh)
     ctx.free(ph)
     ctx.free(ch)
