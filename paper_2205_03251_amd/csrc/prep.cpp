@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <climits>
+#include <functional>
+#include <memory>
 #include <atomic>
 #include <thread>
 #include <unordered_map>
@@ -13,14 +15,20 @@ namespace {
 
 inline bool is_func(uint8_t b) { return (b & kFuncBit) != 0; }
 
-struct Frame {
-    int64_t v;
-    int32_t d;
-    int32_t stage;     // 0 first visit, 1 after the first operand, 2 after both
-    int64_t second;    // operand evaluated second (stage 1)
-    uint32_t mode;
-    uint32_t payload;
+// Per-node work arrays of compile_tree, grown to the largest tree seen.
+struct CompileScratch {
+    int64_t cap = 0;
+    std::unique_ptr<int32_t[]> rch, end_at, len, open, st, chunk;
+    std::unique_ptr<uint8_t[]> need, cut, form;
+    void ensure(int64_t n)
+    {
+        if (n <= cap) return;
+        cap = std::max<int64_t>(n, cap + cap / 2);
+        for (auto* a : {&rch, &end_at, &len, &open, &st, &chunk}) a->reset(new int32_t[cap + 1]);
+        for (auto* a : {&need, &cut, &form}) a->reset(new uint8_t[cap + 1]);
+    }
 };
+
 
 }  // namespace
 
@@ -144,34 +152,45 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         return false;
     }
 
-    std::vector<int32_t> rch(n, -1);      // right child of each function node
-    std::vector<uint8_t> need(n, 1);      // stack slots to produce the value
-    std::vector<int32_t> open(n, 1);      // nodes not yet assigned to a chunk below
-    std::vector<uint8_t> cut(n, 0);       // node roots a chunk of its own
-    std::vector<int32_t> st;
-    st.reserve(1024);
+    // Per node, filled by the right-to-left pass; nodes are written before
+    // they are read, so nothing needs clearing first.  The arrays are kept
+    // per thread and reused: a load compiles many trees on each thread, and
+    // fresh pages cost more than the pass itself.
+    static thread_local CompileScratch ws;
+    ws.ensure(n);
+    int32_t* rch = ws.rch.get();        // right child of each function node
+    int32_t* end_at = ws.end_at.get();  // end of each node's subtree
+    int32_t* len = ws.len.get();        // words its subtree emits in its own chunk
+    int32_t* open = ws.open.get();      // nodes not yet assigned to a chunk below
+    uint8_t* need = ws.need.get();      // stack slots to produce the value
+    uint8_t* cut = ws.cut.get();        // node roots a chunk of its own
+    uint8_t* form = ws.form.get();      // mode | first operand is the right << 3 | folded operand is the left << 4
+    int32_t* st = ws.st.get();          // operand stack of the pass
+    int64_t top = 0;
     const bool index = opt.index_min_size > 0;
-    std::vector<int32_t> end_at(index ? n : 0);   // subtree ends, for the index of large subtrees
     out->big_ends.clear();
+    auto words = [&](int64_t c) -> int32_t { return cut[c] ? 1 : len[c]; };   // LOAD or the code
+    std::vector<int64_t> roots;                 // the cut nodes, as they are cut
 
     // One right-to-left pass: children are finished before their parent.
     for (int64_t i = n - 1; i >= 0; --i) {
         if (!is_func(ops[i])) {
-            st.push_back((int32_t)i);
-            if (index) end_at[i] = (int32_t)(i + 1);
-            if (opaque(i)) cut[i] = 1;        // a compiled chunk: one LOAD
+            st[top++] = (int32_t)i;
+            end_at[i] = (int32_t)(i + 1);
+            cut[i] = opaque(i) ? 1 : 0;       // a compiled chunk: one LOAD
+            need[i] = 1;
+            open[i] = 1;
+            len[i] = 1;                       // PUSH, when not folded into its parent
             continue;
         }
-        int32_t l = st.back();
-        st.pop_back();
-        int32_t r = st.back();
-        st.back() = (int32_t)i;
-        if (index) {
-            end_at[i] = end_at[r];
-            if (full(end_at[i]) - full(i) >= opt.index_min_size)
-                out->big_ends.push_back({(int32_t)full(i), (int32_t)full(end_at[i])});
-        }
+        const int32_t l = st[--top];
+        const int32_t r = st[top - 1];
+        st[top - 1] = (int32_t)i;
+        end_at[i] = end_at[r];
+        if (index && full(end_at[i]) - full(i) >= opt.index_min_size)
+            out->big_ends.push_back({(int32_t)full(i), (int32_t)full(end_at[i])});
         rch[i] = r;
+        cut[i] = 0;
         auto cost = [&](int32_t c) { return cut[c] ? 1 : (int)need[c]; };
         auto need_of = [&]() {
             bool fl = !cut[l] && foldable(l), fr = !cut[r] && foldable(r);
@@ -187,12 +206,29 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
             // its own; its value then arrives by one LOAD (one slot).
             int32_t big = cost(l) >= cost(r) ? l : r;
             cut[big] = 1;
+            roots.push_back(big);
             nd = need_of();
         }
         need[i] = (uint8_t)nd;
+        // the instruction form, fixed now that the operands' cuts are final
+        const bool fl = !cut[l] && foldable(l), fr = !cut[r] && foldable(r);
+        if (fl && fr) {
+            form[i] = M_XX;
+            len[i] = 1;
+        } else if (fl || fr) {
+            form[i] = (uint8_t)((boolean || fl ? M_XS : M_SX) | (fl ? 16 : 0));
+            len[i] = words(fl ? r : l) + 1;
+        } else {
+            const bool first_r = !(cost(l) >= cost(r));
+            form[i] = (uint8_t)((!first_r || boolean ? M_SS : M_RS) | (first_r ? 8 : 0));
+            len[i] = words(l) + words(r) + 1;
+        }
         int64_t o = 1 + (cut[l] ? 1 : open[l]) + (cut[r] ? 1 : open[r]);
         open[i] = (int32_t)std::min<int64_t>(o, INT32_MAX);
-        if (o >= C && i != 0) cut[i] = 1;
+        if (o >= C && i != 0) {
+            cut[i] = 1;
+            roots.push_back(i);
+        }
     }
 
     // Records requested by the crossover points: the mother's vector at the
@@ -226,9 +262,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         Spine sp;
         sp.point = c;
         sp.at_point = rec(c);
-        int64_t e = c;                // last node of c's subtree: follow right children
-        while (is_func(ops[e])) e = rch[e];
-        sp.child_nodes_removed = e + 1 - c;
+        sp.child_nodes_removed = end_at[c] - c;
         for (int64_t k = (int64_t)path.size() - 2; k >= 0; --k) {
             int64_t a = path[k], below = path[k + 1];
             int64_t l = a + 1, r = rch[a];
@@ -247,111 +281,137 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         return false;
     }
     out->n_records = (int64_t)rec_of.size();
+    // A recorded node's STORE follows its own word: recount the code lengths.
+    std::unique_ptr<uint8_t[]> stored;
+    if (!rec_of.empty()) {
+        stored.reset(new uint8_t[n]());
+        for (const auto& kv : rec_of) stored[kv.first] = 1;
+        for (int64_t i = n - 1; i >= 0; --i) {
+            if (!is_func(ops[i])) continue;
+            const int64_t l = i + 1, r = rch[i];
+            const uint32_t m = form[i] & 7;
+            int32_t w = m == M_XX ? 1 : (m == M_XS || m == M_SX) ? words((form[i] & 16) ? r : l) + 1
+                                                                  : words(l) + words(r) + 1;
+            len[i] = w + stored[i];
+        }
+    }
 
     // Chunks: the root plus every cut node, numbered by descending prefix
     // index so that every chunk comes after the chunks it reads.
-    std::vector<int64_t> roots;
-    for (int64_t i = n - 1; i > 0; --i)
-        if (cut[i] && !opaque(i)) roots.push_back(i);
+    std::sort(roots.begin(), roots.end(), std::greater<int64_t>());
     roots.push_back(0);
-    std::vector<int32_t> chunk_of(n, -1);
-    for (size_t k = 0; k < roots.size(); ++k) chunk_of[roots[k]] = (int32_t)k;
-
-    // Chunks are independent once the cuts are known: each one's code is
-    // emitted on its own (in parallel for a large tree) and concatenated in
-    // chunk order.
     const int64_t nch = (int64_t)roots.size();
+    std::unordered_map<int64_t, int32_t> chunk_map;
+    int32_t* chunk_dense = ws.chunk.get();
+    const bool dense = nch > 64;
+    if (dense) {
+        for (int64_t k = 0; k < nch; ++k) chunk_dense[roots[k]] = (int32_t)k;
+    } else {
+        for (int64_t k = 0; k < nch; ++k) chunk_map[roots[k]] = (int32_t)k;
+    }
+    auto chunk_of = [&](int64_t v) { return dense ? chunk_dense[v] : chunk_map[v]; };
+
+    // Chunk k's code: len[root] words, then kEndWord.  Each word's place is
+    // known from the code lengths: an instruction's first operand's code
+    // starts where the instruction's own code starts, the second's after
+    // it, and the instruction's word follows both.  So every chunk's code
+    // is written by one scan of its nodes in prefix order (parents before
+    // their operands), independent of every other chunk's.
     out->chunks.assign(nch, Chunk());
-    std::vector<std::vector<uint32_t>> codes(nch);
+    int64_t total = 0;
+    for (int64_t k = 0; k < nch; ++k) {
+        Chunk& ch = out->chunks[k];
+        ch.code_off = total;
+        ch.code_len = (int64_t)len[roots[k]] + 1;
+        total += ch.code_len;
+    }
+    out->code.resize((size_t)total);
+    // where each node's code starts in its chunk and the slot it leaves its
+    // value in (open and need are not read again); -1: folded into its parent
+    int32_t* at = open;
+    uint8_t* slot = need;
     std::vector<int32_t> slot_hi(nch, 0);
     std::vector<uint8_t> too_many(nch, 0);
-    auto emit = [&](int64_t k, std::vector<Frame>& fr) {
+    auto emit = [&](int64_t k) {
         Chunk& ch = out->chunks[k];
-        std::vector<uint32_t>& code = codes[k];
+        uint32_t* code = out->code.data() + ch.code_off;
+        const int64_t root = roots[k], end = end_at[root];
         int32_t max_slot = 0;
-        int64_t root = roots[k];
         ch.root_node = full(root);
-        ch.end_node = index ? full(end_at[root]) : -1;
+        ch.end_node = index ? full(end) : -1;
         ch.nodes = 0;
-        fr.clear();
-        fr.push_back(Frame{root, 0, 0, 0, 0, 0});
-        while (!fr.empty()) {
-            Frame& F = fr.back();
-            int64_t v = F.v;
-            int32_t d = F.d;
-            if (F.stage == 0) {
-                max_slot = std::max(max_slot, d);
-                if (v != root && cut[v]) {
-                    int32_t child;
-                    if (opaque(v)) {
-                        child = col->opaque[v];
-                    } else {
-                        child = chunk_of[v];
-                        out->chunks[child].parent = id_base + (int32_t)k;
-                        child += id_base;
-                    }
-                    code.push_back(ins_word(0, M_LOAD, d, (uint32_t)ch.inputs.size()));
-                    ch.inputs.push_back(child);
-                    fr.pop_back();
-                    continue;
+        // place operand c's code at q, value in slot d: a LOAD if it roots a chunk
+        auto place = [&](int64_t c, int32_t q, int32_t d) {
+            if (cut[c]) {
+                int32_t id;
+                if (opaque(c)) {
+                    id = col->opaque[c];
+                } else {
+                    id = chunk_of(c);
+                    out->chunks[id].parent = id_base + (int32_t)k;
+                    id += id_base;
                 }
+                code[q] = ins_word(0, M_LOAD, (uint32_t)d, (uint32_t)ch.inputs.size());
+                ch.inputs.push_back(id);
+            } else {
+                at[c] = q;
+                slot[c] = (uint8_t)d;
+            }
+        };
+        at[root] = 0;
+        slot[root] = 0;
+        for (int64_t v = root; v < end;) {
+            if (v != root && cut[v]) {          // a chunk below (or a collapsed one): skip its subtree
+                v = end_at[v];
+                continue;
+            }
+            const int32_t q = at[v];
+            if (q < 0) {                        // folded into its parent
+                ++v;
+                continue;
+            }
+            const int32_t d = slot[v];
+            max_slot = std::max(max_slot, d);
+            if (!is_func(ops[v])) {
+                code[q] = ins_word(0, M_PUSH, (uint32_t)d, external(v) ? (uint32_t)ext[v] : ops[v]);
                 ch.nodes += 1;
-                if (!is_func(ops[v])) {
-                    code.push_back(ins_word(0, M_PUSH, d, external(v) ? (uint32_t)ext[v] : ops[v]));
-                    fr.pop_back();
-                    continue;
-                }
-                int64_t l = v + 1, r = rch[v];
-                bool fl = !cut[l] && foldable(l), fr_ = !cut[r] && foldable(r);
-                if (fl && fr_) {
-                    ch.nodes += 2;
-                    F.mode = M_XX;
-                    F.payload = boolean ? (uint32_t)ops[l] | ((uint32_t)ops[r] << 11) : 0;
-                    F.stage = 2;
-                    continue;
-                }
-                if (fl || fr_) {
-                    ch.nodes += 1;
-                    int64_t other = fl ? r : l;
-                    if (boolean) {
-                        F.mode = M_XS;
-                        F.payload = fl ? ops[l] : ops[r];
-                    } else {
-                        F.mode = fl ? M_XS : M_SX;
-                        F.payload = 0;
-                    }
-                    F.stage = 2;
-                    fr.push_back(Frame{other, d, 0, 0, 0, 0});
-                    continue;
-                }
-                int nl = cut[l] ? 1 : need[l], nr = cut[r] ? 1 : need[r];
-                int64_t first = (nl >= nr) ? l : r;
-                F.second = (first == l) ? r : l;
-                F.mode = (first == l || boolean) ? M_SS : M_RS;
-                F.payload = 0;
-                F.stage = 1;
-                fr.push_back(Frame{first, d, 0, 0, 0, 0});
+                ++v;
                 continue;
             }
-            if (F.stage == 1) {
-                F.stage = 2;
-                int64_t s2 = F.second;
-                fr.push_back(Frame{s2, d + 1, 0, 0, 0, 0});
-                continue;
+            const int64_t l = v + 1, r = rch[v];
+            const uint32_t m = form[v] & 7;
+            int32_t w;                          // the instruction's own word
+            uint32_t payload = 0;
+            if (m == M_XX) {
+                at[l] = at[r] = -1;
+                if (boolean) payload = (uint32_t)ops[l] | ((uint32_t)ops[r] << 11);
+                w = q;
+                ch.nodes += 3;
+            } else if (m == M_XS || m == M_SX) {
+                const bool left_folded = (form[v] & 16) != 0;
+                const int64_t folded = left_folded ? l : r, other = left_folded ? r : l;
+                at[folded] = -1;
+                if (boolean) payload = ops[folded];
+                place(other, q, d);
+                w = q + words(other);
+                ch.nodes += 2;
+            } else {
+                const bool first_r = (form[v] & 8) != 0;
+                const int64_t first = first_r ? r : l, second = first_r ? l : r;
+                place(first, q, d);
+                place(second, q + words(first), d + 1);
+                w = q + words(first) + words(second);
+                max_slot = std::max(max_slot, d + 1);
+                ch.nodes += 1;
             }
-            // stage 2: both operands are in place
-            code.push_back(ins_word(ops[v] & 3, F.mode, d, F.payload));
-            if (F.mode == M_SS || F.mode == M_RS) max_slot = std::max(max_slot, d + 1);
-            if (!rec_of.empty()) {
-                auto it = rec_of.find(v);
-                if (it != rec_of.end()) {
-                    code.push_back(ins_word(0, M_STORE, d, (uint32_t)it->second));
-                    ch.stores = true;
-                }
+            code[w] = ins_word(ops[v] & 3, m, (uint32_t)d, payload);
+            if (stored && stored[v]) {
+                code[w + 1] = ins_word(0, M_STORE, (uint32_t)d, (uint32_t)rec_of.find(v)->second);
+                ch.stores = true;
             }
-            fr.pop_back();
+            ++v;
         }
-        code.push_back(kEndWord);
+        code[ch.code_len - 1] = kEndWord;
         slot_hi[k] = max_slot;
         if (ch.inputs.size() > kMaxPayload) too_many[k] = 1;
     };
@@ -359,34 +419,21 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     if (nth > 1 && n >= 200000) {
         std::atomic<int64_t> next{0};
         auto work = [&]() {
-            std::vector<Frame> fr;
-            fr.reserve(256);
-            for (int64_t k; (k = next++) < nch;) emit(k, fr);
+            for (int64_t k; (k = next++) < nch;) emit(k);
         };
         std::vector<std::thread> th;
         for (int t = 1; t < nth; ++t) th.emplace_back(work);
         work();
         for (auto& t : th) t.join();
     } else {
-        std::vector<Frame> fr;
-        fr.reserve(256);
-        for (int64_t k = 0; k < nch; ++k) emit(k, fr);
+        for (int64_t k = 0; k < nch; ++k) emit(k);
     }
-    size_t total_code = 0;
-    for (const auto& c : codes) total_code += c.size();
-    out->code.clear();
-    out->code.reserve(total_code);
     int32_t max_slot = 0;
     for (int64_t k = 0; k < nch; ++k) {
         if (too_many[k]) {
             if (why) *why = "chunk reads too many child chunks";
             return false;
         }
-        Chunk& ch = out->chunks[k];
-        ch.code_off = (int64_t)out->code.size();
-        ch.code_len = (int64_t)codes[k].size();
-        out->code.insert(out->code.end(), codes[k].begin(), codes[k].end());
-        std::vector<uint32_t>().swap(codes[k]);
         max_slot = std::max(max_slot, slot_hi[k]);
     }
     out->max_stack = max_slot + 1;
