@@ -52,11 +52,18 @@ Two kinds of handler use this:
     flag) and every divisor satisfies |b| <= 2^64: an unprotected divisor is
     then in [1e-6, 2^64], the quotient in [2^-124, 2^80] and the reciprocal
     normal.
-A stack / stack divide keeps the full sequence: checking both operands costs
-as many instructions as the short form saves, and measured slower.
-Each check is made over all lanes and slots of the wave (a scalar branch);
-any value outside the ranges, NaN and infinities included, sends the whole
-wave through the full sequence, and protected lanes take 1.0 either way.
+  * stack / stack: the x / stack argument with the numerator's range checked
+    per case instead of per chunk: every |numerator| in [2^-60, 2^60] and
+    every |divisor| <= 2^64.
+Each check is made over all lanes and slots of the wave (a scalar branch):
+the K values of a lane are reduced to their largest (and smallest) magnitude
+with v_max3 / v_min3, then compared once.  Any value outside the ranges,
+infinities included, sends the whole wave through the full sequence, and
+protected lanes take 1.0 either way.  The reductions pass over a NaN (an IEEE
+max/min returns the other operand), so a lane holding a NaN operand may take
+the short form; every step of it propagates the NaN, so that lane's result is
+NaN as the full sequence's is (payloads may differ; results are compared as
+bit-equal or both NaN).
 """
 from __future__ import annotations
 
@@ -128,6 +135,31 @@ def gen_one(K: int, S: int) -> str:
             a(f"  v_div_fmas_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
             a(f"  v_div_fixup_f32 {T[0]}, {T[0]}, {B}, {A}")
             a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {mask}")
+
+    def reduce_abs(kind, dst, vals):
+        """dst = max or min of |v| over vals (NaN operands are passed over,
+        so a NaN lane takes the short divide too, where it also gives NaN)."""
+        a(f"  v_{kind}3_f32 {dst}, |{vals[0]}|, |{vals[1]}|, |{vals[2]}|")
+        i = 3
+        while i + 1 < len(vals):
+            a(f"  v_{kind}3_f32 {dst}, {dst}, |{vals[i]}|, |{vals[i + 1]}|")
+            i += 2
+        if i < len(vals):
+            a(f"  v_{kind}_f32_e64 {dst}, {dst}, |{vals[i]}|")
+
+    def short_div(dst, num, den):
+        """The division sequence without scaling (see the module docstring),
+        then 1.0 where |den| < 1e-6."""
+        a(f"  v_rcp_f32_e32 {T[1]}, {den}")
+        a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{den}|, {sr('TINY')}")
+        a(f"  v_fma_f32 {T[3]}, -{den}, {T[1]}, 1.0")
+        a(f"  v_fmac_f32_e32 {T[1]}, {T[3]}, {T[1]}")
+        a(f"  v_mul_f32_e32 {T[3]}, {num}, {T[1]}")
+        a(f"  v_fma_f32 {T[4]}, -{den}, {T[3]}, {num}")
+        a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {T[1]}")
+        a(f"  v_fma_f32 {T[0]}, -{den}, {T[3]}, {num}")
+        a(f"  v_fma_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
+        a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {sp('P0')}")
 
     lab = lambda name: f".Lgp{K}_{S}_{name}_%="
     # ---------------------------------------------------------- entry
@@ -214,26 +246,12 @@ def gen_one(K: int, S: int) -> str:
             slow = lab(f"xs{d}")
             a(f"  s_bitcmp0_b32 {sr('FLG')}, 1")
             a(f"  s_cbranch_scc1 {slow}")
-            a("  s_mov_b64 vcc, exec")
-            for k in range(0, K, 2):
-                a(f"  v_cmp_le_f32_e64 {sp('P0')}, |{st(d, k)}|, {sr('HIXS')}")
-                a(f"  v_cmp_le_f32_e64 {sp('J0')}, |{st(d, k + 1)}|, {sr('HIXS')}")
-                a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
-                a(f"  s_and_b64 vcc, vcc, {sp('J0')}")
+            reduce_abs("max", T[2], [st(d, k) for k in range(K)])
+            a(f"  v_cmp_le_f32_e64 vcc, {T[2]}, {sr('HIXS')}")
             a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
             a(f"  s_cbranch_scc1 {slow}")
             for k in range(K):
-                b, x = st(d, k), xv(k)
-                a(f"  v_rcp_f32_e32 {T[1]}, {b}")
-                a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{b}|, {sr('TINY')}")
-                a(f"  v_fma_f32 {T[3]}, -{b}, {T[1]}, 1.0")
-                a(f"  v_fmac_f32_e32 {T[1]}, {T[3]}, {T[1]}")
-                a(f"  v_mul_f32_e32 {T[3]}, {x}, {T[1]}")
-                a(f"  v_fma_f32 {T[4]}, -{b}, {T[3]}, {x}")
-                a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {T[1]}")
-                a(f"  v_fma_f32 {T[0]}, -{b}, {T[3]}, {x}")
-                a(f"  v_fma_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
-                a(f"  v_cndmask_b32_e64 {b}, {T[0]}, 1.0, {sp('P0')}")
+                short_div(st(d, k), xv(k), st(d, k))
             tail()
             a(f"{slow}:")
             for k in range(K):
@@ -245,12 +263,11 @@ def gen_one(K: int, S: int) -> str:
             slow = lab(f"sx{d}")
             a(f"  s_bitcmp0_b32 {sr('FLG')}, 0")
             a(f"  s_cbranch_scc1 {slow}")
-            a("  s_mov_b64 vcc, exec")
-            for k in range(K):
-                a(f"  v_cmp_ge_f32_e64 {sp('P0')}, |{st(d, k)}|, {sr('LOSX')}")
-                a(f"  v_cmp_le_f32_e64 {sp('J0')}, |{st(d, k)}|, {sr('HISX')}")
-                a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
-                a(f"  s_and_b64 vcc, vcc, {sp('J0')}")
+            reduce_abs("min", T[1], [st(d, k) for k in range(K)])
+            reduce_abs("max", T[2], [st(d, k) for k in range(K)])
+            a(f"  v_cmp_ge_f32_e64 {sp('P0')}, {T[1]}, {sr('LOSX')}")
+            a(f"  v_cmp_le_f32_e64 vcc, {T[2]}, {sr('HISX')}")
+            a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
             a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
             a(f"  s_cbranch_scc1 {slow}")
             for k in range(K):
@@ -268,6 +285,29 @@ def gen_one(K: int, S: int) -> str:
         elif mode == M_SX:
             for k in range(K):
                 op(f, st(d, k), st(d, k), xv(k), mask=xm(k))
+        elif mode in (M_SS, M_RS) and f == 3:
+            # stack / stack: the x / stack conditions with the numerator's
+            # range checked per case: |num| in [2^-60, 2^60], |den| <= 2^64
+            slow = lab(f"ss{mode}_{d}")
+            num = [st(d, k) if mode == M_SS else st(d + 1, k) for k in range(K)]
+            den = [st(d + 1, k) if mode == M_SS else st(d, k) for k in range(K)]
+            reduce_abs("max", T[0], num)
+            reduce_abs("min", T[1], num)
+            reduce_abs("max", T[2], den)
+            a(f"  v_cmp_ge_f32_e32 vcc, {P2(60):#x}, {T[0]}")
+            a(f"  s_mov_b64 {sp('P0')}, vcc")
+            a(f"  v_cmp_le_f32_e32 vcc, {P2(-60):#x}, {T[1]}")
+            a(f"  s_and_b64 {sp('P0')}, {sp('P0')}, vcc")
+            a(f"  v_cmp_le_f32_e64 vcc, {T[2]}, {sr('HIXS')}")
+            a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
+            a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
+            a(f"  s_cbranch_scc1 {slow}")
+            for k in range(K):
+                short_div(st(d, k), num[k], den[k])
+            tail()
+            a(f"{slow}:")
+            for k in range(K):
+                op(f, st(d, k), num[k], den[k])
         elif mode == M_SS:
             for k in range(K):
                 op(f, st(d, k), st(d, k), st(d + 1, k))

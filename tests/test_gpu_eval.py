@@ -109,7 +109,7 @@ def _short_divide_cases():
     down = lambda v: np.nextafter(np.float32(v), np.float32(0))
     cols = [[], [], []]
     for blk in range(32):
-        kind = blk % 8
+        kind = blk % 10
         if kind in (0, 1):      # stack / x short path: |x0| <= 2^20, |x1| in [2^-90, 2^70]
             x0 = _signed_pow2(rng, -19.9, 20, B)
             x1 = _signed_pow2(rng, -90, 70, B)
@@ -142,6 +142,28 @@ def _short_divide_cases():
             pool = np.array([0.0, -0.0, 1e-45, -1e-40, 1.17549435e-38, 1e-30, 3.4e38, -3.4e38, np.inf, -np.inf,
                              np.nan, 1e-6, 2.0 ** 100, 2.0 ** -100, 1.0, -2.5], np.float32)
             x0, x1, x2 = (rng.choice(pool, B) for _ in range(3))
+        elif kind == 8:         # stack / stack short path: |x1| in [2^-60, 2^60], |x2| <= 2^64
+            x0 = _signed_pow2(rng, -20, 20, B)
+            x1 = _signed_pow2(rng, -60, 60, B)
+            x2 = _signed_pow2(rng, -25, 64, B)
+            x1[:4] = [2.0 ** -60, -(2.0 ** -60), 2.0 ** 60, -(2.0 ** 60)]
+            x2[:8] = [2.0 ** 64, -(2.0 ** 64), 1e-6, 9.99e-7, 0.0, -0.0, 1e-45, -1e-7]
+            if (blk // 10) % 2:     # a NaN operand, passed over by the range check
+                x1[rng.integers(8, B)] = np.nan
+                x2[rng.integers(8, B)] = np.nan
+        elif kind == 9:         # stack / stack: one value just outside
+            x0 = _signed_pow2(rng, -20, 20, B)
+            x1 = _signed_pow2(rng, -60, 60, B)
+            x2 = _signed_pow2(rng, -25, 64, B)
+            which = (blk // 10) % 3
+            j = rng.integers(B)
+            if which == 0:
+                x1[j] = down(2.0 ** -60)
+            elif which == 1:
+                x1[j] = -up(2.0 ** 60)
+            else:
+                x2[j] = up(2.0 ** 64)
+                x2[(j + 1) % B] = -np.inf
         else:                   # like the benchmark: uniform in [-1, 1]
             x0, x1, x2 = (rng.uniform(-1, 1, B).astype(np.float32) for _ in range(3))
         for c, v in zip(cols, (x0, x1, x2)):
@@ -151,9 +173,10 @@ def _short_divide_cases():
 
 
 def test_short_divides_bit_exact(ctx):
-    """Divisions by x and of x, with operands at, inside and just outside the
-    ranges where the table-dispatch loop takes its short divide, and of one
-    stack value by another, against the oracle's IEEE division."""
+    """Divisions by x, of x and of one stack value by another, with operands
+    at, inside and just outside the ranges where the table-dispatch loop
+    takes its short divide (NaN operands included), against the oracle's
+    IEEE division."""
     from tests.golden_cases import parse_tree
     cases = _short_divide_cases()
     a1 = "(+ x1 (- x0 x0))"                  # x1 on the stack (x0 - x0 = +0 for finite x0)
