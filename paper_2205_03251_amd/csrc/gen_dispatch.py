@@ -55,6 +55,9 @@ Two kinds of handler use this:
   * stack / stack: the x / stack argument with the numerator's range checked
     per case instead of per chunk: every |numerator| in [2^-60, 2^60] and
     every |divisor| <= 2^64.
+Where no lane's divisor is protected (every |divisor| >= 1e-6: a per-chunk
+flag for x, one more min-reduction for a stack value) the short form skips
+the per-case protection compare and select.
 Each check is made over all lanes and slots of the wave (a scalar branch):
 the K values of a lane are reduced to their largest (and smallest) magnitude
 with v_max3 / v_min3, then compared once.  Any value outside the ranges,
@@ -147,19 +150,39 @@ def gen_one(K: int, S: int) -> str:
         if i < len(vals):
             a(f"  v_{kind}_f32_e64 {dst}, {dst}, |{vals[i]}|")
 
-    def short_div(dst, num, den):
+    def short_div(dst, num, den, protect=True):
         """The division sequence without scaling (see the module docstring),
-        then 1.0 where |den| < 1e-6."""
+        then 1.0 where |den| < 1e-6 (protect=False: no lane has such a den)."""
         a(f"  v_rcp_f32_e32 {T[1]}, {den}")
-        a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{den}|, {sr('TINY')}")
+        if protect:
+            a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{den}|, {sr('TINY')}")
+        else:
+            a("  s_nop 0")                    # a transcendental's result is read one instruction later
         a(f"  v_fma_f32 {T[3]}, -{den}, {T[1]}, 1.0")
         a(f"  v_fmac_f32_e32 {T[1]}, {T[3]}, {T[1]}")
         a(f"  v_mul_f32_e32 {T[3]}, {num}, {T[1]}")
         a(f"  v_fma_f32 {T[4]}, -{den}, {T[3]}, {num}")
         a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {T[1]}")
         a(f"  v_fma_f32 {T[0]}, -{den}, {T[3]}, {num}")
-        a(f"  v_fma_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
-        a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {sp('P0')}")
+        if protect:
+            a(f"  v_fma_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
+            a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {sp('P0')}")
+        else:
+            a(f"  v_fma_f32 {dst}, {T[0]}, {T[1]}, {T[3]}")
+
+    def short_div_both(name, dsts, nums, dens):
+        """Both forms of the short divide: the one without the protection
+        select when every lane's smallest |den| (in T[1]) is at least 1e-6."""
+        prot = lab(name)
+        a(f"  v_cmp_ge_f32_e64 vcc, {T[1]}, {sr('TINY')}")
+        a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
+        a(f"  s_cbranch_scc1 {prot}")
+        for k in range(K):
+            short_div(dsts[k], nums[k], dens[k], protect=False)
+        tail()
+        a(f"{prot}:")
+        for k in range(K):
+            short_div(dsts[k], nums[k], dens[k])
 
     lab = lambda name: f".Lgp{K}_{S}_{name}_%="
     # ---------------------------------------------------------- entry
@@ -210,6 +233,12 @@ def gen_one(K: int, S: int) -> str:
     a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
     a(f"  s_cselect_b32 {sr('T0')}, 0, 2")
     a(f"  s_or_b32 {sr('FLG')}, {sr('FLG')}, {sr('T0')}")
+    # FLG bit 2: no lane has |x| < 1e-6, so dividing by x needs no protection select
+    reduce_abs("min", T[0], [xv(k) for k in range(K)])
+    a(f"  v_cmp_ge_f32_e64 vcc, {T[0]}, {sr('TINY')}")
+    a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
+    a(f"  s_cselect_b32 {sr('T0')}, 0, 4")
+    a(f"  s_or_b32 {sr('FLG')}, {sr('FLG')}, {sr('T0')}")
     tail()
     # ---------------------------------------------------------- table
     handlers = {}
@@ -250,8 +279,9 @@ def gen_one(K: int, S: int) -> str:
             a(f"  v_cmp_le_f32_e64 vcc, {T[2]}, {sr('HIXS')}")
             a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
             a(f"  s_cbranch_scc1 {slow}")
-            for k in range(K):
-                short_div(st(d, k), xv(k), st(d, k))
+            reduce_abs("min", T[1], [st(d, k) for k in range(K)])
+            short_div_both(f"xsp{d}", [st(d, k) for k in range(K)], [xv(k) for k in range(K)],
+                           [st(d, k) for k in range(K)])
             tail()
             a(f"{slow}:")
             for k in range(K):
@@ -270,15 +300,24 @@ def gen_one(K: int, S: int) -> str:
             a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
             a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
             a(f"  s_cbranch_scc1 {slow}")
-            for k in range(K):
-                n, x, y = st(d, k), xv(k), yv(k)
-                a(f"  v_mul_f32_e32 {T[3]}, {n}, {y}")
-                a(f"  v_fma_f32 {T[4]}, -{x}, {T[3]}, {n}")
-                a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {y}")
-                a(f"  v_fma_f32 {T[0]}, -{x}, {T[3]}, {n}")
-                a(f"  v_fma_f32 {T[0]}, {T[0]}, {y}, {T[3]}")
-                a(f"  v_cndmask_b32_e64 {n}, {T[0]}, 1.0, {xm(k)}")
-            tail()
+            unprot = lab(f"sxu{d}")
+            a(f"  s_bitcmp1_b32 {sr('FLG')}, 2")
+            a(f"  s_cbranch_scc1 {unprot}")
+            for protect in (True, False):
+                if not protect:
+                    a(f"{unprot}:")
+                for k in range(K):
+                    n, x, y = st(d, k), xv(k), yv(k)
+                    a(f"  v_mul_f32_e32 {T[3]}, {n}, {y}")
+                    a(f"  v_fma_f32 {T[4]}, -{x}, {T[3]}, {n}")
+                    a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {y}")
+                    a(f"  v_fma_f32 {T[0]}, -{x}, {T[3]}, {n}")
+                    if protect:
+                        a(f"  v_fma_f32 {T[0]}, {T[0]}, {y}, {T[3]}")
+                        a(f"  v_cndmask_b32_e64 {n}, {T[0]}, 1.0, {xm(k)}")
+                    else:
+                        a(f"  v_fma_f32 {n}, {T[0]}, {y}, {T[3]}")
+                tail()
             a(f"{slow}:")
             for k in range(K):
                 op(f, st(d, k), st(d, k), xv(k), mask=xm(k))
@@ -302,8 +341,8 @@ def gen_one(K: int, S: int) -> str:
             a(f"  s_and_b64 vcc, vcc, {sp('P0')}")
             a(f"  s_andn2_b64 {sp('A0')}, exec, vcc")
             a(f"  s_cbranch_scc1 {slow}")
-            for k in range(K):
-                short_div(st(d, k), num[k], den[k])
+            reduce_abs("min", T[1], den)
+            short_div_both(f"ssp{mode}_{d}", [st(d, k) for k in range(K)], num, den)
             tail()
             a(f"{slow}:")
             for k in range(K):
