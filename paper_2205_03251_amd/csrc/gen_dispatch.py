@@ -41,6 +41,18 @@ Short divides.  When neither operand nor any intermediate of that sequence
 can leave the normal range, div_scale returns its operand unchanged with VCC
 clear, div_fmas is a plain fma and div_fixup returns its first operand: the
 remaining steps (rcp, the two Newton steps, the final fma) give the same bits.
+The short form then stops one step earlier, by Markstein's theorem (Handbook
+of Floating-Point Arithmetic, on division by FMA): if y is the correctly
+rounded 1/b and q is within one ulp of a/b, the residual r = a - b*q is exact
+and q + r*y rounded to nearest is the correctly rounded a/b.  Here y = rcp(b)
+refined by one Newton step, and on this hardware that y equals the correctly
+rounded 1/b for every divisor with |b| in [2^-21, 2^65) (an exhaustive check
+of all 1.44e9 of them); q = a*y.  So the short form is rcp, two steps for y,
+the product, the residual and one correction (5 instructions per case after
+the rcp, 3 when y is hoisted).  On both short-divide domains it matched IEEE
+division on 1.7e10 random quotients and on 2.6e9 quotients built to lie
+within 63 * 2^-48 (relative) of a rounding midpoint, where the same step with
+the unrefined rcp(b) fails about once in 2400.
 Two kinds of handler use this:
   * stack / x: the refined reciprocal of x is hoisted with the other x-only
     work.  Allowed when every lane's unprotected x lies in [1e-6, 2^20] (a
@@ -151,8 +163,9 @@ def gen_one(K: int, S: int) -> str:
             a(f"  v_{kind}_f32_e64 {dst}, {dst}, |{vals[i]}|")
 
     def short_div(dst, num, den, protect=True):
-        """The division sequence without scaling (see the module docstring),
-        then 1.0 where |den| < 1e-6 (protect=False: no lane has such a den)."""
+        """The short divide (see the module docstring): the refined reciprocal
+        y, q = num * y, one correction q + (num - den * q) * y; then 1.0 where
+        |den| < 1e-6 (protect=False: no lane has such a den)."""
         a(f"  v_rcp_f32_e32 {T[1]}, {den}")
         if protect:
             a(f"  v_cmp_lt_f32_e64 {sp('P0')}, |{den}|, {sr('TINY')}")
@@ -162,13 +175,11 @@ def gen_one(K: int, S: int) -> str:
         a(f"  v_fmac_f32_e32 {T[1]}, {T[3]}, {T[1]}")
         a(f"  v_mul_f32_e32 {T[3]}, {num}, {T[1]}")
         a(f"  v_fma_f32 {T[4]}, -{den}, {T[3]}, {num}")
-        a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {T[1]}")
-        a(f"  v_fma_f32 {T[0]}, -{den}, {T[3]}, {num}")
         if protect:
-            a(f"  v_fma_f32 {T[0]}, {T[0]}, {T[1]}, {T[3]}")
+            a(f"  v_fma_f32 {T[0]}, {T[4]}, {T[1]}, {T[3]}")
             a(f"  v_cndmask_b32_e64 {dst}, {T[0]}, 1.0, {sp('P0')}")
         else:
-            a(f"  v_fma_f32 {dst}, {T[0]}, {T[1]}, {T[3]}")
+            a(f"  v_fma_f32 {dst}, {T[4]}, {T[1]}, {T[3]}")
 
     def short_div_both(name, dsts, nums, dens):
         """Both forms of the short divide: the one without the protection
@@ -310,13 +321,11 @@ def gen_one(K: int, S: int) -> str:
                     n, x, y = st(d, k), xv(k), yv(k)
                     a(f"  v_mul_f32_e32 {T[3]}, {n}, {y}")
                     a(f"  v_fma_f32 {T[4]}, -{x}, {T[3]}, {n}")
-                    a(f"  v_fmac_f32_e32 {T[3]}, {T[4]}, {y}")
-                    a(f"  v_fma_f32 {T[0]}, -{x}, {T[3]}, {n}")
                     if protect:
-                        a(f"  v_fma_f32 {T[0]}, {T[0]}, {y}, {T[3]}")
+                        a(f"  v_fma_f32 {T[0]}, {T[4]}, {y}, {T[3]}")
                         a(f"  v_cndmask_b32_e64 {n}, {T[0]}, 1.0, {xm(k)}")
                     else:
-                        a(f"  v_fma_f32 {n}, {T[0]}, {y}, {T[3]}")
+                        a(f"  v_fma_f32 {n}, {T[4]}, {y}, {T[3]}")
                 tail()
             a(f"{slow}:")
             for k in range(K):

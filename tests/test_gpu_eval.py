@@ -172,6 +172,58 @@ def _short_divide_cases():
     return gen.FloatCases(x, np.zeros(x.shape[1], np.float32))
 
 
+def _near_midpoint_pairs(rng, n, a_exp, b_exp):
+    """(a, b) float32 pairs whose quotient lies within 63 * 2^-48 (relative)
+    of a midpoint between floats: for an odd 24-bit significand B and small
+    odd k, M = k / B mod 2^25 (odd, 25 bits) and X = (B*M - k) / 2^25 give
+    X / B = M / 2^25 - k / (2^25 B).  Exponents are drawn from a_exp, b_exp."""
+    out_a, out_b = [], []
+    while sum(len(v) for v in out_a) < n:
+        B = (rng.integers(0, 1 << 23, 4096, dtype=np.uint64) | np.uint64(0x800001))
+        inv = B.copy()
+        for _ in range(5):                              # Newton's iteration for 1/B mod 2^32
+            inv = (inv * (np.uint64(2) - B * inv)) & np.uint64(0xffffffff)
+        k = (rng.integers(0, 32, B.size) * 2 - 63).astype(np.int64)
+        M = ((inv * (k.astype(np.uint64) & np.uint64(0xffffffff))) & np.uint64(0x1ffffff)).astype(np.int64)
+        num = B.astype(np.int64) * M - k
+        assert not np.any(num & 0x1ffffff)
+        X = num >> 25
+        ok = (M >= 1 << 24) & (X >= 1 << 23) & (X < 1 << 24)
+        X, Bk = X[ok], B[ok].astype(np.int64)
+        ea = rng.integers(a_exp[0], a_exp[1], X.size)
+        eb = rng.integers(b_exp[0], b_exp[1], X.size)
+        sa = rng.choice([-1.0, 1.0], X.size)
+        sb = rng.choice([-1.0, 1.0], X.size)
+        out_a.append((sa * np.ldexp(X.astype(np.float64), ea - 23)).astype(np.float32))
+        out_b.append((sb * np.ldexp(Bk.astype(np.float64), eb - 23)).astype(np.float32))
+    return np.concatenate(out_a)[:n], np.concatenate(out_b)[:n]
+
+
+def test_short_divides_near_midpoints(ctx):
+    """Quotients next to rounding midpoints, the hardest inputs for a
+    division by reciprocal, through every form of the short divide (x /
+    stack, stack / stack, stack / x), unprotected and, in one slice, with a
+    protected divisor; against the oracle's IEEE division."""
+    from tests.golden_cases import parse_tree
+    rng = np.random.default_rng(91)
+    s0, s1 = "(+ x0 (- x1 x1))", "(+ x1 (- x0 x0))"
+    xs_ss = gen.pack([parse_tree(t) for t in [f"(% x0 {s1})", f"(% {s0} {s1})", f"(% {s0} (% {s1} (* x0 x0)))"]],
+                     n_inputs=3)
+    sx = gen.pack([parse_tree(t) for t in [f"(% {s1} x0)", f"(- (% {s1} x0) x0)"]], n_inputs=3)
+    T = 16384
+    for rep in range(3):
+        a, b = _near_midpoint_pairs(rng, T, (-59, 59), (-20, 63))    # x0 = a, x1 = b
+        b[7] = np.float32(1e-7)                                      # one protected divisor
+        cases = gen.FloatCases(np.stack([a, b, b]), np.zeros(T, np.float32))
+        for v in f32_variants():
+            check_float_pop(ctx, xs_ss, cases, variant=v)
+        a, b = _near_midpoint_pairs(rng, T, (-89, 69), (-20, 19))    # x0 = b (the divisor), x1 = a
+        cases = gen.FloatCases(np.stack([b, a, a]), np.zeros(T, np.float32))
+        for v in f32_variants():
+            check_float_pop(ctx, sx, cases, variant=v)
+    say("near-midpoint divides: ok")
+
+
 def test_short_divides_bit_exact(ctx):
     """Divisions by x, of x and of one stack value by another, with operands
     at, inside and just outside the ranges where the table-dispatch loop
