@@ -224,6 +224,34 @@ def test_short_divides_near_midpoints(ctx):
     say("near-midpoint divides: ok")
 
 
+def test_reciprocal_every_float_of_a_binade(ctx):
+    """1 / b for every float b in [1, 2) (all 2^23 significands, both signs
+    alternating), through the x / stack short divide of each table-dispatch
+    variant, against the oracle's IEEE division."""
+    from tests.golden_cases import parse_tree
+    tree = parse_tree("(% x0 (+ x1 (- x0 x0)))")
+    pop = gen.pack([tree], n_inputs=2)
+    T = 16384
+    sig = np.arange(1 << 23, dtype=np.uint32)
+    b_all = (np.uint32(127 << 23) | sig).view(np.float32) * np.where(sig & 1, -1, 1).astype(np.float32)
+    ph = ctx.load_population(g.GP_F32, pop.ops, pop.offsets, n_inputs=2)
+    names = g.variant_names()
+    tbl = [v for v in f32_variants() if names[v].startswith("f32t_")]
+    assert tbl
+    for blk in range(0, b_all.size, T):
+        b = b_all[blk:blk + T]
+        x = np.stack([np.ones(T, np.float32), b])
+        ch = ctx.set_cases(g.GP_F32, x, np.zeros(T, np.float32))
+        want = oracle.eval_f32(tree, x)
+        for v in tbl:
+            ctx.set_variant(v)
+            roots, _, _ = ctx.evaluate_full(ph, ch, g.GP_F32, 1, T)
+            assert np.array_equal(roots[0].view(np.uint32), want.view(np.uint32)), (names[v], blk)
+        ctx.set_variant(-1)
+        ctx.free(ch)
+    ctx.free(ph)
+
+
 def test_short_divides_bit_exact(ctx):
     """Divisions by x, of x and of one stack value by another, with operands
     at, inside and just outside the ranges where the table-dispatch loop
