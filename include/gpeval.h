@@ -355,8 +355,8 @@ int gp_server_stop(gp_ctx* ctx);
  * it loads), inputs_out the child chunk ids each chunk loads, chunk after
  * chunk, in LOAD payload order.  Chunks come children first; the last one is
  * the root.  threads (1..64; values outside are clamped) host threads may
- * emit the chunks of a tree of 200000 nodes or more; the program does not
- * depend on it.  Returns the number of chunks, GP_EINVAL for a malformed tree or
+ * compile a tree of 200000 nodes or more; the program does not depend on
+ * it.  Returns the number of chunks, GP_EINVAL for a malformed tree or
  * GP_ENOMEM when a capacity is too small; *n_code gets the code length and
  * *max_stack the register-stack slots used. */
 int64_t gp_inspect_program(int vtype, int n_inputs, const uint8_t* ops, int64_t n,

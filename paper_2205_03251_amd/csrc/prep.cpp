@@ -165,30 +165,25 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     uint8_t* need = ws.need.get();      // stack slots to produce the value
     uint8_t* cut = ws.cut.get();        // node roots a chunk of its own
     uint8_t* form = ws.form.get();      // mode | first operand is the right << 3 | folded operand is the left << 4
-    int32_t* st = ws.st.get();          // operand stack of the pass
-    int64_t top = 0;
     const bool index = opt.index_min_size > 0;
     out->big_ends.clear();
     auto words = [&](int64_t c) -> int32_t { return cut[c] ? 1 : len[c]; };   // LOAD or the code
-    std::vector<int64_t> roots;                 // the cut nodes, as they are cut
+    std::vector<int64_t> roots;                 // the cut nodes
 
-    // One right-to-left pass: children are finished before their parent.
-    for (int64_t i = n - 1; i >= 0; --i) {
-        if (!is_func(ops[i])) {
-            st[top++] = (int32_t)i;
-            end_at[i] = (int32_t)(i + 1);
-            cut[i] = opaque(i) ? 1 : 0;       // a compiled chunk: one LOAD
-            need[i] = 1;
-            open[i] = 1;
-            len[i] = 1;                       // PUSH, when not folded into its parent
-            continue;
-        }
-        const int32_t l = st[--top];
-        const int32_t r = st[top - 1];
-        st[top - 1] = (int32_t)i;
+    // The pass: a node's values depend on its operands' only, so nodes can be
+    // finished in any order that puts every node after the nodes above it in
+    // index.  leaf(i) and func(i, l, r) do node i.
+    auto leaf = [&](int64_t i) {
+        end_at[i] = (int32_t)(i + 1);
+        cut[i] = opaque(i) ? 1 : 0;           // a compiled chunk: one LOAD
+        need[i] = 1;
+        open[i] = 1;
+        len[i] = 1;                           // PUSH, when not folded into its parent
+    };
+    auto func = [&](int64_t i, int32_t l, int32_t r, std::vector<int64_t>& cuts, std::vector<SubtreeEnd>& bigs) {
         end_at[i] = end_at[r];
         if (index && full(end_at[i]) - full(i) >= opt.index_min_size)
-            out->big_ends.push_back({(int32_t)full(i), (int32_t)full(end_at[i])});
+            bigs.push_back({(int32_t)full(i), (int32_t)full(end_at[i])});
         rch[i] = r;
         cut[i] = 0;
         auto cost = [&](int32_t c) { return cut[c] ? 1 : (int)need[c]; };
@@ -206,7 +201,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
             // its own; its value then arrives by one LOAD (one slot).
             int32_t big = cost(l) >= cost(r) ? l : r;
             cut[big] = 1;
-            roots.push_back(big);
+            cuts.push_back(big);
             nd = need_of();
         }
         need[i] = (uint8_t)nd;
@@ -227,8 +222,62 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         open[i] = (int32_t)std::min<int64_t>(o, INT32_MAX);
         if (o >= C && i != 0) {
             cut[i] = 1;
-            roots.push_back(i);
+            cuts.push_back(i);
         }
+    };
+    const int pth = (int)std::min<int64_t>(std::max(1, opt.threads), 64);
+    if (pth > 1 && n >= 200000 && n_points == 0) {
+        // Segments of the array in parallel, right to left, a node's right
+        // operand found as the end of its left one; a node whose subtree runs
+        // past its segment's end waits.  Then the waiting nodes, about the
+        // tree's depth per segment, in decreasing index order.
+        std::vector<std::vector<int64_t>> seg_cuts(pth), seg_wait(pth);
+        std::vector<std::vector<SubtreeEnd>> seg_big(pth);
+        std::vector<std::thread> th;
+        auto seg = [&](int t) {
+            const int64_t lo = n * t / pth, hi = n * (t + 1) / pth;
+            for (int64_t i = hi - 1; i >= lo; --i) {
+                if (!is_func(ops[i])) {
+                    leaf(i);
+                    continue;
+                }
+                const int32_t l = (int32_t)(i + 1);
+                if (l >= hi || end_at[l] < 0 || end_at[l] >= hi || end_at[end_at[l]] < 0) {
+                    end_at[i] = -1;           // an operand lies beyond this segment
+                    seg_wait[t].push_back(i);
+                    continue;
+                }
+                func(i, l, end_at[l], seg_cuts[t], seg_big[t]);
+            }
+        };
+        for (int t = 1; t < pth; ++t) th.emplace_back(seg, t);
+        seg(0);
+        for (auto& x : th) x.join();
+        std::vector<SubtreeEnd> bigs;
+        for (int t = pth - 1; t >= 0; --t)
+            for (int64_t i : seg_wait[t]) func(i, (int32_t)(i + 1), end_at[i + 1], roots, bigs);
+        for (int t = 0; t < pth; ++t) {
+            roots.insert(roots.end(), seg_cuts[t].begin(), seg_cuts[t].end());
+            out->big_ends.insert(out->big_ends.end(), seg_big[t].begin(), seg_big[t].end());
+        }
+        out->big_ends.insert(out->big_ends.end(), bigs.begin(), bigs.end());
+        std::sort(out->big_ends.begin(), out->big_ends.end());
+    } else {
+        // one pass with an operand stack (the right operand is the second entry)
+        int32_t* st = ws.st.get();
+        int64_t top = 0;
+        for (int64_t i = n - 1; i >= 0; --i) {
+            if (!is_func(ops[i])) {
+                leaf(i);
+                st[top++] = (int32_t)i;
+                continue;
+            }
+            const int32_t l = st[--top];
+            const int32_t r = st[top - 1];
+            st[top - 1] = (int32_t)i;
+            func(i, l, r, roots, out->big_ends);
+        }
+        std::reverse(out->big_ends.begin(), out->big_ends.end());   // found right to left
     }
 
     // Records requested by the crossover points: the mother's vector at the
@@ -242,7 +291,6 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         rec_of.emplace(v, id);
         return id;
     };
-    std::reverse(out->big_ends.begin(), out->big_ends.end());   // found right to left
     out->spines.clear();
     std::vector<int64_t> path;
     for (int64_t p = 0; p < n_points; ++p) {

@@ -99,7 +99,7 @@ struct CompileOptions {
     int64_t chunk_nodes = 4096;  // target nodes per chunk
     int stack_slots = 16;        // register-stack slots available
     int64_t index_min_size = 0;  // > 0: list (node, end) of subtrees this large, sorted by node
-    int threads = 1;             // threads for emitting a large tree's chunks
+    int threads = 1;             // threads for compiling a large tree (same program for any count)
 };
 
 // Section 3.1 format check of one prefix array.

@@ -186,6 +186,8 @@ void prep_worker(Server* S)
             opt.n_inputs = cs->n_inputs;
             opt.chunk_nodes = auto_chunk_nodes(cs->vtype, (int64_t)j->ops.size(), 1, cs->T);
             opt.stack_slots = compile_stack_slots();
+            // a large tree is compiled on a few threads (its latency is mostly this)
+            if (j->ops.size() >= 1000000) opt.threads = 4;
             if (!compile_tree(j->ops.data(), (int64_t)j->ops.size(), opt, j->points.data(), (int64_t)j->points.size(),
                               &j->prog, &why)) {
                 status = GP_EINVAL;

@@ -166,13 +166,15 @@ def test_chunk_sizes_bounded():
 
 
 def test_parallel_emission_matches_serial():
-    """A large tree's chunks may be emitted on several host threads; the
-    program (code, chunk table, load lists, stack use) is the same."""
+    """A large tree may be compiled on several host threads (the pass over
+    segments of the array, then the nodes whose subtrees cross a segment's
+    end; the chunks' code); the program (code, chunk table, load lists,
+    stack use) is the same."""
     rng = np.random.default_rng(23)
     t = gen.sized_tree(rng, 400_001)
     for C in [64, 4096]:
         a = g.inspect_program(t, g.GP_F32, 1, C, 10, threads=1)
-        for th in [3, 8]:
+        for th in [2, 3, 8, 16]:
             b = g.inspect_program(t, g.GP_F32, 1, C, 10, threads=th)
             assert np.array_equal(a.code, b.code)
             assert np.array_equal(a.chunks, b.chunks)
