@@ -185,7 +185,10 @@ def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, load=0.8):
         lat_inc = np.array([done[i]["latency_ms"] for i, j in enumerate(jobs) if j.kind == 1])
         lat = np.array([done[i]["latency_ms"] for i in range(len(jobs))])
         bad = sum(1 for r in done.values() if r["status"] != 0)
+        queue = np.array([done[i]["queue_ms"] for i in range(len(jobs))])
         return {"jobs": len(jobs), "failed": bad, "wall_s": round(wall, 3),
+                "mean_queue_ms": round(float(queue.mean()), 3),          # submit to admission (includes compiling)
+                "mean_run_ms": round(float((lat - queue).mean()), 3),    # admission to completion
                 "jobs_per_s": round(len(jobs) / wall, 1),
                 "equivalent_gpops": round(float(equiv.sum()) / wall / 1e9, 1),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),

@@ -42,6 +42,21 @@ bool validate_prefix(const uint8_t* ops, int64_t n, int n_inputs, std::string* w
         if (why) *why = "tree longer than 2^31-1 nodes";
         return false;
     }
+    {
+        // Branch-free scan: valid iff the open child slots stay >= 1 before
+        // the last byte and reach 0 at it, and no byte is out of range.  The
+        // loop below only runs to say what is wrong.
+        int64_t slots = 1, least = 1;
+        uint32_t bad = 0;
+        const uint32_t nin = (uint32_t)n_inputs;
+        for (int64_t i = 0; i < n; ++i) {
+            const uint32_t b = ops[i], f = b >> 7;
+            slots += 2 * (int64_t)f - 1;
+            least = std::min(least, i + 1 < n ? slots : least);
+            bad |= (f & (uint32_t)((b & 0x7c) != 0)) | ((f ^ 1u) & (uint32_t)(b >= nin));
+        }
+        if (slots == 0 && least >= 1 && bad == 0) return true;
+    }
     int64_t open = 1;   // child slots still to fill
     for (int64_t i = 0; i < n; ++i) {
         if (open == 0) {

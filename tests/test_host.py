@@ -52,6 +52,27 @@ def test_validate_matches_oracle_corpus():
         assert g.validate_tree(cut, n_inputs=3) == oracle.validate(cut, 3)
 
 
+def test_validate_mutated_trees_match_oracle():
+    """The library's validation (a branch-free scan, explained by a second
+    loop on failure) against the oracle on trees with random bytes changed,
+    cut, extended or swapped, valid and invalid."""
+    rng = np.random.default_rng(12)
+    for i in range(2000):
+        nin = int(rng.integers(1, 9))
+        t = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 201)), n_terms=nin).copy()
+        kind = i % 5
+        if kind == 0 and len(t) > 0:
+            t[rng.integers(len(t))] = rng.integers(0, 256)
+        elif kind == 1:
+            t = t[: int(rng.integers(len(t) + 1))]
+        elif kind == 2:
+            t = np.concatenate([t, rng.integers(0, 256, int(rng.integers(1, 4))).astype(np.uint8)])
+        elif kind == 3 and len(t) > 1:
+            a, b = rng.integers(len(t), size=2)
+            t[a], t[b] = t[b], t[a]
+        assert g.validate_tree(t, n_inputs=nin) == oracle.validate(t, nin), (i, t)
+
+
 def _op_f32(f, a, b):
     with np.errstate(all="ignore"):
         if f == 0:
