@@ -743,6 +743,7 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
         // the subtree is a chunk of the mother, from her last evaluation (row).
         struct Ref {
             int64_t slot, row;
+            int64_t input = -1;                 // >= 0: a terminal, its case-set input row
         };
         struct Pick {
             int64_t child, first, count;
@@ -763,6 +764,10 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
         auto add_sub = [&](int64_t i, int64_t b, int64_t e, Ref* ref) -> int64_t {
             const uint8_t* t = tree_of(i);
             int64_t nodes = 0;
+            if (e - b == 1 && !(t[b] & 0x80)) {  // a terminal: its input row, nothing to evaluate
+                *ref = Ref{-1, -1, (int64_t)t[b]};
+                return 0;
+            }
             if (ckpt) {
                 const auto& cl = p->cuts[jobs[i].tree];
                 auto lb = [&](int64_t x) {
@@ -854,7 +859,9 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
         }
         const uint8_t* rv = (const uint8_t*)rp.vecs.p;
         const uint8_t* mv = (const uint8_t*)p->vecs.p;
+        const uint8_t* iv = (const uint8_t*)cs->inputs.p;
         auto ptr = [&](const Ref& rf) -> const void* {
+            if (rf.input >= 0) return (const void*)(iv + (size_t)rf.input * row);
             return rf.row >= 0 ? (const void*)(mv + (size_t)rf.row * row) : (const void*)(rv + (size_t)rf.slot * row);
         };
         std::vector<CoLevel> lv;
