@@ -706,15 +706,19 @@ bool compose_child(const SrcTree& m, int64_t c, int64_t c_end, const SrcTree& f,
             return false;
         }
     }
-    // index entries inside the reused chunks, from the parents' indexes
+    // index entries inside the reused chunks, from the parents' indexes: in
+    // the order of the tops, so sorted, as the recompiled part's are; merged
+    std::vector<SubtreeEnd> reused_big;
     for (const Top& tp : tops) {
         const std::vector<SubtreeEnd>& big = tp.from_mother ? *m.big : *f.big;
         auto it = std::lower_bound(big.begin(), big.end(), SubtreeEnd{(int32_t)tp.src_root, INT32_MIN});
         const int64_t shift = tp.root - tp.src_root;
         for (; it != big.end() && it->first < tp.src_end; ++it)
-            out->big_ends.push_back({(int32_t)(it->first + shift), (int32_t)(it->second + shift)});
+            reused_big.push_back({(int32_t)(it->first + shift), (int32_t)(it->second + shift)});
     }
-    std::sort(out->big_ends.begin(), out->big_ends.end());
+    std::vector<SubtreeEnd> merged(out->big_ends.size() + reused_big.size());
+    std::merge(out->big_ends.begin(), out->big_ends.end(), reused_big.begin(), reused_big.end(), merged.begin());
+    out->big_ends.swap(merged);
     for (int64_t k = (int64_t)out->chunks.size() - 1; k >= 0; --k) {
         Chunk& ch = out->chunks[k];
         ch.path_nodes = ch.nodes + (ch.parent >= 0 ? out->chunks[ch.parent].path_nodes : 0);

@@ -3,7 +3,11 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <sys/mman.h>
+
 #include <atomic>
+#include <cstdlib>
+#include <new>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -77,15 +81,32 @@ struct SpineInfo {
 };
 
 // Allocator whose resize leaves new elements uninitialised: large byte
-// buffers that are written at once need no zeroing pass first.
+// buffers that are written at once need no zeroing pass first.  Blocks of
+// 64 MiB or more are 2 MiB aligned and marked for transparent huge pages, so
+// filling gigabytes takes thousands of page faults rather than millions.
 template <class T> struct NoInitAlloc : std::allocator<T> {
     template <class U> struct rebind {
         using other = NoInitAlloc<U>;
     };
+    static constexpr size_t kHuge = size_t(1) << 21, kLarge = size_t(1) << 26;
     NoInitAlloc() = default;
     template <class U> NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
     template <class U> void construct(U* p) noexcept { ::new ((void*)p) U; }
     template <class U, class... A> void construct(U* p, A&&... a) { ::new ((void*)p) U(std::forward<A>(a)...); }
+    T* allocate(size_t n)
+    {
+        const size_t bytes = n * sizeof(T);
+        if (bytes < kLarge) return std::allocator<T>::allocate(n);
+        void* p = std::aligned_alloc(kHuge, (bytes + kHuge - 1) & ~(kHuge - 1));
+        if (!p) throw std::bad_alloc();
+        (void)madvise(p, bytes, MADV_HUGEPAGE);
+        return (T*)p;
+    }
+    void deallocate(T* p, size_t n)
+    {
+        if (n * sizeof(T) < kLarge) std::allocator<T>::deallocate(p, n);
+        else std::free(p);
+    }
 };
 
 struct Pop {
