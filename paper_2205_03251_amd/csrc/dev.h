@@ -133,7 +133,26 @@ struct Variant {
     int S;                       // register-stack slots
     const void* kernel;          // for occupancy queries
     int max_blocks_per_cu;       // filled at context creation
+    int table;                   // runs the generated table-dispatch loop
+    int max_inputs;              // input rows held in registers (0: any count, staged in LDS)
 };
+
+// Whether variant v can run a population of value type vtype whose programs
+// need max_stack slots, on n_inputs input rows of stride elements of esz bytes
+// (the table loops address a row with a 32-bit byte stride).
+inline bool variant_fits(const Variant& v, int vtype, int max_stack, int n_inputs, int64_t stride, int esz)
+{
+    if (v.vtype != vtype || v.S < max_stack) return false;
+    if (v.max_inputs > 0 && n_inputs > v.max_inputs) return false;
+    if (v.table && stride * esz > (int64_t)0xffffffffLL) return false;
+    return true;
+}
+
+// Bytes of dynamic LDS a launch of v takes for n_inputs input rows.
+inline size_t variant_lds(const Variant& v, int n_inputs)
+{
+    return v.vtype == 1 && v.max_inputs == 0 ? (size_t)n_inputs * kWave * v.K * sizeof(uint64_t) : 0;
+}
 
 int variant_count();
 Variant* variant_table();

@@ -427,15 +427,191 @@ __device__ __forceinline__ void run_f32_dispatch_{K}_{S}(const GP_CONST uint32_t
 """
 
 
-def main(out_path: str) -> None:
-    parts = ["// Generated by gen_dispatch.py; do not edit.\n#pragma once\n"]
-    for K, S in VARIANTS:
-        parts.append(gen_one(K, S))
-    text = "".join(parts)
-    old = open(out_path).read() if os.path.exists(out_path) else None
+# ---------------------------------------------------------------- Boolean
+# The Boolean loop (dispatch_bool.inc): K 64-bit words (64 cases each) per
+# lane, a value being a VGPR pair (lo, hi).  The input words of the slice,
+# up to NI inputs, are loaded into VGPRs when the chunk starts; an instruction
+# names an input by its payload, a wave-uniform index, so the handler reads it
+# in GPR index mode (register number offset by an SGPR) rather than from LDS.
+BOOL_VARIANTS = [(1, 10), (2, 10)]
+BOOL_NI = 16
+
+
+def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
+    V_IN = V_ST + S * K * 2
+    V_T = V_IN + NI * K * 2
+    n_vgpr = V_T + 4 * K
+    names = []
+    for p in ["TB", "TG", "A"]:
+        names += [f"{p}0", f"{p}1"]
+    names += ["INS", "NXT", "OFF", "T0", "T1", "J"]
+    s = {n: S_BASE + i for i, n in enumerate(names)}
+    sr = lambda n: f"s{s[n]}"
+    sp = lambda n: f"s[{s[n]}:{s[n] + 1}]"
+    st = lambda d, k, h: f"v{V_ST + (d * K + k) * 2 + h}"
+    inp = lambda k, h: f"v{V_IN + k * 2 + h}"          # input 0; M0 moves to input j
+    ta = lambda k, h: f"v{V_T + k * 2 + h}"             # first operand read from the inputs
+    tb = lambda k, h: f"v{V_T + 2 * K + k * 2 + h}"     # second
+    L = []
+    a = L.append
+    lab = lambda name: f".Lgb{K}_{S}_{name}_%="
+
+    def tail():
+        a("  s_waitcnt lgkmcnt(0)")
+        a(f"  s_mov_b32 {sr('INS')}, {sr('NXT')}")
+        a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
+        a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+        a(f"  s_and_b32 {sr('TG0')}, {sr('INS')}, 0x3ff")
+        a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
+        a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
+        a(f"  s_setpc_b64 {sp('TG0')}")
+
+    def read_input(idx_sreg, dst):
+        """dst(k, h) = input[idx][k] (half h), read idx * 2K registers past input 0
+        in GPR index mode (the offset applies to SRC0 of the moves in between)."""
+        a(f"  s_lshl_b32 {sr('J')}, {idx_sreg}, {(2 * K).bit_length() - 1}")
+        a(f"  s_set_gpr_idx_on {sr('J')}, gpr_idx(SRC0)")
+        for k in range(K):
+            for h in range(2):
+                a(f"  v_mov_b32_e32 {dst(k, h)}, {inp(k, h)}")
+        a("  s_set_gpr_idx_off")
+
+    def op64(f, d, k, A, B):
+        for h in range(2):
+            dst = st(d, k, h)
+            a(f"  v_{'and' if f in (0, 2) else 'or'}_b32_e32 {dst}, {A(k, h)}, {B(k, h)}")
+            if f >= 2:
+                a(f"  v_not_b32_e32 {dst}, {dst}")
+
+    # ---------------------------------------------------------- entry
+    a(f"  s_getpc_b64 {sp('TB0')}")
+    a(f"{lab('pc')}:")
+    a(f"  s_add_u32 {sr('TB0')}, {sr('TB0')}, {lab('tbl')}-{lab('pc')}")
+    a(f"  s_addc_u32 {sr('TB1')}, {sr('TB1')}, 0")
+    a(f"  s_mov_b32 {sr('OFF')}, 0")
+    a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+    # the slice's input words: row j at inb + j * strideb, for j < n_inputs
+    a(f"  s_mov_b32 {sr('A0')}, %[inb_lo]")
+    a(f"  s_mov_b32 {sr('A1')}, %[inb_hi]")
+    for j in range(NI):
+        a(f"  s_cmp_le_u32 %[nin], {j}")
+        a(f"  s_cbranch_scc1 {lab('inok')}")
+        for k in range(K):
+            a(f"  global_load_dwordx2 v[{V_IN + (j * K + k) * 2}:{V_IN + (j * K + k) * 2 + 1}], %[voff], "
+              f"{sp('A0')} offset:{512 * k}")
+        a(f"  s_add_u32 {sr('A0')}, {sr('A0')}, %[strideb]")
+        a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, 0")
+    a(f"{lab('inok')}:")
+    a("  s_waitcnt vmcnt(0)")
+    tail()
+    # ---------------------------------------------------------- table
+    handlers = {}
+    for key in range(1024):
+        f, mode, d = key & 3, (key >> 2) & 7, key >> 5
+        if key == END_KEY:
+            handlers[key] = "end"
+        elif d < S and mode in (M_XX, M_XS):
+            handlers[key] = f"h{key}"
+        elif d + 1 < S and mode == M_SS:
+            handlers[key] = f"h{key}"
+        elif d < S and f == 0 and mode in (M_PUSH, M_LOAD, M_STORE):
+            handlers[key] = f"h{key}"
+        else:
+            handlers[key] = "end"     # never emitted for Boolean programs; ends the chunk
+    a(f"{lab('tbl')}:")
+    for key in range(1024):
+        a(f"  s_branch {lab(handlers[key])}")
+    # ---------------------------------------------------------- handlers
+    for key in range(1024):
+        if handlers[key] != f"h{key}":
+            continue
+        f, mode, d = key & 3, (key >> 2) & 7, key >> 5
+        a(f"{lab(handlers[key])}:")
+        if mode == M_XX:                 # f(input a, input b), a = payload & 2047, b = payload >> 11
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_and_b32 {sr('T1')}, {sr('T0')}, 0x7ff")
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('T0')}, 11")
+            read_input(sr('T1'), ta)
+            read_input(sr('T0'), tb)
+            for k in range(K):
+                op64(f, d, k, ta, tb)
+        elif mode == M_XS:               # f(input payload, slot d)
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            read_input(sr('T0'), ta)
+            for k in range(K):
+                op64(f, d, k, ta, lambda k_, h: st(d, k_, h))
+        elif mode == M_SS:
+            for k in range(K):
+                op64(f, d, k, lambda k_, h: st(d, k_, h), lambda k_, h: st(d + 1, k_, h))
+        elif mode == M_PUSH:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            read_input(sr('T0'), lambda k, h: st(d, k, h))
+        elif mode == M_LOAD:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 2")
+            a(f"  s_load_dword {sr('T1')}, %[cin], {sr('T0')}")
+            a("  s_waitcnt lgkmcnt(0)")
+            a(f"  s_mul_i32 {sr('A0')}, {sr('T1')}, %[strideb]")
+            a(f"  s_mul_hi_u32 {sr('A1')}, {sr('T1')}, %[strideb]")
+            a(f"  s_add_u32 {sr('A0')}, {sr('A0')}, %[vb_lo]")
+            a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, %[vb_hi]")
+            for k in range(K):
+                a(f"  global_load_dwordx2 v[{V_ST + (d * K + k) * 2}:{V_ST + (d * K + k) * 2 + 1}], %[voff], "
+                  f"{sp('A0')} offset:{512 * k}")
+            a("  s_waitcnt vmcnt(0)")
+        elif mode == M_STORE:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_mul_i32 {sr('A0')}, {sr('T0')}, %[strideb]")
+            a(f"  s_mul_hi_u32 {sr('A1')}, {sr('T0')}, %[strideb]")
+            a(f"  s_add_u32 {sr('A0')}, {sr('A0')}, %[rb_lo]")
+            a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, %[rb_hi]")
+            for k in range(K):
+                a(f"  global_store_dwordx2 %[voff], v[{V_ST + (d * K + k) * 2}:{V_ST + (d * K + k) * 2 + 1}], "
+                  f"{sp('A0')} offset:{512 * k}")
+        tail()
+    # ---------------------------------------------------------- end
+    a(f"{lab('end')}:")
+    a("  s_waitcnt lgkmcnt(0)")
+    for k in range(K):
+        a(f"  global_store_dwordx2 %[voff], v[{V_ST + k * 2}:{V_ST + k * 2 + 1}], %[outb] offset:{512 * k}")
+    a("  s_waitcnt vmcnt(0)")
+
+    body = "\n".join(f'        "{line}\\n"' for line in L)
+    vclob = ", ".join(f'"v{i}"' for i in range(V_ST, n_vgpr))
+    sclob = ", ".join(f'"s{s[n]}"' for n in names)
+    return f"""
+// K = {K} words per lane, S = {S} stack slots, up to {NI} inputs: v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(names) - 1}.
+__device__ __forceinline__ void run_bool_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const uint64_t* inb,
+                                                      const uint64_t* vb, uint64_t* rb, const GP_CONST int32_t* cin,
+                                                      uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin)
+{{
+    const uint64_t inb64 = (uint64_t)inb, vb64 = (uint64_t)vb, rb64 = (uint64_t)rb;
+    asm volatile(
+{body}
+        :
+        : [code] "s"(code), [inb_lo] "s"((uint32_t)inb64), [inb_hi] "s"((uint32_t)(inb64 >> 32)),
+          [vb_lo] "s"((uint32_t)vb64), [vb_hi] "s"((uint32_t)(vb64 >> 32)),
+          [rb_lo] "s"((uint32_t)rb64), [rb_hi] "s"((uint32_t)(rb64 >> 32)), [cin] "s"(cin),
+          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff), [nin] "s"(nin)
+        : "memory", "vcc", "scc", "m0", {sclob},
+          {vclob});
+}}
+"""
+
+
+def write_if_changed(path: str, text: str) -> None:
+    old = open(path).read() if os.path.exists(path) else None
     if old != text:
-        with open(out_path, "w") as fh:
+        with open(path, "w") as fh:
             fh.write(text)
+
+
+def main(out_path: str) -> None:
+    head = "// Generated by gen_dispatch.py; do not edit.\n#pragma once\n"
+    write_if_changed(out_path, head + "".join(gen_one(K, S) for K, S in VARIANTS))
+    write_if_changed(os.path.join(os.path.dirname(out_path), "dispatch_bool.inc"),
+                     head + f"constexpr int kBoolDispatchInputs = {BOOL_NI};\n"
+                     + "".join(gen_bool(K, S) for K, S in BOOL_VARIANTS))
 
 
 if __name__ == "__main__":

@@ -437,6 +437,61 @@ __global__ __launch_bounds__(64) void k_eval_bool(EvalParams p)
     }
 }
 
+// ------------------------------ Boolean interpreter, table dispatch
+// Same work items and chunk hand-off as k_eval_bool.  The generated loop
+// (gen_dispatch.py) loads the slice's input words, at most kBoolRegInputs
+// rows, into registers when a chunk starts and reads them by index in GPR
+// index mode, so no LDS is staged and no barrier is taken.
+#include "dispatch_bool.inc"
+
+constexpr int kBoolRegInputs = kBoolDispatchInputs;
+
+template <int K, int S>
+__device__ __forceinline__ void run_bool_dispatch(const GP_CONST uint32_t* code, const uint64_t* inb,
+                                                  const uint64_t* vb, uint64_t* rb, const GP_CONST int32_t* cin,
+                                                  uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin)
+{
+    if constexpr (K == 1 && S == 10) run_bool_dispatch_1_10(code, inb, vb, rb, cin, strideb, outb, voff, nin);
+    else if constexpr (K == 2 && S == 10) run_bool_dispatch_2_10(code, inb, vb, rb, cin, strideb, outb, voff, nin);
+    else static_assert(K == 1 && S == 10, "no generated Boolean loop for this K and S");
+}
+
+template <int K, int S>
+__global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
+{
+    const int lane = threadIdx.x;
+    const uint32_t voff = (uint32_t)lane * 8u;
+    const uint32_t strideb = (uint32_t)(p.stride * 8);
+    const uint32_t nin = (uint32_t)p.n_inputs;
+    for (;;) {
+        unsigned int it = 0;
+        if (lane == 0) it = atomicAdd(p.cursor, 1u);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if ((int64_t)it >= p.n_items) break;
+        const int64_t item = cst(p.items)[it];
+        int32_t c = (int32_t)(item >> 16);
+        const int32_t s = (int32_t)(item & 0xffff);
+        const int64_t case0 = (int64_t)s * (kWave * K);
+        const uint64_t* inb = (const uint64_t*)p.inputs + case0;
+        const uint64_t* vb = (const uint64_t*)p.vecs + case0;
+        for (;;) {
+            const ChunkHdr ch = load_chunk(cst(p.chunks) + c);
+            uint64_t* rb = (uint64_t*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
+            uint64_t* outb = (uint64_t*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
+            run_bool_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
+                                    outb, voff, nin);
+            if (ch.parent < 0) break;
+            int old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(p.pending + (int64_t)ch.parent * p.n_slices + s, -1,
+                                             __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old != 1) break;
+            c = ch.parent;
+        }
+    }
+}
+
 // ------------------------------------------------------------- init
 __global__ void k_init(int32_t* pending, const int32_t* init, int64_t n, unsigned int* cursor,
                        int n_cursors)
@@ -710,11 +765,13 @@ static Variant g_variants[] = {
     {"f32_k8_s16", 0, 8, 16, (const void*)k_eval_f32<8, 16>, 0},
     {"f32_k4_s10", 0, 4, 10, (const void*)k_eval_f32<4, 10>, 0},
     {"f32_k8_s10", 0, 8, 10, (const void*)k_eval_f32<8, 10>, 0},
-    {"f32t_k4_s10", 0, 4, 10, (const void*)k_eval_f32_tbl<4, 10>, 0},
-    {"f32t_k8_s10", 0, 8, 10, (const void*)k_eval_f32_tbl<8, 10>, 0},
+    {"f32t_k4_s10", 0, 4, 10, (const void*)k_eval_f32_tbl<4, 10>, 0, 1, 0},
+    {"f32t_k8_s10", 0, 8, 10, (const void*)k_eval_f32_tbl<8, 10>, 0, 1, 0},
     {"bool_k1_s16", 1, 1, 16, (const void*)k_eval_bool<1, 16>, 0},
     {"bool_k2_s16", 1, 2, 16, (const void*)k_eval_bool<2, 16>, 0},
     {"bool_k1_s10", 1, 1, 10, (const void*)k_eval_bool<1, 10>, 0},
+    {"boolt_k1_s10", 1, 1, 10, (const void*)k_eval_bool_tbl<1, 10>, 0, 1, kBoolRegInputs},
+    {"boolt_k2_s10", 1, 2, 10, (const void*)k_eval_bool_tbl<2, 10>, 0, 1, kBoolRegInputs},
 };
 
 int variant_count() { return (int)(sizeof(g_variants) / sizeof(g_variants[0])); }
@@ -723,7 +780,7 @@ Variant* variant_table() { return g_variants; }
 hipError_t launch_eval(int variant, const EvalParams& p, int grid, hipStream_t s)
 {
     const Variant& v = g_variants[variant];
-    size_t shm = v.vtype == 1 ? (size_t)p.n_inputs * kWave * v.K * sizeof(uint64_t) : 0;
+    const size_t shm = variant_lds(v, p.n_inputs);
     hipLaunchKernelGGL((void (*)(EvalParams))v.kernel, dim3(grid), dim3(kWave), shm, s, p);
     return hipGetLastError();
 }

@@ -119,7 +119,10 @@ static int ilog2_ceil(int64_t v)
 int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
 {
     Variant* vt = variant_table();
-    auto ok = [&](int v) { return v >= 0 && v < variant_count() && vt[v].vtype == vtype && vt[v].S >= p->max_stack; };
+    auto ok = [&](int v) {
+        return v >= 0 && v < variant_count() &&
+               variant_fits(vt[v], vtype, p->max_stack, p->n_inputs, cs->stride, vtype == GP_BOOL ? 8 : 4);
+    };
     if (ok(c->forced_variant)) return c->forced_variant;
     TuneKey key{vtype, ilog2_ceil(cs->T), ilog2_ceil(std::max<int64_t>(1, p->total_nodes / std::max<int64_t>(1, p->n_trees)))};
     auto it = c->tuned.find(key);
@@ -127,9 +130,9 @@ int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
     int wantK = 1;
     if (vtype == GP_F32) wantK = cs->n_elems <= 64 ? 1 : cs->n_elems <= 128 ? 2 : 4;
     else wantK = cs->n_elems <= 64 ? 1 : 2;
-    // prefer the table-dispatch interpreter (name "f32t_...") when the stack fits
+    // prefer a table-dispatch interpreter when one fits
     for (int v = 0; v < variant_count(); ++v)
-        if (ok(v) && vt[v].K == wantK && vt[v].name[3] == 't') return v;
+        if (ok(v) && vt[v].K == wantK && vt[v].table) return v;
     for (int v = 0; v < variant_count(); ++v)
         if (ok(v) && vt[v].K == wantK) return v;
     for (int v = 0; v < variant_count(); ++v)
@@ -994,7 +997,7 @@ int gp_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, gp_ctx** 
     Variant* vt = variant_table();
     for (int v = 0; v < variant_count(); ++v) {
         int nb = 0;
-        size_t shm = vt[v].vtype == GP_BOOL ? (size_t)8 * kWave * vt[v].K * sizeof(uint64_t) : 0;
+        const size_t shm = variant_lds(vt[v], 8);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, vt[v].kernel, kWave, shm) != hipSuccess) {
             (void)hipGetLastError();
             nb = 4;
@@ -1800,7 +1803,8 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         }
         for (int v = 0; v < variant_count(); ++v) {
             const Variant& vt = variant_table()[v];
-            if (vt.vtype != qp->vtype || vt.S < qp->max_stack) continue;
+            if (!variant_fits(vt, qp->vtype, qp->max_stack, qp->n_inputs, cs->stride, qp->vtype == GP_BOOL ? 8 : 4))
+                continue;
             float t = 0.f;
             RC(time_variant(qp, v, &t));
             if (t < best_t) {

@@ -116,11 +116,14 @@ namespace {
 int choose_for(Server* S, int vtype, const CaseSet* cs, const Pop* p)
 {
     Variant* vt = variant_table();
-    auto ok = [&](int v) { return v >= 0 && v < variant_count() && vt[v].vtype == vtype && vt[v].S >= p->max_stack; };
+    auto ok = [&](int v) {
+        return v >= 0 && v < variant_count() &&
+               variant_fits(vt[v], vtype, p->max_stack, p->n_inputs, cs->stride, vtype == GP_BOOL ? 8 : 4);
+    };
     if (ok(S->forced_variant)) return S->forced_variant;
     int wantK = vtype == GP_F32 ? (cs->n_elems <= 64 ? 1 : cs->n_elems <= 128 ? 2 : 4) : (cs->n_elems <= 64 ? 1 : 2);
     for (int v = 0; v < variant_count(); ++v)
-        if (ok(v) && vt[v].K == wantK && vt[v].name[3] == 't') return v;
+        if (ok(v) && vt[v].K == wantK && vt[v].table) return v;
     for (int v = 0; v < variant_count(); ++v)
         if (ok(v) && vt[v].K == wantK) return v;
     for (int v = 0; v < variant_count(); ++v)

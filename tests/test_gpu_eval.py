@@ -386,6 +386,53 @@ def test_boolean_multiword(ctx, k):
         check_bool_pop(ctx, pop, cases, chunk_nodes=64, variant=v)
 
 
+@pytest.mark.parametrize("k,C", [(6, 32), (6, 300), (8, 64), (12, 128), (16, 64)])
+def test_boolean_table_variants(ctx, k, C):
+    """The table-dispatch Boolean loops, which hold up to 16 input rows in
+    registers, against the oracle; the forced variant must be the one that ran."""
+    cases = gen.bool_cases(k)
+    pop = gen.sized_population(40 + k, 24, 11, 5001, n_terms=k, vtype=gen.VT_BOOL)
+    trees = [pop.tree(i) for i in range(pop.n_trees)] + [np.array([k - 1], np.uint8)]
+    pop = gen.pack(trees, gen.VT_BOOL, k)
+    names = g.variant_names()
+    ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+    ph = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=k, chunk_nodes=C)
+    assert ctx.population_info(ph)["max_stack"] <= 10
+    want_roots, want_fit = oracle.eval_population_bool(pop, cases.inputs, cases.target, cases.T, threads=8)
+    table = [v for v, n in enumerate(names) if n.startswith("boolt")]
+    assert table
+    for v in table:
+        say("bool table", names[v], k, C)
+        ctx.set_variant(v)
+        roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, cases.T)
+        ctx.set_variant(-1)
+        assert st["variant"] == v
+        assert np.array_equal(roots, want_roots)
+        assert np.array_equal(fit, want_fit)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
+def test_boolean_table_variants_refuse_many_inputs(ctx):
+    """With more input rows than the registers hold, a forced table variant is
+    passed over for one that stages the inputs in LDS."""
+    k = 17
+    cases = gen.bool_cases(k)
+    pop = gen.sized_population(57, 6, 11, 2001, n_terms=k, vtype=gen.VT_BOOL)
+    names = g.variant_names()
+    ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+    ph = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=k, chunk_nodes=64)
+    ctx.set_variant(names.index("boolt_k2_s10"))
+    roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, cases.T)
+    ctx.set_variant(-1)
+    assert not names[st["variant"]].startswith("boolt")
+    want_roots, want_fit = oracle.eval_population_bool(pop, cases.inputs, cases.target, cases.T, threads=8)
+    assert np.array_equal(roots, want_roots)
+    assert np.array_equal(fit, want_fit)
+    ctx.free(ph)
+    ctx.free(ch)
+
+
 # -------------------------------------------------------------- incremental
 def make_children(parents, seed, n, donor_hi=200, neutral_frac=0.5, n_terms=1):
     return gen.crossover_children(seed, parents, n, donor_hi=donor_hi, neutral_frac=neutral_frac,
