@@ -86,6 +86,14 @@ import os
 import sys
 
 VARIANTS = [(4, 10), (8, 10)]
+# A chunk's output vector is the one value that waves hand to each other
+# inside a launch (the wave that finishes a chunk's last input reads it with
+# LOAD).  It is written and read with agent-scope coherence (sc1, the form of
+# a relaxed device-scope atomic store and load), and the chunk's end waits for
+# its stores to complete before the kernel decrements the parent's counter.
+# The counter update can then be relaxed: no L2 write-back before it and no
+# L2 invalidation after it, so code, inputs and chunk headers stay cached.
+SHARED = " sc1"
 V_ST = 16
 S_BASE = 64
 M_XX, M_XS, M_SX, M_SS, M_RS, M_PUSH, M_LOAD, M_STORE = range(8)
@@ -386,7 +394,7 @@ def gen_one(K: int, S: int) -> str:
             a(f"  s_add_u32 {sr('A0')}, {sr('A0')}, %[vb_lo]")
             a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, %[vb_hi]")
             for k in range(K):
-                a(f"  global_load_dword {st(d, k)}, %[voff], {sp('A0')} offset:{256 * k}")
+                a(f"  global_load_dword {st(d, k)}, %[voff], {sp('A0')} offset:{256 * k}{SHARED}")
             a("  s_waitcnt vmcnt(0)")
         elif mode == M_STORE:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
@@ -401,7 +409,7 @@ def gen_one(K: int, S: int) -> str:
     a(f"{lab('end')}:")
     a("  s_waitcnt lgkmcnt(0)")
     for k in range(K):
-        a(f"  global_store_dword %[voff], {st(0, k)}, %[outb] offset:{256 * k}")
+        a(f"  global_store_dword %[voff], {st(0, k)}, %[outb] offset:{256 * k}{SHARED}")
     a("  s_waitcnt vmcnt(0)")
 
     body = "\n".join(f'        "{line}\\n"' for line in L)
@@ -557,7 +565,7 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
             a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, %[vb_hi]")
             for k in range(K):
                 a(f"  global_load_dwordx2 v[{V_ST + (d * K + k) * 2}:{V_ST + (d * K + k) * 2 + 1}], %[voff], "
-                  f"{sp('A0')} offset:{512 * k}")
+                  f"{sp('A0')} offset:{512 * k}{SHARED}")
             a("  s_waitcnt vmcnt(0)")
         elif mode == M_STORE:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
@@ -573,7 +581,7 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
     a(f"{lab('end')}:")
     a("  s_waitcnt lgkmcnt(0)")
     for k in range(K):
-        a(f"  global_store_dwordx2 %[voff], v[{V_ST + k * 2}:{V_ST + k * 2 + 1}], %[outb] offset:{512 * k}")
+        a(f"  global_store_dwordx2 %[voff], v[{V_ST + k * 2}:{V_ST + k * 2 + 1}], %[outb] offset:{512 * k}{SHARED}")
     a("  s_waitcnt vmcnt(0)")
 
     body = "\n".join(f'        "{line}\\n"' for line in L)

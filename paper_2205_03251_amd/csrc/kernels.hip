@@ -296,10 +296,14 @@ __global__ __launch_bounds__(64) void k_eval_f32_tbl(EvalParams p)
             run_f32_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
                                    outb, voff);
             if (ch.parent < 0) break;
+            // The loop wrote the chunk's vector with agent-coherent stores and
+            // waited for them to complete, and LOAD reads vectors with
+            // agent-coherent loads, so the hand-off needs no cache write-back
+            // or invalidation: a relaxed decrement orders it.
             int old = 0;
             if (lane == 0)
                 old = __hip_atomic_fetch_add(p.pending + (int64_t)ch.parent * p.n_slices + s, -1,
-                                             __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             old = __builtin_amdgcn_readfirstlane(old);
             if (old != 1) break;
             c = ch.parent;
@@ -481,10 +485,10 @@ __global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
             run_bool_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
                                     outb, voff, nin);
             if (ch.parent < 0) break;
-            int old = 0;
+            int old = 0;      // relaxed, as in k_eval_f32_tbl
             if (lane == 0)
                 old = __hip_atomic_fetch_add(p.pending + (int64_t)ch.parent * p.n_slices + s, -1,
-                                             __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             old = __builtin_amdgcn_readfirstlane(old);
             if (old != 1) break;
             c = ch.parent;
