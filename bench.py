@@ -354,13 +354,13 @@ def main():
         h = hashlib.sha256()
         for f in rec["kernel_source_files"]:
             h.update(open(os.path.join(ROOT, f), "rb").read())
-        same = (h.hexdigest() == rec["kernel_source_sha256"] and
-                rec["workload"] == desc["workload"] and rec["chunk_nodes"] == final_info["chunk_nodes"] and
-                rec["variant"] == used.get("variant", tuned))
-        if same:
-            roofline["traffic"] = int(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
-            roofline["valu_lane_op_frac_counters"] = rec["valu_lane_op_frac"]
-            counted = rec
+        if h.hexdigest() == rec["kernel_source_sha256"] and rec["workload"] == desc["workload"]:
+            # one record per (chunk size, variant) the autotuner has been seen to pick
+            for r in rec["records"]:
+                if r["chunk_nodes"] == final_info["chunk_nodes"] and r["variant"] == used.get("variant", tuned):
+                    roofline["traffic"] = int(r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"])
+                    roofline["valu_lane_op_frac_counters"] = r["valu_lane_op_frac"]
+                    counted = rec
     except (OSError, KeyError, ValueError):
         pass
 
