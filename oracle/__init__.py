@@ -50,6 +50,8 @@ def lib():
         h.orc_validate.argtypes = [u8p, L, C.c_int]
         h.orc_subtree_end.argtypes = [u8p, L, L]
         h.orc_subtree_end.restype = L
+        h.orc_all_ends.argtypes = [u8p, L, i64p]
+        h.orc_parents.argtypes = [u8p, L, i64p]
         h.orc_eval_f32.argtypes = [u8p, L, C.c_int, f32p, L, f32p]
         h.orc_eval_f32_nodes.argtypes = [u8p, L, C.c_int, f32p, L, f32p]
         h.orc_fitness_f32.argtypes = [f32p, f32p, L]
@@ -90,6 +92,24 @@ def validate(tree, n_inputs: int = 1) -> bool:
 def subtree_end(tree, i: int) -> int:
     t = _u8(tree)
     return int(lib().orc_subtree_end(t, len(t), i))
+
+
+def all_ends(tree) -> np.ndarray:
+    """Subtree end (exclusive) of every node of a valid prefix tree."""
+    t = _u8(tree)
+    out = np.zeros(len(t), np.int64)
+    if lib().orc_all_ends(t, len(t), out) != 0:
+        raise ValueError("empty tree")
+    return out
+
+
+def parents(tree) -> np.ndarray:
+    """Parent of every node of a valid prefix tree, -1 at the root."""
+    t = _u8(tree)
+    out = np.zeros(len(t), np.int64)
+    if lib().orc_parents(t, len(t), out) != 0:
+        raise ValueError("empty tree")
+    return out
 
 
 def eval_f32(tree, x) -> np.ndarray:

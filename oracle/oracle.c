@@ -107,6 +107,42 @@ static int all_ends(const uint8_t* ops, int64_t n, int64_t* end)
     return ORC_OK;
 }
 
+/* Section 3.1: the subtree end of every node (the same right-to-left pass). */
+int orc_all_ends(const uint8_t* ops, int64_t n, int64_t* end)
+{
+    if (n < 1) return ORC_EINVAL;
+    return all_ends(ops, n, end);
+}
+
+/* Section 3.1: the parent of every node, -1 at the root.  Reading the prefix
+ * form left to right, a function opens two child positions; each node takes
+ * the next open position of the most recently read function that still has
+ * one, so a stack of functions with positions left is enough. */
+int orc_parents(const uint8_t* ops, int64_t n, int64_t* parent)
+{
+    if (n < 1) return ORC_EINVAL;
+    int64_t* st = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int* left = (int*)malloc(sizeof(int) * (size_t)n);
+    if (!st || !left) {
+        free(st);
+        free(left);
+        return ORC_ENOMEM;
+    }
+    int64_t sp = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        parent[j] = sp > 0 ? st[sp - 1] : -1;
+        if (sp > 0 && --left[sp - 1] == 0) --sp;
+        if (is_func(ops[j])) {
+            st[sp] = j;
+            left[sp] = 2;
+            ++sp;
+        }
+    }
+    free(st);
+    free(left);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------- float32 semantics */
 
 static float op_f32(int f, float a, float b)

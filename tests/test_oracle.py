@@ -50,6 +50,48 @@ def test_subtree_end():
     assert oracle.subtree_end(tree, 6) == 7
 
 
+def test_all_ends_and_parents_hand_worked():
+    tree = t(A, S, X, X, M, X, X)
+    assert oracle.all_ends(tree).tolist() == [7, 4, 3, 4, 7, 6, 7]
+    assert oracle.parents(tree).tolist() == [-1, 0, 1, 1, 0, 4, 4]
+    assert oracle.all_ends(t(X)).tolist() == [1]
+    assert oracle.parents(t(X)).tolist() == [-1]
+
+
+def test_all_ends_and_parents_combs():
+    """Closed forms: a left comb F..F x..x of d functions has node k (< d) as the
+    left child of k - 1 and the right child of function k - 1 at 2d - k; a right
+    comb (F x)^d x has node 2k + 1 and 2k + 2 as the children of function 2k."""
+    for d in [1, 2, 5, 40]:
+        left = t(*([A] * d + [X] * (d + 1)))
+        ends, par = oracle.all_ends(left), oracle.parents(left)
+        for k in range(d):
+            assert ends[k] == 2 * d + 1 - k
+            assert par[k] == k - 1
+            assert par[2 * d - k] == k
+        assert par[d] == d - 1
+        right = t(*([A, X] * d + [X]))
+        ends, par = oracle.all_ends(right), oracle.parents(right)
+        for k in range(d):
+            assert ends[2 * k] == 2 * d + 1
+            assert par[2 * k + 1] == 2 * k and par[2 * k + 2] == 2 * k
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_all_ends_and_parents_brute_force(seed):
+    """Against the forward-scanning subtree end, node by node, and the parent as
+    the nearest earlier node whose subtree holds the node."""
+    rng = np.random.default_rng(900 + seed)
+    for n in [1, 3, 9, 31, 101, 255]:
+        tree = gen.sized_tree(rng, n, n_terms=3)
+        ends, par = oracle.all_ends(tree), oracle.parents(tree)
+        for i in range(n):
+            assert ends[i] == oracle.subtree_end(tree, i)
+        for j in range(n):
+            enclosing = [p for p in range(j) if oracle.subtree_end(tree, p) > j]
+            assert par[j] == (max(enclosing) if enclosing else -1)
+
+
 # -------------------------------------------------------- float semantics (C2)
 def test_hand_worked_float():
     x = SPECIAL[None, :]

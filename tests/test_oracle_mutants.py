@@ -48,6 +48,9 @@ MUTANTS = {
     "tournament ties keep the later draw": ("if (!isnan(a) && (isnan(b) || a < b)) best = c;",
                                             "if (!isnan(a) && (isnan(b) || a <= b)) best = c;"),
     "Boolean tournament prefers fewer hits": ("if (fit[c] > fit[best]) best = c;", "if (fit[c] < fit[best]) best = c;"),
+    "parent is the function that opened the earliest slot": ("parent[j] = sp > 0 ? st[sp - 1] : -1;",
+                                                              "parent[j] = sp > 0 ? st[0] : -1;"),
+    "a function takes three children": ("left[sp] = 2;", "left[sp] = 3;"),
 }
 
 
