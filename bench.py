@@ -414,6 +414,26 @@ def main():
             extra["splice"]["traffic"] = int(counted["splice"]["fetch_bytes_per_launch"] +
                                              counted["splice"]["write_bytes_per_launch"])
 
+    # the first steps of loading, on the device: validity, subtree ends and parents of every node
+    if total_nodes <= 2**31 - 2:
+        dops = torch.from_numpy(pop.ops).to("cuda:0")
+        doffs = torch.from_numpy(pop.offsets).to("cuda:0")
+        ims = []
+        for _ in range(3):
+            valid, iend, ipar, ims_one = ctx.index_trees(dops, doffs, pop.n_inputs)
+            ims.append(ims_one)
+        all_valid = bool((valid == 1).all())
+        del dops, doffs, valid, iend, ipar
+        ix_ms = float(np.median(ims[1:]))
+        ix_bytes = 9 * total_nodes          # each node's byte read, its end and parent (int32) written
+        ix_gbps = ix_bytes / (ix_ms * 1e-3) / 1e9
+        extra["tree_index"] = {"trees": n_trees, "nodes": total_nodes, "device_ms": round(ix_ms, 3),
+                               "nodes_per_s": round(total_nodes / (ix_ms * 1e-3), 1), "bound": "hbm",
+                               "achieved": round(ix_gbps, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                               "frac": round(ix_gbps / PEAK_HBM_GBPS, 4), "algorithmic_bytes": ix_bytes,
+                               "all_valid": all_valid, "host_load_s": round(load_s, 2),
+                               "note": "host_load_s: validation, compilation and upload of the same trees on the host"}
+
     if args.compare:
         _, _, st_pt = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, per_tree=True)
         extra["per_tree_launch_ms"] = st_pt["device_ms"]

@@ -154,6 +154,23 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
 
 int gp_population_info(gp_ctx* ctx, gp_handle pop, gp_pop_info* out);
 
+/* Index a population of prefix trees on the device (the flattened form of
+ * Section 3.1): tree t is ops[offsets[t] .. offsets[t+1]).  Every argument
+ * array is device memory owned by the caller; ops must be 16-byte aligned.
+ * Outputs: valid[t] = 1 when tree t passes the same check as
+ * gp_validate_tree (every byte a function 0x80..0x83 or a terminal below
+ * n_inputs; the count of open child positions stays positive until the last
+ * node and closes there), else 0.  For each node k of a valid tree,
+ * end[k] = the end (exclusive) of k's subtree and parent[k] = k's parent,
+ * both as indices within the tree, parent -1 at the root; every node of an
+ * invalid tree gets -1 in both.  1 <= n_trees <= n_nodes <= 2^31 - 2, where
+ * n_nodes = offsets[n_trees].  Runs on the context stream and returns when
+ * done; device_ms (may be NULL) receives its HIP-event time.  GP_EINVAL when
+ * offsets do not run from 0 to n_nodes without decreasing (outputs then
+ * undefined), or on bad sizes or pointers. */
+int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, double* device_ms);
+
 /* Release a population or case set (and any cache or graph tied to it). */
 int gp_free(gp_ctx* ctx, gp_handle h);
 

@@ -163,6 +163,31 @@ hipError_t launch_eval(int variant, const EvalParams& p, int grid, hipStream_t s
 hipError_t launch_fitness(int vtype, const FitParams& p, int64_t n, hipStream_t s);
 hipError_t launch_walk(int vtype, const WalkParams& p, int64_t n_children, hipStream_t s);
 hipError_t launch_splice(const SpliceItem* items, int64_t n_items, uint8_t* out, hipStream_t s);
+
+// Device-side tree index (index.hip).  E(k), the sum of node steps before
+// position k, is held as el[k] + boff[k / kIxBlock].
+constexpr int kIxBlock = 4096;          // positions per scan block
+constexpr int kIxMaxLevels = 40;        // min-tree levels (2^39 positions)
+
+struct IxParams {
+    const uint8_t* ops;                 // 16-byte aligned
+    const int64_t* offsets;             // [n_trees + 1]
+    int64_t n_trees;
+    int64_t n;                          // positions in all
+    int n_inputs;
+    int top;                            // highest min-tree level (its length is 1)
+    int32_t* el;                        // [n_blocks * kIxBlock + 1]
+    int32_t* boff;                      // [n_blocks + 1]
+    int32_t* seg;                       // min-tree levels 1..top
+    const int64_t* lvl;                 // [2 * kIxMaxLevels]: offset in seg, length; level 0 = E, length n + 1
+    int32_t* valid;                     // [n_trees]
+    int32_t* end;                       // [n], tree-local
+    int32_t* parent;                    // [n], tree-local, -1 at a root
+    int32_t* bad_offsets;               // set to 1 when offsets are not 0..n, non-decreasing
+};
+
+hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t n_blocks, const int64_t* host_len,
+                        hipStream_t s);
 hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipStream_t s);
 // One generation's random choices (Section 6.3): per slot i, the winners of
 // tournaments (i, g, 0) and (i, g, 1) over fit, the crossover point in the

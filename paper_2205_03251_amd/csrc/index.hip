@@ -1,0 +1,264 @@
+// Device-side index of a population of prefix trees: the first steps of
+// loading (Section 3.1 flattens each tree into one byte per node in prefix
+// order).  For every tree it decides validity, and for every node of a valid
+// tree it finds the end of the node's subtree and the node's parent.
+//
+// A node's step is +1 for a function (binary: it opens two child positions
+// and fills one) and -1 for anything else.  E(k) is the sum of the steps of
+// the positions before k, over the whole population.  The tree on [s, e) is
+// valid iff each byte is a known function or a terminal below n_inputs,
+// E(k) >= E(s) for s < k < e, and E(e) = E(s) - 1 (the count of open child
+// positions never runs out early and ends exhausted).  The subtree of node k
+// ends (exclusively) at the first j > k with E(j) < E(k): k + 1 for a
+// terminal; for a function a search over a min-tree of E (level 0 is E,
+// level l holds the minimum of each pair of level l - 1).  The children of a
+// function k are k + 1 and end(k + 1), so the parent index follows from the
+// ends with one write per node.
+#include <algorithm>
+
+#include "dev.h"
+
+namespace gpe {
+
+__device__ __forceinline__ int32_t ix_e(const IxParams& q, int64_t k)
+{
+    return q.el[k] + q.boff[k / kIxBlock];
+}
+
+__device__ __forceinline__ int32_t ix_m(const IxParams& q, int l, int64_t p)
+{
+    return l == 0 ? ix_e(q, p) : q.seg[q.lvl[2 * l] + p];
+}
+
+__device__ __forceinline__ bool ix_bad_byte(uint8_t b, int n_inputs)
+{
+    return (b & 0x80) ? (b & 0x7f) > 3 : (int)b >= n_inputs;
+}
+
+// Last tree t with offsets[t] <= k (offsets non-decreasing; any t in range
+// otherwise).
+__device__ __forceinline__ int64_t ix_tree_of(const IxParams& q, int64_t k)
+{
+    int64_t lo = 0, hi = q.n_trees;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (q.offsets[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// First position j >= s with E(j) < v, or -1.  Climbing keeps every position
+// from s up to the start of node p at level l checked; a left child's parent
+// covers only unchecked positions, so the search moves up while p is even.
+__device__ int64_t ix_first_below(const IxParams& q, int64_t s, int32_t v)
+{
+    int64_t p = s;
+    int l = 0;
+    for (;;) {
+        while (l < q.top && (p & 1) == 0) {
+            p >>= 1;
+            ++l;
+        }
+        if (p >= q.lvl[2 * l + 1]) return -1;
+        if (ix_m(q, l, p) < v) break;
+        ++p;
+    }
+    while (l > 0) {                 // the first child holding a value below v
+        --l;
+        p <<= 1;
+        if (ix_m(q, l, p) >= v && p + 1 < q.lvl[2 * l + 1]) ++p;
+    }
+    return p;
+}
+
+// Steps of one 4096-position block: el = exclusive prefix within the block,
+// bsum = the block's total.  Positions past n step by 0.
+__global__ __launch_bounds__(256) void k_ix_scan(IxParams q, int32_t* bsum)
+{
+    __shared__ int32_t wtot[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kIxBlock + (int64_t)tid * 16;
+    uint32_t word[4] = {0, 0, 0, 0};
+    if (base + 16 <= q.n) {
+        const uint4 v = *(const uint4*)(q.ops + base);
+        word[0] = v.x;
+        word[1] = v.y;
+        word[2] = v.z;
+        word[3] = v.w;
+    } else {
+        for (int j = 0; j < 16; ++j)
+            if (base + j < q.n) word[j >> 2] |= (uint32_t)q.ops[base + j] << (8 * (j & 3));
+    }
+    int32_t pre[16];
+    int32_t run = 0;
+    for (int j = 0; j < 16; ++j) {
+        pre[j] = run;
+        const uint32_t b = (word[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        run += base + j < q.n ? ((b & 0x80u) ? 1 : -1) : 0;
+    }
+    int32_t incl = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int32_t wbase = 0;
+    for (int i = 0; i < w; ++i) wbase += wtot[i];
+    const int32_t excl = wbase + incl - run;
+    int4* dst = (int4*)(q.el + base);
+    for (int j = 0; j < 4; ++j)
+        dst[j] = make_int4(excl + pre[4 * j], excl + pre[4 * j + 1], excl + pre[4 * j + 2], excl + pre[4 * j + 3]);
+    if (tid == 255) bsum[blockIdx.x] = excl + run;
+}
+
+// Exclusive prefix of the block totals (one workgroup); boff[nb] = E(n), and
+// el[nb * kIxBlock] = 0 so that E(n) = el[n] + boff[n / kIxBlock] also when n
+// is a multiple of the block.
+__global__ __launch_bounds__(1024) void k_ix_top(IxParams q, const int32_t* bsum, int64_t nb)
+{
+    __shared__ int32_t wtot[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t a = (int64_t)tid * per, z = a + per < nb ? a + per : nb;
+    int32_t sum = 0;
+    for (int64_t i = a; i < z; ++i) sum += bsum[i];
+    int32_t incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int32_t wbase = 0;
+    for (int i = 0; i < w; ++i) wbase += wtot[i];
+    int32_t r = wbase + incl - sum;
+    for (int64_t i = a; i < z; ++i) {
+        q.boff[i] = r;
+        r += bsum[i];
+    }
+    if (tid == 1023) {
+        q.boff[nb] = r;
+        q.el[nb * kIxBlock] = 0;
+    }
+}
+
+// Level l >= 1 of the min-tree from level l - 1.
+__global__ __launch_bounds__(256) void k_ix_level(IxParams q, int l)
+{
+    const int64_t len = q.lvl[2 * l + 1], src_len = q.lvl[2 * (l - 1) + 1];
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < len; p += (int64_t)gridDim.x * 256) {
+        int32_t m = ix_m(q, l - 1, 2 * p);
+        if (2 * p + 1 < src_len) m = min(m, ix_m(q, l - 1, 2 * p + 1));
+        q.seg[q.lvl[2 * l] + p] = m;
+    }
+}
+
+// valid[t] = 1 for a tree whose offsets are in order and inside [0, n];
+// flags offsets that do not run from 0 to n without decreasing.
+__global__ __launch_bounds__(256) void k_ix_init(IxParams q)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < q.n_trees; t += (int64_t)gridDim.x * 256) {
+        const int64_t s = q.offsets[t], e = q.offsets[t + 1];
+        const bool inside = 0 <= s && s < e && e <= q.n;
+        q.valid[t] = inside ? 1 : 0;
+        if (e < s || (t == 0 && s != 0) || (t == q.n_trees - 1 && e != q.n)) *q.bad_offsets = 1;
+    }
+}
+
+// The positions of one thread: 16 consecutive ones, walking the trees they
+// fall in.  body(k, t, s, e) runs for each position k inside a well-formed
+// tree t = [s, e); other(k) for the rest.
+template <class Body, class Other>
+__device__ __forceinline__ void ix_positions(const IxParams& q, Body body, Other other)
+{
+    const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (k0 >= q.n) return;
+    int64_t t = ix_tree_of(q, k0);
+    int64_t s = q.offsets[t], e = q.offsets[t + 1];
+    for (int j = 0; j < 16; ++j) {
+        const int64_t k = k0 + j;
+        if (k >= q.n) break;
+        while (k >= e && t + 1 < q.n_trees) {
+            ++t;
+            s = q.offsets[t];
+            e = q.offsets[t + 1];
+        }
+        if (0 <= s && s <= k && k < e && e <= q.n) body(k, t, s, e);
+        else other(k);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ix_check(IxParams q)
+{
+    ix_positions(
+        q,
+        [&](int64_t k, int64_t t, int64_t s, int64_t e) {
+            const int32_t es = ix_e(q, s);
+            bool bad = ix_bad_byte(q.ops[k], q.n_inputs);
+            if (k > s && ix_e(q, k) < es) bad = true;
+            if (k == e - 1 && ix_e(q, e) != es - 1) bad = true;
+            if (bad) q.valid[t] = 0;
+        },
+        [&](int64_t) {});
+}
+
+__global__ __launch_bounds__(256) void k_ix_ends(IxParams q)
+{
+    ix_positions(
+        q,
+        [&](int64_t k, int64_t t, int64_t s, int64_t e) {
+            int32_t r = -1;
+            if (q.valid[t]) {
+                if (!(q.ops[k] & 0x80)) {
+                    r = (int32_t)(k + 1 - s);
+                } else {
+                    const int64_t j = ix_first_below(q, k + 1, ix_e(q, k));
+                    if (j > k && j <= e) r = (int32_t)(j - s);
+                }
+            }
+            q.end[k] = r;
+        },
+        [&](int64_t k) { q.end[k] = -1; });
+}
+
+__global__ __launch_bounds__(256) void k_ix_parents(IxParams q)
+{
+    ix_positions(
+        q,
+        [&](int64_t k, int64_t t, int64_t s, int64_t e) {
+            if (!q.valid[t]) {
+                q.parent[k] = -1;
+                return;
+            }
+            if (k == s) q.parent[k] = -1;
+            if ((q.ops[k] & 0x80) && k + 1 < e) {
+                const int32_t me = (int32_t)(k - s);
+                q.parent[k + 1] = me;
+                const int64_t r = s + q.end[k + 1];     // the right child
+                if (r > k + 1 && r < e) q.parent[r] = me;
+            }
+        },
+        [&](int64_t k) { q.parent[k] = -1; });
+}
+
+hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t nb, const int64_t* host_len, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ix_scan, dim3((unsigned)nb), dim3(256), 0, s, q, bsum);
+    hipLaunchKernelGGL(k_ix_top, dim3(1), dim3(1024), 0, s, q, (const int32_t*)bsum, nb);
+    for (int l = 1; l <= q.top; ++l) {
+        const int64_t len = host_len[l];
+        const int64_t grid = std::min<int64_t>(65536, std::max<int64_t>(1, (len + 255) / 256));
+        hipLaunchKernelGGL(k_ix_level, dim3((unsigned)grid), dim3(256), 0, s, q, l);
+    }
+    const int64_t tg = std::min<int64_t>(65536, std::max<int64_t>(1, (q.n_trees + 255) / 256));
+    hipLaunchKernelGGL(k_ix_init, dim3((unsigned)tg), dim3(256), 0, s, q);
+    const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
+    hipLaunchKernelGGL(k_ix_check, dim3((unsigned)pg), dim3(256), 0, s, q);
+    hipLaunchKernelGGL(k_ix_ends, dim3((unsigned)pg), dim3(256), 0, s, q);
+    hipLaunchKernelGGL(k_ix_parents, dim3((unsigned)pg), dim3(256), 0, s, q);
+    return hipGetLastError();
+}
+
+}  // namespace gpe

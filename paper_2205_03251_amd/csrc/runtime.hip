@@ -1844,6 +1844,69 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     return GP_OK;
 }
 
+int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, double* device_ms)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(ctx, GP_EINVAL, "n_inputs must be 1..64");
+    if (n_trees < 1 || n_nodes < 1) return set_err(ctx, GP_EINVAL, "empty population");
+    if (n_nodes > (int64_t)INT32_MAX - 1) return set_err(ctx, GP_EINVAL, "at most 2^31 - 2 nodes per call");
+    if (n_trees > n_nodes) return set_err(ctx, GP_EINVAL, "more trees than nodes");
+    if (!ops || !offsets || !valid || !end || !parent) return set_err(ctx, GP_EINVAL, "missing device array");
+    if (((uintptr_t)ops & 15) != 0) return set_err(ctx, GP_EINVAL, "ops must be 16-byte aligned");
+    const int64_t nb = (n_nodes + kIxBlock - 1) / kIxBlock;
+    // min-tree levels: level 0 is E itself (n + 1 positions), each next one half as long, up to length 1
+    std::vector<int64_t> lvl(2 * kIxMaxLevels, 0), len(kIxMaxLevels, 0);
+    len[0] = n_nodes + 1;
+    lvl[1] = len[0];
+    int top = 0;
+    int64_t seg_total = 0;
+    while (len[top] > 1) {
+        ++top;
+        len[top] = (len[top - 1] + 1) / 2;
+        lvl[2 * top] = seg_total;
+        lvl[2 * top + 1] = len[top];
+        seg_total += len[top];
+    }
+    DevBuf el, boff, bsum, seg, lv, flag;
+    RC(dev_alloc(ctx, el, (size_t)(nb * kIxBlock + 1) * 4));
+    RC(dev_alloc(ctx, boff, (size_t)(nb + 1) * 4));
+    RC(dev_alloc(ctx, bsum, (size_t)nb * 4));
+    RC(dev_alloc(ctx, seg, (size_t)std::max<int64_t>(1, seg_total) * 4));
+    RC(dev_alloc(ctx, lv, lvl.size() * 8));
+    RC(dev_alloc(ctx, flag, 4));
+    HIPC(ctx, hipMemcpyAsync(lv.p, lvl.data(), lvl.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPC(ctx, hipMemsetAsync(flag.p, 0, 4, ctx->stream));
+    IxParams q;
+    q.ops = ops;
+    q.offsets = offsets;
+    q.n_trees = n_trees;
+    q.n = n_nodes;
+    q.n_inputs = n_inputs;
+    q.top = top;
+    q.el = el.as<int32_t>();
+    q.boff = boff.as<int32_t>();
+    q.seg = seg.as<int32_t>();
+    q.lvl = lv.as<int64_t>();
+    q.valid = valid;
+    q.end = end;
+    q.parent = parent;
+    q.bad_offsets = flag.as<int32_t>();
+    HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    HIPC(ctx, launch_index(q, bsum.as<int32_t>(), nb, len.data(), ctx->stream));
+    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    int32_t bad = 0;
+    HIPC(ctx, hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (device_ms) *device_ms = ms;
+    if (bad) return set_err(ctx, GP_EINVAL, "offsets must run from 0 to n_nodes without decreasing");
+    return GP_OK;
+}
+
 int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n)
 {
     if ((vtype != GP_F32 && vtype != GP_BOOL) || n_inputs < 1 || n_inputs > kMaxInputs || !ops) return GP_EINVAL;

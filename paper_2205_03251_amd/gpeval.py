@@ -28,7 +28,7 @@ EXPORTS = [
     "gp_population_info", "gp_free", "gp_evaluate_full", "gp_evaluate_incremental_batch",
     "gp_evaluate_incremental", "gp_fitness", "gp_variant_name", "gp_variant_count", "gp_autotune",
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
-    "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree",
+    "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree", "gp_index_trees",
 ]
 
 
@@ -125,6 +125,7 @@ def lib() -> C.CDLL:
     h.gp_load_population.argtypes = [P, C.c_int, C.c_int, C.c_int, I64, P, P, P, P, I64, C.c_uint32,
                                      C.POINTER(I64)]
     h.gp_population_info.argtypes = [P, I64, C.POINTER(PopInfo)]
+    h.gp_index_trees.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, C.POINTER(C.c_double)]
     h.gp_free.argtypes = [P, I64]
     h.gp_evaluate_full.argtypes = [P, I64, I64, C.c_uint32, P, P, C.POINTER(Stats)]
     h.gp_evaluate_incremental_batch.argtypes = [P, I64, I64, I64, P, P, P, P, C.c_uint32, P, P,
@@ -369,6 +370,22 @@ class Context:
                                              _ptr(donor_offsets), flags, _ptr(ops), cap, _ptr(offs),
                                              C.byref(st)))
         return ops[:total], offs, st.as_dict()
+
+    def index_trees(self, ops, offsets, n_inputs: int, n_nodes=None):
+        """gp_index_trees on device tensors: ops (uint8, 16-byte aligned) and
+        offsets (int64, n_trees + 1).  Returns int32 device tensors valid
+        [n_trees], end [n_nodes] and parent [n_nodes], and the device time."""
+        import torch
+        n_trees = offsets.numel() - 1
+        n = int(ops.numel() if n_nodes is None else n_nodes)
+        dev = f"cuda:{self.device}"
+        valid = torch.empty(max(n_trees, 1), dtype=torch.int32, device=dev)
+        end = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        parent = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        ms = C.c_double(0.0)
+        self._check(lib().gp_index_trees(self._h, n_inputs, n_trees, _ptr(ops), _ptr(offsets), n, _ptr(valid),
+                                         _ptr(end), _ptr(parent), C.byref(ms)))
+        return valid[:n_trees], end[:n], parent[:n], ms.value
 
     def population_info(self, pop) -> dict:
         info = PopInfo()

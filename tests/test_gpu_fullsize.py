@@ -170,3 +170,38 @@ def test_incremental_full_size_sampled(ctx):
     ctx.free(nh)
     ctx.free(ph)
     ctx.free(ch)
+
+
+def test_index_full_size(ctx):
+    """The device index of the default 500-tree population (2.1e9 nodes):
+    every tree valid, the four smallest compared with the oracle node by
+    node, 64 sampled nodes of every tree compared with the oracle's subtree
+    end, and for every sampled node its parent's children include it."""
+    import torch
+    pop = gen.sized_population(4, 500, 10**6, 10**7, threads=16)
+    dev = torch.from_numpy(pop.ops).to("cuda:0")
+    doffs = torch.from_numpy(pop.offsets).to("cuda:0")
+    valid, end, parent, ms = ctx.index_trees(dev, doffs, 1)
+    say("index full size:", int(pop.offsets[-1]), "nodes in", round(ms, 2), "ms")
+    del dev
+    assert bool((valid == 1).all())
+    sizes = pop.sizes()
+    rng = np.random.default_rng(11)
+    for t in range(pop.n_trees):
+        s, e = int(pop.offsets[t]), int(pop.offsets[t + 1])
+        tr = pop.tree(t)
+        ks = rng.integers(0, e - s, 64)
+        idx = torch.from_numpy((s + ks).astype(np.int64)).to(end.device)
+        te = end[idx].cpu().numpy()
+        tp = parent[idx].cpu().numpy()
+        for k, ek, pk in zip(ks.tolist(), te.tolist(), tp.tolist()):
+            assert ek == oracle.subtree_end(tr, k), (t, k)
+            if k == 0:
+                assert pk == -1
+            else:
+                assert tr[pk] & 0x80 and (k == pk + 1 or k == int(end[s + pk + 1]))
+    for t in np.argsort(sizes)[:4].tolist():
+        s, e = int(pop.offsets[t]), int(pop.offsets[t + 1])
+        tr = pop.tree(t)
+        assert np.array_equal(end[s:e].cpu().numpy(), oracle.all_ends(tr))
+        assert np.array_equal(parent[s:e].cpu().numpy(), oracle.parents(tr))
