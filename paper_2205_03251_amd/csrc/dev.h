@@ -167,7 +167,8 @@ hipError_t launch_splice(const SpliceItem* items, int64_t n_items, uint8_t* out,
 // Device-side tree index (index.hip).  E(k), the sum of node steps before
 // position k, is held as el[k] + boff[k / kIxBlock].
 constexpr int kIxBlock = 4096;          // positions per scan block
-constexpr int kIxMaxLevels = 40;        // min-tree levels (2^39 positions)
+constexpr int kIxFan = 16;              // min-tree fan-out
+constexpr int kIxMaxLevels = 16;        // min-tree levels (16^15 positions)
 
 struct IxParams {
     const uint8_t* ops;                 // 16-byte aligned
@@ -175,10 +176,10 @@ struct IxParams {
     int64_t n_trees;
     int64_t n;                          // positions in all
     int n_inputs;
-    int top;                            // highest min-tree level (its length is 1)
-    int32_t* el;                        // [n_blocks * kIxBlock + 1]
+    int top;                            // highest min-tree level (at most kIxFan entries)
+    int32_t* el;                        // [n_blocks * kIxBlock + kIxFan]
     int32_t* boff;                      // [n_blocks + 1]
-    int32_t* seg;                       // min-tree levels 1..top
+    int32_t* seg;                       // min-tree levels 1..top, each padded to whole groups
     const int64_t* lvl;                 // [2 * kIxMaxLevels]: offset in seg, length; level 0 = E, length n + 1
     int32_t* valid;                     // [n_trees]
     int32_t* end;                       // [n], tree-local

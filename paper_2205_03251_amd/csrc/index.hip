@@ -11,7 +11,8 @@
 // positions never runs out early and ends exhausted).  The subtree of node k
 // ends (exclusively) at the first j > k with E(j) < E(k): k + 1 for a
 // terminal; for a function a search over a min-tree of E (level 0 is E,
-// level l holds the minimum of each pair of level l - 1).  The children of a
+// each entry of level l the minimum of a group of kIxFan entries of level
+// l - 1, so a search step reads one 64-byte group).  The children of a
 // function k are k + 1 and end(k + 1), so the parent index follows from the
 // ends with one write per node.
 #include <algorithm>
@@ -20,14 +21,11 @@
 
 namespace gpe {
 
+static_assert(kIxFan == 16, "a group is read as four 16-byte loads");
+
 __device__ __forceinline__ int32_t ix_e(const IxParams& q, int64_t k)
 {
     return q.el[k] + q.boff[k / kIxBlock];
-}
-
-__device__ __forceinline__ int32_t ix_m(const IxParams& q, int l, int64_t p)
-{
-    return l == 0 ? ix_e(q, p) : q.seg[q.lvl[2 * l] + p];
 }
 
 __device__ __forceinline__ bool ix_bad_byte(uint8_t b, int n_inputs)
@@ -48,28 +46,73 @@ __device__ __forceinline__ int64_t ix_tree_of(const IxParams& q, int64_t k)
     return lo;
 }
 
-// First position j >= s with E(j) < v, or -1.  Climbing keeps every position
-// from s up to the start of node p at level l checked; a left child's parent
-// covers only unchecked positions, so the search moves up while p is even.
-__device__ int64_t ix_first_below(const IxParams& q, int64_t s, int32_t v)
+// Group g of min-tree level l (the kIxFan entries from g, g a multiple of
+// kIxFan), read with four 16-byte loads; levels and el are padded to whole
+// groups.  Entries past the level's length hold whatever the padding holds.
+__device__ __forceinline__ void ix_load_group(const IxParams& q, int l, int64_t g, int32_t (&x)[kIxFan])
 {
-    int64_t p = s;
+    int4 w[4];
+    int32_t add = 0;
+    if (l == 0) {
+        const int4* src = (const int4*)(q.el + g);
+        for (int i = 0; i < 4; ++i) w[i] = src[i];
+        add = q.boff[g / kIxBlock];           // a group never straddles a scan block
+    } else {
+        const int4* src = (const int4*)(q.seg + q.lvl[2 * l] + g);
+        for (int i = 0; i < 4; ++i) w[i] = src[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x[4 * i] = w[i].x + add;
+        x[4 * i + 1] = w[i].y + add;
+        x[4 * i + 2] = w[i].z + add;
+        x[4 * i + 3] = w[i].w + add;
+    }
+}
+
+// The first index in [p, end of p's group) of level l whose value is below
+// v, or -1.
+__device__ __forceinline__ int64_t ix_scan_in(const int32_t (&x)[kIxFan], int64_t g, int64_t p, int64_t len,
+                                             int32_t v)
+{
+    int64_t hit = -1;
+#pragma unroll
+    for (int i = kIxFan - 1; i >= 0; --i) {
+        const int64_t idx = g + i;
+        if (idx >= p && idx < len && x[i] < v) hit = idx;
+    }
+    return hit;
+}
+
+__device__ __forceinline__ int64_t ix_scan_group(const IxParams& q, int l, int64_t p, int32_t v)
+{
+    const int64_t g = p & ~(int64_t)(kIxFan - 1);
+    int32_t x[kIxFan];
+    ix_load_group(q, l, g, x);
+    return ix_scan_in(x, g, p, q.lvl[2 * l + 1], v);
+}
+
+// First position j >= s with E(j) < v, or -1.  Going up, every position from
+// s to the end of the current node's parent has been checked when a group
+// scan fails, so the search continues at the parent's next sibling; going
+// down, it takes the first child whose minimum is below v.
+__device__ __forceinline__ int64_t ix_first_below(const IxParams& q, int64_t s, int32_t v)
+{
+    int64_t p = s, hit = -1;
     int l = 0;
     for (;;) {
-        while (l < q.top && (p & 1) == 0) {
-            p >>= 1;
-            ++l;
-        }
         if (p >= q.lvl[2 * l + 1]) return -1;
-        if (ix_m(q, l, p) < v) break;
-        ++p;
+        hit = ix_scan_group(q, l, p, v);
+        if (hit >= 0) break;
+        if (l == q.top) return -1;
+        p = p / kIxFan + 1;
+        ++l;
     }
-    while (l > 0) {                 // the first child holding a value below v
+    while (l > 0 && hit >= 0) {
         --l;
-        p <<= 1;
-        if (ix_m(q, l, p) >= v && p + 1 < q.lvl[2 * l + 1]) ++p;
+        hit = ix_scan_group(q, l, hit * kIxFan, v);
     }
-    return p;
+    return hit;
 }
 
 // Steps of one 4096-position block: el = exclusive prefix within the block,
@@ -144,13 +187,17 @@ __global__ __launch_bounds__(1024) void k_ix_top(IxParams q, const int32_t* bsum
     }
 }
 
-// Level l >= 1 of the min-tree from level l - 1.
+// Level l >= 1 of the min-tree: the minimum of each group of level l - 1.
 __global__ __launch_bounds__(256) void k_ix_level(IxParams q, int l)
 {
     const int64_t len = q.lvl[2 * l + 1], src_len = q.lvl[2 * (l - 1) + 1];
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < len; p += (int64_t)gridDim.x * 256) {
-        int32_t m = ix_m(q, l - 1, 2 * p);
-        if (2 * p + 1 < src_len) m = min(m, ix_m(q, l - 1, 2 * p + 1));
+        const int64_t g = p * kIxFan;
+        int32_t x[kIxFan];
+        ix_load_group(q, l - 1, g, x);
+        int32_t m = INT32_MAX;
+        for (int i = 0; i < kIxFan; ++i)
+            if (g + i < src_len) m = min(m, x[i]);
         q.seg[q.lvl[2 * l] + p] = m;
     }
 }

@@ -1857,24 +1857,25 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
     if (!ops || !offsets || !valid || !end || !parent) return set_err(ctx, GP_EINVAL, "missing device array");
     if (((uintptr_t)ops & 15) != 0) return set_err(ctx, GP_EINVAL, "ops must be 16-byte aligned");
     const int64_t nb = (n_nodes + kIxBlock - 1) / kIxBlock;
-    // min-tree levels: level 0 is E itself (n + 1 positions), each next one half as long, up to length 1
+    // min-tree levels: level 0 is E itself (n + 1 positions), each next one kIxFan times shorter, up to one
+    // group; every level starts on a whole group and is padded to one
     std::vector<int64_t> lvl(2 * kIxMaxLevels, 0), len(kIxMaxLevels, 0);
     len[0] = n_nodes + 1;
     lvl[1] = len[0];
     int top = 0;
     int64_t seg_total = 0;
-    while (len[top] > 1) {
+    while (len[top] > kIxFan) {
         ++top;
-        len[top] = (len[top - 1] + 1) / 2;
+        len[top] = (len[top - 1] + kIxFan - 1) / kIxFan;
         lvl[2 * top] = seg_total;
         lvl[2 * top + 1] = len[top];
-        seg_total += len[top];
+        seg_total += (len[top] + kIxFan - 1) / kIxFan * kIxFan;
     }
     DevBuf el, boff, bsum, seg, lv, flag;
-    RC(dev_alloc(ctx, el, (size_t)(nb * kIxBlock + 1) * 4));
+    RC(dev_alloc(ctx, el, (size_t)(nb * kIxBlock + kIxFan) * 4));
     RC(dev_alloc(ctx, boff, (size_t)(nb + 1) * 4));
     RC(dev_alloc(ctx, bsum, (size_t)nb * 4));
-    RC(dev_alloc(ctx, seg, (size_t)std::max<int64_t>(1, seg_total) * 4));
+    RC(dev_alloc(ctx, seg, (size_t)(seg_total + kIxFan) * 4));
     RC(dev_alloc(ctx, lv, lvl.size() * 8));
     RC(dev_alloc(ctx, flag, 4));
     HIPC(ctx, hipMemcpyAsync(lv.p, lvl.data(), lvl.size() * 8, hipMemcpyHostToDevice, ctx->stream));
