@@ -1765,8 +1765,11 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     std::vector<int64_t> chunk_sizes{p->chunk_nodes};
     if (p->auto_chunk && !p->host_ops.empty()) {
         const int64_t mean = p->total_nodes / std::max<int64_t>(1, p->n_trees);
-        std::vector<int64_t> cand = p->total_nodes > 200000000 ? std::vector<int64_t>{1024, 2048, 4096, 8192}
-                                                               : std::vector<int64_t>{256, 512, 1024, 2048, 4096};
+        // large populations of large trees keep large chunks; mid-size ones (10^8..10^9 nodes) are bound by
+        // chains of chunk hand-offs and do best at 512..1024-node chunks
+        std::vector<int64_t> cand = p->total_nodes > 1000000000  ? std::vector<int64_t>{1024, 2048, 4096, 8192}
+                                    : p->total_nodes > 200000000 ? std::vector<int64_t>{512, 768, 1024, 2048}
+                                                                 : std::vector<int64_t>{256, 512, 1024, 2048, 4096};
         chunk_sizes.clear();
         for (int64_t c : cand)
             if (c <= std::max<int64_t>(256, 4 * mean)) chunk_sizes.push_back(c);
