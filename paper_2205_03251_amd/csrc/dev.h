@@ -19,7 +19,7 @@ struct DevChunk {            // 32 bytes
     int32_t out_slot;        // vector slot receiving this chunk's value
     int32_t in_off;          // chunk_in[in_off + k] = vector slot read by LOAD k
     int32_t rec_base;        // global record slot of this tree's record 0
-    int32_t tree;
+    int32_t n_in;            // LOAD inputs: chunk_in[in_off .. in_off + n_in)
 };
 
 // Work item = (chunk << 16) | slice.

@@ -441,18 +441,24 @@ __device__ __forceinline__ void run_f32_dispatch_{K}_{S}(const GP_CONST uint32_t
 # up to NI inputs, are loaded into VGPRs when the chunk starts; an instruction
 # names an input by its payload, a wave-uniform index, so the handler reads it
 # in GPR index mode (register number offset by an SGPR) rather than from LDS.
+# The vectors of the chunk's first BOOL_NP LOAD inputs are fetched together
+# with the input words when the chunk starts (a chunk runs only once all its
+# inputs are done), so that a LOAD costs register moves instead of a memory
+# round trip on the chains of chunks that bound this launch.
 BOOL_VARIANTS = [(1, 10), (2, 10)]
 BOOL_NI = 16
+BOOL_NP = 4
 
 
-def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
+def gen_bool(K: int, S: int, NI: int = BOOL_NI, NP: int = BOOL_NP) -> str:
     V_IN = V_ST + S * K * 2
     V_T = V_IN + NI * K * 2
-    n_vgpr = V_T + 4 * K
+    V_PF = V_T + 4 * K
+    n_vgpr = V_PF + NP * K * 2
     names = []
     for p in ["TB", "TG", "A"]:
         names += [f"{p}0", f"{p}1"]
-    names += ["INS", "NXT", "OFF", "T0", "T1", "J"]
+    names += ["INS", "NXT", "OFF", "T0", "T1", "J"] + [f"P{j}" for j in range(NP)]
     s = {n: S_BASE + i for i, n in enumerate(names)}
     sr = lambda n: f"s{s[n]}"
     sp = lambda n: f"s[{s[n]}:{s[n] + 1}]"
@@ -474,14 +480,15 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
         a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
         a(f"  s_setpc_b64 {sp('TG0')}")
 
-    def read_input(idx_sreg, dst):
-        """dst(k, h) = input[idx][k] (half h), read idx * 2K registers past input 0
-        in GPR index mode (the offset applies to SRC0 of the moves in between)."""
+    def read_input(idx_sreg, dst, base=V_IN):
+        """dst(k, h) = row idx, word k, half h of the rows held from register
+        base on, read idx * 2K registers past the first row in GPR index mode
+        (the offset applies to SRC0 of the moves in between)."""
         a(f"  s_lshl_b32 {sr('J')}, {idx_sreg}, {(2 * K).bit_length() - 1}")
         a(f"  s_set_gpr_idx_on {sr('J')}, gpr_idx(SRC0)")
         for k in range(K):
             for h in range(2):
-                a(f"  v_mov_b32_e32 {dst(k, h)}, {inp(k, h)}")
+                a(f"  v_mov_b32_e32 {dst(k, h)}, v{base + k * 2 + h}")
         a("  s_set_gpr_idx_off")
 
     def op64(f, d, k, A, B):
@@ -498,6 +505,28 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
     a(f"  s_addc_u32 {sr('TB1')}, {sr('TB1')}, 0")
     a(f"  s_mov_b32 {sr('OFF')}, 0")
     a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+    # the vectors of LOAD inputs 0 .. min(nload, NP) - 1: their slots, then the rows
+    a("  s_cmp_eq_u32 %[nload], 0")
+    a(f"  s_cbranch_scc1 {lab('pfok')}")
+    for j in range(NP):
+        if j:
+            a(f"  s_cmp_le_u32 %[nload], {j}")
+            a(f"  s_cbranch_scc1 {lab('pfslots')}")
+        a(f"  s_load_dword {sr(f'P{j}')}, %[cin], {4 * j}")
+    a(f"{lab('pfslots')}:")
+    a("  s_waitcnt lgkmcnt(0)")
+    for j in range(NP):
+        if j:
+            a(f"  s_cmp_le_u32 %[nload], {j}")
+            a(f"  s_cbranch_scc1 {lab('pfok')}")
+        a(f"  s_mul_i32 {sr('A0')}, {sr(f'P{j}')}, %[strideb]")
+        a(f"  s_mul_hi_u32 {sr('A1')}, {sr(f'P{j}')}, %[strideb]")
+        a(f"  s_add_u32 {sr('A0')}, {sr('A0')}, %[vb_lo]")
+        a(f"  s_addc_u32 {sr('A1')}, {sr('A1')}, %[vb_hi]")
+        for k in range(K):
+            a(f"  global_load_dwordx2 v[{V_PF + (j * K + k) * 2}:{V_PF + (j * K + k) * 2 + 1}], %[voff], "
+              f"{sp('A0')} offset:{512 * k}{SHARED}")
+    a(f"{lab('pfok')}:")
     # the slice's input words: row j at inb + j * strideb, for j < n_inputs
     a(f"  s_mov_b32 {sr('A0')}, %[inb_lo]")
     a(f"  s_mov_b32 {sr('A1')}, %[inb_hi]")
@@ -556,6 +585,11 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
             read_input(sr('T0'), lambda k, h: st(d, k, h))
         elif mode == M_LOAD:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_cmp_lt_u32 {sr('T0')}, {NP}")
+            a(f"  s_cbranch_scc0 {lab(f'ld{key}')}")
+            read_input(sr('T0'), lambda k, h: st(d, k, h), V_PF)     # fetched when the chunk started
+            tail()
+            a(f"{lab(f'ld{key}')}:")
             a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 2")
             a(f"  s_load_dword {sr('T1')}, %[cin], {sr('T0')}")
             a("  s_waitcnt lgkmcnt(0)")
@@ -588,10 +622,12 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI) -> str:
     vclob = ", ".join(f'"v{i}"' for i in range(V_ST, n_vgpr))
     sclob = ", ".join(f'"s{s[n]}"' for n in names)
     return f"""
-// K = {K} words per lane, S = {S} stack slots, up to {NI} inputs: v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(names) - 1}.
+// K = {K} words per lane, S = {S} stack slots, up to {NI} inputs, {NP} LOAD inputs fetched ahead:
+// v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(names) - 1}.
 __device__ __forceinline__ void run_bool_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const uint64_t* inb,
                                                       const uint64_t* vb, uint64_t* rb, const GP_CONST int32_t* cin,
-                                                      uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin)
+                                                      uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin,
+                                                      uint32_t nload)
 {{
     const uint64_t inb64 = (uint64_t)inb, vb64 = (uint64_t)vb, rb64 = (uint64_t)rb;
     asm volatile(
@@ -600,7 +636,7 @@ __device__ __forceinline__ void run_bool_dispatch_{K}_{S}(const GP_CONST uint32_
         : [code] "s"(code), [inb_lo] "s"((uint32_t)inb64), [inb_hi] "s"((uint32_t)(inb64 >> 32)),
           [vb_lo] "s"((uint32_t)vb64), [vb_hi] "s"((uint32_t)(vb64 >> 32)),
           [rb_lo] "s"((uint32_t)rb64), [rb_hi] "s"((uint32_t)(rb64 >> 32)), [cin] "s"(cin),
-          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff), [nin] "s"(nin)
+          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff), [nin] "s"(nin), [nload] "s"(nload)
         : "memory", "vcc", "scc", "m0", {sclob},
           {vclob});
 }}

@@ -99,7 +99,7 @@ __device__ __forceinline__ uint64_t valid_bits(int64_t w, int64_t T)
 
 struct ChunkHdr {
     int64_t code_off;
-    int32_t code_len, parent, out_slot, in_off, rec_base;
+    int32_t code_len, parent, out_slot, in_off, rec_base, n_in;
 };
 
 __device__ __forceinline__ ChunkHdr load_chunk(const GP_CONST DevChunk* c)
@@ -111,6 +111,7 @@ __device__ __forceinline__ ChunkHdr load_chunk(const GP_CONST DevChunk* c)
     h.out_slot = c->out_slot;
     h.in_off = c->in_off;
     h.rec_base = c->rec_base;
+    h.n_in = c->n_in;
     return h;
 }
 
@@ -444,8 +445,9 @@ __global__ __launch_bounds__(64) void k_eval_bool(EvalParams p)
 // ------------------------------ Boolean interpreter, table dispatch
 // Same work items and chunk hand-off as k_eval_bool.  The generated loop
 // (gen_dispatch.py) loads the slice's input words, at most kBoolRegInputs
-// rows, into registers when a chunk starts and reads them by index in GPR
-// index mode, so no LDS is staged and no barrier is taken.
+// rows, and the vectors of the chunk's first LOAD inputs into registers when
+// a chunk starts and reads them by index in GPR index mode, so no LDS is
+// staged and no barrier is taken.
 #include "dispatch_bool.inc"
 
 constexpr int kBoolRegInputs = kBoolDispatchInputs;
@@ -453,10 +455,13 @@ constexpr int kBoolRegInputs = kBoolDispatchInputs;
 template <int K, int S>
 __device__ __forceinline__ void run_bool_dispatch(const GP_CONST uint32_t* code, const uint64_t* inb,
                                                   const uint64_t* vb, uint64_t* rb, const GP_CONST int32_t* cin,
-                                                  uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin)
+                                                  uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin,
+                                                  uint32_t nload)
 {
-    if constexpr (K == 1 && S == 10) run_bool_dispatch_1_10(code, inb, vb, rb, cin, strideb, outb, voff, nin);
-    else if constexpr (K == 2 && S == 10) run_bool_dispatch_2_10(code, inb, vb, rb, cin, strideb, outb, voff, nin);
+    if constexpr (K == 1 && S == 10)
+        run_bool_dispatch_1_10(code, inb, vb, rb, cin, strideb, outb, voff, nin, nload);
+    else if constexpr (K == 2 && S == 10)
+        run_bool_dispatch_2_10(code, inb, vb, rb, cin, strideb, outb, voff, nin, nload);
     else static_assert(K == 1 && S == 10, "no generated Boolean loop for this K and S");
 }
 
@@ -483,7 +488,7 @@ __global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
             uint64_t* rb = (uint64_t*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
             uint64_t* outb = (uint64_t*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
             run_bool_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
-                                    outb, voff, nin);
+                                    outb, voff, nin, (uint32_t)ch.n_in);
             if (ch.parent < 0) break;
             int old = 0;      // relaxed, as in k_eval_f32_tbl
             if (lane == 0)

@@ -351,7 +351,7 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
             d.out_slot = slot[k];
             d.in_off = (int32_t)chunk_in.size();
             d.rec_base = (int32_t)rbase;
-            d.tree = (int32_t)t;
+            d.n_in = (int32_t)ch.inputs.size();
             for (int32_t in : ch.inputs) chunk_in.push_back(slot[in]);
             out->chunk_n_in[cbase + k] = (int32_t)ch.inputs.size();
             out->chunk_tree[cbase + k] = (int32_t)t;
