@@ -423,7 +423,10 @@ def main():
             valid, iend, ipar, ims_one = ctx.index_trees(dops, doffs, pop.n_inputs)
             ims.append(ims_one)
         all_valid = bool((valid == 1).all())
-        del dops, doffs, valid, iend, ipar
+        del valid, iend, ipar
+        _, _, _, isn, ims_sn = ctx.index_trees(dops, doffs, pop.n_inputs, strahler=True)
+        max_sn = int(isn.max())
+        del dops, doffs, isn
         ix_ms = float(np.median(ims[1:]))
         ix_bytes = 9 * total_nodes          # each node's byte read, its end and parent (int32) written
         ix_gbps = ix_bytes / (ix_ms * 1e-3) / 1e9
@@ -431,7 +434,8 @@ def main():
                                "nodes_per_s": round(total_nodes / (ix_ms * 1e-3), 1), "bound": "hbm",
                                "achieved": round(ix_gbps, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                                "frac": round(ix_gbps / PEAK_HBM_GBPS, 4), "algorithmic_bytes": ix_bytes,
-                               "all_valid": all_valid, "host_load_s": round(load_s, 2),
+                               "all_valid": all_valid, "with_strahler_ms": round(ims_sn, 3),
+                               "max_strahler": max_sn, "host_load_s": round(load_s, 2),
                                "note": "host_load_s: validation, compilation and upload of the same trees on the host"}
 
     if args.compare:

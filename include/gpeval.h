@@ -163,13 +163,19 @@ int gp_population_info(gp_ctx* ctx, gp_handle pop, gp_pop_info* out);
  * node and closes there), else 0.  For each node k of a valid tree,
  * end[k] = the end (exclusive) of k's subtree and parent[k] = k's parent,
  * both as indices within the tree, parent -1 at the root; every node of an
- * invalid tree gets -1 in both.  1 <= n_trees <= n_nodes <= 2^31 - 2, where
- * n_nodes = offsets[n_trees].  Runs on the context stream and returns when
- * done; device_ms (may be NULL) receives its HIP-event time.  GP_EINVAL when
- * offsets do not run from 0 to n_nodes without decreasing (outputs then
- * undefined), or on bad sizes or pointers. */
+ * invalid tree gets -1 in both.  strahler (may be NULL; n_nodes bytes of
+ * device memory): the Strahler number of every node of a valid tree (1 at a
+ * terminal; at a function the larger of its children's, plus one when they
+ * are equal), 0 in an invalid tree.  Section 6.2 lets operands be evaluated
+ * in either order; evaluating the larger-numbered child first, a subtree
+ * needs as many stack slots as its number.  1 <= n_trees <= n_nodes <=
+ * 2^31 - 2, where n_nodes = offsets[n_trees].  Runs on the context stream and
+ * returns when done; device_ms (may be NULL) receives its HIP-event time.
+ * GP_EINVAL when offsets do not run from 0 to n_nodes without decreasing
+ * (outputs then undefined), or on bad sizes or pointers. */
 int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
-                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, double* device_ms);
+                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
+                   double* device_ms);
 
 /* Release a population or case set (and any cache or graph tied to it). */
 int gp_free(gp_ctx* ctx, gp_handle h);

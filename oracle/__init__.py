@@ -52,6 +52,7 @@ def lib():
         h.orc_subtree_end.restype = L
         h.orc_all_ends.argtypes = [u8p, L, i64p]
         h.orc_parents.argtypes = [u8p, L, i64p]
+        h.orc_strahler.argtypes = [u8p, L, i32p]
         h.orc_eval_f32.argtypes = [u8p, L, C.c_int, f32p, L, f32p]
         h.orc_eval_f32_nodes.argtypes = [u8p, L, C.c_int, f32p, L, f32p]
         h.orc_fitness_f32.argtypes = [f32p, f32p, L]
@@ -108,6 +109,15 @@ def parents(tree) -> np.ndarray:
     t = _u8(tree)
     out = np.zeros(len(t), np.int64)
     if lib().orc_parents(t, len(t), out) != 0:
+        raise ValueError("empty tree")
+    return out
+
+
+def strahler(tree) -> np.ndarray:
+    """Strahler number of every node of a valid prefix tree (1 at a terminal)."""
+    t = _u8(tree)
+    out = np.zeros(len(t), np.int32)
+    if lib().orc_strahler(t, len(t), out) != 0:
         raise ValueError("empty tree")
     return out
 

@@ -143,6 +143,31 @@ int orc_parents(const uint8_t* ops, int64_t n, int64_t* parent)
     return ORC_OK;
 }
 
+/* Strahler number of every node: 1 at a terminal; at a function the larger
+ * of its children's numbers, plus one when they are equal.  Section 6.2 notes
+ * that the operands may be evaluated in any order; evaluating the child with
+ * the larger number first, a stack evaluation of the subtree needs as many
+ * slots as this number.  Right-to-left pass with a stack of values. */
+int orc_strahler(const uint8_t* ops, int64_t n, int32_t* out)
+{
+    if (n < 1) return ORC_EINVAL;
+    int32_t* st = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!st) return ORC_ENOMEM;
+    int64_t sp = 0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int32_t v = 1;
+        if (is_func(ops[i])) {
+            int32_t l = st[--sp];          /* left child's number (pushed last) */
+            int32_t r = st[--sp];
+            v = l == r ? l + 1 : (l > r ? l : r);
+        }
+        out[i] = v;
+        st[sp++] = v;
+    }
+    free(st);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------- float32 semantics */
 
 static float op_f32(int f, float a, float b)

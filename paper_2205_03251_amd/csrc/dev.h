@@ -184,11 +184,17 @@ struct IxParams {
     int32_t* valid;                     // [n_trees]
     int32_t* end;                       // [n], tree-local
     int32_t* parent;                    // [n], tree-local, -1 at a root
+    uint8_t* sn;                        // [n] Strahler numbers (0 in invalid trees), or null
     int32_t* bad_offsets;               // set to 1 when offsets are not 0..n, non-decreasing
 };
 
 hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t n_blocks, const int64_t* host_len,
                         hipStream_t s);
+hipError_t launch_strahler_init(const IxParams& q, hipStream_t s);
+// One level: raises to level + 1 every node with a function below it whose children are both at level or
+// more; sets *any when there is such a function.  Reuses el and boff.
+hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, int64_t n_blocks, int32_t* any,
+                                 hipStream_t s);
 hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipStream_t s);
 // One generation's random choices (Section 6.3): per slot i, the winners of
 // tournaments (i, g, 0) and (i, g, 1) over fit, the crossover point in the

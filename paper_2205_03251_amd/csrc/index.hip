@@ -14,7 +14,8 @@
 // each entry of level l the minimum of a group of kIxFan entries of level
 // l - 1, so a search step reads one 64-byte group).  The children of a
 // function k are k + 1 and end(k + 1), so the parent index follows from the
-// ends with one write per node.
+// ends with one write per node.  On request the Strahler number of every node
+// follows, one level per pass over the subtree ranges.
 #include <algorithm>
 
 #include "dev.h"
@@ -288,6 +289,84 @@ __global__ __launch_bounds__(256) void k_ix_parents(IxParams q)
             }
         },
         [&](int64_t k) { q.parent[k] = -1; });
+}
+
+// Strahler numbers, one level per pass.  A node's number is at least k + 1
+// iff its subtree holds a function whose two children both have at least k
+// (numbers never decrease towards the root, and a node whose children differ
+// takes the larger).  Pass k marks those functions, counts them with a prefix
+// sum over positions (kept in el/boff, whose E values the ends and parents no
+// longer need), and raises every function whose subtree range holds one.
+__global__ __launch_bounds__(256) void k_ix_sinit(IxParams q)
+{
+    ix_positions(
+        q, [&](int64_t k, int64_t t, int64_t, int64_t) { q.sn[k] = q.valid[t] ? 1 : 0; },
+        [&](int64_t k) { q.sn[k] = 0; });
+}
+
+__global__ __launch_bounds__(256) void k_ix_sflag(IxParams q, int level, int32_t* bsum, int32_t* any)
+{
+    __shared__ int32_t wtot[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t base = ((int64_t)blockIdx.x * 256 + tid) * 16;
+    uint32_t bits = 0;
+    ix_positions(
+        q,
+        [&](int64_t k, int64_t, int64_t s, int64_t e) {
+            // a function with both children at level or more is itself at level already
+            if (q.sn[k] == level && (q.ops[k] & 0x80) && k + 1 < e) {
+                const int64_t r = s + q.end[k + 1];                 // the right child
+                if (r > k + 1 && r < e && q.sn[k + 1] >= level && q.sn[r] >= level) bits |= 1u << (int)(k - base);
+            }
+        },
+        [&](int64_t) {});
+    const int32_t run = __popc(bits);
+    int32_t incl = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int32_t wbase = 0;
+    for (int i = 0; i < w; ++i) wbase += wtot[i];
+    const int32_t excl = wbase + incl - run;
+    int32_t pre[16];
+    for (int j = 0; j < 16; ++j) pre[j] = excl + __popc(bits & ((1u << j) - 1u));
+    int4* dst = (int4*)(q.el + base);
+    for (int j = 0; j < 4; ++j) dst[j] = make_int4(pre[4 * j], pre[4 * j + 1], pre[4 * j + 2], pre[4 * j + 3]);
+    if (tid == 255) bsum[blockIdx.x] = excl + run;
+    if (bits) atomicOr(any, 1);
+}
+
+__global__ __launch_bounds__(256) void k_ix_supd(IxParams q, int level)
+{
+    ix_positions(
+        q,
+        [&](int64_t k, int64_t, int64_t s, int64_t e) {
+            if (q.sn[k] == level && (q.ops[k] & 0x80)) {           // only a node at level can rise
+                const int64_t x = s + q.end[k];                      // the subtree is [k, x)
+                if (x > k && x <= e && ix_e(q, x) > ix_e(q, k)) q.sn[k] = (uint8_t)(level + 1);
+            }
+        },
+        [&](int64_t) {});
+}
+
+hipError_t launch_strahler_init(const IxParams& q, hipStream_t s)
+{
+    const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
+    hipLaunchKernelGGL(k_ix_sinit, dim3((unsigned)pg), dim3(256), 0, s, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, int64_t nb, int32_t* any,
+                                 hipStream_t s)
+{
+    const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
+    hipLaunchKernelGGL(k_ix_sflag, dim3((unsigned)nb), dim3(256), 0, s, q, level, bsum, any);
+    hipLaunchKernelGGL(k_ix_top, dim3(1), dim3(1024), 0, s, q, (const int32_t*)bsum, nb);
+    hipLaunchKernelGGL(k_ix_supd, dim3((unsigned)pg), dim3(256), 0, s, q, level);
+    return hipGetLastError();
 }
 
 hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t nb, const int64_t* host_len, hipStream_t s)

@@ -1848,7 +1848,8 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
 }
 
 int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
-                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, double* device_ms)
+                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
+                   double* device_ms)
 {
     if (!ctx) return GP_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1880,7 +1881,7 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
     RC(dev_alloc(ctx, bsum, (size_t)nb * 4));
     RC(dev_alloc(ctx, seg, (size_t)(seg_total + kIxFan) * 4));
     RC(dev_alloc(ctx, lv, lvl.size() * 8));
-    RC(dev_alloc(ctx, flag, 4));
+    RC(dev_alloc(ctx, flag, 8));
     HIPC(ctx, hipMemcpyAsync(lv.p, lvl.data(), lvl.size() * 8, hipMemcpyHostToDevice, ctx->stream));
     HIPC(ctx, hipMemsetAsync(flag.p, 0, 4, ctx->stream));
     IxParams q;
@@ -1897,11 +1898,25 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
     q.valid = valid;
     q.end = end;
     q.parent = parent;
+    q.sn = strahler;
     q.bad_offsets = flag.as<int32_t>();
     HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     HIPC(ctx, launch_index(q, bsum.as<int32_t>(), nb, len.data(), ctx->stream));
-    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     int32_t bad = 0;
+    if (strahler) {
+        // one pass per level, while some function has two children at the current level
+        int32_t* any = flag.as<int32_t>() + 1;
+        HIPC(ctx, launch_strahler_init(q, ctx->stream));
+        for (int level = 1; level < 64; ++level) {
+            HIPC(ctx, hipMemsetAsync(any, 0, 4, ctx->stream));
+            HIPC(ctx, launch_strahler_level(q, level, bsum.as<int32_t>(), nb, any, ctx->stream));
+            int32_t more = 0;
+            HIPC(ctx, hipMemcpyAsync(&more, any, 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIPC(ctx, hipStreamSynchronize(ctx->stream));
+            if (!more) break;
+        }
+    }
+    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIPC(ctx, hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.f;

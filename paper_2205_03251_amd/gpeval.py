@@ -125,7 +125,7 @@ def lib() -> C.CDLL:
     h.gp_load_population.argtypes = [P, C.c_int, C.c_int, C.c_int, I64, P, P, P, P, I64, C.c_uint32,
                                      C.POINTER(I64)]
     h.gp_population_info.argtypes = [P, I64, C.POINTER(PopInfo)]
-    h.gp_index_trees.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, C.POINTER(C.c_double)]
+    h.gp_index_trees.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
     h.gp_free.argtypes = [P, I64]
     h.gp_evaluate_full.argtypes = [P, I64, I64, C.c_uint32, P, P, C.POINTER(Stats)]
     h.gp_evaluate_incremental_batch.argtypes = [P, I64, I64, I64, P, P, P, P, C.c_uint32, P, P,
@@ -371,10 +371,11 @@ class Context:
                                              C.byref(st)))
         return ops[:total], offs, st.as_dict()
 
-    def index_trees(self, ops, offsets, n_inputs: int, n_nodes=None):
+    def index_trees(self, ops, offsets, n_inputs: int, n_nodes=None, strahler=False):
         """gp_index_trees on device tensors: ops (uint8, 16-byte aligned) and
         offsets (int64, n_trees + 1).  Returns int32 device tensors valid
-        [n_trees], end [n_nodes] and parent [n_nodes], and the device time."""
+        [n_trees], end [n_nodes] and parent [n_nodes], with strahler=True also
+        the uint8 Strahler numbers [n_nodes], and the device time."""
         import torch
         n_trees = offsets.numel() - 1
         n = int(ops.numel() if n_nodes is None else n_nodes)
@@ -382,9 +383,12 @@ class Context:
         valid = torch.empty(max(n_trees, 1), dtype=torch.int32, device=dev)
         end = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         parent = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        sn = torch.empty(max(n, 1), dtype=torch.uint8, device=dev) if strahler else None
         ms = C.c_double(0.0)
         self._check(lib().gp_index_trees(self._h, n_inputs, n_trees, _ptr(ops), _ptr(offsets), n, _ptr(valid),
-                                         _ptr(end), _ptr(parent), C.byref(ms)))
+                                         _ptr(end), _ptr(parent), _ptr(sn), C.byref(ms)))
+        if strahler:
+            return valid[:n_trees], end[:n], parent[:n], sn[:n], ms.value
         return valid[:n_trees], end[:n], parent[:n], ms.value
 
     def population_info(self, pop) -> dict:

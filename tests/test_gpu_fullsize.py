@@ -175,14 +175,15 @@ def test_incremental_full_size_sampled(ctx):
 def test_index_full_size(ctx):
     """The device index of the default 500-tree population (2.1e9 nodes):
     every tree valid, the four smallest compared with the oracle node by
-    node, 64 sampled nodes of every tree compared with the oracle's subtree
-    end, and for every sampled node its parent's children include it."""
+    node (ends, parents, Strahler numbers), 64 sampled nodes of every tree
+    compared with the oracle's subtree end, for every sampled node its
+    parent's children include it, and every 25th tree's root number."""
     import torch
     pop = gen.sized_population(4, 500, 10**6, 10**7, threads=16)
     dev = torch.from_numpy(pop.ops).to("cuda:0")
     doffs = torch.from_numpy(pop.offsets).to("cuda:0")
-    valid, end, parent, ms = ctx.index_trees(dev, doffs, 1)
-    say("index full size:", int(pop.offsets[-1]), "nodes in", round(ms, 2), "ms")
+    valid, end, parent, sn, ms = ctx.index_trees(dev, doffs, 1, strahler=True)
+    say("index full size (with Strahler numbers):", int(pop.offsets[-1]), "nodes in", round(ms, 2), "ms")
     del dev
     assert bool((valid == 1).all())
     sizes = pop.sizes()
@@ -205,3 +206,8 @@ def test_index_full_size(ctx):
         tr = pop.tree(t)
         assert np.array_equal(end[s:e].cpu().numpy(), oracle.all_ends(tr))
         assert np.array_equal(parent[s:e].cpu().numpy(), oracle.parents(tr))
+        assert np.array_equal(sn[s:e].cpu().numpy(), oracle.strahler(tr))
+    # every tree's root number equals the oracle's
+    roots = sn[torch.from_numpy(pop.offsets[:-1].astype(np.int64)).to(sn.device)].cpu().numpy()
+    for t in range(0, pop.n_trees, 25):
+        assert roots[t] == oracle.strahler(pop.tree(t))[0], t

@@ -42,16 +42,20 @@ def pack(trees):
     return np.concatenate(trees).astype(np.uint8), offs
 
 
-def run_index(ctx, trees, n_inputs):
+def run_index(ctx, trees, n_inputs, strahler=False):
     import torch
     ops, offs = pack(trees)
     dev = torch.from_numpy(ops).to("cuda:0")
     doffs = torch.from_numpy(offs).to("cuda:0")
+    if strahler:
+        valid, end, parent, sn, ms = ctx.index_trees(dev, doffs, n_inputs, strahler=True)
+        return (ops, offs, valid.cpu().numpy(), end.cpu().numpy(), parent.cpu().numpy(), ms,
+                sn.cpu().numpy())
     valid, end, parent, ms = ctx.index_trees(dev, doffs, n_inputs)
     return ops, offs, valid.cpu().numpy(), end.cpu().numpy(), parent.cpu().numpy(), ms
 
 
-def check(trees, offs, valid, end, parent, n_inputs):
+def check(trees, offs, valid, end, parent, n_inputs, sn=None):
     for t, tr in enumerate(trees):
         ok = oracle.validate(tr, n_inputs)
         assert bool(valid[t]) == ok, (t, valid[t], ok)
@@ -59,8 +63,12 @@ def check(trees, offs, valid, end, parent, n_inputs):
         if ok:
             assert np.array_equal(end[s:e], oracle.all_ends(tr)), t
             assert np.array_equal(parent[s:e], oracle.parents(tr)), t
+            if sn is not None:
+                assert np.array_equal(sn[s:e], oracle.strahler(tr)), t
         else:
             assert (end[s:e] == -1).all() and (parent[s:e] == -1).all(), t
+            if sn is not None:
+                assert (sn[s:e] == 0).all(), t
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -82,27 +90,47 @@ def test_index_mixed_population(ctx, seed):
     ops, offs, valid, end, parent, ms = run_index(ctx, trees, n_inputs)
     say("index mixed", seed, len(trees), "trees", len(ops), "nodes", round(ms, 3), "ms")
     check(trees, offs, valid, end, parent, n_inputs)
+    ops, offs, valid, end, parent, ms, sn = run_index(ctx, trees, n_inputs, strahler=True)
+    say("index mixed with Strahler numbers", round(ms, 3), "ms")
+    check(trees, offs, valid, end, parent, n_inputs, sn)
 
 
 @pytest.mark.parametrize("sizes", [[1], [4095], [4095, 1], [4097], [8191, 4095, 1, 4097], [1] * 5000])
 def test_index_block_edges(ctx, sizes):
     rng = np.random.default_rng(len(sizes) + sum(sizes))
     trees = [gen.sized_tree(rng, n, n_terms=2) for n in sizes]
-    ops, offs, valid, end, parent, _ = run_index(ctx, trees, 2)
+    ops, offs, valid, end, parent, _, sn = run_index(ctx, trees, 2, strahler=True)
     assert valid.all()
-    check(trees, offs, valid, end, parent, 2)
+    check(trees, offs, valid, end, parent, 2, sn)
+
+
+def _complete(depth):
+    out = []
+
+    def rec(d):
+        if d == 0:
+            out.append(0)
+        else:
+            out.append(F)
+            rec(d - 1)
+            rec(d - 1)
+    rec(depth)
+    return out
 
 
 def test_index_deep_and_large_trees(ctx):
-    """A left comb and a right comb (height n/2) and a random 2e6-node tree."""
+    """A left comb and a right comb (height n/2), a random 2e6-node tree and a
+    complete tree of depth 17 (Strahler number 18 at its root)."""
     d = 30000
     left = np.array([F] * d + [0] * (d + 1), np.uint8)
     right = np.array([F, 0] * d + [0], np.uint8)
     big = gen.sized_tree(np.random.default_rng(3), 2_000_001, n_terms=1)
-    trees = [left, right, big]
-    ops, offs, valid, end, parent, ms = run_index(ctx, trees, 1)
+    full = np.array(_complete(17), np.uint8)
+    trees = [left, right, big, full]
+    ops, offs, valid, end, parent, ms, sn = run_index(ctx, trees, 1, strahler=True)
     say("index deep/large:", len(ops), "nodes", round(ms, 3), "ms")
-    check(trees, offs, valid, end, parent, 1)
+    check(trees, offs, valid, end, parent, 1, sn)
+    assert sn[offs[3]] == 18
 
 
 def test_index_errors(ctx):

@@ -317,3 +317,17 @@ def test_inspect_path_matches_brute_force():
                     assert int(r[3]) == (int(t[a]) & 3) | (4 if right else 0)
     with pytest.raises(g.GPError):
         g.inspect_path(np.array([gen.F_ADD, 0], np.uint8), 0)      # malformed
+
+
+def test_compiler_stack_need_and_the_strahler_number():
+    """One chunk, enough slots: evaluating the larger operand first, the
+    program needs the root's Strahler number of stack slots, or one fewer
+    where terminal operands folded into instructions save the last one."""
+    rng = np.random.default_rng(77)
+    for n in [1, 3, 9, 101, 1001, 20001]:
+        for _ in range(4):
+            tree = gen.sized_tree(rng, n, n_terms=2)
+            s = int(oracle.strahler(tree)[0])
+            for vt in [g.GP_F32, g.GP_BOOL]:
+                prog = g.inspect_program(tree, vt, 2, chunk_nodes=10**7, stack_slots=32)
+                assert s - 1 <= prog.max_stack <= s, (n, s, prog.max_stack)

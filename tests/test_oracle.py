@@ -92,6 +92,50 @@ def test_all_ends_and_parents_brute_force(seed):
             assert par[j] == (max(enclosing) if enclosing else -1)
 
 
+def _full_tree(depth):
+    """Complete binary tree of the given depth (prefix form)."""
+    return [A] + _full_tree(depth - 1) + _full_tree(depth - 1) if depth else [X]
+
+
+def test_strahler_closed_forms():
+    for d in range(0, 9):
+        s = oracle.strahler(t(*_full_tree(d)))
+        assert s[0] == d + 1                    # a complete tree of depth d
+        assert s.max() == d + 1 and s.min() == 1
+    for d in [1, 3, 50]:
+        left = t(*([A] * d + [X] * (d + 1)))    # each function has a terminal child
+        assert oracle.strahler(left).tolist() == [2] * d + [1] * (d + 1)
+        right = t(*([A, X] * d + [X]))
+        assert oracle.strahler(right).tolist() == [2, 1] * d + [1]
+    # a function whose children have different numbers takes the larger
+    assert oracle.strahler(t(A, *_full_tree(2), X)).tolist()[0] == 3
+    assert oracle.strahler(t(A, *_full_tree(2), *_full_tree(2)))[0] == 4
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_strahler_brute_force(seed):
+    """Against the characterisation: a node's number is at least k + 1 iff its
+    subtree holds a function whose two children both have at least k, checked
+    level by level from the subtree ranges."""
+    rng = np.random.default_rng(950 + seed)
+    for n in [1, 3, 7, 31, 127, 511]:
+        tree = gen.sized_tree(rng, n, n_terms=2)
+        got = oracle.strahler(tree)
+        end = [oracle.subtree_end(tree, i) for i in range(n)]
+        s = np.ones(n, np.int64)
+        k = 1
+        while True:
+            flag = [bool(tree[u] & 0x80) and s[u + 1] >= k and s[end[u + 1]] >= k for u in range(n)]
+            up = [any(flag[v:end[v]]) for v in range(n)]
+            if not any(up):
+                break
+            for v in range(n):
+                if up[v]:
+                    s[v] = k + 1
+            k += 1
+        assert np.array_equal(got, s)
+
+
 # -------------------------------------------------------- float semantics (C2)
 def test_hand_worked_float():
     x = SPECIAL[None, :]

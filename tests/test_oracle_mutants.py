@@ -51,6 +51,8 @@ MUTANTS = {
     "parent is the function that opened the earliest slot": ("parent[j] = sp > 0 ? st[sp - 1] : -1;",
                                                               "parent[j] = sp > 0 ? st[0] : -1;"),
     "a function takes three children": ("left[sp] = 2;", "left[sp] = 3;"),
+    "Strahler adds one for unequal children": ("v = l == r ? l + 1 : (l > r ? l : r);", "v = (l > r ? l : r) + 1;"),
+    "Strahler takes the smaller child": ("v = l == r ? l + 1 : (l > r ? l : r);", "v = l == r ? l + 1 : (l < r ? l : r);"),
 }
 
 
