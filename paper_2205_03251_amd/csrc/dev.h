@@ -185,6 +185,7 @@ struct IxParams {
     int32_t* end;                       // [n], tree-local
     int32_t* parent;                    // [n], tree-local, -1 at a root
     uint8_t* sn;                        // [n] Strahler numbers (0 in invalid trees), or null
+    uint8_t* bempty;                    // [n_blocks + 1]: the Strahler pass marked nothing in the block
     int32_t* bad_offsets;               // set to 1 when offsets are not 0..n, non-decreasing
 };
 

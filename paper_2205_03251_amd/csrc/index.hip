@@ -304,22 +304,81 @@ __global__ __launch_bounds__(256) void k_ix_sinit(IxParams q)
         [&](int64_t k) { q.sn[k] = 0; });
 }
 
+// The 16 bytes at p + k0 (zero past n), four to a word.
+__device__ __forceinline__ void ix_bytes16(const uint8_t* p, int64_t k0, int64_t n, uint32_t (&w)[4])
+{
+    if (k0 + 16 <= n && (((uintptr_t)(p + k0)) & 15) == 0) {
+        const uint4 v = *(const uint4*)(p + k0);
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+    } else {
+        w[0] = w[1] = w[2] = w[3] = 0;
+        for (int j = 0; j < 16; ++j)
+            if (k0 + j < n) w[j >> 2] |= (uint32_t)p[k0 + j] << (8 * (j & 3));
+    }
+}
+
+// Positions of this thread's 16 that hold a function still at level: only
+// they can be marked or raised, and a thread with none skips the tree lookup.
+__device__ __forceinline__ uint32_t ix_at_level(const IxParams& q, int64_t k0, int level)
+{
+    uint32_t ops[4], sn[4];
+    ix_bytes16(q.ops, k0, q.n, ops);
+    ix_bytes16(q.sn, k0, q.n, sn);
+    uint32_t m = 0;
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t o = (ops[j >> 2] >> (8 * (j & 3))) & 0xffu, v = (sn[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        if (k0 + j < q.n && (o & 0x80u) && v == (uint32_t)level) m |= 1u << j;
+    }
+    return m;
+}
+
+// For each set bit j of m, body(k0 + j, tree start, tree end), walking the
+// trees from the one holding k0.
+template <class Body>
+__device__ __forceinline__ void ix_each(const IxParams& q, int64_t k0, uint32_t m, Body body)
+{
+    if (!m) return;
+    int64_t t = ix_tree_of(q, k0);
+    int64_t s = q.offsets[t], e = q.offsets[t + 1];
+    while (m) {
+        const int j = __ffs(m) - 1;
+        m &= m - 1;
+        const int64_t k = k0 + j;
+        while (k >= e && t + 1 < q.n_trees) {
+            ++t;
+            s = q.offsets[t];
+            e = q.offsets[t + 1];
+        }
+        if (0 <= s && s <= k && k < e && e <= q.n) body(k, s, e);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_ix_sflag(IxParams q, int level, int32_t* bsum, int32_t* any)
 {
     __shared__ int32_t wtot[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t base = ((int64_t)blockIdx.x * 256 + tid) * 16;
     uint32_t bits = 0;
-    ix_positions(
-        q,
-        [&](int64_t k, int64_t, int64_t s, int64_t e) {
-            // a function with both children at level or more is itself at level already
-            if (q.sn[k] == level && (q.ops[k] & 0x80) && k + 1 < e) {
-                const int64_t r = s + q.end[k + 1];                 // the right child
-                if (r > k + 1 && r < e && q.sn[k + 1] >= level && q.sn[r] >= level) bits |= 1u << (int)(k - base);
-            }
-        },
-        [&](int64_t) {});
+    // a function with both children at level or more is itself at level already
+    ix_each(q, base, base < q.n ? ix_at_level(q, base, level) : 0u, [&](int64_t k, int64_t s, int64_t e) {
+        if (k + 1 < e) {
+            const int64_t r = s + q.end[k + 1];                      // the right child
+            if (r > k + 1 && r < e && q.sn[k + 1] >= level && q.sn[r] >= level) bits |= 1u << (int)(k - base);
+        }
+    });
+    // past the first levels most blocks mark nothing: their prefix is left
+    // unwritten and read as zero
+    if (!__syncthreads_or(bits != 0)) {
+        if (tid == 0) {
+            bsum[blockIdx.x] = 0;
+            q.bempty[blockIdx.x] = 1;
+        }
+        return;
+    }
+    if (tid == 0) q.bempty[blockIdx.x] = 0;
     const int32_t run = __popc(bits);
     int32_t incl = run;
     for (int o = 1; o < 64; o <<= 1) {
@@ -339,17 +398,23 @@ __global__ __launch_bounds__(256) void k_ix_sflag(IxParams q, int level, int32_t
     if (bits) atomicOr(any, 1);
 }
 
+// Marked functions before position x (x <= n): a block that marked none
+// holds no prefix of its own.
+__device__ __forceinline__ int32_t ix_count_before(const IxParams& q, int64_t x)
+{
+    const int64_t b = x / kIxBlock;
+    return q.bempty[b] ? q.boff[b] : ix_e(q, x);
+}
+
 __global__ __launch_bounds__(256) void k_ix_supd(IxParams q, int level)
 {
-    ix_positions(
-        q,
-        [&](int64_t k, int64_t, int64_t s, int64_t e) {
-            if (q.sn[k] == level && (q.ops[k] & 0x80)) {           // only a node at level can rise
-                const int64_t x = s + q.end[k];                      // the subtree is [k, x)
-                if (x > k && x <= e && ix_e(q, x) > ix_e(q, k)) q.sn[k] = (uint8_t)(level + 1);
-            }
-        },
-        [&](int64_t) {});
+    const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (k0 >= q.n) return;
+    // only a node at level can rise
+    ix_each(q, k0, ix_at_level(q, k0, level), [&](int64_t k, int64_t s, int64_t e) {
+        const int64_t x = s + q.end[k];                              // the subtree is [k, x)
+        if (x > k && x <= e && ix_count_before(q, x) > ix_count_before(q, k)) q.sn[k] = (uint8_t)(level + 1);
+    });
 }
 
 hipError_t launch_strahler_init(const IxParams& q, hipStream_t s)

@@ -1899,6 +1899,13 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
     q.end = end;
     q.parent = parent;
     q.sn = strahler;
+    q.bempty = nullptr;
+    DevBuf bempty;
+    if (strahler) {
+        RC(dev_alloc(ctx, bempty, (size_t)nb + 1));
+        HIPC(ctx, hipMemsetAsync(bempty.p, 1, (size_t)nb + 1, ctx->stream));    // block nb holds only E(n)
+        q.bempty = bempty.as<uint8_t>();
+    }
     q.bad_offsets = flag.as<int32_t>();
     HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     HIPC(ctx, launch_index(q, bsum.as<int32_t>(), nb, len.data(), ctx->stream));
