@@ -215,26 +215,50 @@ __global__ __launch_bounds__(256) void k_ix_init(IxParams q)
     }
 }
 
+// The 16 bytes at p + k0 (zero past n), four to a word.
+__device__ __forceinline__ void ix_bytes16(const uint8_t* p, int64_t k0, int64_t n, uint32_t (&w)[4])
+{
+    if (k0 + 16 <= n && (((uintptr_t)(p + k0)) & 15) == 0) {
+        const uint4 v = *(const uint4*)(p + k0);
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+    } else {
+        w[0] = w[1] = w[2] = w[3] = 0;
+        for (int j = 0; j < 16; ++j)
+            if (k0 + j < n) w[j >> 2] |= (uint32_t)p[k0 + j] << (8 * (j & 3));
+    }
+}
+
 // The positions of one thread: 16 consecutive ones, walking the trees they
-// fall in.  body(k, t, s, e) runs for each position k inside a well-formed
-// tree t = [s, e); other(k) for the rest.
+// fall in.  body(k, t, s, e, op, ek) runs for each position k inside a
+// well-formed tree t = [s, e), with k's opcode byte op and E(k); other(k) for
+// the rest.  The opcodes come in one 16-byte load and E is carried along from
+// E(k0) by the steps, so the walk itself reads nothing per position.
 template <class Body, class Other>
 __device__ __forceinline__ void ix_positions(const IxParams& q, Body body, Other other)
 {
     const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
     if (k0 >= q.n) return;
+    uint32_t w[4];
+    ix_bytes16(q.ops, k0, q.n, w);
+    int32_t ek = ix_e(q, k0);
     int64_t t = ix_tree_of(q, k0);
     int64_t s = q.offsets[t], e = q.offsets[t + 1];
     for (int j = 0; j < 16; ++j) {
         const int64_t k = k0 + j;
         if (k >= q.n) break;
+        const uint32_t wj = j < 8 ? (j < 4 ? w[0] : w[1]) : (j < 12 ? w[2] : w[3]);
+        const uint8_t op = (uint8_t)(wj >> (8 * (j & 3)));
         while (k >= e && t + 1 < q.n_trees) {
             ++t;
             s = q.offsets[t];
             e = q.offsets[t + 1];
         }
-        if (0 <= s && s <= k && k < e && e <= q.n) body(k, t, s, e);
+        if (0 <= s && s <= k && k < e && e <= q.n) body(k, t, s, e, op, ek);
         else other(k);
+        ek += (op & 0x80) ? 1 : -1;
     }
 }
 
@@ -242,10 +266,10 @@ __global__ __launch_bounds__(256) void k_ix_check(IxParams q)
 {
     ix_positions(
         q,
-        [&](int64_t k, int64_t t, int64_t s, int64_t e) {
+        [&](int64_t k, int64_t t, int64_t s, int64_t e, uint8_t op, int32_t ek) {
             const int32_t es = ix_e(q, s);
-            bool bad = ix_bad_byte(q.ops[k], q.n_inputs);
-            if (k > s && ix_e(q, k) < es) bad = true;
+            bool bad = ix_bad_byte(op, q.n_inputs);
+            if (k > s && ek < es) bad = true;
             if (k == e - 1 && ix_e(q, e) != es - 1) bad = true;
             if (bad) q.valid[t] = 0;
         },
@@ -256,13 +280,13 @@ __global__ __launch_bounds__(256) void k_ix_ends(IxParams q)
 {
     ix_positions(
         q,
-        [&](int64_t k, int64_t t, int64_t s, int64_t e) {
+        [&](int64_t k, int64_t t, int64_t s, int64_t e, uint8_t op, int32_t ek) {
             int32_t r = -1;
             if (q.valid[t]) {
-                if (!(q.ops[k] & 0x80)) {
+                if (!(op & 0x80)) {
                     r = (int32_t)(k + 1 - s);
                 } else {
-                    const int64_t j = ix_first_below(q, k + 1, ix_e(q, k));
+                    const int64_t j = ix_first_below(q, k + 1, ek);
                     if (j > k && j <= e) r = (int32_t)(j - s);
                 }
             }
@@ -275,13 +299,13 @@ __global__ __launch_bounds__(256) void k_ix_parents(IxParams q)
 {
     ix_positions(
         q,
-        [&](int64_t k, int64_t t, int64_t s, int64_t e) {
+        [&](int64_t k, int64_t t, int64_t s, int64_t e, uint8_t op, int32_t) {
             if (!q.valid[t]) {
                 q.parent[k] = -1;
                 return;
             }
             if (k == s) q.parent[k] = -1;
-            if ((q.ops[k] & 0x80) && k + 1 < e) {
+            if ((op & 0x80) && k + 1 < e) {
                 const int32_t me = (int32_t)(k - s);
                 q.parent[k + 1] = me;
                 const int64_t r = s + q.end[k + 1];     // the right child
@@ -300,24 +324,8 @@ __global__ __launch_bounds__(256) void k_ix_parents(IxParams q)
 __global__ __launch_bounds__(256) void k_ix_sinit(IxParams q)
 {
     ix_positions(
-        q, [&](int64_t k, int64_t t, int64_t, int64_t) { q.sn[k] = q.valid[t] ? 1 : 0; },
+        q, [&](int64_t k, int64_t t, int64_t, int64_t, uint8_t, int32_t) { q.sn[k] = q.valid[t] ? 1 : 0; },
         [&](int64_t k) { q.sn[k] = 0; });
-}
-
-// The 16 bytes at p + k0 (zero past n), four to a word.
-__device__ __forceinline__ void ix_bytes16(const uint8_t* p, int64_t k0, int64_t n, uint32_t (&w)[4])
-{
-    if (k0 + 16 <= n && (((uintptr_t)(p + k0)) & 15) == 0) {
-        const uint4 v = *(const uint4*)(p + k0);
-        w[0] = v.x;
-        w[1] = v.y;
-        w[2] = v.z;
-        w[3] = v.w;
-    } else {
-        w[0] = w[1] = w[2] = w[3] = 0;
-        for (int j = 0; j < 16; ++j)
-            if (k0 + j < n) w[j >> 2] |= (uint32_t)p[k0 + j] << (8 * (j & 3));
-    }
 }
 
 // Positions of this thread's 16 that hold a function still at level: only
