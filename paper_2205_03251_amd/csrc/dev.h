@@ -191,6 +191,7 @@ struct IxParams {
 
 hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t n_blocks, const int64_t* host_len,
                         hipStream_t s);
+// 1 at a terminal and 2 at a function of a valid tree (every function has two children of at least 1), 0 else.
 hipError_t launch_strahler_init(const IxParams& q, hipStream_t s);
 // One level: raises to level + 1 every node with a function below it whose children are both at level or
 // more; sets *any when there is such a function.  Reuses el and boff.

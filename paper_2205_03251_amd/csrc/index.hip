@@ -324,7 +324,10 @@ __global__ __launch_bounds__(256) void k_ix_parents(IxParams q)
 __global__ __launch_bounds__(256) void k_ix_sinit(IxParams q)
 {
     ix_positions(
-        q, [&](int64_t k, int64_t t, int64_t, int64_t, uint8_t, int32_t) { q.sn[k] = q.valid[t] ? 1 : 0; },
+        q,
+        [&](int64_t k, int64_t t, int64_t, int64_t, uint8_t op, int32_t) {
+            q.sn[k] = q.valid[t] ? ((op & 0x80) ? 2 : 1) : 0;               // a function is at least 2
+        },
         [&](int64_t k) { q.sn[k] = 0; });
 }
 

@@ -1914,7 +1914,7 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
         // one pass per level, while some function has two children at the current level
         int32_t* any = flag.as<int32_t>() + 1;
         HIPC(ctx, launch_strahler_init(q, ctx->stream));
-        for (int level = 1; level < 64; ++level) {
+        for (int level = 2; level < 64; ++level) {          // the initial numbers settle level 1
             HIPC(ctx, hipMemsetAsync(any, 0, 4, ctx->stream));
             HIPC(ctx, launch_strahler_level(q, level, bsum.as<int32_t>(), nb, any, ctx->stream));
             int32_t more = 0;
