@@ -43,6 +43,19 @@ def test_boolean_parity6_full_size_all_trees(ctx):
     r2, f2, _ = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, 64, per_tree=True)
     assert np.array_equal(r2, roots) and np.array_equal(f2, fit)
     say("boolean full size:", st)
+    # chunk vectors pass between waves without cache maintenance: every replay of
+    # the captured launch, with other device work between some of them, and with
+    # smaller chunks (more hand-offs), must give the same words
+    for rep in range(30):
+        r3, f3, _ = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, 64)
+        assert np.array_equal(r3, roots) and np.array_equal(f3, fit), rep
+        if rep % 10 == 9:
+            ctx.fitness(ch, g.GP_BOOL, r3)
+    ph2 = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=6, chunk_nodes=32)
+    for rep in range(5):
+        r4, f4, _ = ctx.evaluate_full(ph2, ch, g.GP_BOOL, pop.n_trees, 64)
+        assert np.array_equal(r4, roots) and np.array_equal(f4, fit), rep
+    ctx.free(ph2)
     ctx.free(ph)
     ctx.free(ch)
 
@@ -73,6 +86,11 @@ def test_large_float_full_size_sampled(ctx):
     # properties for every tree: fitness from the returned outputs, same order
     f_again = ctx.fitness(ch, g.GP_F32, roots)
     assert all(a == b or (math.isnan(a) and math.isnan(b)) for a, b in zip(f_again, fit))
+    # replays of the captured launch give the same bits (chunk vectors pass between
+    # waves without cache maintenance)
+    for rep in range(10):
+        r3, _, _ = ctx.evaluate_full(ph, ch, g.GP_F32, pop.n_trees, 1024)
+        assert np.array_equal(r3.view(np.uint32), roots.view(np.uint32)), rep
     ctx.free(ph)
     ctx.free(ch)
 
