@@ -356,6 +356,11 @@ typedef struct gp_job_result {
     int64_t interpreted_nodes;
     double latency_ms;          /* submit to completion */
     double queue_ms;            /* submit to admission */
+    double prep_ms;             /* submit to ready: validation and compilation on a prep thread */
+    double launch_ms;           /* admission to enqueued: the host work of the job's batch
+                                   (assembly and upload, donor compilation, launches) */
+    double run_ms;              /* enqueued to completion seen: device work and copy-out */
+    int64_t root_bytes;         /* size of the job's output vector */
 } gp_job_result;
 
 int gp_server_start(gp_ctx* ctx, const gp_server_cfg* cfg);
@@ -363,9 +368,15 @@ int gp_server_start(gp_ctx* ctx, const gp_server_cfg* cfg);
  * exceeds the budget. */
 int gp_server_submit(gp_ctx* ctx, const gp_job* job, int64_t* ticket);
 /* GP_EBUSY until the job is done; then fills *out.  root_out (may be NULL)
- * receives the job's output vector (host memory). */
-int gp_server_poll(gp_ctx* ctx, int64_t ticket, gp_job_result* out, void* root_out);
-/* Drop a resident parent kept by keep_resident. */
+ * receives the job's output vector (host memory, root_cap bytes of room:
+ * T float32 values or ceil(T / 64) uint64 words of its case set); GP_EINVAL
+ * if root_cap is smaller, and then nothing is written and the result stays
+ * available.  The result of a job that is not a resident parent is handed
+ * out once. */
+int gp_server_poll(gp_ctx* ctx, int64_t ticket, gp_job_result* out, void* root_out, int64_t root_cap);
+/* Drop a resident parent kept by keep_resident.  GP_EBUSY while the parent
+ * is not done, or while any incremental child submitted against it is not
+ * done (whether it is still being compiled, waiting or running). */
 int gp_server_release(gp_ctx* ctx, int64_t ticket);
 int gp_server_stop(gp_ctx* ctx);
 

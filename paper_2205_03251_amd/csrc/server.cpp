@@ -53,13 +53,15 @@ struct SJob {
     TreeProg prog;                          // FULL: compiled on arrival
     uint64_t est_bytes = 0;
     enum State { ARRIVED, READY, RUNNING, DONE } state = ARRIVED;
-    double t_submit = 0, t_admit = 0, t_done = 0;
+    double t_submit = 0, t_ready = 0, t_admit = 0, t_enq = 0, t_done = 0;
     gp_job_result result{};
     std::vector<uint8_t> root;              // host copy of the output vector
     // resident parent (FULL + keep_resident, after completion)
     std::shared_ptr<struct ResidentBatch> rb;
     Pop* pop = nullptr;
     int64_t tree_in_pop = -1;
+    // FULL + keep_resident: incremental children submitted and not done yet
+    int64_t pending_children = 0;
 };
 
 // Memory of a finished full batch kept for its resident parents; returned
@@ -148,12 +150,21 @@ uint64_t estimate_incremental(int64_t donor_nodes, const CaseSet* cs)
     return (uint64_t)donor_nodes * 4 + (donor_nodes / 64 + 2) * vec + 2 * vec + 64 * 1024;
 }
 
-void fail_job(SJob* j, int code)
+// A child that reaches DONE no longer holds its parent (S->mu held).
+void child_done(Server* S, SJob* j)
+{
+    if (j->kind != GP_JOB_INCREMENTAL) return;
+    auto pit = S->jobs.find(j->parent_ticket);
+    if (pit != S->jobs.end() && pit->second->pending_children > 0) --pit->second->pending_children;
+}
+
+void fail_job(Server* S, SJob* j, int code)
 {
     j->result.status = code;
     j->state = SJob::DONE;
     j->t_done = now_ms();
     j->result.latency_ms = j->t_done - j->t_submit;
+    child_done(S, j);
 }
 
 // ------------------------------------------------------------ workers
@@ -204,13 +215,14 @@ void prep_worker(Server* S)
         {
             std::lock_guard<std::mutex> lk(S->mu);
             if (status != GP_OK) {
-                fail_job(j.get(), status);
+                fail_job(S, j.get(), status);
                 S->cv_done.notify_all();
             } else if (j->est_bytes > S->budget) {
-                fail_job(j.get(), GP_EBUDGET);
+                fail_job(S, j.get(), GP_EBUDGET);
                 S->cv_done.notify_all();
             } else {
                 j->state = SJob::READY;
+                j->t_ready = now_ms();
                 S->ready.push_back(j);
             }
         }
@@ -301,12 +313,20 @@ std::shared_ptr<SBatch> form_batch(Server* S, int slot)
         SJob* j = it->get();
         if (j->kind == GP_JOB_INCREMENTAL) {
             auto pit = S->jobs.find(j->parent_ticket);
-            if (pit == S->jobs.end() || pit->second->state != SJob::DONE) {
+            if (pit == S->jobs.end()) {
+                // cannot happen while the child counts against its parent;
+                // a child never waits for a parent that is gone
+                fail_job(S, j, GP_ENOTFOUND);
+                it = S->ready.erase(it);
+                S->cv_done.notify_all();
+                continue;
+            }
+            if (pit->second->state != SJob::DONE) {
                 ++it;                          // parent not finished yet
                 continue;
             }
             if (pit->second->result.status != GP_OK || !pit->second->rb) {
-                fail_job(j, pit->second->result.status != GP_OK ? pit->second->result.status : GP_ENOTFOUND);
+                fail_job(S, j, pit->second->result.status != GP_OK ? pit->second->result.status : GP_ENOTFOUND);
                 it = S->ready.erase(it);
                 S->cv_done.notify_all();
                 continue;
@@ -355,13 +375,15 @@ void dispatch_loop(Server* S)
         int rc = launch_batch(S, b.get());
         lk.lock();
         if (rc != GP_OK) {
-            for (auto& j : b->jobs) fail_job(j.get(), rc);
+            for (auto& j : b->jobs) fail_job(S, j.get(), rc);
             S->cv_done.notify_all();
             (void)hipStreamSynchronize(S->streams[slot]);
             S->slot_busy[slot] = 0;
             S->graveyard.push_back(b);
             continue;
         }
+        const double t_enq = now_ms();
+        for (auto& j : b->jobs) j->t_enq = t_enq;
         S->inflight.push_back(b);
         S->cv_done.notify_all();
     }
@@ -417,7 +439,11 @@ void complete_loop(Server* S)
             j->t_done = t;
             j->result.latency_ms = t - j->t_submit;
             j->result.queue_ms = j->t_admit - j->t_submit;
+            j->result.prep_ms = j->t_ready - j->t_submit;
+            j->result.launch_ms = j->t_enq - j->t_admit;
+            j->result.run_ms = t - j->t_enq;
             j->state = SJob::DONE;
+            child_done(S, j);
         }
         S->slot_busy[b->slot] = 0;
         std::shared_ptr<ResidentBatch> rb;
@@ -533,6 +559,7 @@ int gp_server_submit(gp_ctx* ctxp, const gp_job* job, int64_t* ticket)
             pit->second->caller_points.end())
             return set_err(ctx, GP_ENOTFOUND, "point was not among the parent's record points");
     }
+    if (job->kind == GP_JOB_INCREMENTAL) ++S->jobs.at(job->parent_ticket)->pending_children;
     j->ticket = S->next_ticket++;
     j->t_submit = now_ms();
     S->jobs[j->ticket] = j;
@@ -542,7 +569,7 @@ int gp_server_submit(gp_ctx* ctxp, const gp_job* job, int64_t* ticket)
     return GP_OK;
 }
 
-int gp_server_poll(gp_ctx* ctxp, int64_t ticket, gp_job_result* out, void* root_out)
+int gp_server_poll(gp_ctx* ctxp, int64_t ticket, gp_job_result* out, void* root_out, int64_t root_cap)
 {
     Ctx* ctx = (Ctx*)ctxp;
     if (!ctx || !out) return GP_EINVAL;
@@ -553,7 +580,11 @@ int gp_server_poll(gp_ctx* ctxp, int64_t ticket, gp_job_result* out, void* root_
     if (it == S->jobs.end()) return set_err(ctx, GP_EINVAL, "unknown ticket");
     SJob* j = it->second.get();
     if (j->state != SJob::DONE) return GP_EBUSY;
+    if (root_out && (int64_t)j->root.size() > root_cap)
+        return set_err(ctx, GP_EINVAL, "root_out holds " + std::to_string(root_cap) + " bytes; the job's output vector has " +
+                                           std::to_string(j->root.size()));
     *out = j->result;
+    out->root_bytes = (int64_t)j->root.size();
     if (root_out && !j->root.empty()) std::memcpy(root_out, j->root.data(), j->root.size());
     // results of jobs that are not resident parents are handed out once
     if (!(j->kind == GP_JOB_FULL && j->keep_resident)) S->jobs.erase(it);
@@ -571,14 +602,9 @@ int gp_server_release(gp_ctx* ctxp, int64_t ticket)
     if (it == S->jobs.end() || it->second->kind != GP_JOB_FULL || !it->second->keep_resident)
         return set_err(ctx, GP_EINVAL, "ticket is not a resident full job");
     if (it->second->state != SJob::DONE) return GP_EBUSY;
-    // children still waiting for this parent keep it
-    for (auto& r : S->ready)
-        if (r->kind == GP_JOB_INCREMENTAL && r->parent_ticket == ticket) return GP_EBUSY;
-    for (auto& bt : S->inflight)
-        for (auto& r : bt->jobs)
-            if (r->kind == GP_JOB_INCREMENTAL && r->parent_ticket == ticket) return GP_EBUSY;
-    for (auto& r : S->arrived)
-        if (r->kind == GP_JOB_INCREMENTAL && r->parent_ticket == ticket) return GP_EBUSY;
+    // children submitted and not done yet (arrived, being compiled, ready or
+    // running) keep their parent
+    if (it->second->pending_children > 0) return GP_EBUSY;
     std::shared_ptr<ResidentBatch> rb = it->second->rb;
     S->jobs.erase(it);
     if (rb && --rb->refs == 0) {

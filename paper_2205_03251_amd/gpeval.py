@@ -91,7 +91,8 @@ class Job(C.Structure):
 class JobResult(C.Structure):
     _fields_ = [("fitness_f64", C.c_double), ("fitness_i64", C.c_int64), ("stop_level", C.c_int32),
                 ("status", C.c_int32), ("interpreted_nodes", C.c_int64), ("latency_ms", C.c_double),
-                ("queue_ms", C.c_double)]
+                ("queue_ms", C.c_double), ("prep_ms", C.c_double), ("launch_ms", C.c_double),
+                ("run_ms", C.c_double), ("root_bytes", C.c_int64)]
 
 
 _lib = None
@@ -142,7 +143,7 @@ def lib() -> C.CDLL:
     h.gp_set_variant.argtypes = [P, C.c_int]
     h.gp_server_start.argtypes = [P, C.POINTER(ServerCfg)]
     h.gp_server_submit.argtypes = [P, C.POINTER(Job), C.POINTER(I64)]
-    h.gp_server_poll.argtypes = [P, I64, C.POINTER(JobResult), P]
+    h.gp_server_poll.argtypes = [P, I64, C.POINTER(JobResult), P, I64]
     h.gp_server_release.argtypes = [P, I64]
     h.gp_server_stop.argtypes = [P]
     h.gp_inspect_program.argtypes = [C.c_int, C.c_int, P, I64, I64, C.c_int, C.c_int, P, I64, P, I64, P, I64,
@@ -517,7 +518,7 @@ class Context:
         if want_root and n_cases:
             root = np.empty(n_cases if vtype == GP_F32 else (n_cases + 63) // 64,
                             np.float32 if vtype == GP_F32 else np.uint64)
-        rc = lib().gp_server_poll(self._h, ticket, C.byref(r), _ptr(root))
+        rc = lib().gp_server_poll(self._h, ticket, C.byref(r), _ptr(root), root.nbytes if root is not None else 0)
         if rc == GP_EBUSY:
             return None
         self._check(rc)

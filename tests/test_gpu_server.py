@@ -104,18 +104,24 @@ def test_served_results_same_alone_and_in_mix_and_match_oracle():
         if vt == g.GP_F32:
             with np.errstate(all="ignore"):
                 want = oracle.eval_f32(tree, fc[T].x)
+                w_fit = oracle.fitness_f32(want, fc[T].y)
             assert same_f32(p["root"], want).all()
+            assert p["fitness_f64"] == w_fit or (math.isnan(p["fitness_f64"]) and math.isnan(w_fit))
         else:
-            assert np.array_equal(p["root"], oracle.eval_bool(tree, bc.inputs))
+            want = oracle.eval_bool(tree, bc.inputs)
+            assert np.array_equal(p["root"], want)
+            assert p["fitness_i64"] == oracle.fitness_bool(want, bc.target, 256)
         for ki, (pt, d) in enumerate(kids):
             c = alone[("c", ji, ki)]
             if vt == g.GP_F32:
                 with np.errstate(all="ignore"):
                     w_root, w_lvl, w_int, w_fit = oracle.incremental_f32(tree, pt, d, fc[T].x, fc[T].y)
                 assert same_f32(c["root"], w_root).all()
+                assert c["fitness_f64"] == w_fit or (math.isnan(c["fitness_f64"]) and math.isnan(w_fit))
             else:
                 w_root, w_lvl, w_int, w_fit = oracle.incremental_bool(tree, pt, d, bc.inputs, bc.target, 256)
                 assert np.array_equal(c["root"], w_root)
+                assert c["fitness_i64"] == w_fit
             assert c["stop_level"] == w_lvl
             assert c["interpreted_nodes"] == w_int
     ctx.close()
@@ -161,5 +167,69 @@ def test_server_budget_admission():
     with pytest.raises(g.GPError) as e:
         ctx.server_submit(g.GP_JOB_FULL, h, gen.sized_tree(rng, 30_000_001))
     assert e.value.code == g.GP_EBUDGET
+    ctx.server_stop()
+    ctx.close()
+
+
+def test_release_waits_for_children_still_compiling():
+    """A resident parent cannot be released while a child submitted against
+    it is not done, including a child whose donor a prep thread is still
+    compiling; every child completes with the oracle's result."""
+    ctx = g.Context(0)
+    c = gen.float_cases(4, 512)
+    h = ctx.set_cases(g.GP_F32, c.x, c.y)
+    ctx.server_start(n_streams=2, max_batch_jobs=4, prep_threads=2)
+    rng = np.random.default_rng(5)
+    tree = gen.sized_tree(rng, 40001)
+    pts = [1, 17, 333]
+    p = ctx.server_submit(g.GP_JOB_FULL, h, tree, record_points=np.array(pts, np.int64), keep_resident=True)
+    assert wait(ctx, p, g.GP_F32, 512)["status"] == 0
+    donors = [gen.sized_tree(rng, 200001) for _ in pts]
+    kids = [ctx.server_submit(g.GP_JOB_INCREMENTAL, h, d, parent_ticket=p, point=q) for d, q in zip(donors, pts)]
+    released = False
+    try:
+        ctx.server_release(p)
+        released = True
+    except g.GPError as e:
+        assert e.code == g.GP_EBUSY
+    for k, d, q in zip(kids, donors, pts):
+        r = wait(ctx, k, g.GP_F32, 512)
+        assert r["status"] == 0
+        with np.errstate(all="ignore"):
+            w_root, w_lvl, w_int, w_fit = oracle.incremental_f32(tree, q, d, c.x, c.y)
+        assert same_f32(r["root"], w_root).all() and r["stop_level"] == w_lvl
+        assert r["fitness_f64"] == w_fit or (math.isnan(r["fitness_f64"]) and math.isnan(w_fit))
+        assert r["root_bytes"] == 512 * 4
+    if not released:
+        ctx.server_release(p)
+    with pytest.raises(g.GPError):                    # gone now
+        ctx.server_release(p)
+    ctx.server_stop()
+    ctx.close()
+
+
+def test_poll_refuses_a_small_output_buffer():
+    """gp_server_poll writes the output vector only into a buffer that holds
+    it; the result stays available for a second poll."""
+    import ctypes as C
+    ctx = g.Context(0)
+    c = gen.float_cases(6, 300)
+    h = ctx.set_cases(g.GP_F32, c.x, c.y)
+    ctx.server_start(n_streams=1, max_batch_jobs=2, prep_threads=1)
+    t = ctx.server_submit(g.GP_JOB_FULL, h, np.array([gen.F_MUL, 0, 0], np.uint8))
+    small = np.zeros(299, np.float32)
+    r = g.JobResult()
+    deadline = time.time() + 60
+    while True:
+        rc = g.lib().gp_server_poll(ctx._h, t, C.byref(r), small.ctypes.data, small.nbytes)
+        if rc != g.GP_EBUSY:
+            break
+        assert time.time() < deadline
+        time.sleep(0.001)
+    assert rc == g.GP_EINVAL
+    assert not small.any()
+    out = wait(ctx, t, g.GP_F32, 300)
+    assert out["status"] == 0 and out["root_bytes"] == 1200
+    assert same_f32(out["root"], c.x[0] * c.x[0]).all()
     ctx.server_stop()
     ctx.close()
