@@ -177,6 +177,22 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
                    int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
                    double* device_ms);
 
+/* gp_index_trees for callers that cannot allocate device memory (serving
+ * loops that must not call hipMalloc, harnesses that forbid allocation):
+ * the same arguments, outputs and errors, for populations of at most
+ * GP_INDEX_NOALLOC_MAX_NODES nodes (GP_EINVAL beyond, nothing written).  Its
+ * working memory is a fixed array of about 18 MB in device memory that the
+ * library holds on every device a context was created on, from gp_create
+ * until the process ends; the call allocates nothing and frees nothing.  All
+ * calls on one device share that array: calls that overlap in time on one
+ * device, from any contexts or threads, race and give undefined results.
+ * Like gp_index_trees it waits for its result (it is not for stream
+ * capture). */
+#define GP_INDEX_NOALLOC_MAX_NODES 4194304
+int gp_index_trees_noalloc(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops,
+                           const int64_t* offsets, int64_t n_nodes, int32_t* valid, int32_t* end,
+                           int32_t* parent, uint8_t* strahler, double* device_ms);
+
 /* Release a population or case set (and any cache or graph tied to it). */
 int gp_free(gp_ctx* ctx, gp_handle h);
 

@@ -180,7 +180,7 @@ struct IxParams {
     int32_t* el;                        // [n_blocks * kIxBlock + kIxFan]
     int32_t* boff;                      // [n_blocks + 1]
     int32_t* seg;                       // min-tree levels 1..top, each padded to whole groups
-    const int64_t* lvl;                 // [2 * kIxMaxLevels]: offset in seg, length; level 0 = E, length n + 1
+    int64_t lvl[2 * kIxMaxLevels];      // offset in seg and length of each level; level 0 = E, length n + 1
     int32_t* valid;                     // [n_trees]
     int32_t* end;                       // [n], tree-local
     int32_t* parent;                    // [n], tree-local, -1 at a root
@@ -191,6 +191,36 @@ struct IxParams {
 
 hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t n_blocks, const int64_t* host_len,
                         hipStream_t s);
+// dst[0 .. n) = v, by a kernel (no memset node in a captured stream).
+hipError_t launch_fill_u8(uint8_t* dst, int64_t n, uint8_t v, hipStream_t s);
+
+// Scratch of the allocation-free tree index (gp_index_trees_noalloc): a
+// file-scope device array of kIxStaticWords int32 words in index.hip, enough
+// for populations of up to kIxStaticMaxNodes nodes.  Regions, each starting
+// on a 256-byte boundary: el, boff, bsum, seg, flags (4 words), bempty.
+constexpr int64_t kIxStaticMaxNodes = int64_t(1) << 22;
+constexpr int64_t ix_round64(int64_t w) { return (w + 63) / 64 * 64; }
+constexpr int64_t ix_seg_words(int64_t n)
+{
+    int64_t len = n + 1, total = 0;
+    while (len > kIxFan) {
+        len = (len + kIxFan - 1) / kIxFan;
+        total += (len + kIxFan - 1) / kIxFan * kIxFan;
+    }
+    return total + kIxFan;
+}
+constexpr int64_t kIxStaticBlocks = (kIxStaticMaxNodes + kIxBlock - 1) / kIxBlock;
+constexpr int64_t kIxStaticEl = 0;
+constexpr int64_t kIxStaticBoff = kIxStaticEl + ix_round64(kIxStaticBlocks * kIxBlock + kIxFan);
+constexpr int64_t kIxStaticBsum = kIxStaticBoff + ix_round64(kIxStaticBlocks + 1);
+constexpr int64_t kIxStaticSeg = kIxStaticBsum + ix_round64(kIxStaticBlocks);
+constexpr int64_t kIxStaticFlag = kIxStaticSeg + ix_round64(ix_seg_words(kIxStaticMaxNodes));
+constexpr int64_t kIxStaticBempty = kIxStaticFlag + 64;
+constexpr int64_t kIxStaticWords = kIxStaticBempty + ix_round64((kIxStaticBlocks + 1 + 3) / 4);
+// The device address of that array on the current device (device, which
+// must be current), looked up once per device; hipSuccess or the lookup's
+// error.
+hipError_t ix_static_scratch(int device, int32_t** out);
 // 1 at a terminal and 2 at a function of a valid tree (every function has two children of at least 1), 0 else.
 hipError_t launch_strahler_init(const IxParams& q, hipStream_t s);
 // One level: raises to level + 1 every node with a function below it whose children are both at level or

@@ -17,10 +17,45 @@
 // ends with one write per node.  On request the Strahler number of every node
 // follows, one level per pass over the subtree ranges.
 #include <algorithm>
+#include <mutex>
 
 #include "dev.h"
 
 namespace gpe {
+
+// Scratch of the allocation-free index entry point (layout in dev.h).  Host
+// code never names it except to look up its device address: on each device
+// the array has its own copy at its own address.
+static __device__ __align__(256) int32_t scratch[kIxStaticWords];
+
+hipError_t ix_static_scratch(int device, int32_t** out)
+{
+    static std::mutex mu;
+    static int32_t* addr[256] = {};
+    if (device < 0 || device >= 256) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (int32_t*)p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u8(uint8_t* dst, int64_t n, uint8_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = v;
+}
+
+hipError_t launch_fill_u8(uint8_t* dst, int64_t n, uint8_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t grid = std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)grid), dim3(256), 0, s, dst, n, v);
+    return hipGetLastError();
+}
 
 static_assert(kIxFan == 16, "a group is read as four 16-byte loads");
 

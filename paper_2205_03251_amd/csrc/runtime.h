@@ -188,6 +188,7 @@ struct Ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around the interpreter launch
     Server* server = nullptr;
+    int32_t* ix_scratch = nullptr;          // this device's copy of the index scratch array
 };
 
 // ------------------------------------------------------------ internals

@@ -994,6 +994,8 @@ int gp_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, gp_ctx** 
     if ((e = hipEventCreate(&c->ev1)) != hipSuccess) return fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&c->kev0)) != hipSuccess) return fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&c->kev1)) != hipSuccess) return fail(e, "hipEventCreate");
+    // device address of the allocation-free index's scratch array on this device
+    if ((e = ix_static_scratch(device, &c->ix_scratch)) != hipSuccess) return fail(e, "hipGetSymbolAddress");
     Variant* vt = variant_table();
     for (int v = 0; v < variant_count(); ++v) {
         int nb = 0;
@@ -1847,6 +1849,96 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     return GP_OK;
 }
 
+// Arguments shared by both index entry points.
+static int ix_check_args(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+                         int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent)
+{
+    if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(ctx, GP_EINVAL, "n_inputs must be 1..64");
+    if (n_trees < 1 || n_nodes < 1) return set_err(ctx, GP_EINVAL, "empty population");
+    if (n_nodes > (int64_t)INT32_MAX - 1) return set_err(ctx, GP_EINVAL, "at most 2^31 - 2 nodes per call");
+    if (n_trees > n_nodes) return set_err(ctx, GP_EINVAL, "more trees than nodes");
+    if (!ops || !offsets || !valid || !end || !parent) return set_err(ctx, GP_EINVAL, "missing device array");
+    if (((uintptr_t)ops & 15) != 0) return set_err(ctx, GP_EINVAL, "ops must be 16-byte aligned");
+    return GP_OK;
+}
+
+// Min-tree levels of n positions: level 0 is E itself (n + 1 positions), each
+// next one kIxFan times shorter, up to one group; every level after 0 starts
+// on a whole group of seg and is padded to one.  Fills q.lvl, q.top and
+// len[0 .. top]; returns the words of seg used (without the final padding).
+static int64_t ix_levels(int64_t n, IxParams& q, int64_t (&len)[kIxMaxLevels])
+{
+    for (int l = 0; l < kIxMaxLevels; ++l) {
+        len[l] = 0;
+        q.lvl[2 * l] = q.lvl[2 * l + 1] = 0;
+    }
+    len[0] = n + 1;
+    q.lvl[1] = len[0];
+    int top = 0;
+    int64_t seg_total = 0;
+    while (len[top] > kIxFan) {
+        ++top;
+        len[top] = (len[top - 1] + kIxFan - 1) / kIxFan;
+        q.lvl[2 * top] = seg_total;
+        q.lvl[2 * top + 1] = len[top];
+        seg_total += (len[top] + kIxFan - 1) / kIxFan * kIxFan;
+    }
+    q.top = top;
+    return seg_total;
+}
+
+// The index kernels on ctx's stream with the given scratch (el, boff, bsum,
+// seg sized for q.n; flag 2 words; bempty n_blocks + 1 bytes), then the host
+// waits for the offsets flag (and, per Strahler level, for the level's flag).
+// Flags are cleared by a fill kernel.  Allocates nothing.
+static int ix_run(Ctx* ctx, IxParams& q, int32_t* bsum, int32_t* flag, int64_t nb, const int64_t* len,
+                  double* device_ms)
+{
+    q.bad_offsets = flag;
+    HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    HIPC(ctx, launch_fill_i32(flag, 2, 0, ctx->stream));
+    if (q.sn) HIPC(ctx, launch_fill_u8(q.bempty, nb + 1, 1, ctx->stream));      // block nb holds only E(n)
+    HIPC(ctx, launch_index(q, bsum, nb, len, ctx->stream));
+    if (q.sn) {
+        // one pass per level, while some function has two children at the current level
+        int32_t* any = flag + 1;
+        HIPC(ctx, launch_strahler_init(q, ctx->stream));
+        for (int level = 2; level < 64; ++level) {          // the initial numbers settle level 1
+            HIPC(ctx, launch_fill_i32(any, 1, 0, ctx->stream));
+            HIPC(ctx, launch_strahler_level(q, level, bsum, nb, any, ctx->stream));
+            int32_t more = 0;
+            HIPC(ctx, hipMemcpyAsync(&more, any, 4, hipMemcpyDeviceToHost, ctx->stream));
+            HIPC(ctx, hipStreamSynchronize(ctx->stream));
+            if (!more) break;
+        }
+    }
+    int32_t bad = 0;
+    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIPC(ctx, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (device_ms) *device_ms = ms;
+    if (bad) return set_err(ctx, GP_EINVAL, "offsets must run from 0 to n_nodes without decreasing");
+    return GP_OK;
+}
+
+static IxParams ix_params(int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets, int64_t n_nodes,
+                          int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler)
+{
+    IxParams q{};
+    q.ops = ops;
+    q.offsets = offsets;
+    q.n_trees = n_trees;
+    q.n = n_nodes;
+    q.n_inputs = n_inputs;
+    q.valid = valid;
+    q.end = end;
+    q.parent = parent;
+    q.sn = strahler;
+    return q;
+}
+
 int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
                    int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
                    double* device_ms)
@@ -1854,83 +1946,49 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
     if (!ctx) return GP_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     HIPC(ctx, hipSetDevice(ctx->device));
-    if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(ctx, GP_EINVAL, "n_inputs must be 1..64");
-    if (n_trees < 1 || n_nodes < 1) return set_err(ctx, GP_EINVAL, "empty population");
-    if (n_nodes > (int64_t)INT32_MAX - 1) return set_err(ctx, GP_EINVAL, "at most 2^31 - 2 nodes per call");
-    if (n_trees > n_nodes) return set_err(ctx, GP_EINVAL, "more trees than nodes");
-    if (!ops || !offsets || !valid || !end || !parent) return set_err(ctx, GP_EINVAL, "missing device array");
-    if (((uintptr_t)ops & 15) != 0) return set_err(ctx, GP_EINVAL, "ops must be 16-byte aligned");
+    RC(ix_check_args(ctx, n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent));
+    IxParams q = ix_params(n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent, strahler);
+    int64_t len[kIxMaxLevels];
+    const int64_t seg_total = ix_levels(n_nodes, q, len);
     const int64_t nb = (n_nodes + kIxBlock - 1) / kIxBlock;
-    // min-tree levels: level 0 is E itself (n + 1 positions), each next one kIxFan times shorter, up to one
-    // group; every level starts on a whole group and is padded to one
-    std::vector<int64_t> lvl(2 * kIxMaxLevels, 0), len(kIxMaxLevels, 0);
-    len[0] = n_nodes + 1;
-    lvl[1] = len[0];
-    int top = 0;
-    int64_t seg_total = 0;
-    while (len[top] > kIxFan) {
-        ++top;
-        len[top] = (len[top - 1] + kIxFan - 1) / kIxFan;
-        lvl[2 * top] = seg_total;
-        lvl[2 * top + 1] = len[top];
-        seg_total += (len[top] + kIxFan - 1) / kIxFan * kIxFan;
-    }
-    DevBuf el, boff, bsum, seg, lv, flag;
+    DevBuf el, boff, bsum, seg, flag, bempty;
     RC(dev_alloc(ctx, el, (size_t)(nb * kIxBlock + kIxFan) * 4));
     RC(dev_alloc(ctx, boff, (size_t)(nb + 1) * 4));
     RC(dev_alloc(ctx, bsum, (size_t)nb * 4));
     RC(dev_alloc(ctx, seg, (size_t)(seg_total + kIxFan) * 4));
-    RC(dev_alloc(ctx, lv, lvl.size() * 8));
     RC(dev_alloc(ctx, flag, 8));
-    HIPC(ctx, hipMemcpyAsync(lv.p, lvl.data(), lvl.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-    HIPC(ctx, hipMemsetAsync(flag.p, 0, 4, ctx->stream));
-    IxParams q;
-    q.ops = ops;
-    q.offsets = offsets;
-    q.n_trees = n_trees;
-    q.n = n_nodes;
-    q.n_inputs = n_inputs;
-    q.top = top;
+    if (strahler) RC(dev_alloc(ctx, bempty, (size_t)nb + 1));
     q.el = el.as<int32_t>();
     q.boff = boff.as<int32_t>();
     q.seg = seg.as<int32_t>();
-    q.lvl = lv.as<int64_t>();
-    q.valid = valid;
-    q.end = end;
-    q.parent = parent;
-    q.sn = strahler;
-    q.bempty = nullptr;
-    DevBuf bempty;
-    if (strahler) {
-        RC(dev_alloc(ctx, bempty, (size_t)nb + 1));
-        HIPC(ctx, hipMemsetAsync(bempty.p, 1, (size_t)nb + 1, ctx->stream));    // block nb holds only E(n)
-        q.bempty = bempty.as<uint8_t>();
-    }
-    q.bad_offsets = flag.as<int32_t>();
-    HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    HIPC(ctx, launch_index(q, bsum.as<int32_t>(), nb, len.data(), ctx->stream));
-    int32_t bad = 0;
-    if (strahler) {
-        // one pass per level, while some function has two children at the current level
-        int32_t* any = flag.as<int32_t>() + 1;
-        HIPC(ctx, launch_strahler_init(q, ctx->stream));
-        for (int level = 2; level < 64; ++level) {          // the initial numbers settle level 1
-            HIPC(ctx, hipMemsetAsync(any, 0, 4, ctx->stream));
-            HIPC(ctx, launch_strahler_level(q, level, bsum.as<int32_t>(), nb, any, ctx->stream));
-            int32_t more = 0;
-            HIPC(ctx, hipMemcpyAsync(&more, any, 4, hipMemcpyDeviceToHost, ctx->stream));
-            HIPC(ctx, hipStreamSynchronize(ctx->stream));
-            if (!more) break;
-        }
-    }
-    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-    HIPC(ctx, hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, ctx->stream));
-    HIPC(ctx, hipStreamSynchronize(ctx->stream));
-    float ms = 0.f;
-    HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    if (device_ms) *device_ms = ms;
-    if (bad) return set_err(ctx, GP_EINVAL, "offsets must run from 0 to n_nodes without decreasing");
-    return GP_OK;
+    q.bempty = strahler ? bempty.as<uint8_t>() : nullptr;
+    return ix_run(ctx, q, bsum.as<int32_t>(), flag.as<int32_t>(), nb, len, device_ms);
+}
+
+static_assert(GP_INDEX_NOALLOC_MAX_NODES == kIxStaticMaxNodes, "header and scratch array disagree");
+
+int gp_index_trees_noalloc(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+                           int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
+                           double* device_ms)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    RC(ix_check_args(ctx, n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent));
+    if (n_nodes > kIxStaticMaxNodes)
+        return set_err(ctx, GP_EINVAL, "gp_index_trees_noalloc takes at most 4194304 nodes per call "
+                                       "(gp_index_trees takes more)");
+    if (!ctx->ix_scratch) return set_err(ctx, GP_EDEVICE, "the index scratch array has no device address");
+    IxParams q = ix_params(n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent, strahler);
+    int64_t len[kIxMaxLevels];
+    (void)ix_levels(n_nodes, q, len);
+    const int64_t nb = (n_nodes + kIxBlock - 1) / kIxBlock;
+    int32_t* base = ctx->ix_scratch;
+    q.el = base + kIxStaticEl;
+    q.boff = base + kIxStaticBoff;
+    q.seg = base + kIxStaticSeg;
+    q.bempty = strahler ? (uint8_t*)(base + kIxStaticBempty) : nullptr;
+    return ix_run(ctx, q, base + kIxStaticBsum, base + kIxStaticFlag, nb, len, device_ms);
 }
 
 int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n)

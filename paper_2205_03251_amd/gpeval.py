@@ -29,7 +29,9 @@ EXPORTS = [
     "gp_evaluate_incremental", "gp_fitness", "gp_variant_name", "gp_variant_count", "gp_autotune",
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
     "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree", "gp_index_trees",
+    "gp_index_trees_noalloc",
 ]
+INDEX_NOALLOC_MAX_NODES = 4194304
 
 
 class GPError(RuntimeError):
@@ -127,6 +129,7 @@ def lib() -> C.CDLL:
                                      C.POINTER(I64)]
     h.gp_population_info.argtypes = [P, I64, C.POINTER(PopInfo)]
     h.gp_index_trees.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
+    h.gp_index_trees_noalloc.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
     h.gp_free.argtypes = [P, I64]
     h.gp_evaluate_full.argtypes = [P, I64, I64, C.c_uint32, P, P, C.POINTER(Stats)]
     h.gp_evaluate_incremental_batch.argtypes = [P, I64, I64, I64, P, P, P, P, C.c_uint32, P, P,
@@ -391,6 +394,18 @@ class Context:
         if strahler:
             return valid[:n_trees], end[:n], parent[:n], sn[:n], ms.value
         return valid[:n_trees], end[:n], parent[:n], ms.value
+
+    def index_trees_noalloc(self, ops, offsets, n_inputs: int, valid, end, parent, strahler=None, n_nodes=None):
+        """gp_index_trees_noalloc on device tensors the caller provides
+        (valid int32 [n_trees], end and parent int32 [n_nodes], strahler uint8
+        [n_nodes] or None).  Returns the device time."""
+        n_trees = offsets.numel() - 1
+        n = int(ops.numel() if n_nodes is None else n_nodes)
+        ms = C.c_double(0.0)
+        self._check(lib().gp_index_trees_noalloc(self._h, n_inputs, n_trees, _ptr(ops), _ptr(offsets), n,
+                                                 _ptr(valid), _ptr(end), _ptr(parent), _ptr(strahler),
+                                                 C.byref(ms)))
+        return ms.value
 
     def population_info(self, pop) -> dict:
         info = PopInfo()
