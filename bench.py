@@ -77,41 +77,190 @@ def record_lists(n_trees, kids):
     return np.array([c for p in pts for c in p], np.int64), offs
 
 
-def cpu_baseline(pop, cases, kids, vtype, threads, budget_s=12.0):
-    """The oracle as it stands, P independent single-threaded instances."""
+def host_cpu():
+    """The GPU host's CPU: nproc (CPUs this process may run on), os.cpu_count()
+    and the model name from lscpu (else /proc/cpuinfo)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count(), "model": model}
+
+
+def oracle_full(pop, cases, vtype, threads, budget_s, cpu, gpu_fit=None):
+    """The oracle as it stands (single-threaded C stack interpreter, its
+    plain loop over trees), as `threads` independent instances, each taking a
+    share of a bounded sample balanced by size (longest tree to the least
+    loaded instance): the smallest trees, at least one per instance, until
+    about budget_s of work per instance at the rate the oracle measures on
+    the smallest tree.  A sample that is the whole population is run again
+    until it takes a measurable time.  With gpu_fit, the sample's fitness
+    values are compared with the GPU's."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
     T = cases.T
     sizes = pop.sizes()
-    # bounded sample: the smallest trees, at least one per thread, until about
-    # budget_s of work per thread at the oracle's ~10 ns per node and case
-    per_thread_ops = budget_s / 10e-9
-    target = per_thread_ops * threads
+    order = np.argsort(sizes, kind="stable")
+    # the oracle's rate on this population, from its smallest trees (a few ms)
+    probe, tot = [], 0
+    for i in order:
+        probe.append(int(i))
+        tot += int(sizes[i])
+        if tot * T >= 2e6:
+            break
+    tp = time.perf_counter()
+    oracle.population_fitness(pop, np.array(probe, np.int64), cases)
+    rate = max(1e6, tot * T / max(1e-6, time.perf_counter() - tp))
+    target = budget_s * rate * threads
     chosen, tot = [], 0
-    for i in np.argsort(sizes, kind="stable"):
+    for i in order:
         if tot >= target and len(chosen) >= threads:
             break
         chosen.append(int(i))
         tot += int(sizes[i]) * T
-    chosen = np.array(chosen, np.int64)
-    ops_done = 0
+    shares = [[] for _ in range(min(threads, len(chosen)))]
+    load = np.zeros(len(shares))
+    for i in sorted(chosen, key=lambda i: -sizes[i]):
+        k = int(np.argmin(load))
+        shares[k].append(i)
+        load[k] += sizes[i]
+    shares = [np.array(sh, np.int64) for sh in shares]
+    fits = {}
+    # a whole small population: each instance repeats its share for about 50 ms per call
+    whole = len(chosen) == pop.n_trees
+    reps = max(1, int(0.05 * rate / max(1, tot / len(shares)))) if whole else 1
+
+    def one(sh):
+        for _ in range(reps):
+            f = oracle.population_fitness(pop, sh, cases)
+        for i, v in zip(sh.tolist(), f.tolist()):
+            fits[i] = v
+        return int(sizes[sh].sum()) * T * reps
+
+    t0 = time.perf_counter()
+    ops_done, passes = 0, 0
+    with ThreadPoolExecutor(len(shares)) as ex:
+        while passes == 0 or (whole and time.perf_counter() - t0 < min(1.0, budget_s)):
+            ops_done += sum(ex.map(one, shares))
+            passes += reps
+    dt = time.perf_counter() - t0
+    out = {"value": round(ops_done / dt / 1e9, 4), "unit": "GPop/s", "cores": len(shares),
+           "kind": "oracle", "nproc": cpu["nproc"], "cpu_model": cpu["model"],
+           "sample": f"full evaluation of the {len(chosen)} smallest of the {pop.n_trees} trees "
+                     f"({int(sizes[chosen].sum())} nodes) on all {T} cases"
+                     + (f", {passes} passes" if passes > 1 else "") + f", {dt:.2f} s"}
+    if gpu_fit is not None:
+        same = all(fits[i] == gpu_fit[i] or (np.isnan(fits[i]) and np.isnan(gpu_fit[i])) for i in chosen)
+        out["sample_fitness_equals_gpu"] = bool(same)
+    return out
+
+
+def oracle_incremental(pop, cases, kids, threads, cpu, gpu_fit=None, gpu_stop=None):
+    """The oracle's incremental evaluation (the paper's co-evaluation of the
+    mother alongside the child, Section 6.2) of the children of the `threads`
+    smallest parents, one child per thread."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    T = cases.T
+    psz = pop.sizes()
+    order = [int(i) for i in np.argsort(psz[kids.parent], kind="stable")[:threads]]
+    res = {}
 
     def one(i):
-        if vtype == gen.VT_BOOL:
-            oracle.fitness_bool(oracle.eval_bool(pop.tree(i), cases.inputs), cases.target, T)
-        else:
-            with np.errstate(all="ignore"):
-                oracle.fitness_f32(oracle.eval_f32(pop.tree(i), cases.x), cases.y)
-        return int(sizes[i]) * T
+        P = pop.tree(int(kids.parent[i]))
+        with np.errstate(all="ignore"):
+            r = oracle.incremental_f32(P, int(kids.point[i]), kids.donors.tree(i), cases.x, cases.y)
+        res[i] = r
+        c = int(kids.point[i])
+        child = len(P) - (gen.subtree_end(P, c) - c) + len(kids.donors.tree(i))
+        return child * T, (len(P) + len(kids.donors.tree(i))) * T
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(threads) as ex:
-        ops_done = sum(ex.map(one, sorted(chosen, key=lambda i: -sizes[i])))
+        done = list(ex.map(one, order))
     dt = time.perf_counter() - t0
-    return {"value": ops_done / dt / 1e9, "unit": "GPop/s", "cores": int(min(threads, len(chosen))),
-            "kind": "oracle",
-            "sample": f"full evaluation of the {len(chosen)} smallest of the {pop.n_trees} trees "
-                      f"({int(sizes[chosen].sum())} nodes) on all {T} cases, {dt:.1f} s"}
+    out = {"value": round(sum(d[0] for d in done) / dt / 1e9, 4), "unit": "equivalent GPop/s",
+           "executed_gpops": round(sum(d[1] for d in done) / dt / 1e9, 4),
+           "cores": int(min(threads, len(order))), "kind": "oracle", "nproc": cpu["nproc"],
+           "cpu_model": cpu["model"],
+           "sample": f"incremental evaluation (mother co-evaluated) of the {len(order)} children of the smallest "
+                     f"parents ({int(psz[kids.parent[order]].sum())} mother nodes) on all {T} cases, {dt:.1f} s"}
+    if gpu_fit is not None:
+        out["sample_equals_gpu"] = bool(all(
+            (res[i][3] == gpu_fit[i] or (np.isnan(res[i][3]) and np.isnan(gpu_fit[i]))) and
+            res[i][1] == gpu_stop[i] for i in order))
+    return out
+
+
+def measure_config(ctx, g, name, threads, cpu, cpu_budget_s, no_cpu=False):
+    """One full-evaluation configuration on its own: autotuned batched launch
+    (graph replay) against one launch per tree, the interpreter kernel's
+    roofline, and the oracle on 1 core and on `threads` cores."""
+    t0 = time.perf_counter()
+    pop, cases, _, desc = workload_inputs(name, 1.0, threads)
+    vtype = g.GP_BOOL if desc["value_type"] == "bool" else g.GP_F32
+    T = cases.T
+    n = pop.n_trees
+    total = int(pop.sizes().sum())
+    if vtype == g.GP_BOOL:
+        ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, T)
+    else:
+        ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+    t1 = time.perf_counter()
+    ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs)
+    load_s = time.perf_counter() - t1
+    v, _ = ctx.autotune(ph, ch)
+    info = ctx.population_info(ph)
+    _, fit, st = ctx.evaluate_full(ph, ch, vtype, n, T, roots=False)
+    reps = 50 if total * T < 10**9 else 10
+    bms, wms = [], []
+    for _ in range(reps):
+        _, _, st = ctx.evaluate_full(ph, ch, vtype, n, T, roots=False, device=True)
+        bms.append(st["device_ms"])
+        wms.append(st["wall_ms"])
+    batched_ms = float(np.median(bms))
+    kms = [ctx.evaluate_full(ph, ch, vtype, n, T, roots=False, graph=False)[2]["kernel_ms"] for _ in range(5)]
+    kernel_ms = float(np.median(kms))
+    pts = [ctx.evaluate_full(ph, ch, vtype, n, T, roots=False, per_tree=True, graph=False)[2]["device_ms"]
+           for _ in range(2 if total * T < 10**10 else 1)]
+    per_tree_ms = float(min(pts))
+    func_nodes = (total - n) // 2
+    achieved = func_nodes * T / (kernel_ms * 1e-3)
+    out = {**desc, "total_nodes": total, "chunk_nodes": info["chunk_nodes"], "variant": g.variant_names()[v],
+           "host_load_s": round(load_s, 3),
+           "batched_ms": round(batched_ms, 4), "batched_wall_ms": round(float(np.median(wms)), 4),
+           "per_tree_ms": round(per_tree_ms, 3), "batched_speedup": round(per_tree_ms / batched_ms, 1),
+           "equivalent_gpops": round(total * T / (batched_ms * 1e-3) / 1e9, 2),
+           "roofline": {"bound": "alu", "kernel": "k_eval_" + ("bool" if vtype == g.GP_BOOL else "f32") + "_tbl",
+                        "kernel_ms": round(kernel_ms, 4), "achieved": round(achieved / 1e12, 4),
+                        "peak": round(PEAK_FP32_LANE_OPS / 1e12, 2), "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_FP32_LANE_OPS, 4), "traffic": None}}
+    if vtype == g.GP_BOOL:
+        out["roofline"]["unit"] = "Tbit-op/s"
+        out["roofline"]["note"] = ("one 64-bit word operation per function node evaluates 64 cases; achieved counts "
+                                   "function nodes x cases against the 32-bit lane-op issue rate")
+    if not no_cpu:
+        out["cpu_1core"] = oracle_full(pop, cases, pop.vtype, 1, cpu_budget_s, cpu, gpu_fit=fit)
+        out["cpu_baseline"] = oracle_full(pop, cases, pop.vtype, threads, cpu_budget_s, cpu, gpu_fit=fit)
+    ctx.free(ph)
+    ctx.free(ch)
+    out["bench_s"] = round(time.perf_counter() - t0, 1)
+    log(f"[config] {desc['workload']}: {out}")
+    return out
 
 
 def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, load=0.8):
@@ -222,9 +371,14 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the population size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--compare", action="store_true",
-                    help="also time per-tree launches and full re-evaluation of the children")
-    ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip per-tree launches and the full re-evaluation of the built children")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the small, Boolean and large full-evaluation configurations")
+    ap.add_argument("--cpu-budget", type=float, default=4.0,
+                    help="seconds of oracle work per thread for each configuration's CPU baselines")
+    # the host's CPU share for one GPU is 16 threads, whatever nproc shows
+    ap.add_argument("--threads", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--serve-jobs", type=int, default=2000, help="served-stream jobs (0 = skip serving)")
     ap.add_argument("--generations", type=int, default=2, help="generations of the evolution leg (0 = skip)")
     ap.add_argument("--chunk-nodes", type=int, default=0, help="fix the chunk size (0 = automatic / tuned)")
@@ -313,6 +467,13 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed / args.steps * 1e3
+
+    # host copies of the results, for comparison with the oracle's samples
+    _, gfit, _ = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False)
+    inc_fit = None
+    if kids is not None:
+        _, inc_fit, _ = ctx.evaluate_incremental(ph, ch, vtype, T, kids.parent, kids.point, kids.donors.ops,
+                                                 kids.donors.offsets, roots=False)
 
     equiv_nodes = total_nodes
     interp_nodes = total_nodes
@@ -438,18 +599,38 @@ def main():
                                "max_strahler": max_sn, "host_load_s": round(load_s, 2),
                                "note": "host_load_s: validation, compilation and upload of the same trees on the host"}
 
-    if args.compare:
-        _, _, st_pt = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, per_tree=True)
-        extra["per_tree_launch_ms"] = st_pt["device_ms"]
-        _, _, st_b = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False)
-        extra["batched_launch_ms"] = st_b["device_ms"]
+    # the two legs of the step, each timed on its own (HIP events on the library stream)
+    bms = [ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, device=True, fit_buf=fit_buf)[2]["device_ms"]
+           for _ in range(5)]
+    batched_ms = float(np.median(bms))
+    legs = {"parents_full_evaluation": {"trees": n_trees, "nodes": total_nodes, "device_ms": round(batched_ms, 3),
+                                        "equivalent_gpops": round(total_nodes * T / (batched_ms * 1e-3) / 1e9, 1)}}
+    if kids is not None:
+        legs["children_incremental"] = {
+            "children": int(len(kids.parent)), "nodes": int(inc_stats["child_nodes"].sum()),
+            "device_ms": round(inc_stats["device_ms"], 3),
+            "equivalent_gpops": round(extra["incremental"]["equivalent_gpops"], 1),
+            "interpreted_gpops": round(extra["incremental"]["interpreted_gpops"], 1)}
+    extra["legs"] = legs
+    if not args.no_compare:
+        log("[bench] one launch per tree ...")
+        _, _, st_pt = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, per_tree=True, graph=False)
+        extra["compare"] = {"batched_launch_ms": round(batched_ms, 3), "per_tree_launch_ms": round(st_pt["device_ms"], 3),
+                            "batched_speedup": round(st_pt["device_ms"] / batched_ms, 1)}
         if kids is not None:
+            log("[bench] full re-evaluation of the built children ...")
             n_kids = len(child_offs) - 1
+            t_c = time.perf_counter()
             cph = ctx.load_population(vtype, child_ops.cpu().numpy(), child_offs, n_inputs=pop.n_inputs)
-            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, n_kids, T, roots=False)
-            _, _, st_c = ctx.evaluate_full(cph, ch, vtype, n_kids, T, roots=False)
-            extra["children_full_reeval_ms"] = st_c["device_ms"]
-            extra["children_full_reeval_gpops"] = int(child_offs[-1]) * T / (st_c["device_ms"] * 1e-3) / 1e9
+            c_load_s = time.perf_counter() - t_c
+            ctx.autotune(cph, ch)
+            rms = [ctx.evaluate_full(cph, ch, vtype, n_kids, T, roots=False)[2]["device_ms"] for _ in range(3)]
+            reeval_ms = float(np.median(rms))
+            inc_ms = inc_stats["device_ms"]
+            extra["compare"].update({
+                "children_full_reeval_ms": round(reeval_ms, 3), "children_incremental_ms": round(inc_ms, 3),
+                "incremental_speedup": round(reeval_ms / inc_ms, 1), "children_host_load_s": round(c_load_s, 2),
+                "children_full_reeval_gpops": round(int(child_offs[-1]) * T / (reeval_ms * 1e-3) / 1e9, 1)})
             ctx.free(cph)
     del child_ops
 
@@ -475,10 +656,22 @@ def main():
         ctx.free(ph)
         serving = serve_bench(ctx, g, args.serve_jobs, args.threads)
 
-    cpu = None
+    hostcpu = host_cpu()
+    configs = None
+    if not args.no_configs and args.workload == "incremental":
+        configs = {}
+        for name, key in (("small", "small_ramped"), ("boolean", "boolean_parity6"), ("full_large", "full_large")):
+            log(f"[bench] configuration {key} ...")
+            configs[key] = measure_config(ctx, g, name, args.threads, hostcpu, args.cpu_budget, args.no_cpu_baseline)
+
+    cpu = cpu1 = cpu_inc = None
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(pop, cases, kids, pop.vtype, args.threads)
+        log("[bench] timing the CPU oracle on bounded samples ...")
+        cpu = oracle_full(pop, cases, pop.vtype, args.threads, 10.0, hostcpu, gpu_fit=gfit)
+        cpu1 = oracle_full(pop, cases, pop.vtype, 1, 8.0, hostcpu, gpu_fit=gfit)
+        if kids is not None:
+            cpu_inc = oracle_incremental(pop, cases, kids, args.threads, hostcpu, gpu_fit=inc_fit,
+                                         gpu_stop=inc_stats["stop_level"])
 
     value = equiv_nodes * T / (ms_per_step * 1e-3) / 1e9
     out = {
@@ -498,9 +691,15 @@ def main():
                    "parallelism": "single_gpu"},
         "interpreted_gpops": round(interp_nodes * T / (ms_per_step * 1e-3) / 1e9, 3),
         "host_load_s": round(load_s, 2),
+        "value_note": "equivalent GPop/s of the whole step: (parent nodes + child nodes) x cases / step time; the "
+                      "two legs' own rates are under legs",
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_1core": cpu1,
+        "cpu_incremental": cpu_inc,
+        "host_cpu": hostcpu,
         **extra,
+        "configs": configs,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

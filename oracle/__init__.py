@@ -67,6 +67,8 @@ def lib():
                                           i32p, i64p, f64p]
         h.orc_incremental_bool.argtypes = [u8p, L, L, u8p, L, C.c_int, u64p, u64p, L, L, u64p,
                                            i32p, i64p, i64p]
+        h.orc_population_f32.argtypes = [u8p, i64p, i64p, L, C.c_int, f32p, f32p, L, f64p]
+        h.orc_population_bool.argtypes = [u8p, i64p, i64p, L, C.c_int, u64p, u64p, L, L, i64p]
         u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
         h.orc_philox.argtypes = [u32p, u32p, u32p]
         h.orc_uniform.argtypes = [C.c_uint32, C.c_uint64]
@@ -215,6 +217,28 @@ def incremental_bool(parent, c: int, donor, inputs, target, T: int):
 
 
 # ----------------------------------------------------------- population helpers
+def population_fitness(pop, which, cases, T=None):
+    """Fitness of trees `which` of a population (float32 cases: .x/.y;
+    Boolean: .inputs/.target/.T), evaluated one after another in C."""
+    which = np.ascontiguousarray(which, np.int64)
+    ops = _u8(pop.ops)
+    offs = np.ascontiguousarray(pop.offsets, np.int64)
+    if hasattr(cases, "x"):
+        x = np.ascontiguousarray(np.atleast_2d(cases.x), np.float32)
+        y = np.ascontiguousarray(cases.y, np.float32)
+        fit = np.empty(len(which), np.float64)
+        rc = lib().orc_population_f32(ops, offs, which, len(which), x.shape[0], x, y, x.shape[1], fit)
+    else:
+        inp = np.ascontiguousarray(cases.inputs, np.uint64)
+        tg = np.ascontiguousarray(cases.target, np.uint64)
+        fit = np.empty(len(which), np.int64)
+        rc = lib().orc_population_bool(ops, offs, which, len(which), inp.shape[0], inp, tg, inp.shape[1],
+                                       cases.T if T is None else T, fit)
+    if rc != 0:
+        raise ValueError(f"oracle population evaluation failed ({rc})")
+    return fit
+
+
 def eval_population_f32(pop, x, y, threads: int = 1):
     """Evaluate every tree; several independent single-threaded oracle
     instances when threads > 1 (ctypes releases the GIL during each call)."""

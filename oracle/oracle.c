@@ -341,6 +341,50 @@ int64_t orc_fitness_bool(const uint64_t* out, const uint64_t* target, int64_t W,
     return hits;
 }
 
+/* ------------------------------------------------------------- population */
+
+/* Full evaluation and fitness (Section 4.2) of the listed trees of a
+ * population, tree which[k] being ops[offsets[which[k]] .. offsets[which[k] + 1]),
+ * one after another: the loop a caller would otherwise write around
+ * orc_eval_f32 and orc_fitness_f32 (orc_eval_bool and orc_fitness_bool).
+ * fit[k] receives tree which[k]'s fitness. */
+int orc_population_f32(const uint8_t* ops, const int64_t* offsets, const int64_t* which, int64_t n_which,
+                       int n_inputs, const float* inputs, const float* y, int64_t T, double* fit)
+{
+    float* out = (float*)malloc(sizeof(float) * (size_t)T);
+    if (!out) return ORC_ENOMEM;
+    for (int64_t k = 0; k < n_which; ++k) {
+        const int64_t s = offsets[which[k]], e = offsets[which[k] + 1];
+        int rc = orc_eval_f32(ops + s, e - s, n_inputs, inputs, T, out);
+        if (rc != ORC_OK) {
+            free(out);
+            return rc;
+        }
+        fit[k] = orc_fitness_f32(out, y, T);
+    }
+    free(out);
+    return ORC_OK;
+}
+
+int orc_population_bool(const uint8_t* ops, const int64_t* offsets, const int64_t* which, int64_t n_which,
+                        int n_inputs, const uint64_t* inputs, const uint64_t* target, int64_t W, int64_t T,
+                        int64_t* fit)
+{
+    uint64_t* out = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)W);
+    if (!out) return ORC_ENOMEM;
+    for (int64_t k = 0; k < n_which; ++k) {
+        const int64_t s = offsets[which[k]], e = offsets[which[k] + 1];
+        int rc = orc_eval_bool(ops + s, e - s, n_inputs, inputs, W, out);
+        if (rc != ORC_OK) {
+            free(out);
+            return rc;
+        }
+        fit[k] = orc_fitness_bool(out, target, W, T);
+    }
+    free(out);
+    return ORC_OK;
+}
+
 /* -------------------------------------------------------------- crossover */
 
 /* Figure 1: child = P[0:c] ++ D ++ P[end(c):].  Returns the child's length,

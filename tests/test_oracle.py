@@ -539,3 +539,23 @@ def test_evolve_invariants_small():
             out = oracle.eval_f32(t, cases.x)
             got = oracle.fitness_f32(out, cases.y)
             assert got == f or (math.isnan(got) and math.isnan(f))        # incremental = full evaluation
+
+
+def test_population_loop_equals_per_tree_calls():
+    """orc_population_* is the plain loop over trees: each listed tree's
+    fitness equals eval + fitness of that tree alone (in any order, repeats
+    allowed)."""
+    pop = gen.sized_population(91, 12, 1, 2001)
+    cases = gen.float_cases(92, 100)
+    which = np.array([3, 0, 11, 3, 7], np.int64)
+    got = oracle.population_fitness(pop, which, cases)
+    for k, t in enumerate(which):
+        with np.errstate(all="ignore"):
+            w = oracle.fitness_f32(oracle.eval_f32(pop.tree(int(t)), cases.x), cases.y)
+        assert got[k] == w or (np.isnan(got[k]) and np.isnan(w))
+    bc = gen.bool_cases(7)
+    bpop = gen.sized_population(93, 9, 1, 901, n_terms=7, vtype=gen.VT_BOOL)
+    which = np.arange(9)[::-1].copy()
+    got = oracle.population_fitness(bpop, which, bc)
+    for k, t in enumerate(which):
+        assert got[k] == oracle.fitness_bool(oracle.eval_bool(bpop.tree(int(t)), bc.inputs), bc.target, bc.T)
