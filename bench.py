@@ -263,23 +263,78 @@ def measure_config(ctx, g, name, threads, cpu, cpu_budget_s, no_cpu=False):
     return out
 
 
-def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, load=0.8):
+def oracle_stream(jobs, cases_of, threads, budget_s, cpu):
+    """The oracle on the first jobs of the served stream (arrival order), as
+    `threads` independent single-threaded instances taking jobs from a shared
+    queue: a full job is the tree's evaluation and fitness, an incremental
+    child the oracle's bottom-up evaluation with its mother co-evaluated."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    # about budget_s of work per thread at ~1e8 node-cases/s (the oracle's float rate on this host class);
+    # a job that alone would take more than half of that on one thread is left out of the sample
+    rate = 1.0e8
+    target = budget_s * rate * threads
+    chosen, skipped, tot = [], 0, 0
+    for i, j in enumerate(jobs):
+        if tot >= target:
+            break
+        n = len(j.ops) if j.kind == 0 else len(jobs[j.parent].ops) + len(j.ops)
+        cost = n * (j.T if j.vtype == gen.VT_F32 else (j.T + 63) // 64)
+        if cost > 0.5 * budget_s * rate:
+            skipped += 1
+            continue
+        chosen.append(i)
+        tot += cost
+
+    def one(i):
+        j = jobs[i]
+        c = cases_of[(j.vtype, j.T)]
+        if j.kind == 0:
+            if j.vtype == gen.VT_BOOL:
+                oracle.fitness_bool(oracle.eval_bool(j.ops, c.inputs), c.target, j.T)
+            else:
+                with np.errstate(all="ignore"):
+                    oracle.fitness_f32(oracle.eval_f32(j.ops, c.x), c.y)
+            return len(j.ops) * j.T
+        P = jobs[j.parent].ops
+        if j.vtype == gen.VT_BOOL:
+            oracle.incremental_bool(P, j.point, j.ops, c.inputs, c.target, j.T)
+        else:
+            with np.errstate(all="ignore"):
+                oracle.incremental_f32(P, j.point, j.ops, c.x, c.y)
+        return (len(P) - (gen.subtree_end(P, j.point) - j.point) + len(j.ops)) * j.T
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        eq = sum(ex.map(one, sorted(chosen, key=lambda i: -len(jobs[i].ops))))
+    dt = time.perf_counter() - t0
+    return {"jobs_per_s": round(len(chosen) / dt, 2), "equivalent_gpops": round(eq / dt / 1e9, 3),
+            "cores": threads, "kind": "oracle", "nproc": cpu["nproc"], "cpu_model": cpu["model"],
+            "sample": f"{len(chosen)} of the first {len(chosen) + skipped} jobs of the stream in arrival order "
+                      f"(left out: {skipped} jobs above {0.5 * budget_s * rate:.0e} node-cases), {dt:.1f} s"}
+
+
+def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, loads=(0.5, 0.8, 0.95), cpu=None, oracle_s=8.0):
     """Served mixed stream: full jobs (kept resident as parents) and
     incremental children arriving over time; continuous batching in the
-    library's server.  Returns throughput and latency percentiles."""
+    library's server.  All jobs at once (saturation), then Poisson arrivals at
+    the given fractions of the saturation rate.  Returns throughput, latency
+    percentiles and where the latency goes."""
     t0 = time.perf_counter()
-    jobs = gen.served_stream(5, n_jobs)
+    jobs = gen.served_stream(5, n_jobs, threads=threads)
     log(f"[serve] generated {n_jobs} jobs in {time.perf_counter() - t0:.1f} s")
-    handles = {}
+    handles, cases_of = {}, {}
     for j in jobs:
         key = (j.vtype, j.T)
         if key not in handles:
             if j.vtype == gen.VT_BOOL:
                 bc = gen.bool_cases(j.T.bit_length() - 1)
                 handles[key] = ctx.set_cases(g.GP_BOOL, bc.inputs, bc.target, j.T)
+                cases_of[key] = bc
             else:
                 fc = gen.float_cases(j.T, j.T)
                 handles[key] = ctx.set_cases(g.GP_F32, fc.x, fc.y)
+                cases_of[key] = fc
     equiv = np.zeros(len(jobs), np.int64)
     for i, j in enumerate(jobs):
         if j.kind == 0:
@@ -287,23 +342,29 @@ def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, load=0.8):
         else:
             p = jobs[j.parent].ops
             equiv[i] = (len(p) - (gen.subtree_end(p, j.point) - j.point) + len(j.ops)) * j.T
+    base_mem = ctx.memory_used
 
     def run(rate):
         ctx.server_start(n_streams=4, max_batch_jobs=64, prep_threads=threads, budget_bytes=int(budget_gb * 2**30))
         tickets = [0] * len(jobs)
         done = {}
         pending = []
+        peak = [0]
         t_start = time.perf_counter()
+
+        def sweep():
+            peak[0] = max(peak[0], ctx.memory_used - base_mem)
+            return [k for k in pending if not collect(k, done, tickets)]
+
         for i, j in enumerate(jobs):
             if rate:
                 wait_s = j.arrival / rate - (time.perf_counter() - t_start)
                 while wait_s > 0:
                     # collect finished jobs while waiting for the next arrival
-                    pending = [k for k in pending if not collect(k, done, tickets)]
+                    pending = sweep()
                     wait_s = j.arrival / rate - (time.perf_counter() - t_start)
                     if wait_s > 0.0005:
                         time.sleep(min(wait_s, 0.0005))
-            vt = g.GP_BOOL if j.vtype == gen.VT_BOOL else g.GP_F32
             if j.kind == 0:
                 tickets[i] = ctx.server_submit(g.GP_JOB_FULL, handles[(j.vtype, j.T)], j.ops,
                                                record_points=j.points, keep_resident=True)
@@ -312,14 +373,14 @@ def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, load=0.8):
                                                parent_ticket=tickets[j.parent], point=j.point)
             pending.append(i)
         while pending:
-            pending = [k for k in pending if not collect(k, done, tickets)]
+            pending = sweep()
             time.sleep(0.0002)
         wall = time.perf_counter() - t_start
         for i, j in enumerate(jobs):
             if j.kind == 0:
                 ctx.server_release(tickets[i])
         ctx.server_stop()
-        return done, wall
+        return done, wall, peak[0]
 
     def collect(i, done, tickets):
         j = jobs[i]
@@ -329,36 +390,45 @@ def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, load=0.8):
         done[i] = r
         return True
 
-    def summary(done, wall):
-        lat_full = np.array([done[i]["latency_ms"] for i, j in enumerate(jobs) if j.kind == 0])
-        lat_inc = np.array([done[i]["latency_ms"] for i, j in enumerate(jobs) if j.kind == 1])
+    def summary(done, wall, peak):
+        def pct(key, sel):
+            v = np.array([done[i][key] for i, j in enumerate(jobs) if sel(j)])
+            return {"mean": round(float(v.mean()), 3), "p50": round(float(np.percentile(v, 50)), 3),
+                    "p99": round(float(np.percentile(v, 99)), 3)}
         lat = np.array([done[i]["latency_ms"] for i in range(len(jobs))])
         bad = sum(1 for r in done.values() if r["status"] != 0)
-        queue = np.array([done[i]["queue_ms"] for i in range(len(jobs))])
+        full = [j.kind == 0 for j in jobs]
         return {"jobs": len(jobs), "failed": bad, "wall_s": round(wall, 3),
-                "mean_queue_ms": round(float(queue.mean()), 3),          # submit to admission (includes compiling)
-                "mean_run_ms": round(float((lat - queue).mean()), 3),    # admission to completion
                 "jobs_per_s": round(len(jobs) / wall, 1),
                 "equivalent_gpops": round(float(equiv.sum()) / wall / 1e9, 1),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "full_p50_ms": round(float(np.percentile(lat_full, 50)), 3),
-                "full_p99_ms": round(float(np.percentile(lat_full, 99)), 3),
-                "incremental_p50_ms": round(float(np.percentile(lat_inc, 50)), 3),
-                "incremental_p99_ms": round(float(np.percentile(lat_inc, 99)), 3)}
+                "full_p50_ms": round(float(np.percentile(lat[full], 50)), 3),
+                "full_p99_ms": round(float(np.percentile(lat[full], 99)), 3),
+                "incremental_p50_ms": round(float(np.percentile(lat[~np.array(full)], 50)), 3),
+                "incremental_p99_ms": round(float(np.percentile(lat[~np.array(full)], 99)), 3),
+                # where a job's latency goes: prep threads (validate, compile), waiting for admission,
+                # its batch's host work (assembly, upload, launches), device work and copy-out
+                "split_ms": {k: pct(k, lambda j: True) for k in ("prep_ms", "queue_ms", "launch_ms", "run_ms")},
+                "peak_device_gb": round(peak / 2**30, 2)}
 
-    done, wall = run(None)
-    sat = summary(done, wall)
-    log(f"[serve] saturation: {sat}")
-    rate = load * len(jobs) / wall / max(1e-9, jobs[-1].arrival / len(jobs))
-    done, wall = run(rate)
-    at_load = summary(done, wall)
-    log(f"[serve] at {load:.2f} x saturation: {at_load}")
+    out = {"stream": f"{n_jobs} jobs, 30% full (resident parents, 3 recorded points) / 70% incremental; "
+                     "10..1e7 nodes log-uniform; float32 or Boolean 50/50; 256..4096 cases; donors 1..1e4 nodes, "
+                     "half neutral; budget 200 GB",
+           "parent_nodes": int(sum(len(j.ops) for j in jobs if j.kind == 0))}
+    done, wall, peak = run(None)
+    out["saturation"] = summary(done, wall, peak)
+    log(f"[serve] saturation: {out['saturation']}")
+    for load in loads:
+        rate = load * len(jobs) / wall / max(1e-9, jobs[-1].arrival / len(jobs))
+        d2, w2, p2 = run(rate)
+        out[f"poisson_{load:.2f}x"] = summary(d2, w2, p2)
+        log(f"[serve] at {load:.2f} x saturation: {out[f'poisson_{load:.2f}x']}")
     for h in handles.values():
         ctx.free(h)
-    return {"stream": f"{n_jobs} jobs, 30% full (resident parents, 3 recorded points) / 70% incremental; "
-                      "10..1e7 nodes log-uniform; float32 or Boolean 50/50; 256..4096 cases; donors 1..1e4 nodes, "
-                      "half neutral; budget 200 GB",
-            "saturation": sat, f"poisson_{load:.2f}x": at_load}
+    if cpu is not None:
+        out["cpu_baseline"] = oracle_stream(jobs, cases_of, threads, oracle_s, cpu)
+        log(f"[serve] oracle on the stream: {out['cpu_baseline']}")
+    return out
 
 
 def main():
@@ -379,7 +449,8 @@ def main():
                     help="seconds of oracle work per thread for each configuration's CPU baselines")
     # the host's CPU share for one GPU is 16 threads, whatever nproc shows
     ap.add_argument("--threads", type=int, default=min(16, len(os.sched_getaffinity(0))))
-    ap.add_argument("--serve-jobs", type=int, default=2000, help="served-stream jobs (0 = skip serving)")
+    ap.add_argument("--serve-jobs", type=int, default=20000, help="served-stream jobs (0 = skip serving)")
+    ap.add_argument("--serve-only", action="store_true", help="run the served stream alone")
     ap.add_argument("--generations", type=int, default=2, help="generations of the evolution leg (0 = skip)")
     ap.add_argument("--chunk-nodes", type=int, default=0, help="fix the chunk size (0 = automatic / tuned)")
     ap.add_argument("--variant", default="", help="fix the interpreter variant, e.g. f32_k4_s16")
@@ -404,6 +475,15 @@ def main():
 
     import torch
     from paper_2205_03251_amd import gpeval as g
+
+    if args.serve_only:
+        torch.cuda.init()
+        ctx = g.Context(0)
+        hc = host_cpu()
+        res = serve_bench(ctx, g, args.serve_jobs, args.threads, cpu=None if args.no_cpu_baseline else hc)
+        print(json.dumps({"serving": res, "host_cpu": hc}), flush=True)
+        ctx.close()
+        return
 
     t0 = time.perf_counter()
     pop, cases, kids, desc = workload_inputs(args.workload, args.scale, args.threads)
@@ -654,7 +734,8 @@ def main():
     serving = None
     if args.serve_jobs > 0:
         ctx.free(ph)
-        serving = serve_bench(ctx, g, args.serve_jobs, args.threads)
+        serving = serve_bench(ctx, g, args.serve_jobs, args.threads,
+                              cpu=None if args.no_cpu_baseline else host_cpu())
 
     hostcpu = host_cpu()
     configs = None

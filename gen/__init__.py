@@ -342,12 +342,17 @@ class ServedJob:
 
 def served_stream(seed: int, n_jobs: int, full_frac: float = 0.3, node_lo: int = 10, node_hi: int = 10**7,
                   t_choices=(256, 512, 1024, 2048, 4096), bool_frac: float = 0.5, donor_hi: int = 10**4,
-                  points_per_parent: int = 3) -> list:
+                  points_per_parent: int = 3, threads: int = 1) -> list:
     """Jobs with exponential inter-arrival gaps (mean 1); a share full_frac of
     full jobs (kept resident as parents, each with crossover points drawn
     ahead), the rest incremental children of earlier parents with the same
     value type and case count; half of the children's donors neutral.
-    Boolean jobs with T cases use k = log2(T) inputs."""
+    Boolean jobs with T cases use k = log2(T) inputs.
+
+    The job list (kinds, sizes, points, parents) is drawn first from one
+    stream; then every tree is built from a seed stream of its own (parents,
+    then donors, which may copy a subtree of their parent), so the result does
+    not depend on the number of threads."""
     rng = rng_for(seed)
     jobs: list = []
     parents: dict = {}
@@ -356,30 +361,52 @@ def served_stream(seed: int, n_jobs: int, full_frac: float = 0.3, node_lo: int =
         t += float(rng.exponential(1.0))
         vtype = VT_BOOL if rng.random() < bool_frac else VT_F32
         T = int(t_choices[int(rng.integers(len(t_choices)))])
-        k = T.bit_length() - 1
-        n_terms = k if vtype == VT_BOOL else 1
         key = (vtype, T)
         if key not in parents or rng.random() < full_frac:
             n = int(log_uniform_odd(rng, node_lo, node_hi))
-            tree = sized_tree(rng, n, n_terms)
             pts = np.unique(rng.integers(n, size=points_per_parent)).astype(np.int64)
-            jobs.append(ServedJob(0, vtype, T, tree, t, points=pts))
+            jobs.append(ServedJob(0, vtype, T, np.empty(n, np.uint8), t, points=pts))
             parents.setdefault(key, []).append(len(jobs) - 1)
         else:
             pj = parents[key][int(rng.integers(len(parents[key])))]
-            ptree = jobs[pj].ops
             c = int(jobs[pj].points[int(rng.integers(len(jobs[pj].points)))])
             m = int(log_uniform_odd(rng, 1, donor_hi))
             neutral = rng.random() < 0.5
-            donor = None
-            if neutral:
-                e = subtree_end(ptree, c, max_len=max(1, m - 4))
-                if e > 0:
-                    S = ptree[c:e].copy()
-                    donor = neutral_donor(rng, S, m) if vtype == VT_F32 else bool_neutral_donor(rng, S, m, n_terms)
-                else:
-                    neutral = False
-            if donor is None:
-                donor = sized_tree(rng, m, n_terms)
-            jobs.append(ServedJob(1, vtype, T, donor, t, parent=pj, point=c, neutral=neutral))
+            jobs.append(ServedJob(1, vtype, T, np.empty(m, np.uint8), t, parent=pj, point=c, neutral=neutral))
+    seqs = np.random.SeedSequence([seed, n_jobs]).spawn(n_jobs)
+
+    def n_terms(j):
+        return j.T.bit_length() - 1 if j.vtype == VT_BOOL else 1
+
+    def build_parent(i):
+        j = jobs[i]
+        j.ops = sized_tree(np.random.default_rng(seqs[i]), len(j.ops), n_terms(j))
+
+    def build_donor(i):
+        j = jobs[i]
+        r = np.random.default_rng(seqs[i])
+        m = len(j.ops)
+        donor = None
+        if j.neutral:
+            ptree = jobs[j.parent].ops
+            e = subtree_end(ptree, j.point, max_len=max(1, m - 4))
+            if e > 0:
+                S = ptree[j.point:e].copy()
+                donor = neutral_donor(r, S, m) if j.vtype == VT_F32 else bool_neutral_donor(r, S, m, n_terms(j))
+            else:
+                j.neutral = False
+        j.ops = donor if donor is not None else sized_tree(r, m, n_terms(j))
+
+    full = sorted((i for i, j in enumerate(jobs) if j.kind == 0), key=lambda i: -len(jobs[i].ops))
+    inc = [i for i, j in enumerate(jobs) if j.kind == 1]
+    if threads > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(build_parent, full))
+            list(ex.map(build_donor, inc))
+    else:
+        for i in full:
+            build_parent(i)
+        for i in inc:
+            build_donor(i)
     return jobs
