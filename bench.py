@@ -724,11 +724,13 @@ def main():
             "ms_score_build_eval": [[round(x["ms_score"], 1), round(x["ms_build"], 1), round(x["ms_eval"], 1)]
                                     for x in gstats],
             "built_fraction": [round(x["built"] / x["children"], 4) for x in gstats],
+            "chunks_evaluated_of_built": [[int(x["chunks_evaluated"]), int(x["chunks"])] for x in gstats],
             "child_nodes": [int(x["child_nodes"]) for x in gstats],
             "interpreted_nodes": [int(x["interpreted_nodes"]) for x in gstats],
             "best_error": [x["best_f64"] if vtype == g.GP_F32 else int(x["best_i64"]) for x in gstats],
             "note": "the last generation builds all children; building includes the children's programs, made "
-                    "from their parents' chunks"}
+                    "from their parents' chunks; evaluating them runs only the chunks compiled anew, the reused ones "
+                    "take their parents' values"}
         ctx.free(nh)
 
     serving = None

@@ -201,6 +201,13 @@ int gp_free(gp_ctx* ctx, gp_handle h);
 /* Full evaluation (Section 4.2) of every tree on every case of `cases`, in
  * one persistent work-stealing launch (or one launch per tree with
  * GP_PER_TREE).  Records the parent caches requested at load time.
+ * The crossover points whose parent caches are recorded are fixed when the
+ * population is loaded (gp_load_population's record_points), not passed
+ * here: recording is compiled into the programs, a STORE after the point,
+ * each ancestor and each ancestor's other operand.  New points therefore
+ * need a new load; a child at a point that was not recorded is evaluated
+ * with GP_COEVAL instead (gp_evaluate_incremental_batch), which needs no
+ * cache.
  * root_out: [n_trees][T] float32 or [n_trees][W] uint64, or NULL.
  * fitness_out: [n_trees] double (GP_F32) or int64 (GP_BOOL), or NULL.
  * st: optional statistics. */
@@ -278,7 +285,10 @@ typedef struct gp_gen_stats {
     double ms;                 /* wall time of the generation, of which: */
     double ms_score;           /*   drawing parents and points, scoring the children, drawing the next tournaments */
     double ms_build;           /*   building the drawn children: bytes on the device and the host, programs */
-    double ms_eval;            /*   evaluating the built children in full (the next generation's caches) */
+    double ms_eval;            /*   evaluating the built children (the next generation's chunk values): chunks
+                                    reused from a parent take that parent chunk's values, the rest run */
+    int64_t chunks;            /* chunks of the built children */
+    int64_t chunks_evaluated;  /* of which compiled anew and run (the others are reused) */
 } gp_gen_stats;
 
 typedef struct gp_gen_child {
@@ -312,6 +322,14 @@ typedef struct gp_gen_child {
  * cfg->generations * N records, or NULL. */
 int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* cfg, gp_gen_stats* stats,
               gp_gen_child* children, gp_handle* out_pop);
+
+/* The results of a population's last full evaluation (gp_evaluate_full,
+ * or the evaluation gp_evolve ends with), without evaluating again: root_out
+ * [n_trees][T] float32 or [n_trees][W] uint64, fitness_out [n_trees] double
+ * or int64 (either may be NULL), host memory or, with GP_DEVICE_PTR, device
+ * memory.  GP_ENOTFOUND if that evaluation was not on `cases`. */
+int gp_population_results(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags, void* root_out,
+                          void* fitness_out);
 
 /* The trees of a population, as loaded (host memory): offsets_out gets
  * n_trees + 1 entries; ops_out (may be NULL to get the offsets only) gets

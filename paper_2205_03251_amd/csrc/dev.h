@@ -261,5 +261,8 @@ hipError_t launch_mark(const MarkParams& p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gather_rows(const void* src, const int64_t* src_rows, int64_t n_rows, int64_t row_bytes, void* dst,
                               hipStream_t s);
+// Row rows[2k] of dst = row rows[2k + 1] of src, k < n_rows (rows of row_bytes, a multiple of 16).
+hipError_t launch_move_rows(const void* src, const int64_t* rows, int64_t n_rows, int64_t row_bytes, void* dst,
+                            hipStream_t s);
 
 }  // namespace gpe

@@ -1142,6 +1142,29 @@ hipError_t launch_gather_rows(const void* src, const int64_t* src_rows, int64_t 
     return hipGetLastError();
 }
 
+// Row rows[2k] of dst = row rows[2k + 1] of src: the values of chunks a child
+// reuses from its parents, moved from the parents' chunk vectors.  Each
+// workgroup moves whole rows, one 16-byte word per thread per step.
+__global__ __launch_bounds__(256) void k_move_rows(const uint4* src, const int64_t* rows, int64_t n_rows, uint4* dst,
+                                                   int64_t row_u4)
+{
+    for (int64_t k = blockIdx.x; k < n_rows; k += gridDim.x) {
+        const int64_t d = rows[2 * k], r = rows[2 * k + 1];
+        for (int64_t i = threadIdx.x; i < row_u4; i += 256) dst[d * row_u4 + i] = src[r * row_u4 + i];
+    }
+}
+
+hipError_t launch_move_rows(const void* src, const int64_t* rows, int64_t n_rows, int64_t row_bytes, void* dst,
+                            hipStream_t s)
+{
+    if (n_rows <= 0) return hipSuccess;
+    if (row_bytes % 16 != 0) return hipErrorInvalidValue;
+    const int64_t grid = std::min<int64_t>(n_rows, 65536);
+    hipLaunchKernelGGL(k_move_rows, dim3((unsigned)grid), dim3(256), 0, s, (const uint4*)src, rows, n_rows,
+                       (uint4*)dst, row_bytes / 16);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- splice
 // Children are built from three contiguous byte ranges each (the mother's
 // nodes before the replaced subtree, the donor, the mother's nodes after it;

@@ -161,6 +161,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         return !is_func(ops[v]) && !external(v) && !opaque(v) && (boolean || ops[v] == 0);
     };
     auto full = [&](int64_t v) { return col != nullptr ? col->node_map[v] : v; };
+    auto forced = [&](int64_t v) { return col != nullptr && col->cut_at != nullptr && col->cut_at[v] != 0; };
     const int32_t id_base = col != nullptr ? col->id_base : 0;
     if (col != nullptr && n_points > 0) {
         if (why) *why = "record points in a collapsed tree";
@@ -235,7 +236,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         }
         int64_t o = 1 + (cut[l] ? 1 : open[l]) + (cut[r] ? 1 : open[r]);
         open[i] = (int32_t)std::min<int64_t>(o, INT32_MAX);
-        if (o >= C && i != 0) {
+        if ((o >= C || forced(i)) && i != 0) {
             cut[i] = 1;
             cuts.push_back(i);
         }
@@ -615,6 +616,7 @@ bool compose_child(const SrcTree& m, int64_t c, int64_t c_end, const SrcTree& f,
         ch.code_off = 0;
         ch.code_len = s.code_len;
         ch.dev_src = s.code_off;
+        ch.src_vec = s.vec_slot;
         ch.root_node = root;
         ch.end_node = end;
         ch.nodes = s.nodes;
@@ -682,7 +684,32 @@ bool compose_child(const SrcTree& m, int64_t c, int64_t c_end, const SrcTree& f,
             if (why) *why = "compose_child: overlapping chunks";
             return false;
         }
-        Collapsed col{opq.data(), nmap.data(), n_reused};
+        // Only the path from the point to the root must be evaluated anew;
+        // every subtree hanging off it that is not a reused chunk gets a chunk
+        // of its own when it is not small, so those run side by side and the
+        // chain of dependent chunks holds little more than the path itself.
+        const int64_t G = (int64_t)gops.size();
+        std::vector<int32_t> gend(G), gst;
+        gst.reserve(64);
+        for (int64_t v = G - 1; v >= 0; --v) {
+            if (gops[v] & kFuncBit && opq[v] < 0) {
+                gst.pop_back();
+                gend[v] = gend[gst.back()];
+                gst.pop_back();
+            } else {
+                gend[v] = (int32_t)(v + 1);
+            }
+            gst.push_back((int32_t)v);
+        }
+        std::vector<uint8_t> cut_at(G, 0);
+        const int64_t gp = std::upper_bound(nmap.begin(), nmap.end() - 1, c) - nmap.begin() - 1;   // glue node at c
+        for (int64_t v = 0; v != gp && v >= 0 && v < G && (gops[v] & kFuncBit) && opq[v] < 0;) {
+            const int64_t l = v + 1, r = gend[l];
+            const int64_t next = gp < r ? l : r, sib = next == l ? r : l;
+            if (opq[sib] < 0 && (gops[sib] & kFuncBit) && gend[sib] - sib >= kPathSiblingChunk) cut_at[sib] = 1;
+            v = next;
+        }
+        Collapsed col{opq.data(), nmap.data(), n_reused, cut_at.data()};
         TreeProg glue;
         if (!compile_tree(gops.data(), (int64_t)gops.size(), opt, nullptr, 0, &glue, why, nullptr, &col))
             return false;

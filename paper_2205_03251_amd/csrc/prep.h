@@ -45,6 +45,10 @@ constexpr int kPayloadShift = 10;
 constexpr uint32_t kKeyMask = 0x3ffu;
 constexpr uint32_t kMaxPayload = (1u << 22) - 1;
 constexpr int kMaxStackSlots = 32;
+// A child built from its parents' chunks: a subtree of at least this many
+// nodes hanging off the path from the crossover point to the root is
+// compiled as a chunk of its own (see compose_child).
+constexpr int64_t kPathSiblingChunk = 64;
 
 inline uint32_t ins_word(uint32_t f, uint32_t mode, uint32_t d, uint32_t payload)
 {
@@ -63,6 +67,9 @@ struct Chunk {
     int64_t dev_src = -1;        // >= 0: the code is not in TreeProg::code but at this word
                                  // offset of an already uploaded program (see compose_child)
     bool stores = false;         // records parent caches (STORE words)
+    int64_t vec_slot = -1;       // its vector slot in its population (chunks kept for children)
+    int64_t src_vec = -1;        // reused (dev_src >= 0): the vector slot of the chunk it copies in the
+                                 // population it comes from; its last values are this chunk's values
     std::vector<int32_t> inputs; // local chunk ids read by LOAD payload 0, 1, ...
 };
 
@@ -145,6 +152,8 @@ struct Collapsed {
     const int32_t* opaque;       // per node: -1, or the chunk id of a collapsed leaf
     const int64_t* node_map;
     int32_t id_base;
+    const uint8_t* cut_at = nullptr;  // per node (may be null): 1 = a function node that roots a chunk
+                                      // of its own whatever its size
 };
 
 // Compile one validated prefix tree.  points: crossover points (prefix

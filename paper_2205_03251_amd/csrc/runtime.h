@@ -151,6 +151,13 @@ struct Pop {
     // compiled with the subtree index), for building children from them
     std::vector<std::vector<Chunk>> kept_chunks;
     std::vector<int32_t> kept_max_stack;
+    // composed children (assemble_population with reused chunks): per chunk,
+    // the vector slot of the chunk it reuses in the population it comes from
+    // (-1: compiled anew), and its longest chunk chain to the tree root
+    std::vector<int64_t> promo_src;
+    std::vector<int32_t> promo_in;          // per chunk: how many of its inputs are reused chunks
+    std::vector<int64_t> promo_rows;        // (vector slot, source vector slot) of every reused chunk
+    std::vector<int64_t> chunk_path;
     // evaluation state
     int64_t stride = 0;                     // case stride of vecs/recs
     DevBuf vecs;                            // [n_chunks][stride]: roots are slots 0..n_trees-1
@@ -213,6 +220,13 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
                         hipStream_t s, const uint32_t* dev_code_src = nullptr);
 // Make sure vecs/recs/fit match the case set; allocate if needed.
 int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs);
+// Full evaluation of composed children (p->promo_src filled) whose reused
+// chunks take their values from src, the population their code comes from,
+// as src's last full evaluation on the same case set left them: those rows
+// of src->vecs are copied, and only the chunks compiled anew are evaluated.
+// Synchronises s.  n_evaluated (may be null) receives their number.
+int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const CaseSet* cs, int variant,
+                     hipStream_t s, int64_t* n_evaluated);
 // Enqueue a full evaluation on stream s (no copies out, no synchronisation).
 // time_kernel: record c->kev0/kev1 around the interpreter launch.
 int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int variant, bool per_tree,

@@ -280,11 +280,14 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
     // Chunks whose code is already on the device (dev_src, from
     // dev_code_src) are gathered after all host code.
     int64_t n_chunks = 0, n_code = 0, n_rec = 0, n_in = 0, n_lv = 0, n_dev = 0;
+    bool promo = false;
     for (auto& pg : progs) {
         n_chunks += (int64_t)pg.chunks.size();
         n_code += (int64_t)pg.code.size();
-        for (auto& ch : pg.chunks)
+        for (auto& ch : pg.chunks) {
             if (ch.dev_src >= 0) n_dev += ch.code_len;
+            if (ch.src_vec >= 0) promo = true;
+        }
         n_rec += pg.n_records;
         for (auto& ch : pg.chunks) n_in += (int64_t)ch.inputs.size();
         for (auto& sp : pg.spines) n_lv += (int64_t)sp.levels.size();
@@ -310,6 +313,15 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
     levels.reserve(n_lv);
     out->chunk_n_in.assign(n_chunks, 0);
     out->chunk_tree.assign(n_chunks, 0);
+    out->promo_src.clear();
+    out->promo_in.clear();
+    out->promo_rows.clear();
+    out->chunk_path.clear();
+    if (promo) {
+        out->promo_src.assign(n_chunks, -1);
+        out->promo_in.assign(n_chunks, 0);
+        out->chunk_path.assign(n_chunks, 0);
+    }
     out->rec_base.assign(n_trees, 0);
     out->leaves.clear();
     out->spines.clear();
@@ -355,6 +367,15 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
             for (int32_t in : ch.inputs) chunk_in.push_back(slot[in]);
             out->chunk_n_in[cbase + k] = (int32_t)ch.inputs.size();
             out->chunk_tree[cbase + k] = (int32_t)t;
+            if (promo) {
+                out->promo_src[cbase + k] = ch.src_vec;
+                out->chunk_path[cbase + k] = ch.path_nodes;
+                for (int32_t in : ch.inputs) out->promo_in[cbase + k] += pg.chunks[in].src_vec >= 0 ? 1 : 0;
+                if (ch.src_vec >= 0) {
+                    out->promo_rows.push_back(slot[k]);
+                    out->promo_rows.push_back(ch.src_vec);
+                }
+            }
             if (ch.inputs.empty()) out->leaves.emplace_back(ch.path_nodes, (int32_t)(cbase + k));
         }
         for (auto& sp : pg.spines) {
@@ -375,6 +396,8 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
             for (int64_t k = 0; k < nc; ++k) {
                 pg.chunks[k].code_off = dch[cbase + k].code_off;
                 pg.chunks[k].dev_src = -1;
+                pg.chunks[k].vec_slot = slot[k];
+                pg.chunks[k].src_vec = -1;
             }
             out->kept_chunks[t].swap(pg.chunks);
             out->kept_max_stack[t] = pg.max_stack;
@@ -581,6 +604,70 @@ int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int varia
         if (launches) *launches += 1;
     }
     p->evaluated_with = cases_h;
+    return GP_OK;
+}
+
+// Cache promotion for children built from their parents' chunks (Section 5,
+// Figure 1): a reused chunk runs its parent chunk's code on the same inputs
+// (its inputs are reused chunks too), so its values are that chunk's values
+// from the parents' last full evaluation.  Those rows are moved over, and a
+// plan of its own runs only the chunks compiled anew: a chunk whose inputs
+// are all reused is a leaf work item, and every dependency counter counts
+// only the inputs compiled anew.
+int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const CaseSet* cs, int variant,
+                     hipStream_t s, int64_t* n_evaluated)
+{
+    if (p->promo_src.size() != (size_t)p->n_chunks || p->promo_in.size() != (size_t)p->n_chunks)
+        return set_err(c, GP_EINVAL, "internal error: no record of reused chunks");
+    if (src->evaluated_with != cases_h || src->stride != cs->stride || !src->vecs.p)
+        return set_err(c, GP_EINVAL, "internal error: the parents hold no values for this case set");
+    RC(ensure_eval_buffers(c, p, cs));
+    const Variant& v = variant_table()[variant];
+    Plan pl;
+    pl.variant = variant;
+    pl.per_tree = false;
+    pl.n_slices = (int32_t)((cs->n_elems + kWave * v.K - 1) / (kWave * v.K));
+    std::vector<std::pair<int64_t, int32_t>> ready;
+    std::vector<int32_t> pend((size_t)p->n_chunks * pl.n_slices, 0);
+    int64_t n_eval = 0;
+    for (int64_t k = 0; k < p->n_chunks; ++k) {
+        if (p->promo_src[k] >= 0) continue;
+        ++n_eval;
+        const int32_t left = p->chunk_n_in[k] - p->promo_in[k];
+        for (int32_t sl = 0; sl < pl.n_slices; ++sl) pend[(size_t)k * pl.n_slices + sl] = left;
+        if (left == 0) ready.emplace_back(p->chunk_path[k], (int32_t)k);
+    }
+    std::stable_sort(ready.begin(), ready.end(),
+                     [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                         return x.first > y.first;
+                     });
+    std::vector<int64_t> items;
+    items.reserve(ready.size() * pl.n_slices);
+    for (auto& r : ready)
+        for (int32_t sl = 0; sl < pl.n_slices; ++sl) items.push_back(((int64_t)r.second << 16) | sl);
+    pl.n_items = (int64_t)items.size();
+    const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
+    const int64_t n_rows = (int64_t)p->promo_rows.size() / 2;
+    DevBuf rows;
+    if (n_rows > 0) {
+        RC(upload(c, rows, p->promo_rows.data(), p->promo_rows.size() * sizeof(int64_t), s));
+        HIPC(c, launch_move_rows(src->vecs.p, rows.as<int64_t>(), n_rows, (int64_t)(cs->stride * esz), p->vecs.p, s));
+    }
+    if (pl.n_items > 0) {
+        RC(upload(c, pl.items, items.data(), items.size() * sizeof(int64_t), s));
+        RC(upload(c, pl.pending_init, pend.data(), pend.size() * sizeof(int32_t), s));
+        RC(dev_alloc(c, pl.pending, pend.size() * sizeof(int32_t)));
+        RC(dev_alloc(c, pl.cursor, sizeof(unsigned int)));
+        const int64_t full = (int64_t)std::max(1, v.max_blocks_per_cu) * std::max(1, c->n_cu);
+        pl.grid = (int)std::max<int64_t>(1, std::min<int64_t>(full, pl.n_items));
+        RC(enqueue_body(c, p, cs, &pl, s, nullptr, false));
+    } else {
+        // every child is one reused chunk (a whole subtree of a parent): nothing runs but the fitness
+        HIPC(c, launch_fitness(p->vtype, fit_params(p, cs), p->n_trees, s));
+    }
+    p->evaluated_with = cases_h;
+    HIPC(c, hipStreamSynchronize(s));            // the plan and the row list are freed on return
+    if (n_evaluated) *n_evaluated = n_eval;
     return GP_OK;
 }
 
@@ -1454,6 +1541,27 @@ int gp_population_ops(gp_ctx* ctx, gp_handle pop, uint8_t* ops_out, int64_t ops_
     return GP_OK;
 }
 
+int gp_population_results(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags, void* root_out,
+                          void* fitness_out)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Pop* p;
+    CaseSet* cs;
+    RC(lookup(ctx, pop, cases, &p, &cs));
+    if (p->evaluated_with != cases || !p->vecs.p)
+        return set_err(ctx, GP_ENOTFOUND, "the population's last full evaluation was not on this case set");
+    const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
+    RC(copy_out(ctx, root_out, p->vecs.p, p->n_trees, cs->n_elems, cs->stride, esz, flags));
+    if (fitness_out) {
+        const hipMemcpyKind kind = (flags & GP_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        HIPC(ctx, hipMemcpyAsync(fitness_out, p->fit.p, (size_t)p->n_trees * 8, kind, ctx->stream));
+    }
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    return GP_OK;
+}
+
 int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* cfg, gp_gen_stats* stats,
               gp_gen_child* children, gp_handle* out_pop)
 {
@@ -1492,6 +1600,7 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
     std::vector<int32_t> stop(N), drawn(N);
     std::vector<int64_t> interp(N), removed(N), dend(N);
     std::vector<uint8_t> fit_h((size_t)N * 8);
+    DevBuf spare_vecs;
     for (int64_t gi = 0; gi < G; ++gi) {
         const double t0 = now_ms();
         const int64_t g = cfg->first_generation + gi;
@@ -1673,8 +1782,21 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
         const double t2 = now_ms();
         const int variant = choose_variant(ctx, vtype, cs, np.get());
         if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits the children");
-        RC(enqueue_full(ctx, np.get(), cases, cs, variant, false, false, s, nullptr));
-        HIPC(ctx, hipStreamSynchronize(s));
+        int64_t n_eval = np->n_chunks;
+        // the chunk vectors of the generation before last hold nothing needed any more: reused when large enough
+        const size_t vec_bytes = (size_t)np->n_chunks * cs->stride * (boolean ? 8 : 4);
+        if (spare_vecs.p && spare_vecs.bytes >= vec_bytes) {
+            np->vecs.swap(spare_vecs);
+            np->stride = cs->stride;
+            RC(dev_alloc(ctx, np->fit, (size_t)np->n_trees * 8));
+        }
+        if (!np->promo_src.empty()) {
+            // reused chunks take their parents' values; only the chunks compiled anew run
+            RC(enqueue_promoted(ctx, np.get(), cur, cases, cs, variant, s, &n_eval));
+        } else {
+            RC(enqueue_full(ctx, np.get(), cases, cs, variant, false, false, s, nullptr));
+            HIPC(ctx, hipStreamSynchronize(s));
+        }
         const double t3 = now_ms();
         // statistics and records
         const double* ff = (const double*)fit_h.data();
@@ -1698,6 +1820,8 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
             st.ms_score = t1 - t0;
             st.ms_build = t2 - t1;
             st.ms_eval = t3 - t2;
+            st.chunks = np->n_chunks;
+            st.chunks_evaluated = n_eval;
         }
         if (children)
             for (int64_t i = 0; i < N; ++i) {
@@ -1718,6 +1842,8 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
             slot_size[i] = new_slot[i] >= 0 ? child_nodes[i] : 0;
         }
         fitv.swap(fitn);
+        spare_vecs.release();
+        if (holder) spare_vecs.swap(holder->vecs);   // the generation before this one is dropped now
         holder = np;
         cur = np.get();
     }

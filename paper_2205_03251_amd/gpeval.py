@@ -29,7 +29,7 @@ EXPORTS = [
     "gp_evaluate_incremental", "gp_fitness", "gp_variant_name", "gp_variant_count", "gp_autotune",
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
     "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree", "gp_index_trees",
-    "gp_index_trees_noalloc",
+    "gp_index_trees_noalloc", "gp_population_results", "gp_evolve", "gp_population_ops",
 ]
 INDEX_NOALLOC_MAX_NODES = 4194304
 
@@ -58,7 +58,8 @@ class EvolveCfg(C.Structure):
 class GenStats(C.Structure):
     _fields_ = [("best_f64", C.c_double), ("best_i64", C.c_int64), ("children", C.c_int64), ("built", C.c_int64),
                 ("child_nodes", C.c_int64), ("built_nodes", C.c_int64), ("interpreted_nodes", C.c_int64),
-                ("ms", C.c_double), ("ms_score", C.c_double), ("ms_build", C.c_double), ("ms_eval", C.c_double)]
+                ("ms", C.c_double), ("ms_score", C.c_double), ("ms_build", C.c_double), ("ms_eval", C.c_double),
+                ("chunks", C.c_int64), ("chunks_evaluated", C.c_int64)]
 
 
 class GenChild(C.Structure):
@@ -130,6 +131,7 @@ def lib() -> C.CDLL:
     h.gp_population_info.argtypes = [P, I64, C.POINTER(PopInfo)]
     h.gp_index_trees.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
     h.gp_index_trees_noalloc.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
+    h.gp_population_results.argtypes = [P, I64, I64, C.c_uint32, P, P]
     h.gp_free.argtypes = [P, I64]
     h.gp_evaluate_full.argtypes = [P, I64, I64, C.c_uint32, P, P, C.POINTER(Stats)]
     h.gp_evaluate_incremental_batch.argtypes = [P, I64, I64, I64, P, P, P, P, C.c_uint32, P, P,
@@ -494,6 +496,15 @@ class Context:
         arr = np.ctypeslib.as_array(recs)
         rec = {k: np.array(arr[k]).reshape(generations, n) for k, _ in GenChild._fields_}
         return out.value, st, rec
+
+    def population_results(self, pop, cases, vtype, n_cases):
+        """Root vectors and fitness of the population's last full evaluation."""
+        n = self.population_info(pop)["n_trees"]
+        shape, vdt, fdt = self._out_shape(vtype, n, n_cases)
+        r = np.empty(shape, vdt)
+        f = np.empty(n, fdt)
+        self._check(lib().gp_population_results(self._h, pop, cases, 0, _ptr(r), _ptr(f)))
+        return r, f
 
     def population_ops(self, pop):
         """(ops, offsets) of a population's trees, as loaded."""

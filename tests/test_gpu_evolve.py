@@ -129,3 +129,37 @@ def test_evolve_errors(ctx):
     assert e.value.code == g.GP_EINVAL
     for h in (post, ph, ch):
         ctx.free(h)
+
+
+@pytest.mark.parametrize("boolean,T,chunk_nodes", [(False, 1000, 16), (False, 48, 64), (True, 256, 16)])
+def test_promoted_children_equal_full_evaluation(ctx, boolean, T, chunk_nodes):
+    """Built children take the values of the chunks they reuse from their
+    parents' last evaluation and run only the chunks compiled anew (Section 5,
+    Figure 1): their outputs and fitness equal a full evaluation of the same
+    population and the oracle's, and the next generation, whose co-evaluation
+    reads those chunk values, still matches the oracle draw by draw."""
+    rng = np.random.default_rng(107 + T)
+    k = T.bit_length() - 1 if boolean else 1
+    trees = [gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 101, 3001)), n_terms=k) for _ in range(36)]
+    cases = gen.bool_cases(k) if boolean else gen.float_cases(108, T)
+    ph, ch, nh, stats, rec, want, final, gt = run_both(ctx, trees, boolean, cases, 3, 3, 13, n_inputs=k,
+                                                      chunk_nodes=chunk_nodes)
+    check(rec, want, final, ctx, nh, boolean)
+    for st in stats:
+        assert 0 < st["chunks_evaluated"] < st["chunks"], st
+    r1, f1 = ctx.population_results(nh, ch, gt, cases.T)
+    r2, f2, _ = ctx.evaluate_full(nh, ch, gt, len(final), cases.T)
+    if boolean:
+        assert np.array_equal(r1, r2) and np.array_equal(f1, f2)
+        wr, wf = oracle.eval_population_bool(gen.pack(final, gen.VT_BOOL, k), cases.inputs, cases.target, cases.T)
+        assert np.array_equal(r1, wr) and np.array_equal(f1, wf)
+    else:
+        same = (r1.view(np.uint32) == r2.view(np.uint32)) | (np.isnan(r1) & np.isnan(r2))
+        assert same.all() and np.all((f1 == f2) | (np.isnan(f1) & np.isnan(f2)))
+        with np.errstate(all="ignore"):
+            wr, wf = oracle.eval_population_f32(gen.pack(final), cases.x, cases.y)
+        same = (r1.view(np.uint32) == wr.view(np.uint32)) | (np.isnan(r1) & np.isnan(wr))
+        assert same.all() and np.all((f1 == wf) | (np.isnan(f1) & np.isnan(wf)))
+    say("promoted: chunks evaluated", [(s["chunks_evaluated"], s["chunks"]) for s in stats])
+    for h in (nh, ph, ch):
+        ctx.free(h)
