@@ -52,7 +52,10 @@ the product, the residual and one correction (5 instructions per case after
 the rcp, 3 when y is hoisted).  On both short-divide domains it matched IEEE
 division on 1.7e10 random quotients and on 2.6e9 quotients built to lie
 within 63 * 2^-48 (relative) of a rounding midpoint, where the same step with
-the unrefined rcp(b) fails about once in 2400.
+the unrefined rcp(b) fails about once in 2400.  Because q = a*y can be up to
+1.5 ulp from a/b, outside the theorem's hypothesis, the short form is also
+checked exhaustively over every numerator significand for sampled divisor
+significands (tests/csrc/short_divide_check.c).
 Two kinds of handler use this:
   * stack / x: the refined reciprocal of x is hoisted with the other x-only
     work.  Allowed when every lane's unprotected x lies in [1e-6, 2^20] (a
