@@ -32,7 +32,10 @@ sys.path.insert(0, ROOT)
 
 import gen  # noqa: E402
 
-PEAK_FP32_LANE_OPS = 256 * 4 * 16 * 2.4e9      # non-packed FP32 VALU lane-ops/s (39.3e12)
+# FP32 VALU peak: 256 CUs x 4 SIMDs x 32 lane-operations per cycle x 2.4 GHz = 78.64e12 lane-ops/s, the published
+# 157.3 TFLOP/s with an FMA counted as two flops (a wave64 add, mul or fma issues every two cycles per SIMD; the
+# VALU calibration measures 2.34)
+PEAK_FP32_LANE_OPS = 256 * 4 * 32 * 2.4e9
 PEAK_HBM_GBPS = 8000.0                        # MI355X HBM3E
 
 
@@ -456,7 +459,32 @@ def main():
     ap.add_argument("--variant", default="", help="fix the interpreter variant, e.g. f32_k4_s16")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only run launches of known VALU instruction counts per class (reference for VALU counters)")
     args = ap.parse_args()
+    if args.calibrate_valu:
+        import torch
+        from paper_2205_03251_amd import gpeval as g
+        torch.cuda.init()
+        ctx = g.Context(0)
+        names = ["v_add_f32", "v_mul_f32", "v_fma_f32", "v_rcp_f32", "v_cndmask_b32", "v_cmp_lt_f32",
+                 "v_max3_f32", "v_mov_b32", "v_add_f32+v_rcp_f32", "v_add_f32+v_cmp_lt_f32"]
+        waves, iters = 256 * 4 * 8, 4000        # eight waves per SIMD; 128000 VALU instructions per wave
+        res = []
+        for cls, name in enumerate(names):
+            ctx.valu_calibration(cls, waves, 0)
+            t0 = min(ctx.valu_calibration(cls, waves, 0) for _ in range(3))
+            t1 = min(ctx.valu_calibration(cls, waves, iters) for _ in range(3))
+            n = waves * 32 * iters
+            rate = n * 64 / ((t1 - t0) * 1e-3)
+            res.append({"class": cls, "instructions": name, "waves": waves, "valu_per_wave_loop": 32 * iters,
+                        "ms": round(t1, 4), "ms_iters0": round(t0, 4), "lane_ops_per_s": rate,
+                        "frac_of_peak": round(rate / PEAK_FP32_LANE_OPS, 4),
+                        "instr_per_simd_cycle": round(n / 1024 / ((t1 - t0) * 1e-3 * 2.4e9), 4)})
+            log(f"[calibrate] {res[-1]}")
+        print(json.dumps({"valu_calibration": res}))
+        ctx.close()
+        return
     if args.calibrate_copy:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -583,8 +611,11 @@ def main():
     achieved = func_nodes * T / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_FP32_LANE_OPS / 1e12, 2),
                 "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_LANE_OPS, 4), "traffic": None,
-                "kernel": "k_eval_" + ("bool" if vtype == g.GP_BOOL else "f32"), "kernel_ms": round(kernel_ms, 3),
-                "gp_ops_per_s": round(total_nodes * T / (kernel_ms * 1e-3) / 1e12, 4)}
+                "kernel": "k_eval_" + ("bool" if vtype == g.GP_BOOL else "f32") + "_tbl", "kernel_ms": round(kernel_ms, 3),
+                "gp_ops_per_s": round(total_nodes * T / (kernel_ms * 1e-3) / 1e12, 4),
+                "peak_note": "256 CU x 4 SIMD x 32 lane-ops/cycle x 2.4 GHz: the published 157.3 TFLOP/s counts an FMA as "
+                             "two flops; + - x / are one op per lane at the same issue rate. achieved = function nodes "
+                             "x cases / interpreter launch time (terminals excluded)"}
     if vtype == g.GP_BOOL:
         roofline["note"] = "Boolean: one 64-bit word op per function node per 64 cases"
     # HBM bytes from the committed counter runs, valid only for the kernel source they were taken with
@@ -599,8 +630,11 @@ def main():
             # one record per (chunk size, variant) the autotuner has been seen to pick
             for r in rec["records"]:
                 if r["chunk_nodes"] == final_info["chunk_nodes"] and r["variant"] == used.get("variant", tuned):
+                    # read bytes by request size (FETCH_SIZE counts a 128-byte request as 64 bytes on this chip)
                     roofline["traffic"] = int(r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"])
-                    roofline["valu_lane_op_frac_counters"] = r["valu_lane_op_frac"]
+                    roofline["traffic_GBps"] = round(roofline["traffic"] / (kernel_ms * 1e-3) / 1e9, 1)
+                    roofline["valu_lane_op_frac_counters"] = round(
+                        r["valu_instructions_per_launch"] * 64 / (kernel_ms * 1e-3) / PEAK_FP32_LANE_OPS, 4)
                     counted = rec
     except (OSError, KeyError, ValueError):
         pass

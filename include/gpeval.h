@@ -414,6 +414,19 @@ int gp_server_poll(gp_ctx* ctx, int64_t ticket, gp_job_result* out, void* root_o
 int gp_server_release(gp_ctx* ctx, int64_t ticket);
 int gp_server_stop(gp_ctx* ctx);
 
+/* ------------------------------------------------------------- measurement */
+
+/* Counter calibration, not part of evaluation: one launch of n_waves
+ * single-wave workgroups in which every wave runs iters x 32 VALU
+ * instructions of one class on eight independent registers (0 v_add_f32,
+ * 1 v_mul_f32, 2 v_fma_f32, 3 v_rcp_f32, 4 v_cndmask_b32, 5 v_cmp_lt_f32,
+ * 6 v_max3_f32, 7 v_mov_b32, 8 v_add_f32 and v_rcp_f32 alternating,
+ * 9 v_add_f32 and v_cmp_lt_f32 alternating), so that hardware counters and
+ * issue rates can be read against a known instruction count (two runs that
+ * differ only in iters differ by exactly 32 x iters VALU instructions per
+ * wave).  device_ms (may be NULL) receives the launch's HIP-event time. */
+int gp_valu_calibration(gp_ctx* ctx, int cls, int64_t n_waves, int64_t iters, double* device_ms);
+
 /* ----------------------------------------------- host-only inspection */
 
 /* Compile one prefix tree on the host only (no GPU needed) and return the

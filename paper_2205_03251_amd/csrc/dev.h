@@ -261,6 +261,9 @@ hipError_t launch_mark(const MarkParams& p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* dst, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gather_rows(const void* src, const int64_t* src_rows, int64_t n_rows, int64_t row_bytes, void* dst,
                               hipStream_t s);
+// Counter calibration: n_waves single-wave workgroups, each running iters x 32
+// VALU instructions of class cls (see k_valu_cal); out: n_waves * 64 floats.
+hipError_t launch_valu_cal(int cls, int64_t n_waves, int64_t iters, float* out, hipStream_t s);
 // Row rows[2k] of dst = row rows[2k + 1] of src, k < n_rows (rows of row_bytes, a multiple of 16).
 hipError_t launch_move_rows(const void* src, const int64_t* rows, int64_t n_rows, int64_t row_bytes, void* dst,
                             hipStream_t s);

@@ -1165,6 +1165,70 @@ hipError_t launch_move_rows(const void* src, const int64_t* rows, int64_t n_rows
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------- measurement
+// Counter calibration: every wave runs `iters` times a block of 32 VALU
+// instructions of one class over eight independent registers (so no
+// instruction waits for the one before it), the loop itself being scalar.
+// A run with iters = 0 gives the fixed instructions around the loop, so the
+// difference of two runs is exactly 32 x iters VALU instructions per wave.
+#define GP_CAL8(op) op(0) op(1) op(2) op(3) op(4) op(5) op(6) op(7)
+#define GP_CAL32(op) GP_CAL8(op) GP_CAL8(op) GP_CAL8(op) GP_CAL8(op)
+#define GP_ADD(i) "v_add_f32_e32 %" #i ", %" #i ", %8\n"
+#define GP_MUL(i) "v_mul_f32_e32 %" #i ", %" #i ", %8\n"
+#define GP_FMA(i) "v_fma_f32 %" #i ", %" #i ", %8, %9\n"
+#define GP_RCP(i) "v_rcp_f32_e32 %" #i ", %" #i "\n"
+#define GP_CND(i) "v_cndmask_b32_e32 %" #i ", %" #i ", %8, vcc\n"
+#define GP_CMP(i) "v_cmp_lt_f32_e32 vcc, %" #i ", %8\n"
+#define GP_MAX3(i) "v_max3_f32 %" #i ", %" #i ", %8, %9\n"
+#define GP_MOV(i) "v_mov_b32_e32 %" #i ", %8\n"
+#define GP_ADDRCP(i) "v_add_f32_e32 %" #i ", %" #i ", %8\nv_rcp_f32_e32 %9, %8\n"
+#define GP_ADDCMP(i) "v_add_f32_e32 %" #i ", %" #i ", %8\nv_cmp_lt_f32_e32 vcc, %" #i ", %8\n"
+
+template <int CLS>
+__global__ __launch_bounds__(64) void k_valu_cal(int64_t iters, float* out)
+{
+    float a0 = threadIdx.x, a1 = a0 + 1, a2 = a0 + 2, a3 = a0 + 3, a4 = a0 + 4, a5 = a0 + 5, a6 = a0 + 6, a7 = a0 + 7;
+    float b = 1.0f + 1e-7f * threadIdx.x, c = 0.5f;
+    asm volatile("s_mov_b64 vcc, -1" ::: "vcc");
+    for (int64_t it = 0; it < iters; ++it) {
+#define GP_CAL_ASM(body) \
+        asm volatile(body : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7) \
+                     : "v"(b), "v"(c) : "vcc")
+        if constexpr (CLS == 0) GP_CAL_ASM(GP_CAL32(GP_ADD));
+        else if constexpr (CLS == 1) GP_CAL_ASM(GP_CAL32(GP_MUL));
+        else if constexpr (CLS == 2) GP_CAL_ASM(GP_CAL32(GP_FMA));
+        else if constexpr (CLS == 3) GP_CAL_ASM(GP_CAL32(GP_RCP));
+        else if constexpr (CLS == 4) GP_CAL_ASM(GP_CAL32(GP_CND));
+        else if constexpr (CLS == 5) GP_CAL_ASM(GP_CAL32(GP_CMP));
+        else if constexpr (CLS == 6) GP_CAL_ASM(GP_CAL32(GP_MAX3));
+        else if constexpr (CLS == 7) GP_CAL_ASM(GP_CAL32(GP_MOV));
+        else if constexpr (CLS == 8) GP_CAL_ASM(GP_CAL8(GP_ADDRCP) GP_CAL8(GP_ADDRCP));
+        else GP_CAL_ASM(GP_CAL8(GP_ADDCMP) GP_CAL8(GP_ADDCMP));
+#undef GP_CAL_ASM
+    }
+    out[(int64_t)blockIdx.x * 64 + threadIdx.x] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+}
+
+hipError_t launch_valu_cal(int cls, int64_t n_waves, int64_t iters, float* out, hipStream_t s)
+{
+    if (n_waves < 1 || n_waves > 0x7fffffff || iters < 0) return hipErrorInvalidValue;
+    const dim3 g((unsigned)n_waves), b(64);
+    switch (cls) {
+    case 0: hipLaunchKernelGGL(k_valu_cal<0>, g, b, 0, s, iters, out); break;
+    case 1: hipLaunchKernelGGL(k_valu_cal<1>, g, b, 0, s, iters, out); break;
+    case 2: hipLaunchKernelGGL(k_valu_cal<2>, g, b, 0, s, iters, out); break;
+    case 3: hipLaunchKernelGGL(k_valu_cal<3>, g, b, 0, s, iters, out); break;
+    case 4: hipLaunchKernelGGL(k_valu_cal<4>, g, b, 0, s, iters, out); break;
+    case 5: hipLaunchKernelGGL(k_valu_cal<5>, g, b, 0, s, iters, out); break;
+    case 6: hipLaunchKernelGGL(k_valu_cal<6>, g, b, 0, s, iters, out); break;
+    case 7: hipLaunchKernelGGL(k_valu_cal<7>, g, b, 0, s, iters, out); break;
+    case 8: hipLaunchKernelGGL(k_valu_cal<8>, g, b, 0, s, iters, out); break;
+    case 9: hipLaunchKernelGGL(k_valu_cal<9>, g, b, 0, s, iters, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- splice
 // Children are built from three contiguous byte ranges each (the mother's
 // nodes before the replaced subtree, the donor, the mother's nodes after it;

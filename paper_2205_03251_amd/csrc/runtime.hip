@@ -2117,6 +2117,25 @@ int gp_index_trees_noalloc(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uin
     return ix_run(ctx, q, base + kIxStaticBsum, base + kIxStaticFlag, nb, len, device_ms);
 }
 
+int gp_valu_calibration(gp_ctx* ctx, int cls, int64_t n_waves, int64_t iters, double* device_ms)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    if (cls < 0 || cls > 9) return set_err(ctx, GP_EINVAL, "instruction class must be 0..9");
+    if (n_waves < 1 || n_waves > (int64_t(1) << 24) || iters < 0) return set_err(ctx, GP_EINVAL, "bad size");
+    DevBuf out;
+    RC(dev_alloc(ctx, out, (size_t)n_waves * 64 * 4));
+    HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    HIPC(ctx, launch_valu_cal(cls, n_waves, iters, out.as<float>(), ctx->stream));
+    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (device_ms) *device_ms = ms;
+    return GP_OK;
+}
+
 int gp_validate_tree(int vtype, int n_inputs, const uint8_t* ops, int64_t n)
 {
     if ((vtype != GP_F32 && vtype != GP_BOOL) || n_inputs < 1 || n_inputs > kMaxInputs || !ops) return GP_EINVAL;

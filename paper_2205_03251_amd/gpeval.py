@@ -29,7 +29,7 @@ EXPORTS = [
     "gp_evaluate_incremental", "gp_fitness", "gp_variant_name", "gp_variant_count", "gp_autotune",
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
     "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree", "gp_index_trees",
-    "gp_index_trees_noalloc", "gp_population_results", "gp_evolve", "gp_population_ops",
+    "gp_index_trees_noalloc", "gp_population_results", "gp_evolve", "gp_population_ops", "gp_valu_calibration",
 ]
 INDEX_NOALLOC_MAX_NODES = 4194304
 
@@ -132,6 +132,7 @@ def lib() -> C.CDLL:
     h.gp_index_trees.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
     h.gp_index_trees_noalloc.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
     h.gp_population_results.argtypes = [P, I64, I64, C.c_uint32, P, P]
+    h.gp_valu_calibration.argtypes = [P, C.c_int, I64, I64, C.POINTER(C.c_double)]
     h.gp_free.argtypes = [P, I64]
     h.gp_evaluate_full.argtypes = [P, I64, I64, C.c_uint32, P, P, C.POINTER(Stats)]
     h.gp_evaluate_incremental_batch.argtypes = [P, I64, I64, I64, P, P, P, P, C.c_uint32, P, P,
@@ -496,6 +497,12 @@ class Context:
         arr = np.ctypeslib.as_array(recs)
         rec = {k: np.array(arr[k]).reshape(generations, n) for k, _ in GenChild._fields_}
         return out.value, st, rec
+
+    def valu_calibration(self, cls, n_waves, iters) -> float:
+        """gp_valu_calibration: the launch time in ms."""
+        ms = C.c_double(0.0)
+        self._check(lib().gp_valu_calibration(self._h, cls, n_waves, iters, C.byref(ms)))
+        return ms.value
 
     def population_results(self, pop, cases, vtype, n_cases):
         """Root vectors and fitness of the population's last full evaluation."""
