@@ -448,7 +448,7 @@ def main():
                     help="skip per-tree launches and the full re-evaluation of the built children")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the small, Boolean and large full-evaluation configurations")
-    ap.add_argument("--cpu-budget", type=float, default=4.0,
+    ap.add_argument("--cpu-budget", type=float, default=1.5,
                     help="seconds of oracle work per thread for each configuration's CPU baselines")
     # the host's CPU share for one GPU is 16 threads, whatever nproc shows
     ap.add_argument("--threads", type=int, default=min(16, len(os.sched_getaffinity(0))))
