@@ -81,6 +81,7 @@ enum { GP_PREFIX = 0, GP_POSTFIX = 1 };    /* load layout */
                                 memory (charged to the budget) for gp_splice_children */
 #define GP_COEVAL     0x20u  /* gp_evaluate_incremental_batch: re-evaluate the mother
                                 alongside each child instead of reading parent caches */
+#define GP_DEVICE_COMPILE 0x40u  /* gp_load_population: compile the trees on the device */
 
 typedef struct gp_stats {
     double device_ms;          /* HIP-event time on the context stream (0 with GP_ASYNC) */
@@ -146,13 +147,44 @@ int gp_set_cases(gp_ctx* ctx, int vtype, int n_inputs, int64_t n_cases, const vo
  * the given layout) whose parent caches every full evaluation must record,
  * for later incremental evaluation of children made at those points.
  * chunk_nodes: target nodes per chunk (0 = automatic).  flags: GP_KEEP_TREES
- * keeps a device copy of ops for gp_splice_children; other bits are ignored. */
+ * keeps a device copy of ops for gp_splice_children.  GP_DEVICE_COMPILE
+ * (prefix layout only) validates and compiles the trees on the device: the
+ * same checks, and programs, chunk tables and parent-cache records identical
+ * byte for byte to the host compiler's (gp_population_dump shows them), in
+ * passes over the flattened trees (Section 3.1) instead of a host pass per
+ * tree; it also re-chunks on the device when gp_autotune tries other chunk
+ * sizes.  GP_DEVICE_PTR: ops and offsets are device pointers (ops any
+ * alignment), compiled on the device as with GP_DEVICE_COMPILE; the library
+ * keeps a host copy of the trees (for co-evaluation and re-chunking) either
+ * way.  record_points and record_offsets are host arrays in every case.
+ * Other bits are ignored. */
 int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t n_trees,
                        const uint8_t* ops, const int64_t* offsets, const int64_t* record_points,
                        const int64_t* record_offsets, int64_t chunk_nodes, uint32_t flags,
                        gp_handle* pop_out);
 
 int gp_population_info(gp_ctx* ctx, gp_handle pop, gp_pop_info* out);
+
+/* The compiled form of a loaded population, for inspection and for checking
+ * two compilations against each other: one byte string of sections, each an
+ * int64 byte count followed by its bytes, in this order: header (8 int64:
+ * trees, chunks, instruction words, records, stack slots, chunk target,
+ * nodes, layout); instruction words (+1 trailing word); chunk table (32 bytes
+ * per chunk: int64 code offset, int32 code length, parent, output slot, input
+ * offset, record base, input count); chunk input slots (int32); per chunk its
+ * input count and its tree (int32); per tree its record base (int64); the
+ * scheduling order of leaf chunks ((priority, chunk) int64 pairs); spines (5
+ * int64: tree, vector at the point, first level, levels, nodes removed);
+ * spine keys ((tree << 32 | point, spine) int64 pairs, sorted); spine levels
+ * (4 int32: function | side, sibling vector, ancestor vector, 0); per tree
+ * its large subtrees (count, then (node, end) pairs); its chunk roots (count,
+ * then (node, end, vector slot) triples); its chunks (count, then per chunk
+ * code offset, length, parent, root node, nodes, longest chain, subtree end,
+ * reused code offset, records, vector slot, reused vector slot, input count,
+ * inputs, all int64); per tree its stack slots (int32) and nodes (int64).
+ * out == NULL: *size receives the byte count only.  GP_EINVAL when cap is
+ * smaller than that. */
+int gp_population_dump(gp_ctx* ctx, gp_handle pop, uint8_t* out, int64_t cap, int64_t* size);
 
 /* Index a population of prefix trees on the device (the flattened form of
  * Section 3.1): tree t is ops[offsets[t] .. offsets[t+1]).  Every argument

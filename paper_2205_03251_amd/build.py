@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgpeval.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["prep.cpp", "kernels.hip", "index.hip", "runtime.hip", "server.cpp"]
+SOURCES = ["prep.cpp", "kernels.hip", "index.hip", "devcompile.hip", "runtime.hip", "server.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off",                      # no fused multiply-add anywhere

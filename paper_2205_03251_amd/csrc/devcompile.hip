@@ -1,0 +1,619 @@
+// Device-side compilation of a population of prefix trees (Section 3.1):
+// the programs, chunk tables and parent-cache spines that compile_tree and
+// assemble_population build on the host, byte for byte, built from the trees'
+// bytes in device memory.  The per-thread steps are in devcompile_core.h.
+//
+// Passes: the device tree index (validity, subtree ends, parents); one thread
+// per terminal finishes nodes bottom-up (stack need, cuts, instruction form,
+// code length); the crossover points' paths are read up the parent index and
+// their records assigned on the host; chunk roots are compacted, numbered and
+// given code offsets (host prefix sums over per-chunk lengths); one thread per
+// chunk counts its LOADs, then writes its code straight into the population's
+// program.  The host keeps only per-chunk and per-record tables.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <unordered_map>
+
+#include "devcompile_core.h"
+#include "runtime.h"
+
+namespace gpe {
+
+namespace {
+
+// Values handed from one thread to another: agent-coherent (sc1) stores and
+// loads, and a relaxed agent-scope counter.  The writer waits for its stores
+// to complete before it counts; the reader loads only after the count
+// returned (a compiler barrier keeps the loads after it; they depend on its
+// value).  The same hand-off as the interpreter's chunk pending counters.
+struct DevMem {
+    __device__ static int32_t ld(const int32_t* p)
+    {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void st(int32_t* p, int32_t v)
+    {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static int32_t fetch_add(int32_t* p, int32_t v)
+    {
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static void publish() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+    __device__ static void after_count() { asm volatile("" ::: "memory"); }
+    __device__ static void err(int32_t* p, int32_t v) { atomicOr(p, v); }
+};
+
+__global__ __launch_bounds__(256) void k_dc_up(DcNodes q)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= q.n || (q.ops[g] & kFuncBit)) return;
+    const int64_t t = dc_tree_of(q, g);
+    const int64_t s = q.offsets[t], e = q.offsets[t + 1];
+    dc_leaf<DevMem>(q, g);
+    for (int64_t v = g; v >= 0;) v = dc_step<DevMem>(q, s, e, v);
+}
+
+// Adds the wave's count of set flags to *count.
+__device__ __forceinline__ void dc_count(bool f, unsigned long long* count)
+{
+    const uint64_t b = __ballot(f);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
+// flags[g] = 1 where g roots a chunk: a cut node or a tree's root.
+__global__ __launch_bounds__(256) void k_dc_roots(DcNodes q, uint8_t* flags, unsigned long long* count)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool f = false;
+    if (g < q.n) {
+        f = (q.info[g] & kDcCut) != 0 || q.parl[g] < 0;
+        flags[g] = f ? 1 : 0;
+    }
+    dc_count(f, count);
+}
+
+// flags[g] = 1 for a function whose subtree has at least min_size nodes.
+__global__ __launch_bounds__(256) void k_dc_big(DcNodes q, uint8_t* flags, int64_t min_size,
+                                                unsigned long long* count)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool f = false;
+    if (g < q.n) {
+        if (q.ops[g] & kFuncBit) {
+            const int64_t s = q.offsets[dc_tree_of(q, g)];
+            f = s + q.endl[g] - g >= min_size;
+        }
+        flags[g] = f ? 1 : 0;
+    }
+    dc_count(f, count);
+}
+
+// Chunk roots: their chunk ids into cnt, their code lengths and subtree ends out.
+__global__ __launch_bounds__(256) void k_dc_root_info(DcNodes q, const int64_t* roots, const int32_t* ids, int64_t n,
+                                                      int32_t* rlen, int32_t* rend)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const int64_t g = roots[k];
+    q.cnt[g] = ids[k];
+    rlen[k] = q.len[g];
+    rend[k] = q.endl[g];
+}
+
+// Subtree ends of listed nodes.
+__global__ __launch_bounds__(256) void k_dc_ends(DcNodes q, const int64_t* nodes, int64_t n, int32_t* out)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) out[k] = q.endl[nodes[k]];
+}
+
+// Paths of crossover points (global node pts[i]) up to the root.  Count pass
+// (lv null): depth[i].  Write pass: per ancestor, nearest first, from
+// lv[lv_off[i]]; the point's opcode and subtree end.
+__global__ __launch_bounds__(256) void k_dc_paths(DcNodes q, const int64_t* pts, int64_t n_pts, const int64_t* lv_off,
+                                                  int32_t* depth, DcPathLevel* lv, uint8_t* pop, int32_t* pend)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_pts) return;
+    const int64_t c = pts[i];
+    const int64_t s = q.offsets[dc_tree_of(q, c)];
+    if (!lv) {
+        int32_t d = 0;
+        for (int32_t a = q.parl[c]; a >= 0; a = q.parl[s + a]) ++d;
+        depth[i] = d;
+        return;
+    }
+    pop[i] = q.ops[c];
+    pend[i] = q.endl[c];
+    DcPathLevel* out = lv + lv_off[i];
+    int32_t below = (int32_t)(c - s);
+    for (int32_t a = q.parl[c]; a >= 0; a = q.parl[s + a]) {
+        const int32_t l = a + 1, r = q.endl[s + l];
+        const bool right = below != l;
+        const int32_t sib = right ? l : r;
+        DcPathLevel x;
+        x.a = a;
+        x.sib = sib;
+        x.fside = (q.ops[s + a] & 3) | (right ? 4 : 0);
+        x.sib_op = q.ops[s + sib];
+        *out++ = x;
+        below = a;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dc_cut_of(DcNodes q, const int64_t* nodes, int64_t n, uint8_t* out)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) out[k] = (q.info[nodes[k]] & kDcCut) ? 1 : 0;
+}
+
+// Recorded nodes: their STOREs lengthen their own subtrees' code.
+__global__ __launch_bounds__(256) void k_dc_store(DcNodes q, const int64_t* nodes, const int32_t* inc,
+                                                  const int32_t* rec_id, int64_t n, int32_t* rec)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const int64_t g = nodes[k];
+    q.len[g] += inc[k];
+    rec[g] = rec_id[k];
+}
+
+__global__ __launch_bounds__(256) void k_dc_emit(DcNodes q, DcChunks c, int write)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < c.n) dc_emit(q, c, k, write);
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+#define HIPC(c, x)                                        \
+    do {                                                  \
+        int rc__ = hip_check((c), (x), #x);               \
+        if (rc__ != GP_OK) return rc__;                   \
+    } while (0)
+
+#define RC(x)                                             \
+    do {                                                  \
+        int rc__ = (x);                                   \
+        if (rc__ != GP_OK) return rc__;                   \
+    } while (0)
+
+int up(Ctx* c, DevBuf& b, const void* src, size_t bytes, hipStream_t s)
+{
+    RC(dev_alloc(c, b, bytes));
+    if (bytes) HIPC(c, hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
+    return GP_OK;
+}
+
+int down(Ctx* c, void* dst, const DevBuf& b, size_t bytes, hipStream_t s)
+{
+    if (bytes) HIPC(c, hipMemcpyAsync(dst, b.p, bytes, hipMemcpyDeviceToHost, s));
+    return GP_OK;
+}
+
+// The flagged positions of flags[0 .. n), ascending, into out (count known).
+int dc_select(Ctx* c, const uint8_t* flags, int64_t n, int64_t count, DevBuf& out, hipStream_t s)
+{
+    DevBuf num, tmp;
+    RC(dev_alloc(c, num, 8));
+    RC(dev_alloc(c, out, (size_t)std::max<int64_t>(1, count) * 8));
+    size_t tb = 0;
+    hipcub::CountingInputIterator<int64_t> it(0);
+    HIPC(c, hipcub::DeviceSelect::Flagged(nullptr, tb, it, flags, out.as<int64_t>(), num.as<int64_t>(), (int)n, s));
+    RC(dev_alloc(c, tmp, std::max<size_t>(tb, 256)));
+    HIPC(c, hipcub::DeviceSelect::Flagged(tmp.p, tb, it, flags, out.as<int64_t>(), num.as<int64_t>(), (int)n, s));
+    int64_t got = 0;
+    HIPC(c, hipMemcpyAsync(&got, num.p, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    if (got != count) return set_err(c, GP_EINVAL, "internal error: compaction count differs");
+    return GP_OK;
+}
+
+}  // namespace
+
+int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, const uint8_t* dops,
+                              const int64_t* doffs, const int64_t* offsets, const uint8_t* host_ops,
+                              const int64_t* rec_points, const int64_t* rec_offsets, int64_t chunk_nodes,
+                              int64_t index_min_size, Pop* out, hipStream_t s)
+{
+    const int64_t n = offsets[n_trees];
+    if (n < 1 || n > (int64_t)INT32_MAX - 1) return set_err(c, GP_EINVAL, "at most 2^31 - 2 nodes per load");
+    if (n_trees > INT32_MAX / 2) return set_err(c, GP_EINVAL, "too many trees");
+    // crossover points: checked before any device work
+    int64_t n_pts = 0;
+    if (rec_points) {
+        for (int64_t t = 0; t < n_trees; ++t) {
+            if (rec_offsets[t + 1] < rec_offsets[t])
+                return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + ": record_offsets not increasing");
+            for (int64_t i = rec_offsets[t]; i < rec_offsets[t + 1]; ++i)
+                if (rec_points[i] < 0 || rec_points[i] >= offsets[t + 1] - offsets[t])
+                    return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + ": record point " +
+                                                     std::to_string(rec_points[i]) + " out of range");
+        }
+        n_pts = rec_offsets[n_trees];
+    }
+    // validity, subtree ends and parents
+    DevBuf valid, endl, parl;
+    RC(dev_alloc(c, valid, (size_t)n_trees * 4));
+    RC(dev_alloc(c, endl, (size_t)n * 4));
+    RC(dev_alloc(c, parl, (size_t)n * 4));
+    RC(index_trees(c, n_inputs, n_trees, dops, doffs, n, valid.as<int32_t>(), endl.as<int32_t>(),
+                   parl.as<int32_t>(), nullptr, nullptr));
+    {
+        std::vector<int32_t> v(n_trees);
+        RC(down(c, v.data(), valid, (size_t)n_trees * 4, s));
+        HIPC(c, hipStreamSynchronize(s));
+        for (int64_t t = 0; t < n_trees; ++t) {
+            if (v[t]) continue;
+            // the host check of that tree says what is wrong with it
+            std::vector<uint8_t> tree((size_t)(offsets[t + 1] - offsets[t]));
+            if (host_ops) std::copy(host_ops + offsets[t], host_ops + offsets[t + 1], tree.begin());
+            else HIPC(c, hipMemcpy(tree.data(), dops + offsets[t], tree.size(), hipMemcpyDeviceToHost));
+            std::string why = "not a valid prefix tree";
+            validate_prefix(tree.data(), (int64_t)tree.size(), n_inputs, &why);
+            return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + ": " + why);
+        }
+    }
+    valid.release();
+
+    DevBuf info, len, open, cnt, err, flags, counter;
+    RC(dev_alloc(c, info, (size_t)n * 4));
+    RC(dev_alloc(c, len, (size_t)n * 4));
+    RC(dev_alloc(c, open, (size_t)n * 4));
+    RC(dev_alloc(c, cnt, (size_t)n * 4));
+    RC(dev_alloc(c, err, 4));
+    RC(dev_alloc(c, counter, 16));
+    HIPC(c, launch_fill_i32(cnt.as<int32_t>(), n, 0, s));
+    HIPC(c, launch_fill_i32(err.as<int32_t>(), 1, 0, s));
+    DcNodes q{};
+    q.ops = dops;
+    q.offsets = doffs;
+    q.n_trees = n_trees;
+    q.n = n;
+    q.endl = endl.as<int32_t>();
+    q.parl = parl.as<int32_t>();
+    q.info = info.as<int32_t>();
+    q.len = len.as<int32_t>();
+    q.open = open.as<int32_t>();
+    q.cnt = cnt.as<int32_t>();
+    q.err = err.as<int32_t>();
+    q.boolean = vtype == GP_BOOL ? 1 : 0;
+    q.S = compile_stack_slots();
+    q.C = std::max<int64_t>(2, chunk_nodes);
+    hipLaunchKernelGGL(k_dc_up, dim3(blocks_for(n)), dim3(256), 0, s, q);
+    HIPC(c, hipGetLastError());
+    int32_t errv = 0;
+    HIPC(c, hipMemcpyAsync(&errv, err.p, 4, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    if (errv) return set_err(c, GP_EINVAL, "internal error: inconsistent tree index (" + std::to_string(errv) + ")");
+
+    // parent-cache records (Section 6.2): the points' paths, read on the device
+    std::vector<int64_t> rec_base(n_trees, 0), n_rec(n_trees, 0);
+    std::vector<std::vector<Spine>> spines(n_trees);
+    DevBuf rec;
+    if (n_pts > 0) {
+        std::vector<int64_t> pts(n_pts);
+        for (int64_t t = 0; t < n_trees; ++t)
+            for (int64_t i = rec_offsets[t]; i < rec_offsets[t + 1]; ++i) pts[i] = offsets[t] + rec_points[i];
+        DevBuf pts_d, depth_d, lvoff_d, lv_d, pop_d, pend_d;
+        RC(up(c, pts_d, pts.data(), (size_t)n_pts * 8, s));
+        RC(dev_alloc(c, depth_d, (size_t)n_pts * 4));
+        hipLaunchKernelGGL(k_dc_paths, dim3(blocks_for(n_pts)), dim3(256), 0, s, q, pts_d.as<int64_t>(), n_pts,
+                           (const int64_t*)nullptr, depth_d.as<int32_t>(), (DcPathLevel*)nullptr, (uint8_t*)nullptr,
+                           (int32_t*)nullptr);
+        HIPC(c, hipGetLastError());
+        std::vector<int32_t> depth(n_pts);
+        RC(down(c, depth.data(), depth_d, (size_t)n_pts * 4, s));
+        HIPC(c, hipStreamSynchronize(s));
+        std::vector<int64_t> lv_off(n_pts + 1, 0);
+        for (int64_t i = 0; i < n_pts; ++i) lv_off[i + 1] = lv_off[i] + depth[i];
+        RC(up(c, lvoff_d, lv_off.data(), (size_t)(n_pts + 1) * 8, s));
+        RC(dev_alloc(c, lv_d, (size_t)std::max<int64_t>(1, lv_off[n_pts]) * sizeof(DcPathLevel)));
+        RC(dev_alloc(c, pop_d, (size_t)n_pts));
+        RC(dev_alloc(c, pend_d, (size_t)n_pts * 4));
+        hipLaunchKernelGGL(k_dc_paths, dim3(blocks_for(n_pts)), dim3(256), 0, s, q, pts_d.as<int64_t>(), n_pts,
+                           lvoff_d.as<int64_t>(), (int32_t*)nullptr, lv_d.as<DcPathLevel>(), pop_d.as<uint8_t>(),
+                           pend_d.as<int32_t>());
+        HIPC(c, hipGetLastError());
+        std::vector<DcPathLevel> lv((size_t)lv_off[n_pts]);
+        std::vector<uint8_t> pop(n_pts);
+        std::vector<int32_t> pend(n_pts);
+        RC(down(c, lv.data(), lv_d, lv.size() * sizeof(DcPathLevel), s));
+        RC(down(c, pop.data(), pop_d, (size_t)n_pts, s));
+        RC(down(c, pend.data(), pend_d, (size_t)n_pts * 4, s));
+        HIPC(c, hipStreamSynchronize(s));
+        std::vector<DcStored> stored;
+        int64_t rb = 0;
+        for (int64_t t = 0; t < n_trees; ++t) {
+            const int64_t p0 = rec_offsets[t], np = rec_offsets[t + 1] - p0;
+            std::vector<int64_t> loff(np + 1);
+            for (int64_t i = 0; i <= np; ++i) loff[i] = lv_off[p0 + i] - lv_off[p0];
+            rec_base[t] = rb;
+            n_rec[t] = dc_tree_records(offsets[t], np, rec_points + p0, pop.data() + p0, pend.data() + p0,
+                                       loff.data(), lv.data() + lv_off[p0], &spines[t], &stored);
+            if (n_rec[t] > (int64_t)kMaxPayload)
+                return set_err(c, GP_EINVAL,
+                               "tree " + std::to_string(t) + ": too many parent-cache records in one tree");
+            rb += n_rec[t];
+        }
+        if (rb > INT32_MAX / 2) return set_err(c, GP_EINVAL, "population too large for one load");
+        const int64_t ns = (int64_t)stored.size();
+        if (ns > 0) {
+            std::vector<int64_t> nodes(ns);
+            std::vector<int32_t> ids(ns);
+            for (int64_t i = 0; i < ns; ++i) {
+                nodes[i] = stored[i].node;
+                ids[i] = stored[i].rec;
+            }
+            DevBuf nodes_d, cut_d, inc_d, ids_d;
+            RC(up(c, nodes_d, nodes.data(), (size_t)ns * 8, s));
+            RC(dev_alloc(c, cut_d, (size_t)ns));
+            hipLaunchKernelGGL(k_dc_cut_of, dim3(blocks_for(ns)), dim3(256), 0, s, q, nodes_d.as<int64_t>(), ns,
+                               cut_d.as<uint8_t>());
+            HIPC(c, hipGetLastError());
+            std::vector<uint8_t> cut(ns);
+            RC(down(c, cut.data(), cut_d, (size_t)ns, s));
+            HIPC(c, hipStreamSynchronize(s));
+            std::vector<int32_t> inc;
+            dc_store_words(stored, cut, &inc);
+            RC(up(c, inc_d, inc.data(), (size_t)ns * 4, s));
+            RC(up(c, ids_d, ids.data(), (size_t)ns * 4, s));
+            RC(dev_alloc(c, rec, (size_t)n * 4));
+            HIPC(c, launch_fill_i32(rec.as<int32_t>(), n, -1, s));
+            hipLaunchKernelGGL(k_dc_store, dim3(blocks_for(ns)), dim3(256), 0, s, q, nodes_d.as<int64_t>(),
+                               inc_d.as<int32_t>(), ids_d.as<int32_t>(), ns, rec.as<int32_t>());
+            HIPC(c, hipGetLastError());
+            HIPC(c, hipStreamSynchronize(s));
+            q.rec = rec.as<int32_t>();
+        }
+    }
+
+    // chunk roots, ascending, and their numbering
+    RC(dev_alloc(c, flags, (size_t)n));
+    unsigned long long nsel = 0;
+    HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
+    hipLaunchKernelGGL(k_dc_roots, dim3(blocks_for(n)), dim3(256), 0, s, q, flags.as<uint8_t>(),
+                       counter.as<unsigned long long>());
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipMemcpyAsync(&nsel, counter.p, 8, hipMemcpyDeviceToHost, s));
+    HIPC(c, hipStreamSynchronize(s));
+    const int64_t nch = (int64_t)nsel;
+    if (nch < n_trees || nch > INT32_MAX / 2) return set_err(c, GP_EINVAL, "population too large for one load");
+    DevBuf roots_d;
+    RC(dc_select(c, flags.as<uint8_t>(), n, nch, roots_d, s));
+    std::vector<int64_t> roots_asc(nch);
+    RC(down(c, roots_asc.data(), roots_d, (size_t)nch * 8, s));
+    HIPC(c, hipStreamSynchronize(s));
+    std::vector<int64_t> root, tstart, cbase;
+    std::vector<int32_t> ctree, ids;
+    if (!dc_number_chunks(roots_asc, offsets, n_trees, &root, &tstart, &ctree, &ids, &cbase))
+        return set_err(c, GP_EINVAL, "internal error: a tree without its root chunk");
+    std::vector<int32_t> rlen(nch), rend(nch);
+    {
+        DevBuf ids_d, rlen_d, rend_d;
+        RC(up(c, ids_d, ids.data(), (size_t)nch * 4, s));
+        RC(dev_alloc(c, rlen_d, (size_t)nch * 4));
+        RC(dev_alloc(c, rend_d, (size_t)nch * 4));
+        hipLaunchKernelGGL(k_dc_root_info, dim3(blocks_for(nch)), dim3(256), 0, s, q, roots_d.as<int64_t>(),
+                           ids_d.as<int32_t>(), nch, rlen_d.as<int32_t>(), rend_d.as<int32_t>());
+        HIPC(c, hipGetLastError());
+        // in ascending root order
+        std::vector<int32_t> a(nch), b(nch);
+        RC(down(c, a.data(), rlen_d, (size_t)nch * 4, s));
+        RC(down(c, b.data(), rend_d, (size_t)nch * 4, s));
+        HIPC(c, hipStreamSynchronize(s));
+        for (int64_t j = 0; j < nch; ++j) {
+            rlen[ids[j]] = a[j];
+            rend[ids[j]] = b[j];
+        }
+    }
+    roots_d.release();
+    std::vector<int64_t> code_len(nch), code_off(nch + 1, 0);
+    for (int64_t k = 0; k < nch; ++k) {
+        code_len[k] = (int64_t)rlen[k] + 1;
+        code_off[k + 1] = code_off[k] + code_len[k];
+    }
+    const int64_t n_code = code_off[nch];
+
+    // code emission: count the LOADs, then write
+    DevBuf root_d, ts_d, off_d, nin_d, par_d, nodes_d, ms_d, st_d, slot;
+    RC(up(c, root_d, root.data(), (size_t)nch * 8, s));
+    RC(up(c, ts_d, tstart.data(), (size_t)nch * 8, s));
+    RC(up(c, off_d, code_off.data(), (size_t)nch * 8, s));
+    RC(dev_alloc(c, nin_d, (size_t)nch * 4));
+    RC(dev_alloc(c, par_d, (size_t)nch * 4));
+    RC(dev_alloc(c, nodes_d, (size_t)nch * 8));
+    RC(dev_alloc(c, ms_d, (size_t)nch * 4));
+    RC(dev_alloc(c, st_d, (size_t)nch));
+    RC(dev_alloc(c, slot, (size_t)n));
+    q.slot = slot.as<uint8_t>();
+    HIPC(c, launch_fill_i32(par_d.as<int32_t>(), nch, -1, s));
+    DcChunks ck{};
+    ck.n = nch;
+    ck.root = root_d.as<int64_t>();
+    ck.tree_start = ts_d.as<int64_t>();
+    ck.code_off = off_d.as<int64_t>();
+    ck.n_in = nin_d.as<int32_t>();
+    ck.parent = par_d.as<int32_t>();
+    ck.nodes = nodes_d.as<int64_t>();
+    ck.max_slot = ms_d.as<int32_t>();
+    ck.stores = st_d.as<uint8_t>();
+    hipLaunchKernelGGL(k_dc_emit, dim3(blocks_for(nch)), dim3(256), 0, s, q, ck, 0);
+    HIPC(c, hipGetLastError());
+    std::vector<int32_t> n_in(nch);
+    RC(down(c, n_in.data(), nin_d, (size_t)nch * 4, s));
+    HIPC(c, hipStreamSynchronize(s));
+    std::vector<int64_t> in_off(nch + 1, 0);
+    for (int64_t k = 0; k < nch; ++k) {
+        if ((uint32_t)n_in[k] > kMaxPayload) return set_err(c, GP_EINVAL, "chunk reads too many child chunks");
+        in_off[k + 1] = in_off[k] + n_in[k];
+    }
+    if (in_off[nch] != nch - n_trees) return set_err(c, GP_EINVAL, "internal error: chunk inputs do not add up");
+    DevBuf inoff_d, ins_d;
+    RC(up(c, inoff_d, in_off.data(), (size_t)(nch + 1) * 8, s));
+    RC(dev_alloc(c, ins_d, (size_t)std::max<int64_t>(1, in_off[nch]) * 4));
+    RC(dev_alloc(c, out->code, (size_t)(n_code + 1) * 4));
+    HIPC(c, launch_fill_i32((int32_t*)out->code.p + n_code, 1, 0, s));   // one word past the end for the fetch-ahead
+    ck.in_off = inoff_d.as<int64_t>();
+    ck.inputs = ins_d.as<int32_t>();
+    ck.code = out->code.as<uint32_t>();
+    hipLaunchKernelGGL(k_dc_emit, dim3(blocks_for(nch)), dim3(256), 0, s, q, ck, 1);
+    HIPC(c, hipGetLastError());
+    std::vector<int32_t> parent(nch), ins((size_t)in_off[nch]), max_slot(nch);
+    std::vector<int64_t> nodes(nch);
+    std::vector<uint8_t> stores(nch);
+    RC(down(c, parent.data(), par_d, (size_t)nch * 4, s));
+    RC(down(c, nodes.data(), nodes_d, (size_t)nch * 8, s));
+    RC(down(c, max_slot.data(), ms_d, (size_t)nch * 4, s));
+    RC(down(c, stores.data(), st_d, (size_t)nch, s));
+    RC(down(c, ins.data(), ins_d, ins.size() * 4, s));
+
+    // subtrees of at least index_min_size nodes (co-evaluation's path search)
+    std::vector<int64_t> big_nodes;
+    std::vector<int32_t> big_end;
+    if (index_min_size > 0) {
+        HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
+        hipLaunchKernelGGL(k_dc_big, dim3(blocks_for(n)), dim3(256), 0, s, q, flags.as<uint8_t>(), index_min_size,
+                           counter.as<unsigned long long>());
+        HIPC(c, hipGetLastError());
+        HIPC(c, hipMemcpyAsync(&nsel, counter.p, 8, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        const int64_t nb = (int64_t)nsel;
+        if (nb > 0) {
+            DevBuf big_d, bend_d;
+            RC(dc_select(c, flags.as<uint8_t>(), n, nb, big_d, s));
+            RC(dev_alloc(c, bend_d, (size_t)nb * 4));
+            hipLaunchKernelGGL(k_dc_ends, dim3(blocks_for(nb)), dim3(256), 0, s, q, big_d.as<int64_t>(), nb,
+                               bend_d.as<int32_t>());
+            HIPC(c, hipGetLastError());
+            big_nodes.resize(nb);
+            big_end.resize(nb);
+            RC(down(c, big_nodes.data(), big_d, (size_t)nb * 8, s));
+            RC(down(c, big_end.data(), bend_d, (size_t)nb * 4, s));
+            HIPC(c, hipStreamSynchronize(s));
+        }
+    }
+    HIPC(c, hipStreamSynchronize(s));
+
+    // the population's tables, as assemble_population builds them
+    out->vtype = vtype;
+    out->n_inputs = n_inputs;
+    out->n_trees = n_trees;
+    out->chunk_nodes = chunk_nodes;
+    out->tree_nodes.resize(n_trees);
+    for (int64_t t = 0; t < n_trees; ++t) out->tree_nodes[t] = offsets[t + 1] - offsets[t];
+    out->total_nodes = n;
+    out->n_chunks = nch;
+    out->n_code = n_code;
+    out->rec_base = rec_base;
+    out->chunk_n_in = n_in;
+    out->chunk_tree = ctree;
+    out->promo_src.clear();
+    out->promo_in.clear();
+    out->promo_rows.clear();
+    out->chunk_path.clear();
+    out->leaves.clear();
+    out->spines.clear();
+    out->spine_of.clear();
+    std::vector<int64_t> out_slot(nch), path(nch, 0);
+    {
+        int64_t next_slot = n_trees;
+        for (int64_t t = 0; t < n_trees; ++t)
+            for (int64_t k = cbase[t]; k < cbase[t + 1]; ++k) out_slot[k] = (k == cbase[t + 1] - 1) ? t : next_slot++;
+    }
+    for (int64_t k = nch - 1; k >= 0; --k) {
+        const int64_t last = cbase[ctree[k] + 1] - 1;
+        const bool top = k == last;
+        if (top != (parent[k] < 0) || (!top && (parent[k] <= k || parent[k] > last)))
+            return set_err(c, GP_EINVAL, "internal error: inconsistent chunk graph");
+        path[k] = nodes[k] + (top ? 0 : path[parent[k]]);
+    }
+    std::vector<DevChunk> dch(nch);
+    std::vector<int32_t> chunk_in((size_t)in_off[nch]);
+    std::vector<SpineLvl> levels;
+    out->kept_chunks.assign(n_trees, {});
+    out->kept_max_stack.assign(n_trees, 0);
+    out->cuts.assign(n_trees, {});
+    out->max_stack = 0;
+    int64_t n_records = 0;
+    for (int64_t t = 0; t < n_trees; ++t) {
+        const int64_t b = cbase[t], m = cbase[t + 1] - b, s0 = offsets[t];
+        auto& kc = out->kept_chunks[t];
+        kc.resize(m);
+        auto& cl = out->cuts[t];
+        cl.reserve(m);
+        int32_t tms = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t k = b + i;
+            DevChunk& d = dch[k];
+            d.code_off = code_off[k];
+            d.code_len = (int32_t)code_len[k];
+            d.parent = parent[k];
+            d.out_slot = (int32_t)out_slot[k];
+            d.in_off = (int32_t)in_off[k];
+            d.rec_base = (int32_t)rec_base[t];
+            d.n_in = n_in[k];
+            Chunk& ch = kc[i];
+            ch.code_off = code_off[k];
+            ch.code_len = code_len[k];
+            ch.parent = parent[k] >= 0 ? parent[k] - (int32_t)b : -1;
+            ch.root_node = root[k] - s0;
+            ch.nodes = nodes[k];
+            ch.path_nodes = path[k];
+            ch.end_node = index_min_size > 0 ? rend[k] : -1;
+            ch.dev_src = -1;
+            ch.stores = stores[k] != 0;
+            ch.vec_slot = out_slot[k];
+            ch.src_vec = -1;
+            ch.inputs.resize(n_in[k]);
+            for (int64_t j = in_off[k]; j < in_off[k + 1]; ++j) {
+                chunk_in[j] = (int32_t)out_slot[ins[j]];
+                ch.inputs[j - in_off[k]] = ins[j] - (int32_t)b;
+            }
+            if (n_in[k] == 0) out->leaves.emplace_back(path[k], (int32_t)k);
+            tms = std::max(tms, max_slot[k] + 1);
+            cl.push_back(Pop::CutSlot{(int32_t)ch.root_node, rend[k], (int32_t)out_slot[k]});
+        }
+        std::sort(cl.begin(), cl.end(), [](const Pop::CutSlot& x, const Pop::CutSlot& y) { return x.node < y.node; });
+        if (tms > compile_stack_slots()) return set_err(c, GP_EINVAL, "internal error: stack bound exceeded");
+        out->kept_max_stack[t] = tms;
+        out->max_stack = std::max(out->max_stack, tms);
+        for (auto& sp : spines[t]) {
+            const uint64_t key = ((uint64_t)t << 32) | (uint32_t)sp.point;
+            if (out->spine_of.count(key)) continue;
+            SpineInfo si;
+            si.tree = (int32_t)t;
+            si.at_point = sp.at_point;
+            si.level_off = (int64_t)levels.size();
+            si.n_levels = (int32_t)sp.levels.size();
+            si.removed_nodes = sp.child_nodes_removed;
+            for (auto& lv : sp.levels) levels.push_back(SpineLvl{lv.fside, lv.sib, lv.par, 0});
+            out->spine_of[key] = (int32_t)out->spines.size();
+            out->spines.push_back(si);
+        }
+        n_records += n_rec[t];
+    }
+    out->n_records = n_records;
+    if (index_min_size > 0) {
+        out->big_ends.assign(n_trees, {});
+        out->big_built.assign(n_trees, 1);
+        int64_t t = 0;
+        for (size_t i = 0; i < big_nodes.size(); ++i) {
+            while (big_nodes[i] >= offsets[t + 1]) ++t;
+            out->big_ends[t].push_back({(int32_t)(big_nodes[i] - offsets[t]), big_end[i]});
+        }
+    }
+    std::stable_sort(out->leaves.begin(), out->leaves.end(),
+                     [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                         return x.first > y.first;
+                     });
+    RC(up(c, out->chunks, dch.data(), dch.size() * sizeof(DevChunk), s));
+    RC(up(c, out->chunk_in, chunk_in.data(), chunk_in.size() * 4, s));
+    RC(up(c, out->levels, levels.data(), levels.size() * sizeof(SpineLvl), s));
+    HIPC(c, hipStreamSynchronize(s));
+    return GP_OK;
+}
+
+}  // namespace gpe

@@ -114,6 +114,7 @@ struct Pop {
     int n_inputs = 0;
     int layout = 0;
     bool auto_chunk = false;                // chunk size may be re-tuned
+    bool device_compiled = false;           // compiled on the device (re-chunked there too)
     // host copy of the trees, for re-chunking by the autotuner
     std::vector<uint8_t, NoInitAlloc<uint8_t>> host_ops;
     std::vector<int64_t> host_offsets, host_rec_points, host_rec_offsets;
@@ -253,6 +254,26 @@ int enqueue_incremental(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases
 // rounds synchronously on s; interp receives the nodes actually executed.
 int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, const CaseSet* cs,
                    bool want_roots, hipStream_t s, IncOut* out, int64_t* launches, int64_t* rounds);
+// Device tree index (gp_index_trees without the lock): on the context stream,
+// waits for the result.
+int index_trees(Ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+                int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler, double* device_ms);
+// Compile a population of prefix trees on the device (devcompile.hip): the
+// same programs and tables as build_population.  dops/doffs: the trees and
+// offsets in device memory (dops 16-byte aligned); offsets: host copy;
+// host_ops (may be null): host copy, for error messages; record points as
+// build_population's, host arrays.  Runs on the context stream s and waits.
+int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, const uint8_t* dops,
+                              const int64_t* doffs, const int64_t* offsets, const uint8_t* host_ops,
+                              const int64_t* rec_points, const int64_t* rec_offsets, int64_t chunk_nodes,
+                              int64_t index_min_size, Pop* out, hipStream_t s);
+// build_population on the device for prefix trees given in host memory
+// (host_ops) or device memory (dev_ops); offsets in host memory.  When
+// ops_keep is given, it receives a device copy of the trees (32 bytes of
+// padding) for the population's tree_ops.
+int build_population_device(Ctx* c, int vtype, int n_inputs, int64_t n_trees, const uint8_t* host_ops,
+                            const uint8_t* dev_ops, const int64_t* offsets, const int64_t* rec_points,
+                            const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, DevBuf* ops_keep);
 int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p);
 int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_t T);
 int compile_stack_slots();

@@ -249,6 +249,42 @@ int build_population(Ctx* c, int vtype, int layout, int n_inputs, int64_t n_tree
     return assemble_population(c, vtype, n_inputs, progs, tree_nodes, chunk_nodes, out, stream);
 }
 
+int build_population_device(Ctx* c, int vtype, int n_inputs, int64_t n_trees, const uint8_t* host_ops,
+                            const uint8_t* dev_ops, const int64_t* offsets, const int64_t* rec_points,
+                            const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, DevBuf* ops_keep)
+{
+    if (vtype != GP_F32 && vtype != GP_BOOL) return set_err(c, GP_EINVAL, "unknown value type");
+    if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(c, GP_EINVAL, "n_inputs must be 1..64");
+    if (n_trees < 1 || (!host_ops && !dev_ops) || !offsets) return set_err(c, GP_EINVAL, "empty population");
+    if (n_trees > INT32_MAX / 2) return set_err(c, GP_EINVAL, "too many trees");
+    if (offsets[0] != 0) return set_err(c, GP_EINVAL, "offsets[0] must be 0");
+    for (int64_t t = 0; t < n_trees; ++t)
+        if (offsets[t + 1] <= offsets[t]) return set_err(c, GP_EINVAL, "tree " + std::to_string(t) + " is empty");
+    if (rec_points && !rec_offsets) return set_err(c, GP_EINVAL, "record_points needs record_offsets");
+    if (rec_offsets && rec_offsets[0] != 0) return set_err(c, GP_EINVAL, "record_offsets[0] must be 0");
+    const int64_t total = offsets[n_trees];
+    if (chunk_nodes <= 0) chunk_nodes = auto_chunk_nodes(vtype, total, n_trees, 0);
+    chunk_nodes = std::max<int64_t>(chunk_nodes, 16);
+    hipStream_t s = c->stream;
+    // the index reads the trees with 16-byte loads: a copy of our own unless
+    // the caller's device array is aligned and need not be kept
+    DevBuf ops_buf, offs;
+    const uint8_t* dops = dev_ops;
+    if (!dev_ops || ((uintptr_t)dev_ops & 15) != 0 || ops_keep) {
+        RC(dev_alloc(c, ops_buf, (size_t)total + 32));
+        HIPC(c, hipMemcpyAsync(ops_buf.p, host_ops ? host_ops : dev_ops, (size_t)total,
+                               host_ops ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        dops = ops_buf.as<uint8_t>();
+    }
+    RC(upload(c, offs, offsets, (size_t)(n_trees + 1) * sizeof(int64_t), s));
+    RC(device_compile_population(c, vtype, n_inputs, n_trees, dops, offs.as<int64_t>(), offsets, host_ops,
+                                 rec_points, rec_offsets, chunk_nodes, kBigSubtree, out, s));
+    out->layout = GP_PREFIX;
+    out->device_compiled = true;
+    if (ops_keep) ops_keep->swap(ops_buf);
+    return GP_OK;
+}
+
 // One copy for k_splice, cut into pieces that end on 64 KiB boundaries of
 // the destination (one workgroup each).
 static void add_splice_item(std::vector<SpliceItem>& items, const uint8_t* src, int64_t dst, int64_t len)
@@ -1172,6 +1208,44 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
     std::lock_guard<std::mutex> lk(ctx->mu);
     HIPC(ctx, hipSetDevice(ctx->device));
     auto p = std::make_shared<Pop>();
+    if (flags & (GP_DEVICE_PTR | GP_DEVICE_COMPILE)) {
+        if (layout != GP_PREFIX) return set_err(ctx, GP_EINVAL, "device compilation takes prefix trees");
+        if (!ops || !offsets || n_trees < 1) return set_err(ctx, GP_EINVAL, "empty population");
+        if (n_trees > INT32_MAX / 2) return set_err(ctx, GP_EINVAL, "too many trees");
+        const bool on_dev = (flags & GP_DEVICE_PTR) != 0;
+        std::vector<int64_t> hoff;
+        const int64_t* offs = offsets;
+        if (on_dev) {
+            hoff.resize(n_trees + 1);
+            HIPC(ctx, hipMemcpy(hoff.data(), offsets, (size_t)(n_trees + 1) * 8, hipMemcpyDeviceToHost));
+            offs = hoff.data();
+        }
+        DevBuf keep;
+        RC(build_population_device(ctx, vtype, n_inputs, n_trees, on_dev ? nullptr : ops, on_dev ? ops : nullptr,
+                                   offs, record_points, record_offsets, chunk_nodes, p.get(),
+                                   (flags & GP_KEEP_TREES) ? &keep : nullptr));
+        p->auto_chunk = chunk_nodes <= 0;
+        const size_t nb = (size_t)offs[n_trees];
+        if (on_dev) {
+            p->host_ops.resize(nb);
+            HIPC(ctx, hipMemcpy(p->host_ops.data(), ops, nb, hipMemcpyDeviceToHost));
+        } else {
+            p->host_ops.assign(ops, ops + nb);
+        }
+        p->host_offsets.assign(offs, offs + n_trees + 1);
+        if (flags & GP_KEEP_TREES) {
+            p->tree_ops.swap(keep);
+            p->tree_off = p->host_offsets;
+        }
+        if (p->auto_chunk && record_points) {
+            p->host_rec_offsets.assign(record_offsets, record_offsets + n_trees + 1);
+            p->host_rec_points.assign(record_points, record_points + record_offsets[n_trees]);
+        }
+        gp_handle h = ctx->next_handle++;
+        ctx->pops[h] = p;
+        *pop_out = h;
+        return GP_OK;
+    }
     RC(build_population(ctx, vtype, layout, n_inputs, n_trees, ops, offsets, record_points, record_offsets,
                         chunk_nodes, p.get(), ctx->stream, true));
     p->auto_chunk = chunk_nodes <= 0;
@@ -1218,6 +1292,106 @@ int gp_population_info(gp_ctx* ctx, gp_handle pop, gp_pop_info* out)
     out->device_bytes = (int64_t)b;
     out->max_stack = p->max_stack;
     out->chunk_nodes = (int32_t)p->chunk_nodes;
+    return GP_OK;
+}
+
+// The compiled form of a population as one byte string: sections, each an
+// int64 byte count and its bytes, in the order documented in gpeval.h.
+static int dump_population(Ctx* c, const Pop* p, std::vector<uint8_t>* out)
+{
+    out->clear();
+    auto sec = [&](const void* src, size_t bytes) {
+        const int64_t b = (int64_t)bytes;
+        const uint8_t* q = (const uint8_t*)&b;
+        out->insert(out->end(), q, q + 8);
+        out->insert(out->end(), (const uint8_t*)src, (const uint8_t*)src + bytes);
+    };
+    auto dev_sec = [&](const DevBuf& b, size_t bytes) -> int {
+        std::vector<uint8_t> h(bytes);
+        if (bytes) HIPC(c, hipMemcpy(h.data(), b.p, bytes, hipMemcpyDeviceToHost));
+        sec(h.data(), bytes);
+        return GP_OK;
+    };
+    const int64_t head[8] = {p->n_trees, p->n_chunks, p->n_code, p->n_records, p->max_stack, p->chunk_nodes,
+                             p->total_nodes, p->layout};
+    sec(head, sizeof(head));
+    RC(dev_sec(p->code, (size_t)(p->n_code + 1) * 4));
+    RC(dev_sec(p->chunks, (size_t)p->n_chunks * sizeof(DevChunk)));
+    int64_t n_in = 0, n_lv = 0;
+    for (int32_t v : p->chunk_n_in) n_in += v;
+    for (const auto& si : p->spines) n_lv += si.n_levels;
+    RC(dev_sec(p->chunk_in, (size_t)n_in * 4));
+    sec(p->chunk_n_in.data(), p->chunk_n_in.size() * 4);
+    sec(p->chunk_tree.data(), p->chunk_tree.size() * 4);
+    sec(p->rec_base.data(), p->rec_base.size() * 8);
+    std::vector<int64_t> v;
+    for (const auto& lf : p->leaves) {
+        v.push_back(lf.first);
+        v.push_back(lf.second);
+    }
+    sec(v.data(), v.size() * 8);
+    v.clear();
+    for (const auto& si : p->spines) {
+        for (int64_t x : {(int64_t)si.tree, (int64_t)si.at_point, si.level_off, (int64_t)si.n_levels, si.removed_nodes})
+            v.push_back(x);
+    }
+    sec(v.data(), v.size() * 8);
+    std::vector<std::pair<uint64_t, int32_t>> keys(p->spine_of.begin(), p->spine_of.end());
+    std::sort(keys.begin(), keys.end());
+    v.clear();
+    for (const auto& kv : keys) {
+        v.push_back((int64_t)kv.first);
+        v.push_back(kv.second);
+    }
+    sec(v.data(), v.size() * 8);
+    RC(dev_sec(p->levels, (size_t)n_lv * sizeof(SpineLvl)));
+    v.clear();
+    for (const auto& be : p->big_ends) {
+        v.push_back((int64_t)be.size());
+        for (const auto& x : be) {
+            v.push_back(x.first);
+            v.push_back(x.second);
+        }
+    }
+    sec(v.data(), v.size() * 8);
+    v.clear();
+    for (const auto& cl : p->cuts) {
+        v.push_back((int64_t)cl.size());
+        for (const auto& x : cl)
+            for (int64_t y : {(int64_t)x.node, (int64_t)x.end, (int64_t)x.slot}) v.push_back(y);
+    }
+    sec(v.data(), v.size() * 8);
+    v.clear();
+    for (const auto& kc : p->kept_chunks) {
+        v.push_back((int64_t)kc.size());
+        for (const Chunk& ch : kc) {
+            for (int64_t y : {ch.code_off, ch.code_len, (int64_t)ch.parent, ch.root_node, ch.nodes, ch.path_nodes,
+                              ch.end_node, ch.dev_src, (int64_t)ch.stores, ch.vec_slot, ch.src_vec,
+                              (int64_t)ch.inputs.size()})
+                v.push_back(y);
+            for (int32_t y : ch.inputs) v.push_back(y);
+        }
+    }
+    sec(v.data(), v.size() * 8);
+    sec(p->kept_max_stack.data(), p->kept_max_stack.size() * 4);
+    sec(p->tree_nodes.data(), p->tree_nodes.size() * 8);
+    return GP_OK;
+}
+
+int gp_population_dump(gp_ctx* ctx, gp_handle pop, uint8_t* out, int64_t cap, int64_t* size)
+{
+    if (!ctx || !size) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    auto it = ctx->pops.find(pop);
+    if (it == ctx->pops.end()) return set_err(ctx, GP_EINVAL, "unknown population handle");
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<uint8_t> d;
+    RC(dump_population(ctx, it->second.get(), &d));
+    *size = (int64_t)d.size();
+    if (!out) return GP_OK;
+    if (cap < (int64_t)d.size()) return set_err(ctx, GP_EINVAL, "dump buffer too small");
+    std::memcpy(out, d.data(), d.size());
     return GP_OK;
 }
 
@@ -1927,9 +2101,19 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         if (cn != p->chunk_nodes) {
             q = std::make_shared<Pop>();
             const bool rec = !p->host_rec_points.empty() || !p->host_rec_offsets.empty();
-            RC(build_population(ctx, p->vtype, p->layout, p->n_inputs, p->n_trees, p->host_ops.data(),
-                                p->host_offsets.data(), rec ? p->host_rec_points.data() : nullptr,
-                                rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), ctx->stream, true));
+            if (p->device_compiled) {
+                // from the kept device copy of the trees when there is one
+                const bool kept = p->tree_ops.p && p->tree_off == p->host_offsets;
+                RC(build_population_device(ctx, p->vtype, p->n_inputs, p->n_trees,
+                                           kept ? nullptr : p->host_ops.data(),
+                                           kept ? p->tree_ops.as<uint8_t>() : nullptr, p->host_offsets.data(),
+                                           rec ? p->host_rec_points.data() : nullptr,
+                                           rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), nullptr));
+            } else {
+                RC(build_population(ctx, p->vtype, p->layout, p->n_inputs, p->n_trees, p->host_ops.data(),
+                                    p->host_offsets.data(), rec ? p->host_rec_points.data() : nullptr,
+                                    rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), ctx->stream, true));
+            }
             qp = q.get();
         }
         for (int v = 0; v < variant_count(); ++v) {
@@ -1976,7 +2160,7 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
 }
 
 // Arguments shared by both index entry points.
-static int ix_check_args(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+static int ix_check_args(Ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
                          int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent)
 {
     if (n_inputs < 1 || n_inputs > kMaxInputs) return set_err(ctx, GP_EINVAL, "n_inputs must be 1..64");
@@ -2065,13 +2249,12 @@ static IxParams ix_params(int n_inputs, int64_t n_trees, const uint8_t* ops, con
     return q;
 }
 
-int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
-                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
-                   double* device_ms)
+}  // extern "C"
+
+int gpe::index_trees(Ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+                     int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
+                     double* device_ms)
 {
-    if (!ctx) return GP_EINVAL;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    HIPC(ctx, hipSetDevice(ctx->device));
     RC(ix_check_args(ctx, n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent));
     IxParams q = ix_params(n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent, strahler);
     int64_t len[kIxMaxLevels];
@@ -2089,6 +2272,18 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
     q.seg = seg.as<int32_t>();
     q.bempty = strahler ? bempty.as<uint8_t>() : nullptr;
     return ix_run(ctx, q, bsum.as<int32_t>(), flag.as<int32_t>(), nb, len, device_ms);
+}
+
+extern "C" {
+
+int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
+                   int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
+                   double* device_ms)
+{
+    if (!ctx) return GP_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    HIPC(ctx, hipSetDevice(ctx->device));
+    return index_trees(ctx, n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent, strahler, device_ms);
 }
 
 static_assert(GP_INDEX_NOALLOC_MAX_NODES == kIxStaticMaxNodes, "header and scratch array disagree");

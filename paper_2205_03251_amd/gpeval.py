@@ -19,6 +19,7 @@ GP_OK, GP_EINVAL, GP_ENOMEM, GP_EBUDGET, GP_EDEVICE, GP_ENOTFOUND, GP_EBUSY = 0,
 GP_F32, GP_BOOL = 0, 1
 GP_PREFIX, GP_POSTFIX = 0, 1
 GP_DEVICE_PTR, GP_ASYNC, GP_PER_TREE, GP_NO_GRAPH, GP_KEEP_TREES, GP_COEVAL = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+GP_DEVICE_COMPILE = 0x40
 GP_JOB_FULL, GP_JOB_INCREMENTAL = 0, 1
 ERRNAMES = {GP_EINVAL: "EINVAL", GP_ENOMEM: "ENOMEM", GP_EBUDGET: "EBUDGET", GP_EDEVICE: "EDEVICE",
             GP_ENOTFOUND: "ENOTFOUND", GP_EBUSY: "EBUSY"}
@@ -30,6 +31,7 @@ EXPORTS = [
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
     "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree", "gp_index_trees",
     "gp_index_trees_noalloc", "gp_population_results", "gp_evolve", "gp_population_ops", "gp_valu_calibration",
+    "gp_population_dump",
 ]
 INDEX_NOALLOC_MAX_NODES = 4194304
 
@@ -129,6 +131,7 @@ def lib() -> C.CDLL:
     h.gp_load_population.argtypes = [P, C.c_int, C.c_int, C.c_int, I64, P, P, P, P, I64, C.c_uint32,
                                      C.POINTER(I64)]
     h.gp_population_info.argtypes = [P, I64, C.POINTER(PopInfo)]
+    h.gp_population_dump.argtypes = [P, I64, P, I64, C.POINTER(I64)]
     h.gp_index_trees.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
     h.gp_index_trees_noalloc.argtypes = [P, C.c_int, I64, P, P, I64, P, P, P, P, C.POINTER(C.c_double)]
     h.gp_population_results.argtypes = [P, I64, I64, C.c_uint32, P, P]
@@ -337,14 +340,28 @@ class Context:
         return out.value
 
     def load_population(self, vtype, ops, offsets, n_inputs=1, layout=GP_PREFIX, record_points=None,
-                        record_offsets=None, chunk_nodes=0, keep_trees=False) -> int:
-        ops = _np(ops, np.uint8)
-        offsets = _np(offsets, np.int64)
+                        record_offsets=None, chunk_nodes=0, keep_trees=False, device_compile=False) -> int:
+        """gp_load_population.  ops and offsets are host arrays, or uint8 and
+        int64 tensors on the context's device (then compiled there);
+        device_compile compiles host arrays on the device."""
+        flags = GP_KEEP_TREES if keep_trees else 0
+        if hasattr(ops, "is_cuda") and ops.is_cuda:
+            import torch
+            if ops.dtype != torch.uint8 or offsets.dtype != torch.int64 or not offsets.is_cuda:
+                raise TypeError("device trees: uint8 ops and int64 offsets, both on the device")
+            ops, offsets = ops.contiguous(), offsets.contiguous()
+            n_trees = offsets.numel() - 1
+            flags |= GP_DEVICE_PTR
+        else:
+            ops = _np(ops, np.uint8)
+            offsets = _np(offsets, np.int64)
+            n_trees = len(offsets) - 1
+            if device_compile:
+                flags |= GP_DEVICE_COMPILE
         rp = _np(record_points, np.int64) if record_points is not None else None
         ro = _np(record_offsets, np.int64) if record_offsets is not None else None
         out = I64(0)
-        flags = GP_KEEP_TREES if keep_trees else 0
-        self._check(lib().gp_load_population(self._h, vtype, layout, n_inputs, len(offsets) - 1, _ptr(ops),
+        self._check(lib().gp_load_population(self._h, vtype, layout, n_inputs, n_trees, _ptr(ops),
                                              _ptr(offsets), _ptr(rp), _ptr(ro), chunk_nodes, flags,
                                              C.byref(out)))
         return out.value
@@ -414,6 +431,14 @@ class Context:
         info = PopInfo()
         self._check(lib().gp_population_info(self._h, pop, C.byref(info)))
         return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def population_dump(self, pop) -> bytes:
+        """gp_population_dump: the compiled form of a population as bytes."""
+        size = I64(0)
+        self._check(lib().gp_population_dump(self._h, pop, None, 0, C.byref(size)))
+        buf = np.empty(max(size.value, 1), np.uint8)
+        self._check(lib().gp_population_dump(self._h, pop, _ptr(buf), buf.size, C.byref(size)))
+        return buf[:size.value].tobytes()
 
     def free(self, h):
         self._check(lib().gp_free(self._h, h))
