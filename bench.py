@@ -71,6 +71,20 @@ def workload_inputs(name: str, scale: float, threads: int):
     raise SystemExit(f"unknown workload {name}")
 
 
+def load_timed(ctx, vtype, pop, host=True, **kw):
+    """Load pop compiled on the device (returned, with its wall time) and,
+    when host is set, the same trees compiled on the host (timed, freed)."""
+    host_s = None
+    if host:
+        t = time.perf_counter()
+        h = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, **kw)
+        host_s = time.perf_counter() - t
+        ctx.free(h)
+    t = time.perf_counter()
+    ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, device_compile=True, **kw)
+    return ph, time.perf_counter() - t, host_s
+
+
 def record_lists(n_trees, kids):
     pts = [[] for _ in range(n_trees)]
     for p, c in zip(kids.parent, kids.point):
@@ -223,9 +237,7 @@ def measure_config(ctx, g, name, threads, cpu, cpu_budget_s, no_cpu=False):
         ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, T)
     else:
         ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
-    t1 = time.perf_counter()
-    ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs)
-    load_s = time.perf_counter() - t1
+    ph, load_s, host_load_s = load_timed(ctx, vtype, pop)
     v, _ = ctx.autotune(ph, ch)
     info = ctx.population_info(ph)
     _, fit, st = ctx.evaluate_full(ph, ch, vtype, n, T, roots=False)
@@ -244,7 +256,7 @@ def measure_config(ctx, g, name, threads, cpu, cpu_budget_s, no_cpu=False):
     func_nodes = (total - n) // 2
     achieved = func_nodes * T / (kernel_ms * 1e-3)
     out = {**desc, "total_nodes": total, "chunk_nodes": info["chunk_nodes"], "variant": g.variant_names()[v],
-           "host_load_s": round(load_s, 3),
+           "device_load_s": round(load_s, 3), "host_load_s": round(host_load_s, 3),
            "batched_ms": round(batched_ms, 4), "batched_wall_ms": round(float(np.median(wms)), 4),
            "per_tree_ms": round(per_tree_ms, 3), "batched_speedup": round(per_tree_ms / batched_ms, 1),
            "equivalent_gpops": round(total * T / (batched_ms * 1e-3) / 1e9, 2),
@@ -527,16 +539,15 @@ def main():
         ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, T)
     else:
         ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
-    t1 = time.perf_counter()
     if kids is not None:
         rp, ro = record_lists(pop.n_trees, kids)
-        ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, record_points=rp,
-                                 record_offsets=ro, chunk_nodes=args.chunk_nodes, keep_trees=True)
+        ph, load_s, host_load_s = load_timed(ctx, vtype, pop, host=not args.no_compare, record_points=rp,
+                                             record_offsets=ro, chunk_nodes=args.chunk_nodes, keep_trees=True)
     else:
-        ph = ctx.load_population(vtype, pop.ops, pop.offsets, n_inputs=pop.n_inputs, chunk_nodes=args.chunk_nodes)
-    load_s = time.perf_counter() - t1
+        ph, load_s, host_load_s = load_timed(ctx, vtype, pop, host=not args.no_compare,
+                                             chunk_nodes=args.chunk_nodes)
     info = ctx.population_info(ph)
-    log(f"[bench] loaded in {load_s:.1f} s: {info}")
+    log(f"[bench] loaded in {load_s:.2f} s compiled on the device ({host_load_s} s on the host): {info}")
 
     tuned = None
     if args.variant:
@@ -710,8 +721,7 @@ def main():
                                "achieved": round(ix_gbps, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                                "frac": round(ix_gbps / PEAK_HBM_GBPS, 4), "algorithmic_bytes": ix_bytes,
                                "all_valid": all_valid, "with_strahler_ms": round(ims_sn, 3),
-                               "max_strahler": max_sn, "host_load_s": round(load_s, 2),
-                               "note": "host_load_s: validation, compilation and upload of the same trees on the host"}
+                               "max_strahler": max_sn}
 
     # the two legs of the step, each timed on its own (HIP events on the library stream)
     bms = [ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, device=True, fit_buf=fit_buf)[2]["device_ms"]
@@ -735,7 +745,16 @@ def main():
             log("[bench] full re-evaluation of the built children ...")
             n_kids = len(child_offs) - 1
             t_c = time.perf_counter()
-            cph = ctx.load_population(vtype, child_ops.cpu().numpy(), child_offs, n_inputs=pop.n_inputs)
+            c_host = child_ops.cpu().numpy()
+            hph = ctx.load_population(vtype, c_host, child_offs, n_inputs=pop.n_inputs)
+            c_host_load_s = time.perf_counter() - t_c
+            ctx.free(hph)
+            del c_host
+            # the children as the splice left them, in device memory, compiled there
+            torch.cuda.synchronize()
+            t_c = time.perf_counter()
+            cph = ctx.load_population(vtype, child_ops, torch.from_numpy(child_offs).to("cuda:0"),
+                                      n_inputs=pop.n_inputs)
             c_load_s = time.perf_counter() - t_c
             ctx.autotune(cph, ch)
             rms = [ctx.evaluate_full(cph, ch, vtype, n_kids, T, roots=False)[2]["device_ms"] for _ in range(3)]
@@ -743,7 +762,8 @@ def main():
             inc_ms = inc_stats["device_ms"]
             extra["compare"].update({
                 "children_full_reeval_ms": round(reeval_ms, 3), "children_incremental_ms": round(inc_ms, 3),
-                "incremental_speedup": round(reeval_ms / inc_ms, 1), "children_host_load_s": round(c_load_s, 2),
+                "incremental_speedup": round(reeval_ms / inc_ms, 1), "children_device_load_s": round(c_load_s, 2),
+                "children_host_load_s": round(c_host_load_s, 2),
                 "children_full_reeval_gpops": round(int(child_offs[-1]) * T / (reeval_ms * 1e-3) / 1e9, 1)})
             ctx.free(cph)
     del child_ops
@@ -807,7 +827,11 @@ def main():
         "config": {**desc, "chunk_nodes": final_info["chunk_nodes"], "variant": used.get("variant", tuned),
                    "parallelism": "single_gpu"},
         "interpreted_gpops": round(interp_nodes * T / (ms_per_step * 1e-3) / 1e9, 3),
-        "host_load_s": round(load_s, 2),
+        "load": {"device_compile_s": round(load_s, 2),
+                 "host_compile_s": None if host_load_s is None else round(host_load_s, 2),
+                 "note": "loading the parents: validation, compilation into chunked programs and upload, on the "
+                         "device (the population benchmarked) and on the host (the same programs, timed and "
+                         "freed)"},
         "value_note": "equivalent GPop/s of the whole step: (parent nodes + child nodes) x cases / step time; the "
                       "two legs' own rates are under legs",
         "roofline": roofline,

@@ -16,16 +16,20 @@ SOURCES = ["prep.cpp", "kernels.hip", "index.hip", "devcompile.hip", "runtime.hi
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off",                      # no fused multiply-add anywhere
-    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]
+# The interpreter's dispatch loops branch on wave-uniform values only; keeping
+# those regions unstructured keeps the loops tight.  Only for that file: with
+# it, a divergent region around a uniform branch can lose the merge of a
+# boolean's lane mask (seen in the device compiler's persistent loops).
+EXTRA = {"kernels.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

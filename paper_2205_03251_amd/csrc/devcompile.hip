@@ -10,9 +10,12 @@
 // given code offsets (host prefix sums over per-chunk lengths); one thread per
 // chunk counts its LOADs, then writes its code straight into the population's
 // program.  The host keeps only per-chunk and per-record tables.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
 #include <unordered_map>
 
 #include "devcompile_core.h"
@@ -40,6 +43,10 @@ struct DevMem {
     {
         return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __device__ static uint64_t fetch_or64(uint64_t* p, uint64_t v)
+    {
+        return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ static void publish() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
     __device__ static void after_count() { asm volatile("" ::: "memory"); }
     __device__ static void err(int32_t* p, int32_t v) { atomicOr(p, v); }
@@ -55,39 +62,71 @@ __global__ __launch_bounds__(256) void k_dc_up(DcNodes q)
     for (int64_t v = g; v >= 0;) v = dc_step<DevMem>(q, s, e, v);
 }
 
-// Adds the wave's count of set flags to *count.
-__device__ __forceinline__ void dc_count(bool f, unsigned long long* count)
+// The same with the packed hand-off (chunk targets up to kDcPackMaxC): the
+// values of a finished node reach its parent in the arrival atomic itself;
+// the per-node stores are read only by later launches.
+struct DevMemPacked : DevMem {
+    __device__ static void st(int32_t* p, int32_t v) { *p = v; }
+};
+
+// Persistent waves: a wave takes kDcBatch positions at a time from a shared
+// cursor, and each lane whose walk has ended takes the next terminal of the
+// wave's batch, so no lane idles while the longest walk of its wave goes on.
+constexpr int kDcBatch = 1024;
+
+__device__ __forceinline__ int64_t dc_uniform(int64_t x)
 {
-    const uint64_t b = __ballot(f);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// flags[g] = 1 where g roots a chunk: a cut node or a tree's root.
-__global__ __launch_bounds__(256) void k_dc_roots(DcNodes q, uint8_t* flags, unsigned long long* count)
+// The next batch [*pb, *pe) of [0, n) for this wave; false once none is left.
+__device__ __forceinline__ bool dc_take_batch(unsigned long long* cursor, int64_t n, int64_t batch, int64_t* pb,
+                                              int64_t* pe)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool f = false;
-    if (g < q.n) {
-        f = (q.info[g] & kDcCut) != 0 || q.parl[g] < 0;
-        flags[g] = f ? 1 : 0;
-    }
-    dc_count(f, count);
+    int64_t b = 0;
+    if ((threadIdx.x & 63) == 0) b = (int64_t)atomicAdd(cursor, (unsigned long long)batch);
+    b = dc_uniform(b);
+    *pb = b;
+    *pe = b + batch < n ? b + batch : n;
+    return b < n;
 }
 
-// flags[g] = 1 for a function whose subtree has at least min_size nodes.
-__global__ __launch_bounds__(256) void k_dc_big(DcNodes q, uint8_t* flags, int64_t min_size,
-                                                unsigned long long* count)
+__global__ __launch_bounds__(256) void k_dc_up_packed(DcNodes q, unsigned long long* cursor)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool f = false;
-    if (g < q.n) {
-        if (q.ops[g] & kFuncBit) {
-            const int64_t s = q.offsets[dc_tree_of(q, g)];
-            f = s + q.endl[g] - g >= min_size;
+    const uint64_t below = (1ull << (threadIdx.x & 63)) - 1;
+    int64_t v = -1, s = 0, e = 0, ts = 0, te = 0, pb = 0, pe = 0;
+    uint32_t w = 0;
+    bool more = true;
+    for (;;) {
+        if (pb >= pe && more) more = dc_take_batch(cursor, q.n, kDcBatch, &pb, &pe);
+        const uint64_t idle = __ballot(v < 0);
+        if (v < 0 && pb < pe) {
+            const int64_t g = pb + __popcll(idle & below);
+            if (g < pe && !(q.ops[g] & kFuncBit)) {
+                if (g < ts || g >= te) {
+                    const int64_t t = dc_tree_of(q, g);
+                    ts = q.offsets[t];
+                    te = q.offsets[t + 1];
+                }
+                s = ts;
+                e = te;
+                w = dc_leaf_packed<DevMemPacked>(q, g);
+                v = g;
+            }
         }
-        flags[g] = f ? 1 : 0;
+        if (pb < pe) pb += __popcll(idle);
+        if (v >= 0) v = dc_step_packed<DevMemPacked>(q, s, e, v, &w);
+        if (!more && pb >= pe && __ballot(v >= 0) == 0) break;
     }
-    dc_count(f, count);
+}
+
+// After the bottom-up pass: cuts into the info words, chunk-root flags.
+__global__ __launch_bounds__(256) void k_dc_finish(DcNodes q, uint8_t* flags)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g < q.n) flags[g] = dc_finish(q, g) ? 1 : 0;
 }
 
 // Chunk roots: their chunk ids into cnt, their code lengths and subtree ends out.
@@ -146,7 +185,7 @@ __global__ __launch_bounds__(256) void k_dc_paths(DcNodes q, const int64_t* pts,
 __global__ __launch_bounds__(256) void k_dc_cut_of(DcNodes q, const int64_t* nodes, int64_t n, uint8_t* out)
 {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k < n) out[k] = (q.info[nodes[k]] & kDcCut) ? 1 : 0;
+    if (k < n) out[k] = dc_cut(q, nodes[k]) ? 1 : 0;
 }
 
 // Recorded nodes: their STOREs lengthen their own subtrees' code.
@@ -160,10 +199,80 @@ __global__ __launch_bounds__(256) void k_dc_store(DcNodes q, const int64_t* node
     rec[g] = rec_id[k];
 }
 
-__global__ __launch_bounds__(256) void k_dc_emit(DcNodes q, DcChunks c, int write)
+// Compaction of a flag array, in order: a block takes kDcSpan positions, 16
+// per thread.  Count pass: the block's set flags.  Write pass: each set
+// position to out[boff[block] + its rank in the block].
+constexpr int kDcSpan = 4096;
+
+__device__ __forceinline__ uint32_t dc_flags16(const uint8_t* flags, int64_t base, int64_t n)
 {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k < c.n) dc_emit(q, c, k, write);
+    uint32_t m = 0;
+    if (base + 16 <= n) {                       // flags hold 0 or 1; base is a multiple of 16
+        const uint4 x = *(const uint4*)(flags + base);
+        const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
+        for (int j = 0; j < 16; ++j) m |= ((wd[j >> 2] >> (8 * (j & 3))) & 1u) << j;
+        return m;
+    }
+    for (int j = 0; j < 16; ++j)
+        if (base + j < n && flags[base + j]) m |= 1u << j;
+    return m;
+}
+
+__global__ __launch_bounds__(256) void k_dc_compact_count(const uint8_t* flags, int64_t n, int64_t* bcount)
+{
+    __shared__ int32_t wsum[4];
+    const int64_t base = (int64_t)blockIdx.x * kDcSpan + (int64_t)threadIdx.x * 16;
+    int32_t c = __popc(dc_flags16(flags, base, n));
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) bcount[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__global__ __launch_bounds__(256) void k_dc_compact_write(const uint8_t* flags, int64_t n, const int64_t* boff,
+                                                          int64_t* out)
+{
+    __shared__ int32_t pre[256];
+    const int64_t base = (int64_t)blockIdx.x * kDcSpan + (int64_t)threadIdx.x * 16;
+    const uint32_t m = dc_flags16(flags, base, n);
+    pre[threadIdx.x] = __popc(m);
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {              // inclusive scan over the block's threads
+        const int32_t v = threadIdx.x >= (unsigned)o ? pre[threadIdx.x - o] : 0;
+        __syncthreads();
+        pre[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t at = boff[blockIdx.x] + pre[threadIdx.x] - __popc(m);
+    for (int j = 0; j < 16; ++j)
+        if (m & (1u << j)) out[at++] = base + j;
+}
+
+// Emission on persistent waves: a lane whose chunk is done takes the next
+// chunk of its wave's batch.
+constexpr int kDcEmitBatch = 64;
+
+__global__ __launch_bounds__(256) void k_dc_emit(DcNodes q, DcChunks c, unsigned long long* cursor)
+{
+    const uint64_t below = (1ull << (threadIdx.x & 63)) - 1;
+    int64_t pb = 0, pe = 0;
+    bool more = true;
+    int32_t busy = 0;                           // an integer, not a lane-mask boolean, across the branches
+    DcEmit st{};
+    for (;;) {
+        if (pb >= pe && more) more = dc_take_batch(cursor, c.n, kDcEmitBatch, &pb, &pe);
+        const uint64_t idle = __ballot(busy == 0);
+        if (busy == 0 && pb < pe) {
+            const int64_t k = pb + __popcll(idle & below);
+            if (k < pe) {
+                dc_emit_begin(q, c, k, st);
+                busy = 1;
+            }
+        }
+        if (pb < pe) pb += __popcll(idle);
+        if (busy) busy = dc_emit_step(q, c, st) ? 1 : 0;
+        if (!more && pb >= pe && __ballot(busy != 0) == 0) break;
+    }
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -193,23 +302,80 @@ int down(Ctx* c, void* dst, const DevBuf& b, size_t bytes, hipStream_t s)
     return GP_OK;
 }
 
-// The flagged positions of flags[0 .. n), ascending, into out (count known).
-int dc_select(Ctx* c, const uint8_t* flags, int64_t n, int64_t count, DevBuf& out, hipStream_t s)
+// The flagged positions of flags[0 .. n), ascending, into out; their number
+// into *count.
+int dc_select(Ctx* c, const uint8_t* flags, int64_t n, DevBuf& out, int64_t* count, hipStream_t s)
 {
-    DevBuf num, tmp;
-    RC(dev_alloc(c, num, 8));
-    RC(dev_alloc(c, out, (size_t)std::max<int64_t>(1, count) * 8));
-    size_t tb = 0;
-    hipcub::CountingInputIterator<int64_t> it(0);
-    HIPC(c, hipcub::DeviceSelect::Flagged(nullptr, tb, it, flags, out.as<int64_t>(), num.as<int64_t>(), (int)n, s));
-    RC(dev_alloc(c, tmp, std::max<size_t>(tb, 256)));
-    HIPC(c, hipcub::DeviceSelect::Flagged(tmp.p, tb, it, flags, out.as<int64_t>(), num.as<int64_t>(), (int)n, s));
-    int64_t got = 0;
-    HIPC(c, hipMemcpyAsync(&got, num.p, 8, hipMemcpyDeviceToHost, s));
+    const int64_t nb = (n + kDcSpan - 1) / kDcSpan;
+    DevBuf bc;
+    RC(dev_alloc(c, bc, (size_t)nb * 8));
+    hipLaunchKernelGGL(k_dc_compact_count, dim3((unsigned)nb), dim3(256), 0, s, flags, n, bc.as<int64_t>());
+    HIPC(c, hipGetLastError());
+    std::vector<int64_t> h(nb);
+    RC(down(c, h.data(), bc, (size_t)nb * 8, s));
     HIPC(c, hipStreamSynchronize(s));
-    if (got != count) return set_err(c, GP_EINVAL, "internal error: compaction count differs");
+    int64_t run = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t v = h[b];
+        h[b] = run;
+        run += v;
+    }
+    *count = run;
+    RC(dev_alloc(c, out, (size_t)std::max<int64_t>(1, run) * 8));
+    if (run == 0) return GP_OK;
+    HIPC(c, hipMemcpyAsync(bc.p, h.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_dc_compact_write, dim3((unsigned)nb), dim3(256), 0, s, flags, n, bc.as<int64_t>(),
+                       out.as<int64_t>());
+    HIPC(c, hipGetLastError());
+    HIPC(c, hipStreamSynchronize(s));
     return GP_OK;
 }
+
+// Blocks of persistent waves for a launch over `items` units of work.
+unsigned dc_persistent_blocks(Ctx* c, int64_t items, int64_t batch)
+{
+    const int64_t want = (items + batch * 4 - 1) / (batch * 4);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)std::max(1, c->n_cu) * 8));
+}
+
+// f(i) for every i in [0, n), on up to 16 host threads taking blocks of
+// consecutive indices.
+template <class F> void dc_parallel(int64_t n, F f)
+{
+    const int64_t hw = std::min<int64_t>(16, std::max(1u, std::thread::hardware_concurrency()));
+    const int nth = (int)std::min<int64_t>(hw, n);
+    if (nth <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    const int64_t blk = std::max<int64_t>(1, n / (nth * 32));
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        for (;;) {
+            const int64_t a = next.fetch_add(blk);
+            if (a >= n) return;
+            for (int64_t i = a; i < std::min(n, a + blk); ++i) f(i);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) th.emplace_back(work);
+    work();
+    for (auto& x : th) x.join();
+}
+
+// Phase times of a compilation on stderr when GPEVAL_TRACE_LOAD is set.
+struct DcTrace {
+    bool on = std::getenv("GPEVAL_TRACE_LOAD") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char* what)
+    {
+        if (!on) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[devcompile] %-28s %9.2f ms\n", what,
+                     std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
 
 }  // namespace
 
@@ -234,6 +400,7 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         }
         n_pts = rec_offsets[n_trees];
     }
+    DcTrace tr;
     // validity, subtree ends and parents
     DevBuf valid, endl, parl;
     RC(dev_alloc(c, valid, (size_t)n_trees * 4));
@@ -257,15 +424,27 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         }
     }
     valid.release();
+    tr.mark("index");
 
-    DevBuf info, len, open, cnt, err, flags, counter;
+    // the packed hand-off when every value it carries fits (see devcompile_core.h)
+    const int64_t C = std::max<int64_t>(2, chunk_nodes);
+    const bool packed = C <= kDcPackMaxC && compile_stack_slots() <= 32;
+    DevBuf info, len, open, cnt, ncut, slot64, err, flags, big, counter;
+    if (index_min_size > 0) RC(dev_alloc(c, big, (size_t)n));
     RC(dev_alloc(c, info, (size_t)n * 4));
     RC(dev_alloc(c, len, (size_t)n * 4));
     RC(dev_alloc(c, open, (size_t)n * 4));
     RC(dev_alloc(c, cnt, (size_t)n * 4));
+    RC(dev_alloc(c, ncut, (size_t)n));
     RC(dev_alloc(c, err, 4));
     RC(dev_alloc(c, counter, 16));
-    HIPC(c, launch_fill_i32(cnt.as<int32_t>(), n, 0, s));
+    if (packed) {
+        RC(dev_alloc(c, slot64, (size_t)n * 8));
+        HIPC(c, launch_fill_i32(slot64.as<int32_t>(), 2 * n, 0, s));
+    } else {
+        HIPC(c, launch_fill_i32(cnt.as<int32_t>(), n, 0, s));
+    }
+    HIPC(c, launch_fill_u8(ncut.as<uint8_t>(), n, 0, s));
     HIPC(c, launch_fill_i32(err.as<int32_t>(), 1, 0, s));
     DcNodes q{};
     q.ops = dops;
@@ -278,16 +457,28 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     q.len = len.as<int32_t>();
     q.open = open.as<int32_t>();
     q.cnt = cnt.as<int32_t>();
+    q.slot64 = slot64.as<uint64_t>();
+    q.ncut = ncut.as<uint8_t>();
+    q.big = index_min_size > 0 ? big.as<uint8_t>() : nullptr;
+    q.big_min = index_min_size;
     q.err = err.as<int32_t>();
     q.boolean = vtype == GP_BOOL ? 1 : 0;
     q.S = compile_stack_slots();
-    q.C = std::max<int64_t>(2, chunk_nodes);
-    hipLaunchKernelGGL(k_dc_up, dim3(blocks_for(n)), dim3(256), 0, s, q);
+    q.C = C;
+    if (packed) {
+        HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
+        hipLaunchKernelGGL(k_dc_up_packed, dim3(dc_persistent_blocks(c, n, kDcBatch)), dim3(256), 0, s, q,
+                           counter.as<unsigned long long>());
+    } else {
+        hipLaunchKernelGGL(k_dc_up, dim3(blocks_for(n)), dim3(256), 0, s, q);
+    }
     HIPC(c, hipGetLastError());
     int32_t errv = 0;
     HIPC(c, hipMemcpyAsync(&errv, err.p, 4, hipMemcpyDeviceToHost, s));
     HIPC(c, hipStreamSynchronize(s));
     if (errv) return set_err(c, GP_EINVAL, "internal error: inconsistent tree index (" + std::to_string(errv) + ")");
+    slot64.release();
+    tr.mark(packed ? "bottom-up pass (packed)" : "bottom-up pass");
 
     // parent-cache records (Section 6.2): the points' paths, read on the device
     std::vector<int64_t> rec_base(n_trees, 0), n_rec(n_trees, 0);
@@ -324,29 +515,37 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         RC(down(c, pop.data(), pop_d, (size_t)n_pts, s));
         RC(down(c, pend.data(), pend_d, (size_t)n_pts * 4, s));
         HIPC(c, hipStreamSynchronize(s));
-        std::vector<DcStored> stored;
-        int64_t rb = 0;
-        for (int64_t t = 0; t < n_trees; ++t) {
+        // per tree, in parallel: its records and spines, then (once the cut
+        // flags are known) the words its recorded nodes add
+        std::vector<std::vector<DcStored>> st_t(n_trees);
+        dc_parallel(n_trees, [&](int64_t t) {
             const int64_t p0 = rec_offsets[t], np = rec_offsets[t + 1] - p0;
             std::vector<int64_t> loff(np + 1);
             for (int64_t i = 0; i <= np; ++i) loff[i] = lv_off[p0 + i] - lv_off[p0];
-            rec_base[t] = rb;
             n_rec[t] = dc_tree_records(offsets[t], np, rec_points + p0, pop.data() + p0, pend.data() + p0,
-                                       loff.data(), lv.data() + lv_off[p0], &spines[t], &stored);
+                                       loff.data(), lv.data() + lv_off[p0], &spines[t], &st_t[t]);
+        });
+        std::vector<int64_t> st_off(n_trees + 1, 0);
+        int64_t rb = 0;
+        for (int64_t t = 0; t < n_trees; ++t) {
             if (n_rec[t] > (int64_t)kMaxPayload)
                 return set_err(c, GP_EINVAL,
                                "tree " + std::to_string(t) + ": too many parent-cache records in one tree");
+            rec_base[t] = rb;
             rb += n_rec[t];
+            st_off[t + 1] = st_off[t] + (int64_t)st_t[t].size();
         }
         if (rb > INT32_MAX / 2) return set_err(c, GP_EINVAL, "population too large for one load");
-        const int64_t ns = (int64_t)stored.size();
+        const int64_t ns = st_off[n_trees];
         if (ns > 0) {
             std::vector<int64_t> nodes(ns);
-            std::vector<int32_t> ids(ns);
-            for (int64_t i = 0; i < ns; ++i) {
-                nodes[i] = stored[i].node;
-                ids[i] = stored[i].rec;
-            }
+            std::vector<int32_t> ids(ns), inc(ns);
+            dc_parallel(n_trees, [&](int64_t t) {
+                for (size_t i = 0; i < st_t[t].size(); ++i) {
+                    nodes[st_off[t] + i] = st_t[t][i].node;
+                    ids[st_off[t] + i] = st_t[t][i].rec;
+                }
+            });
             DevBuf nodes_d, cut_d, inc_d, ids_d;
             RC(up(c, nodes_d, nodes.data(), (size_t)ns * 8, s));
             RC(dev_alloc(c, cut_d, (size_t)ns));
@@ -356,8 +555,9 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             std::vector<uint8_t> cut(ns);
             RC(down(c, cut.data(), cut_d, (size_t)ns, s));
             HIPC(c, hipStreamSynchronize(s));
-            std::vector<int32_t> inc;
-            dc_store_words(stored, cut, &inc);
+            dc_parallel(n_trees, [&](int64_t t) {
+                dc_store_words(st_t[t].data(), cut.data() + st_off[t], st_t[t].size(), inc.data() + st_off[t]);
+            });
             RC(up(c, inc_d, inc.data(), (size_t)ns * 4, s));
             RC(up(c, ids_d, ids.data(), (size_t)ns * 4, s));
             RC(dev_alloc(c, rec, (size_t)n * 4));
@@ -369,20 +569,18 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             q.rec = rec.as<int32_t>();
         }
     }
-
+    tr.mark("records");
     // chunk roots, ascending, and their numbering
     RC(dev_alloc(c, flags, (size_t)n));
-    unsigned long long nsel = 0;
-    HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
-    hipLaunchKernelGGL(k_dc_roots, dim3(blocks_for(n)), dim3(256), 0, s, q, flags.as<uint8_t>(),
-                       counter.as<unsigned long long>());
+    hipLaunchKernelGGL(k_dc_finish, dim3(blocks_for(n)), dim3(256), 0, s, q, flags.as<uint8_t>());
     HIPC(c, hipGetLastError());
-    HIPC(c, hipMemcpyAsync(&nsel, counter.p, 8, hipMemcpyDeviceToHost, s));
-    HIPC(c, hipStreamSynchronize(s));
-    const int64_t nch = (int64_t)nsel;
-    if (nch < n_trees || nch > INT32_MAX / 2) return set_err(c, GP_EINVAL, "population too large for one load");
     DevBuf roots_d;
-    RC(dc_select(c, flags.as<uint8_t>(), n, nch, roots_d, s));
+    int64_t nch = 0;
+    RC(dc_select(c, flags.as<uint8_t>(), n, roots_d, &nch, s));   // waits for the stream
+    flags.release();
+    ncut.release();
+    q.ncut = nullptr;                                               // the cuts are in the info words now
+    if (nch < n_trees || nch > INT32_MAX / 2) return set_err(c, GP_EINVAL, "population too large for one load");
     std::vector<int64_t> roots_asc(nch);
     RC(down(c, roots_asc.data(), roots_d, (size_t)nch * 8, s));
     HIPC(c, hipStreamSynchronize(s));
@@ -410,6 +608,7 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         }
     }
     roots_d.release();
+    tr.mark("chunk roots");
     std::vector<int64_t> code_len(nch), code_off(nch + 1, 0);
     for (int64_t k = 0; k < nch; ++k) {
         code_len[k] = (int64_t)rlen[k] + 1;
@@ -417,73 +616,80 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     }
     const int64_t n_code = code_off[nch];
 
-    // code emission: count the LOADs, then write
-    DevBuf root_d, ts_d, off_d, nin_d, par_d, nodes_d, ms_d, st_d, slot;
+    // code emission, one pass: each child chunk learns its parent and which of
+    // the parent's LOADs reads it; the LOAD lists are then put together here
+    DevBuf root_d, ts_d, off_d, nin_d, par_d, lix_d, nodes_d, ms_d, st_d, slot;
     RC(up(c, root_d, root.data(), (size_t)nch * 8, s));
     RC(up(c, ts_d, tstart.data(), (size_t)nch * 8, s));
     RC(up(c, off_d, code_off.data(), (size_t)nch * 8, s));
     RC(dev_alloc(c, nin_d, (size_t)nch * 4));
     RC(dev_alloc(c, par_d, (size_t)nch * 4));
+    RC(dev_alloc(c, lix_d, (size_t)nch * 4));
     RC(dev_alloc(c, nodes_d, (size_t)nch * 8));
     RC(dev_alloc(c, ms_d, (size_t)nch * 4));
     RC(dev_alloc(c, st_d, (size_t)nch));
     RC(dev_alloc(c, slot, (size_t)n));
     q.slot = slot.as<uint8_t>();
     HIPC(c, launch_fill_i32(par_d.as<int32_t>(), nch, -1, s));
+    HIPC(c, launch_fill_i32(lix_d.as<int32_t>(), nch, -1, s));
+    RC(dev_alloc(c, out->code, (size_t)(n_code + 1) * 4));
+    HIPC(c, launch_fill_i32((int32_t*)out->code.p + n_code, 1, 0, s));   // one word past the end for the fetch-ahead
     DcChunks ck{};
     ck.n = nch;
     ck.root = root_d.as<int64_t>();
     ck.tree_start = ts_d.as<int64_t>();
     ck.code_off = off_d.as<int64_t>();
+    ck.code = out->code.as<uint32_t>();
     ck.n_in = nin_d.as<int32_t>();
     ck.parent = par_d.as<int32_t>();
+    ck.load_idx = lix_d.as<int32_t>();
     ck.nodes = nodes_d.as<int64_t>();
     ck.max_slot = ms_d.as<int32_t>();
     ck.stores = st_d.as<uint8_t>();
-    hipLaunchKernelGGL(k_dc_emit, dim3(blocks_for(nch)), dim3(256), 0, s, q, ck, 0);
+    HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
+    hipLaunchKernelGGL(k_dc_emit, dim3(dc_persistent_blocks(c, nch, kDcEmitBatch)), dim3(256), 0, s, q, ck,
+                       counter.as<unsigned long long>());
     HIPC(c, hipGetLastError());
-    std::vector<int32_t> n_in(nch);
-    RC(down(c, n_in.data(), nin_d, (size_t)nch * 4, s));
-    HIPC(c, hipStreamSynchronize(s));
-    std::vector<int64_t> in_off(nch + 1, 0);
-    for (int64_t k = 0; k < nch; ++k) {
-        if ((uint32_t)n_in[k] > kMaxPayload) return set_err(c, GP_EINVAL, "chunk reads too many child chunks");
-        in_off[k + 1] = in_off[k] + n_in[k];
-    }
-    if (in_off[nch] != nch - n_trees) return set_err(c, GP_EINVAL, "internal error: chunk inputs do not add up");
-    DevBuf inoff_d, ins_d;
-    RC(up(c, inoff_d, in_off.data(), (size_t)(nch + 1) * 8, s));
-    RC(dev_alloc(c, ins_d, (size_t)std::max<int64_t>(1, in_off[nch]) * 4));
-    RC(dev_alloc(c, out->code, (size_t)(n_code + 1) * 4));
-    HIPC(c, launch_fill_i32((int32_t*)out->code.p + n_code, 1, 0, s));   // one word past the end for the fetch-ahead
-    ck.in_off = inoff_d.as<int64_t>();
-    ck.inputs = ins_d.as<int32_t>();
-    ck.code = out->code.as<uint32_t>();
-    hipLaunchKernelGGL(k_dc_emit, dim3(blocks_for(nch)), dim3(256), 0, s, q, ck, 1);
-    HIPC(c, hipGetLastError());
-    std::vector<int32_t> parent(nch), ins((size_t)in_off[nch]), max_slot(nch);
+    std::vector<int32_t> n_in(nch), parent(nch), load_idx(nch), max_slot(nch);
     std::vector<int64_t> nodes(nch);
     std::vector<uint8_t> stores(nch);
+    RC(down(c, n_in.data(), nin_d, (size_t)nch * 4, s));
     RC(down(c, parent.data(), par_d, (size_t)nch * 4, s));
+    RC(down(c, load_idx.data(), lix_d, (size_t)nch * 4, s));
     RC(down(c, nodes.data(), nodes_d, (size_t)nch * 8, s));
     RC(down(c, max_slot.data(), ms_d, (size_t)nch * 4, s));
     RC(down(c, stores.data(), st_d, (size_t)nch, s));
-    RC(down(c, ins.data(), ins_d, ins.size() * 4, s));
+    HIPC(c, hipStreamSynchronize(s));
+    slot.release();
+    for (int64_t k = 0; k < nch; ++k)
+        if ((uint32_t)n_in[k] > kMaxPayload) return set_err(c, GP_EINVAL, "chunk reads too many child chunks");
+    std::vector<int64_t> in_off;
+    std::vector<int32_t> ins;
+    if (!dc_scatter_inputs(nch, n_in.data(), parent.data(), load_idx.data(), &in_off, &ins) ||
+        in_off[nch] != nch - n_trees) {
+        int64_t loads = 0, orphans = 0, first = -1;
+        for (int64_t k = 0; k < nch; ++k) {
+            loads += n_in[k];
+            const bool top = k == cbase[ctree[k] + 1] - 1;
+            if (!top && parent[k] < 0 && orphans++ == 0) first = k;
+        }
+        return set_err(c, GP_EINVAL, "internal error: chunk inputs do not add up (" + std::to_string(loads) +
+                                         " LOADs, " + std::to_string(nch - n_trees) + " child chunks, " +
+                                         std::to_string(orphans) + " without a parent, first " +
+                                         std::to_string(first) + ")");
+    }
+    tr.mark("emission");
 
-    // subtrees of at least index_min_size nodes (co-evaluation's path search)
+    // subtrees of at least index_min_size nodes (co-evaluation's path search),
+    // flagged by the bottom-up pass
     std::vector<int64_t> big_nodes;
     std::vector<int32_t> big_end;
     if (index_min_size > 0) {
-        HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
-        hipLaunchKernelGGL(k_dc_big, dim3(blocks_for(n)), dim3(256), 0, s, q, flags.as<uint8_t>(), index_min_size,
-                           counter.as<unsigned long long>());
-        HIPC(c, hipGetLastError());
-        HIPC(c, hipMemcpyAsync(&nsel, counter.p, 8, hipMemcpyDeviceToHost, s));
-        HIPC(c, hipStreamSynchronize(s));
-        const int64_t nb = (int64_t)nsel;
+        DevBuf big_d;
+        int64_t nb = 0;
+        RC(dc_select(c, big.as<uint8_t>(), n, big_d, &nb, s));
         if (nb > 0) {
-            DevBuf big_d, bend_d;
-            RC(dc_select(c, flags.as<uint8_t>(), n, nb, big_d, s));
+            DevBuf bend_d;
             RC(dev_alloc(c, bend_d, (size_t)nb * 4));
             hipLaunchKernelGGL(k_dc_ends, dim3(blocks_for(nb)), dim3(256), 0, s, q, big_d.as<int64_t>(), nb,
                                bend_d.as<int32_t>());
@@ -495,7 +701,7 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             HIPC(c, hipStreamSynchronize(s));
         }
     }
-    HIPC(c, hipStreamSynchronize(s));
+    tr.mark("large subtrees");
 
     // the population's tables, as assemble_population builds them
     out->vtype = vtype;
@@ -532,13 +738,10 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     }
     std::vector<DevChunk> dch(nch);
     std::vector<int32_t> chunk_in((size_t)in_off[nch]);
-    std::vector<SpineLvl> levels;
     out->kept_chunks.assign(n_trees, {});
     out->kept_max_stack.assign(n_trees, 0);
     out->cuts.assign(n_trees, {});
-    out->max_stack = 0;
-    int64_t n_records = 0;
-    for (int64_t t = 0; t < n_trees; ++t) {
+    dc_parallel(n_trees, [&](int64_t t) {
         const int64_t b = cbase[t], m = cbase[t + 1] - b, s0 = offsets[t];
         auto& kc = out->kept_chunks[t];
         kc.resize(m);
@@ -572,13 +775,20 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
                 chunk_in[j] = (int32_t)out_slot[ins[j]];
                 ch.inputs[j - in_off[k]] = ins[j] - (int32_t)b;
             }
-            if (n_in[k] == 0) out->leaves.emplace_back(path[k], (int32_t)k);
             tms = std::max(tms, max_slot[k] + 1);
             cl.push_back(Pop::CutSlot{(int32_t)ch.root_node, rend[k], (int32_t)out_slot[k]});
         }
         std::sort(cl.begin(), cl.end(), [](const Pop::CutSlot& x, const Pop::CutSlot& y) { return x.node < y.node; });
-        if (tms > compile_stack_slots()) return set_err(c, GP_EINVAL, "internal error: stack bound exceeded");
         out->kept_max_stack[t] = tms;
+    });
+    for (int64_t k = 0; k < nch; ++k)
+        if (n_in[k] == 0) out->leaves.emplace_back(path[k], (int32_t)k);
+    std::vector<SpineLvl> levels;
+    out->max_stack = 0;
+    int64_t n_records = 0;
+    for (int64_t t = 0; t < n_trees; ++t) {
+        const int32_t tms = out->kept_max_stack[t];
+        if (tms > compile_stack_slots()) return set_err(c, GP_EINVAL, "internal error: stack bound exceeded");
         out->max_stack = std::max(out->max_stack, tms);
         for (auto& sp : spines[t]) {
             const uint64_t key = ((uint64_t)t << 32) | (uint32_t)sp.point;
@@ -613,6 +823,7 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     RC(up(c, out->chunk_in, chunk_in.data(), chunk_in.size() * 4, s));
     RC(up(c, out->levels, levels.data(), levels.size() * sizeof(SpineLvl), s));
     HIPC(c, hipStreamSynchronize(s));
+    tr.mark("tables");
     return GP_OK;
 }
 

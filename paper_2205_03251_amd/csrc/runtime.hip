@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <limits>
@@ -268,6 +269,8 @@ int build_population_device(Ctx* c, int vtype, int n_inputs, int64_t n_trees, co
     hipStream_t s = c->stream;
     // the index reads the trees with 16-byte loads: a copy of our own unless
     // the caller's device array is aligned and need not be kept
+    const bool trace = std::getenv("GPEVAL_TRACE_LOAD") != nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
     DevBuf ops_buf, offs;
     const uint8_t* dops = dev_ops;
     if (!dev_ops || ((uintptr_t)dev_ops & 15) != 0 || ops_keep) {
@@ -277,6 +280,11 @@ int build_population_device(Ctx* c, int vtype, int n_inputs, int64_t n_trees, co
         dops = ops_buf.as<uint8_t>();
     }
     RC(upload(c, offs, offsets, (size_t)(n_trees + 1) * sizeof(int64_t), s));
+    if (trace) {
+        HIPC(c, hipStreamSynchronize(s));
+        std::fprintf(stderr, "[devcompile] %-28s %9.2f ms\n", "trees to the device",
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
     RC(device_compile_population(c, vtype, n_inputs, n_trees, dops, offs.as<int64_t>(), offsets, host_ops,
                                  rec_points, rec_offsets, chunk_nodes, kBigSubtree, out, s));
     out->layout = GP_PREFIX;
@@ -1200,6 +1208,25 @@ int gp_set_cases(gp_ctx* ctx, int vtype, int n_inputs, int64_t n_cases, const vo
     return GP_OK;
 }
 
+// dst = src[0 .. n), in slices on up to 16 threads when large.
+static void copy_host_bytes(std::vector<uint8_t, NoInitAlloc<uint8_t>>& dst, const uint8_t* src, size_t n)
+{
+    dst.resize(n);
+    const size_t slice = size_t(64) << 20;
+    const int nth = (int)std::min<size_t>({16, std::max(1u, std::thread::hardware_concurrency()), n / slice + 1});
+    if (nth <= 1) {
+        std::memcpy(dst.data(), src, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t]() {
+            const size_t a = n * t / nth, b = n * (t + 1) / nth;
+            std::memcpy(dst.data() + a, src + a, b - a);
+        });
+    for (auto& x : th) x.join();
+}
+
 int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t n_trees, const uint8_t* ops,
                        const int64_t* offsets, const int64_t* record_points, const int64_t* record_offsets,
                        int64_t chunk_nodes, uint32_t flags, gp_handle* pop_out)
@@ -1221,16 +1248,22 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
             offs = hoff.data();
         }
         DevBuf keep;
-        RC(build_population_device(ctx, vtype, n_inputs, n_trees, on_dev ? nullptr : ops, on_dev ? ops : nullptr,
-                                   offs, record_points, record_offsets, chunk_nodes, p.get(),
-                                   (flags & GP_KEEP_TREES) ? &keep : nullptr));
+        int rc = GP_OK;
+        try {
+            rc = build_population_device(ctx, vtype, n_inputs, n_trees, on_dev ? nullptr : ops,
+                                         on_dev ? ops : nullptr, offs, record_points, record_offsets, chunk_nodes,
+                                         p.get(), (flags & GP_KEEP_TREES) ? &keep : nullptr);
+        } catch (const std::bad_alloc&) {
+            rc = set_err(ctx, GP_ENOMEM, "out of host memory while compiling on the device");
+        }
+        RC(rc);
         p->auto_chunk = chunk_nodes <= 0;
         const size_t nb = (size_t)offs[n_trees];
         if (on_dev) {
             p->host_ops.resize(nb);
             HIPC(ctx, hipMemcpy(p->host_ops.data(), ops, nb, hipMemcpyDeviceToHost));
         } else {
-            p->host_ops.assign(ops, ops + nb);
+            copy_host_bytes(p->host_ops, ops, nb);
         }
         p->host_offsets.assign(offs, offs + n_trees + 1);
         if (flags & GP_KEEP_TREES) {
@@ -1251,7 +1284,7 @@ int gp_load_population(gp_ctx* ctx, int vtype, int layout, int n_inputs, int64_t
     p->auto_chunk = chunk_nodes <= 0;
     // host copy of the trees: re-chunking by the autotuner, sibling subtrees
     // for co-evaluation
-    p->host_ops.assign(ops, ops + offsets[n_trees]);
+    copy_host_bytes(p->host_ops, ops, (size_t)offsets[n_trees]);
     p->host_offsets.assign(offsets, offsets + n_trees + 1);
     if (flags & GP_KEEP_TREES) {
         const size_t nb = (size_t)offsets[n_trees];

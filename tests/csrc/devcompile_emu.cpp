@@ -9,7 +9,8 @@
 // "second operand to arrive computes the node" rule is exercised with every
 // operand order; emission runs the chunks in a random order.
 //
-// Input (stdin, text): vtype n_inputs chunk_nodes index_min_size n_trees seed mode,
+// Input (stdin, text): vtype n_inputs chunk_nodes index_min_size n_trees seed mode
+// handoff (0: through per-node memory; 1: packed into one word per function),
 // then n_trees + 1 offsets, the ops bytes, n_trees + 1 record offsets and the
 // record points.  Output: "ok chunks <n> words <w> records <r>", or a line
 // naming the first difference (exit status 1).
@@ -32,6 +33,12 @@ struct CpuMem {
     {
         const int32_t o = *p;
         *p = o + v;
+        return o;
+    }
+    static uint64_t fetch_or64(uint64_t* p, uint64_t v)
+    {
+        const uint64_t o = *p;
+        *p = o | v;
         return o;
     }
     static void publish() {}
@@ -60,6 +67,8 @@ int main()
     const int64_t chunk_nodes = rd<int64_t>(), index_min = rd<int64_t>(), n_trees = rd<int64_t>();
     const uint64_t seed = rd<uint64_t>();
     const int mode = rd<int>();
+    const int handoff = rd<int>();
+    if (handoff == 1 && chunk_nodes > kDcPackMaxC) fail("the packed hand-off takes chunk targets up to 8192");
     std::vector<int64_t> off(n_trees + 1);
     for (auto& v : off) v = rd<int64_t>();
     const int64_t n = off[n_trees];
@@ -98,7 +107,8 @@ int main()
     }
 
     std::vector<int32_t> info(n, -7), len(n, -7), open(n, -7), cnt(n, 0), rec;
-    std::vector<uint8_t> slot(n, 0);
+    std::vector<uint8_t> slot(n, 0), ncut(n, 0), big(n, 7);
+    std::vector<uint64_t> slot64(n, 0);
     int32_t err = 0;
     DcNodes q{};
     q.ops = ops.data();
@@ -111,6 +121,10 @@ int main()
     q.len = len.data();
     q.open = open.data();
     q.cnt = cnt.data();
+    q.slot64 = slot64.data();
+    q.ncut = ncut.data();
+    q.big = index_min > 0 ? big.data() : nullptr;
+    q.big_min = index_min;
     q.slot = slot.data();
     q.err = &err;
     q.boolean = vtype == 1;
@@ -121,36 +135,38 @@ int main()
     struct Th {
         int64_t v, s, e;
         bool started;
+        uint32_t w;
     };
     std::vector<Th> th;
     for (int64_t g = 0; g < n; ++g)
         if (!(ops[g] & kFuncBit)) {
             const int64_t t = dc_tree_of(q, g);
-            th.push_back(Th{g, off[t], off[t + 1], false});
+            th.push_back(Th{g, off[t], off[t + 1], false, 0});
         }
+    // one step of a thread: its terminal, or one arrival; false when it ends
+    auto step = [&](Th& x) {
+        if (!x.started) {
+            x.started = true;
+            if (handoff) x.w = dc_leaf_packed<CpuMem>(q, x.v);
+            else dc_leaf<CpuMem>(q, x.v);
+            return true;
+        }
+        const int64_t nv = handoff ? dc_step_packed<CpuMem>(q, x.s, x.e, x.v, &x.w) : dc_step<CpuMem>(q, x.s, x.e, x.v);
+        if (nv < 0) return false;
+        x.v = nv;
+        return true;
+    };
     if (mode == 0) {
         std::shuffle(th.begin(), th.end(), rng);
-        for (auto& x : th) {
-            dc_leaf<CpuMem>(q, x.v);
-            for (int64_t v = x.v; v >= 0;) v = dc_step<CpuMem>(q, x.s, x.e, v);
-        }
+        for (auto& x : th)
+            while (step(x)) {
+            }
     } else {
         while (!th.empty()) {
             const size_t i = (size_t)(rng() % th.size());
-            Th& x = th[i];
-            int64_t nv;
-            if (!x.started) {
-                dc_leaf<CpuMem>(q, x.v);
-                x.started = true;
-                nv = x.v;
-            } else {
-                nv = dc_step<CpuMem>(q, x.s, x.e, x.v);
-            }
-            if (nv < 0) {
+            if (!step(th[i])) {
                 th[i] = th.back();
                 th.pop_back();
-            } else {
-                x.v = nv;
             }
         }
     }
@@ -187,9 +203,9 @@ int main()
     }
     if (!stored.empty()) {
         std::vector<uint8_t> cut(stored.size());
-        for (size_t i = 0; i < stored.size(); ++i) cut[i] = (info[stored[i].node] & kDcCut) ? 1 : 0;
-        std::vector<int32_t> inc;
-        dc_store_words(stored, cut, &inc);
+        for (size_t i = 0; i < stored.size(); ++i) cut[i] = dc_cut(q, stored[i].node) ? 1 : 0;
+        std::vector<int32_t> inc(stored.size());
+        dc_store_words(stored.data(), cut.data(), stored.size(), inc.data());
         rec.assign(n, -1);
         for (size_t i = 0; i < stored.size(); ++i) {
             len[stored[i].node] += inc[i];
@@ -201,7 +217,7 @@ int main()
     // chunk roots and numbering
     std::vector<int64_t> roots_asc;
     for (int64_t g = 0; g < n; ++g)
-        if ((info[g] & kDcCut) || parl[g] < 0) roots_asc.push_back(g);
+        if (dc_finish(q, g)) roots_asc.push_back(g);
     std::vector<int64_t> root, tstart, cbase;
     std::vector<int32_t> ctree, ids;
     if (!dc_number_chunks(roots_asc, off.data(), n_trees, &root, &tstart, &ctree, &ids, &cbase))
@@ -211,8 +227,8 @@ int main()
     std::vector<int64_t> code_off(nch + 1, 0);
     for (int64_t k = 0; k < nch; ++k) code_off[k + 1] = code_off[k] + len[root[k]] + 1;
     std::vector<uint32_t> code(code_off[nch] + 1, 0xdeadbeefu);
-    std::vector<int32_t> n_in(nch, -1), parent(nch, -1), max_slot(nch, -1);
-    std::vector<int64_t> nodes(nch, -1), in_off(nch + 1, 0);
+    std::vector<int32_t> n_in(nch, -1), parent(nch, -1), load_idx(nch, -1), max_slot(nch, -1);
+    std::vector<int64_t> nodes(nch, -1);
     std::vector<uint8_t> stores(nch, 9);
     DcChunks ck{};
     ck.n = nch;
@@ -222,19 +238,33 @@ int main()
     ck.code = code.data();
     ck.n_in = n_in.data();
     ck.parent = parent.data();
+    ck.load_idx = load_idx.data();
     ck.nodes = nodes.data();
     ck.max_slot = max_slot.data();
     ck.stores = stores.data();
-    std::vector<int64_t> order(nch);
-    for (int64_t k = 0; k < nch; ++k) order[k] = k;
-    std::shuffle(order.begin(), order.end(), rng);
-    for (int64_t k : order) dc_emit(q, ck, k, 0);
-    for (int64_t k = 0; k < nch; ++k) in_off[k + 1] = in_off[k] + n_in[k];
-    std::vector<int32_t> inputs(std::max<int64_t>(1, in_off[nch]), -1);
-    ck.in_off = in_off.data();
-    ck.inputs = inputs.data();
-    std::shuffle(order.begin(), order.end(), rng);
-    for (int64_t k : order) dc_emit(q, ck, k, 1);
+    // emission: chunks in random order, their steps interleaved at random
+    {
+        std::vector<int64_t> order(nch);
+        for (int64_t k = 0; k < nch; ++k) order[k] = k;
+        std::shuffle(order.begin(), order.end(), rng);
+        std::vector<DcEmit> live;
+        size_t next = 0;
+        while (next < order.size() || !live.empty()) {
+            while (live.size() < 8 && next < order.size()) {
+                live.emplace_back();
+                dc_emit_begin(q, ck, order[next++], live.back());
+            }
+            const size_t i = (size_t)(rng() % live.size());
+            if (!dc_emit_step(q, ck, live[i])) {
+                live[i] = live.back();
+                live.pop_back();
+            }
+        }
+    }
+    std::vector<int64_t> in_off;
+    std::vector<int32_t> inputs;
+    if (!dc_scatter_inputs(nch, n_in.data(), parent.data(), load_idx.data(), &in_off, &inputs))
+        fail("inconsistent LOAD lists");
 
     // against compile_tree, tree by tree
     CompileOptions opt;
@@ -292,10 +322,12 @@ int main()
                     fail(T + "spine " + std::to_string(i) + " level " + std::to_string(j));
         }
         if (index_min > 0) {
-            std::vector<SubtreeEnd> big;
-            for (int64_t i = 0; i < m; ++i)
-                if ((ops[s + i] & kFuncBit) && endl[s + i] - i >= index_min) big.push_back({(int32_t)i, endl[s + i]});
-            if (big != prog.big_ends) fail(T + "large subtrees");
+            std::vector<SubtreeEnd> bl;
+            for (int64_t i = 0; i < m; ++i) {
+                if (big[s + i] > 1) fail(T + "large-subtree flag never written");
+                if (big[s + i]) bl.push_back({(int32_t)i, endl[s + i]});
+            }
+            if (bl != prog.big_ends) fail(T + "large subtrees");
         }
     }
     std::printf("ok chunks %lld words %lld records %lld\n", (long long)nch, (long long)code_off[nch],

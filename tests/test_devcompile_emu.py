@@ -34,10 +34,21 @@ def emu(tmp_path_factory):
     return exe
 
 
-def run(exe, pop, chunk_nodes, index_min=0, points=None, seed=1, mode=1):
+def run(exe, pop, chunk_nodes, index_min=0, points=None, seed=1, mode=1, handoffs=None):
+    """Runs both hand-offs (the packed one where the chunk target allows it)
+    and checks each against compile_tree."""
+    if handoffs is None:
+        handoffs = [0, 1] if chunk_nodes <= 8192 else [0]
+    got = None
+    for h in handoffs:
+        got = run_one(exe, pop, chunk_nodes, index_min, points, seed, mode, h)
+    return got
+
+
+def run_one(exe, pop, chunk_nodes, index_min, points, seed, mode, handoff):
     pts = points if points is not None else [[] for _ in range(pop.n_trees)]
     ro = np.cumsum([0] + [len(p) for p in pts])
-    words = [pop.vtype, pop.n_inputs, chunk_nodes, index_min, pop.n_trees, seed, mode]
+    words = [pop.vtype, pop.n_inputs, chunk_nodes, index_min, pop.n_trees, seed, mode, handoff]
     text = " ".join(map(str, words)) + "\n" + " ".join(map(str, pop.offsets.tolist())) + "\n" + \
         " ".join(map(str, pop.ops.tolist())) + "\n" + " ".join(map(str, ro.tolist())) + "\n" + \
         " ".join(str(c) for p in pts for c in p) + "\n"
@@ -127,7 +138,7 @@ def test_combs_and_single_nodes(emu):
              np.array([0x81, 0, 0], np.uint8), np.array([0], np.uint8)]
     pop = gen.pack(trees, gen.VT_F32, 1)
     pts = [[0, 5, 2999, 6000], [0], [1, 5997, 3000], [0, 1, 2], []]
-    for c in (2, 16, 128, 5000):
+    for c in (2, 16, 128, 5000, 8192, 8193):
         run(emu, pop, c, 64, pts, seed=c)
 
 
@@ -135,3 +146,4 @@ def test_one_large_tree_interleaved(emu):
     pop = gen.sized_population(11, 1, 200001, 200001)
     got = run(emu, pop, 1024, 4096, [[0, 7, 1000, 150000]])
     assert got["chunks"] > 100
+    run(emu, pop, 8192, 4096, [[0, 7, 1000, 150000]], mode=0)

@@ -146,6 +146,17 @@ def test_automatic_chunk_size_and_one_large_tree(ctx):
     ctx.free(compare(ctx, big, 0, random_points(33, big, 1), "12 trees up to 4e5 nodes"))
 
 
+def test_many_batches_per_wave(ctx):
+    # the persistent kernels run at most 8 blocks of 4 waves per compute unit;
+    # beyond 8192 waves' single batches (8.4e6 nodes in the bottom-up pass,
+    # 524288 chunks in emission) waves take several batches each
+    pop = gen.sized_population(35, 30, 300001, 500001, threads=8)
+    assert pop.offsets[-1] > 9_000_000
+    ph = compare(ctx, pop, 16, random_points(36, pop, 1), "30 trees, 16-node chunks")
+    assert ctx.population_info(ph)["n_chunks"] > 600_000
+    ctx.free(ph)
+
+
 def test_device_resident_trees(ctx):
     import torch
     pop = gen.sized_population(41, 30, 1, 20001)
