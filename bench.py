@@ -329,7 +329,8 @@ def oracle_stream(jobs, cases_of, threads, budget_s, cpu):
                       f"(left out: {skipped} jobs above {0.5 * budget_s * rate:.0e} node-cases), {dt:.1f} s"}
 
 
-def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, loads=(0.5, 0.8, 0.95), cpu=None, oracle_s=8.0):
+def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, loads=(0.5, 0.8, 0.95), cpu=None, oracle_s=8.0,
+                device_compile_nodes=0):
     """Served mixed stream: full jobs (kept resident as parents) and
     incremental children arriving over time; continuous batching in the
     library's server.  All jobs at once (saturation), then Poisson arrivals at
@@ -360,7 +361,8 @@ def serve_bench(ctx, g, n_jobs, threads, budget_gb=200.0, loads=(0.5, 0.8, 0.95)
     base_mem = ctx.memory_used
 
     def run(rate):
-        ctx.server_start(n_streams=4, max_batch_jobs=64, prep_threads=threads, budget_bytes=int(budget_gb * 2**30))
+        ctx.server_start(n_streams=4, max_batch_jobs=64, prep_threads=threads, budget_bytes=int(budget_gb * 2**30),
+                         device_compile_nodes=device_compile_nodes)
         tickets = [0] * len(jobs)
         done = {}
         pending = []
@@ -466,6 +468,9 @@ def main():
     ap.add_argument("--threads", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--serve-jobs", type=int, default=20000, help="served-stream jobs (0 = skip serving)")
     ap.add_argument("--serve-only", action="store_true", help="run the served stream alone")
+    ap.add_argument("--serve-device-compile", type=int, default=0,
+                    help="served full jobs of at least this many nodes compile on the device (0: none, the "
+                         "library's default)")
     ap.add_argument("--generations", type=int, default=2, help="generations of the evolution leg (0 = skip)")
     ap.add_argument("--chunk-nodes", type=int, default=0, help="fix the chunk size (0 = automatic / tuned)")
     ap.add_argument("--variant", default="", help="fix the interpreter variant, e.g. f32_k4_s16")
@@ -520,7 +525,8 @@ def main():
         torch.cuda.init()
         ctx = g.Context(0)
         hc = host_cpu()
-        res = serve_bench(ctx, g, args.serve_jobs, args.threads, cpu=None if args.no_cpu_baseline else hc)
+        res = serve_bench(ctx, g, args.serve_jobs, args.threads, cpu=None if args.no_cpu_baseline else hc,
+                          device_compile_nodes=args.serve_device_compile)
         print(json.dumps({"serving": res, "host_cpu": hc}), flush=True)
         ctx.close()
         return
@@ -791,7 +797,8 @@ def main():
     if args.serve_jobs > 0:
         ctx.free(ph)
         serving = serve_bench(ctx, g, args.serve_jobs, args.threads,
-                              cpu=None if args.no_cpu_baseline else host_cpu())
+                              cpu=None if args.no_cpu_baseline else host_cpu(),
+                              device_compile_nodes=args.serve_device_compile)
 
     hostcpu = host_cpu()
     configs = None

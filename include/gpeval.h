@@ -394,7 +394,11 @@ typedef struct gp_server_cfg {
     int32_t n_streams;          /* batches that may be in flight at once (>= 1) */
     int32_t max_batch_jobs;     /* jobs merged into one launch at most */
     int32_t prep_threads;       /* host threads compiling arriving trees */
-    int32_t reserved;
+    int32_t device_compile_nodes; /* > 0: FULL jobs of at least this many nodes are compiled on
+                                     the device, on their prep thread's stream, into the same
+                                     programs as on the host; 0 or less: every job on the host
+                                     (the default: its prep threads use otherwise idle cores,
+                                     while device compilation contends with the batches in flight) */
     uint64_t budget_bytes;      /* HBM admitted at once (0 = the context budget) */
 } gp_server_cfg;
 
@@ -427,6 +431,8 @@ typedef struct gp_job_result {
                                    (assembly and upload, donor compilation, launches) */
     double run_ms;              /* enqueued to completion seen: device work and copy-out */
     int64_t root_bytes;         /* size of the job's output vector */
+    int32_t device_compiled;    /* FULL: 1 when its tree was compiled on the device */
+    int32_t reserved;
 } gp_job_result;
 
 int gp_server_start(gp_ctx* ctx, const gp_server_cfg* cfg);

@@ -289,9 +289,9 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
         if (rc__ != GP_OK) return rc__;                   \
     } while (0)
 
-int up(Ctx* c, DevBuf& b, const void* src, size_t bytes, hipStream_t s)
+int up(Ctx* c, DevArena* arena, DevBuf& b, const void* src, size_t bytes, hipStream_t s)
 {
-    RC(dev_alloc(c, b, bytes));
+    RC(scratch_alloc(c, arena, b, bytes));
     if (bytes) HIPC(c, hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
     return GP_OK;
 }
@@ -304,11 +304,11 @@ int down(Ctx* c, void* dst, const DevBuf& b, size_t bytes, hipStream_t s)
 
 // The flagged positions of flags[0 .. n), ascending, into out; their number
 // into *count.
-int dc_select(Ctx* c, const uint8_t* flags, int64_t n, DevBuf& out, int64_t* count, hipStream_t s)
+int dc_select(Ctx* c, DevArena* arena, const uint8_t* flags, int64_t n, DevBuf& out, int64_t* count, hipStream_t s)
 {
     const int64_t nb = (n + kDcSpan - 1) / kDcSpan;
     DevBuf bc;
-    RC(dev_alloc(c, bc, (size_t)nb * 8));
+    RC(scratch_alloc(c, arena, bc, (size_t)nb * 8));
     hipLaunchKernelGGL(k_dc_compact_count, dim3((unsigned)nb), dim3(256), 0, s, flags, n, bc.as<int64_t>());
     HIPC(c, hipGetLastError());
     std::vector<int64_t> h(nb);
@@ -321,7 +321,7 @@ int dc_select(Ctx* c, const uint8_t* flags, int64_t n, DevBuf& out, int64_t* cou
         run += v;
     }
     *count = run;
-    RC(dev_alloc(c, out, (size_t)std::max<int64_t>(1, run) * 8));
+    RC(scratch_alloc(c, arena, out, (size_t)std::max<int64_t>(1, run) * 8));
     if (run == 0) return GP_OK;
     HIPC(c, hipMemcpyAsync(bc.p, h.data(), (size_t)nb * 8, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_dc_compact_write, dim3((unsigned)nb), dim3(256), 0, s, flags, n, bc.as<int64_t>(),
@@ -332,10 +332,12 @@ int dc_select(Ctx* c, const uint8_t* flags, int64_t n, DevBuf& out, int64_t* cou
 }
 
 // Blocks of persistent waves for a launch over `items` units of work.
-unsigned dc_persistent_blocks(Ctx* c, int64_t items, int64_t batch)
+unsigned dc_persistent_blocks(Ctx* c, int64_t items, int64_t batch, int max_blocks)
 {
     const int64_t want = (items + batch * 4 - 1) / (batch * 4);
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)std::max(1, c->n_cu) * 8));
+    int64_t cap = (int64_t)std::max(1, c->n_cu) * 8;
+    if (max_blocks > 0) cap = std::min<int64_t>(cap, max_blocks);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
 }
 
 // f(i) for every i in [0, n), on up to 16 host threads taking blocks of
@@ -381,8 +383,9 @@ struct DcTrace {
 
 int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, const uint8_t* dops,
                               const int64_t* doffs, const int64_t* offsets, const uint8_t* host_ops,
-                              const int64_t* rec_points, const int64_t* rec_offsets, int64_t chunk_nodes,
-                              int64_t index_min_size, Pop* out, hipStream_t s)
+                              const int64_t* rec_points, const int64_t* rec_offsets, const int64_t* key_points,
+                              int64_t chunk_nodes, int64_t index_min_size, Pop* out,
+                              std::vector<TreeProg>* progs_out, DevArena* arena, hipStream_t s, int max_blocks)
 {
     const int64_t n = offsets[n_trees];
     if (n < 1 || n > (int64_t)INT32_MAX - 1) return set_err(c, GP_EINVAL, "at most 2^31 - 2 nodes per load");
@@ -403,11 +406,11 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     DcTrace tr;
     // validity, subtree ends and parents
     DevBuf valid, endl, parl;
-    RC(dev_alloc(c, valid, (size_t)n_trees * 4));
-    RC(dev_alloc(c, endl, (size_t)n * 4));
-    RC(dev_alloc(c, parl, (size_t)n * 4));
+    RC(scratch_alloc(c, arena, valid, (size_t)n_trees * 4));
+    RC(scratch_alloc(c, arena, endl, (size_t)n * 4));
+    RC(scratch_alloc(c, arena, parl, (size_t)n * 4));
     RC(index_trees(c, n_inputs, n_trees, dops, doffs, n, valid.as<int32_t>(), endl.as<int32_t>(),
-                   parl.as<int32_t>(), nullptr, nullptr));
+                   parl.as<int32_t>(), nullptr, nullptr, s, arena));
     {
         std::vector<int32_t> v(n_trees);
         RC(down(c, v.data(), valid, (size_t)n_trees * 4, s));
@@ -430,16 +433,16 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     const int64_t C = std::max<int64_t>(2, chunk_nodes);
     const bool packed = C <= kDcPackMaxC && compile_stack_slots() <= 32;
     DevBuf info, len, open, cnt, ncut, slot64, err, flags, big, counter;
-    if (index_min_size > 0) RC(dev_alloc(c, big, (size_t)n));
-    RC(dev_alloc(c, info, (size_t)n * 4));
-    RC(dev_alloc(c, len, (size_t)n * 4));
-    RC(dev_alloc(c, open, (size_t)n * 4));
-    RC(dev_alloc(c, cnt, (size_t)n * 4));
-    RC(dev_alloc(c, ncut, (size_t)n));
-    RC(dev_alloc(c, err, 4));
-    RC(dev_alloc(c, counter, 16));
+    if (index_min_size > 0) RC(scratch_alloc(c, arena, big, (size_t)n));
+    RC(scratch_alloc(c, arena, info, (size_t)n * 4));
+    RC(scratch_alloc(c, arena, len, (size_t)n * 4));
+    RC(scratch_alloc(c, arena, open, (size_t)n * 4));
+    RC(scratch_alloc(c, arena, cnt, (size_t)n * 4));
+    RC(scratch_alloc(c, arena, ncut, (size_t)n));
+    RC(scratch_alloc(c, arena, err, 4));
+    RC(scratch_alloc(c, arena, counter, 16));
     if (packed) {
-        RC(dev_alloc(c, slot64, (size_t)n * 8));
+        RC(scratch_alloc(c, arena, slot64, (size_t)n * 8));
         HIPC(c, launch_fill_i32(slot64.as<int32_t>(), 2 * n, 0, s));
     } else {
         HIPC(c, launch_fill_i32(cnt.as<int32_t>(), n, 0, s));
@@ -467,7 +470,7 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     q.C = C;
     if (packed) {
         HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
-        hipLaunchKernelGGL(k_dc_up_packed, dim3(dc_persistent_blocks(c, n, kDcBatch)), dim3(256), 0, s, q,
+        hipLaunchKernelGGL(k_dc_up_packed, dim3(dc_persistent_blocks(c, n, kDcBatch, max_blocks)), dim3(256), 0, s, q,
                            counter.as<unsigned long long>());
     } else {
         hipLaunchKernelGGL(k_dc_up, dim3(blocks_for(n)), dim3(256), 0, s, q);
@@ -489,8 +492,8 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         for (int64_t t = 0; t < n_trees; ++t)
             for (int64_t i = rec_offsets[t]; i < rec_offsets[t + 1]; ++i) pts[i] = offsets[t] + rec_points[i];
         DevBuf pts_d, depth_d, lvoff_d, lv_d, pop_d, pend_d;
-        RC(up(c, pts_d, pts.data(), (size_t)n_pts * 8, s));
-        RC(dev_alloc(c, depth_d, (size_t)n_pts * 4));
+        RC(up(c, arena, pts_d, pts.data(), (size_t)n_pts * 8, s));
+        RC(scratch_alloc(c, arena, depth_d, (size_t)n_pts * 4));
         hipLaunchKernelGGL(k_dc_paths, dim3(blocks_for(n_pts)), dim3(256), 0, s, q, pts_d.as<int64_t>(), n_pts,
                            (const int64_t*)nullptr, depth_d.as<int32_t>(), (DcPathLevel*)nullptr, (uint8_t*)nullptr,
                            (int32_t*)nullptr);
@@ -500,10 +503,10 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         HIPC(c, hipStreamSynchronize(s));
         std::vector<int64_t> lv_off(n_pts + 1, 0);
         for (int64_t i = 0; i < n_pts; ++i) lv_off[i + 1] = lv_off[i] + depth[i];
-        RC(up(c, lvoff_d, lv_off.data(), (size_t)(n_pts + 1) * 8, s));
-        RC(dev_alloc(c, lv_d, (size_t)std::max<int64_t>(1, lv_off[n_pts]) * sizeof(DcPathLevel)));
-        RC(dev_alloc(c, pop_d, (size_t)n_pts));
-        RC(dev_alloc(c, pend_d, (size_t)n_pts * 4));
+        RC(up(c, arena, lvoff_d, lv_off.data(), (size_t)(n_pts + 1) * 8, s));
+        RC(scratch_alloc(c, arena, lv_d, (size_t)std::max<int64_t>(1, lv_off[n_pts]) * sizeof(DcPathLevel)));
+        RC(scratch_alloc(c, arena, pop_d, (size_t)n_pts));
+        RC(scratch_alloc(c, arena, pend_d, (size_t)n_pts * 4));
         hipLaunchKernelGGL(k_dc_paths, dim3(blocks_for(n_pts)), dim3(256), 0, s, q, pts_d.as<int64_t>(), n_pts,
                            lvoff_d.as<int64_t>(), (int32_t*)nullptr, lv_d.as<DcPathLevel>(), pop_d.as<uint8_t>(),
                            pend_d.as<int32_t>());
@@ -524,6 +527,8 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             for (int64_t i = 0; i <= np; ++i) loff[i] = lv_off[p0 + i] - lv_off[p0];
             n_rec[t] = dc_tree_records(offsets[t], np, rec_points + p0, pop.data() + p0, pend.data() + p0,
                                        loff.data(), lv.data() + lv_off[p0], &spines[t], &st_t[t]);
+            if (key_points)
+                for (int64_t i = 0; i < np; ++i) spines[t][i].point = key_points[p0 + i];
         });
         std::vector<int64_t> st_off(n_trees + 1, 0);
         int64_t rb = 0;
@@ -547,8 +552,8 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
                 }
             });
             DevBuf nodes_d, cut_d, inc_d, ids_d;
-            RC(up(c, nodes_d, nodes.data(), (size_t)ns * 8, s));
-            RC(dev_alloc(c, cut_d, (size_t)ns));
+            RC(up(c, arena, nodes_d, nodes.data(), (size_t)ns * 8, s));
+            RC(scratch_alloc(c, arena, cut_d, (size_t)ns));
             hipLaunchKernelGGL(k_dc_cut_of, dim3(blocks_for(ns)), dim3(256), 0, s, q, nodes_d.as<int64_t>(), ns,
                                cut_d.as<uint8_t>());
             HIPC(c, hipGetLastError());
@@ -558,9 +563,9 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             dc_parallel(n_trees, [&](int64_t t) {
                 dc_store_words(st_t[t].data(), cut.data() + st_off[t], st_t[t].size(), inc.data() + st_off[t]);
             });
-            RC(up(c, inc_d, inc.data(), (size_t)ns * 4, s));
-            RC(up(c, ids_d, ids.data(), (size_t)ns * 4, s));
-            RC(dev_alloc(c, rec, (size_t)n * 4));
+            RC(up(c, arena, inc_d, inc.data(), (size_t)ns * 4, s));
+            RC(up(c, arena, ids_d, ids.data(), (size_t)ns * 4, s));
+            RC(scratch_alloc(c, arena, rec, (size_t)n * 4));
             HIPC(c, launch_fill_i32(rec.as<int32_t>(), n, -1, s));
             hipLaunchKernelGGL(k_dc_store, dim3(blocks_for(ns)), dim3(256), 0, s, q, nodes_d.as<int64_t>(),
                                inc_d.as<int32_t>(), ids_d.as<int32_t>(), ns, rec.as<int32_t>());
@@ -571,12 +576,12 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     }
     tr.mark("records");
     // chunk roots, ascending, and their numbering
-    RC(dev_alloc(c, flags, (size_t)n));
+    RC(scratch_alloc(c, arena, flags, (size_t)n));
     hipLaunchKernelGGL(k_dc_finish, dim3(blocks_for(n)), dim3(256), 0, s, q, flags.as<uint8_t>());
     HIPC(c, hipGetLastError());
     DevBuf roots_d;
     int64_t nch = 0;
-    RC(dc_select(c, flags.as<uint8_t>(), n, roots_d, &nch, s));   // waits for the stream
+    RC(dc_select(c, arena, flags.as<uint8_t>(), n, roots_d, &nch, s));   // waits for the stream
     flags.release();
     ncut.release();
     q.ncut = nullptr;                                               // the cuts are in the info words now
@@ -591,9 +596,9 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     std::vector<int32_t> rlen(nch), rend(nch);
     {
         DevBuf ids_d, rlen_d, rend_d;
-        RC(up(c, ids_d, ids.data(), (size_t)nch * 4, s));
-        RC(dev_alloc(c, rlen_d, (size_t)nch * 4));
-        RC(dev_alloc(c, rend_d, (size_t)nch * 4));
+        RC(up(c, arena, ids_d, ids.data(), (size_t)nch * 4, s));
+        RC(scratch_alloc(c, arena, rlen_d, (size_t)nch * 4));
+        RC(scratch_alloc(c, arena, rend_d, (size_t)nch * 4));
         hipLaunchKernelGGL(k_dc_root_info, dim3(blocks_for(nch)), dim3(256), 0, s, q, roots_d.as<int64_t>(),
                            ids_d.as<int32_t>(), nch, rlen_d.as<int32_t>(), rend_d.as<int32_t>());
         HIPC(c, hipGetLastError());
@@ -619,27 +624,31 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     // code emission, one pass: each child chunk learns its parent and which of
     // the parent's LOADs reads it; the LOAD lists are then put together here
     DevBuf root_d, ts_d, off_d, nin_d, par_d, lix_d, nodes_d, ms_d, st_d, slot;
-    RC(up(c, root_d, root.data(), (size_t)nch * 8, s));
-    RC(up(c, ts_d, tstart.data(), (size_t)nch * 8, s));
-    RC(up(c, off_d, code_off.data(), (size_t)nch * 8, s));
-    RC(dev_alloc(c, nin_d, (size_t)nch * 4));
-    RC(dev_alloc(c, par_d, (size_t)nch * 4));
-    RC(dev_alloc(c, lix_d, (size_t)nch * 4));
-    RC(dev_alloc(c, nodes_d, (size_t)nch * 8));
-    RC(dev_alloc(c, ms_d, (size_t)nch * 4));
-    RC(dev_alloc(c, st_d, (size_t)nch));
-    RC(dev_alloc(c, slot, (size_t)n));
+    RC(up(c, arena, root_d, root.data(), (size_t)nch * 8, s));
+    RC(up(c, arena, ts_d, tstart.data(), (size_t)nch * 8, s));
+    RC(up(c, arena, off_d, code_off.data(), (size_t)nch * 8, s));
+    RC(scratch_alloc(c, arena, nin_d, (size_t)nch * 4));
+    RC(scratch_alloc(c, arena, par_d, (size_t)nch * 4));
+    RC(scratch_alloc(c, arena, lix_d, (size_t)nch * 4));
+    RC(scratch_alloc(c, arena, nodes_d, (size_t)nch * 8));
+    RC(scratch_alloc(c, arena, ms_d, (size_t)nch * 4));
+    RC(scratch_alloc(c, arena, st_d, (size_t)nch));
+    RC(scratch_alloc(c, arena, slot, (size_t)n));
     q.slot = slot.as<uint8_t>();
     HIPC(c, launch_fill_i32(par_d.as<int32_t>(), nch, -1, s));
     HIPC(c, launch_fill_i32(lix_d.as<int32_t>(), nch, -1, s));
-    RC(dev_alloc(c, out->code, (size_t)(n_code + 1) * 4));
-    HIPC(c, launch_fill_i32((int32_t*)out->code.p + n_code, 1, 0, s));   // one word past the end for the fetch-ahead
+    // the program: the population's own buffer, or a temporary one copied to the host
+    DevBuf code_tmp;
+    DevBuf& code = out ? out->code : code_tmp;
+    if (out) RC(dev_alloc(c, code, (size_t)(n_code + 1) * 4));
+    else RC(scratch_alloc(c, arena, code, (size_t)(n_code + 1) * 4));
+    HIPC(c, launch_fill_i32((int32_t*)code.p + n_code, 1, 0, s));   // one word past the end for the fetch-ahead
     DcChunks ck{};
     ck.n = nch;
     ck.root = root_d.as<int64_t>();
     ck.tree_start = ts_d.as<int64_t>();
     ck.code_off = off_d.as<int64_t>();
-    ck.code = out->code.as<uint32_t>();
+    ck.code = code.as<uint32_t>();
     ck.n_in = nin_d.as<int32_t>();
     ck.parent = par_d.as<int32_t>();
     ck.load_idx = lix_d.as<int32_t>();
@@ -647,7 +656,7 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     ck.max_slot = ms_d.as<int32_t>();
     ck.stores = st_d.as<uint8_t>();
     HIPC(c, launch_fill_i32(counter.as<int32_t>(), 4, 0, s));
-    hipLaunchKernelGGL(k_dc_emit, dim3(dc_persistent_blocks(c, nch, kDcEmitBatch)), dim3(256), 0, s, q, ck,
+    hipLaunchKernelGGL(k_dc_emit, dim3(dc_persistent_blocks(c, nch, kDcEmitBatch, max_blocks)), dim3(256), 0, s, q, ck,
                        counter.as<unsigned long long>());
     HIPC(c, hipGetLastError());
     std::vector<int32_t> n_in(nch), parent(nch), load_idx(nch), max_slot(nch);
@@ -687,10 +696,10 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     if (index_min_size > 0) {
         DevBuf big_d;
         int64_t nb = 0;
-        RC(dc_select(c, big.as<uint8_t>(), n, big_d, &nb, s));
+        RC(dc_select(c, arena, big.as<uint8_t>(), n, big_d, &nb, s));
         if (nb > 0) {
             DevBuf bend_d;
-            RC(dev_alloc(c, bend_d, (size_t)nb * 4));
+            RC(scratch_alloc(c, arena, bend_d, (size_t)nb * 4));
             hipLaunchKernelGGL(k_dc_ends, dim3(blocks_for(nb)), dim3(256), 0, s, q, big_d.as<int64_t>(), nb,
                                bend_d.as<int32_t>());
             HIPC(c, hipGetLastError());
@@ -702,6 +711,58 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         }
     }
     tr.mark("large subtrees");
+
+    if (progs_out) {
+        // each tree's program in host memory, as compile_tree leaves it
+        std::vector<uint32_t> words((size_t)n_code);
+        HIPC(c, hipMemcpyAsync(words.data(), code.p, (size_t)n_code * 4, hipMemcpyDeviceToHost, s));
+        HIPC(c, hipStreamSynchronize(s));
+        progs_out->assign(n_trees, TreeProg());
+        int bad = 0;
+        dc_parallel(n_trees, [&](int64_t t) {
+            TreeProg& pg = (*progs_out)[t];
+            const int64_t b = cbase[t], m = cbase[t + 1] - b, s0 = offsets[t], w0 = code_off[b];
+            pg.code.assign(words.begin() + w0, words.begin() + code_off[cbase[t + 1]]);
+            pg.chunks.resize(m);
+            int32_t tms = 0;
+            for (int64_t i = m - 1; i >= 0; --i) {
+                const int64_t k = b + i;
+                Chunk& ch = pg.chunks[i];
+                const bool top = i == m - 1;
+                if (top != (parent[k] < 0) || (!top && (parent[k] <= k || parent[k] >= b + m))) {
+                    bad = 1;
+                    return;
+                }
+                ch.code_off = code_off[k] - w0;
+                ch.code_len = code_len[k];
+                ch.parent = top ? -1 : parent[k] - (int32_t)b;
+                ch.root_node = root[k] - s0;
+                ch.nodes = nodes[k];
+                ch.path_nodes = nodes[k] + (top ? 0 : pg.chunks[ch.parent].path_nodes);
+                ch.end_node = index_min_size > 0 ? rend[k] : -1;
+                ch.stores = stores[k] != 0;
+                ch.inputs.resize(n_in[k]);
+                for (int64_t j = in_off[k]; j < in_off[k + 1]; ++j) ch.inputs[j - in_off[k]] = ins[j] - (int32_t)b;
+                tms = std::max(tms, max_slot[k] + 1);
+            }
+            pg.max_stack = tms;
+            pg.n_records = n_rec[t];
+            pg.spines.swap(spines[t]);
+        });
+        if (bad) return set_err(c, GP_EINVAL, "internal error: inconsistent chunk graph");
+        for (int64_t t = 0; t < n_trees; ++t)
+            if ((*progs_out)[t].max_stack > compile_stack_slots())
+                return set_err(c, GP_EINVAL, "internal error: stack bound exceeded");
+        if (index_min_size > 0) {
+            int64_t t = 0;
+            for (size_t i = 0; i < big_nodes.size(); ++i) {
+                while (big_nodes[i] >= offsets[t + 1]) ++t;
+                (*progs_out)[t].big_ends.push_back({(int32_t)(big_nodes[i] - offsets[t]), big_end[i]});
+            }
+        }
+        tr.mark("programs to the host");
+        return GP_OK;
+    }
 
     // the population's tables, as assemble_population builds them
     out->vtype = vtype;
@@ -736,17 +797,20 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             return set_err(c, GP_EINVAL, "internal error: inconsistent chunk graph");
         path[k] = nodes[k] + (top ? 0 : path[parent[k]]);
     }
+    // with the subtree index, each tree's chunk list and chunk roots are kept
+    // for building children (as assemble_population does)
+    const bool keep = index_min_size > 0;
     std::vector<DevChunk> dch(nch);
-    std::vector<int32_t> chunk_in((size_t)in_off[nch]);
-    out->kept_chunks.assign(n_trees, {});
-    out->kept_max_stack.assign(n_trees, 0);
-    out->cuts.assign(n_trees, {});
+    std::vector<int32_t> chunk_in((size_t)in_off[nch]), tree_ms(n_trees, 0);
+    out->kept_chunks.clear();
+    out->kept_max_stack.clear();
+    out->cuts.clear();
+    if (keep) {
+        out->kept_chunks.resize(n_trees);
+        out->cuts.resize(n_trees);
+    }
     dc_parallel(n_trees, [&](int64_t t) {
         const int64_t b = cbase[t], m = cbase[t + 1] - b, s0 = offsets[t];
-        auto& kc = out->kept_chunks[t];
-        kc.resize(m);
-        auto& cl = out->cuts[t];
-        cl.reserve(m);
         int32_t tms = 0;
         for (int64_t i = 0; i < m; ++i) {
             const int64_t k = b + i;
@@ -758,6 +822,17 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             d.in_off = (int32_t)in_off[k];
             d.rec_base = (int32_t)rec_base[t];
             d.n_in = n_in[k];
+            for (int64_t j = in_off[k]; j < in_off[k + 1]; ++j) chunk_in[j] = (int32_t)out_slot[ins[j]];
+            tms = std::max(tms, max_slot[k] + 1);
+        }
+        tree_ms[t] = tms;
+        if (!keep) return;
+        auto& kc = out->kept_chunks[t];
+        kc.resize(m);
+        auto& cl = out->cuts[t];
+        cl.reserve(m);
+        for (int64_t i = 0; i < m; ++i) {
+            const int64_t k = b + i;
             Chunk& ch = kc[i];
             ch.code_off = code_off[k];
             ch.code_len = code_len[k];
@@ -765,29 +840,25 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
             ch.root_node = root[k] - s0;
             ch.nodes = nodes[k];
             ch.path_nodes = path[k];
-            ch.end_node = index_min_size > 0 ? rend[k] : -1;
+            ch.end_node = rend[k];
             ch.dev_src = -1;
             ch.stores = stores[k] != 0;
             ch.vec_slot = out_slot[k];
             ch.src_vec = -1;
             ch.inputs.resize(n_in[k]);
-            for (int64_t j = in_off[k]; j < in_off[k + 1]; ++j) {
-                chunk_in[j] = (int32_t)out_slot[ins[j]];
-                ch.inputs[j - in_off[k]] = ins[j] - (int32_t)b;
-            }
-            tms = std::max(tms, max_slot[k] + 1);
+            for (int64_t j = in_off[k]; j < in_off[k + 1]; ++j) ch.inputs[j - in_off[k]] = ins[j] - (int32_t)b;
             cl.push_back(Pop::CutSlot{(int32_t)ch.root_node, rend[k], (int32_t)out_slot[k]});
         }
         std::sort(cl.begin(), cl.end(), [](const Pop::CutSlot& x, const Pop::CutSlot& y) { return x.node < y.node; });
-        out->kept_max_stack[t] = tms;
     });
+    if (keep) out->kept_max_stack = tree_ms;
     for (int64_t k = 0; k < nch; ++k)
         if (n_in[k] == 0) out->leaves.emplace_back(path[k], (int32_t)k);
     std::vector<SpineLvl> levels;
     out->max_stack = 0;
     int64_t n_records = 0;
     for (int64_t t = 0; t < n_trees; ++t) {
-        const int32_t tms = out->kept_max_stack[t];
+        const int32_t tms = tree_ms[t];
         if (tms > compile_stack_slots()) return set_err(c, GP_EINVAL, "internal error: stack bound exceeded");
         out->max_stack = std::max(out->max_stack, tms);
         for (auto& sp : spines[t]) {
@@ -819,9 +890,9 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
                      [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
                          return x.first > y.first;
                      });
-    RC(up(c, out->chunks, dch.data(), dch.size() * sizeof(DevChunk), s));
-    RC(up(c, out->chunk_in, chunk_in.data(), chunk_in.size() * 4, s));
-    RC(up(c, out->levels, levels.data(), levels.size() * sizeof(SpineLvl), s));
+    RC(up(c, nullptr, out->chunks, dch.data(), dch.size() * sizeof(DevChunk), s));
+    RC(up(c, nullptr, out->chunk_in, chunk_in.data(), chunk_in.size() * 4, s));
+    RC(up(c, nullptr, out->levels, levels.data(), levels.size() * sizeof(SpineLvl), s));
     HIPC(c, hipStreamSynchronize(s));
     tr.mark("tables");
     return GP_OK;

@@ -30,6 +30,7 @@ struct DevBuf {
     Ctx* ctx = nullptr;
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;       // memory of a DevArena: not freed by release()
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -40,8 +41,19 @@ struct DevBuf {
         std::swap(ctx, o.ctx);
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
+        std::swap(borrowed, o.borrowed);
     }
     template <class T> T* as() const { return (T*)p; }
+};
+
+// Device memory a caller reuses across calls (a server's prep thread
+// compiling tree after tree): temporaries are carved from one buffer instead
+// of being allocated and freed one by one, since a free waits for the whole
+// device and would stall every batch in flight.
+struct DevArena {
+    DevBuf buf;
+    size_t used = 0;             // bytes handed out since the last reset
+    size_t high = 0;             // most ever asked for between two resets
 };
 
 struct CaseSet {
@@ -202,6 +214,12 @@ struct Ctx {
 // ------------------------------------------------------------ internals
 int set_err(Ctx* c, int code, const std::string& msg);
 int dev_alloc(Ctx* c, DevBuf& b, size_t bytes);
+// b = bytes of temporary device memory: from arena a when it is given and has
+// room (b then does not own it), else allocated.
+int scratch_alloc(Ctx* c, DevArena* a, DevBuf& b, size_t bytes);
+// All of the arena's memory is free again (nothing may still use it); it
+// grows to the most that was asked for since the last reset.
+int arena_reset(Ctx* c, DevArena* a);
 int hip_check(Ctx* c, hipError_t e, const char* what);
 
 // Compile and upload a population (prefix or postfix trees) on stream s
@@ -254,19 +272,31 @@ int enqueue_incremental(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases
 // rounds synchronously on s; interp receives the nodes actually executed.
 int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, const CaseSet* cs,
                    bool want_roots, hipStream_t s, IncOut* out, int64_t* launches, int64_t* rounds);
-// Device tree index (gp_index_trees without the lock): on the context stream,
-// waits for the result.
+// Device tree index (gp_index_trees without the lock) on stream st; waits for
+// the result.  device_ms (may be null) uses the context's events: only for
+// callers holding the context lock.
 int index_trees(Ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
-                int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler, double* device_ms);
+                int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler, double* device_ms,
+                hipStream_t st, DevArena* arena = nullptr);
 // Compile a population of prefix trees on the device (devcompile.hip): the
 // same programs and tables as build_population.  dops/doffs: the trees and
 // offsets in device memory (dops 16-byte aligned); offsets: host copy;
 // host_ops (may be null): host copy, for error messages; record points as
-// build_population's, host arrays.  Runs on the context stream s and waits.
+// build_population's, host arrays (prefix indices); key_points (may be null):
+// the caller's indices of the same points, for the spine keys.
+// index_min_size > 0: index large subtrees and keep each tree's chunk list
+// for building children (as build_population with index_subtrees).  The
+// result goes to exactly one of out (a population on the device) or
+// progs_out (each tree's program in host memory, as compile_tree gives it,
+// for assemble_population).  arena (may be null): where temporaries come
+// from.  max_blocks > 0 caps the workgroups of its persistent kernels (a
+// compilation that shares the device with running work).  Runs on stream s
+// (any thread; it does not use the context stream or events) and waits for it.
 int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, const uint8_t* dops,
                               const int64_t* doffs, const int64_t* offsets, const uint8_t* host_ops,
-                              const int64_t* rec_points, const int64_t* rec_offsets, int64_t chunk_nodes,
-                              int64_t index_min_size, Pop* out, hipStream_t s);
+                              const int64_t* rec_points, const int64_t* rec_offsets, const int64_t* key_points,
+                              int64_t chunk_nodes, int64_t index_min_size, Pop* out,
+                              std::vector<TreeProg>* progs_out, DevArena* arena, hipStream_t s, int max_blocks = 0);
 // build_population on the device for prefix trees given in host memory
 // (host_ops) or device memory (dev_ops); offsets in host memory.  When
 // ops_keep is given, it receives a device copy of the trees (32 bytes of

@@ -47,12 +47,38 @@ DevBuf::~DevBuf() { release(); }
 
 void DevBuf::release()
 {
-    if (p) {
+    if (p && !borrowed) {
         (void)hipFree(p);
         if (ctx) ctx->used -= bytes;
     }
     p = nullptr;
     bytes = 0;
+    borrowed = false;
+}
+
+int scratch_alloc(Ctx* c, DevArena* a, DevBuf& b, size_t bytes)
+{
+    if (!a) return dev_alloc(c, b, bytes);
+    b.release();
+    const size_t r = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    a->high = std::max(a->high, a->used + r);
+    if (a->used + r > a->buf.bytes) return dev_alloc(c, b, bytes);   // the arena grows at its next reset
+    b.p = (uint8_t*)a->buf.p + a->used;
+    b.bytes = r;
+    b.ctx = nullptr;
+    b.borrowed = true;
+    a->used += r;
+    return GP_OK;
+}
+
+int arena_reset(Ctx* c, DevArena* a)
+{
+    a->used = 0;
+    if (a->high > a->buf.bytes) {
+        a->buf.release();
+        RC(dev_alloc(c, a->buf, a->high + a->high / 4));
+    }
+    return GP_OK;
 }
 
 int dev_alloc(Ctx* c, DevBuf& b, size_t bytes)
@@ -286,7 +312,8 @@ int build_population_device(Ctx* c, int vtype, int n_inputs, int64_t n_trees, co
                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
     }
     RC(device_compile_population(c, vtype, n_inputs, n_trees, dops, offs.as<int64_t>(), offsets, host_ops,
-                                 rec_points, rec_offsets, chunk_nodes, kBigSubtree, out, s));
+                                 rec_points, rec_offsets, nullptr, chunk_nodes, kBigSubtree, out, nullptr, nullptr,
+                                 s));
     out->layout = GP_PREFIX;
     out->device_compiled = true;
     if (ops_keep) ops_keep->swap(ops_buf);
@@ -2235,33 +2262,36 @@ static int64_t ix_levels(int64_t n, IxParams& q, int64_t (&len)[kIxMaxLevels])
 // waits for the offsets flag (and, per Strahler level, for the level's flag).
 // Flags are cleared by a fill kernel.  Allocates nothing.
 static int ix_run(Ctx* ctx, IxParams& q, int32_t* bsum, int32_t* flag, int64_t nb, const int64_t* len,
-                  double* device_ms)
+                  double* device_ms, hipStream_t st)
 {
     q.bad_offsets = flag;
-    HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    HIPC(ctx, launch_fill_i32(flag, 2, 0, ctx->stream));
-    if (q.sn) HIPC(ctx, launch_fill_u8(q.bempty, nb + 1, 1, ctx->stream));      // block nb holds only E(n)
-    HIPC(ctx, launch_index(q, bsum, nb, len, ctx->stream));
+    // timed with the context's events (entry points that hold the context lock only)
+    if (device_ms) HIPC(ctx, hipEventRecord(ctx->ev0, st));
+    HIPC(ctx, launch_fill_i32(flag, 2, 0, st));
+    if (q.sn) HIPC(ctx, launch_fill_u8(q.bempty, nb + 1, 1, st));      // block nb holds only E(n)
+    HIPC(ctx, launch_index(q, bsum, nb, len, st));
     if (q.sn) {
         // one pass per level, while some function has two children at the current level
         int32_t* any = flag + 1;
-        HIPC(ctx, launch_strahler_init(q, ctx->stream));
+        HIPC(ctx, launch_strahler_init(q, st));
         for (int level = 2; level < 64; ++level) {          // the initial numbers settle level 1
-            HIPC(ctx, launch_fill_i32(any, 1, 0, ctx->stream));
-            HIPC(ctx, launch_strahler_level(q, level, bsum, nb, any, ctx->stream));
+            HIPC(ctx, launch_fill_i32(any, 1, 0, st));
+            HIPC(ctx, launch_strahler_level(q, level, bsum, nb, any, st));
             int32_t more = 0;
-            HIPC(ctx, hipMemcpyAsync(&more, any, 4, hipMemcpyDeviceToHost, ctx->stream));
-            HIPC(ctx, hipStreamSynchronize(ctx->stream));
+            HIPC(ctx, hipMemcpyAsync(&more, any, 4, hipMemcpyDeviceToHost, st));
+            HIPC(ctx, hipStreamSynchronize(st));
             if (!more) break;
         }
     }
     int32_t bad = 0;
-    HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-    HIPC(ctx, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
-    HIPC(ctx, hipStreamSynchronize(ctx->stream));
-    float ms = 0.f;
-    HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    if (device_ms) *device_ms = ms;
+    if (device_ms) HIPC(ctx, hipEventRecord(ctx->ev1, st));
+    HIPC(ctx, hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    if (device_ms) {
+        float ms = 0.f;
+        HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        *device_ms = ms;
+    }
     if (bad) return set_err(ctx, GP_EINVAL, "offsets must run from 0 to n_nodes without decreasing");
     return GP_OK;
 }
@@ -2286,7 +2316,7 @@ static IxParams ix_params(int n_inputs, int64_t n_trees, const uint8_t* ops, con
 
 int gpe::index_trees(Ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops, const int64_t* offsets,
                      int64_t n_nodes, int32_t* valid, int32_t* end, int32_t* parent, uint8_t* strahler,
-                     double* device_ms)
+                     double* device_ms, hipStream_t st, DevArena* arena)
 {
     RC(ix_check_args(ctx, n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent));
     IxParams q = ix_params(n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent, strahler);
@@ -2294,17 +2324,17 @@ int gpe::index_trees(Ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops
     const int64_t seg_total = ix_levels(n_nodes, q, len);
     const int64_t nb = (n_nodes + kIxBlock - 1) / kIxBlock;
     DevBuf el, boff, bsum, seg, flag, bempty;
-    RC(dev_alloc(ctx, el, (size_t)(nb * kIxBlock + kIxFan) * 4));
-    RC(dev_alloc(ctx, boff, (size_t)(nb + 1) * 4));
-    RC(dev_alloc(ctx, bsum, (size_t)nb * 4));
-    RC(dev_alloc(ctx, seg, (size_t)(seg_total + kIxFan) * 4));
-    RC(dev_alloc(ctx, flag, 8));
-    if (strahler) RC(dev_alloc(ctx, bempty, (size_t)nb + 1));
+    RC(scratch_alloc(ctx, arena, el, (size_t)(nb * kIxBlock + kIxFan) * 4));
+    RC(scratch_alloc(ctx, arena, boff, (size_t)(nb + 1) * 4));
+    RC(scratch_alloc(ctx, arena, bsum, (size_t)nb * 4));
+    RC(scratch_alloc(ctx, arena, seg, (size_t)(seg_total + kIxFan) * 4));
+    RC(scratch_alloc(ctx, arena, flag, 8));
+    if (strahler) RC(scratch_alloc(ctx, arena, bempty, (size_t)nb + 1));
     q.el = el.as<int32_t>();
     q.boff = boff.as<int32_t>();
     q.seg = seg.as<int32_t>();
     q.bempty = strahler ? bempty.as<uint8_t>() : nullptr;
-    return ix_run(ctx, q, bsum.as<int32_t>(), flag.as<int32_t>(), nb, len, device_ms);
+    return ix_run(ctx, q, bsum.as<int32_t>(), flag.as<int32_t>(), nb, len, device_ms, st);
 }
 
 extern "C" {
@@ -2316,7 +2346,8 @@ int gp_index_trees(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* op
     if (!ctx) return GP_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     HIPC(ctx, hipSetDevice(ctx->device));
-    return index_trees(ctx, n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent, strahler, device_ms);
+    return index_trees(ctx, n_inputs, n_trees, ops, offsets, n_nodes, valid, end, parent, strahler, device_ms,
+                       ctx->stream);
 }
 
 static_assert(GP_INDEX_NOALLOC_MAX_NODES == kIxStaticMaxNodes, "header and scratch array disagree");
@@ -2342,7 +2373,7 @@ int gp_index_trees_noalloc(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uin
     q.boff = base + kIxStaticBoff;
     q.seg = base + kIxStaticSeg;
     q.bempty = strahler ? (uint8_t*)(base + kIxStaticBempty) : nullptr;
-    return ix_run(ctx, q, base + kIxStaticBsum, base + kIxStaticFlag, nb, len, device_ms);
+    return ix_run(ctx, q, base + kIxStaticBsum, base + kIxStaticFlag, nb, len, device_ms, ctx->stream);
 }
 
 int gp_valu_calibration(gp_ctx* ctx, int cls, int64_t n_waves, int64_t iters, double* device_ms)

@@ -51,6 +51,7 @@ struct SJob {
     bool keep_resident = false;
     int layout = GP_PREFIX;
     TreeProg prog;                          // FULL: compiled on arrival
+    bool device_compiled = false;           // FULL: prog was built on the device
     uint64_t est_bytes = 0;
     enum State { ARRIVED, READY, RUNNING, DONE } state = ARRIVED;
     double t_submit = 0, t_ready = 0, t_admit = 0, t_enq = 0, t_done = 0;
@@ -107,6 +108,9 @@ struct Server {
     uint64_t admitted_bytes = 0;
 
     std::vector<hipStream_t> streams;
+    std::vector<hipStream_t> prep_streams;   // one per prep thread, for device compilation
+    std::vector<std::unique_ptr<DevArena>> prep_arenas;   // and its temporaries
+    int64_t device_compile_nodes = 0;        // FULL jobs this large compile on the device (0: never)
     std::vector<void*> pinned;               // per slot staging buffer
     size_t pinned_bytes = 0;
     std::vector<std::thread> workers;
@@ -143,6 +147,46 @@ uint64_t estimate_full(const TreeProg& pg, const CaseSet* cs)
     return b + 64 * 1024;   // plan, graph-free launch state, fitness
 }
 
+// Workgroups a prep thread's compilation may use at once: a small slice of the
+// device, which is busy with the batches in flight.
+constexpr int kPrepBlocks = 32;
+
+// Compile a FULL job's tree on the device, on its prep thread's stream st with
+// that thread's arena for temporaries, into j->prog (host memory), so the job
+// batches with the others exactly as a tree compiled on the host.
+int compile_on_device(Server* S, SJob* j, hipStream_t st, DevArena* arena)
+{
+    Ctx* c = S->ctx;
+    const CaseSet* cs = j->cs.get();
+    const int64_t n = (int64_t)j->ops.size();
+    int rc = arena_reset(c, arena);
+    if (rc != GP_OK) return rc;
+    DevBuf dops, doffs;
+    rc = scratch_alloc(c, arena, dops, (size_t)n + 32);
+    if (rc != GP_OK) return rc;
+    rc = scratch_alloc(c, arena, doffs, 16);
+    if (rc != GP_OK) return rc;
+    const int64_t offs[2] = {0, n};
+    if (hipMemcpyAsync(dops.p, j->ops.data(), (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(doffs.p, offs, 16, hipMemcpyHostToDevice, st) != hipSuccess)
+        return set_err(c, GP_EDEVICE, "upload of a served tree failed");
+    const int64_t np = (int64_t)j->points.size();
+    const int64_t roffs[2] = {0, np};
+    std::vector<TreeProg> progs;
+    rc = device_compile_population(c, cs->vtype, cs->n_inputs, 1, dops.as<uint8_t>(), doffs.as<int64_t>(), offs,
+                                   j->ops.data(), np ? j->points.data() : nullptr, np ? roffs : nullptr,
+                                   np ? j->caller_points.data() : nullptr,
+                                   auto_chunk_nodes(cs->vtype, n, 1, cs->T), 0, nullptr, &progs, arena, st,
+                                   kPrepBlocks);
+    if (rc != GP_OK) {
+        (void)hipStreamSynchronize(st);        // nothing may still use the arena
+        return rc;
+    }
+    j->prog = std::move(progs[0]);
+    j->device_compiled = true;
+    return GP_OK;
+}
+
 uint64_t estimate_incremental(int64_t donor_nodes, const CaseSet* cs)
 {
     const uint64_t esz = cs->vtype == GP_BOOL ? 8 : 4;
@@ -168,7 +212,7 @@ void fail_job(Server* S, SJob* j, int code)
 }
 
 // ------------------------------------------------------------ workers
-void prep_worker(Server* S)
+void prep_worker(Server* S, int idx)
 {
     for (;;) {
         std::shared_ptr<SJob> j;
@@ -194,7 +238,14 @@ void prep_worker(Server* S)
         } else if (!validate_prefix(j->ops.data(), (int64_t)j->ops.size(), cs->n_inputs, &why)) {
             status = GP_EINVAL;
         }
-        if (status == GP_OK && j->kind == GP_JOB_FULL) {
+        if (status == GP_OK && j->kind == GP_JOB_FULL && S->device_compile_nodes > 0 &&
+            (int64_t)j->ops.size() >= S->device_compile_nodes) {
+            status = compile_on_device(S, j.get(), S->prep_streams[idx], S->prep_arenas[idx].get());
+            if (status == GP_OK) {
+                for (size_t i = 0; i < j->caller_points.size(); ++i) j->prog.spines[i].point = j->caller_points[i];
+                j->est_bytes = estimate_full(j->prog, cs);
+            }
+        } else if (status == GP_OK && j->kind == GP_JOB_FULL) {
             CompileOptions opt;
             opt.vtype = cs->vtype;
             opt.n_inputs = cs->n_inputs;
@@ -270,11 +321,11 @@ int launch_batch(Server* S, SBatch* b)
             nodes[i] = (int64_t)b->jobs[i]->ops.size();
         }
         b->pop = std::make_shared<Pop>();
-        int rc = assemble_population(c, cs->vtype, cs->n_inputs, progs, nodes, 0, b->pop.get(), s);
-        if (rc != GP_OK) return rc;
+        int rc0 = assemble_population(c, cs->vtype, cs->n_inputs, progs, nodes, 0, b->pop.get(), s);
+        if (rc0 != GP_OK) return rc0;
         const int v = choose_for(S, cs->vtype, cs, b->pop.get());
         if (v < 0) return GP_EINVAL;
-        rc = enqueue_full(c, b->pop.get(), ch, cs, v, false, false, s, nullptr);
+        const int rc = enqueue_full(c, b->pop.get(), ch, cs, v, false, false, s, nullptr);
         if (rc != GP_OK) return rc;
         if (hipMemcpyAsync(st_fit, b->pop->fit.p, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpy2DAsync(st_root, vbytes, b->pop->vecs.p, (size_t)cs->stride * esz, vbytes, n,
@@ -433,6 +484,7 @@ void complete_loop(Server* S)
             } else {
                 j->result.stop_level = -1;
                 j->result.interpreted_nodes = (int64_t)j->ops.size();
+                j->result.device_compiled = j->device_compiled ? 1 : 0;
                 if (j->keep_resident) j->tree_in_pop = i;
             }
             j->result.status = GP_OK;
@@ -486,6 +538,8 @@ int gp_server_start(gp_ctx* ctxp, const gp_server_cfg* cfg)
     S->cfg.max_batch_jobs = cfg && cfg->max_batch_jobs > 0 ? cfg->max_batch_jobs : 64;
     S->cfg.prep_threads = cfg && cfg->prep_threads > 0 ? cfg->prep_threads : 8;
     S->cfg.budget_bytes = cfg ? cfg->budget_bytes : 0;
+    S->cfg.device_compile_nodes = cfg ? cfg->device_compile_nodes : 0;
+    S->device_compile_nodes = std::max<int64_t>(0, S->cfg.device_compile_nodes);
     S->budget = S->cfg.budget_bytes ? std::min<uint64_t>(S->cfg.budget_bytes, ctx->budget) : ctx->budget;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -504,9 +558,21 @@ int gp_server_start(gp_ctx* ctxp, const gp_server_cfg* cfg)
         S->streams.push_back(s);
         S->pinned.push_back(h);
     }
+    for (int i = 0; i < S->cfg.prep_threads; ++i) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : S->streams) (void)hipStreamDestroy(x);
+            for (auto x : S->prep_streams) (void)hipStreamDestroy(x);
+            for (auto h : S->pinned) (void)hipHostFree(h);
+            delete S;
+            return set_err(ctx, GP_EDEVICE, "server stream allocation failed");
+        }
+        S->prep_streams.push_back(s);
+        S->prep_arenas.push_back(std::make_unique<DevArena>());
+    }
     S->slot_busy.assign(S->cfg.n_streams, 0);
     ctx->server = S;
-    for (int i = 0; i < S->cfg.prep_threads; ++i) S->workers.emplace_back(prep_worker, S);
+    for (int i = 0; i < S->cfg.prep_threads; ++i) S->workers.emplace_back(prep_worker, S, i);
     S->dispatcher = std::thread(dispatch_loop, S);
     S->completer = std::thread(complete_loop, S);
     return GP_OK;
@@ -648,6 +714,8 @@ int gp_server_stop(gp_ctx* ctxp)
     S->ready.clear();
     S->arrived.clear();
     for (auto s : S->streams) (void)hipStreamDestroy(s);
+    for (auto s : S->prep_streams) (void)hipStreamDestroy(s);
+    S->prep_arenas.clear();
     for (auto h : S->pinned) (void)hipHostFree(h);
     ctx->server = nullptr;
     delete S;

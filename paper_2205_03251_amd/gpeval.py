@@ -83,7 +83,7 @@ class PopInfo(C.Structure):
 
 class ServerCfg(C.Structure):
     _fields_ = [("n_streams", C.c_int32), ("max_batch_jobs", C.c_int32), ("prep_threads", C.c_int32),
-                ("reserved", C.c_int32), ("budget_bytes", C.c_uint64)]
+                ("device_compile_nodes", C.c_int32), ("budget_bytes", C.c_uint64)]
 
 
 class Job(C.Structure):
@@ -97,7 +97,8 @@ class JobResult(C.Structure):
     _fields_ = [("fitness_f64", C.c_double), ("fitness_i64", C.c_int64), ("stop_level", C.c_int32),
                 ("status", C.c_int32), ("interpreted_nodes", C.c_int64), ("latency_ms", C.c_double),
                 ("queue_ms", C.c_double), ("prep_ms", C.c_double), ("launch_ms", C.c_double),
-                ("run_ms", C.c_double), ("root_bytes", C.c_int64)]
+                ("run_ms", C.c_double), ("root_bytes", C.c_int64), ("device_compiled", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -555,8 +556,8 @@ class Context:
         return f
 
     # ------------------------------------------------------------ serving
-    def server_start(self, n_streams=4, max_batch_jobs=64, prep_threads=8, budget_bytes=0):
-        cfg = ServerCfg(n_streams, max_batch_jobs, prep_threads, 0, budget_bytes)
+    def server_start(self, n_streams=4, max_batch_jobs=64, prep_threads=8, budget_bytes=0, device_compile_nodes=0):
+        cfg = ServerCfg(n_streams, max_batch_jobs, prep_threads, device_compile_nodes, budget_bytes)
         self._check(lib().gp_server_start(self._h, C.byref(cfg)))
 
     def server_submit(self, kind, cases, ops, layout=GP_PREFIX, record_points=None, parent_ticket=0, point=0,
@@ -580,7 +581,7 @@ class Context:
         if rc == GP_EBUSY:
             return None
         self._check(rc)
-        out = {k: getattr(r, k) for k, _ in r._fields_}
+        out = {k: getattr(r, k) for k, _ in r._fields_ if k != "reserved"}
         out["root"] = root
         return out
 

@@ -135,7 +135,7 @@ def test_served_stream_shape_alone_mix_and_oracle():
     ctx = g.Context(0)
     handles = {g.GP_F32: ctx.set_cases(g.GP_F32, fc.x, fc.y),
                g.GP_BOOL: ctx.set_cases(g.GP_BOOL, bc.inputs, bc.target, T)}
-    ctx.server_start(n_streams=4, max_batch_jobs=16, prep_threads=8)
+    ctx.server_start(n_streams=4, max_batch_jobs=16, prep_threads=8, device_compile_nodes=262144)
     say("alone")
     alone = run(ctx, handles, parents, small, mix=False)
     say("mix")
@@ -145,6 +145,8 @@ def test_served_stream_shape_alone_mix_and_oracle():
     assert alone.keys() == mixed.keys()
     for k in alone:
         assert same_result(alone[k], mixed[k]), k
+    for pi in range(len(parents)):                  # trees of 1.2e6..1e7 nodes: compiled on the device
+        assert alone[("p", pi)]["device_compiled"] == 1 and mixed[("p", pi)]["device_compiled"] == 1
     say("oracle")
     with ThreadPoolExecutor(POOL) as pool:
         sample = np.concatenate([np.arange(0, 128), np.arange(T - 128, T)])

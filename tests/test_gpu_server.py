@@ -233,3 +233,91 @@ def test_poll_refuses_a_small_output_buffer():
     assert same_f32(out["root"], c.x[0] * c.x[0]).all()
     ctx.server_stop()
     ctx.close()
+
+
+def to_postfix(t):
+    """Reverse Polish form of a prefix tree and the RPN index of every prefix
+    node (operands left then right, then the function)."""
+    ends = gen.subtree_ends(t)
+    out = []
+    where = np.empty(len(t), np.int64)
+    stack = [(0, False)]
+    while stack:
+        i, done = stack.pop()
+        if done or not (int(t[i]) & 0x80):
+            where[i] = len(out)
+            out.append(int(t[i]))
+            continue
+        stack.append((i, True))
+        stack.append((int(ends[i + 1]), False))
+        stack.append((i + 1, False))
+    return np.array(out, np.uint8), where
+
+
+def test_device_compiled_jobs_match_host_compiled():
+    """Full jobs compiled on the device (every one of them, down to one-node
+    trees, with device_compile_nodes=1) give the same results, and their
+    children the same incremental results, as with host compilation; a job
+    given in reverse Polish order keeps its caller's point indices."""
+    rng = np.random.default_rng(5)
+    fc = gen.float_cases(7, 512)
+    bc = gen.bool_cases(8)
+    ctx = g.Context(0)
+    hf = ctx.set_cases(g.GP_F32, fc.x, fc.y)
+    hb = ctx.set_cases(g.GP_BOOL, bc.inputs, bc.target, 256)
+    jobs = []    # (vtype, handle, layout, ops, points (job layout), children [(point (job layout), donor (job layout))])
+    for n, vt in [(1, g.GP_F32), (3, g.GP_BOOL), (2001, g.GP_F32), (40001, g.GP_BOOL), (300001, g.GP_F32),
+                  (120001, g.GP_F32)]:
+        nt = 8 if vt == g.GP_BOOL else 1
+        tree = gen.sized_tree(rng, n, n_terms=nt)
+        pts = sorted(set(int(p) for p in rng.integers(n, size=3)))
+        kids = [(p, gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 201)), n_terms=nt)) for p in pts]
+        jobs.append((vt, hb if vt == g.GP_BOOL else hf, g.GP_PREFIX, tree, pts, kids))
+    # the last one in reverse Polish order, points and donors too
+    vt, h, _, tree, pts, kids = jobs[-1]
+    post, where = to_postfix(tree)
+    jobs[-1] = (vt, h, g.GP_POSTFIX, post, [int(where[p]) for p in pts],
+                [(int(where[p]), to_postfix(d)[0]) for p, d in kids])
+    results = {}
+    for dcn in (-1, 1):
+        ctx.server_start(n_streams=4, max_batch_jobs=8, prep_threads=4, device_compile_nodes=dcn)
+        out, tickets = {}, []
+        for ji, (vt, h, lay, ops, pts, kids) in enumerate(jobs):
+            tickets.append(ctx.server_submit(g.GP_JOB_FULL, h, ops, layout=lay, record_points=np.array(pts, np.int64),
+                                             keep_resident=True))
+        kid_t = []
+        for ji, (vt, h, lay, ops, pts, kids) in enumerate(jobs):
+            for ki, (p, d) in enumerate(kids):
+                kid_t.append((ji, ki, ctx.server_submit(g.GP_JOB_INCREMENTAL, h, d, layout=lay,
+                                                        parent_ticket=tickets[ji], point=p)))
+        Ts = {hf: fc.T, hb: 256}
+        for ji, t in enumerate(tickets):
+            out[("p", ji)] = wait(ctx, t, jobs[ji][0], Ts[jobs[ji][1]])
+        for ji, ki, t in kid_t:
+            out[("c", ji, ki)] = wait(ctx, t, jobs[ji][0], Ts[jobs[ji][1]])
+        for t in tickets:
+            ctx.server_release(t)
+        ctx.server_stop()
+        results[dcn] = out
+    host, dev = results[-1], results[1]
+    for k in host:
+        a, b = host[k], dev[k]
+        assert a["status"] == 0 and b["status"] == 0, k
+        if a["root"].dtype == np.float32:
+            assert same_f32(a["root"], b["root"]).all(), k
+            assert a["fitness_f64"] == b["fitness_f64"] or (math.isnan(a["fitness_f64"]) and math.isnan(b["fitness_f64"]))
+        else:
+            assert np.array_equal(a["root"], b["root"]) and a["fitness_i64"] == b["fitness_i64"], k
+        assert a["stop_level"] == b["stop_level"] and a["interpreted_nodes"] == b["interpreted_nodes"], k
+        if k[0] == "p":
+            assert a["device_compiled"] == 0 and b["device_compiled"] == 1, k
+    ctx.close()
+    # the device-compiled parents against the oracle (their children were compared above)
+    for ji, (vt, h, lay, ops, pts, kids) in enumerate(jobs[:-1]):
+        got = dev[("p", ji)]
+        if vt == g.GP_F32:
+            with np.errstate(all="ignore"):
+                want = oracle.eval_f32(ops, fc.x)
+            assert same_f32(got["root"], want).all(), ji
+        else:
+            assert np.array_equal(got["root"], oracle.eval_bool(ops, bc.inputs)), ji
