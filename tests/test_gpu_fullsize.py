@@ -229,3 +229,39 @@ def test_index_full_size(ctx):
     roots = sn[torch.from_numpy(pop.offsets[:-1].astype(np.int64)).to(sn.device)].cpu().numpy()
     for t in range(0, pop.n_trees, 25):
         assert roots[t] == oracle.strahler(pop.tree(t))[0], t
+
+
+def test_device_compilation_full_size(ctx):
+    """The default 500-tree population (2.1e9 nodes) with one recorded point
+    per child, loaded as bench.py loads it: compiled on the device, its
+    program, chunk tables, records, spines, subtree index and per-tree chunk
+    lists equal the host compiler's byte for byte (gp_population_dump,
+    section by section)."""
+    parents = gen.sized_population(4, 500, 10**6, 10**7, threads=16)
+    kids = gen.crossover_children(40, parents, 500, donor_lo=1, donor_hi=10**4, neutral_frac=0.5)
+    pts = [[] for _ in range(parents.n_trees)]
+    for p, c in zip(kids.parent, kids.point):
+        pts[int(p)].append(int(c))
+    ro = np.cumsum([0] + [len(p) for p in pts]).astype(np.int64)
+    rp = np.array([c for p in pts for c in p], np.int64)
+
+    def sections(d):
+        out, i = [], 0
+        while i < len(d):
+            n = int(np.frombuffer(d[i:i + 8], np.int64)[0])
+            out.append(np.frombuffer(d, np.uint8, count=n, offset=i + 8))
+            i += 8 + n
+        assert i == len(d)
+        return out
+
+    dumps = []
+    for dc in (False, True):
+        h = ctx.load_population(g.GP_F32, parents.ops, parents.offsets, record_points=rp, record_offsets=ro,
+                                keep_trees=True, device_compile=dc)
+        dumps.append(ctx.population_dump(h))
+        say("dump", "device" if dc else "host", len(dumps[-1]), "bytes")
+        ctx.free(h)
+    a, b = (sections(d) for d in dumps)
+    assert len(a) == len(b) == 16
+    for k, (x, y) in enumerate(zip(a, b)):
+        assert x.size == y.size and np.array_equal(x, y), k
