@@ -15,17 +15,33 @@ namespace {
 
 inline bool is_func(uint8_t b) { return (b & kFuncBit) != 0; }
 
+// compile_tree's state of one node, in one 16-byte record so that reading an
+// operand touches one cache line: the end of its subtree, the words its
+// subtree emits in its own chunk, the nodes not yet assigned to a chunk below
+// it (during emission: where its code starts, -1 when folded into its
+// parent), its stack need, whether it roots a chunk, its instruction form
+// (mode | first operand is the right << 3 | folded operand is the left << 4)
+// and, during emission, the stack slot of its value.
+struct NodeRec {
+    int32_t end;
+    int32_t len;
+    int32_t open;
+    uint8_t need, cut, form, slot;
+};
+static_assert(sizeof(NodeRec) == 16, "one node record is 16 bytes");
+
 // Per-node work arrays of compile_tree, grown to the largest tree seen.
 struct CompileScratch {
     int64_t cap = 0;
-    std::unique_ptr<int32_t[]> rch, end_at, len, open, st, chunk;
-    std::unique_ptr<uint8_t[]> need, cut, form;
+    std::unique_ptr<NodeRec[]> node;
+    std::unique_ptr<int32_t[]> st, chunk;
     void ensure(int64_t n)
     {
         if (n <= cap) return;
         cap = std::max<int64_t>(n, cap + cap / 2);
-        for (auto* a : {&rch, &end_at, &len, &open, &st, &chunk}) a->reset(new int32_t[cap + 1]);
-        for (auto* a : {&need, &cut, &form}) a->reset(new uint8_t[cap + 1]);
+        node.reset(new NodeRec[cap + 1]);
+        st.reset(new int32_t[cap + 1]);
+        chunk.reset(new int32_t[cap + 1]);
     }
 };
 
@@ -169,80 +185,78 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     }
 
     // Per node, filled by the right-to-left pass; nodes are written before
-    // they are read, so nothing needs clearing first.  The arrays are kept
+    // they are read, so nothing needs clearing first.  The records are kept
     // per thread and reused: a load compiles many trees on each thread, and
     // fresh pages cost more than the pass itself.
     static thread_local CompileScratch ws;
     ws.ensure(n);
-    int32_t* rch = ws.rch.get();        // right child of each function node
-    int32_t* end_at = ws.end_at.get();  // end of each node's subtree
-    int32_t* len = ws.len.get();        // words its subtree emits in its own chunk
-    int32_t* open = ws.open.get();      // nodes not yet assigned to a chunk below
-    uint8_t* need = ws.need.get();      // stack slots to produce the value
-    uint8_t* cut = ws.cut.get();        // node roots a chunk of its own
-    uint8_t* form = ws.form.get();      // mode | first operand is the right << 3 | folded operand is the left << 4
+    NodeRec* nd = ws.node.get();
     const bool index = opt.index_min_size > 0;
     out->big_ends.clear();
-    auto words = [&](int64_t c) -> int32_t { return cut[c] ? 1 : len[c]; };   // LOAD or the code
+    auto words = [&](int64_t c) -> int32_t { return nd[c].cut ? 1 : nd[c].len; };   // LOAD or the code
     std::vector<int64_t> roots;                 // the cut nodes
 
     // The pass: a node's values depend on its operands' only, so nodes can be
     // finished in any order that puts every node after the nodes above it in
     // index.  leaf(i) and func(i, l, r) do node i.
     auto leaf = [&](int64_t i) {
-        end_at[i] = (int32_t)(i + 1);
-        cut[i] = opaque(i) ? 1 : 0;           // a compiled chunk: one LOAD
-        need[i] = 1;
-        open[i] = 1;
-        len[i] = 1;                           // PUSH, when not folded into its parent
+        NodeRec& x = nd[i];
+        x.end = (int32_t)(i + 1);
+        x.cut = opaque(i) ? 1 : 0;            // a compiled chunk: one LOAD
+        x.need = 1;
+        x.open = 1;
+        x.len = 1;                            // PUSH, when not folded into its parent
     };
     auto func = [&](int64_t i, int32_t l, int32_t r, std::vector<int64_t>& cuts, std::vector<SubtreeEnd>& bigs) {
-        end_at[i] = end_at[r];
-        if (index && full(end_at[i]) - full(i) >= opt.index_min_size)
-            bigs.push_back({(int32_t)full(i), (int32_t)full(end_at[i])});
-        rch[i] = r;
-        cut[i] = 0;
-        auto cost = [&](int32_t c) { return cut[c] ? 1 : (int)need[c]; };
+        NodeRec& x = nd[i];
+        NodeRec& L = nd[l];
+        NodeRec& R = nd[r];
+        x.end = R.end;
+        if (index && full(x.end) - full(i) >= opt.index_min_size)
+            bigs.push_back({(int32_t)full(i), (int32_t)full(x.end)});
+        x.cut = 0;
+        const bool fol = foldable(l), fo_r = foldable(r);
+        auto cost = [](const NodeRec& c) { return c.cut ? 1 : (int)c.need; };
         auto need_of = [&]() {
-            bool fl = !cut[l] && foldable(l), fr = !cut[r] && foldable(r);
+            bool fl = !L.cut && fol, fr = !R.cut && fo_r;
             if (fl && fr) return 1;
-            if (fl) return cost(r);
-            if (fr) return cost(l);
-            int nl = cost(l), nr = cost(r);
+            if (fl) return cost(R);
+            if (fr) return cost(L);
+            int nl = cost(L), nr = cost(R);
             return nl >= nr ? std::max(nl, nr + 1) : std::max(nr, nl + 1);
         };
-        int nd = need_of();
-        if (nd > S) {
+        int need = need_of();
+        if (need > S) {
             // Both operands need a full stack: give the bigger one a chunk of
             // its own; its value then arrives by one LOAD (one slot).
-            int32_t big = cost(l) >= cost(r) ? l : r;
-            cut[big] = 1;
+            int32_t big = cost(L) >= cost(R) ? l : r;
+            nd[big].cut = 1;
             cuts.push_back(big);
-            nd = need_of();
+            need = need_of();
         }
-        need[i] = (uint8_t)nd;
+        x.need = (uint8_t)need;
         // the instruction form, fixed now that the operands' cuts are final
-        const bool fl = !cut[l] && foldable(l), fr = !cut[r] && foldable(r);
+        const bool fl = !L.cut && fol, fr = !R.cut && fo_r;
         if (fl && fr) {
-            form[i] = M_XX;
-            len[i] = 1;
+            x.form = M_XX;
+            x.len = 1;
         } else if (fl || fr) {
-            form[i] = (uint8_t)((boolean || fl ? M_XS : M_SX) | (fl ? 16 : 0));
-            len[i] = words(fl ? r : l) + 1;
+            x.form = (uint8_t)((boolean || fl ? M_XS : M_SX) | (fl ? 16 : 0));
+            x.len = words(fl ? r : l) + 1;
         } else {
-            const bool first_r = !(cost(l) >= cost(r));
-            form[i] = (uint8_t)((!first_r || boolean ? M_SS : M_RS) | (first_r ? 8 : 0));
-            len[i] = words(l) + words(r) + 1;
+            const bool first_r = !(cost(L) >= cost(R));
+            x.form = (uint8_t)((!first_r || boolean ? M_SS : M_RS) | (first_r ? 8 : 0));
+            x.len = words(l) + words(r) + 1;
         }
-        int64_t o = 1 + (cut[l] ? 1 : open[l]) + (cut[r] ? 1 : open[r]);
-        open[i] = (int32_t)std::min<int64_t>(o, INT32_MAX);
+        int64_t o = 1 + (L.cut ? 1 : L.open) + (R.cut ? 1 : R.open);
+        x.open = (int32_t)std::min<int64_t>(o, INT32_MAX);
         if ((o >= C || forced(i)) && i != 0) {
-            cut[i] = 1;
+            x.cut = 1;
             cuts.push_back(i);
         }
     };
     const int pth = (int)std::min<int64_t>(std::max(1, opt.threads), 64);
-    if (pth > 1 && n >= 200000 && n_points == 0) {
+    if (pth > 1 && n >= 200000) {
         // Segments of the array in parallel, right to left, a node's right
         // operand found as the end of its left one; a node whose subtree runs
         // past its segment's end waits.  Then the waiting nodes, about the
@@ -258,12 +272,12 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
                     continue;
                 }
                 const int32_t l = (int32_t)(i + 1);
-                if (l >= hi || end_at[l] < 0 || end_at[l] >= hi || end_at[end_at[l]] < 0) {
-                    end_at[i] = -1;           // an operand lies beyond this segment
+                if (l >= hi || nd[l].end < 0 || nd[l].end >= hi || nd[nd[l].end].end < 0) {
+                    nd[i].end = -1;           // an operand lies beyond this segment
                     seg_wait[t].push_back(i);
                     continue;
                 }
-                func(i, l, end_at[l], seg_cuts[t], seg_big[t]);
+                func(i, l, nd[l].end, seg_cuts[t], seg_big[t]);
             }
         };
         for (int t = 1; t < pth; ++t) th.emplace_back(seg, t);
@@ -271,7 +285,7 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         for (auto& x : th) x.join();
         std::vector<SubtreeEnd> bigs;
         for (int t = pth - 1; t >= 0; --t)
-            for (int64_t i : seg_wait[t]) func(i, (int32_t)(i + 1), end_at[i + 1], roots, bigs);
+            for (int64_t i : seg_wait[t]) func(i, (int32_t)(i + 1), nd[i + 1].end, roots, bigs);
         for (int t = 0; t < pth; ++t) {
             roots.insert(roots.end(), seg_cuts[t].begin(), seg_cuts[t].end());
             out->big_ends.insert(out->big_ends.end(), seg_big[t].begin(), seg_big[t].end());
@@ -319,17 +333,17 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         int64_t v = 0;
         path.push_back(0);
         while (v != c) {
-            int64_t l = v + 1, r = rch[v];
+            int64_t l = v + 1, r = nd[l].end;
             v = (c < r) ? l : r;
             path.push_back(v);
         }
         Spine sp;
         sp.point = c;
         sp.at_point = rec(c);
-        sp.child_nodes_removed = end_at[c] - c;
+        sp.child_nodes_removed = nd[c].end - c;
         for (int64_t k = (int64_t)path.size() - 2; k >= 0; --k) {
             int64_t a = path[k], below = path[k + 1];
-            int64_t l = a + 1, r = rch[a];
+            int64_t l = a + 1, r = nd[l].end;
             bool right = below != l;
             int64_t sib = right ? l : r;
             SpineLevel lv;
@@ -345,18 +359,26 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
         return false;
     }
     out->n_records = (int64_t)rec_of.size();
-    // A recorded node's STORE follows its own word: recount the code lengths.
+    // A recorded node's STORE follows its own word: recount the code lengths
+    // of the recorded nodes, operands before parents.  Every ancestor of a
+    // recorded node is recorded (the point's ancestors, and the siblings'
+    // parents are on that path), so no other node's code grows.
     std::unique_ptr<uint8_t[]> stored;
     if (!rec_of.empty()) {
         stored.reset(new uint8_t[n]());
-        for (const auto& kv : rec_of) stored[kv.first] = 1;
-        for (int64_t i = n - 1; i >= 0; --i) {
-            if (!is_func(ops[i])) continue;
-            const int64_t l = i + 1, r = rch[i];
-            const uint32_t m = form[i] & 7;
-            int32_t w = m == M_XX ? 1 : (m == M_XS || m == M_SX) ? words((form[i] & 16) ? r : l) + 1
+        std::vector<int64_t> recd;
+        recd.reserve(rec_of.size());
+        for (const auto& kv : rec_of) {
+            stored[kv.first] = 1;
+            recd.push_back(kv.first);
+        }
+        std::sort(recd.begin(), recd.end(), std::greater<int64_t>());
+        for (int64_t i : recd) {
+            const int64_t l = i + 1, r = nd[l].end;
+            const uint32_t m = nd[i].form & 7;
+            int32_t w = m == M_XX ? 1 : (m == M_XS || m == M_SX) ? words((nd[i].form & 16) ? r : l) + 1
                                                                   : words(l) + words(r) + 1;
-            len[i] = w + stored[i];
+            nd[i].len = w + 1;
         }
     }
 
@@ -386,27 +408,25 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
     for (int64_t k = 0; k < nch; ++k) {
         Chunk& ch = out->chunks[k];
         ch.code_off = total;
-        ch.code_len = (int64_t)len[roots[k]] + 1;
+        ch.code_len = (int64_t)nd[roots[k]].len + 1;
         total += ch.code_len;
     }
     out->code.resize((size_t)total);
-    // where each node's code starts in its chunk and the slot it leaves its
-    // value in (open and need are not read again); -1: folded into its parent
-    int32_t* at = open;
-    uint8_t* slot = need;
+    // where each node's code starts in its chunk (in open, not read again)
+    // and the slot it leaves its value in; -1: folded into its parent
     std::vector<int32_t> slot_hi(nch, 0);
     std::vector<uint8_t> too_many(nch, 0);
     auto emit = [&](int64_t k) {
         Chunk& ch = out->chunks[k];
         uint32_t* code = out->code.data() + ch.code_off;
-        const int64_t root = roots[k], end = end_at[root];
+        const int64_t root = roots[k], end = nd[root].end;
         int32_t max_slot = 0;
         ch.root_node = full(root);
         ch.end_node = index ? full(end) : -1;
         ch.nodes = 0;
         // place operand c's code at q, value in slot d: a LOAD if it roots a chunk
         auto place = [&](int64_t c, int32_t q, int32_t d) {
-            if (cut[c]) {
+            if (nd[c].cut) {
                 int32_t id;
                 if (opaque(c)) {
                     id = col->opaque[c];
@@ -418,23 +438,23 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
                 code[q] = ins_word(0, M_LOAD, (uint32_t)d, (uint32_t)ch.inputs.size());
                 ch.inputs.push_back(id);
             } else {
-                at[c] = q;
-                slot[c] = (uint8_t)d;
+                nd[c].open = q;
+                nd[c].slot = (uint8_t)d;
             }
         };
-        at[root] = 0;
-        slot[root] = 0;
+        nd[root].open = 0;
+        nd[root].slot = 0;
         for (int64_t v = root; v < end;) {
-            if (v != root && cut[v]) {          // a chunk below (or a collapsed one): skip its subtree
-                v = end_at[v];
+            if (v != root && nd[v].cut) {       // a chunk below (or a collapsed one): skip its subtree
+                v = nd[v].end;
                 continue;
             }
-            const int32_t q = at[v];
+            const int32_t q = nd[v].open;
             if (q < 0) {                        // folded into its parent
                 ++v;
                 continue;
             }
-            const int32_t d = slot[v];
+            const int32_t d = nd[v].slot;
             max_slot = std::max(max_slot, d);
             if (!is_func(ops[v])) {
                 code[q] = ins_word(0, M_PUSH, (uint32_t)d, external(v) ? (uint32_t)ext[v] : ops[v]);
@@ -442,25 +462,25 @@ bool compile_tree(const uint8_t* ops, int64_t n, const CompileOptions& opt, cons
                 ++v;
                 continue;
             }
-            const int64_t l = v + 1, r = rch[v];
-            const uint32_t m = form[v] & 7;
+            const int64_t l = v + 1, r = nd[l].end;
+            const uint32_t m = nd[v].form & 7;
             int32_t w;                          // the instruction's own word
             uint32_t payload = 0;
             if (m == M_XX) {
-                at[l] = at[r] = -1;
+                nd[l].open = nd[r].open = -1;
                 if (boolean) payload = (uint32_t)ops[l] | ((uint32_t)ops[r] << 11);
                 w = q;
                 ch.nodes += 3;
             } else if (m == M_XS || m == M_SX) {
-                const bool left_folded = (form[v] & 16) != 0;
+                const bool left_folded = (nd[v].form & 16) != 0;
                 const int64_t folded = left_folded ? l : r, other = left_folded ? r : l;
-                at[folded] = -1;
+                nd[folded].open = -1;
                 if (boolean) payload = ops[folded];
                 place(other, q, d);
                 w = q + words(other);
                 ch.nodes += 2;
             } else {
-                const bool first_r = (form[v] & 8) != 0;
+                const bool first_r = (nd[v].form & 8) != 0;
                 const int64_t first = first_r ? r : l, second = first_r ? l : r;
                 place(first, q, d);
                 place(second, q + words(first), d + 1);

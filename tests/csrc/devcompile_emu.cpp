@@ -10,7 +10,8 @@
 // operand order; emission runs the chunks in a random order.
 //
 // Input (stdin, text): vtype n_inputs chunk_nodes index_min_size n_trees seed mode
-// handoff (0: through per-node memory; 1: packed into one word per function),
+// handoff (0: through per-node memory; 1: packed into one word per function)
+// host_threads (the threads compile_tree may use for a large tree),
 // then n_trees + 1 offsets, the ops bytes, n_trees + 1 record offsets and the
 // record points.  Output: "ok chunks <n> words <w> records <r>", or a line
 // naming the first difference (exit status 1).
@@ -68,6 +69,7 @@ int main()
     const uint64_t seed = rd<uint64_t>();
     const int mode = rd<int>();
     const int handoff = rd<int>();
+    const int host_threads = rd<int>();
     if (handoff == 1 && chunk_nodes > kDcPackMaxC) fail("the packed hand-off takes chunk targets up to 8192");
     std::vector<int64_t> off(n_trees + 1);
     for (auto& v : off) v = rd<int64_t>();
@@ -273,6 +275,7 @@ int main()
     opt.chunk_nodes = chunk_nodes;
     opt.stack_slots = S;
     opt.index_min_size = index_min;
+    opt.threads = host_threads;
     int64_t total_rec = 0;
     for (int64_t t = 0; t < n_trees; ++t) {
         const int64_t s = off[t], m = off[t + 1] - s, b = cbase[t], nc = cbase[t + 1] - b;

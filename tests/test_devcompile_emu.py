@@ -34,21 +34,21 @@ def emu(tmp_path_factory):
     return exe
 
 
-def run(exe, pop, chunk_nodes, index_min=0, points=None, seed=1, mode=1, handoffs=None):
+def run(exe, pop, chunk_nodes, index_min=0, points=None, seed=1, mode=1, handoffs=None, host_threads=1):
     """Runs both hand-offs (the packed one where the chunk target allows it)
-    and checks each against compile_tree."""
+    and checks each against compile_tree (on host_threads threads)."""
     if handoffs is None:
         handoffs = [0, 1] if chunk_nodes <= 8192 else [0]
     got = None
     for h in handoffs:
-        got = run_one(exe, pop, chunk_nodes, index_min, points, seed, mode, h)
+        got = run_one(exe, pop, chunk_nodes, index_min, points, seed, mode, h, host_threads)
     return got
 
 
-def run_one(exe, pop, chunk_nodes, index_min, points, seed, mode, handoff):
+def run_one(exe, pop, chunk_nodes, index_min, points, seed, mode, handoff, host_threads):
     pts = points if points is not None else [[] for _ in range(pop.n_trees)]
     ro = np.cumsum([0] + [len(p) for p in pts])
-    words = [pop.vtype, pop.n_inputs, chunk_nodes, index_min, pop.n_trees, seed, mode, handoff]
+    words = [pop.vtype, pop.n_inputs, chunk_nodes, index_min, pop.n_trees, seed, mode, handoff, host_threads]
     text = " ".join(map(str, words)) + "\n" + " ".join(map(str, pop.offsets.tolist())) + "\n" + \
         " ".join(map(str, pop.ops.tolist())) + "\n" + " ".join(map(str, ro.tolist())) + "\n" + \
         " ".join(str(c) for p in pts for c in p) + "\n"
@@ -147,3 +147,15 @@ def test_one_large_tree_interleaved(emu):
     got = run(emu, pop, 1024, 4096, [[0, 7, 1000, 150000]])
     assert got["chunks"] > 100
     run(emu, pop, 8192, 4096, [[0, 7, 1000, 150000]], mode=0)
+
+
+@pytest.mark.parametrize("host_threads", [2, 4, 7])
+def test_host_compiler_on_several_threads_with_records(emu, host_threads):
+    # compile_tree's parallel pass (trees of 2e5 nodes and more): segments of
+    # the array, then the nodes whose subtrees cross a segment's end; with
+    # crossover points recorded it must give the same programs as one thread
+    # (and as the device steps)
+    pop = gen.sized_population(60 + host_threads, 4, 200001, 600001)
+    pts = random_points(61, pop, 3)
+    run(emu, pop, 256, 4096, pts, host_threads=host_threads, handoffs=[1])
+    run(emu, pop, 16, 0, pts, host_threads=host_threads, handoffs=[1], mode=0)
