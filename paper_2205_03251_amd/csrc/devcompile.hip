@@ -659,6 +659,10 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
     hipLaunchKernelGGL(k_dc_emit, dim3(dc_persistent_blocks(c, nch, kDcEmitBatch, max_blocks)), dim3(256), 0, s, q, ck,
                        counter.as<unsigned long long>());
     HIPC(c, hipGetLastError());
+    if (tr.on) {
+        HIPC(c, hipStreamSynchronize(s));
+        tr.mark("emission kernel");
+    }
     std::vector<int32_t> n_in(nch), parent(nch), load_idx(nch), max_slot(nch);
     std::vector<int64_t> nodes(nch);
     std::vector<uint8_t> stores(nch);
@@ -711,7 +715,6 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         }
     }
     tr.mark("large subtrees");
-
     if (progs_out) {
         // each tree's program in host memory, as compile_tree leaves it
         std::vector<uint32_t> words((size_t)n_code);
@@ -877,24 +880,33 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         n_records += n_rec[t];
     }
     out->n_records = n_records;
+    tr.mark("chunk tables and spines");
     if (index_min_size > 0) {
+        // the list is sorted by node, so each tree's entries are one range
         out->big_ends.assign(n_trees, {});
         out->big_built.assign(n_trees, 1);
-        int64_t t = 0;
-        for (size_t i = 0; i < big_nodes.size(); ++i) {
-            while (big_nodes[i] >= offsets[t + 1]) ++t;
-            out->big_ends[t].push_back({(int32_t)(big_nodes[i] - offsets[t]), big_end[i]});
-        }
+        dc_parallel(n_trees, [&](int64_t t) {
+            const auto a = std::lower_bound(big_nodes.begin(), big_nodes.end(), offsets[t]);
+            const auto b = std::lower_bound(a, big_nodes.end(), offsets[t + 1]);
+            auto& be = out->big_ends[t];
+            be.resize(b - a);
+            for (auto it = a; it != b; ++it) {
+                const size_t i = (size_t)(it - big_nodes.begin());
+                be[it - a] = {(int32_t)(big_nodes[i] - offsets[t]), big_end[i]};
+            }
+        });
     }
+    tr.mark("large-subtree lists");
     std::stable_sort(out->leaves.begin(), out->leaves.end(),
                      [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
                          return x.first > y.first;
                      });
+    tr.mark("leaf order");
     RC(up(c, nullptr, out->chunks, dch.data(), dch.size() * sizeof(DevChunk), s));
     RC(up(c, nullptr, out->chunk_in, chunk_in.data(), chunk_in.size() * 4, s));
     RC(up(c, nullptr, out->levels, levels.data(), levels.size() * sizeof(SpineLvl), s));
     HIPC(c, hipStreamSynchronize(s));
-    tr.mark("tables");
+    tr.mark("tables to the device");
     return GP_OK;
 }
 
