@@ -290,8 +290,12 @@ __global__ __launch_bounds__(64) void k_eval_f32_tbl(EvalParams p)
         const int64_t case0 = (int64_t)s * (kWave * K);
         const float* inb = (const float*)p.inputs + case0;
         const float* vb = (const float*)p.vecs + case0;
+        ChunkHdr ch = load_chunk(cst(p.chunks) + c);
         for (;;) {
-            const ChunkHdr ch = load_chunk(cst(p.chunks) + c);
+            // the parent's header is fetched with this chunk's, so continuing
+            // into the parent waits for no load
+            ChunkHdr next = ch;
+            if (ch.parent >= 0) next = load_chunk(cst(p.chunks) + ch.parent);
             float* rb = (float*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
             float* outb = (float*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
             run_f32_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
@@ -308,6 +312,7 @@ __global__ __launch_bounds__(64) void k_eval_f32_tbl(EvalParams p)
             old = __builtin_amdgcn_readfirstlane(old);
             if (old != 1) break;
             c = ch.parent;
+            ch = next;
         }
     }
 }
@@ -483,8 +488,10 @@ __global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
         const int64_t case0 = (int64_t)s * (kWave * K);
         const uint64_t* inb = (const uint64_t*)p.inputs + case0;
         const uint64_t* vb = (const uint64_t*)p.vecs + case0;
+        ChunkHdr ch = load_chunk(cst(p.chunks) + c);
         for (;;) {
-            const ChunkHdr ch = load_chunk(cst(p.chunks) + c);
+            ChunkHdr next = ch;          // the parent's header, fetched with this chunk's
+            if (ch.parent >= 0) next = load_chunk(cst(p.chunks) + ch.parent);
             uint64_t* rb = (uint64_t*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
             uint64_t* outb = (uint64_t*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
             run_bool_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
@@ -497,6 +504,7 @@ __global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
             old = __builtin_amdgcn_readfirstlane(old);
             if (old != 1) break;
             c = ch.parent;
+            ch = next;
         }
     }
 }
