@@ -508,6 +508,10 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI, NP: int = BOOL_NP) -> str:
     a(f"  s_addc_u32 {sr('TB1')}, {sr('TB1')}, 0")
     a(f"  s_mov_b32 {sr('OFF')}, 0")
     a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+    # one word of each of the chunk's first 64 code lines (64 bytes apart; the
+    # offset is clamped to the last word), so that the scalar loads of the
+    # words find their lines in L2
+    a(f"  global_load_dword {ta(0, 0)}, %[vcoff], %[code]")
     # the vectors of LOAD inputs 0 .. min(nload, NP) - 1: their slots, then the rows
     a("  s_cmp_eq_u32 %[nload], 0")
     a(f"  s_cbranch_scc1 {lab('pfok')}")
@@ -630,7 +634,7 @@ def gen_bool(K: int, S: int, NI: int = BOOL_NI, NP: int = BOOL_NP) -> str:
 __device__ __forceinline__ void run_bool_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const uint64_t* inb,
                                                       const uint64_t* vb, uint64_t* rb, const GP_CONST int32_t* cin,
                                                       uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin,
-                                                      uint32_t nload)
+                                                      uint32_t nload, uint32_t vcoff)
 {{
     const uint64_t inb64 = (uint64_t)inb, vb64 = (uint64_t)vb, rb64 = (uint64_t)rb;
     asm volatile(
@@ -639,7 +643,8 @@ __device__ __forceinline__ void run_bool_dispatch_{K}_{S}(const GP_CONST uint32_
         : [code] "s"(code), [inb_lo] "s"((uint32_t)inb64), [inb_hi] "s"((uint32_t)(inb64 >> 32)),
           [vb_lo] "s"((uint32_t)vb64), [vb_hi] "s"((uint32_t)(vb64 >> 32)),
           [rb_lo] "s"((uint32_t)rb64), [rb_hi] "s"((uint32_t)(rb64 >> 32)), [cin] "s"(cin),
-          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff), [nin] "s"(nin), [nload] "s"(nload)
+          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff), [nin] "s"(nin), [nload] "s"(nload),
+          [vcoff] "v"(vcoff)
         : "memory", "vcc", "scc", "m0", {sclob},
           {vclob});
 }}

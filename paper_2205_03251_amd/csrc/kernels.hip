@@ -461,12 +461,12 @@ template <int K, int S>
 __device__ __forceinline__ void run_bool_dispatch(const GP_CONST uint32_t* code, const uint64_t* inb,
                                                   const uint64_t* vb, uint64_t* rb, const GP_CONST int32_t* cin,
                                                   uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin,
-                                                  uint32_t nload)
+                                                  uint32_t nload, uint32_t vcoff)
 {
     if constexpr (K == 1 && S == 10)
-        run_bool_dispatch_1_10(code, inb, vb, rb, cin, strideb, outb, voff, nin, nload);
+        run_bool_dispatch_1_10(code, inb, vb, rb, cin, strideb, outb, voff, nin, nload, vcoff);
     else if constexpr (K == 2 && S == 10)
-        run_bool_dispatch_2_10(code, inb, vb, rb, cin, strideb, outb, voff, nin, nload);
+        run_bool_dispatch_2_10(code, inb, vb, rb, cin, strideb, outb, voff, nin, nload, vcoff);
     else static_assert(K == 1 && S == 10, "no generated Boolean loop for this K and S");
 }
 
@@ -494,8 +494,10 @@ __global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
             if (ch.parent >= 0) next = load_chunk(cst(p.chunks) + ch.parent);
             uint64_t* rb = (uint64_t*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
             uint64_t* outb = (uint64_t*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
+            // lane l touches the code line at word 16 l (clamped to the chunk's last word)
+            const uint32_t vcoff = (uint32_t)min(lane * 16, max(ch.code_len - 1, 0)) * 4u;
             run_bool_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
-                                    outb, voff, nin, (uint32_t)ch.n_in);
+                                    outb, voff, nin, (uint32_t)ch.n_in, vcoff);
             if (ch.parent < 0) break;
             int old = 0;      // relaxed, as in k_eval_f32_tbl
             if (lane == 0)
