@@ -256,6 +256,7 @@ def measure_config(ctx, g, name, threads, cpu, cpu_budget_s, no_cpu=False):
     func_nodes = (total - n) // 2
     achieved = func_nodes * T / (kernel_ms * 1e-3)
     out = {**desc, "total_nodes": total, "chunk_nodes": info["chunk_nodes"], "variant": g.variant_names()[v],
+           "waves_per_cu": st["waves_per_cu"],
            "device_load_s": round(load_s, 3), "host_load_s": round(host_load_s, 3),
            "batched_ms": round(batched_ms, 4), "batched_wall_ms": round(float(np.median(wms)), 4),
            "per_tree_ms": round(per_tree_ms, 3), "batched_speedup": round(per_tree_ms / batched_ms, 1),
@@ -474,6 +475,8 @@ def main():
     ap.add_argument("--generations", type=int, default=2, help="generations of the evolution leg (0 = skip)")
     ap.add_argument("--chunk-nodes", type=int, default=0, help="fix the chunk size (0 = automatic / tuned)")
     ap.add_argument("--variant", default="", help="fix the interpreter variant, e.g. f32_k4_s16")
+    ap.add_argument("--waves-per-cu", type=int, default=-1,
+                    help="cap the interpreter launch's resident waves per CU (0: all that fit; -1: tuned)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--calibrate-valu", action="store_true",
@@ -556,6 +559,8 @@ def main():
     log(f"[bench] loaded in {load_s:.2f} s compiled on the device ({host_load_s} s on the host): {info}")
 
     tuned = None
+    if args.waves_per_cu >= 0:
+        ctx.set_launch_width(args.waves_per_cu)
     if args.variant:
         ctx.set_variant(g.variant_names().index(args.variant))
         tuned = args.variant
@@ -576,6 +581,7 @@ def main():
         _, _, st_full = ctx.evaluate_full(ph, ch, vtype, n_trees, T, roots=False, device=True, async_=True,
                                           fit_buf=fit_buf)
         used["variant"] = g.variant_names()[st_full["variant"]]
+        used["waves_per_cu"] = st_full["waves_per_cu"]
         if kids is None:
             return st_full, None
         _, _, st_inc = ctx.evaluate_incremental(ph, ch, vtype, T, kids.parent, kids.point, kids.donors.ops,
@@ -646,7 +652,8 @@ def main():
         if h.hexdigest() == rec["kernel_source_sha256"] and rec["workload"] == desc["workload"]:
             # one record per (chunk size, variant) the autotuner has been seen to pick
             for r in rec["records"]:
-                if r["chunk_nodes"] == final_info["chunk_nodes"] and r["variant"] == used.get("variant", tuned):
+                if (r["chunk_nodes"] == final_info["chunk_nodes"] and r["variant"] == used.get("variant", tuned)
+                        and r.get("waves_per_cu", 0) == used.get("waves_per_cu", 0)):
                     # read bytes by request size (FETCH_SIZE counts a 128-byte request as 64 bytes on this chip)
                     roofline["traffic"] = int(r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"])
                     roofline["traffic_GBps"] = round(roofline["traffic"] / (kernel_ms * 1e-3) / 1e9, 1)
@@ -832,7 +839,7 @@ def main():
         "dtype": "bool" if vtype == g.GP_BOOL else "f32",
         "data": "synthetic",
         "config": {**desc, "chunk_nodes": final_info["chunk_nodes"], "variant": used.get("variant", tuned),
-                   "parallelism": "single_gpu"},
+                   "waves_per_cu": used.get("waves_per_cu", 0), "parallelism": "single_gpu"},
         "interpreted_gpops": round(interp_nodes * T / (ms_per_step * 1e-3) / 1e9, 3),
         "load": {"device_compile_s": round(load_s, 2),
                  "host_compile_s": None if host_load_s is None else round(host_load_s, 2),

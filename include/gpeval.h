@@ -94,7 +94,8 @@ typedef struct gp_stats {
     int64_t interpreted_ops;   /* nodes actually executed x T */
     int64_t launches;          /* kernel launches or graph replays issued */
     int32_t variant;           /* interpreter variant index (gp_variant_name) */
-    int32_t reserved;
+    int32_t waves_per_cu;      /* the interpreter launch's resident workgroups (one wave each) were
+                                  capped at this many per compute unit; 0: all that fit */
 } gp_stats;
 
 typedef struct gp_inc_result {
@@ -380,13 +381,23 @@ int gp_fitness(gp_ctx* ctx, gp_handle cases, const void* outputs, int64_t n, uin
 const char* gp_variant_name(int variant);
 int gp_variant_count(void);
 
-/* Time each variant (and grid size) on this population and case set, keep
- * the fastest for later calls with the same value type, case-count bucket
- * and size bucket, and return its index. */
+/* Time each variant on this population and case set (and, for a population
+ * loaded without a fixed chunk size, each candidate chunk size, recompiling
+ * it in place), then, at the best chunk size, each variant again with fewer
+ * resident waves per compute unit (a full evaluation is one persistent launch
+ * whose length is set by its longest chains of chunks; fewer waves sharing a
+ * SIMD shorten those chains' issue).  The fastest (variant, waves per CU) is
+ * kept for later calls with the same value type, case-count bucket and
+ * tree-size bucket; its variant index and time are returned. */
 int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, double* best_ms);
 
 /* Force a variant for later calls (-1 = automatic choice). */
 int gp_set_variant(gp_ctx* ctx, int variant);
+
+/* Cap the resident waves per compute unit of later full-evaluation launches:
+ * -1 = the tuned cap (none before gp_autotune), 0 = all that fit, n > 0 = at
+ * most n.  Returns GP_EINVAL below -1. */
+int gp_set_launch_width(gp_ctx* ctx, int waves_per_cu);
 
 /* ------------------------------------------------------------- serving */
 

@@ -13,6 +13,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -67,9 +68,19 @@ struct CaseSet {
     DevBuf target;               // [stride]
 };
 
-// Launch plan of one population for one interpreter variant and slicing.
+// How a full evaluation is launched: the interpreter variant, and how many of
+// its one-wave workgroups may be resident per compute unit (0: as many as
+// fit).  Fewer resident waves give the waves on the longest chunk chains more
+// of their SIMD's issue slots, which shortens launches bound by those chains.
+struct Launch {
+    int variant = -1;
+    int waves_per_cu = 0;
+};
+
+// Launch plan of one population for one launch choice and slicing.
 struct Plan {
     int variant = -1;
+    int waves_per_cu = 0;
     bool per_tree = false;
     int32_t n_slices = 0;
     int64_t n_items = 0;
@@ -177,7 +188,7 @@ struct Pop {
     DevBuf recs;                            // [n_records][stride]
     DevBuf fit;                             // [n_trees] double or int64
     gp_handle evaluated_with = 0;           // case set of the last full evaluation
-    std::map<std::pair<int, int>, std::unique_ptr<Plan>> plans;  // (variant, per_tree)
+    std::map<std::tuple<int, int, int>, std::unique_ptr<Plan>> plans;  // (variant, waves_per_cu, per_tree)
 };
 
 struct TuneKey {
@@ -204,7 +215,8 @@ struct Ctx {
     std::unordered_map<gp_handle, std::shared_ptr<CaseSet>> cases;
     std::unordered_map<gp_handle, std::shared_ptr<Pop>> pops;
     int forced_variant = -1;
-    std::map<TuneKey, int> tuned;
+    int forced_waves = -1;                  // -1: tuned or all that fit; 0: all that fit; n: at most n per CU
+    std::map<TuneKey, Launch> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around the interpreter launch
     Server* server = nullptr;
@@ -244,11 +256,11 @@ int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs);
 // as src's last full evaluation on the same case set left them: those rows
 // of src->vecs are copied, and only the chunks compiled anew are evaluated.
 // Synchronises s.  n_evaluated (may be null) receives their number.
-int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const CaseSet* cs, int variant,
+int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const CaseSet* cs, Launch L,
                      hipStream_t s, int64_t* n_evaluated);
 // Enqueue a full evaluation on stream s (no copies out, no synchronisation).
 // time_kernel: record c->kev0/kev1 around the interpreter launch.
-int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int variant, bool per_tree,
+int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, Launch L, bool per_tree,
                  bool use_graph, hipStream_t s, int64_t* launches, bool time_kernel = false);
 // Build the walk descriptors of an incremental batch and enqueue donor
 // evaluation + walk on s.  Outputs are device buffers owned by the caller.
@@ -304,7 +316,13 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
 int build_population_device(Ctx* c, int vtype, int n_inputs, int64_t n_trees, const uint8_t* host_ops,
                             const uint8_t* dev_ops, const int64_t* offsets, const int64_t* rec_points,
                             const int64_t* rec_offsets, int64_t chunk_nodes, Pop* out, DevBuf* ops_keep);
-int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p);
+// The launch for a full evaluation of p on cs: the forced variant, else the
+// tuned one for this value type and size buckets, else a default (variant -1
+// when none fits); the forced width, else the tuned one, else all that fit.
+Launch choose_launch(Ctx* c, int vtype, const CaseSet* cs, const Pop* p);
+// Workgroups of one launch of variant v: the resident ones, at most
+// waves_per_cu per compute unit when that is positive.
+int64_t resident_grid(const Ctx* c, const Variant& v, int waves_per_cu);
 int64_t auto_chunk_nodes(int vtype, int64_t total_nodes, int64_t n_trees, int64_t T);
 int compile_stack_slots();
 

@@ -143,17 +143,19 @@ static int ilog2_ceil(int64_t v)
     return b;
 }
 
-int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
+static TuneKey tune_key(int vtype, const CaseSet* cs, const Pop* p)
+{
+    return TuneKey{vtype, ilog2_ceil(cs->T), ilog2_ceil(std::max<int64_t>(1, p->total_nodes / std::max<int64_t>(1, p->n_trees)))};
+}
+
+static int default_variant(int vtype, const CaseSet* cs, const Pop* p, int forced)
 {
     Variant* vt = variant_table();
     auto ok = [&](int v) {
         return v >= 0 && v < variant_count() &&
                variant_fits(vt[v], vtype, p->max_stack, p->n_inputs, cs->stride, vtype == GP_BOOL ? 8 : 4);
     };
-    if (ok(c->forced_variant)) return c->forced_variant;
-    TuneKey key{vtype, ilog2_ceil(cs->T), ilog2_ceil(std::max<int64_t>(1, p->total_nodes / std::max<int64_t>(1, p->n_trees)))};
-    auto it = c->tuned.find(key);
-    if (it != c->tuned.end() && ok(it->second)) return it->second;
+    if (ok(forced)) return forced;
     int wantK = 1;
     if (vtype == GP_F32) wantK = cs->n_elems <= 64 ? 1 : cs->n_elems <= 128 ? 2 : 4;
     else wantK = cs->n_elems <= 64 ? 1 : 2;
@@ -165,6 +167,30 @@ int choose_variant(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
     for (int v = 0; v < variant_count(); ++v)
         if (ok(v)) return v;
     return -1;
+}
+
+Launch choose_launch(Ctx* c, int vtype, const CaseSet* cs, const Pop* p)
+{
+    Launch L;
+    const int v = default_variant(vtype, cs, p, c->forced_variant);
+    auto it = c->tuned.find(tune_key(vtype, cs, p));
+    const bool tuned = it != c->tuned.end() &&
+                       (c->forced_variant < 0 || it->second.variant == v) &&
+                       default_variant(vtype, cs, p, it->second.variant) == it->second.variant;
+    if (tuned && c->forced_variant < 0) L = it->second;
+    else {
+        L.variant = v;
+        L.waves_per_cu = tuned ? it->second.waves_per_cu : 0;
+    }
+    if (c->forced_waves >= 0) L.waves_per_cu = c->forced_waves;
+    return L;
+}
+
+int64_t resident_grid(const Ctx* c, const Variant& v, int waves_per_cu)
+{
+    int per_cu = std::max(1, v.max_blocks_per_cu);
+    if (waves_per_cu > 0) per_cu = std::min(per_cu, waves_per_cu);
+    return (int64_t)per_cu * std::max(1, c->n_cu);
 }
 
 // Subtrees of at least this many nodes are indexed for co-evaluation's path
@@ -527,12 +553,13 @@ int ensure_eval_buffers(Ctx* c, Pop* p, const CaseSet* cs)
     return GP_OK;
 }
 
-static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, int variant, bool per_tree, Plan** out,
+static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, Launch L, bool per_tree, Plan** out,
                      hipStream_t stream)
 {
+    const int variant = L.variant;
     const Variant& v = variant_table()[variant];
     const int32_t n_slices = (int32_t)((cs->n_elems + kWave * v.K - 1) / (kWave * v.K));
-    auto key = std::make_pair(variant, per_tree ? 1 : 0);
+    auto key = std::make_tuple(variant, std::max(0, L.waves_per_cu), per_tree ? 1 : 0);
     auto it = p->plans.find(key);
     if (it != p->plans.end() && it->second->n_slices == n_slices) {
         *out = it->second.get();
@@ -540,6 +567,7 @@ static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, int variant, bool per_tr
     }
     auto pl = std::make_unique<Plan>();
     pl->variant = variant;
+    pl->waves_per_cu = std::max(0, L.waves_per_cu);
     pl->per_tree = per_tree;
     pl->n_slices = n_slices;
     std::vector<int64_t> items;
@@ -568,8 +596,7 @@ static int make_plan(Ctx* c, Pop* p, const CaseSet* cs, int variant, bool per_tr
     RC(upload(c, pl->pending_init, pend.data(), pend.size() * sizeof(int32_t), stream));
     RC(dev_alloc(c, pl->pending, pend.size() * sizeof(int32_t)));
     RC(dev_alloc(c, pl->cursor, (size_t)(per_tree ? p->n_trees : 1) * sizeof(unsigned int)));
-    const int64_t full = (int64_t)std::max(1, v.max_blocks_per_cu) * std::max(1, c->n_cu);
-    pl->grid = (int)std::max<int64_t>(1, std::min<int64_t>(full, pl->n_items));
+    pl->grid = (int)std::max<int64_t>(1, std::min<int64_t>(resident_grid(c, v, pl->waves_per_cu), pl->n_items));
     HIPC(c, hipStreamSynchronize(stream));
     p->plans[key] = std::move(pl);
     *out = p->plans[key].get();
@@ -623,8 +650,7 @@ static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t
         HIPC(c, launch_eval(pl->variant, e, pl->grid, s));
         ++nl;
     } else {
-        const Variant& v = variant_table()[pl->variant];
-        const int64_t full = (int64_t)std::max(1, v.max_blocks_per_cu) * std::max(1, c->n_cu);
+        const int64_t full = resident_grid(c, variant_table()[pl->variant], pl->waves_per_cu);
         for (int64_t t = 0; t < p->n_trees; ++t) {
             EvalParams et = e;
             et.items = e.items + pl->tree_item_begin[t];
@@ -642,12 +668,12 @@ static int enqueue_body(Ctx* c, Pop* p, const CaseSet* cs, Plan* pl, hipStream_t
     return GP_OK;
 }
 
-int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int variant, bool per_tree,
+int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, Launch L, bool per_tree,
                  bool use_graph, hipStream_t s, int64_t* launches, bool time_kernel)
 {
     RC(ensure_eval_buffers(c, p, cs));
     Plan* pl = nullptr;
-    RC(make_plan(c, p, cs, variant, per_tree, &pl, s));
+    RC(make_plan(c, p, cs, L, per_tree, &pl, s));
     if (!use_graph) {
         RC(enqueue_body(c, p, cs, pl, s, launches, time_kernel));
     } else {
@@ -685,7 +711,7 @@ int enqueue_full(Ctx* c, Pop* p, gp_handle cases_h, const CaseSet* cs, int varia
 // plan of its own runs only the chunks compiled anew: a chunk whose inputs
 // are all reused is a leaf work item, and every dependency counter counts
 // only the inputs compiled anew.
-int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const CaseSet* cs, int variant,
+int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const CaseSet* cs, Launch L,
                      hipStream_t s, int64_t* n_evaluated)
 {
     if (p->promo_src.size() != (size_t)p->n_chunks || p->promo_in.size() != (size_t)p->n_chunks)
@@ -693,9 +719,10 @@ int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const Ca
     if (src->evaluated_with != cases_h || src->stride != cs->stride || !src->vecs.p)
         return set_err(c, GP_EINVAL, "internal error: the parents hold no values for this case set");
     RC(ensure_eval_buffers(c, p, cs));
-    const Variant& v = variant_table()[variant];
+    const Variant& v = variant_table()[L.variant];
     Plan pl;
-    pl.variant = variant;
+    pl.variant = L.variant;
+    pl.waves_per_cu = std::max(0, L.waves_per_cu);
     pl.per_tree = false;
     pl.n_slices = (int32_t)((cs->n_elems + kWave * v.K - 1) / (kWave * v.K));
     std::vector<std::pair<int64_t, int32_t>> ready;
@@ -729,8 +756,7 @@ int enqueue_promoted(Ctx* c, Pop* p, const Pop* src, gp_handle cases_h, const Ca
         RC(upload(c, pl.pending_init, pend.data(), pend.size() * sizeof(int32_t), s));
         RC(dev_alloc(c, pl.pending, pend.size() * sizeof(int32_t)));
         RC(dev_alloc(c, pl.cursor, sizeof(unsigned int)));
-        const int64_t full = (int64_t)std::max(1, v.max_blocks_per_cu) * std::max(1, c->n_cu);
-        pl.grid = (int)std::max<int64_t>(1, std::min<int64_t>(full, pl.n_items));
+        pl.grid = (int)std::max<int64_t>(1, std::min<int64_t>(resident_grid(c, v, pl.waves_per_cu), pl.n_items));
         RC(enqueue_body(c, p, cs, &pl, s, nullptr, false));
     } else {
         // every child is one reused chunk (a whole subtree of a parent): nothing runs but the fitness
@@ -789,14 +815,14 @@ int enqueue_incremental(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases
     // Inserted subtrees: evaluated on every case like any population.
     RC(build_population(c, vtype, GP_PREFIX, jobs[0].parent->n_inputs, n, dops.data(), doffs.data(), nullptr,
                         nullptr, 0, &out->donors, s));
-    const int variant = choose_variant(c, vtype, cs, &out->donors);
-    if (variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the donors");
+    const Launch L = choose_launch(c, vtype, cs, &out->donors);
+    if (L.variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the donors");
     RC(upload(c, out->wc, wc.data(), wc.size() * sizeof(WalkChild), s));
     RC(dev_alloc(c, out->root, want_roots ? (size_t)n * cs->stride * esz : 256));
     RC(dev_alloc(c, out->fit, (size_t)n * 8));
     RC(dev_alloc(c, out->stop, (size_t)n * 4));
     RC(dev_alloc(c, out->interp, (size_t)n * 8));
-    RC(enqueue_full(c, &out->donors, cases_h, cs, variant, false, false, s, launches));
+    RC(enqueue_full(c, &out->donors, cases_h, cs, L, false, false, s, launches));
     WalkParams wp;
     wp.children = out->wc.as<WalkChild>();
     wp.inputs = cs->inputs.p;
@@ -1014,9 +1040,9 @@ int enqueue_coeval(Ctx* c, const std::vector<IncJob>& jobs, gp_handle cases_h, c
             }
             RC(build_population(c, vtype, GP_PREFIX, p->n_inputs, (int64_t)offs.size() - 1, ops.data(), offs.data(),
                                 nullptr, nullptr, 0, &rp, s, false, ext.data()));
-            const int variant = choose_variant(c, vtype, ecs, &rp);
-            if (variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the sibling subtrees");
-            RC(enqueue_full(c, &rp, cases_h, ecs, variant, false, false, s, launches));
+            const Launch L = choose_launch(c, vtype, ecs, &rp);
+            if (L.variant < 0) return set_err(c, GP_EINVAL, "no interpreter variant fits the sibling subtrees");
+            RC(enqueue_full(c, &rp, cases_h, ecs, L, false, false, s, launches));
         }
         const uint8_t* rv = (const uint8_t*)rp.vecs.p;
         const uint8_t* mv = (const uint8_t*)p->vecs.p;
@@ -1512,13 +1538,13 @@ int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags
     RC(lookup(ctx, pop, cases, &p, &cs));
     if ((flags & GP_ASYNC) && !(flags & GP_DEVICE_PTR))
         return set_err(ctx, GP_EINVAL, "GP_ASYNC needs GP_DEVICE_PTR outputs");
-    const int variant = choose_variant(ctx, p->vtype, cs, p);
-    if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits this population");
+    const Launch L = choose_launch(ctx, p->vtype, cs, p);
+    if (L.variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits this population");
     const bool per_tree = (flags & GP_PER_TREE) != 0;
     const bool graph = !(flags & GP_NO_GRAPH);
     int64_t launches = 0;
     HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    RC(enqueue_full(ctx, p, cases, cs, variant, per_tree, graph, ctx->stream, &launches, !graph));
+    RC(enqueue_full(ctx, p, cases, cs, L, per_tree, graph, ctx->stream, &launches, !graph));
     HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     const size_t esz = p->vtype == GP_BOOL ? 8 : 4;
     RC(copy_out(ctx, root_out, p->vecs.p, p->n_trees, cs->n_elems, cs->stride, esz, flags));
@@ -1538,7 +1564,8 @@ int gp_evaluate_full(gp_ctx* ctx, gp_handle pop, gp_handle cases, uint32_t flags
         st->equivalent_ops = p->total_nodes * cs->T;
         st->interpreted_ops = p->total_nodes * cs->T;
         st->launches = launches;
-        st->variant = variant;
+        st->variant = L.variant;
+        st->waves_per_cu = std::max(0, L.waves_per_cu);
         st->wall_ms = now_ms() - t0;
     }
     return GP_OK;
@@ -2014,8 +2041,8 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
         np->host_offsets = noffs;
         np->tree_off = noffs;
         const double t2 = now_ms();
-        const int variant = choose_variant(ctx, vtype, cs, np.get());
-        if (variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits the children");
+        const Launch L = choose_launch(ctx, vtype, cs, np.get());
+        if (L.variant < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits the children");
         int64_t n_eval = np->n_chunks;
         // the chunk vectors of the generation before last hold nothing needed any more: reused when large enough
         const size_t vec_bytes = (size_t)np->n_chunks * cs->stride * (boolean ? 8 : 4);
@@ -2026,9 +2053,9 @@ int gp_evolve(gp_ctx* ctx, gp_handle pop, gp_handle cases, const gp_evolve_cfg* 
         }
         if (!np->promo_src.empty()) {
             // reused chunks take their parents' values; only the chunks compiled anew run
-            RC(enqueue_promoted(ctx, np.get(), cur, cases, cs, variant, s, &n_eval));
+            RC(enqueue_promoted(ctx, np.get(), cur, cases, cs, L, s, &n_eval));
         } else {
-            RC(enqueue_full(ctx, np.get(), cases, cs, variant, false, false, s, nullptr));
+            RC(enqueue_full(ctx, np.get(), cases, cs, L, false, false, s, nullptr));
             HIPC(ctx, hipStreamSynchronize(s));
         }
         const double t3 = now_ms();
@@ -2112,6 +2139,15 @@ int gp_set_variant(gp_ctx* ctx, int variant)
     return GP_OK;
 }
 
+int gp_set_launch_width(gp_ctx* ctx, int waves_per_cu)
+{
+    if (!ctx) return GP_EINVAL;
+    if (waves_per_cu < -1) return set_err(ctx, GP_EINVAL, "waves_per_cu must be -1, 0 or positive");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->forced_waves = waves_per_cu;
+    return GP_OK;
+}
+
 // Time every interpreter variant, and for automatically chunked populations
 // every candidate chunk size, on this population and case set; keep the
 // fastest (chunk size: recompiled in place; variant: remembered per value
@@ -2136,12 +2172,12 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         for (int64_t c : cand)
             if (c <= std::max<int64_t>(256, 4 * mean)) chunk_sizes.push_back(c);
     }
-    auto time_variant = [&](Pop* q, int v, float* out) -> int {
-        RC(enqueue_full(ctx, q, cases, cs, v, false, true, ctx->stream, nullptr));   // warm-up + capture
+    auto time_variant = [&](Pop* q, Launch L, float* out) -> int {
+        RC(enqueue_full(ctx, q, cases, cs, L, false, true, ctx->stream, nullptr));   // warm-up + capture
         float tmin = 1e30f;
         for (int r = 0; r < 3; ++r) {
             HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-            RC(enqueue_full(ctx, q, cases, cs, v, false, true, ctx->stream, nullptr));
+            RC(enqueue_full(ctx, q, cases, cs, L, false, true, ctx->stream, nullptr));
             HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
             HIPC(ctx, hipStreamSynchronize(ctx->stream));
             float ms = 0.f;
@@ -2155,6 +2191,7 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     int64_t best_c = p->chunk_nodes;
     float best_t = 1e30f;
     std::shared_ptr<Pop> best_pop;
+    std::map<std::pair<int64_t, int>, float> all_fits;      // (chunk size, variant) -> time with all waves
     for (int64_t cn : chunk_sizes) {
         std::shared_ptr<Pop> q;
         Pop* qp = p;
@@ -2181,7 +2218,8 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
             if (!variant_fits(vt, qp->vtype, qp->max_stack, qp->n_inputs, cs->stride, qp->vtype == GP_BOOL ? 8 : 4))
                 continue;
             float t = 0.f;
-            RC(time_variant(qp, v, &t));
+            RC(time_variant(qp, Launch{v, 0}, &t));
+            all_fits[{cn, v}] = t;
             if (t < best_t) {
                 best_t = t;
                 best = v;
@@ -2208,12 +2246,41 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         best_pop->tree_off.swap(p->tree_off);
         ctx->pops[pop] = best_pop;
         p = best_pop.get();
-        RC(enqueue_full(ctx, p, cases, cs, best, false, true, ctx->stream, nullptr));
-        HIPC(ctx, hipStreamSynchronize(ctx->stream));
     }
-    (void)best_c;
-    TuneKey key{p->vtype, ilog2_ceil(cs->T), ilog2_ceil(std::max<int64_t>(1, p->total_nodes / std::max<int64_t>(1, p->n_trees)))};
-    ctx->tuned[key] = best;
+    // At the chosen chunk size, every variant with fewer resident waves per
+    // CU, from the most that fit downwards, until two caps in a row are no
+    // faster than that variant's best so far.
+    int best_w = 0;
+    for (int v = 0; v < variant_count(); ++v) {
+        auto it = all_fits.find({best_c, v});
+        if (it == all_fits.end()) continue;
+        float vbest = it->second;
+        int slower = 0;
+        for (int w : {24, 16, 12, 8, 6, 4, 3, 2}) {
+            if (w >= variant_table()[v].max_blocks_per_cu) continue;
+            float t = 0.f;
+            RC(time_variant(p, Launch{v, w}, &t));
+            if (t < best_t) {
+                best_t = t;
+                best = v;
+                best_w = w;
+            }
+            if (t < vbest) {
+                vbest = t;
+                slower = 0;
+            } else if (++slower == 2) {
+                break;
+            }
+        }
+    }
+    // keep only the chosen launch's plans
+    for (auto it = p->plans.begin(); it != p->plans.end();) {
+        if (std::get<0>(it->first) != best || std::get<1>(it->first) != best_w) it = p->plans.erase(it);
+        else ++it;
+    }
+    RC(enqueue_full(ctx, p, cases, cs, Launch{best, best_w}, false, true, ctx->stream, nullptr));
+    HIPC(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->tuned[tune_key(p->vtype, cs, p)] = Launch{best, best_w};
     if (best_variant) *best_variant = best;
     if (best_ms) *best_ms = best_t;
     return GP_OK;

@@ -92,8 +92,9 @@ struct Server {
     Ctx* ctx = nullptr;
     gp_server_cfg cfg{};
     uint64_t budget = 0;
-    std::map<TuneKey, int> tuned;
+    std::map<TuneKey, Launch> tuned;
     int forced_variant = -1;
+    int forced_waves = -1;
 
     std::mutex mu;
     std::condition_variable cv_prep, cv_disp, cv_done;
@@ -119,7 +120,7 @@ struct Server {
 
 namespace {
 
-int choose_for(Server* S, int vtype, const CaseSet* cs, const Pop* p)
+int variant_for(Server* S, int vtype, const CaseSet* cs, const Pop* p)
 {
     Variant* vt = variant_table();
     auto ok = [&](int v) {
@@ -323,9 +324,9 @@ int launch_batch(Server* S, SBatch* b)
         b->pop = std::make_shared<Pop>();
         int rc0 = assemble_population(c, cs->vtype, cs->n_inputs, progs, nodes, 0, b->pop.get(), s);
         if (rc0 != GP_OK) return rc0;
-        const int v = choose_for(S, cs->vtype, cs, b->pop.get());
-        if (v < 0) return GP_EINVAL;
-        const int rc = enqueue_full(c, b->pop.get(), ch, cs, v, false, false, s, nullptr);
+        const Launch L{variant_for(S, cs->vtype, cs, b->pop.get()), std::max(0, S->forced_waves)};
+        if (L.variant < 0) return GP_EINVAL;
+        const int rc = enqueue_full(c, b->pop.get(), ch, cs, L, false, false, s, nullptr);
         if (rc != GP_OK) return rc;
         if (hipMemcpyAsync(st_fit, b->pop->fit.p, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpy2DAsync(st_root, vbytes, b->pop->vecs.p, (size_t)cs->stride * esz, vbytes, n,
@@ -545,6 +546,7 @@ int gp_server_start(gp_ctx* ctxp, const gp_server_cfg* cfg)
         std::lock_guard<std::mutex> lk(ctx->mu);
         S->tuned = ctx->tuned;
         S->forced_variant = ctx->forced_variant;
+        S->forced_waves = ctx->forced_waves;
     }
     S->pinned_bytes = (size_t)S->cfg.max_batch_jobs * (20 + (size_t)16384 * 8);
     for (int i = 0; i < S->cfg.n_streams; ++i) {

@@ -31,7 +31,7 @@ EXPORTS = [
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
     "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree", "gp_index_trees",
     "gp_index_trees_noalloc", "gp_population_results", "gp_evolve", "gp_population_ops", "gp_valu_calibration",
-    "gp_population_dump",
+    "gp_population_dump", "gp_set_launch_width",
 ]
 INDEX_NOALLOC_MAX_NODES = 4194304
 
@@ -46,10 +46,10 @@ class Stats(C.Structure):
     _fields_ = [("device_ms", C.c_double), ("kernel_ms", C.c_double), ("wall_ms", C.c_double),
                 ("equivalent_ops", C.c_int64),
                 ("interpreted_ops", C.c_int64), ("launches", C.c_int64), ("variant", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("waves_per_cu", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class EvolveCfg(C.Structure):
@@ -151,6 +151,7 @@ def lib() -> C.CDLL:
     h.gp_variant_count.argtypes = []
     h.gp_autotune.argtypes = [P, I64, I64, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     h.gp_set_variant.argtypes = [P, C.c_int]
+    h.gp_set_launch_width.argtypes = [P, C.c_int]
     h.gp_server_start.argtypes = [P, C.POINTER(ServerCfg)]
     h.gp_server_submit.argtypes = [P, C.POINTER(Job), C.POINTER(I64)]
     h.gp_server_poll.argtypes = [P, I64, C.POINTER(JobResult), P, I64]
@@ -446,6 +447,10 @@ class Context:
 
     def set_variant(self, v: int):
         self._check(lib().gp_set_variant(self._h, v))
+
+    def set_launch_width(self, waves_per_cu: int):
+        """-1: the tuned cap; 0: all resident waves that fit; n: at most n per CU."""
+        self._check(lib().gp_set_launch_width(self._h, waves_per_cu))
 
     def autotune(self, pop, cases):
         v = C.c_int(0)

@@ -413,6 +413,56 @@ def test_boolean_table_variants(ctx, k, C):
     ctx.free(ch)
 
 
+@pytest.mark.parametrize("vtype,C", [(gen.VT_BOOL, 32), (gen.VT_BOOL, 2000), (gen.VT_F32, 64)])
+def test_launch_width(ctx, vtype, C):
+    """Capping the resident waves per CU (down to one) leaves every result
+    unchanged; the cap that ran is reported; the autotuner's choice is the one
+    later calls use."""
+    if vtype == gen.VT_BOOL:
+        cases = gen.bool_cases(6)
+        pop = gen.sized_population(71, 40, 11, 20001, n_terms=6, vtype=gen.VT_BOOL)
+        ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+        want_roots, want_fit = oracle.eval_population_bool(pop, cases.inputs, cases.target, cases.T, threads=8)
+        vt = g.GP_BOOL
+    else:
+        cases = gen.float_cases(72, 300)
+        pop = gen.sized_population(72, 40, 11, 8001)
+        ch = ctx.set_cases(g.GP_F32, cases.x, cases.y)
+        with np.errstate(all="ignore"):
+            want_roots, want_fit = oracle.eval_population_f32(pop, cases.x, cases.y, threads=8)
+        vt = g.GP_F32
+    ph = ctx.load_population(vt, pop.ops, pop.offsets, n_inputs=pop.n_inputs, chunk_nodes=C)
+
+    def check(st, roots, fit):
+        if vt == g.GP_BOOL:
+            assert np.array_equal(roots, want_roots)
+            assert np.array_equal(fit, want_fit)
+        else:
+            assert same_f32(roots, want_roots).all()
+            assert all(fit_equal(a, b) for a, b in zip(fit, want_fit))
+
+    try:
+        for w in (1, 2, 5, 0):
+            ctx.set_launch_width(w)
+            for graph in (True, False):
+                roots, fit, st = ctx.evaluate_full(ph, ch, vt, pop.n_trees, cases.T, graph=graph)
+                say("width", w, "variant", g.variant_names()[st["variant"]], "graph", graph)
+                assert st["waves_per_cu"] == w
+                check(st, roots, fit)
+        with pytest.raises(g.GPError):
+            ctx.set_launch_width(-2)
+        ctx.set_launch_width(-1)
+        v, _ = ctx.autotune(ph, ch)
+        roots, fit, st = ctx.evaluate_full(ph, ch, vt, pop.n_trees, cases.T)
+        say("tuned", g.variant_names()[v], st["waves_per_cu"])
+        assert st["variant"] == v and st["waves_per_cu"] >= 0
+        check(st, roots, fit)
+    finally:
+        ctx.set_launch_width(-1)
+        ctx.free(ph)
+        ctx.free(ch)
+
+
 def test_boolean_table_variants_refuse_many_inputs(ctx):
     """With more input rows than the registers hold, a forced table variant is
     passed over for one that stages the inputs in LDS."""
