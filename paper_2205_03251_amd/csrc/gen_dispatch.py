@@ -111,7 +111,8 @@ def gen_one(K: int, S: int) -> str:
     V_Q = V_X + K
     V_Y = V_Q + K
     V_T = V_Y + K
-    n_vgpr = V_T + 5
+    V_CP = V_T + 5                    # destination of the code-line touches, read by nothing
+    n_vgpr = V_CP + 1
     names = []
     for p in ["TB", "TG", "A", "J", "P"] + [f"XM{k}" for k in range(K)]:
         names += [f"{p}0", f"{p}1"]                   # pairs first: all even-aligned
@@ -217,6 +218,10 @@ def gen_one(K: int, S: int) -> str:
     a(f"  s_addc_u32 {sr('TB1')}, {sr('TB1')}, 0")
     a(f"  s_mov_b32 {sr('OFF')}, 0")
     a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+    # one word of each of the chunk's first 256 code lines (offsets clamped to
+    # the last word): the scalar loads of the words then find them in L2
+    for i in range(4):
+        a(f"  global_load_dword v{V_CP}, %[vc{i}], %[code]")
     a("  s_waitcnt vmcnt(0)")
     xm = lambda k: sp(f"XM{k}")
     yv = lambda k: f"v{V_Y + k}"
@@ -422,7 +427,8 @@ def gen_one(K: int, S: int) -> str:
 // K = {K} cases per lane, S = {S} stack slots: v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(names) - 1}.
 __device__ __forceinline__ void run_f32_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const float* inb,
                                                      const float* vb, float* rb, const GP_CONST int32_t* cin,
-                                                     uint32_t strideb, float* outb, uint32_t voff)
+                                                     uint32_t strideb, float* outb, uint32_t voff,
+                                                     uint32_t vc0, uint32_t vc1, uint32_t vc2, uint32_t vc3)
 {{
     const uint64_t inb64 = (uint64_t)inb, vb64 = (uint64_t)vb, rb64 = (uint64_t)rb;
     asm volatile(
@@ -431,7 +437,8 @@ __device__ __forceinline__ void run_f32_dispatch_{K}_{S}(const GP_CONST uint32_t
         : [code] "s"(code), [inb] "s"(inb), [inb_lo] "s"((uint32_t)inb64), [inb_hi] "s"((uint32_t)(inb64 >> 32)),
           [vb_lo] "s"((uint32_t)vb64), [vb_hi] "s"((uint32_t)(vb64 >> 32)),
           [rb_lo] "s"((uint32_t)rb64), [rb_hi] "s"((uint32_t)(rb64 >> 32)), [cin] "s"(cin),
-          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff)
+          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff),
+          [vc0] "v"(vc0), [vc1] "v"(vc1), [vc2] "v"(vc2), [vc3] "v"(vc3)
         : "memory", "vcc", "scc", {sclob},
           {vclob});
 }}

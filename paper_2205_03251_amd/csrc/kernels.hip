@@ -266,10 +266,16 @@ __global__ __launch_bounds__(64) void k_eval_f32(EvalParams p)
 template <int K, int S>
 __device__ __forceinline__ void run_f32_dispatch(const GP_CONST uint32_t* code, const float* inb, const float* vb,
                                                  float* rb, const GP_CONST int32_t* cin, uint32_t strideb,
-                                                 float* outb, uint32_t voff)
+                                                 float* outb, uint32_t voff, uint32_t code_len)
 {
-    if constexpr (K == 4 && S == 10) run_f32_dispatch_4_10(code, inb, vb, rb, cin, strideb, outb, voff);
-    else if constexpr (K == 8 && S == 10) run_f32_dispatch_8_10(code, inb, vb, rb, cin, strideb, outb, voff);
+    // lane l touches the code lines at words 16 l + 1024 i, i < 4 (clamped to the chunk's last word)
+    const uint32_t last = code_len > 0 ? code_len - 1 : 0, l16 = (voff / 4u) * 16u;
+    const uint32_t vc0 = min(l16, last) * 4u, vc1 = min(l16 + 1024u, last) * 4u;
+    const uint32_t vc2 = min(l16 + 2048u, last) * 4u, vc3 = min(l16 + 3072u, last) * 4u;
+    if constexpr (K == 4 && S == 10)
+        run_f32_dispatch_4_10(code, inb, vb, rb, cin, strideb, outb, voff, vc0, vc1, vc2, vc3);
+    else if constexpr (K == 8 && S == 10)
+        run_f32_dispatch_8_10(code, inb, vb, rb, cin, strideb, outb, voff, vc0, vc1, vc2, vc3);
     else static_assert(K == 4 && S == 10, "no generated dispatch loop for this K and S");
 }
 
@@ -299,7 +305,7 @@ __global__ __launch_bounds__(64) void k_eval_f32_tbl(EvalParams p)
             float* rb = (float*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
             float* outb = (float*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
             run_f32_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
-                                   outb, voff);
+                                   outb, voff, (uint32_t)ch.code_len);
             if (ch.parent < 0) break;
             // The loop wrote the chunk's vector with agent-coherent stores and
             // waited for them to complete, and LOAD reads vectors with
