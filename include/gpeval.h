@@ -115,6 +115,7 @@ typedef struct gp_pop_info {
     int64_t device_bytes;      /* HBM held by this population */
     int32_t max_stack;         /* deepest evaluation-stack slot used + 1 */
     int32_t chunk_nodes;       /* chunk size target used */
+    int64_t max_code_len;      /* longest chunk program, in instruction words */
 } gp_pop_info;
 
 /* ---------------------------------------------------------------- context */

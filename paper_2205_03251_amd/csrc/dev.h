@@ -135,14 +135,17 @@ struct Variant {
     int max_blocks_per_cu;       // filled at context creation
     int table;                   // runs the generated table-dispatch loop
     int max_inputs;              // input rows held in registers (0: any count, staged in LDS)
+    int max_elems;               // > 0: at most this many case words (Boolean) or cases (float)
 };
 
 // Whether variant v can run a population of value type vtype whose programs
 // need max_stack slots, on n_inputs input rows of stride elements of esz bytes
 // (the table loops address a row with a 32-bit byte stride).
-inline bool variant_fits(const Variant& v, int vtype, int max_stack, int n_inputs, int64_t stride, int esz)
+inline bool variant_fits(const Variant& v, int vtype, int max_stack, int n_inputs, int64_t n_elems,
+                         int64_t stride, int esz)
 {
     if (v.vtype != vtype || v.S < max_stack) return false;
+    if (v.max_elems > 0 && n_elems > v.max_elems) return false;
     if (v.max_inputs > 0 && n_inputs > v.max_inputs) return false;
     if (v.table && stride * esz > (int64_t)0xffffffffLL) return false;
     return true;

@@ -620,6 +620,7 @@ int device_compile_population(Ctx* c, int vtype, int n_inputs, int64_t n_trees, 
         code_off[k + 1] = code_off[k] + code_len[k];
     }
     const int64_t n_code = code_off[nch];
+    if (out) out->max_code_len = nch ? *std::max_element(code_len.begin(), code_len.end()) : 0;
 
     // code emission, one pass: each child chunk learns its parent and which of
     // the parent's LOADs reads it; the LOAD lists are then put together here

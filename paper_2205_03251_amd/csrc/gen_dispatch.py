@@ -658,6 +658,216 @@ __device__ __forceinline__ void run_bool_dispatch_{K}_{S}(const GP_CONST uint32_
 """
 
 
+# ---------------------------------------------------------- one Boolean word
+# When every test case fits in one 64-bit word (T <= 64) a chunk's value is
+# the same for the whole wave, so this loop keeps it on the scalar unit: the
+# stack slots st[d] and the input words in[j] are SGPR pairs, the handlers
+# use the scalar unit's 64-bit AND, OR, NAND and NOR, and a handler picks
+# input j by relative SGPR addressing (s_movrels_b64 with M0 = 2j, one wait
+# state after M0 is written).  Vector memory is used only where other waves
+# are involved: LOAD reads lane 0's word of a chunk vector with an
+# agent-coherent vector load, and STORE and the chunk's end write lane 0's
+# word (every other lane is masked off for those loads and stores).
+BOOLW_S = 10
+BOOLW_NI = 8
+BOOLW_NP = 4
+BOOLW_SBASE = 40
+
+
+def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP) -> str:
+    names = []
+    for p in ["TB", "TG", "X", "Y"] + [f"ST{d}" for d in range(S)] + [f"IN{j}" for j in range(NI)] + \
+            [f"LD{j}" for j in range(NP)]:
+        names += [f"{p}0", f"{p}1"]                   # pairs first: all even-aligned
+    names += ["INS", "NXT", "OFF", "T0", "T1"]
+    s = {n: BOOLW_SBASE + i for i, n in enumerate(names)}
+    assert BOOLW_SBASE % 2 == 0 and BOOLW_SBASE + len(names) <= 100
+    sr = lambda n: f"s{s[n]}"
+    sp = lambda n: f"s[{s[n + '0']}:{s[n + '0'] + 1}]"
+    V_CP, V_T, V_PF = 16, 18, 20                      # code-line touches, a word, the prefetched LOAD words
+    n_vgpr = V_PF + 2 * NP
+    OPS = ["s_and_b64", "s_or_b64", "s_nand_b64", "s_nor_b64"]
+    L = []
+    a = L.append
+    lab = lambda name: f".Lgw{S}_{name}_%="
+
+    def tail():
+        a("  s_waitcnt lgkmcnt(0)")
+        a(f"  s_mov_b32 {sr('INS')}, {sr('NXT')}")
+        a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
+        a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+        a(f"  s_and_b32 {sr('TG0')}, {sr('INS')}, 0x3ff")
+        a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
+        a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
+        a(f"  s_setpc_b64 {sp('TG')}")
+
+    def lane0_store(src, addr, shared):
+        """Lane 0 writes the SGPR pair src to the 8 bytes at addr + voff."""
+        a(f"  s_mov_b64 {sp('Y')}, exec")
+        a("  s_mov_b64 exec, 1")
+        a(f"  v_mov_b32_e32 v{V_T}, {sr(src + '0')}")
+        a(f"  v_mov_b32_e32 v{V_T + 1}, {sr(src + '1')}")
+        a(f"  global_store_dwordx2 %[voff], v[{V_T}:{V_T + 1}], {addr}{shared}")
+        a(f"  s_mov_b64 exec, {sp('Y')}")
+
+    def row_address(slot_sreg, lo, hi):
+        a(f"  s_mul_i32 {sr('X0')}, {slot_sreg}, %[strideb]")
+        a(f"  s_mul_hi_u32 {sr('X1')}, {slot_sreg}, %[strideb]")
+        a(f"  s_add_u32 {sr('X0')}, {sr('X0')}, {lo}")
+        a(f"  s_addc_u32 {sr('X1')}, {sr('X1')}, {hi}")
+
+    # ---------------------------------------------------------- entry
+    a(f"  s_getpc_b64 {sp('TB')}")
+    a(f"{lab('pc')}:")
+    a(f"  s_add_u32 {sr('TB0')}, {sr('TB0')}, {lab('tbl')}-{lab('pc')}")
+    a(f"  s_addc_u32 {sr('TB1')}, {sr('TB1')}, 0")
+    a(f"  s_mov_b32 {sr('OFF')}, 0")
+    a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
+    # one word of each of the chunk's first 64 code lines (offset clamped to
+    # the last word), so that the scalar loads of the words find them in L2;
+    # nothing reads v{V_CP}, and the chunk's end waits for the load
+    a(f"  global_load_dword v{V_CP}, %[vcoff], %[code]")
+    # the vector slots of LOAD inputs 0 .. min(nload, NP) - 1 (into LD{j}0)
+    a("  s_cmp_eq_u32 %[nload], 0")
+    a(f"  s_cbranch_scc1 {lab('slots')}")
+    for j in range(NP):
+        if j:
+            a(f"  s_cmp_le_u32 %[nload], {j}")
+            a(f"  s_cbranch_scc1 {lab('slots')}")
+        a(f"  s_load_dword {sr(f'LD{j}0')}, %[cin], {4 * j}")
+    a(f"{lab('slots')}:")
+    # the input words: row j at inb + j * strideb, for j < nin
+    a(f"  s_mov_b32 {sr('T1')}, 0")
+    for j in range(NI):
+        a(f"  s_cmp_le_u32 %[nin], {j}")
+        a(f"  s_cbranch_scc1 {lab('inok')}")
+        a(f"  s_load_dwordx2 {sp(f'IN{j}')}, %[inb], {sr('T1')}")
+        a(f"  s_add_u32 {sr('T1')}, {sr('T1')}, %[strideb]")
+    a(f"{lab('inok')}:")
+    a("  s_waitcnt lgkmcnt(0)")
+    a("  s_cmp_eq_u32 %[nload], 0")
+    a(f"  s_cbranch_scc1 {lab('pfok')}")
+    a(f"  s_mov_b64 {sp('Y')}, exec")               # lane 0 alone reads the vectors' words
+    a("  s_mov_b64 exec, 1")
+    for j in range(NP):
+        if j:
+            a(f"  s_cmp_le_u32 %[nload], {j}")
+            a(f"  s_cbranch_scc1 {lab('pfwait')}")
+        row_address(sr(f'LD{j}0'), "%[vb_lo]", "%[vb_hi]")
+        a(f"  global_load_dwordx2 v[{V_PF + 2 * j}:{V_PF + 2 * j + 1}], %[voff], {sp('X')}{SHARED}")
+    a(f"{lab('pfwait')}:")
+    a(f"  s_mov_b64 exec, {sp('Y')}")
+    a("  s_waitcnt vmcnt(0)")
+    for j in range(NP):              # lane 0's word; pairs past nload are never read
+        a(f"  v_readfirstlane_b32 {sr(f'LD{j}0')}, v{V_PF + 2 * j}")
+        a(f"  v_readfirstlane_b32 {sr(f'LD{j}1')}, v{V_PF + 2 * j + 1}")
+    a(f"{lab('pfok')}:")
+    tail()
+    # ---------------------------------------------------------- table
+    handlers = {}
+    for key in range(1024):
+        f, mode, d = key & 3, (key >> 2) & 7, key >> 5
+        if key == END_KEY:
+            handlers[key] = "end"
+        elif d < S and mode in (M_XX, M_XS):
+            handlers[key] = f"h{key}"
+        elif d + 1 < S and mode == M_SS:
+            handlers[key] = f"h{key}"
+        elif d < S and f == 0 and mode in (M_PUSH, M_LOAD, M_STORE):
+            handlers[key] = f"h{key}"
+        else:
+            handlers[key] = "end"     # never emitted for Boolean programs; ends the chunk
+    a(f"{lab('tbl')}:")
+    for key in range(1024):
+        a(f"  s_branch {lab(handlers[key])}")
+    # ---------------------------------------------------------- handlers
+    for key in range(1024):
+        if handlers[key] != f"h{key}":
+            continue
+        f, mode, d = key & 3, (key >> 2) & 7, key >> 5
+        st = f"ST{d}"
+        a(f"{lab(handlers[key])}:")
+        if mode == M_XX:                 # f(input a, input b), a = payload & 2047, b = payload >> 11
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_and_b32 {sr('T1')}, {sr('T0')}, 0x7ff")
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('T0')}, 11")
+            a(f"  s_lshl_b32 m0, {sr('T1')}, 1")
+            a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 1")
+            a(f"  s_movrels_b64 {sp('X')}, {sp('IN0')}")
+            a(f"  s_mov_b32 m0, {sr('T0')}")
+            a("  s_nop 0")
+            a(f"  s_movrels_b64 {sp('Y')}, {sp('IN0')}")
+            a(f"  {OPS[f]} {sp(st)}, {sp('X')}, {sp('Y')}")
+        elif mode == M_XS:               # f(input payload, slot d)
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_lshl_b32 m0, {sr('T0')}, 1")
+            a("  s_nop 0")
+            a(f"  s_movrels_b64 {sp('X')}, {sp('IN0')}")
+            a(f"  {OPS[f]} {sp(st)}, {sp('X')}, {sp(st)}")
+        elif mode == M_SS:
+            a(f"  {OPS[f]} {sp(st)}, {sp(st)}, {sp(f'ST{d + 1}')}")
+        elif mode == M_PUSH:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_lshl_b32 m0, {sr('T0')}, 1")
+            a("  s_nop 0")
+            a(f"  s_movrels_b64 {sp(st)}, {sp('IN0')}")
+        elif mode == M_LOAD:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            a(f"  s_cmp_lt_u32 {sr('T0')}, {NP}")
+            a(f"  s_cbranch_scc0 {lab(f'ld{key}')}")
+            a(f"  s_lshl_b32 m0, {sr('T0')}, 1")        # fetched when the chunk started
+            a("  s_nop 0")
+            a(f"  s_movrels_b64 {sp(st)}, {sp('LD0')}")
+            tail()
+            a(f"{lab(f'ld{key}')}:")
+            a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 2")
+            a(f"  s_load_dword {sr('T1')}, %[cin], {sr('T0')}")
+            a("  s_waitcnt lgkmcnt(0)")
+            row_address(sr('T1'), "%[vb_lo]", "%[vb_hi]")
+            a(f"  s_mov_b64 {sp('Y')}, exec")
+            a("  s_mov_b64 exec, 1")
+            a(f"  global_load_dwordx2 v[{V_T}:{V_T + 1}], %[voff], {sp('X')}{SHARED}")
+            a(f"  s_mov_b64 exec, {sp('Y')}")
+            a("  s_waitcnt vmcnt(0)")
+            a(f"  v_readfirstlane_b32 {sr(st + '0')}, v{V_T}")
+            a(f"  v_readfirstlane_b32 {sr(st + '1')}, v{V_T + 1}")
+        elif mode == M_STORE:
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
+            row_address(sr('T0'), "%[rb_lo]", "%[rb_hi]")
+            lane0_store(st, sp('X'), "")
+        tail()
+    # ---------------------------------------------------------- end
+    a(f"{lab('end')}:")
+    a("  s_waitcnt lgkmcnt(0)")
+    lane0_store("ST0", "%[outb]", SHARED)
+    a("  s_waitcnt vmcnt(0)")
+
+    body = "\n".join(f'        "{line}\\n"' for line in L)
+    vclob = ", ".join(f'"v{i}"' for i in range(V_CP, n_vgpr))
+    sclob = ", ".join(f'"s{s[n]}"' for n in names)
+    return f"""
+// One 64-bit word of test cases per chunk value, held in SGPRs: S = {S} stack slots, up to {NI} inputs,
+// {NP} LOAD inputs fetched ahead: s{BOOLW_SBASE}..s{BOOLW_SBASE + len(names) - 1}, v{V_CP}..v{n_vgpr - 1}.
+constexpr int kBoolWordInputs = {NI};
+__device__ __forceinline__ void run_boolw_dispatch_{S}(const GP_CONST uint32_t* code, const uint64_t* inb,
+                                                   const uint64_t* vb, uint64_t* rb, const GP_CONST int32_t* cin,
+                                                   uint32_t strideb, uint64_t* outb, uint32_t voff, uint32_t nin,
+                                                   uint32_t nload, uint32_t vcoff)
+{{
+    const uint64_t vb64 = (uint64_t)vb, rb64 = (uint64_t)rb;
+    asm volatile(
+{body}
+        :
+        : [code] "s"(code), [inb] "s"(inb), [vb_lo] "s"((uint32_t)vb64), [vb_hi] "s"((uint32_t)(vb64 >> 32)),
+          [rb_lo] "s"((uint32_t)rb64), [rb_hi] "s"((uint32_t)(rb64 >> 32)), [cin] "s"(cin),
+          [strideb] "s"(strideb), [outb] "s"(outb), [voff] "v"(voff), [nin] "s"(nin), [nload] "s"(nload),
+          [vcoff] "v"(vcoff)
+        : "memory", "vcc", "scc", "m0", "exec", {sclob},
+          {vclob});
+}}
+"""
+
+
 def write_if_changed(path: str, text: str) -> None:
     old = open(path).read() if os.path.exists(path) else None
     if old != text:
@@ -670,7 +880,7 @@ def main(out_path: str) -> None:
     write_if_changed(out_path, head + "".join(gen_one(K, S) for K, S in VARIANTS))
     write_if_changed(os.path.join(os.path.dirname(out_path), "dispatch_bool.inc"),
                      head + f"constexpr int kBoolDispatchInputs = {BOOL_NI};\n"
-                     + "".join(gen_bool(K, S) for K, S in BOOL_VARIANTS))
+                     + "".join(gen_bool(K, S) for K, S in BOOL_VARIANTS) + gen_bool_word())
 
 
 if __name__ == "__main__":

@@ -476,7 +476,9 @@ __device__ __forceinline__ void run_bool_dispatch(const GP_CONST uint32_t* code,
     else static_assert(K == 1 && S == 10, "no generated Boolean loop for this K and S");
 }
 
-template <int K, int S>
+// WORD: the one-word loop (T <= 64: the whole case set in lane 0's word, kept
+// in SGPRs), with K = 1.
+template <int K, int S, bool WORD = false>
 __global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
 {
     const int lane = threadIdx.x;
@@ -502,8 +504,14 @@ __global__ __launch_bounds__(64) void k_eval_bool_tbl(EvalParams p)
             uint64_t* outb = (uint64_t*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
             // lane l touches the code line at word 16 l (clamped to the chunk's last word)
             const uint32_t vcoff = (uint32_t)min(lane * 16, max(ch.code_len - 1, 0)) * 4u;
-            run_bool_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
-                                    outb, voff, nin, (uint32_t)ch.n_in, vcoff);
+            if constexpr (WORD) {
+                static_assert(K == 1 && S == 10, "one generated one-word loop: K = 1, S = 10");
+                run_boolw_dispatch_10(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
+                                      outb, voff, nin, (uint32_t)ch.n_in, vcoff);
+            } else {
+                run_bool_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off,
+                                        strideb, outb, voff, nin, (uint32_t)ch.n_in, vcoff);
+            }
             if (ch.parent < 0) break;
             int old = 0;      // relaxed, as in k_eval_f32_tbl
             if (lane == 0)
@@ -795,6 +803,7 @@ static Variant g_variants[] = {
     {"bool_k1_s16", 1, 1, 16, (const void*)k_eval_bool<1, 16>, 0},
     {"bool_k2_s16", 1, 2, 16, (const void*)k_eval_bool<2, 16>, 0},
     {"bool_k1_s10", 1, 1, 10, (const void*)k_eval_bool<1, 10>, 0},
+    {"boolw_s10", 1, 1, 10, (const void*)k_eval_bool_tbl<1, 10, true>, 0, 1, kBoolWordInputs, 1},
     {"boolt_k1_s10", 1, 1, 10, (const void*)k_eval_bool_tbl<1, 10>, 0, 1, kBoolRegInputs},
     {"boolt_k2_s10", 1, 2, 10, (const void*)k_eval_bool_tbl<2, 10>, 0, 1, kBoolRegInputs},
 };

@@ -145,6 +145,7 @@ struct Pop {
     int64_t total_nodes = 0;
     int64_t chunk_nodes = 0;
     int32_t max_stack = 0;
+    int64_t max_code_len = 0;               // longest chunk program, in words
     std::vector<int64_t> tree_nodes;
     // compiled program
     int64_t n_chunks = 0;

@@ -153,7 +153,8 @@ static int default_variant(int vtype, const CaseSet* cs, const Pop* p, int force
     Variant* vt = variant_table();
     auto ok = [&](int v) {
         return v >= 0 && v < variant_count() &&
-               variant_fits(vt[v], vtype, p->max_stack, p->n_inputs, cs->stride, vtype == GP_BOOL ? 8 : 4);
+               variant_fits(vt[v], vtype, p->max_stack, p->n_inputs, cs->n_elems, cs->stride,
+                            vtype == GP_BOOL ? 8 : 4);
     };
     if (ok(forced)) return forced;
     int wantK = 1;
@@ -425,6 +426,7 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
     out->spine_of.clear();
     out->cuts.clear();
     out->max_stack = 0;
+    out->max_code_len = 0;
     int64_t cbase = 0, rbase = 0, next_slot = n_trees;
     std::vector<int32_t> slot;
     for (int64_t t = 0; t < n_trees; ++t) {
@@ -456,6 +458,7 @@ int assemble_population(Ctx* c, int vtype, int n_inputs, std::vector<TreeProg>& 
                 d.code_off = obase + ch.code_off;
             }
             d.code_len = (int32_t)ch.code_len;
+            out->max_code_len = std::max(out->max_code_len, ch.code_len);
             d.parent = ch.parent >= 0 ? (int32_t)(cbase + ch.parent) : -1;
             d.out_slot = slot[k];
             d.in_off = (int32_t)chunk_in.size();
@@ -1378,6 +1381,7 @@ int gp_population_info(gp_ctx* ctx, gp_handle pop, gp_pop_info* out)
     out->device_bytes = (int64_t)b;
     out->max_stack = p->max_stack;
     out->chunk_nodes = (int32_t)p->chunk_nodes;
+    out->max_code_len = p->max_code_len;
     return GP_OK;
 }
 
@@ -2215,7 +2219,8 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         }
         for (int v = 0; v < variant_count(); ++v) {
             const Variant& vt = variant_table()[v];
-            if (!variant_fits(vt, qp->vtype, qp->max_stack, qp->n_inputs, cs->stride, qp->vtype == GP_BOOL ? 8 : 4))
+            if (!variant_fits(vt, qp->vtype, qp->max_stack, qp->n_inputs, cs->n_elems, cs->stride,
+                              qp->vtype == GP_BOOL ? 8 : 4))
                 continue;
             float t = 0.f;
             RC(time_variant(qp, Launch{v, 0}, &t));

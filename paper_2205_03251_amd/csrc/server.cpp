@@ -125,7 +125,8 @@ int variant_for(Server* S, int vtype, const CaseSet* cs, const Pop* p)
     Variant* vt = variant_table();
     auto ok = [&](int v) {
         return v >= 0 && v < variant_count() &&
-               variant_fits(vt[v], vtype, p->max_stack, p->n_inputs, cs->stride, vtype == GP_BOOL ? 8 : 4);
+               variant_fits(vt[v], vtype, p->max_stack, p->n_inputs, cs->n_elems, cs->stride,
+                            vtype == GP_BOOL ? 8 : 4);
     };
     if (ok(S->forced_variant)) return S->forced_variant;
     int wantK = vtype == GP_F32 ? (cs->n_elems <= 64 ? 1 : cs->n_elems <= 128 ? 2 : 4) : (cs->n_elems <= 64 ? 1 : 2);

@@ -78,7 +78,8 @@ class IncResult(C.Structure):
 class PopInfo(C.Structure):
     _fields_ = [("n_trees", C.c_int64), ("total_nodes", C.c_int64), ("n_chunks", C.c_int64),
                 ("n_instructions", C.c_int64), ("n_records", C.c_int64), ("n_spines", C.c_int64),
-                ("device_bytes", C.c_int64), ("max_stack", C.c_int32), ("chunk_nodes", C.c_int32)]
+                ("device_bytes", C.c_int64), ("max_stack", C.c_int32), ("chunk_nodes", C.c_int32),
+                ("max_code_len", C.c_int64)]
 
 
 class ServerCfg(C.Structure):

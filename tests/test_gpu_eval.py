@@ -413,6 +413,78 @@ def test_boolean_table_variants(ctx, k, C):
     ctx.free(ch)
 
 
+@pytest.mark.parametrize("k,C", [(1, 7), (3, 13), (5, 32), (6, 7), (6, 64), (6, 300), (6, 900), (6, 2000),
+                                 (8, 48)])
+def test_boolean_one_word_variant(ctx, k, C):
+    """The one-word loop (all cases in one 64-bit word, evaluated on the scalar
+    unit) against the oracle: every operand mode, chunks with more LOADs than
+    are fetched ahead (complete trees cut into small chunks), programs longer
+    than the lines touched at chunk start, one-node trees, and a case set of
+    64 random cases over 8 inputs.  It is the default choice for such case
+    sets."""
+    rng = np.random.default_rng(90 + k + C)
+    if k == 8:
+        inputs = rng.integers(0, 2 ** 63, size=(8, 1), dtype=np.uint64)
+        target = rng.integers(0, 2 ** 63, size=1, dtype=np.uint64)
+        cases = gen.BoolCases(inputs, target, 64)
+    else:
+        cases = gen.bool_cases(k)
+    pop = gen.sized_population(80 + k, 30, 11, 20001, n_terms=k, vtype=gen.VT_BOOL)
+    trees = [pop.tree(i) for i in range(pop.n_trees)] + [np.array([k - 1], np.uint8)]
+    full = gen.ramped_half_and_half(81 + k, 20, min_depth=6, max_depth=9, n_terms=k, max_nodes=1100,
+                                     vtype=gen.VT_BOOL)
+    trees += [full.tree(i) for i in range(full.n_trees)]
+    pop = gen.pack(trees, gen.VT_BOOL, k)
+    names = g.variant_names()
+    ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+    ph = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=k, chunk_nodes=C)
+    want_roots, want_fit = oracle.eval_population_bool(pop, cases.inputs, cases.target, cases.T, threads=8)
+    assert ctx.population_info(ph)["max_code_len"] > 1024 or C < 2000
+    try:
+        roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, cases.T)
+        assert names[st["variant"]] == "boolw_s10"
+        assert np.array_equal(roots, want_roots)
+        assert np.array_equal(fit, want_fit)
+        for w in (1, 3):
+            ctx.set_launch_width(w)
+            roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, cases.T, graph=False)
+            assert names[st["variant"]] == "boolw_s10"
+            assert np.array_equal(roots, want_roots)
+            assert np.array_equal(fit, want_fit)
+    finally:
+        ctx.set_launch_width(-1)
+        ctx.free(ph)
+        ctx.free(ch)
+
+
+def test_boolean_one_word_variant_limits(ctx):
+    """More than one word of cases, or more inputs than the loop holds in
+    SGPRs: the one-word loop is passed over even when forced."""
+    names = g.variant_names()
+    w = names.index("boolw_s10")
+    for k, T in ((7, 128), (9, 64)):
+        if T == 128:
+            cases = gen.bool_cases(k)
+        else:
+            rng = np.random.default_rng(k)
+            cases = gen.BoolCases(rng.integers(0, 2 ** 63, size=(k, 1), dtype=np.uint64),
+                                  rng.integers(0, 2 ** 63, size=1, dtype=np.uint64), T)
+        pop = gen.sized_population(95 + k, 8, 11, 3001, n_terms=k, vtype=gen.VT_BOOL)
+        ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+        ph = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=k, chunk_nodes=32)
+        ctx.set_variant(w)
+        try:
+            roots, fit, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, cases.T)
+        finally:
+            ctx.set_variant(-1)
+        assert st["variant"] != w
+        want_roots, want_fit = oracle.eval_population_bool(pop, cases.inputs, cases.target, cases.T, threads=8)
+        assert np.array_equal(roots, want_roots)
+        assert np.array_equal(fit, want_fit)
+        ctx.free(ph)
+        ctx.free(ch)
+
+
 @pytest.mark.parametrize("vtype,C", [(gen.VT_BOOL, 32), (gen.VT_BOOL, 2000), (gen.VT_F32, 64)])
 def test_launch_width(ctx, vtype, C):
     """Capping the resident waves per CU (down to one) leaves every result
