@@ -2168,10 +2168,10 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     if (p->auto_chunk && !p->host_ops.empty()) {
         const int64_t mean = p->total_nodes / std::max<int64_t>(1, p->n_trees);
         // large populations of large trees keep large chunks; mid-size ones (10^8..10^9 nodes) are bound by
-        // chains of chunk hand-offs and do best at 512..1024-node chunks
+        // chains of chunk hand-offs and do best at 512..1024-node chunks; small ones, down to 128
         std::vector<int64_t> cand = p->total_nodes > 1000000000  ? std::vector<int64_t>{1024, 2048, 4096, 8192}
                                     : p->total_nodes > 200000000 ? std::vector<int64_t>{512, 768, 1024, 2048}
-                                                                 : std::vector<int64_t>{256, 512, 1024, 2048, 4096};
+                                                                 : std::vector<int64_t>{128, 192, 256, 512, 1024, 2048, 4096};
         chunk_sizes.clear();
         for (int64_t c : cand)
             if (c <= std::max<int64_t>(256, 4 * mean)) chunk_sizes.push_back(c);
@@ -2191,11 +2191,9 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         *out = tmin;
         return GP_OK;
     };
-    int best = -1;
-    int64_t best_c = p->chunk_nodes;
+    int best = -1, best_w = 0;
     float best_t = 1e30f;
     std::shared_ptr<Pop> best_pop;
-    std::map<std::pair<int64_t, int>, float> all_fits;      // (chunk size, variant) -> time with all waves
     for (int64_t cn : chunk_sizes) {
         std::shared_ptr<Pop> q;
         Pop* qp = p;
@@ -2217,6 +2215,17 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
             }
             qp = q.get();
         }
+        bool improved = false;
+        auto consider = [&](Launch L, float t) {
+            if (t < best_t) {
+                best_t = t;
+                best = L.variant;
+                best_w = L.waves_per_cu;
+                improved = true;
+            }
+        };
+        // every variant with all the waves that fit
+        std::vector<std::pair<float, int>> full;
         for (int v = 0; v < variant_count(); ++v) {
             const Variant& vt = variant_table()[v];
             if (!variant_fits(vt, qp->vtype, qp->max_stack, qp->n_inputs, cs->n_elems, cs->stride,
@@ -2224,20 +2233,32 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
                 continue;
             float t = 0.f;
             RC(time_variant(qp, Launch{v, 0}, &t));
-            all_fits[{cn, v}] = t;
-            if (t < best_t) {
-                best_t = t;
-                best = v;
-                best_c = cn;
-                best_pop = q;
+            full.emplace_back(t, v);
+            consider(Launch{v, 0}, t);
+        }
+        // the two fastest of them with fewer resident waves per CU, from the
+        // most that fit downwards, until two caps in a row are no faster than
+        // that variant's best so far
+        std::sort(full.begin(), full.end());
+        for (size_t i = 0; i < std::min<size_t>(2, full.size()); ++i) {
+            const int v = full[i].second;
+            float vbest = full[i].first;
+            int slower = 0;
+            for (int w : {24, 16, 12, 8, 6, 4, 3, 2}) {
+                if (w >= variant_table()[v].max_blocks_per_cu) continue;
+                float t = 0.f;
+                RC(time_variant(qp, Launch{v, w}, &t));
+                consider(Launch{v, w}, t);
+                if (t < vbest) {
+                    vbest = t;
+                    slower = 0;
+                } else if (++slower == 2) {
+                    break;
+                }
             }
         }
-        if (q && q != best_pop) {
-            q.reset();
-        } else if (q) {
-            // keep only the best compiled copy alive
-            continue;
-        }
+        // keep only the compiled copy of the best chunk size so far
+        if (improved) best_pop = q;
     }
     if (best < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits this population");
     if (best_pop) {
@@ -2251,32 +2272,6 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         best_pop->tree_off.swap(p->tree_off);
         ctx->pops[pop] = best_pop;
         p = best_pop.get();
-    }
-    // At the chosen chunk size, every variant with fewer resident waves per
-    // CU, from the most that fit downwards, until two caps in a row are no
-    // faster than that variant's best so far.
-    int best_w = 0;
-    for (int v = 0; v < variant_count(); ++v) {
-        auto it = all_fits.find({best_c, v});
-        if (it == all_fits.end()) continue;
-        float vbest = it->second;
-        int slower = 0;
-        for (int w : {24, 16, 12, 8, 6, 4, 3, 2}) {
-            if (w >= variant_table()[v].max_blocks_per_cu) continue;
-            float t = 0.f;
-            RC(time_variant(p, Launch{v, w}, &t));
-            if (t < best_t) {
-                best_t = t;
-                best = v;
-                best_w = w;
-            }
-            if (t < vbest) {
-                vbest = t;
-                slower = 0;
-            } else if (++slower == 2) {
-                break;
-            }
-        }
     }
     // keep only the chosen launch's plans
     for (auto it = p->plans.begin(); it != p->plans.end();) {
