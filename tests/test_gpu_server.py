@@ -29,12 +29,13 @@ def wait(ctx, ticket, vtype, T, timeout=60.0):
 def build_jobs(seed=1):
     rng = np.random.default_rng(seed)
     fc = {T: gen.float_cases(T, T) for T in (256, 1024)}
-    bc = gen.bool_cases(8)
+    # Boolean: 8 inputs (256 cases, four words) and 6 inputs (64 cases, the one-word loop)
+    bc = {256: gen.bool_cases(8), 64: gen.bool_cases(6)}
     jobs = []   # (vtype, T, parent tree, points, children [(point, donor)])
     for i in range(8):
-        vt = g.GP_BOOL if i % 4 == 3 else g.GP_F32
-        T = 256 if vt == g.GP_BOOL else (256 if i % 2 else 1024)
-        n_terms = 8 if vt == g.GP_BOOL else 1
+        vt = g.GP_BOOL if i % 4 == 3 or i == 5 else g.GP_F32
+        T = (64 if i == 5 else 256) if vt == g.GP_BOOL else (256 if i % 2 else 1024)
+        n_terms = (6 if T == 64 else 8) if vt == g.GP_BOOL else 1
         tree = gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 11, 60001)), n_terms=n_terms)
         pts = sorted(set(int(p) for p in rng.integers(len(tree), size=3)))
         kids = []
@@ -82,7 +83,8 @@ def test_served_results_same_alone_and_in_mix_and_match_oracle():
     ctx = g.Context(0)
     jobs, fc, bc = build_jobs()
     handles = {(g.GP_F32, T): ctx.set_cases(g.GP_F32, c.x, c.y) for T, c in fc.items()}
-    handles[(g.GP_BOOL, 256)] = ctx.set_cases(g.GP_BOOL, bc.inputs, bc.target, 256)
+    for T, c in bc.items():
+        handles[(g.GP_BOOL, T)] = ctx.set_cases(g.GP_BOOL, c.inputs, c.target, T)
     ctx.server_start(n_streams=4, max_batch_jobs=16, prep_threads=4)
     alone = run(ctx, jobs, handles, mix=False)
     print("alone done", file=sys.stderr, flush=True)
@@ -108,9 +110,9 @@ def test_served_results_same_alone_and_in_mix_and_match_oracle():
             assert same_f32(p["root"], want).all()
             assert p["fitness_f64"] == w_fit or (math.isnan(p["fitness_f64"]) and math.isnan(w_fit))
         else:
-            want = oracle.eval_bool(tree, bc.inputs)
+            want = oracle.eval_bool(tree, bc[T].inputs)
             assert np.array_equal(p["root"], want)
-            assert p["fitness_i64"] == oracle.fitness_bool(want, bc.target, 256)
+            assert p["fitness_i64"] == oracle.fitness_bool(want, bc[T].target, T)
         for ki, (pt, d) in enumerate(kids):
             c = alone[("c", ji, ki)]
             if vt == g.GP_F32:
@@ -119,7 +121,7 @@ def test_served_results_same_alone_and_in_mix_and_match_oracle():
                 assert same_f32(c["root"], w_root).all()
                 assert c["fitness_f64"] == w_fit or (math.isnan(c["fitness_f64"]) and math.isnan(w_fit))
             else:
-                w_root, w_lvl, w_int, w_fit = oracle.incremental_bool(tree, pt, d, bc.inputs, bc.target, 256)
+                w_root, w_lvl, w_int, w_fit = oracle.incremental_bool(tree, pt, d, bc[T].inputs, bc[T].target, T)
                 assert np.array_equal(c["root"], w_root)
                 assert c["fitness_i64"] == w_fit
             assert c["stop_level"] == w_lvl
