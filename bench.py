@@ -459,6 +459,9 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the population size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning-file", default="",
+                    help="JSON lines of autotuner choices: loaded first when the file exists (the autotuner then "
+                         "applies its choices without timing), written after the run")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip per-tree launches and the full re-evaluation of the built children")
     ap.add_argument("--no-configs", action="store_true",
@@ -544,6 +547,8 @@ def main():
 
     torch.cuda.init()
     ctx = g.Context(0)
+    if args.tuning_file and os.path.exists(args.tuning_file):
+        ctx.tuning_load(args.tuning_file)
     if vtype == g.GP_BOOL:
         ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, T)
     else:
@@ -814,6 +819,8 @@ def main():
         for name, key in (("small", "small_ramped"), ("boolean", "boolean_parity6"), ("full_large", "full_large")):
             log(f"[bench] configuration {key} ...")
             configs[key] = measure_config(ctx, g, name, args.threads, hostcpu, args.cpu_budget, args.no_cpu_baseline)
+    if args.tuning_file:
+        ctx.tuning_save(args.tuning_file)
 
     cpu = cpu1 = cpu_inc = None
     if not args.no_cpu_baseline:

@@ -395,6 +395,22 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
 /* Force a variant for later calls (-1 = automatic choice). */
 int gp_set_variant(gp_ctx* ctx, int variant);
 
+/* The autotuner's choices kept across processes, as JSON lines, one object per
+ * (value type, case-count bucket, tree-size bucket) tuned on a device:
+ *   {"device": "gfx950:256", "vtype": 0, "t_bucket": 10, "s_bucket": 22,
+ *    "variant": "f32t_k8_s10", "waves_per_cu": 0, "chunk_nodes": 2048}
+ * (buckets: ceil(log2 T) and ceil(log2 mean tree size); the device is the
+ * architecture and compute-unit count).  gp_tuning_save writes every choice this
+ * context holds.  gp_tuning_load adds the file's choices for this device (lines
+ * for other devices or for variants this library lacks are skipped); later
+ * evaluations use them, and gp_autotune applies a loaded choice without timing
+ * the alternatives, recompiling an automatically chunked population at the
+ * saved chunk size.  Errors: GP_ENOTFOUND if the file cannot be read, GP_EINVAL
+ * for a malformed line or out-of-range value (nothing is loaded then) or a file
+ * that cannot be written. */
+int gp_tuning_save(gp_ctx* ctx, const char* path);
+int gp_tuning_load(gp_ctx* ctx, const char* path);
+
 /* Cap the resident waves per compute unit of later full-evaluation launches:
  * -1 = the tuned cap (none before gp_autotune), 0 = all that fit, n > 0 = at
  * most n.  Returns GP_EINVAL below -1. */

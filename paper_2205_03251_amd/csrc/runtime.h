@@ -218,6 +218,9 @@ struct Ctx {
     int forced_variant = -1;
     int forced_waves = -1;                  // -1: tuned or all that fit; 0: all that fit; n: at most n per CU
     std::map<TuneKey, Launch> tuned;
+    std::map<TuneKey, int64_t> tuned_chunk; // chunk size of each tuned choice
+    std::map<TuneKey, bool> tuned_loaded;   // read by gp_tuning_load, not timed in this process
+    std::string device_name;                // architecture and compute units, keys saved tuning
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t kev0 = nullptr, kev1 = nullptr;   // around the interpreter launch
     Server* server = nullptr;

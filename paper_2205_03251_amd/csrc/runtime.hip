@@ -2,6 +2,7 @@
 // assembly, launch plans (one persistent batched launch captured in a
 // hipGraph, or one launch per tree), incremental batches and the C ABI.
 #include <algorithm>
+#include <cctype>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1166,6 +1167,7 @@ int gp_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, gp_ctx** 
         return GP_EDEVICE;
     }
     c->n_cu = prop.multiProcessorCount;
+    c->device_name = std::string(prop.gcnArchName) + ":" + std::to_string(c->n_cu);
     size_t free_b = 0, total_b = 0;
     if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) return fail(e, "hipMemGetInfo");
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
@@ -2143,6 +2145,135 @@ int gp_set_variant(gp_ctx* ctx, int variant)
     return GP_OK;
 }
 
+// One flat JSON object per line: string values ("...", no escapes) and
+// integers.  False on anything else.
+static bool parse_flat_json(const std::string& line, std::map<std::string, std::string>* kv)
+{
+    size_t i = 0;
+    auto ws = [&] { while (i < line.size() && std::isspace((unsigned char)line[i])) ++i; };
+    auto str = [&](std::string* out) {
+        if (i >= line.size() || line[i] != '"') return false;
+        const size_t e = line.find('"', i + 1);
+        if (e == std::string::npos) return false;
+        *out = line.substr(i + 1, e - i - 1);
+        i = e + 1;
+        return out->find('\\') == std::string::npos;
+    };
+    ws();
+    if (i >= line.size() || line[i++] != '{') return false;
+    for (;;) {
+        ws();
+        std::string k, v;
+        if (!str(&k)) return false;
+        ws();
+        if (i >= line.size() || line[i++] != ':') return false;
+        ws();
+        if (i < line.size() && line[i] == '"') {
+            if (!str(&v)) return false;
+        } else {
+            const size_t b = i;
+            if (i < line.size() && line[i] == '-') ++i;
+            while (i < line.size() && std::isdigit((unsigned char)line[i])) ++i;
+            if (i == b || (i == b + 1 && line[b] == '-')) return false;
+            v = line.substr(b, i - b);
+        }
+        (*kv)[k] = v;
+        ws();
+        if (i < line.size() && line[i] == ',') {
+            ++i;
+            continue;
+        }
+        if (i < line.size() && line[i] == '}') {
+            ++i;
+            ws();
+            return i == line.size();
+        }
+        return false;
+    }
+}
+
+int gp_tuning_save(gp_ctx* ctxp, const char* path)
+{
+    Ctx* ctx = ctxp;
+    if (!ctx) return GP_EINVAL;
+    if (!path) return set_err(ctx, GP_EINVAL, "no path");
+    std::string out;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (const auto& kv : ctx->tuned) {
+            const TuneKey& k = kv.first;
+            const auto ch = ctx->tuned_chunk.find(k);
+            out += "{\"device\": \"" + ctx->device_name + "\", \"vtype\": " + std::to_string(k.vtype) +
+                   ", \"t_bucket\": " + std::to_string(k.tbucket) + ", \"s_bucket\": " + std::to_string(k.sbucket) +
+                   ", \"variant\": \"" + variant_table()[kv.second.variant].name + "\", \"waves_per_cu\": " +
+                   std::to_string(kv.second.waves_per_cu) + ", \"chunk_nodes\": " +
+                   std::to_string(ch != ctx->tuned_chunk.end() ? ch->second : 0) + "}\n";
+        }
+    }
+    FILE* f = std::fopen(path, "w");
+    if (!f) return set_err(ctx, GP_EINVAL, std::string("cannot write ") + path);
+    const bool ok = std::fwrite(out.data(), 1, out.size(), f) == out.size();
+    if (std::fclose(f) != 0 || !ok) return set_err(ctx, GP_EINVAL, std::string("cannot write ") + path);
+    return GP_OK;
+}
+
+int gp_tuning_load(gp_ctx* ctxp, const char* path)
+{
+    Ctx* ctx = ctxp;
+    if (!ctx) return GP_EINVAL;
+    if (!path) return set_err(ctx, GP_EINVAL, "no path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return set_err(ctx, GP_ENOTFOUND, std::string("cannot read ") + path);
+    std::vector<std::pair<TuneKey, std::pair<Launch, int64_t>>> got;
+    std::string line;
+    int c = 0, lineno = 0;
+    bool bad = false;
+    std::string why;
+    while (!bad) {
+        line.clear();
+        while ((c = std::fgetc(f)) != EOF && c != '\n') line.push_back((char)c);
+        if (line.empty() && c == EOF) break;
+        ++lineno;
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        std::map<std::string, std::string> kv;
+        if (!parse_flat_json(line, &kv)) {
+            bad = true;
+            why = "malformed line " + std::to_string(lineno);
+            break;
+        }
+        for (const char* k : {"device", "vtype", "t_bucket", "s_bucket", "variant", "waves_per_cu", "chunk_nodes"})
+            if (!kv.count(k)) {
+                bad = true;
+                why = "line " + std::to_string(lineno) + " lacks \"" + k + "\"";
+            }
+        if (bad) break;
+        if (kv["device"] != ctx->device_name) continue;     // tuned on another device
+        int v = -1;
+        for (int i = 0; i < variant_count(); ++i)
+            if (kv["variant"] == variant_table()[i].name) v = i;
+        if (v < 0) continue;                                 // a variant this library does not have
+        const TuneKey key{std::atoi(kv["vtype"].c_str()), std::atoi(kv["t_bucket"].c_str()),
+                          std::atoi(kv["s_bucket"].c_str())};
+        const int w = std::atoi(kv["waves_per_cu"].c_str());
+        const int64_t cn = std::atoll(kv["chunk_nodes"].c_str());
+        if ((key.vtype != GP_F32 && key.vtype != GP_BOOL) || variant_table()[v].vtype != key.vtype || w < 0 || cn < 0) {
+            bad = true;
+            why = "line " + std::to_string(lineno) + " has values out of range";
+            break;
+        }
+        got.push_back({key, {Launch{v, w}, cn}});
+    }
+    std::fclose(f);
+    if (bad) return set_err(ctx, GP_EINVAL, std::string(path) + ": " + why);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (const auto& e : got) {
+        ctx->tuned[e.first] = e.second.first;
+        ctx->tuned_chunk[e.first] = e.second.second;
+        ctx->tuned_loaded[e.first] = true;
+    }
+    return GP_OK;
+}
+
 int gp_set_launch_width(gp_ctx* ctx, int waves_per_cu)
 {
     if (!ctx) return GP_EINVAL;
@@ -2156,6 +2287,42 @@ int gp_set_launch_width(gp_ctx* ctx, int waves_per_cu)
 // every candidate chunk size, on this population and case set; keep the
 // fastest (chunk size: recompiled in place; variant: remembered per value
 // type, case-count bucket and tree-size bucket).
+// The population p recompiled at chunk size cn into a new Pop (from the kept
+// device copy of the trees, else from the host copy).
+static int rechunk(Ctx* ctx, Pop* p, int64_t cn, std::shared_ptr<Pop>* out)
+{
+    auto q = std::make_shared<Pop>();
+    const bool rec = !p->host_rec_points.empty() || !p->host_rec_offsets.empty();
+    if (p->device_compiled) {
+        const bool kept = p->tree_ops.p && p->tree_off == p->host_offsets;
+        RC(build_population_device(ctx, p->vtype, p->n_inputs, p->n_trees, kept ? nullptr : p->host_ops.data(),
+                                   kept ? p->tree_ops.as<uint8_t>() : nullptr, p->host_offsets.data(),
+                                   rec ? p->host_rec_points.data() : nullptr,
+                                   rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), nullptr));
+    } else {
+        RC(build_population(ctx, p->vtype, p->layout, p->n_inputs, p->n_trees, p->host_ops.data(),
+                            p->host_offsets.data(), rec ? p->host_rec_points.data() : nullptr,
+                            rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), ctx->stream, true));
+    }
+    *out = std::move(q);
+    return GP_OK;
+}
+
+// The re-chunked copy q replaces population p under the same handle; it takes
+// over the host and device copies of the trees.
+static Pop* replace_population(Ctx* ctx, gp_handle pop, Pop* p, const std::shared_ptr<Pop>& q)
+{
+    q->auto_chunk = true;
+    q->host_ops.swap(p->host_ops);
+    q->host_offsets.swap(p->host_offsets);
+    q->host_rec_points.swap(p->host_rec_points);
+    q->host_rec_offsets.swap(p->host_rec_offsets);
+    q->tree_ops.swap(p->tree_ops);
+    q->tree_off.swap(p->tree_off);
+    ctx->pops[pop] = q;
+    return q.get();
+}
+
 int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, double* best_ms)
 {
     if (!ctx) return GP_EINVAL;
@@ -2164,6 +2331,31 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     Pop* p;
     CaseSet* cs;
     RC(lookup(ctx, pop, cases, &p, &cs));
+    {
+        // a choice read by gp_tuning_load: applied without timing the others
+        const TuneKey key = tune_key(p->vtype, cs, p);
+        auto it = ctx->tuned.find(key);
+        if (ctx->tuned_loaded.count(key) && it != ctx->tuned.end() &&
+            default_variant(p->vtype, cs, p, it->second.variant) == it->second.variant) {
+            const Launch L = it->second;
+            const int64_t cn = ctx->tuned_chunk.count(key) ? ctx->tuned_chunk[key] : p->chunk_nodes;
+            if (p->auto_chunk && !p->host_ops.empty() && cn > 0 && cn != p->chunk_nodes) {
+                std::shared_ptr<Pop> q;
+                RC(rechunk(ctx, p, cn, &q));
+                p = replace_population(ctx, pop, p, q);
+            }
+            RC(enqueue_full(ctx, p, cases, cs, L, false, true, ctx->stream, nullptr));   // warm-up + capture
+            HIPC(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+            RC(enqueue_full(ctx, p, cases, cs, L, false, true, ctx->stream, nullptr));
+            HIPC(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+            HIPC(ctx, hipStreamSynchronize(ctx->stream));
+            float ms = 0.f;
+            HIPC(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            if (best_variant) *best_variant = L.variant;
+            if (best_ms) *best_ms = ms;
+            return GP_OK;
+        }
+    }
     std::vector<int64_t> chunk_sizes{p->chunk_nodes};
     if (p->auto_chunk && !p->host_ops.empty()) {
         const int64_t mean = p->total_nodes / std::max<int64_t>(1, p->n_trees);
@@ -2198,21 +2390,7 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         std::shared_ptr<Pop> q;
         Pop* qp = p;
         if (cn != p->chunk_nodes) {
-            q = std::make_shared<Pop>();
-            const bool rec = !p->host_rec_points.empty() || !p->host_rec_offsets.empty();
-            if (p->device_compiled) {
-                // from the kept device copy of the trees when there is one
-                const bool kept = p->tree_ops.p && p->tree_off == p->host_offsets;
-                RC(build_population_device(ctx, p->vtype, p->n_inputs, p->n_trees,
-                                           kept ? nullptr : p->host_ops.data(),
-                                           kept ? p->tree_ops.as<uint8_t>() : nullptr, p->host_offsets.data(),
-                                           rec ? p->host_rec_points.data() : nullptr,
-                                           rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), nullptr));
-            } else {
-                RC(build_population(ctx, p->vtype, p->layout, p->n_inputs, p->n_trees, p->host_ops.data(),
-                                    p->host_offsets.data(), rec ? p->host_rec_points.data() : nullptr,
-                                    rec ? p->host_rec_offsets.data() : nullptr, cn, q.get(), ctx->stream, true));
-            }
+            RC(rechunk(ctx, p, cn, &q));
             qp = q.get();
         }
         bool improved = false;
@@ -2261,18 +2439,7 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
         if (improved) best_pop = q;
     }
     if (best < 0) return set_err(ctx, GP_EINVAL, "no interpreter variant fits this population");
-    if (best_pop) {
-        // the re-chunked copy replaces the population under the same handle
-        best_pop->auto_chunk = true;
-        best_pop->host_ops.swap(p->host_ops);
-        best_pop->host_offsets.swap(p->host_offsets);
-        best_pop->host_rec_points.swap(p->host_rec_points);
-        best_pop->host_rec_offsets.swap(p->host_rec_offsets);
-        best_pop->tree_ops.swap(p->tree_ops);
-        best_pop->tree_off.swap(p->tree_off);
-        ctx->pops[pop] = best_pop;
-        p = best_pop.get();
-    }
+    if (best_pop) p = replace_population(ctx, pop, p, best_pop);
     // keep only the chosen launch's plans
     for (auto it = p->plans.begin(); it != p->plans.end();) {
         if (std::get<0>(it->first) != best || std::get<1>(it->first) != best_w) it = p->plans.erase(it);
@@ -2280,7 +2447,10 @@ int gp_autotune(gp_ctx* ctx, gp_handle pop, gp_handle cases, int* best_variant, 
     }
     RC(enqueue_full(ctx, p, cases, cs, Launch{best, best_w}, false, true, ctx->stream, nullptr));
     HIPC(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->tuned[tune_key(p->vtype, cs, p)] = Launch{best, best_w};
+    const TuneKey key = tune_key(p->vtype, cs, p);
+    ctx->tuned[key] = Launch{best, best_w};
+    ctx->tuned_chunk[key] = p->chunk_nodes;
+    ctx->tuned_loaded.erase(key);
     if (best_variant) *best_variant = best;
     if (best_ms) *best_ms = best_t;
     return GP_OK;

@@ -31,7 +31,7 @@ EXPORTS = [
     "gp_set_variant", "gp_server_start", "gp_server_submit", "gp_server_poll", "gp_server_release",
     "gp_server_stop", "gp_inspect_program", "gp_inspect_child_program", "gp_validate_tree", "gp_index_trees",
     "gp_index_trees_noalloc", "gp_population_results", "gp_evolve", "gp_population_ops", "gp_valu_calibration",
-    "gp_population_dump", "gp_set_launch_width",
+    "gp_population_dump", "gp_set_launch_width", "gp_tuning_save", "gp_tuning_load",
 ]
 INDEX_NOALLOC_MAX_NODES = 4194304
 
@@ -153,6 +153,8 @@ def lib() -> C.CDLL:
     h.gp_autotune.argtypes = [P, I64, I64, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     h.gp_set_variant.argtypes = [P, C.c_int]
     h.gp_set_launch_width.argtypes = [P, C.c_int]
+    h.gp_tuning_save.argtypes = [P, C.c_char_p]
+    h.gp_tuning_load.argtypes = [P, C.c_char_p]
     h.gp_server_start.argtypes = [P, C.POINTER(ServerCfg)]
     h.gp_server_submit.argtypes = [P, C.POINTER(Job), C.POINTER(I64)]
     h.gp_server_poll.argtypes = [P, I64, C.POINTER(JobResult), P, I64]
@@ -448,6 +450,12 @@ class Context:
 
     def set_variant(self, v: int):
         self._check(lib().gp_set_variant(self._h, v))
+
+    def tuning_save(self, path: str):
+        self._check(lib().gp_tuning_save(self._h, os.fsencode(path)))
+
+    def tuning_load(self, path: str):
+        self._check(lib().gp_tuning_load(self._h, os.fsencode(path)))
 
     def set_launch_width(self, waves_per_cu: int):
         """-1: the tuned cap; 0: all resident waves that fit; n: at most n per CU."""

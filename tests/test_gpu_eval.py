@@ -535,6 +535,70 @@ def test_launch_width(ctx, vtype, C):
         ctx.free(ch)
 
 
+def test_tuning_saved_and_loaded(ctx, tmp_path):
+    """gp_tuning_save writes the autotuner's choice (variant, launch width,
+    chunk size) keyed by device and buckets; another context that loads it
+    applies the same choice without timing the others (recompiling an
+    automatically chunked population at the saved chunk size) and gets the
+    oracle's results.  Malformed and missing files are refused; lines for
+    another device are skipped."""
+    import json
+    cases = gen.bool_cases(6)
+    pop = gen.sized_population(73, 60, 101, 20001, n_terms=6, vtype=gen.VT_BOOL)
+    want_roots, want_fit = oracle.eval_population_bool(pop, cases.inputs, cases.target, cases.T, threads=8)
+    names = g.variant_names()
+    ch = ctx.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+    ph = ctx.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=6)
+    v, _ = ctx.autotune(ph, ch)
+    info = ctx.population_info(ph)
+    _, _, st = ctx.evaluate_full(ph, ch, g.GP_BOOL, pop.n_trees, cases.T)
+    path = str(tmp_path / "tuning.jsonl")
+    ctx.tuning_save(path)
+    lines = [json.loads(line) for line in open(path)]
+    mine = [e for e in lines if e["vtype"] == g.GP_BOOL and e["variant"] == names[v]]
+    assert mine and mine[0]["chunk_nodes"] == info["chunk_nodes"] and mine[0]["waves_per_cu"] == st["waves_per_cu"]
+    ctx.free(ph)
+    ctx.free(ch)
+
+    c2 = g.Context(0)
+    try:
+        c2.tuning_load(path)
+        ch2 = c2.set_cases(g.GP_BOOL, cases.inputs, cases.target, cases.T)
+        ph2 = c2.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=6, chunk_nodes=1024)
+        roots, fit, st2 = c2.evaluate_full(ph2, ch2, g.GP_BOOL, pop.n_trees, cases.T)
+        assert st2["variant"] == v and st2["waves_per_cu"] == st["waves_per_cu"]      # loaded choice, no tuning
+        assert np.array_equal(roots, want_roots) and np.array_equal(fit, want_fit)
+        ph3 = c2.load_population(g.GP_BOOL, pop.ops, pop.offsets, n_inputs=6)
+        v3, _ = c2.autotune(ph3, ch2)
+        assert v3 == v and c2.population_info(ph3)["chunk_nodes"] == info["chunk_nodes"]
+        roots, fit, _ = c2.evaluate_full(ph3, ch2, g.GP_BOOL, pop.n_trees, cases.T)
+        assert np.array_equal(roots, want_roots) and np.array_equal(fit, want_fit)
+
+        bad = str(tmp_path / "bad.jsonl")
+        open(bad, "w").write('{"device": "x", "vtype": 1\n')
+        with pytest.raises(g.GPError) as e:
+            c2.tuning_load(bad)
+        assert e.value.code == g.GP_EINVAL
+        open(bad, "w").write('{"device": "x", "vtype": 1, "t_bucket": 6}\n')
+        with pytest.raises(g.GPError) as e:
+            c2.tuning_load(bad)
+        assert e.value.code == g.GP_EINVAL
+        with pytest.raises(g.GPError) as e:
+            c2.tuning_load(str(tmp_path / "missing.jsonl"))
+        assert e.value.code == g.GP_ENOTFOUND
+        other = str(tmp_path / "other.jsonl")
+        open(other, "w").write(open(path).read().replace(lines[0]["device"], "gfx000:1"))
+        c3 = g.Context(0)
+        try:
+            c3.tuning_load(other)
+            c3.tuning_save(str(tmp_path / "none.jsonl"))
+            assert open(str(tmp_path / "none.jsonl")).read() == ""
+        finally:
+            c3.close()
+    finally:
+        c2.close()
+
+
 def test_boolean_table_variants_refuse_many_inputs(ctx):
     """With more input rows than the registers hold, a forced table variant is
     passed over for one that stages the inputs in LDS."""
