@@ -668,13 +668,22 @@ __device__ __forceinline__ void run_bool_dispatch_{K}_{S}(const GP_CONST uint32_
 # are involved: LOAD reads lane 0's word of a chunk vector with an
 # agent-coherent vector load, and STORE and the chunk's end write lane 0's
 # word (every other lane is masked off for those loads and stores).
+#
+# Dispatch is direct: the handler of key k (with the fetch of the next-but-one
+# word and the jump to the next word's handler) fills a slot of BOOLW_SLOT
+# bytes at table + k * BOOLW_SLOT, so a word costs one jump instead of the
+# table's two (the slot's start is computed, not read).  The assembler checks
+# that no slot outgrows its place; code that would (the LOADs past the ones
+# fetched ahead) and the way out sit before the slots, within a branch's reach.
 BOOLW_S = 10
 BOOLW_NI = 8
 BOOLW_NP = 4
 BOOLW_SBASE = 40
+BOOLW_SLOT = 128
 
 
-def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP) -> str:
+def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP, SLOT: int = BOOLW_SLOT) -> str:
+    assert SLOT & (SLOT - 1) == 0
     names = []
     for p in ["TB", "TG", "X", "Y"] + [f"ST{d}" for d in range(S)] + [f"IN{j}" for j in range(NI)] + \
             [f"LD{j}" for j in range(NP)]:
@@ -692,12 +701,14 @@ def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP) -> s
     lab = lambda name: f".Lgw{S}_{name}_%="
 
     def tail():
+        # the handler of key k starts at table + k * SLOT: one jump per word
         a("  s_waitcnt lgkmcnt(0)")
         a(f"  s_mov_b32 {sr('INS')}, {sr('NXT')}")
         a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
         a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
         a(f"  s_and_b32 {sr('TG0')}, {sr('INS')}, 0x3ff")
-        a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
+        a(f"  s_lshl_b32 {sr('TG0')}, {sr('TG0')}, {SLOT.bit_length() - 1}")
+        a(f"  s_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
         a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
         a(f"  s_setpc_b64 {sp('TG')}")
 
@@ -763,31 +774,57 @@ def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP) -> s
         a(f"  v_readfirstlane_b32 {sr(f'LD{j}1')}, v{V_PF + 2 * j + 1}")
     a(f"{lab('pfok')}:")
     tail()
-    # ---------------------------------------------------------- table
+    # ---------------------------------------------------------- slots
     handlers = {}
     for key in range(1024):
         f, mode, d = key & 3, (key >> 2) & 7, key >> 5
         if key == END_KEY:
-            handlers[key] = "end"
+            handlers[key] = False
         elif d < S and mode in (M_XX, M_XS):
-            handlers[key] = f"h{key}"
+            handlers[key] = True
         elif d + 1 < S and mode == M_SS:
-            handlers[key] = f"h{key}"
+            handlers[key] = True
         elif d < S and f == 0 and mode in (M_PUSH, M_LOAD, M_STORE):
-            handlers[key] = f"h{key}"
+            handlers[key] = True
         else:
-            handlers[key] = "end"     # never emitted for Boolean programs; ends the chunk
+            handlers[key] = False     # never emitted for Boolean programs; ends the chunk
+    # Out-of-line code, before the slots so that branches to it stay within
+    # the +-128 KiB a branch reaches: the LOADs past the ones fetched ahead,
+    # and the jump to the chunk's end, which follows the last slot.
+    for key in range(1024):
+        f, mode, d = key & 3, (key >> 2) & 7, key >> 5
+        if not handlers[key] or mode != M_LOAD:
+            continue
+        assert key * SLOT < 96 * 1024
+        a(f"{lab(f'ld{key}')}:")
+        a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 2")
+        a(f"  s_load_dword {sr('T1')}, %[cin], {sr('T0')}")
+        a("  s_waitcnt lgkmcnt(0)")
+        row_address(sr('T1'), "%[vb_lo]", "%[vb_hi]")
+        a(f"  s_mov_b64 {sp('Y')}, exec")
+        a("  s_mov_b64 exec, 1")
+        a(f"  global_load_dwordx2 v[{V_T}:{V_T + 1}], %[voff], {sp('X')}{SHARED}")
+        a(f"  s_mov_b64 exec, {sp('Y')}")
+        a("  s_waitcnt vmcnt(0)")
+        a(f"  v_readfirstlane_b32 {sr(f'ST{d}0')}, v{V_T}")
+        a(f"  v_readfirstlane_b32 {sr(f'ST{d}1')}, v{V_T + 1}")
+        tail()
+    a(f"{lab('endjump')}:")
+    a(f"  s_add_u32 {sr('TG0')}, {sr('TB0')}, {1024 * SLOT:#x}")
+    a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
+    a(f"  s_setpc_b64 {sp('TG')}")
+    a(f"  .p2align {SLOT.bit_length() - 1}")
     a(f"{lab('tbl')}:")
     for key in range(1024):
-        a(f"  s_branch {lab(handlers[key])}")
-    # ---------------------------------------------------------- handlers
-    for key in range(1024):
-        if handlers[key] != f"h{key}":
-            continue
         f, mode, d = key & 3, (key >> 2) & 7, key >> 5
         st = f"ST{d}"
-        a(f"{lab(handlers[key])}:")
-        if mode == M_XX:                 # f(input a, input b), a = payload & 2047, b = payload >> 11
+        slot = lab(f"s{key}")
+        if key:
+            a(f"  .p2align {SLOT.bit_length() - 1}")
+        a(f"{slot}:")
+        if not handlers[key]:
+            a(f"  s_branch {lab('endjump') if key < 512 else lab('end')}")
+        elif mode == M_XX:               # f(input a, input b), a = payload & 2047, b = payload >> 11
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
             a(f"  s_and_b32 {sr('T1')}, {sr('T0')}, 0x7ff")
             a(f"  s_lshr_b32 {sr('T0')}, {sr('T0')}, 11")
@@ -798,19 +835,23 @@ def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP) -> s
             a("  s_nop 0")
             a(f"  s_movrels_b64 {sp('Y')}, {sp('IN0')}")
             a(f"  {OPS[f]} {sp(st)}, {sp('X')}, {sp('Y')}")
+            tail()
         elif mode == M_XS:               # f(input payload, slot d)
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
             a(f"  s_lshl_b32 m0, {sr('T0')}, 1")
             a("  s_nop 0")
             a(f"  s_movrels_b64 {sp('X')}, {sp('IN0')}")
             a(f"  {OPS[f]} {sp(st)}, {sp('X')}, {sp(st)}")
+            tail()
         elif mode == M_SS:
             a(f"  {OPS[f]} {sp(st)}, {sp(st)}, {sp(f'ST{d + 1}')}")
+            tail()
         elif mode == M_PUSH:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
             a(f"  s_lshl_b32 m0, {sr('T0')}, 1")
             a("  s_nop 0")
             a(f"  s_movrels_b64 {sp(st)}, {sp('IN0')}")
+            tail()
         elif mode == M_LOAD:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
             a(f"  s_cmp_lt_u32 {sr('T0')}, {NP}")
@@ -819,30 +860,22 @@ def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP) -> s
             a("  s_nop 0")
             a(f"  s_movrels_b64 {sp(st)}, {sp('LD0')}")
             tail()
-            a(f"{lab(f'ld{key}')}:")
-            a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 2")
-            a(f"  s_load_dword {sr('T1')}, %[cin], {sr('T0')}")
-            a("  s_waitcnt lgkmcnt(0)")
-            row_address(sr('T1'), "%[vb_lo]", "%[vb_hi]")
-            a(f"  s_mov_b64 {sp('Y')}, exec")
-            a("  s_mov_b64 exec, 1")
-            a(f"  global_load_dwordx2 v[{V_T}:{V_T + 1}], %[voff], {sp('X')}{SHARED}")
-            a(f"  s_mov_b64 exec, {sp('Y')}")
-            a("  s_waitcnt vmcnt(0)")
-            a(f"  v_readfirstlane_b32 {sr(st + '0')}, v{V_T}")
-            a(f"  v_readfirstlane_b32 {sr(st + '1')}, v{V_T + 1}")
         elif mode == M_STORE:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
             row_address(sr('T0'), "%[rb_lo]", "%[rb_hi]")
             lane0_store(st, sp('X'), "")
-        tail()
-    # ---------------------------------------------------------- end
+            tail()
+        # the assembler refuses a slot that outgrows its place
+        a(f"  .if . - {slot} > {SLOT}")
+        a(f"  .error \"dispatch slot {key} is longer than {SLOT} bytes\"")
+        a("  .endif")
+    # ---------------------------------------------------------- end (at table + 1024 * SLOT)
+    a(f"  .p2align {SLOT.bit_length() - 1}")
     a(f"{lab('end')}:")
-    a("  s_waitcnt lgkmcnt(0)")
     lane0_store("ST0", "%[outb]", SHARED)
     a("  s_waitcnt vmcnt(0)")
 
-    body = "\n".join(f'        "{line}\\n"' for line in L)
+    body = "\n".join('        "' + line.replace('"', '\\"') + '\\n"' for line in L)
     vclob = ", ".join(f'"v{i}"' for i in range(V_CP, n_vgpr))
     sclob = ", ".join(f'"s{s[n]}"' for n in names)
     return f"""
