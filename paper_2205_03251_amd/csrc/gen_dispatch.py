@@ -1,8 +1,10 @@
 """Generate the gfx950 dispatch loop of the float32 interpreter.
 
-Writes dispatch_f32.inc: for each (K, S) in VARIANTS a device function
-run_f32_dispatch_K_S() holding one inline-asm block that runs one chunk's
-program and stores the chunk's value.
+Writes dispatch_f32.inc: for each (K, S) in VARIANTS two device functions,
+run_f32_dispatch_K_S() (branch-table dispatch) and run_f32d_dispatch_K_S()
+(direct dispatch into handler slots), each holding one inline-asm block that
+runs one chunk's program and stores the chunk's value; and dispatch_bool.inc,
+the Boolean loops.
 
 Why assembly: the interpreter spends most of its scalar instructions on
 choosing the handler.  The compiler lowers a switch to a tree of compares
@@ -105,7 +107,12 @@ TINY = 0x358637BD                     # 1e-6f
 P2 = lambda e: (127 + e) << 23        # bit pattern of 2^e (normal range)
 
 
-def gen_one(K: int, S: int) -> str:
+def gen_one(K: int, S: int, direct: bool = False, SLOT: int = 128) -> str:
+    """direct=False: the key indexes a table of branches to the handlers (two
+    jumps per word).  direct=True: the key's slot of SLOT bytes at table +
+    key * SLOT holds the handler itself for +, - and x (and the copy of x/x),
+    so those words take one jump; divides, PUSH, LOAD and STORE stay out of
+    line, one branch from their slot."""
     assert K % 2 == 0, "the range checks pair up slots"
     V_X = V_ST + S * K
     V_Q = V_X + K
@@ -135,7 +142,11 @@ def gen_one(K: int, S: int) -> str:
         a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
         a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
         a(f"  s_and_b32 {sr('TG0')}, {sr('INS')}, 0x3ff")
-        a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
+        if direct:          # the slot of key k starts at table + k * SLOT
+            a(f"  s_lshl_b32 {sr('TG0')}, {sr('TG0')}, {SLOT.bit_length() - 1}")
+            a(f"  s_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
+        else:               # entry k of the branch table
+            a(f"  s_lshl2_add_u32 {sr('TG0')}, {sr('TG0')}, {sr('TB0')}")
         a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
         a(f"  s_setpc_b64 {sp('TG0')}")
 
@@ -207,7 +218,7 @@ def gen_one(K: int, S: int) -> str:
         for k in range(K):
             short_div(dsts[k], nums[k], dens[k])
 
-    lab = lambda name: f".Lgp{K}_{S}_{name}_%="
+    lab = lambda name: f".Lgp{'d' if direct else ''}{K}_{S}_{name}_%="
     # ---------------------------------------------------------- entry
     a(f"  s_mov_b32 {sr('TINY')}, {TINY:#x}")
     for k in range(K):
@@ -283,15 +294,9 @@ def gen_one(K: int, S: int) -> str:
         else:
             name = "end"          # never emitted by the compiler; ends the chunk
         handlers[key] = name
-    a(f"{lab('tbl')}:")
-    for key in range(1024):
-        a(f"  s_branch {lab(handlers[key])}")
     # ---------------------------------------------------------- handlers
-    for key in range(1024):
-        if handlers[key] == "end" or handlers[key] != f"h{key}":
-            continue
+    def emit(key):
         f, mode, d = key & 3, (key >> 2) & 7, key >> 5
-        a(f"{lab(handlers[key])}:")
         if mode == M_XX and f == 3:
             for k in range(K):
                 a(f"  v_mov_b32_e32 {st(d, k)}, v{V_Q + k}")
@@ -413,19 +418,65 @@ def gen_one(K: int, S: int) -> str:
             for k in range(K):
                 a(f"  global_store_dword %[voff], {st(d, k)}, {sp('A0')} offset:{256 * k}")
         tail()
-    # ---------------------------------------------------------- end
-    a(f"{lab('end')}:")
+
+    def in_slot(key):
+        """+, -, x (and the copy of x / x): the handler and the next word's
+        dispatch fit the key's slot.  Divides, PUSH, LOAD and STORE are out of
+        line, one branch away."""
+        f, mode = key & 3, (key >> 2) & 7
+        return handlers[key] == f"h{key}" and (mode == M_XX or (f != 3 and mode in (M_XS, M_SX, M_SS, M_RS)))
+
+    if not direct:
+        a(f"{lab('tbl')}:")
+        for key in range(1024):
+            a(f"  s_branch {lab(handlers[key])}")
+        for key in range(1024):
+            if handlers[key] == f"h{key}":
+                a(f"{lab(handlers[key])}:")
+                emit(key)
+        a(f"{lab('end')}:")
+    # out-of-line handlers and the way out, before the slots (within a branch's reach)
+    for key in range(1024 if direct else 0):
+        if handlers[key] == f"h{key}" and not in_slot(key):
+            assert key * SLOT < 64 * 1024
+            a(f"{lab(handlers[key])}:")
+            emit(key)
+    if direct:
+        a(f"{lab('endjump')}:")
+        a(f"  s_add_u32 {sr('TG0')}, {sr('TB0')}, {1024 * SLOT:#x}")
+        a(f"  s_addc_u32 {sr('TG1')}, {sr('TB1')}, 0")
+        a(f"  s_setpc_b64 {sp('TG0')}")
+        # ------------------------------------------------------ slots
+        a(f"  .p2align {SLOT.bit_length() - 1}")
+        a(f"{lab('tbl')}:")
+    for key in range(1024 if direct else 0):
+        slot = lab(f"s{key}")
+        if key:
+            a(f"  .p2align {SLOT.bit_length() - 1}")
+        a(f"{slot}:")
+        if in_slot(key):
+            emit(key)
+        elif handlers[key] == f"h{key}":
+            a(f"  s_branch {lab(handlers[key])}")
+        else:
+            a(f"  s_branch {lab('endjump') if key < 512 else lab('end')}")
+        a(f"  .if . - {slot} > {SLOT}")
+        a(f"  .error \"dispatch slot {key} is longer than {SLOT} bytes\"")
+        a("  .endif")
+    if direct:              # the end, at table + 1024 * SLOT
+        a(f"  .p2align {SLOT.bit_length() - 1}")
+        a(f"{lab('end')}:")
     a("  s_waitcnt lgkmcnt(0)")
     for k in range(K):
         a(f"  global_store_dword %[voff], {st(0, k)}, %[outb] offset:{256 * k}{SHARED}")
     a("  s_waitcnt vmcnt(0)")
 
-    body = "\n".join(f'        "{line}\\n"' for line in L)
+    body = "\n".join('        "' + line.replace('"', '\\"') + '\\n"' for line in L)
     vclob = ", ".join(f'"v{i}"' for i in range(V_ST, n_vgpr))
     sclob = ", ".join(f'"s{s[n]}"' for n in names)
     return f"""
 // K = {K} cases per lane, S = {S} stack slots: v{V_ST}..v{n_vgpr - 1}, s{S_BASE}..s{S_BASE + len(names) - 1}.
-__device__ __forceinline__ void run_f32_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const float* inb,
+__device__ __forceinline__ void run_f32{'d' if direct else ''}_dispatch_{K}_{S}(const GP_CONST uint32_t* code, const float* inb,
                                                      const float* vb, float* rb, const GP_CONST int32_t* cin,
                                                      uint32_t strideb, float* outb, uint32_t voff,
                                                      uint32_t vc0, uint32_t vc1, uint32_t vc2, uint32_t vc3)
@@ -910,7 +961,7 @@ def write_if_changed(path: str, text: str) -> None:
 
 def main(out_path: str) -> None:
     head = "// Generated by gen_dispatch.py; do not edit.\n#pragma once\n"
-    write_if_changed(out_path, head + "".join(gen_one(K, S) for K, S in VARIANTS))
+    write_if_changed(out_path, head + "".join(gen_one(K, S, direct) for K, S in VARIANTS for direct in (False, True)))
     write_if_changed(os.path.join(os.path.dirname(out_path), "dispatch_bool.inc"),
                      head + f"constexpr int kBoolDispatchInputs = {BOOL_NI};\n"
                      + "".join(gen_bool(K, S) for K, S in BOOL_VARIANTS) + gen_bool_word())

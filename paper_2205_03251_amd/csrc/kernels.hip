@@ -263,7 +263,7 @@ __global__ __launch_bounds__(64) void k_eval_f32(EvalParams p)
 // which chooses each handler through a branch table.
 #include "dispatch_f32.inc"
 
-template <int K, int S>
+template <int K, int S, bool DIRECT>
 __device__ __forceinline__ void run_f32_dispatch(const GP_CONST uint32_t* code, const float* inb, const float* vb,
                                                  float* rb, const GP_CONST int32_t* cin, uint32_t strideb,
                                                  float* outb, uint32_t voff, uint32_t code_len)
@@ -272,14 +272,19 @@ __device__ __forceinline__ void run_f32_dispatch(const GP_CONST uint32_t* code, 
     const uint32_t last = code_len > 0 ? code_len - 1 : 0, l16 = (voff / 4u) * 16u;
     const uint32_t vc0 = min(l16, last) * 4u, vc1 = min(l16 + 1024u, last) * 4u;
     const uint32_t vc2 = min(l16 + 2048u, last) * 4u, vc3 = min(l16 + 3072u, last) * 4u;
-    if constexpr (K == 4 && S == 10)
+    if constexpr (K == 4 && S == 10 && !DIRECT)
         run_f32_dispatch_4_10(code, inb, vb, rb, cin, strideb, outb, voff, vc0, vc1, vc2, vc3);
-    else if constexpr (K == 8 && S == 10)
+    else if constexpr (K == 8 && S == 10 && !DIRECT)
         run_f32_dispatch_8_10(code, inb, vb, rb, cin, strideb, outb, voff, vc0, vc1, vc2, vc3);
+    else if constexpr (K == 4 && S == 10 && DIRECT)
+        run_f32d_dispatch_4_10(code, inb, vb, rb, cin, strideb, outb, voff, vc0, vc1, vc2, vc3);
+    else if constexpr (K == 8 && S == 10 && DIRECT)
+        run_f32d_dispatch_8_10(code, inb, vb, rb, cin, strideb, outb, voff, vc0, vc1, vc2, vc3);
     else static_assert(K == 4 && S == 10, "no generated dispatch loop for this K and S");
 }
 
-template <int K, int S>
+// DIRECT: the loop that dispatches into handler slots (see gen_dispatch.py).
+template <int K, int S, bool DIRECT = false>
 __global__ __launch_bounds__(64) void k_eval_f32_tbl(EvalParams p)
 {
     const int lane = threadIdx.x;
@@ -304,8 +309,8 @@ __global__ __launch_bounds__(64) void k_eval_f32_tbl(EvalParams p)
             if (ch.parent >= 0) next = load_chunk(cst(p.chunks) + ch.parent);
             float* rb = (float*)p.recs + (int64_t)ch.rec_base * p.stride + case0;
             float* outb = (float*)p.vecs + (int64_t)ch.out_slot * p.stride + case0;
-            run_f32_dispatch<K, S>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off, strideb,
-                                   outb, voff, (uint32_t)ch.code_len);
+            run_f32_dispatch<K, S, DIRECT>(cst(p.code) + ch.code_off, inb, vb, rb, cst(p.chunk_in) + ch.in_off,
+                                           strideb, outb, voff, (uint32_t)ch.code_len);
             if (ch.parent < 0) break;
             // The loop wrote the chunk's vector with agent-coherent stores and
             // waited for them to complete, and LOAD reads vectors with
@@ -800,6 +805,8 @@ static Variant g_variants[] = {
     {"f32_k8_s10", 0, 8, 10, (const void*)k_eval_f32<8, 10>, 0},
     {"f32t_k4_s10", 0, 4, 10, (const void*)k_eval_f32_tbl<4, 10>, 0, 1, 0},
     {"f32t_k8_s10", 0, 8, 10, (const void*)k_eval_f32_tbl<8, 10>, 0, 1, 0},
+    {"f32d_k4_s10", 0, 4, 10, (const void*)k_eval_f32_tbl<4, 10, true>, 0, 1, 0},
+    {"f32d_k8_s10", 0, 8, 10, (const void*)k_eval_f32_tbl<8, 10, true>, 0, 1, 0},
     {"bool_k1_s16", 1, 1, 16, (const void*)k_eval_bool<1, 16>, 0},
     {"bool_k2_s16", 1, 2, 16, (const void*)k_eval_bool<2, 16>, 0},
     {"bool_k1_s10", 1, 1, 10, (const void*)k_eval_bool<1, 10>, 0},

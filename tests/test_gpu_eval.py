@@ -236,7 +236,7 @@ def test_reciprocal_every_float_of_a_binade(ctx):
     b_all = (np.uint32(127 << 23) | sig).view(np.float32) * np.where(sig & 1, -1, 1).astype(np.float32)
     ph = ctx.load_population(g.GP_F32, pop.ops, pop.offsets, n_inputs=2)
     names = g.variant_names()
-    tbl = [v for v in f32_variants() if names[v].startswith("f32t_")]
+    tbl = [v for v in f32_variants() if names[v].startswith(("f32t_", "f32d_"))]
     assert tbl
     for blk in range(0, b_all.size, T):
         b = b_all[blk:blk + T]
