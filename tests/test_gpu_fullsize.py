@@ -2,7 +2,8 @@
 
 Where the oracle is fast enough (Boolean, 64 cases) every tree is compared;
 for the large float populations a sample of trees / children is compared with
-the oracle one by one (several independent oracle instances in threads) and
+the oracle one by one (several independent oracle instances in threads; for
+the children of the largest parents, one oracle walk per block of cases) and
 properties that hold at any size are checked for all of them.
 """
 import math
@@ -15,6 +16,7 @@ import pytest
 import gen
 import oracle
 from paper_2205_03251_amd import gpeval as g
+from tests import split_oracle
 from tests.scalar_ref import same_f32
 
 pytestmark = pytest.mark.gpu
@@ -141,6 +143,20 @@ def test_incremental_full_size_sampled(ctx):
         assert info["interpreted_nodes"][i] == w_int
         assert same_f32(roots[i], w_root).all()
         assert fit[i] == w_fit or (math.isnan(fit[i]) and math.isnan(w_fit))
+    # children of the largest parents (about 1e7 nodes; one neutral, two random) on all 1024 cases, the
+    # oracle's incremental walk computed over blocks of cases on host threads (tests/split_oracle.py)
+    big = ([i for i in reversed(by_size) if kids.neutral[i]][:1] +
+           [i for i in reversed(by_size) if not kids.neutral[i]][:2])
+    with ThreadPoolExecutor(16) as pool:
+        for i in big:
+            say("oracle on the child of a", int(sizes[int(kids.parent[i])]), "node parent")
+            w_root, w_lvl, w_int, w_fit = split_oracle.incremental_f32(
+                parents.tree(int(kids.parent[i])), int(kids.point[i]), kids.donors.tree(i), cases.x, cases.y,
+                32, pool)
+            assert stop[i] == w_lvl, (i, stop[i], w_lvl)
+            assert info["interpreted_nodes"][i] == w_int
+            assert same_f32(roots[i], w_root).all()
+            assert fit[i] == w_fit or (math.isnan(fit[i]) and math.isnan(w_fit))
     # the paper's form: the mother co-evaluated alongside, no parent caches
     r2, f2, i2 = ctx.evaluate_incremental(ph, ch, g.GP_F32, 1024, kids.parent, kids.point, kids.donors.ops,
                                           kids.donors.offsets, coeval=True)
