@@ -73,7 +73,8 @@ def test_large_float_full_size_sampled(ctx):
     sizes = pop.sizes()
     order = np.argsort(sizes)
     rng = np.random.default_rng(0)
-    sample = list(order[:10]) + list(rng.choice(pop.n_trees, 5, replace=False)) + [int(order[-1])]
+    # the 10 smallest, 54 at random and the 16 largest (about 1e6 nodes) of the 1000
+    sample = list(order[:10]) + list(rng.choice(pop.n_trees, 54, replace=False)) + list(order[-16:])
 
     def check(i):
         with np.errstate(all="ignore"):
