@@ -734,7 +734,7 @@ BOOLW_SLOT = 128
 
 
 def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP, SLOT: int = BOOLW_SLOT) -> str:
-    assert SLOT & (SLOT - 1) == 0
+    assert SLOT & (SLOT - 1) == 0 and S <= 16       # the key's top bit is then 0 (see the handlers)
     names = []
     for p in ["TB", "TG", "X", "Y"] + [f"ST{d}" for d in range(S)] + [f"IN{j}" for j in range(NI)] + \
             [f"LD{j}" for j in range(NP)]:
@@ -751,11 +751,14 @@ def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP, SLOT
     a = L.append
     lab = lambda name: f".Lgw{S}_{name}_%="
 
-    def tail():
-        # the handler of key k starts at table + k * SLOT: one jump per word
+    def tail(advanced=False):
+        # the handler of key k starts at table + k * SLOT: one jump per word.
+        # advanced: the handler has already stepped OFF (in the wait state an
+        # s_movrels needs after M0 is written)
         a("  s_waitcnt lgkmcnt(0)")
         a(f"  s_mov_b32 {sr('INS')}, {sr('NXT')}")
-        a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
+        if not advanced:
+            a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
         a(f"  s_load_dword {sr('NXT')}, %[code], {sr('OFF')}")
         a(f"  s_and_b32 {sr('TG0')}, {sr('INS')}, 0x3ff")
         a(f"  s_lshl_b32 {sr('TG0')}, {sr('TG0')}, {SLOT.bit_length() - 1}")
@@ -875,42 +878,40 @@ def gen_bool_word(S: int = BOOLW_S, NI: int = BOOLW_NI, NP: int = BOOLW_NP, SLOT
         a(f"{slot}:")
         if not handlers[key]:
             a(f"  s_branch {lab('endjump') if key < 512 else lab('end')}")
+        # A word is key | payload << 10 and the key's top bit is 0 (d < 16), so
+        # INS >> 9 is twice the payload: M0 for the SGPR pair it names.
         elif mode == M_XX:               # f(input a, input b), a = payload & 2047, b = payload >> 11
-            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
-            a(f"  s_and_b32 {sr('T1')}, {sr('T0')}, 0x7ff")
-            a(f"  s_lshr_b32 {sr('T0')}, {sr('T0')}, 11")
-            a(f"  s_lshl_b32 m0, {sr('T1')}, 1")
-            a(f"  s_lshl_b32 {sr('T0')}, {sr('T0')}, 1")
+            a(f"  s_lshr_b32 {sr('T1')}, {sr('INS')}, 9")
+            a(f"  s_and_b32 m0, {sr('T1')}, 0xffe")
+            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 21")
             a(f"  s_movrels_b64 {sp('X')}, {sp('IN0')}")
-            a(f"  s_mov_b32 m0, {sr('T0')}")
-            a("  s_nop 0")
+            a(f"  s_lshl_b32 m0, {sr('T0')}, 1")
+            a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
             a(f"  s_movrels_b64 {sp('Y')}, {sp('IN0')}")
             a(f"  {OPS[f]} {sp(st)}, {sp('X')}, {sp('Y')}")
-            tail()
+            tail(advanced=True)
         elif mode == M_XS:               # f(input payload, slot d)
-            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
-            a(f"  s_lshl_b32 m0, {sr('T0')}, 1")
-            a("  s_nop 0")
+            a(f"  s_lshr_b32 m0, {sr('INS')}, 9")
+            a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
             a(f"  s_movrels_b64 {sp('X')}, {sp('IN0')}")
             a(f"  {OPS[f]} {sp(st)}, {sp('X')}, {sp(st)}")
-            tail()
+            tail(advanced=True)
         elif mode == M_SS:
             a(f"  {OPS[f]} {sp(st)}, {sp(st)}, {sp(f'ST{d + 1}')}")
             tail()
         elif mode == M_PUSH:
-            a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
-            a(f"  s_lshl_b32 m0, {sr('T0')}, 1")
-            a("  s_nop 0")
+            a(f"  s_lshr_b32 m0, {sr('INS')}, 9")
+            a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
             a(f"  s_movrels_b64 {sp(st)}, {sp('IN0')}")
-            tail()
+            tail(advanced=True)
         elif mode == M_LOAD:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
             a(f"  s_cmp_lt_u32 {sr('T0')}, {NP}")
             a(f"  s_cbranch_scc0 {lab(f'ld{key}')}")
-            a(f"  s_lshl_b32 m0, {sr('T0')}, 1")        # fetched when the chunk started
-            a("  s_nop 0")
+            a(f"  s_lshr_b32 m0, {sr('INS')}, 9")         # fetched when the chunk started
+            a(f"  s_add_u32 {sr('OFF')}, {sr('OFF')}, 4")
             a(f"  s_movrels_b64 {sp(st)}, {sp('LD0')}")
-            tail()
+            tail(advanced=True)
         elif mode == M_STORE:
             a(f"  s_lshr_b32 {sr('T0')}, {sr('INS')}, 10")
             row_address(sr('T0'), "%[rb_lo]", "%[rb_hi]")
