@@ -223,6 +223,33 @@ def oracle_incremental(pop, cases, kids, threads, cpu, gpu_fit=None, gpu_stop=No
     return out
 
 
+def add_counted(roofline, workload, chunk_nodes, variant, waves_per_cu, kernel_ms):
+    """Fill roofline's traffic and counter VALU rate from profiles/counters.json:
+    a record of the same workload, chunk size, variant and launch width, taken
+    with the current kernel sources.  Returns the file's contents, or None."""
+    try:
+        import hashlib
+        rec = json.load(open(os.path.join(ROOT, "profiles", "counters.json")))
+        h = hashlib.sha256()
+        for f in rec["kernel_source_files"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["kernel_source_sha256"]:
+            return None
+        for r in rec["records"]:
+            if (r.get("workload", rec["workload"]) == workload and r["chunk_nodes"] == chunk_nodes
+                    and r["variant"] == variant and r.get("waves_per_cu", 0) == waves_per_cu):
+                # read bytes by request size (FETCH_SIZE counts a 128-byte request as 64 bytes on this chip)
+                roofline["traffic"] = int(r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"])
+                roofline["traffic_GBps"] = round(roofline["traffic"] / (kernel_ms * 1e-3) / 1e9, 1)
+                roofline["valu_lane_op_frac_counters"] = round(
+                    r["valu_instructions_per_launch"] * 64 / (kernel_ms * 1e-3) / PEAK_FP32_LANE_OPS, 4)
+                roofline["counters_source"] = r.get("source")
+                return rec
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
 def measure_config(ctx, g, name, threads, cpu, cpu_budget_s, no_cpu=False):
     """One full-evaluation configuration on its own: autotuned batched launch
     (graph replay) against one launch per tree, the interpreter kernel's
@@ -265,6 +292,8 @@ def measure_config(ctx, g, name, threads, cpu, cpu_budget_s, no_cpu=False):
                         "kernel_ms": round(kernel_ms, 4), "achieved": round(achieved / 1e12, 4),
                         "peak": round(PEAK_FP32_LANE_OPS / 1e12, 2), "unit": "TFLOP/s",
                         "frac": round(achieved / PEAK_FP32_LANE_OPS, 4), "traffic": None}}
+    add_counted(out["roofline"], desc["workload"], info["chunk_nodes"], g.variant_names()[v], st["waves_per_cu"],
+                kernel_ms)
     if vtype == g.GP_BOOL:
         out["roofline"]["unit"] = "Tbit-op/s"
         out["roofline"]["note"] = ("one 64-bit word operation per function node evaluates 64 cases; achieved counts "
@@ -647,26 +676,8 @@ def main():
     if vtype == g.GP_BOOL:
         roofline["note"] = "Boolean: one 64-bit word op per function node per 64 cases"
     # HBM bytes from the committed counter runs, valid only for the kernel source they were taken with
-    counted = None
-    try:
-        import hashlib
-        rec = json.load(open(os.path.join(ROOT, "profiles", "counters.json")))
-        h = hashlib.sha256()
-        for f in rec["kernel_source_files"]:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        if h.hexdigest() == rec["kernel_source_sha256"] and rec["workload"] == desc["workload"]:
-            # one record per (chunk size, variant) the autotuner has been seen to pick
-            for r in rec["records"]:
-                if (r["chunk_nodes"] == final_info["chunk_nodes"] and r["variant"] == used.get("variant", tuned)
-                        and r.get("waves_per_cu", 0) == used.get("waves_per_cu", 0)):
-                    # read bytes by request size (FETCH_SIZE counts a 128-byte request as 64 bytes on this chip)
-                    roofline["traffic"] = int(r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"])
-                    roofline["traffic_GBps"] = round(roofline["traffic"] / (kernel_ms * 1e-3) / 1e9, 1)
-                    roofline["valu_lane_op_frac_counters"] = round(
-                        r["valu_instructions_per_launch"] * 64 / (kernel_ms * 1e-3) / PEAK_FP32_LANE_OPS, 4)
-                    counted = rec
-    except (OSError, KeyError, ValueError):
-        pass
+    counted = add_counted(roofline, desc["workload"], final_info["chunk_nodes"], used.get("variant", tuned),
+                          used.get("waves_per_cu", 0), kernel_ms)
 
     # the paper's own incremental form: the mother co-evaluated alongside each child (no parent caches)
     if kids is not None:
