@@ -159,6 +159,24 @@ def test_compiled_boolean_programs_match_oracle():
             assert np.array_equal(got, oracle.eval_bool(t, c.inputs))
 
 
+def test_word_keys_leave_bit_9_clear():
+    """The one-word Boolean loop reads twice an instruction's payload as
+    word >> 9, which holds while the key's top bit (bit 4 of the slot index)
+    is 0.  Populations are compiled for 10 slots, so every word's slot index
+    is below 10; checked here on programs as loaded, complete trees that need
+    every slot, and chunks cut by the slot limit."""
+    rng = np.random.default_rng(21)
+    trees = [gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 20001)), n_terms=6) for _ in range(20)]
+    full = gen.ramped_half_and_half(22, 10, min_depth=9, max_depth=11, n_terms=6, max_nodes=5000, vtype=gen.VT_BOOL)
+    trees += [full.tree(i) for i in range(full.n_trees)]
+    for t in trees:
+        for chunk_nodes in (7, 192, 1 << 30):
+            prog = g.inspect_program(t, g.GP_BOOL, 6, chunk_nodes, 10)
+            assert prog.max_stack <= 10
+            assert all((int(w) >> 9) & 1 == 0 for w in prog.code)
+            assert all((int(w) >> 5) & 31 < 10 for w in prog.code if int(w) & 0x3ff != 1 | (7 << 2))
+
+
 def test_stack_need_is_logarithmic():
     # Ershov order: a full binary tree of height h needs about h slots, a
     # random tree of 100k nodes far fewer than its height.
