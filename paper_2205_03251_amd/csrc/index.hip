@@ -128,14 +128,14 @@ __device__ __forceinline__ int64_t ix_scan_group(const IxParams& q, int l, int64
     return ix_scan_in(x, g, p, q.lvl[2 * l + 1], v);
 }
 
-// First position j >= s with E(j) < v, or -1.  Going up, every position from
-// s to the end of the current node's parent has been checked when a group
-// scan fails, so the search continues at the parent's next sibling; going
-// down, it takes the first child whose minimum is below v.
-__device__ __forceinline__ int64_t ix_first_below(const IxParams& q, int64_t s, int32_t v)
+// First position at or after entry p of level l whose E is below v, or -1
+// (p times kIxFan^l is the first position searched).  Going up, every
+// position from there to the end of the current node's parent has been
+// checked when a group scan fails, so the search continues at the parent's
+// next sibling; going down, it takes the first child whose minimum is below v.
+__device__ __forceinline__ int64_t ix_first_below_at(const IxParams& q, int l, int64_t p, int32_t v)
 {
-    int64_t p = s, hit = -1;
-    int l = 0;
+    int64_t hit = -1;
     for (;;) {
         if (p >= q.lvl[2 * l + 1]) return -1;
         hit = ix_scan_group(q, l, p, v);
@@ -147,6 +147,37 @@ __device__ __forceinline__ int64_t ix_first_below(const IxParams& q, int64_t s, 
     while (l > 0 && hit >= 0) {
         --l;
         hit = ix_scan_group(q, l, hit * kIxFan, v);
+    }
+    return hit;
+}
+
+// Last position at or before the end of entry p of level l whose E is at
+// most v, or -1: the mirror image of ix_first_below_at.
+__device__ __forceinline__ int64_t ix_last_at_most_at(const IxParams& q, int l, int64_t p, int32_t v)
+{
+    int64_t hit = -1;
+    int32_t x[kIxFan];
+    for (;;) {
+        if (p < 0) return -1;
+        const int64_t g = p & ~(int64_t)(kIxFan - 1);
+        ix_load_group(q, l, g, x);
+#pragma unroll
+        for (int i = 0; i < kIxFan; ++i)
+            if (g + i <= p && x[i] <= v) hit = g + i;
+        if (hit >= 0) break;
+        if (l == q.top) return -1;
+        p = g / kIxFan - 1;
+        ++l;
+    }
+    while (l > 0) {
+        --l;
+        const int64_t g = hit * kIxFan, len = q.lvl[2 * l + 1];
+        ix_load_group(q, l, g, x);
+        hit = -1;
+#pragma unroll
+        for (int i = 0; i < kIxFan; ++i)
+            if (g + i < len && x[i] <= v) hit = g + i;
+        if (hit < 0) return -1;
     }
     return hit;
 }
@@ -311,43 +342,275 @@ __global__ __launch_bounds__(256) void k_ix_check(IxParams q)
         [&](int64_t) {});
 }
 
-__global__ __launch_bounds__(256) void k_ix_ends(IxParams q)
+// Within one block: E of its positions less the block's offset (the scan's
+// el, which stays within +-kIxBlock), the minimum of each group of kIxFan
+// (one thread's positions) and of each kIxFan of those.
+struct alignas(16) IxBlockMins {
+    int16_t e0[kIxBlock];
+    int16_t m1[kIxBlock / kIxFan];
+    int16_t m2[kIxBlock / kIxFan / kIxFan];
+};
+static_assert(kIxBlock == kIxFan * kIxFan * kIxFan, "a block is three min-tree levels");
+
+// The kIxFan entries of a block level from g (a multiple of kIxFan), with
+// two 16-byte LDS reads.
+__device__ __forceinline__ void ix_lds_group(const int16_t* a, int g, int32_t (&x)[kIxFan])
 {
-    ix_positions(
-        q,
-        [&](int64_t k, int64_t t, int64_t s, int64_t e, uint8_t op, int32_t ek) {
-            int32_t r = -1;
-            if (q.valid[t]) {
-                if (!(op & 0x80)) {
-                    r = (int32_t)(k + 1 - s);
-                } else {
-                    const int64_t j = ix_first_below(q, k + 1, ek);
-                    if (j > k && j <= e) r = (int32_t)(j - s);
-                }
-            }
-            q.end[k] = r;
-        },
-        [&](int64_t k) { q.end[k] = -1; });
+    const int4* p = (const int4*)(a + g);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int4 w = p[i];
+        const int32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            x[8 * i + 2 * h] = (int32_t)(int16_t)(u[h] & 0xffff);
+            x[8 * i + 2 * h + 1] = u[h] >> 16;
+        }
+    }
 }
 
-__global__ __launch_bounds__(256) void k_ix_parents(IxParams q)
+// First index in [lo, g + kIxFan) whose entry is below v, or -1.
+__device__ __forceinline__ int ix_first_lt(const int32_t (&x)[kIxFan], int g, int lo, int32_t v)
 {
-    ix_positions(
-        q,
-        [&](int64_t k, int64_t t, int64_t s, int64_t e, uint8_t op, int32_t) {
-            if (!q.valid[t]) {
-                q.parent[k] = -1;
-                return;
+    int hit = -1;
+#pragma unroll
+    for (int i = kIxFan - 1; i >= 0; --i)
+        if (g + i >= lo && x[i] < v) hit = g + i;
+    return hit;
+}
+
+// Last index in [g, hi] whose entry is at most v, or -1.
+__device__ __forceinline__ int ix_last_le(const int32_t (&x)[kIxFan], int g, int hi, int32_t v)
+{
+    int hit = -1;
+#pragma unroll
+    for (int i = 0; i < kIxFan; ++i)
+        if (g + i <= hi && x[i] <= v) hit = g + i;
+    return hit;
+}
+
+// First block position whose E is below v after the group of position i
+// (that group already searched), or -1.
+__device__ __forceinline__ int ix_lds_first_below(const IxBlockMins& b, int i, int32_t v)
+{
+    int32_t x[kIxFan];
+    const int g1 = i / kIxFan;
+    ix_lds_group(b.m1, g1 & ~(kIxFan - 1), x);
+    int h1 = ix_first_lt(x, g1 & ~(kIxFan - 1), g1 + 1, v);
+    if (h1 < 0) {
+        ix_lds_group(b.m2, 0, x);
+        const int h2 = ix_first_lt(x, 0, g1 / kIxFan + 1, v);
+        if (h2 < 0) return -1;
+        ix_lds_group(b.m1, kIxFan * h2, x);
+        h1 = ix_first_lt(x, kIxFan * h2, 0, v);
+        if (h1 < 0) return -1;
+    }
+    ix_lds_group(b.e0, kIxFan * h1, x);
+    return ix_first_lt(x, kIxFan * h1, 0, v);
+}
+
+// Last block position whose E is at most v before the group of position i
+// (that group already searched), or -1.
+__device__ __forceinline__ int ix_lds_last_at_most(const IxBlockMins& b, int i, int32_t v)
+{
+    int32_t x[kIxFan];
+    const int g1 = i / kIxFan;
+    ix_lds_group(b.m1, g1 & ~(kIxFan - 1), x);
+    int h1 = ix_last_le(x, g1 & ~(kIxFan - 1), g1 - 1, v);
+    if (h1 < 0) {
+        ix_lds_group(b.m2, 0, x);
+        const int h2 = ix_last_le(x, 0, g1 / kIxFan - 1, v);
+        if (h2 < 0) return -1;
+        ix_lds_group(b.m1, kIxFan * h2, x);
+        h1 = ix_last_le(x, kIxFan * h2, kIxBlock, v);
+        if (h1 < 0) return -1;
+    }
+    ix_lds_group(b.e0, kIxFan * h1, x);
+    return ix_last_le(x, kIxFan * h1, kIxBlock, v);
+}
+
+// tfirst[b] = the tree holding the first position of scan block b (bsum,
+// free once the block offsets are summed, holds them).
+__global__ __launch_bounds__(256) void k_ix_tfirst(IxParams q, int32_t* tfirst, int64_t nb)
+{
+    for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < nb; b += (int64_t)gridDim.x * 256)
+        tfirst[b] = (int32_t)ix_tree_of(q, b * kIxBlock);
+}
+
+// The last tree t in [lo, hi] with offsets[t] <= k, or lo.
+__device__ __forceinline__ int64_t ix_tree_in(const IxParams& q, int64_t lo, int64_t hi, int64_t k)
+{
+    ++hi;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (q.offsets[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+constexpr int kIxQueue = 1024;            // block-leaving searches shared out per workgroup
+
+// A search that left the block, continued in the global min-tree from the
+// level whose entries are whole blocks (or the top): the end (parent = false)
+// or the parent of position k of tree [s, e), whose E is v.
+__device__ __forceinline__ int32_t ix_global_link(const IxParams& q, int64_t B, int64_t k, int64_t s, int64_t e,
+                                                  int32_t v, bool parent)
+{
+    const int L = q.top < 3 ? q.top : 3;
+    if (!parent) {
+        const int64_t J = ix_first_below_at(q, L, (B + kIxBlock) >> (4 * L), v);
+        return J > k && J <= e ? (int32_t)(J - s) : -1;
+    }
+    const int64_t P = B > 0 ? ix_last_at_most_at(q, L, (B >> (4 * L)) - 1, v) : -1;
+    return P >= s && P < k ? (int32_t)(P - s) : -1;
+}
+
+// Subtree end and parent of every position, one scan block per workgroup.
+// The end of function k is the first j > k with E(j) < E(k); its parent (any
+// non-root k) is the last i < k with E(i) <= E(k): the previous position when
+// that is a function (k is its first child), else the function whose first
+// child's subtree ends at k, since every position strictly between that
+// function and k has a larger E.  Both searches run first within the
+// thread's own positions, then in the block's minima in LDS.  Those that
+// leave the block (for a random walk about the square root of the block's
+// length, and they crowd the block's two ends) are queued and shared out over
+// all the workgroup's threads, which continue them in the global min-tree; a
+// thread whose search finds the queue full continues its own.  Results are
+// gathered in LDS and written out in whole lines: written per position, a
+// wave's stores are spread over 64 lines per array and reach memory one
+// partial line at a time.
+__global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfirst)
+{
+    __shared__ IxBlockMins bm;
+    __shared__ uint16_t queue[kIxQueue];      // block position | 1 << 12 for a parent search
+    __shared__ int32_t queued;
+    __shared__ int32_t res_end[kIxBlock], res_par[kIxBlock];   // written out in whole lines
+    const int tid = threadIdx.x;
+    const int64_t B = (int64_t)blockIdx.x * kIxBlock, k0 = B + (int64_t)tid * kIxFan;
+    const int64_t nb = (q.n + kIxBlock - 1) / kIxBlock;
+    const int64_t t_lo = tfirst[blockIdx.x], t_hi = blockIdx.x + 1 < nb ? tfirst[blockIdx.x + 1] : q.n_trees - 1;
+    uint32_t w[4];
+    ix_bytes16(q.ops, k0, q.n, w);
+    int32_t ev[kIxFan];
+    int32_t run = q.el[k0];                   // as the scan: positions past n step by 0
+#pragma unroll
+    for (int j = 0; j < kIxFan; ++j) {
+        ev[j] = run;
+        const uint32_t b = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
+        run += k0 + j < q.n ? ((b & 0x80u) ? 1 : -1) : 0;
+    }
+    int32_t mn = ev[0];
+#pragma unroll
+    for (int j = 1; j < kIxFan; ++j) mn = min(mn, ev[j]);
+#pragma unroll
+    for (int j = 0; j < kIxFan; j += 8)
+        *(int4*)&bm.e0[tid * kIxFan + j] =
+            make_int4((ev[j] & 0xffff) | (ev[j + 1] << 16), (ev[j + 2] & 0xffff) | (ev[j + 3] << 16),
+                      (ev[j + 4] & 0xffff) | (ev[j + 5] << 16), (ev[j + 6] & 0xffff) | (ev[j + 7] << 16));
+    bm.m1[tid] = (int16_t)mn;
+    if (tid == 0) queued = 0;
+    // both searches within the thread's own positions, four bits per
+    // position: the distance less one, 15 when the answer lies outside
+    uint64_t nxt = 0, prv = 0;
+#pragma unroll
+    for (int j = 0; j < kIxFan; ++j) {
+        uint32_t f = 15, b = 15;
+#pragma unroll
+        for (int m = kIxFan - 1; m > j; --m)
+            if (ev[m] < ev[j]) f = (uint32_t)(m - j - 1);
+#pragma unroll
+        for (int m = 0; m < j; ++m)
+            if (ev[m] <= ev[j]) b = (uint32_t)(j - m - 1);
+        nxt |= (uint64_t)f << (4 * j);
+        prv |= (uint64_t)b << (4 * j);
+    }
+    __syncthreads();
+    if (tid < kIxFan) {
+        int32_t x = bm.m1[tid * kIxFan];
+        for (int i = 1; i < kIxFan; ++i) x = min(x, (int32_t)bm.m1[tid * kIxFan + i]);
+        bm.m2[tid] = (int16_t)x;
+    }
+    __syncthreads();
+    const int32_t boff = q.boff[blockIdx.x];
+    if (k0 < q.n) {
+        int64_t t = ix_tree_in(q, t_lo, t_hi, k0);
+        int64_t s = q.offsets[t], e = q.offsets[t + 1];
+        bool ok = q.valid[t] != 0;
+        for (int j = 0; j < kIxFan; ++j) {
+            const int64_t k = k0 + j;
+            if (k >= q.n) break;
+            while (k >= e && t + 1 < q.n_trees) {
+                ++t;
+                s = q.offsets[t];
+                e = q.offsets[t + 1];
+                ok = q.valid[t] != 0;
             }
-            if (k == s) q.parent[k] = -1;
-            if ((op & 0x80) && k + 1 < e) {
-                const int32_t me = (int32_t)(k - s);
-                q.parent[k + 1] = me;
-                const int64_t r = s + q.end[k + 1];     // the right child
-                if (r > k + 1 && r < e) q.parent[r] = me;
+            int32_t r_end = -1, r_par = -1;
+            bool end_later = false, par_later = false;
+            if (ok && 0 <= s && s <= k && k < e && e <= q.n) {
+                const int i = tid * kIxFan + j;
+                const int32_t v = bm.e0[i];
+                const uint32_t wj = j < 8 ? (j < 4 ? w[0] : w[1]) : (j < 12 ? w[2] : w[3]);
+                const uint32_t f = (uint32_t)(nxt >> (4 * j)) & 15u, pb = (uint32_t)(prv >> (4 * j)) & 15u;
+                if (((wj >> (8 * (j & 3))) & 0x80u) == 0) {
+                    r_end = (int32_t)(k + 1 - s);
+                } else if (f < 15) {
+                    r_end = (int32_t)(k + 1 + f - s);
+                } else {
+                    const int m = ix_lds_first_below(bm, i, v);
+                    if (m >= 0) {
+                        r_end = B + m <= e ? (int32_t)(B + m - s) : -1;
+                    } else {
+                        const int slot = atomicAdd(&queued, 1);
+                        if (slot < kIxQueue) {
+                            queue[slot] = (uint16_t)i;
+                            end_later = true;
+                        } else {
+                            r_end = ix_global_link(q, B, k, s, e, v + boff, false);
+                        }
+                    }
+                }
+                if (k > s) {
+                    if (pb < 15) {
+                        r_par = (int32_t)(k - 1 - pb - s);
+                    } else {
+                        const int m = ix_lds_last_at_most(bm, i, v);
+                        if (m >= 0) {
+                            r_par = B + m >= s ? (int32_t)(B + m - s) : -1;
+                        } else {
+                            const int slot = atomicAdd(&queued, 1);
+                            if (slot < kIxQueue) {
+                                queue[slot] = (uint16_t)(i | (1 << 12));
+                                par_later = true;
+                            } else {
+                                r_par = ix_global_link(q, B, k, s, e, v + boff, true);
+                            }
+                        }
+                    }
+                }
             }
-        },
-        [&](int64_t k) { q.parent[k] = -1; });
+            if (!end_later) res_end[tid * kIxFan + j] = r_end;
+            if (!par_later) res_par[tid * kIxFan + j] = r_par;
+        }
+    }
+    __syncthreads();
+    const int nq = min(queued, kIxQueue);
+    for (int x = tid; x < nq; x += 256) {
+        const int i = queue[x] & (kIxBlock - 1);
+        const bool parent = (queue[x] >> 12) != 0;
+        const int64_t k = B + i;
+        const int64_t t = ix_tree_in(q, t_lo, t_hi, k);
+        const int32_t r = ix_global_link(q, B, k, q.offsets[t], q.offsets[t + 1], bm.e0[i] + boff, parent);
+        if (parent) res_par[i] = r;
+        else res_end[i] = r;
+    }
+    __syncthreads();
+    const int here = (int)min<int64_t>(kIxBlock, q.n - B);
+    for (int x = tid; x < here; x += 256) {
+        q.end[B + x] = res_end[x];
+        q.parent[B + x] = res_par[x];
+    }
 }
 
 // Strahler numbers, one level per pass.  A node's number is at least k + 1
@@ -493,8 +756,9 @@ hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t nb, const int6
     hipLaunchKernelGGL(k_ix_init, dim3((unsigned)tg), dim3(256), 0, s, q);
     const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
     hipLaunchKernelGGL(k_ix_check, dim3((unsigned)pg), dim3(256), 0, s, q);
-    hipLaunchKernelGGL(k_ix_ends, dim3((unsigned)pg), dim3(256), 0, s, q);
-    hipLaunchKernelGGL(k_ix_parents, dim3((unsigned)pg), dim3(256), 0, s, q);
+    const int64_t bg = std::min<int64_t>(65536, std::max<int64_t>(1, (nb + 255) / 256));
+    hipLaunchKernelGGL(k_ix_tfirst, dim3((unsigned)bg), dim3(256), 0, s, q, bsum, nb);
+    hipLaunchKernelGGL(k_ix_links, dim3((unsigned)pg), dim3(256), 0, s, q, (const int32_t*)bsum);
     return hipGetLastError();
 }
 
