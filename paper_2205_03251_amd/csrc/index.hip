@@ -471,25 +471,28 @@ __device__ __forceinline__ int32_t ix_global_link(const IxParams& q, int64_t B, 
 // non-root k) is the last i < k with E(i) <= E(k): the previous position when
 // that is a function (k is its first child), else the function whose first
 // child's subtree ends at k, since every position strictly between that
-// function and k has a larger E.  Both searches run first within the
-// thread's own positions, then in the block's minima in LDS.  Those that
-// leave the block (for a random walk about the square root of the block's
-// length, and they crowd the block's two ends) are queued and shared out over
-// all the workgroup's threads, which continue them in the global min-tree; a
-// thread whose search finds the queue full continues its own.  Results are
-// gathered in LDS and written out in whole lines: written per position, a
-// wave's stores are spread over 64 lines per array and reach memory one
-// partial line at a time.
+// function and k has a larger E.  Ends, then parents: each thread settles
+// what its own positions answer (in registers); the searches that go past
+// them are listed and shared out over the workgroup, which runs them in the
+// block's minima in LDS with every lane busy (run where they arise, a wave
+// would step through every search any of its lanes needs); those that leave
+// the block (for a random walk about the square root of the block's length)
+// are queued and continued in the global min-tree, and a search that finds
+// the queue full continues at once.  Results are gathered in LDS and written
+// out in whole lines: written per position, a wave's stores spread over 64
+// lines and reach memory one partial line at a time.
 __global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfirst)
 {
     __shared__ IxBlockMins bm;
-    __shared__ uint16_t queue[kIxQueue];      // block position | 1 << 12 for a parent search
-    __shared__ int32_t queued;
-    __shared__ int32_t res_end[kIxBlock], res_par[kIxBlock];   // written out in whole lines
+    __shared__ uint16_t work[kIxBlock];       // block positions searched in the block minima
+    __shared__ uint16_t queue[kIxQueue];      // block positions searched in the global min-tree
+    __shared__ int32_t res[kIxBlock];         // this pass's results, tree-local
+    __shared__ int32_t n_work, queued;
     const int tid = threadIdx.x;
     const int64_t B = (int64_t)blockIdx.x * kIxBlock, k0 = B + (int64_t)tid * kIxFan;
     const int64_t nb = (q.n + kIxBlock - 1) / kIxBlock;
     const int64_t t_lo = tfirst[blockIdx.x], t_hi = blockIdx.x + 1 < nb ? tfirst[blockIdx.x + 1] : q.n_trees - 1;
+    const int here = (int)min<int64_t>(kIxBlock, q.n - B);
     uint32_t w[4];
     ix_bytes16(q.ops, k0, q.n, w);
     int32_t ev[kIxFan];
@@ -509,7 +512,6 @@ __global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfi
             make_int4((ev[j] & 0xffff) | (ev[j + 1] << 16), (ev[j + 2] & 0xffff) | (ev[j + 3] << 16),
                       (ev[j + 4] & 0xffff) | (ev[j + 5] << 16), (ev[j + 6] & 0xffff) | (ev[j + 7] << 16));
     bm.m1[tid] = (int16_t)mn;
-    if (tid == 0) queued = 0;
     // both searches within the thread's own positions, four bits per
     // position: the distance less one, 15 when the answer lies outside
     uint64_t nxt = 0, prv = 0;
@@ -531,85 +533,71 @@ __global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfi
         for (int i = 1; i < kIxFan; ++i) x = min(x, (int32_t)bm.m1[tid * kIxFan + i]);
         bm.m2[tid] = (int16_t)x;
     }
-    __syncthreads();
     const int32_t boff = q.boff[blockIdx.x];
-    if (k0 < q.n) {
-        int64_t t = ix_tree_in(q, t_lo, t_hi, k0);
-        int64_t s = q.offsets[t], e = q.offsets[t + 1];
-        bool ok = q.valid[t] != 0;
-        for (int j = 0; j < kIxFan; ++j) {
-            const int64_t k = k0 + j;
-            if (k >= q.n) break;
-            while (k >= e && t + 1 < q.n_trees) {
-                ++t;
-                s = q.offsets[t];
-                e = q.offsets[t + 1];
-                ok = q.valid[t] != 0;
-            }
-            int32_t r_end = -1, r_par = -1;
-            bool end_later = false, par_later = false;
-            if (ok && 0 <= s && s <= k && k < e && e <= q.n) {
-                const int i = tid * kIxFan + j;
-                const int32_t v = bm.e0[i];
-                const uint32_t wj = j < 8 ? (j < 4 ? w[0] : w[1]) : (j < 12 ? w[2] : w[3]);
-                const uint32_t f = (uint32_t)(nxt >> (4 * j)) & 15u, pb = (uint32_t)(prv >> (4 * j)) & 15u;
-                if (((wj >> (8 * (j & 3))) & 0x80u) == 0) {
-                    r_end = (int32_t)(k + 1 - s);
-                } else if (f < 15) {
-                    r_end = (int32_t)(k + 1 + f - s);
-                } else {
-                    const int m = ix_lds_first_below(bm, i, v);
-                    if (m >= 0) {
-                        r_end = B + m <= e ? (int32_t)(B + m - s) : -1;
-                    } else {
-                        const int slot = atomicAdd(&queued, 1);
-                        if (slot < kIxQueue) {
-                            queue[slot] = (uint16_t)i;
-                            end_later = true;
-                        } else {
-                            r_end = ix_global_link(q, B, k, s, e, v + boff, false);
-                        }
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool parent = pass == 1;
+        if (tid == 0) n_work = queued = 0;
+        __syncthreads();
+        if (k0 < q.n) {
+            const uint64_t near = parent ? prv : nxt;
+            int64_t t = ix_tree_in(q, t_lo, t_hi, k0);
+            int64_t s = q.offsets[t], e = q.offsets[t + 1];
+            bool ok = q.valid[t] != 0;
+            for (int j = 0; j < kIxFan; ++j) {
+                const int64_t k = k0 + j;
+                if (k >= q.n) break;
+                while (k >= e && t + 1 < q.n_trees) {
+                    ++t;
+                    s = q.offsets[t];
+                    e = q.offsets[t + 1];
+                    ok = q.valid[t] != 0;
+                }
+                int32_t r = -1;
+                if (ok && 0 <= s && s <= k && k < e && e <= q.n) {
+                    const uint32_t d = (uint32_t)(near >> (4 * j)) & 15u;
+                    const uint32_t wj = j < 8 ? (j < 4 ? w[0] : w[1]) : (j < 12 ? w[2] : w[3]);
+                    const bool fn = ((wj >> (8 * (j & 3))) & 0x80u) != 0;
+                    if (!parent) {
+                        if (!fn) r = (int32_t)(k + 1 - s);
+                        else if (d < 15) r = (int32_t)(k + 1 + d - s);
+                        else work[atomicAdd(&n_work, 1)] = (uint16_t)(tid * kIxFan + j);
+                    } else if (k > s) {
+                        if (d < 15) r = (int32_t)(k - 1 - d - s);
+                        else work[atomicAdd(&n_work, 1)] = (uint16_t)(tid * kIxFan + j);
                     }
                 }
-                if (k > s) {
-                    if (pb < 15) {
-                        r_par = (int32_t)(k - 1 - pb - s);
-                    } else {
-                        const int m = ix_lds_last_at_most(bm, i, v);
-                        if (m >= 0) {
-                            r_par = B + m >= s ? (int32_t)(B + m - s) : -1;
-                        } else {
-                            const int slot = atomicAdd(&queued, 1);
-                            if (slot < kIxQueue) {
-                                queue[slot] = (uint16_t)(i | (1 << 12));
-                                par_later = true;
-                            } else {
-                                r_par = ix_global_link(q, B, k, s, e, v + boff, true);
-                            }
-                        }
-                    }
-                }
+                res[tid * kIxFan + j] = r;          // a listed search overwrites it
             }
-            if (!end_later) res_end[tid * kIxFan + j] = r_end;
-            if (!par_later) res_par[tid * kIxFan + j] = r_par;
         }
-    }
-    __syncthreads();
-    const int nq = min(queued, kIxQueue);
-    for (int x = tid; x < nq; x += 256) {
-        const int i = queue[x] & (kIxBlock - 1);
-        const bool parent = (queue[x] >> 12) != 0;
-        const int64_t k = B + i;
-        const int64_t t = ix_tree_in(q, t_lo, t_hi, k);
-        const int32_t r = ix_global_link(q, B, k, q.offsets[t], q.offsets[t + 1], bm.e0[i] + boff, parent);
-        if (parent) res_par[i] = r;
-        else res_end[i] = r;
-    }
-    __syncthreads();
-    const int here = (int)min<int64_t>(kIxBlock, q.n - B);
-    for (int x = tid; x < here; x += 256) {
-        q.end[B + x] = res_end[x];
-        q.parent[B + x] = res_par[x];
+        __syncthreads();
+        const int nw = n_work;
+        for (int x = tid; x < nw; x += 256) {
+            const int i = work[x];
+            const int64_t k = B + i;
+            const int32_t v = bm.e0[i];
+            const int m = parent ? ix_lds_last_at_most(bm, i, v) : ix_lds_first_below(bm, i, v);
+            const int64_t t = ix_tree_in(q, t_lo, t_hi, k);
+            const int64_t s = q.offsets[t], e = q.offsets[t + 1];
+            if (m >= 0) {
+                const int64_t J = B + m;
+                res[i] = (parent ? J >= s : J <= e) ? (int32_t)(J - s) : -1;
+            } else {
+                const int slot = atomicAdd(&queued, 1);
+                if (slot < kIxQueue) queue[slot] = (uint16_t)i;
+                else res[i] = ix_global_link(q, B, k, s, e, v + boff, parent);
+            }
+        }
+        __syncthreads();
+        const int nq = min(queued, kIxQueue);
+        for (int x = tid; x < nq; x += 256) {
+            const int i = queue[x];
+            const int64_t k = B + i;
+            const int64_t t = ix_tree_in(q, t_lo, t_hi, k);
+            res[i] = ix_global_link(q, B, k, q.offsets[t], q.offsets[t + 1], bm.e0[i] + boff, parent);
+        }
+        __syncthreads();
+        int32_t* out = parent ? q.parent : q.end;
+        for (int x = tid; x < here; x += 256) out[B + x] = res[x];
     }
 }
 
