@@ -369,24 +369,24 @@ __device__ __forceinline__ void ix_lds_group(const int16_t* a, int g, int32_t (&
     }
 }
 
-// First index in [lo, g + kIxFan) whose entry is below v, or -1.
-__device__ __forceinline__ int ix_first_lt(const int32_t (&x)[kIxFan], int g, int lo, int32_t v)
+// First index in [g + from, g + kIxFan) whose entry is below v, or -1.
+__device__ __forceinline__ int ix_first_lt(const int32_t (&x)[kIxFan], int g, int from, int32_t v)
 {
-    int hit = -1;
+    int hit = kIxFan;
 #pragma unroll
     for (int i = kIxFan - 1; i >= 0; --i)
-        if (g + i >= lo && x[i] < v) hit = g + i;
-    return hit;
+        if (i >= from && x[i] < v) hit = i;
+    return hit < kIxFan ? g + hit : -1;
 }
 
-// Last index in [g, hi] whose entry is at most v, or -1.
-__device__ __forceinline__ int ix_last_le(const int32_t (&x)[kIxFan], int g, int hi, int32_t v)
+// Last index in [g, g + upto] whose entry is at most v, or -1.
+__device__ __forceinline__ int ix_last_le(const int32_t (&x)[kIxFan], int g, int upto, int32_t v)
 {
     int hit = -1;
 #pragma unroll
     for (int i = 0; i < kIxFan; ++i)
-        if (g + i <= hi && x[i] <= v) hit = g + i;
-    return hit;
+        if (i <= upto && x[i] <= v) hit = i;
+    return hit >= 0 ? g + hit : -1;
 }
 
 // First block position whose E is below v after the group of position i
@@ -396,7 +396,7 @@ __device__ __forceinline__ int ix_lds_first_below(const IxBlockMins& b, int i, i
     int32_t x[kIxFan];
     const int g1 = i / kIxFan;
     ix_lds_group(b.m1, g1 & ~(kIxFan - 1), x);
-    int h1 = ix_first_lt(x, g1 & ~(kIxFan - 1), g1 + 1, v);
+    int h1 = ix_first_lt(x, g1 & ~(kIxFan - 1), (g1 & (kIxFan - 1)) + 1, v);
     if (h1 < 0) {
         ix_lds_group(b.m2, 0, x);
         const int h2 = ix_first_lt(x, 0, g1 / kIxFan + 1, v);
@@ -416,17 +416,17 @@ __device__ __forceinline__ int ix_lds_last_at_most(const IxBlockMins& b, int i, 
     int32_t x[kIxFan];
     const int g1 = i / kIxFan;
     ix_lds_group(b.m1, g1 & ~(kIxFan - 1), x);
-    int h1 = ix_last_le(x, g1 & ~(kIxFan - 1), g1 - 1, v);
+    int h1 = ix_last_le(x, g1 & ~(kIxFan - 1), (g1 & (kIxFan - 1)) - 1, v);
     if (h1 < 0) {
         ix_lds_group(b.m2, 0, x);
         const int h2 = ix_last_le(x, 0, g1 / kIxFan - 1, v);
         if (h2 < 0) return -1;
         ix_lds_group(b.m1, kIxFan * h2, x);
-        h1 = ix_last_le(x, kIxFan * h2, kIxBlock, v);
+        h1 = ix_last_le(x, kIxFan * h2, kIxFan - 1, v);
         if (h1 < 0) return -1;
     }
     ix_lds_group(b.e0, kIxFan * h1, x);
-    return ix_last_le(x, kIxFan * h1, kIxBlock, v);
+    return ix_last_le(x, kIxFan * h1, kIxFan - 1, v);
 }
 
 // tfirst[b] = the tree holding the first position of scan block b (bsum,
@@ -543,7 +543,27 @@ __global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfi
             int64_t t = ix_tree_in(q, t_lo, t_hi, k0);
             int64_t s = q.offsets[t], e = q.offsets[t + 1];
             bool ok = q.valid[t] != 0;
-            for (int j = 0; j < kIxFan; ++j) {
+            const bool one_tree = ok && 0 <= s && s <= k0 && k0 + kIxFan <= e && e <= q.n;
+            if (one_tree) {
+                // the common case: all 16 positions in one valid tree
+                const int32_t base = (int32_t)(k0 - s);
+#pragma unroll
+                for (int j = 0; j < kIxFan; ++j) {
+                    const uint32_t d = (uint32_t)(near >> (4 * j)) & 15u;
+                    const bool fn = ((w[j >> 2] >> (8 * (j & 3))) & 0x80u) != 0;
+                    int32_t r = -1;
+                    if (!parent) {
+                        if (!fn) r = base + j + 1;
+                        else if (d < 15) r = base + j + 1 + (int32_t)d;
+                        else work[atomicAdd(&n_work, 1)] = (uint16_t)(tid * kIxFan + j);
+                    } else if (base + j > 0) {
+                        if (d < 15) r = base + j - 1 - (int32_t)d;
+                        else work[atomicAdd(&n_work, 1)] = (uint16_t)(tid * kIxFan + j);
+                    }
+                    res[tid * kIxFan + j] = r;
+                }
+            }
+            for (int j = 0; j < kIxFan && !one_tree; ++j) {
                 const int64_t k = k0 + j;
                 if (k >= q.n) break;
                 while (k >= e && t + 1 < q.n_trees) {
@@ -591,9 +611,8 @@ __global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfi
         const int nq = min(queued, kIxQueue);
         for (int x = tid; x < nq; x += 256) {
             const int i = queue[x];
-            const int64_t k = B + i;
-            const int64_t t = ix_tree_in(q, t_lo, t_hi, k);
-            res[i] = ix_global_link(q, B, k, q.offsets[t], q.offsets[t + 1], bm.e0[i] + boff, parent);
+            const int64_t t = ix_tree_in(q, t_lo, t_hi, B + i);
+            res[i] = ix_global_link(q, B, B + i, q.offsets[t], q.offsets[t + 1], bm.e0[i] + boff, parent);
         }
         __syncthreads();
         int32_t* out = parent ? q.parent : q.end;
