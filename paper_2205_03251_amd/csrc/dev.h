@@ -228,8 +228,9 @@ hipError_t ix_static_scratch(int device, int32_t** out);
 hipError_t launch_strahler_init(const IxParams& q, hipStream_t s);
 // One level: raises to level + 1 every node with a function below it whose children are both at level or
 // more; sets *any when there is such a function.  Reuses el and boff.
-hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, int64_t n_blocks, int32_t* any,
-                                 hipStream_t s);
+// Pass `level` of the Strahler numbers; afterwards boff[n_blocks] holds the
+// number of functions it marked (none: the numbers are final).
+hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, int64_t n_blocks, hipStream_t s);
 hipError_t launch_coeval(int vtype, const CoParams& p, int64_t n_children, hipStream_t s);
 // One generation's random choices (Section 6.3): per slot i, the winners of
 // tournaments (i, g, 0) and (i, g, 1) over fit, the crossover point in the

@@ -638,9 +638,9 @@ __global__ __launch_bounds__(256) void k_ix_sinit(IxParams q)
 
 // Positions of this thread's 16 that hold a function still at level: only
 // they can be marked or raised, and a thread with none skips the tree lookup.
-__device__ __forceinline__ uint32_t ix_at_level(const IxParams& q, int64_t k0, int level)
+__device__ __forceinline__ uint32_t ix_at_level(const IxParams& q, int64_t k0, int level, uint32_t (&sn)[4])
 {
-    uint32_t ops[4], sn[4];
+    uint32_t ops[4];
     ix_bytes16(q.ops, k0, q.n, ops);
     ix_bytes16(q.sn, k0, q.n, sn);
     uint32_t m = 0;
@@ -651,14 +651,53 @@ __device__ __forceinline__ uint32_t ix_at_level(const IxParams& q, int64_t k0, i
     return m;
 }
 
-// For each set bit j of m, body(k0 + j, tree start, tree end), walking the
-// trees from the one holding k0.
-template <class Body>
-__device__ __forceinline__ void ix_each(const IxParams& q, int64_t k0, uint32_t m, Body body)
+__device__ __forceinline__ uint32_t ix_at_level(const IxParams& q, int64_t k0, int level)
 {
-    if (!m) return;
-    int64_t t = ix_tree_of(q, k0);
-    int64_t s = q.offsets[t], e = q.offsets[t + 1];
+    uint32_t sn[4];
+    return ix_at_level(q, k0, level, sn);
+}
+
+// Trees [lo, hi] that scan block b may hold, for the Strahler passes: the
+// per-block first trees are copied into the global min-tree's storage, free
+// once ends and parents are written (with no min-tree levels the population
+// has at most kIxFan positions, one block).
+__device__ __forceinline__ void ix_block_trees(const IxParams& q, int64_t b, int64_t& lo, int64_t& hi)
+{
+    const int64_t nb = (q.n + kIxBlock - 1) / kIxBlock;
+    if (q.top == 0) {
+        lo = 0;
+        hi = q.n_trees - 1;
+        return;
+    }
+    lo = q.seg[b];
+    hi = b + 1 < nb ? q.seg[b + 1] : q.n_trees - 1;
+}
+
+// end[k0 .. k0 + 16), with four 16-byte loads where aligned (k0 + 16 <= n).
+__device__ __forceinline__ void ix_ends16(const IxParams& q, int64_t k0, int32_t (&en)[kIxFan])
+{
+    if ((((uintptr_t)(q.end + k0)) & 15) == 0) {
+        const int4* p = (const int4*)(q.end + k0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int4 v = p[i];
+            en[4 * i] = v.x;
+            en[4 * i + 1] = v.y;
+            en[4 * i + 2] = v.z;
+            en[4 * i + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kIxFan; ++i) en[i] = q.end[k0 + i];
+    }
+}
+
+// For each set bit j of m, body(k0 + j, tree start, tree end), walking the
+// trees from tree t = [s, e), the one holding k0.
+template <class Body>
+__device__ __forceinline__ void ix_each_from(const IxParams& q, int64_t k0, uint32_t m, int64_t t, int64_t s, int64_t e,
+                                             Body body)
+{
     while (m) {
         const int j = __ffs(m) - 1;
         m &= m - 1;
@@ -672,19 +711,49 @@ __device__ __forceinline__ void ix_each(const IxParams& q, int64_t k0, uint32_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_ix_sflag(IxParams q, int level, int32_t* bsum, int32_t* any)
+__global__ __launch_bounds__(256) void k_ix_sflag(IxParams q, int level, int32_t* bsum)
 {
     __shared__ int32_t wtot[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t base = ((int64_t)blockIdx.x * 256 + tid) * 16;
     uint32_t bits = 0;
     // a function with both children at level or more is itself at level already
-    ix_each(q, base, base < q.n ? ix_at_level(q, base, level) : 0u, [&](int64_t k, int64_t s, int64_t e) {
-        if (k + 1 < e) {
-            const int64_t r = s + q.end[k + 1];                      // the right child
-            if (r > k + 1 && r < e && q.sn[k + 1] >= level && q.sn[r] >= level) bits |= 1u << (int)(k - base);
+    uint32_t snw[4];
+    const uint32_t m = base < q.n ? ix_at_level(q, base, level, snw) : 0u;
+    int64_t t = 0, s = 0, e = 0;
+    if (m) {
+        int64_t lo, hi;
+        ix_block_trees(q, blockIdx.x, lo, hi);
+        t = ix_tree_in(q, lo, hi, base);
+        s = q.offsets[t];
+        e = q.offsets[t + 1];
+    }
+    if (m && 0 <= s && s <= base && base + kIxFan < e && e <= q.n) {
+        // every position and its first child in one tree: the ends and the
+        // right children's numbers are loaded all at once
+        int32_t en[kIxFan];
+        ix_ends16(q, base, en);                                          // end[base .. base + 15]
+        const int32_t en16 = q.end[base + kIxFan];
+        const uint32_t sn16 = q.sn[base + kIxFan];
+        uint32_t snr[kIxFan];
+#pragma unroll
+        for (int j = 0; j < kIxFan; ++j) {
+            const int64_t r = s + (j + 1 < kIxFan ? en[j + 1] : en16);  // the right child of base + j
+            snr[j] = ((m >> j) & 1u) && r > base + j + 1 && r < e ? q.sn[r] : 0u;
         }
-    });
+#pragma unroll
+        for (int j = 0; j < kIxFan; ++j) {
+            const uint32_t sl = j + 1 < kIxFan ? (snw[(j + 1) >> 2] >> (8 * ((j + 1) & 3))) & 0xffu : sn16;
+            if (((m >> j) & 1u) && sl >= (uint32_t)level && snr[j] >= (uint32_t)level) bits |= 1u << j;
+        }
+    } else {
+        ix_each_from(q, base, m, t, s, e, [&](int64_t k, int64_t s, int64_t e) {
+            if (k + 1 < e) {
+                const int64_t r = s + q.end[k + 1];                  // the right child
+                if (r > k + 1 && r < e && q.sn[k + 1] >= level && q.sn[r] >= level) bits |= 1u << (int)(k - base);
+            }
+        });
+    }
     // past the first levels most blocks mark nothing: their prefix is left
     // unwritten and read as zero
     if (!__syncthreads_or(bits != 0)) {
@@ -711,7 +780,6 @@ __global__ __launch_bounds__(256) void k_ix_sflag(IxParams q, int level, int32_t
     int4* dst = (int4*)(q.el + base);
     for (int j = 0; j < 4; ++j) dst[j] = make_int4(pre[4 * j], pre[4 * j + 1], pre[4 * j + 2], pre[4 * j + 3]);
     if (tid == 255) bsum[blockIdx.x] = excl + run;
-    if (bits) atomicOr(any, 1);
 }
 
 // Marked functions before position x (x <= n): a block that marked none
@@ -722,12 +790,53 @@ __device__ __forceinline__ int32_t ix_count_before(const IxParams& q, int64_t x)
     return q.bempty[b] ? q.boff[b] : ix_e(q, x);
 }
 
+// DENSE: the first pass, where every function starts at the level, so each
+// thread has several nodes to test; later passes test few nodes per thread
+// and run the plain walk (the batched loads' registers would cost them
+// resident waves).
+template <bool DENSE>
 __global__ __launch_bounds__(256) void k_ix_supd(IxParams q, int level)
 {
     const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
     if (k0 >= q.n) return;
     // only a node at level can rise
-    ix_each(q, k0, ix_at_level(q, k0, level), [&](int64_t k, int64_t s, int64_t e) {
+    uint32_t snw[4];
+    const uint32_t m = ix_at_level(q, k0, level, snw);
+    if (!m) return;
+    int64_t lo, hi;
+    ix_block_trees(q, k0 / kIxBlock, lo, hi);
+    const int64_t t = ix_tree_in(q, lo, hi, k0);
+    const int64_t s = q.offsets[t], e = q.offsets[t + 1];
+    if (DENSE && 0 <= s && s <= k0 && k0 + kIxFan <= e && e <= q.n) {
+        // all 16 positions in one tree: their ends, then the counts at the
+        // subtree ends, loaded all at once; the numbers written back together
+        int32_t en[kIxFan];
+        ix_ends16(q, k0, en);
+        int32_t cx[kIxFan];
+#pragma unroll
+        for (int j = 0; j < kIxFan; ++j) {
+            const int64_t x = s + en[j];                                 // the subtree is [k0 + j, x)
+            cx[j] = ((m >> j) & 1u) && x > k0 + j && x <= e ? ix_count_before(q, x) : INT32_MIN;
+        }
+        uint32_t raised = 0;
+#pragma unroll
+        for (int j = 0; j < kIxFan; ++j)
+            if (cx[j] != INT32_MIN && cx[j] > ix_count_before(q, k0 + j)) raised |= 1u << j;
+        if (!raised) return;
+#pragma unroll
+        for (int j = 0; j < kIxFan; ++j)
+            if ((raised >> j) & 1u)
+                snw[j >> 2] = (snw[j >> 2] & ~(0xffu << (8 * (j & 3)))) | ((uint32_t)(level + 1) << (8 * (j & 3)));
+        if ((((uintptr_t)(q.sn + k0)) & 15) == 0) {
+            *(uint4*)(q.sn + k0) = make_uint4(snw[0], snw[1], snw[2], snw[3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kIxFan; ++j)
+                if ((raised >> j) & 1u) q.sn[k0 + j] = (uint8_t)(level + 1);
+        }
+        return;
+    }
+    ix_each_from(q, k0, m, t, s, e, [&](int64_t k, int64_t s, int64_t e) {
         const int64_t x = s + q.end[k];                              // the subtree is [k, x)
         if (x > k && x <= e && ix_count_before(q, x) > ix_count_before(q, k)) q.sn[k] = (uint8_t)(level + 1);
     });
@@ -735,18 +844,24 @@ __global__ __launch_bounds__(256) void k_ix_supd(IxParams q, int level)
 
 hipError_t launch_strahler_init(const IxParams& q, hipStream_t s)
 {
+    if (q.top > 0) {
+        const int64_t nb = (q.n + kIxBlock - 1) / kIxBlock;
+        const int64_t bg = std::min<int64_t>(65536, std::max<int64_t>(1, (nb + 255) / 256));
+        hipLaunchKernelGGL(k_ix_tfirst, dim3((unsigned)bg), dim3(256), 0, s, q, q.seg, nb);
+    }
     const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
     hipLaunchKernelGGL(k_ix_sinit, dim3((unsigned)pg), dim3(256), 0, s, q);
     return hipGetLastError();
 }
 
-hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, int64_t nb, int32_t* any,
+hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, int64_t nb,
                                  hipStream_t s)
 {
     const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
-    hipLaunchKernelGGL(k_ix_sflag, dim3((unsigned)nb), dim3(256), 0, s, q, level, bsum, any);
+    hipLaunchKernelGGL(k_ix_sflag, dim3((unsigned)nb), dim3(256), 0, s, q, level, bsum);
     hipLaunchKernelGGL(k_ix_top, dim3(1), dim3(1024), 0, s, q, (const int32_t*)bsum, nb);
-    hipLaunchKernelGGL(k_ix_supd, dim3((unsigned)pg), dim3(256), 0, s, q, level);
+    if (level == 2) hipLaunchKernelGGL(k_ix_supd<true>, dim3((unsigned)pg), dim3(256), 0, s, q, level);
+    else hipLaunchKernelGGL(k_ix_supd<false>, dim3((unsigned)pg), dim3(256), 0, s, q, level);
     return hipGetLastError();
 }
 

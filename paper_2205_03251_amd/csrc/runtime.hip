@@ -2496,7 +2496,7 @@ static int64_t ix_levels(int64_t n, IxParams& q, int64_t (&len)[kIxMaxLevels])
 
 // The index kernels on ctx's stream with the given scratch (el, boff, bsum,
 // seg sized for q.n; flag 2 words; bempty n_blocks + 1 bytes), then the host
-// waits for the offsets flag (and, per Strahler level, for the level's flag).
+// waits for the offsets flag (and, per Strahler level, for the level's count).
 // Flags are cleared by a fill kernel.  Allocates nothing.
 static int ix_run(Ctx* ctx, IxParams& q, int32_t* bsum, int32_t* flag, int64_t nb, const int64_t* len,
                   double* device_ms, hipStream_t st)
@@ -2508,14 +2508,13 @@ static int ix_run(Ctx* ctx, IxParams& q, int32_t* bsum, int32_t* flag, int64_t n
     if (q.sn) HIPC(ctx, launch_fill_u8(q.bempty, nb + 1, 1, st));      // block nb holds only E(n)
     HIPC(ctx, launch_index(q, bsum, nb, len, st));
     if (q.sn) {
-        // one pass per level, while some function has two children at the current level
-        int32_t* any = flag + 1;
+        // one pass per level, while some function has two children at the
+        // current level (the pass leaves their number in boff[nb])
         HIPC(ctx, launch_strahler_init(q, st));
         for (int level = 2; level < 64; ++level) {          // the initial numbers settle level 1
-            HIPC(ctx, launch_fill_i32(any, 1, 0, st));
-            HIPC(ctx, launch_strahler_level(q, level, bsum, nb, any, st));
+            HIPC(ctx, launch_strahler_level(q, level, bsum, nb, st));
             int32_t more = 0;
-            HIPC(ctx, hipMemcpyAsync(&more, any, 4, hipMemcpyDeviceToHost, st));
+            HIPC(ctx, hipMemcpyAsync(&more, q.boff + nb, 4, hipMemcpyDeviceToHost, st));
             HIPC(ctx, hipStreamSynchronize(st));
             if (!more) break;
         }
