@@ -223,18 +223,26 @@ __global__ __launch_bounds__(256) void k_ix_scan(IxParams q, int32_t* bsum)
     if (tid == 255) bsum[blockIdx.x] = excl + run;
 }
 
-// Exclusive prefix of the block totals (one workgroup); boff[nb] = E(n), and
-// el[nb * kIxBlock] = 0 so that E(n) = el[n] + boff[n / kIxBlock] also when n
-// is a multiple of the block.
-__global__ __launch_bounds__(1024) void k_ix_top(IxParams q, const int32_t* bsum, int64_t nb)
+// Exclusive prefix of the block totals bsum[0 .. nb) into boff, boff[nb] =
+// their sum (E(n) after the position scan), and el[nb * kIxBlock] = 0 so that
+// E(n) = el[n] + boff[n / kIxBlock] also when n is a multiple of the block.
+// Three launches: the prefix within each group of kIxBlock totals (a
+// workgroup per group, 16 a thread), whose sum then replaces the group's
+// first total (read by then); the group sums scanned in place by one
+// workgroup; each group's offset added.  bsum is left clobbered.
+__global__ __launch_bounds__(256) void k_ix_top_local(IxParams q, int32_t* bsum, int64_t nb)
 {
-    __shared__ int32_t wtot[16];
+    __shared__ int32_t wtot[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t per = (nb + 1023) / 1024;
-    const int64_t a = (int64_t)tid * per, z = a + per < nb ? a + per : nb;
-    int32_t sum = 0;
-    for (int64_t i = a; i < z; ++i) sum += bsum[i];
-    int32_t incl = sum;
+    const int64_t g0 = (int64_t)blockIdx.x * kIxBlock, i0 = g0 + (int64_t)tid * 16;
+    int32_t pre[16];
+    int32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        pre[j] = run;
+        run += i0 + j < nb ? bsum[i0 + j] : 0;
+    }
+    int32_t incl = run;
     for (int o = 1; o < 64; o <<= 1) {
         const int32_t y = __shfl_up(incl, o, 64);
         if (lane >= o) incl += y;
@@ -243,15 +251,55 @@ __global__ __launch_bounds__(1024) void k_ix_top(IxParams q, const int32_t* bsum
     __syncthreads();
     int32_t wbase = 0;
     for (int i = 0; i < w; ++i) wbase += wtot[i];
-    int32_t r = wbase + incl - sum;
-    for (int64_t i = a; i < z; ++i) {
-        q.boff[i] = r;
-        r += bsum[i];
+    const int32_t excl = wbase + incl - run;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (i0 + j < nb) q.boff[i0 + j] = excl + pre[j];
+    __syncthreads();                          // every total of the group read
+    if (tid == 255) bsum[g0] = excl + run;
+}
+
+constexpr int kIxTopGroups = 256;         // groups of kIxBlock totals one workgroup scans
+
+__global__ __launch_bounds__(kIxTopGroups) void k_ix_top_groups(IxParams q, int32_t* bsum, int64_t nb)
+{
+    __shared__ int32_t wtot[kIxTopGroups / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t ng = (nb + kIxBlock - 1) / kIxBlock;
+    const int32_t v = tid < ng ? bsum[(int64_t)tid * kIxBlock] : 0;
+    int32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
     }
-    if (tid == 1023) {
-        q.boff[nb] = r;
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int32_t wbase = 0;
+    for (int i = 0; i < w; ++i) wbase += wtot[i];
+    if (tid < ng) bsum[(int64_t)tid * kIxBlock] = wbase + incl - v;
+    if (tid == kIxTopGroups - 1) {
+        q.boff[nb] = wbase + incl;
         q.el[nb * kIxBlock] = 0;
     }
+}
+
+__global__ __launch_bounds__(256) void k_ix_top_add(IxParams q, const int32_t* bsum, int64_t nb)
+{
+    for (int64_t i = kIxBlock + (int64_t)blockIdx.x * 256 + threadIdx.x; i < nb; i += (int64_t)gridDim.x * 256)
+        q.boff[i] += bsum[i / kIxBlock * kIxBlock];
+}
+
+static hipError_t launch_top(const IxParams& q, int32_t* bsum, int64_t nb, hipStream_t s)
+{
+    const int64_t ng = (nb + kIxBlock - 1) / kIxBlock;
+    if (ng > kIxTopGroups) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ix_top_local, dim3((unsigned)ng), dim3(256), 0, s, q, bsum, nb);
+    hipLaunchKernelGGL(k_ix_top_groups, dim3(1), dim3(kIxTopGroups), 0, s, q, bsum, nb);
+    if (ng > 1) {
+        const int64_t grid = std::min<int64_t>(65536, (nb - kIxBlock + 255) / 256);
+        hipLaunchKernelGGL(k_ix_top_add, dim3((unsigned)grid), dim3(256), 0, s, q, (const int32_t*)bsum, nb);
+    }
+    return hipGetLastError();
 }
 
 // Level l >= 1 of the min-tree: the minimum of each group of level l - 1.
@@ -859,7 +907,8 @@ hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, in
 {
     const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
     hipLaunchKernelGGL(k_ix_sflag, dim3((unsigned)nb), dim3(256), 0, s, q, level, bsum);
-    hipLaunchKernelGGL(k_ix_top, dim3(1), dim3(1024), 0, s, q, (const int32_t*)bsum, nb);
+    const hipError_t et = launch_top(q, bsum, nb, s);
+    if (et != hipSuccess) return et;
     if (level == 2) hipLaunchKernelGGL(k_ix_supd<true>, dim3((unsigned)pg), dim3(256), 0, s, q, level);
     else hipLaunchKernelGGL(k_ix_supd<false>, dim3((unsigned)pg), dim3(256), 0, s, q, level);
     return hipGetLastError();
@@ -868,7 +917,8 @@ hipError_t launch_strahler_level(const IxParams& q, int level, int32_t* bsum, in
 hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t nb, const int64_t* host_len, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ix_scan, dim3((unsigned)nb), dim3(256), 0, s, q, bsum);
-    hipLaunchKernelGGL(k_ix_top, dim3(1), dim3(1024), 0, s, q, (const int32_t*)bsum, nb);
+    const hipError_t et = launch_top(q, bsum, nb, s);
+    if (et != hipSuccess) return et;
     for (int l = 1; l <= q.top; ++l) {
         const int64_t len = host_len[l];
         const int64_t grid = std::min<int64_t>(65536, std::max<int64_t>(1, (len + 255) / 256));
