@@ -10,12 +10,12 @@
 // E(k) >= E(s) for s < k < e, and E(e) = E(s) - 1 (the count of open child
 // positions never runs out early and ends exhausted).  The subtree of node k
 // ends (exclusively) at the first j > k with E(j) < E(k): k + 1 for a
-// terminal; for a function a search over a min-tree of E (level 0 is E,
-// each entry of level l the minimum of a group of kIxFan entries of level
-// l - 1, so a search step reads one 64-byte group).  The children of a
-// function k are k + 1 and end(k + 1), so the parent index follows from the
-// ends with one write per node.  On request the Strahler number of every node
-// follows, one level per pass over the subtree ranges.
+// terminal.  Its parent is the last i < k with E(i) <= E(k).  Both searches
+// run per 4096-position block, in registers and in the block's minima in
+// LDS; the few that leave the block continue in a min-tree of E (level 0 is
+// E, each entry of level l the minimum of a group of kIxFan entries of level
+// l - 1, so a search step reads one 64-byte group).  On request the Strahler
+// number of every node follows, one level per pass over the subtree ranges.
 #include <algorithm>
 #include <mutex>
 
