@@ -349,3 +349,23 @@ def test_compiler_stack_need_and_the_strahler_number():
             for vt in [g.GP_F32, g.GP_BOOL]:
                 prog = g.inspect_program(tree, vt, 2, chunk_nodes=10**7, stack_slots=32)
                 assert s - 1 <= prog.max_stack <= s, (n, s, prog.max_stack)
+
+
+def test_ends_and_parents_are_nearest_smaller_values():
+    """The device index finds both links as searches over E(k), the sum of the
+    node steps (+1 function, -1 terminal) before position k: a node's subtree
+    ends at the first j > k with E(j) < E(k), and a non-root node's parent is
+    the last i < k with E(i) <= E(k).  Checked here by brute force against the
+    oracle's ends and parents on random trees, combs and a complete tree."""
+    rng = np.random.default_rng(17)
+    F = gen.F_ADD
+    trees = [gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 2001)), n_terms=2) for _ in range(40)]
+    trees += [np.array([F] * 50 + [0] * 51, np.uint8), np.array([F, 0] * 50 + [0], np.uint8)]
+    trees.append(np.array([F, F, F, 0, 0, F, 0, 0, F, F, 0, 0, F, 0, 0], np.uint8))     # complete, depth 3
+    for tr in trees:
+        n = len(tr)
+        E = np.concatenate([[0], np.cumsum(np.where(tr & 0x80, 1, -1))])
+        end = np.array([next(j for j in range(k + 1, n + 1) if E[j] < E[k]) for k in range(n)])
+        par = np.array([-1] + [max(i for i in range(k) if E[i] <= E[k]) for k in range(1, n)])
+        assert np.array_equal(end, oracle.all_ends(tr))
+        assert np.array_equal(par, oracle.parents(tr))
