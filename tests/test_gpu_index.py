@@ -153,3 +153,32 @@ def test_index_errors(ctx):
     valid, end, parent, _ = ctx.index_trees(dev[16:], doffs, 1, n_nodes=len(ops))   # still works after errors
     assert valid.cpu().tolist() == [1, 1]
     assert end.cpu().tolist() == [3, 2, 3, 1] and parent.cpu().tolist() == [-1, 0, 0, -1]
+
+
+def test_index_outputs_at_odd_addresses(ctx):
+    """Ends, parents and Strahler numbers written to caller buffers that start
+    4 and 1 bytes past a 16-byte boundary (where the kernels' 16-byte loads
+    and stores of a thread's positions fall back to single elements) equal
+    those of the aligned buffers the allocating call returns."""
+    import torch
+    rng = np.random.default_rng(91)
+    trees = [gen.sized_tree(rng, int(gen.log_uniform_odd(rng, 1, 200001)), n_terms=2) for _ in range(30)]
+    ops, offs = pack(trees)
+    n = len(ops)
+    assert n <= g.INDEX_NOALLOC_MAX_NODES
+    dev = torch.from_numpy(ops).to("cuda:0")
+    doffs = torch.from_numpy(offs).to("cuda:0")
+    v1, e1, p1, s1, _ = ctx.index_trees(dev, doffs, 2, strahler=True)
+    v2 = torch.full((len(trees),), 77, dtype=torch.int32, device="cuda:0")
+    eb = torch.full((n + 1,), 77, dtype=torch.int32, device="cuda:0")
+    pb = torch.full((n + 1,), 77, dtype=torch.int32, device="cuda:0")
+    sb = torch.full((n + 1,), 77, dtype=torch.uint8, device="cuda:0")
+    say("index at odd addresses:", len(trees), "trees", n, "nodes")
+    ctx.index_trees_noalloc(dev, doffs, 2, v2, eb[1:], pb[1:], sb[1:])
+    assert eb[1:].data_ptr() % 16 == 4 and sb[1:].data_ptr() % 16 == 1
+    assert np.array_equal(v2.cpu().numpy(), v1.cpu().numpy())
+    assert np.array_equal(eb[1:].cpu().numpy(), e1.cpu().numpy())
+    assert np.array_equal(pb[1:].cpu().numpy(), p1.cpu().numpy())
+    assert np.array_equal(sb[1:].cpu().numpy(), s1.cpu().numpy())
+    assert int(eb[0]) == 77 and int(pb[0]) == 77 and int(sb[0]) == 77
+    check(trees, offs, v1.cpu().numpy(), e1.cpu().numpy(), p1.cpu().numpy(), 2, s1.cpu().numpy())
