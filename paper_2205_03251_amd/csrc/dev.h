@@ -180,7 +180,7 @@ struct IxParams {
     int64_t n;                          // positions in all
     int n_inputs;
     int top;                            // highest min-tree level (at most kIxFan entries)
-    int32_t* el;                        // [n_blocks * kIxBlock + kIxFan]
+    int16_t* el;                        // [n_blocks * kIxBlock + kIxFan], within-block values (|x| <= kIxBlock)
     int32_t* boff;                      // [n_blocks + 1]
     int32_t* seg;                       // min-tree levels 1..top, each padded to whole groups
     int64_t lvl[2 * kIxMaxLevels];      // offset in seg and length of each level; level 0 = E, length n + 1

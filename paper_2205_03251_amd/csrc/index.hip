@@ -59,6 +59,12 @@ hipError_t launch_fill_u8(uint8_t* dst, int64_t n, uint8_t v, hipStream_t s)
 
 static_assert(kIxFan == 16, "a group is read as four 16-byte loads");
 
+// Two int16 values (within +-32767) in one word, the first in the low half.
+__device__ __forceinline__ int32_t ix_pack16(int32_t lo, int32_t hi)
+{
+    return (int32_t)(((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16));
+}
+
 __device__ __forceinline__ int32_t ix_e(const IxParams& q, int64_t k)
 {
     return q.el[k] + q.boff[k / kIxBlock];
@@ -83,26 +89,34 @@ __device__ __forceinline__ int64_t ix_tree_of(const IxParams& q, int64_t k)
 }
 
 // Group g of min-tree level l (the kIxFan entries from g, g a multiple of
-// kIxFan), read with four 16-byte loads; levels and el are padded to whole
-// groups.  Entries past the level's length hold whatever the padding holds.
+// kIxFan), read with four 16-byte loads (two for el); levels and el are
+// padded to whole groups.  Entries past the level's length hold whatever the padding holds.
 __device__ __forceinline__ void ix_load_group(const IxParams& q, int l, int64_t g, int32_t (&x)[kIxFan])
 {
-    int4 w[4];
-    int32_t add = 0;
     if (l == 0) {
+        // 16 int16 entries, two 16-byte loads
         const int4* src = (const int4*)(q.el + g);
-        for (int i = 0; i < 4; ++i) w[i] = src[i];
-        add = q.boff[g / kIxBlock];           // a group never straddles a scan block
-    } else {
-        const int4* src = (const int4*)(q.seg + q.lvl[2 * l] + g);
-        for (int i = 0; i < 4; ++i) w[i] = src[i];
+        const int32_t add = q.boff[g / kIxBlock];   // a group never straddles a scan block
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int4 w = src[i];
+            const int32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                x[8 * i + 2 * h] = (int32_t)(int16_t)(u[h] & 0xffff) + add;
+                x[8 * i + 2 * h + 1] = (u[h] >> 16) + add;
+            }
+        }
+        return;
     }
+    const int4* src = (const int4*)(q.seg + q.lvl[2 * l] + g);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        x[4 * i] = w[i].x + add;
-        x[4 * i + 1] = w[i].y + add;
-        x[4 * i + 2] = w[i].z + add;
-        x[4 * i + 3] = w[i].w + add;
+        const int4 w = src[i];
+        x[4 * i] = w.x;
+        x[4 * i + 1] = w.y;
+        x[4 * i + 2] = w.z;
+        x[4 * i + 3] = w.w;
     }
 }
 
@@ -218,8 +232,11 @@ __global__ __launch_bounds__(256) void k_ix_scan(IxParams q, int32_t* bsum)
     for (int i = 0; i < w; ++i) wbase += wtot[i];
     const int32_t excl = wbase + incl - run;
     int4* dst = (int4*)(q.el + base);
-    for (int j = 0; j < 4; ++j)
-        dst[j] = make_int4(excl + pre[4 * j], excl + pre[4 * j + 1], excl + pre[4 * j + 2], excl + pre[4 * j + 3]);
+    for (int j = 0; j < 2; ++j)
+        dst[j] = make_int4(ix_pack16(excl + pre[8 * j], excl + pre[8 * j + 1]),
+                           ix_pack16(excl + pre[8 * j + 2], excl + pre[8 * j + 3]),
+                           ix_pack16(excl + pre[8 * j + 4], excl + pre[8 * j + 5]),
+                           ix_pack16(excl + pre[8 * j + 6], excl + pre[8 * j + 7]));
     if (tid == 255) bsum[blockIdx.x] = excl + run;
 }
 
@@ -826,7 +843,9 @@ __global__ __launch_bounds__(256) void k_ix_sflag(IxParams q, int level, int32_t
     int32_t pre[16];
     for (int j = 0; j < 16; ++j) pre[j] = excl + __popc(bits & ((1u << j) - 1u));
     int4* dst = (int4*)(q.el + base);
-    for (int j = 0; j < 4; ++j) dst[j] = make_int4(pre[4 * j], pre[4 * j + 1], pre[4 * j + 2], pre[4 * j + 3]);
+    for (int j = 0; j < 2; ++j)
+        dst[j] = make_int4(ix_pack16(pre[8 * j], pre[8 * j + 1]), ix_pack16(pre[8 * j + 2], pre[8 * j + 3]),
+                           ix_pack16(pre[8 * j + 4], pre[8 * j + 5]), ix_pack16(pre[8 * j + 6], pre[8 * j + 7]));
     if (tid == 255) bsum[blockIdx.x] = excl + run;
 }
 

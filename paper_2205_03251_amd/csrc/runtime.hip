@@ -2566,7 +2566,7 @@ int gpe::index_trees(Ctx* ctx, int n_inputs, int64_t n_trees, const uint8_t* ops
     RC(scratch_alloc(ctx, arena, seg, (size_t)(seg_total + kIxFan) * 4));
     RC(scratch_alloc(ctx, arena, flag, 8));
     if (strahler) RC(scratch_alloc(ctx, arena, bempty, (size_t)nb + 1));
-    q.el = el.as<int32_t>();
+    q.el = el.as<int16_t>();
     q.boff = boff.as<int32_t>();
     q.seg = seg.as<int32_t>();
     q.bempty = strahler ? bempty.as<uint8_t>() : nullptr;
@@ -2605,7 +2605,7 @@ int gp_index_trees_noalloc(gp_ctx* ctx, int n_inputs, int64_t n_trees, const uin
     (void)ix_levels(n_nodes, q, len);
     const int64_t nb = (n_nodes + kIxBlock - 1) / kIxBlock;
     int32_t* base = ctx->ix_scratch;
-    q.el = base + kIxStaticEl;
+    q.el = (int16_t*)(base + kIxStaticEl);
     q.boff = base + kIxStaticBoff;
     q.seg = base + kIxStaticSeg;
     q.bempty = strahler ? (uint8_t*)(base + kIxStaticBempty) : nullptr;
