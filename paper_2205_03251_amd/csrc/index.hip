@@ -88,6 +88,18 @@ __device__ __forceinline__ int64_t ix_tree_of(const IxParams& q, int64_t k)
     return lo;
 }
 
+// The last tree t in [lo, hi] with offsets[t] <= k, or lo.
+__device__ __forceinline__ int64_t ix_tree_in(const IxParams& q, int64_t lo, int64_t hi, int64_t k)
+{
+    ++hi;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (q.offsets[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Group g of min-tree level l (the kIxFan entries from g, g a multiple of
 // kIxFan), read with four 16-byte loads (two for el); levels and el are
 // padded to whole groups.  Entries past the level's length hold whatever the padding holds.
@@ -393,18 +405,43 @@ __device__ __forceinline__ void ix_positions(const IxParams& q, Body body, Other
     }
 }
 
-__global__ __launch_bounds__(256) void k_ix_check(IxParams q)
+// Validity, in two parts.  Every byte a known opcode: one pass over the
+// bytes, which looks a tree up only for a bad byte.  The count of open child
+// positions never running out before the end and running out there: with
+// steps of +-1, the first j > s with E(j) < E(s) is e, one search per tree.
+__global__ __launch_bounds__(256) void k_ix_bytes(IxParams q, const int32_t* tfirst)
 {
-    ix_positions(
-        q,
-        [&](int64_t k, int64_t t, int64_t s, int64_t e, uint8_t op, int32_t ek) {
-            const int32_t es = ix_e(q, s);
-            bool bad = ix_bad_byte(op, q.n_inputs);
-            if (k > s && ek < es) bad = true;
-            if (k == e - 1 && ix_e(q, e) != es - 1) bad = true;
-            if (bad) q.valid[t] = 0;
-        },
-        [&](int64_t) {});
+    const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (k0 >= q.n) return;
+    uint32_t w[4];
+    ix_bytes16(q.ops, k0, q.n, w);
+    uint32_t bad = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (k0 + j < q.n && ix_bad_byte((uint8_t)(w[j >> 2] >> (8 * (j & 3))), q.n_inputs)) bad |= 1u << j;
+    if (!bad) return;
+    const int64_t b = k0 / kIxBlock, nb = (q.n + kIxBlock - 1) / kIxBlock;
+    int64_t t = ix_tree_in(q, tfirst[b], b + 1 < nb ? tfirst[b + 1] : q.n_trees - 1, k0);
+    int64_t s = q.offsets[t], e = q.offsets[t + 1];
+    while (bad) {
+        const int64_t k = k0 + (__ffs(bad) - 1);
+        bad &= bad - 1;
+        while (k >= e && t + 1 < q.n_trees) {
+            ++t;
+            s = q.offsets[t];
+            e = q.offsets[t + 1];
+        }
+        if (0 <= s && s <= k && k < e) q.valid[t] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ix_trees(IxParams q)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < q.n_trees; t += (int64_t)gridDim.x * 256) {
+        const int64_t s = q.offsets[t], e = q.offsets[t + 1];
+        if (!(0 <= s && s < e && e <= q.n)) continue;           // refused by k_ix_init
+        if (ix_first_below_at(q, 0, s + 1, ix_e(q, s)) != e) q.valid[t] = 0;
+    }
 }
 
 // Within one block: E of its positions less the block's offset (the scan's
@@ -500,18 +537,6 @@ __global__ __launch_bounds__(256) void k_ix_tfirst(IxParams q, int32_t* tfirst, 
 {
     for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < nb; b += (int64_t)gridDim.x * 256)
         tfirst[b] = (int32_t)ix_tree_of(q, b * kIxBlock);
-}
-
-// The last tree t in [lo, hi] with offsets[t] <= k, or lo.
-__device__ __forceinline__ int64_t ix_tree_in(const IxParams& q, int64_t lo, int64_t hi, int64_t k)
-{
-    ++hi;
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (q.offsets[mid] <= k) lo = mid;
-        else hi = mid;
-    }
-    return lo;
 }
 
 constexpr int kIxQueue = 1024;            // block-leaving searches shared out per workgroup
@@ -945,10 +970,11 @@ hipError_t launch_index(const IxParams& q, int32_t* bsum, int64_t nb, const int6
     }
     const int64_t tg = std::min<int64_t>(65536, std::max<int64_t>(1, (q.n_trees + 255) / 256));
     hipLaunchKernelGGL(k_ix_init, dim3((unsigned)tg), dim3(256), 0, s, q);
-    const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
-    hipLaunchKernelGGL(k_ix_check, dim3((unsigned)pg), dim3(256), 0, s, q);
     const int64_t bg = std::min<int64_t>(65536, std::max<int64_t>(1, (nb + 255) / 256));
     hipLaunchKernelGGL(k_ix_tfirst, dim3((unsigned)bg), dim3(256), 0, s, q, bsum, nb);
+    const int64_t pg = (q.n + 16 * 256 - 1) / (16 * 256);
+    hipLaunchKernelGGL(k_ix_bytes, dim3((unsigned)pg), dim3(256), 0, s, q, (const int32_t*)bsum);
+    hipLaunchKernelGGL(k_ix_trees, dim3((unsigned)tg), dim3(256), 0, s, q);
     hipLaunchKernelGGL(k_ix_links, dim3((unsigned)pg), dim3(256), 0, s, q, (const int32_t*)bsum);
     return hipGetLastError();
 }
