@@ -710,6 +710,22 @@ __global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfi
     }
 }
 
+// Trees [lo, hi] that scan block b may hold, for the Strahler passes: the
+// per-block first trees are copied into the global min-tree's storage, free
+// once ends and parents are written (with no min-tree levels the population
+// has at most kIxFan positions, one block).
+__device__ __forceinline__ void ix_block_trees(const IxParams& q, int64_t b, int64_t& lo, int64_t& hi)
+{
+    const int64_t nb = (q.n + kIxBlock - 1) / kIxBlock;
+    if (q.top == 0) {
+        lo = 0;
+        hi = q.n_trees - 1;
+        return;
+    }
+    lo = q.seg[b];
+    hi = b + 1 < nb ? q.seg[b + 1] : q.n_trees - 1;
+}
+
 // Strahler numbers, one level per pass.  A node's number is at least k + 1
 // iff its subtree holds a function whose two children both have at least k
 // (numbers never decrease towards the root, and a node whose children differ
@@ -718,6 +734,24 @@ __global__ __launch_bounds__(256) void k_ix_links(IxParams q, const int32_t* tfi
 // longer need), and raises every function whose subtree range holds one.
 __global__ __launch_bounds__(256) void k_ix_sinit(IxParams q)
 {
+    const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (k0 + 16 <= q.n && (((uintptr_t)(q.sn + k0)) & 15) == 0) {
+        // 16 positions in one tree: the numbers from the opcode bytes at once
+        int64_t lo, hi;
+        ix_block_trees(q, k0 / kIxBlock, lo, hi);
+        const int64_t t = ix_tree_in(q, lo, hi, k0);
+        const int64_t s = q.offsets[t], e = q.offsets[t + 1];
+        if (0 <= s && s <= k0 && k0 + 16 <= e && e <= q.n) {
+            uint32_t w[4];
+            ix_bytes16(q.ops, k0, q.n, w);
+            const bool ok = q.valid[t] != 0;
+            uint32_t v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = ok ? ((w[i] & 0x80808080u) >> 7) + 0x01010101u : 0u;
+            *(uint4*)(q.sn + k0) = make_uint4(v[0], v[1], v[2], v[3]);
+            return;
+        }
+    }
     ix_positions(
         q,
         [&](int64_t k, int64_t t, int64_t, int64_t, uint8_t op, int32_t) {
@@ -745,22 +779,6 @@ __device__ __forceinline__ uint32_t ix_at_level(const IxParams& q, int64_t k0, i
 {
     uint32_t sn[4];
     return ix_at_level(q, k0, level, sn);
-}
-
-// Trees [lo, hi] that scan block b may hold, for the Strahler passes: the
-// per-block first trees are copied into the global min-tree's storage, free
-// once ends and parents are written (with no min-tree levels the population
-// has at most kIxFan positions, one block).
-__device__ __forceinline__ void ix_block_trees(const IxParams& q, int64_t b, int64_t& lo, int64_t& hi)
-{
-    const int64_t nb = (q.n + kIxBlock - 1) / kIxBlock;
-    if (q.top == 0) {
-        lo = 0;
-        hi = q.n_trees - 1;
-        return;
-    }
-    lo = q.seg[b];
-    hi = b + 1 < nb ? q.seg[b + 1] : q.n_trees - 1;
 }
 
 // end[k0 .. k0 + 16), with four 16-byte loads where aligned (k0 + 16 <= n).
